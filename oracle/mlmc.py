@@ -1,0 +1,117 @@
+"""Multilevel Monte Carlo estimator (oracle side), Sec. 2.2-2.3.
+
+  Y_0 = Q_0,  Y_l = Q_l - Q_{l-1}, the two meshes of a level-l sample sharing
+  one draw xi(l, i) (eq. mlmc_average and the sentence after it)
+  Qtilde_L = sum_l mean(Y_l)                                 (eq. mlmc_average)
+  V(Y_l)  = (1/N_l) sum_i (Y_l^i - mean(Y_l))^2  -- note 1/N (eq. sample_variance)
+  V(Qtilde_L) = sum_l V(Y_l) / N_l                           (Sec. 2.2)
+  N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_i sqrt(V_i C_i))   (eq. mlmc_num_samples)
+  L   = ceil(log_s(sqrt(2) c / eps) / alpha)                 (eq. mlmc_num_levels)
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence
+
+import numpy as np
+
+from . import fe, field, pcg, rng
+
+
+def solve_qoi(n: int, kap: np.ndarray, qoi: int, rtol: float, max_iter: int):
+    """Q(u_h) for one sample: Jacobi-PCG on the assembled operator, f = 1."""
+    A = fe.assemble(n, kap)
+    b = fe.load_constant(n)
+    u, it, rel = pcg.jacobi_pcg(A, b, rtol, max_iter)
+    return float(fe.qoi_weights(n, qoi) @ u), it, rel, u
+
+
+def sample_level(wl, level: int, first: int, count: int, rtol=None, max_iter=None,
+                 common_random_numbers: bool = False):
+    """Per-sample (Y, Q_fine, Q_coarse, iterations_fine) for one level.
+
+    common_random_numbers: draw xi with level 0 in the counter for every level
+    (test-only mode used by the telescoping identity).
+    """
+    rtol = wl.rtol if rtol is None else rtol
+    max_iter = wl.max_iter if max_iter is None else max_iter
+    xi = rng.draw_xi(wl.seed, 0 if common_random_numbers else level, first, count, wl.n_modes)
+    nf = wl.n(level)
+    kf = field.kappa(nf, wl.corr_len, wl.sigma2, wl.n_modes, xi)
+    kc = field.kappa(nf // 2, wl.corr_len, wl.sigma2, wl.n_modes, xi) if level > 0 else None
+    Y = np.empty(count); Qf = np.empty(count); Qc = np.zeros(count); its = np.empty(count, dtype=np.int64)
+    for s in range(count):
+        Qf[s], its[s], _, _ = solve_qoi(nf, kf[s], wl.qoi, rtol, max_iter)
+        if level > 0:
+            Qc[s], _, _, _ = solve_qoi(nf // 2, kc[s], wl.qoi, rtol, max_iter)
+        Y[s] = Qf[s] - Qc[s]
+    return Y, Qf, Qc, its
+
+
+@dataclasses.dataclass
+class RunningStats:
+    """Count, mean and sum of squared deviations (Welford, in sample order)."""
+    n: int = 0
+    mean: float = 0.0
+    m2: float = 0.0
+
+    def push(self, y: float):
+        self.n += 1
+        d = y - self.mean
+        self.mean += d / self.n
+        self.m2 += d * (y - self.mean)
+
+    def merge(self, other: "RunningStats") -> "RunningStats":
+        """Chan, Golub and LeVeque pairwise combination."""
+        n = self.n + other.n
+        if n == 0:
+            return RunningStats()
+        d = other.mean - self.mean
+        mean = self.mean + d * other.n / n
+        m2 = self.m2 + other.m2 + d * d * self.n * other.n / n
+        return RunningStats(n, mean, m2)
+
+    @property
+    def var(self) -> float:
+        """eq. sample_variance: 1/N normalisation."""
+        return self.m2 / self.n if self.n else 0.0
+
+
+def estimator(stats: Sequence[RunningStats]):
+    """(Qtilde, per-level V(Y_l), V(Qtilde) = sum V_l / N_l)."""
+    qt = sum(s.mean for s in stats)
+    v = [s.var for s in stats]
+    vq = sum(s.var / s.n for s in stats if s.n)
+    return qt, v, vq
+
+
+def optimal_samples(var: Sequence[float], cost: Sequence[float], eps: float) -> List[int]:
+    """eq. mlmc_num_samples."""
+    tot = sum(math.sqrt(v * c) for v, c in zip(var, cost))
+    return [int(math.ceil(2.0 / (eps * eps) * math.sqrt(v / c) * tot)) for v, c in zip(var, cost)]
+
+
+def num_levels(c: float, alpha: float, eps: float, s: float = 2.0) -> int:
+    """eq. mlmc_num_levels."""
+    return int(math.ceil(math.log(math.sqrt(2.0) * c / eps, s) / alpha))
+
+
+def level_cost(wl, level: int) -> float:
+    """Deterministic cost model: interior unknowns solved for one Y_l sample."""
+    n = wl.n(level)
+    return float((n - 1) ** 3 + ((n // 2 - 1) ** 3 if level > 0 else 0))
+
+
+def run_mlmc(wl, n_per_level: Sequence[int]):
+    """Plain MLMC with fixed N_l; returns (Qtilde, V_l list, V(Qtilde), stats, Ys)."""
+    stats, ys = [], []
+    for lvl, N in enumerate(n_per_level):
+        Y, _, _, _ = sample_level(wl, lvl, 0, N)
+        st = RunningStats()
+        for y in Y:
+            st.push(float(y))
+        stats.append(st)
+        ys.append(Y)
+    qt, v, vq = estimator(stats)
+    return qt, v, vq, stats, ys

@@ -1,0 +1,163 @@
+"""Pins for the multigrid pieces and the MLMC statistics of the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fe, gmg, mlmc, rng
+from workloads import C1, Workload, element_field, grid_vector
+
+
+def test_coarsen_kappa_mean():
+    n = 8
+    kap = element_field(n, 2, seed=1)
+    kc = gmg.coarsen_kappa(n, kap)
+    # element (1, 2, 3) of the n/2 grid has children (2..3, 4..5, 6..7)
+    want = np.mean([kap[1, x + n * (y + n * z)] for x in (2, 3) for y in (4, 5) for z in (6, 7)])
+    assert kc[1, 1 + 4 * (2 + 4 * 3)] == pytest.approx(want, rel=1e-15)
+    assert np.all(gmg.coarsen_kappa(n, np.full(n ** 3, 2.5)) == 2.5)
+
+
+@pytest.mark.parametrize("n", [4, 8, 16])
+def test_galerkin_identity_constant_kappa(n):
+    # nested conforming spaces: P^T A_h P = A_2h exactly for constant kappa
+    c = 1.7
+    Af = fe.assemble(n, np.full(n ** 3, c))
+    Ac = fe.assemble(n // 2, np.full((n // 2) ** 3, c))
+    P = gmg.prolongation(n)
+    G = (P.T @ Af @ P).toarray()
+    assert np.abs(G - Ac.toarray()).max() <= 1e-14 * np.abs(Ac.toarray()).max()
+
+
+def test_prolongation_reproduces_coarse_trilinear():
+    # a function trilinear on each coarse cell and zero on the boundary
+    n = 8
+    nc = n // 2
+    cg = fe.interior_ijk(nc)
+    uc = grid_vector(nc, 1, seed=2)[0]
+    uf = gmg.prolongation(n) @ uc
+    full = np.zeros((nc + 1,) * 3)
+    full[cg[:, 2], cg[:, 1], cg[:, 0]] = uc
+    for i, j, k in fe.interior_ijk(n)[::7]:
+        X = np.array([i, j, k]) / 2.0
+        lo = np.floor(X).astype(int)
+        t = X - lo
+        val = 0.0
+        for a in range(8):
+            o = np.array([a & 1, (a >> 1) & 1, (a >> 2) & 1])
+            p = np.minimum(lo + o, nc)
+            w = np.prod(np.where(o == 1, t, 1 - t))
+            val += w * full[p[2], p[1], p[0]]
+        assert uf[fe.interior_index(n, i, j, k)] == pytest.approx(val, abs=1e-15)
+
+
+def test_chebyshev_matches_polynomial():
+    n = 4
+    kap = element_field(n, 1, seed=4)[0]
+    A = fe.assemble(n, kap)
+    dinv = 1.0 / A.diagonal()
+    xstar = grid_vector(n, 1, seed=5)[0]
+    b = A @ xstar
+    x0 = grid_vector(n, 1, seed=6)[0]
+    lo, hi = 0.5, 2.0
+    # symmetric form S = D^-1/2 A D^-1/2; e_s = D^-1/2 p(S) D^1/2 e_0
+    d = np.sqrt(A.diagonal())
+    S = A.toarray() / d[:, None] / d[None, :]
+    lam, V = np.linalg.eigh(S)
+    for deg in (1, 2, 3, 4):
+        xs = gmg.chebyshev(A, dinv, b, x0, deg, lo, hi)
+        p = gmg.chebyshev_polynomial(lam, deg, lo, hi)
+        e = (V @ (p * (V.T @ (d * (xstar - x0))))) / d
+        assert np.abs((xstar - xs) - e).max() < 1e-12 * np.abs(xstar - x0).max()
+
+
+def test_vcycle_symmetric_positive_contracting():
+    n = 8
+    kap = element_field(n, 1, seed=7, spread=1.5)[0]
+    H = gmg.Hierarchy(n, kap)
+    r1, r2 = grid_vector(n, 2, seed=8)
+    v1 = H.vcycle(r1, 2, 4.0, 2.0)
+    v2 = H.vcycle(r2, 2, 4.0, 2.0)
+    assert abs(v1 @ r2 - v2 @ r1) <= 1e-12 * abs(v1 @ r2)
+    assert v1 @ r1 > 0
+    # two-grid-like contraction of I - B A on a random error
+    A = H.As[0]
+    e = r1.copy()
+    for _ in range(3):
+        e = e - H.vcycle(A @ e, 2, 4.0, 2.0)
+    assert np.linalg.norm(e) < 0.05 * np.linalg.norm(r1)
+
+
+def test_welford_and_chan_against_two_pass():
+    y = np.random.default_rng(9).standard_normal(1001) * 3 + 0.7
+    s = mlmc.RunningStats()
+    for v in y:
+        s.push(v)
+    assert s.mean == pytest.approx(y.mean(), rel=1e-14)
+    assert s.var == pytest.approx(np.mean((y - y.mean()) ** 2), rel=1e-13)   # 1/N
+    a, b = mlmc.RunningStats(), mlmc.RunningStats()
+    for v in y[:400]:
+        a.push(v)
+    for v in y[400:]:
+        b.push(v)
+    m = a.merge(b)
+    assert m.n == 1001 and m.mean == pytest.approx(s.mean, rel=1e-14)
+    assert m.m2 == pytest.approx(s.m2, rel=1e-13)
+
+
+def test_optimal_allocation_is_the_lagrange_optimum():
+    V = [4e-4, 3e-5, 2e-6, 1.5e-7]
+    C = [1.0, 8.0, 64.0, 512.0]
+    eps = 1e-3
+    N = mlmc.optimal_samples(V, C, eps)
+    # continuous optimum: N_l = 2 eps^-2 sqrt(V_l/C_l) sum sqrt(V C); it meets
+    # sum V_l / N_l = eps^2 / 2 exactly before the ceiling
+    cont = [2 / eps ** 2 * math.sqrt(v / c) * sum(math.sqrt(a * b) for a, b in zip(V, C)) for v, c in zip(V, C)]
+    assert N == [math.ceil(x) for x in cont]
+    assert sum(v / x for v, x in zip(V, cont)) == pytest.approx(eps ** 2 / 2, rel=1e-12)
+    assert sum(v / x for v, x in zip(V, N)) <= eps ** 2 / 2
+    # any feasible perturbation costs more
+    base = sum(c * x for c, x in zip(C, cont))
+    for l in range(4):
+        pert = list(cont)
+        pert[l] *= 1.1
+        other = (l + 1) % 4
+        # keep the variance constraint by adjusting another level
+        rest = eps ** 2 / 2 - sum(V[i] / pert[i] for i in range(4) if i != other)
+        pert[other] = V[other] / rest
+        assert sum(c * x for c, x in zip(C, pert)) > base
+
+
+def test_num_levels_formula():
+    # with alpha = 2, s = 2: L = ceil(log2(sqrt 2 c / eps) / 2)
+    assert mlmc.num_levels(1.0, 2.0, 1e-3) == math.ceil(math.log2(math.sqrt(2) * 1e3) / 2)
+
+
+def test_sample_scaling_law_table():
+    # Sec. 5: N_l proportional to exp(Gamma log(s) (L - l)), Gamma = 4, s = 2,
+    # L = 2; the paper's Table (sample sizes by level) lists 1024, 64, 4.
+    table = [int(x) for x in open(__file__.replace("test_oracle_gmg_mlmc.py", "golden/sample_sizes_by_level.txt"))
+             .read().split("#")[0].split()]
+    law = [math.exp(4 * math.log(2.0) * (2 - l)) for l in range(3)]
+    assert [round(4 * x) for x in law] == table
+
+
+def test_telescoping_identity_common_random_numbers():
+    # with common random numbers and equal N_l, sum_l mean(Y_l) = mean(Q_L)
+    wl = Workload("tele", n0=2, levels=3, sigma2=1.0, corr_len=0.5, n_modes=8, rtol=1e-12, solver=1)
+    N = 6
+    ys, qL = [], None
+    for lvl in range(3):
+        Y, Qf, Qc, _ = mlmc.sample_level(wl, lvl, 0, N, common_random_numbers=True)
+        ys.append(Y)
+        if lvl == 2:
+            qL = Qf
+    tel = sum(y.mean() for y in ys)
+    assert tel == pytest.approx(qL.mean(), rel=1e-14)
+
+
+def test_c1_variance_decays_with_level():
+    qt, v, vq, stats, ys = mlmc.run_mlmc(C1, (40, 20, 8))
+    assert v[1] < v[0] / 4 and v[2] < v[1] / 4
+    assert 0.0 < qt < 0.05
+    assert vq == pytest.approx(sum(s.var / s.n for s in stats))
