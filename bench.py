@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Throughput of the MLMC finite-element hot path on one MI355X.
+
+Workload: the single-level batched solve of 1024 samples on the 64^3 Q1 mesh
+(M = 64 KL modes, correlation length 0.3, sigma^2 = 1, f = 1, homogeneous
+Dirichlet data, QoI = mean of u over [1/4, 3/4]^3), each sample solved by
+GMG-preconditioned CG to true relative residual 1e-8.  One step = one pass of
+the whole path over one batch: Philox draw of xi, MFMA KLE field, multigrid
+hierarchy, batched solve, QoI and level statistics.  Every step draws fresh
+samples (sample indices advance by the batch size).
+
+Prints one JSON line:  value = sample-DOFs solved per second (interior
+unknowns (n-1)^3 summed over the solves of the timed steps / wall time).
+Also reported: the fp64 path on the same workload, the roofline of the
+dominant kernel (algorithmic bytes / event-timed duration on the library's
+stream), and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+METRIC = "MLMC sample-DOFs solved/s at rel.res 1e-8"
+
+
+def _cpu_worker(args):
+    seed_first, wl_name = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import mlmc as omlmc
+    import workloads
+    wl = {w.name: w for w in workloads.ALL}[wl_name]
+    t = time.perf_counter()
+    y, qf, qc, it = omlmc.sample_level(wl, 0, seed_first, 1)
+    return time.perf_counter() - t, float(qf[0]), int(it[0])
+
+
+def cpu_baseline(wl, samples: int):
+    """The oracle (assembled CSR + Jacobi-PCG, fp64) on `samples` samples of
+    the workload, one single-threaded process per core."""
+    import multiprocessing as mp
+    cores = max(1, min(samples, os.cpu_count() or 1, 16))
+    t0 = time.perf_counter()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [(i, wl.name) for i in range(samples)])
+    wall = time.perf_counter() - t0
+    dofs = (wl.n0 - 1) ** 3
+    return {"value": samples * dofs / wall, "unit": "sample-DOFs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{samples} samples of the 64^3 workload (level 0, indices 0..{samples - 1}), "
+                      f"assembled CSR + Jacobi-PCG to rel.res 1e-8, {cores} processes x 1 thread",
+            "wall_s": round(wall, 3), "mean_sample_s": round(sum(r[0] for r in res) / samples, 3),
+            "cpu": platform.processor() or platform.machine()}
+
+
+def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bool):
+    import numpy as np
+    import torch
+    import paper_2111_11788_amd as mm
+
+    ctx = mm.Context(wl, precision=precision, max_batch=batch)
+    dofs = (wl.n0 - 1) ** 3
+    first = 0
+    for _ in range(warmup):
+        ctx.sample_level(0, first, batch)
+        first += batch
+    torch.cuda.synchronize()
+    its = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        y, qf, qc, it = ctx.sample_level(0, first, batch)
+        its.append(it)
+        first += batch
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"value": steps * batch * dofs / wall, "ms_per_step": 1e3 * wall / steps,
+           "iters_mean": float(np.mean(its)), "iters_max": int(np.max(its))}
+    if profile:
+        ctx.set_profiling(True)
+        ctx.sample_level(0, first, batch)
+        rows = []
+        for name in mm.KERNELS:
+            for p in (0, 1):
+                n, ms, by = ctx.kernel_time(name, p)
+                if n:
+                    rows.append((ms, name, "f64" if p == 0 else "f32", n, by))
+        ctx.set_profiling(False)
+        rows.sort(reverse=True)
+        ms, name, dt, n, by = rows[0]
+        avg_ms = ms / n
+        achieved = by / n / (avg_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": f"{name} ({dt})", "achieved": round(achieved, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": None, "launches": n, "avg_launch_us": round(1e3 * avg_ms, 2),
+                           "bytes_per_launch": by / n}
+        out["kernels"] = [{"kernel": f"{r[1]} ({r[2]})", "ms": round(r[0], 3), "launches": r[3],
+                           "GBps": round(r[4] / (r[0] * 1e-3) / 1e9, 1) if r[0] > 0 else None} for r in rows[:12]]
+    ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the fp64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-samples", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); samples are independent, "
+              "so a multi-GPU run is N copies of this one on disjoint sample ranges", file=sys.stderr)
+        sys.exit(2)
+
+    import workloads
+    wl = workloads.C2
+    prec = 1 if args.precision == "mixed" else 0
+    main_run = run_gpu(wl, prec, args.steps, args.warmup, args.batch, profile=True)
+    fp64 = None
+    if prec == 1 and not args.no_fp64:
+        fp64 = run_gpu(wl, 0, max(1, args.steps // 2), 1, args.batch, profile=False)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_samples)
+
+    line = {
+        "metric": METRIC, "value": main_run["value"], "unit": "sample-DOFs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == 1 else "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "mesh": f"{wl.n0}^3 Q1 hexahedra", "samples_per_step": args.batch,
+                   "dofs_per_sample": (wl.n0 - 1) ** 3, "n_modes": wl.n_modes, "corr_len": wl.corr_len,
+                   "sigma2": wl.sigma2, "qoi": "subcube [1/4,3/4]^3 average", "rtol": wl.rtol,
+                   "solver": "GMG-PCG (Chebyshev-Jacobi deg 2, V-cycle to 2^3)",
+                   "precision": "fp32 GMG-PCG inside fp64 refinement" if prec == 1 else "fp64"},
+        "iterations": {"mean": main_run["iters_mean"], "max": main_run["iters_max"]},
+        "roofline": main_run.get("roofline"),
+        "kernels": main_run.get("kernels"),
+        "fp64_path": None if fp64 is None else {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
+                                                "iters_mean": fp64["iters_mean"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

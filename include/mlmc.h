@@ -1,0 +1,214 @@
+/*
+ * mlmc.h -- C-ABI of the MI355X multilevel Monte Carlo finite-element library.
+ *
+ * The library estimates E[Q(u)] for the random diffusion problem
+ *     -div(kappa(x, omega) grad u) = f  in D,   u = u0 on the boundary
+ * (paper Sec. 2.1, eq. model) by the telescoping multilevel estimator
+ *     Qtilde_L = sum_{l=0}^{L} mean(Y_l),  Y_0 = Q_0,  Y_l = Q_l - Q_{l-1}
+ * (Sec. 2.2, eq. mlmc_average), with D = [0,1]^3, f = 1, u0 = 0, a log-normal
+ * kappa given by a Karhunen-Loeve expansion with exponential covariance
+ * (Sec. 5.2), Q1 hexahedral meshes with n_l = n0 * 2^l elements per side
+ * (Sec. 2.2, s = 2), and one batched finite-element solve per sample and mesh.
+ *
+ * Conventions shared by every entry point
+ *   Status: every call returns an int status (MLMC_OK, MLMC_PENDING or a
+ *     negative MLMC_E_* code).  On error, mlmc_last_error(ctx) describes it;
+ *     outputs are left unspecified unless stated otherwise.
+ *   Memory: the library allocates no device memory.  All device work space
+ *     comes from the caller's arena (mlmc_config.arena/arena_bytes), which is
+ *     the device-memory budget; pointers documented as "device" are caller
+ *     owned device allocations, "host" pointers are caller-owned host memory.
+ *   Stream: all device work of a context is issued on mlmc_config.stream
+ *     (a hipStream_t; NULL = the null stream).  Step-level calls return once
+ *     work is queued; whole-path calls (sample_level, estimate) synchronise.
+ *   Threading: a context is used by one host thread at a time.
+ *
+ * Layouts
+ *   Interior node (i, j, k), 1 <= i, j, k <= n-1, of an n^3 mesh; element
+ *   e = ex + n*(ey + n*ez), 0 <= ex, ey, ez < n.
+ *   "grid layout" vector of a batch of B samples on mesh n: B blocks of
+ *     mlmc_grid_stride(n) entries; node (i, j, k) of sample b sits at
+ *     b*stride + i + n*j + n*n*k.  Every entry that is not an interior node
+ *     (i == 0, j == 0, k == 0, k == n, and the tail padding) must hold 0 and
+ *     is never written by the library.
+ *   "element layout" coefficient of a batch: B blocks of n^3 entries,
+ *     element e of sample b at b*n^3 + e.
+ */
+#ifndef MLMC_H
+#define MLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MLMC_OK = 0,
+  MLMC_PENDING = 1,       /* mlmc_poll: the request has not finished yet */
+  MLMC_E_INVALID = -1,    /* bad argument or configuration */
+  MLMC_E_NOMEM = -2,      /* the arena cannot hold the work space of the call */
+  MLMC_E_BUDGET = -3,     /* a request does not fit the HBM budget at all */
+  MLMC_E_NOCONV = -4,     /* a solve hit max_iter above its tolerance */
+  MLMC_E_NONFINITE = -5,  /* a NaN or Inf appeared in a field or residual */
+  MLMC_E_DEVICE = -6      /* a HIP runtime call failed */
+};
+
+enum { MLMC_QOI_DOMAIN_AVERAGE = 0, MLMC_QOI_SUBCUBE_AVERAGE = 1 };
+enum { MLMC_PREC_FP64 = 0, MLMC_PREC_MIXED = 1 };
+enum { MLMC_SOLVER_GMG_PCG = 0, MLMC_SOLVER_JACOBI_PCG = 1 };
+
+typedef struct mlmc_config {
+  int32_t n0;          /* elements per side of the coarsest MLMC mesh, >= 2, power of 2 */
+  int32_t levels;      /* L + 1 >= 1; level l uses n0 << l elements per side */
+  double sigma2;       /* variance of the Gaussian log-field, >= 0 */
+  double corr_len;     /* correlation length of exp(-|dx|/corr_len), > 0 */
+  int32_t n_modes;     /* number M of 3D KL modes (length of xi), 1..4096 */
+  uint64_t seed;       /* Philox key word 0 */
+  int32_t qoi;         /* MLMC_QOI_*; the subcube QoI needs 4 | n on every mesh */
+  double rtol;         /* true relative residual ||b - A x||_2 / ||b||_2 to reach */
+  int32_t max_iter;    /* cap on PCG iterations (outer + inner for mixed) */
+  int32_t precision;   /* MLMC_PREC_* */
+  int32_t solver;      /* MLMC_SOLVER_* */
+  int32_t cheb_degree; /* Chebyshev smoothing degree per half V-cycle, 1..8 (0: 2) */
+  int32_t max_batch;   /* largest number of samples solved together, >= 1 */
+  void* arena;         /* device memory owned by the caller, 256-byte aligned */
+  size_t arena_bytes;  /* size of the arena: the HBM budget of the context */
+  void* stream;        /* hipStream_t for all device work of the context */
+} mlmc_config;
+
+typedef struct mlmc_ctx mlmc_ctx;
+
+typedef struct mlmc_level_stats {
+  uint64_t n;          /* samples accumulated */
+  double mean;         /* mean of Y_l */
+  double m2;           /* sum of squared deviations from the mean */
+  double var;          /* m2 / n, the 1/N sample variance of eq. sample_variance */
+  double cost;         /* mean cost per sample used by the allocation (see below) */
+} mlmc_level_stats;
+
+typedef struct mlmc_estimate_out {
+  double qtilde;       /* sum_l mean(Y_l), eq. mlmc_average */
+  double var_qtilde;   /* sum_l var_l / n_l, Sec. 2.2 */
+  int32_t levels;      /* number of levels reported below */
+  mlmc_level_stats level[16];
+} mlmc_estimate_out;
+
+/* ------------------------------------------------------------------ setup */
+
+/* Create a context for the configuration; computes the 1D KL eigenpairs and
+ * the M-mode 3D selection on the host (Sec. 5.2, KLE with exponential
+ * covariance).  *out receives the context, or NULL on error.
+ * Errors: MLMC_E_INVALID for a bad field, MLMC_E_DEVICE. */
+int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out);
+
+/* Destroy a context; cancels requests still queued.  NULL is ignored. */
+void mlmc_destroy(mlmc_ctx* ctx);
+
+/* Text of the last error of the context (or of the last failed create when
+ * ctx is NULL).  Valid until the next call on the context. */
+const char* mlmc_last_error(const mlmc_ctx* ctx);
+
+/* Entries per sample in the grid layout of an n^3 mesh (>= (n+1) n^2). */
+size_t mlmc_grid_stride(int32_t n);
+
+/* Arena bytes needed by mlmc_sample_level for `batch` samples of `level`
+ * under the configuration (without creating a context). */
+size_t mlmc_workspace_bytes(const mlmc_config* cfg, int32_t level, int32_t batch);
+
+/* The selected 3D modes: triples[3*m + d] is the 1D mode index of axis d of
+ * mode m and lambda[m] = sigma2 * lambda_i lambda_j lambda_k (host arrays of
+ * n_modes entries each; either may be NULL). */
+int mlmc_modes(const mlmc_ctx* ctx, int32_t* triples, double* lambda);
+
+/* ------------------------------------------- step-level entry points (device) */
+
+/* K1 -- xi[s*n_modes + m] (device, fp64, [count][n_modes]) for the samples
+ * first .. first+count-1 of `level`: Philox4x64-10 blocks with key (seed, 0)
+ * and counter (sample, level, block, 0), uniforms ((w >> 12) + 1/2) 2^-52 and
+ * Box-Muller pairs.  The randomness of omega in Sec. 2.1, drawn per sample
+ * index as the batches of Sec. 4.2 hand them out. */
+int mlmc_draw_xi(mlmc_ctx* ctx, int32_t level, uint64_t first, int64_t count, double* xi);
+
+/* K2 -- kappa (device, element layout, fp64) = exp(sum_m sqrt(lambda_m)
+ * phi_m(c_e) xi_m) at the element centroids c_e of the n^3 mesh, for `count`
+ * samples whose xi (device, [count][n_modes]) is given.  Log-normal KLE
+ * coefficient of Sec. 5.2; the contraction runs on fp64 MFMA.
+ * kappa32 (device, may be NULL) receives the same values rounded to fp32. */
+int mlmc_field(mlmc_ctx* ctx, int32_t n, int64_t count, const double* xi,
+               double* kappa, float* kappa32);
+
+/* K5 -- y = A(kappa) u for `count` samples on the n^3 mesh: the Q1 stiffness
+ * of eq. model with per-element kappa and homogeneous Dirichlet rows and
+ * columns eliminated (Sec. 2.1-2.2).  u, y: device, grid layout, fp64;
+ * kappa: device, element layout, fp64.  u and y must not overlap. */
+int mlmc_apply(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa,
+               const double* u, double* y);
+
+/* One multigrid V-cycle z = B(kappa) r of the preconditioner used by the
+ * GMG-PCG solve (rediscretised coarse operators with the 8-child mean of
+ * kappa, trilinear transfers, Chebyshev-Jacobi smoothing of degree
+ * cheb_degree on [1/2, 2] of D^-1 A, exact solve on the 2^3 mesh).
+ * r, z: device, grid layout, fp64; kappa: device, element layout, fp64. */
+int mlmc_vcycle(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa,
+                const double* r, double* z);
+
+/* Solve A(kappa) u = b for f = 1 (b_i = h^3) for `count` samples with the
+ * configured solver and precision, starting from u = 0, to the configured
+ * true relative residual.  u: device, grid layout, fp64 (output);
+ * iters (host, may be NULL) receives the PCG iteration count per sample.
+ * Returns MLMC_E_NOCONV if some sample did not converge (u holds the last
+ * iterate). */
+int mlmc_solve(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa,
+               double* u, int32_t* iters);
+
+/* K13 -- q[s] = Q(u_s) (device, fp64, [count]) for the configured QoI:
+ * domain average h^3 sum_i u_i, or the mean of u_h over [1/4, 3/4]^3 as the
+ * exact integral of the trilinear interpolant (Sec. 2.1, "an integral of u
+ * on a sub-region").  u: device, grid layout. */
+int mlmc_qoi(mlmc_ctx* ctx, int32_t n, int64_t count, const double* u, double* q);
+
+/* -------------------------------------------------- whole path (host out) */
+
+/* Draw, field, solve and QoI for the samples first .. first+count-1 of
+ * `level`; a level l > 0 sample solves the n_l and n_{l-1} meshes on the same
+ * xi and returns Y = Q_l - Q_{l-1} (Sec. 2.2), level 0 returns Y = Q_0.
+ * y, q_fine, q_coarse (q_coarse = 0 at level 0) are host arrays of `count`
+ * doubles; iters (host, may be NULL) gets the fine-mesh iteration counts.
+ * The samples are also folded into the context's running statistics of the
+ * level (count, mean, M2 by the Chan et al. merge in sample order).
+ * Work is split into batches of at most max_batch samples.
+ * Errors: MLMC_E_NOMEM if the arena cannot hold one batch, MLMC_E_NOCONV. */
+int mlmc_sample_level(mlmc_ctx* ctx, int32_t level, uint64_t first, uint64_t count,
+                      double* y, double* q_fine, double* q_coarse, int32_t* iters);
+
+/* Running statistics of every level and the estimator of eq. mlmc_average
+ * with the statistical error sum_l V(Y_l)/N_l (Sec. 2.2). */
+int mlmc_get_estimate(const mlmc_ctx* ctx, mlmc_estimate_out* out);
+
+/* Clear the running statistics of every level. */
+int mlmc_reset_stats(mlmc_ctx* ctx);
+
+/* ----------------------------------------------------------- diagnostics */
+
+/* Enable (1) or disable (0) per-kernel event timing on the context stream
+ * (clears the counters), and read the launch count, total event-timed
+ * milliseconds and total algorithmic bytes (bytes a kernel must move at
+ * minimum: every distinct vector read or written once) of kernel `kernel_id`
+ * (MLMC_K_*) in `precision` (0: fp64 instance, 1: fp32 instance) since
+ * timing was enabled. */
+enum {
+  MLMC_K_XI = 0, MLMC_K_FIELD, MLMC_K_APPLY, MLMC_K_CHEB_ZERO, MLMC_K_CHEB, MLMC_K_CHEB_XO,
+  MLMC_K_RESIDUAL, MLMC_K_RESTRICT, MLMC_K_PROLONG, MLMC_K_COARSEST, MLMC_K_COARSEN,
+  MLMC_K_PCG_APPLY, MLMC_K_PCG_UPDATE, MLMC_K_PCG_DOT, MLMC_K_PCG_DIRECTION,
+  MLMC_K_TRUE_RESIDUAL, MLMC_K_REDUCE, MLMC_K_QOI, MLMC_K_MISC, MLMC_K_COUNT
+};
+int mlmc_set_profiling(mlmc_ctx* ctx, int32_t on);
+int mlmc_kernel_time(mlmc_ctx* ctx, int32_t kernel_id, int32_t precision, int64_t* launches,
+                     double* total_ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLMC_H */

@@ -1,0 +1,259 @@
+"""Python binding of the MI355X MLMC finite-element library (libmlmc.so).
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels
+behind the C-ABI declared in include/mlmc.h.  PyTorch supplies the device
+memory (one arena tensor per context, plus the input/output tensors of the
+step-level calls) and the stream.  There is no CPU fallback: if the shared
+library is missing the first use raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlmc.so")
+
+MLMC_OK, MLMC_PENDING = 0, 1
+ERRORS = {-1: "MLMC_E_INVALID", -2: "MLMC_E_NOMEM", -3: "MLMC_E_BUDGET", -4: "MLMC_E_NOCONV",
+          -5: "MLMC_E_NONFINITE", -6: "MLMC_E_DEVICE"}
+KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "RESTRICT", "PROLONG",
+           "COARSEST", "COARSEN", "PCG_APPLY", "PCG_UPDATE", "PCG_DOT", "PCG_DIRECTION", "TRUE_RESIDUAL",
+           "REDUCE", "QOI", "MISC"]
+
+# exported symbols of include/mlmc.h (checked by the CPU test suite)
+SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
+           "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_vcycle", "mlmc_solve", "mlmc_qoi",
+           "mlmc_sample_level", "mlmc_get_estimate", "mlmc_reset_stats", "mlmc_set_profiling",
+           "mlmc_kernel_time"]
+
+
+class MLMCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int32), ("levels", ctypes.c_int32), ("sigma2", ctypes.c_double),
+                ("corr_len", ctypes.c_double), ("n_modes", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("qoi", ctypes.c_int32), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("solver", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
+                ("stream", ctypes.c_void_p)]
+
+
+class LevelStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("mean", ctypes.c_double), ("m2", ctypes.c_double),
+                ("var", ctypes.c_double), ("cost", ctypes.c_double)]
+
+
+class EstimateOut(ctypes.Structure):
+    _fields_ = [("qtilde", ctypes.c_double), ("var_qtilde", ctypes.c_double), ("levels", ctypes.c_int32),
+                ("level", LevelStats * 16)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C-ABI library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "mlmc_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(P)]),
+        "mlmc_destroy": (None, [P]),
+        "mlmc_last_error": (ctypes.c_char_p, [P]),
+        "mlmc_grid_stride": (ctypes.c_size_t, [I32]),
+        "mlmc_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config), I32, I32]),
+        "mlmc_modes": (ctypes.c_int, [P, P, P]),
+        "mlmc_draw_xi": (ctypes.c_int, [P, I32, U64, I64, P]),
+        "mlmc_field": (ctypes.c_int, [P, I32, I64, P, P, P]),
+        "mlmc_apply": (ctypes.c_int, [P, I32, I64, P, P, P]),
+        "mlmc_vcycle": (ctypes.c_int, [P, I32, I64, P, P, P]),
+        "mlmc_solve": (ctypes.c_int, [P, I32, I64, P, P, P]),
+        "mlmc_qoi": (ctypes.c_int, [P, I32, I64, P, P]),
+        "mlmc_sample_level": (ctypes.c_int, [P, I32, U64, U64, P, P, P, P]),
+        "mlmc_get_estimate": (ctypes.c_int, [P, ctypes.POINTER(EstimateOut)]),
+        "mlmc_reset_stats": (ctypes.c_int, [P]),
+        "mlmc_set_profiling": (ctypes.c_int, [P, I32]),
+        "mlmc_kernel_time": (ctypes.c_int, [P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(D),
+                                            ctypes.POINTER(D)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def grid_stride(n: int) -> int:
+    return int(lib().mlmc_grid_stride(n))
+
+
+def make_config(wl, arena_ptr: int = 0, arena_bytes: int = 0, stream: int = 0, **over) -> Config:
+    """mlmc_config from a workloads.Workload (fields may be overridden)."""
+    v = dict(n0=wl.n0, levels=wl.levels, sigma2=wl.sigma2, corr_len=wl.corr_len, n_modes=wl.n_modes,
+             seed=wl.seed, qoi=wl.qoi, rtol=wl.rtol, max_iter=wl.max_iter, precision=wl.precision,
+             solver=wl.solver, cheb_degree=0, max_batch=max(1, wl.batch or 64))
+    v.update(over)
+    return Config(v["n0"], v["levels"], v["sigma2"], v["corr_len"], v["n_modes"], v["seed"], v["qoi"],
+                  v["rtol"], v["max_iter"], v["precision"], v["solver"], v["cheb_degree"], v["max_batch"],
+                  arena_ptr, arena_bytes, stream)
+
+
+def workspace_bytes(cfg: Config, level: int, batch: int) -> int:
+    return int(lib().mlmc_workspace_bytes(ctypes.byref(cfg), level, batch))
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else t.data_ptr()
+
+
+class Context:
+    """One library context on cuda:0 with its own arena tensor."""
+
+    def __init__(self, wl, arena_bytes: Optional[int] = None, **over):
+        import torch
+        self.torch = torch
+        self.wl = wl
+        probe = make_config(wl, **over)
+        if arena_bytes is None:
+            need = max(workspace_bytes(probe, l, probe.max_batch) for l in range(probe.levels))
+            fp64 = make_config(wl, **dict(over, precision=0, solver=0))
+            need = max(need, max(workspace_bytes(fp64, l, probe.max_batch) for l in range(probe.levels)))
+            arena_bytes = need + (1 << 20)
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+        self.stream = torch.cuda.current_stream()
+        self.cfg = make_config(wl, self.arena.data_ptr(), arena_bytes, self.stream.cuda_stream, **over)
+        h = ctypes.c_void_p()
+        rc = lib().mlmc_create(ctypes.byref(self.cfg), ctypes.byref(h))
+        if rc:
+            raise MLMCError(rc, lib().mlmc_last_error(None).decode())
+        self.h = h
+        self.M = self.cfg.n_modes
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mlmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, allow=()):
+        if rc and rc not in allow:
+            raise MLMCError(rc, lib().mlmc_last_error(self.h).decode())
+        return rc
+
+    # --- step-level calls (device tensors) -----------------------------------
+    def modes(self):
+        tri = np.zeros((self.M, 3), dtype=np.int32)
+        lam = np.zeros(self.M)
+        self._check(lib().mlmc_modes(self.h, tri.ctypes.data, lam.ctypes.data))
+        return tri, lam
+
+    def draw_xi(self, level: int, first: int, count: int):
+        xi = self.torch.empty((count, self.M), dtype=self.torch.float64, device="cuda")
+        self._check(lib().mlmc_draw_xi(self.h, level, first, count, _ptr(xi)))
+        return xi
+
+    def field(self, n: int, xi, want32: bool = False):
+        B = xi.shape[0]
+        k = self.torch.empty((B, n ** 3), dtype=self.torch.float64, device="cuda")
+        k32 = self.torch.empty((B, n ** 3), dtype=self.torch.float32, device="cuda") if want32 else None
+        self._check(lib().mlmc_field(self.h, n, B, _ptr(xi.contiguous()), _ptr(k), _ptr(k32)))
+        return (k, k32) if want32 else k
+
+    def apply(self, n: int, kappa, u_grid):
+        y = self.torch.zeros_like(u_grid)
+        self._check(lib().mlmc_apply(self.h, n, u_grid.shape[0], _ptr(kappa), _ptr(u_grid), _ptr(y)))
+        return y
+
+    def vcycle(self, n: int, kappa, r_grid):
+        z = self.torch.zeros_like(r_grid)
+        self._check(lib().mlmc_vcycle(self.h, n, r_grid.shape[0], _ptr(kappa), _ptr(r_grid), _ptr(z)))
+        return z
+
+    def solve(self, n: int, kappa, allow_noconv: bool = False):
+        B = kappa.shape[0]
+        u = self.torch.zeros((B, grid_stride(n)), dtype=self.torch.float64, device="cuda")
+        it = np.zeros(B, dtype=np.int32)
+        rc = lib().mlmc_solve(self.h, n, B, _ptr(kappa), _ptr(u), it.ctypes.data)
+        self._check(rc, allow=(-4,) if allow_noconv else ())
+        return u, it
+
+    def qoi(self, n: int, u_grid):
+        q = self.torch.empty(u_grid.shape[0], dtype=self.torch.float64, device="cuda")
+        self._check(lib().mlmc_qoi(self.h, n, u_grid.shape[0], _ptr(u_grid), _ptr(q)))
+        return q
+
+    # --- whole path (host outputs) -------------------------------------------
+    def sample_level(self, level: int, first: int, count: int):
+        y = np.zeros(count)
+        qf = np.zeros(count)
+        qc = np.zeros(count)
+        it = np.zeros(count, dtype=np.int32)
+        self._check(lib().mlmc_sample_level(self.h, level, first, count, y.ctypes.data, qf.ctypes.data,
+                                            qc.ctypes.data, it.ctypes.data))
+        return y, qf, qc, it
+
+    def get_estimate(self):
+        out = EstimateOut()
+        self._check(lib().mlmc_get_estimate(self.h, ctypes.byref(out)))
+        lv = [dict(n=out.level[l].n, mean=out.level[l].mean, m2=out.level[l].m2, var=out.level[l].var,
+                   cost=out.level[l].cost) for l in range(out.levels)]
+        return dict(qtilde=out.qtilde, var_qtilde=out.var_qtilde, levels=lv)
+
+    def reset_stats(self):
+        self._check(lib().mlmc_reset_stats(self.h))
+
+    def set_profiling(self, on: bool):
+        self._check(lib().mlmc_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_time(self, name: str, precision: int = 0):
+        """(launches, total ms, algorithmic bytes) of one kernel; precision 0 fp64, 1 fp32."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        self._check(lib().mlmc_kernel_time(self.h, KERNELS.index(name), precision, ctypes.byref(n),
+                                           ctypes.byref(ms), ctypes.byref(by)))
+        return n.value, ms.value, by.value
+
+
+# --- layout marshalling (index bookkeeping only) ------------------------------
+
+def interior_positions(n: int) -> np.ndarray:
+    """Grid-layout position of every interior node, in canonical order
+    g = (i-1) + (n-1)((j-1) + (n-1)(k-1)); position = i + n j + n^2 k."""
+    m = n - 1
+    g = np.arange(m ** 3)
+    i, j, k = g % m + 1, (g // m) % m + 1, g // (m * m) + 1
+    return i + n * j + n * n * k
+
+
+def to_grid(v, n: int):
+    """[B, (n-1)^3] canonical (torch, cuda) -> [B, stride] grid layout with zero boundary."""
+    import torch
+    pos = torch.as_tensor(interior_positions(n), device=v.device)
+    out = torch.zeros((v.shape[0], grid_stride(n)), dtype=v.dtype, device=v.device)
+    out[:, pos] = v
+    return out
+
+
+def from_grid(g, n: int):
+    import torch
+    pos = torch.as_tensor(interior_positions(n), device=g.device)
+    return g[:, pos]

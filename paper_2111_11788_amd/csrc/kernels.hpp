@@ -1,0 +1,96 @@
+// Host-callable launchers of the HIP kernels (implemented in the .hip files).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mlmc {
+
+// rng.hip
+hipError_t launch_draw_xi(uint64_t seed, int level, uint64_t first, int64_t count, int M,
+                          double* xi, hipStream_t st);
+
+// field.hip: kappa[b][e] = exp(sum_m xi[b][m] sqrtlam[m] tab[ex][t0] tab[ey][t1] tab[ez][t2])
+hipError_t launch_field(int n, int M, int64_t count, const double* xi, const double* sqrtlam,
+                        const int* triples, const double* tab, int K1, double* kappa,
+                        float* kappa32, hipStream_t st);
+
+// Per-sample scalar state of a batched Krylov solve (device arrays of B entries).
+struct SolveState {
+  double* rz;       // r . z of the current iteration
+  double* alpha;
+  double* beta;
+  double* rr;       // ||r||^2
+  double* bb;       // ||b||^2
+  double* partial;  // [B][nchunk] partial sums of the current reduction
+  int* active;      // 1 while the sample iterates
+  int* iters;       // iterations done
+  int* nactive;     // single counter (device) of active samples
+  int nchunk;       // partial sums per sample
+};
+
+// stencil.hip -- grid-layout kernels on an n^3 mesh for `B` samples; `active`
+// (may be null) skips samples whose flag is 0.
+template <class T>
+hipError_t launch_apply(int n, int B, const T* kap, const T* u, T* y, const int* active, hipStream_t st);
+template <class T>
+hipError_t launch_residual(int n, int B, const T* kap, const T* b, const T* x, T* r,
+                           const int* active, hipStream_t st);
+// Chebyshev step.  zero_x: out = c2 D^-1 b (x0 = 0).  Otherwise
+// out = x + c1 (x - xo) + c2 D^-1 (b - A x), where use_xo == 0 takes xo = 0.
+// out may alias xo, never x.
+template <class T>
+hipError_t launch_cheb(int n, int B, const T* kap, const T* b, const T* x, const T* xo, T* out,
+                       double c1, double c2, bool zero_x, bool use_xo, const int* active,
+                       hipStream_t st);
+template <class T>
+hipError_t launch_restrict(int nf, int B, const T* rf, T* bc, const int* active, hipStream_t st);
+template <class T>
+hipError_t launch_prolong_add(int nf, int B, const T* xc, T* xf, const int* active, hipStream_t st);
+template <class T>
+hipError_t launch_coarsest(int B, const T* kap, const T* b, T* x, const int* active, hipStream_t st);
+template <class T>
+hipError_t launch_coarsen(int nf, int B, const T* kf, T* kc, hipStream_t st);
+template <class Ts, class Td>
+hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st);
+template <class T>
+hipError_t launch_fill_interior(int n, int B, T* v, double value, const int* active, hipStream_t st);
+
+// krylov.hip -- PCG building blocks, fp64 scalars and partial sums.
+int krylov_chunks(int n);
+template <class T>
+hipError_t launch_pcg_apply_dot(int n, int B, const T* kap, const T* p, T* q, SolveState s,
+                                hipStream_t st);
+template <class T>
+hipError_t launch_pcg_update(int n, int B, T* x, const T* p, T* r, const T* q, SolveState s,
+                             hipStream_t st);
+template <class Ta, class Tb>
+hipError_t launch_dot(int n, int B, const Ta* a, const Tb* b, SolveState s, hipStream_t st);
+template <class T>
+hipError_t launch_pcg_direction(int n, int B, const T* z, T* p, SolveState s, hipStream_t st);
+// outer residual of the refinement loop: r = b - A x in fp64 plus ||r||^2 partials
+hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x,
+                                double* r, SolveState s, hipStream_t st);
+// x64 += d (fp32 correction) on active samples
+hipError_t launch_add_correction(int n, int B, double* x, const float* d, SolveState s,
+                                 hipStream_t st);
+// r32 = (float) r64 on active samples
+hipError_t launch_demote(int n, int B, const double* r, float* r32, SolveState s, hipStream_t st);
+
+enum ReduceOp : int {
+  RED_BB = 0,       // bb = sum
+  RED_ALPHA = 1,    // alpha = rz / sum; iters += 1
+  RED_RR = 2,       // rr = sum; converged when rr <= tol2 * bb -> active = 0
+  RED_RZ_INIT = 3,  // rz = sum
+  RED_BETA = 4,     // beta = sum / rz; rz = sum
+  RED_STORE = 5     // out[b] = sum
+};
+hipError_t launch_reduce(int B, int op, double tol2, SolveState s, double* out, hipStream_t st);
+hipError_t launch_count_active(int B, SolveState s, hipStream_t st);
+hipError_t launch_set_active(int B, SolveState s, int value, hipStream_t st);
+
+// qoi.hip: partial sums of w . u into s.partial (reduce with RED_STORE)
+hipError_t launch_qoi_partial(int n, int B, int qoi, const double* u, SolveState s,
+                              hipStream_t st);
+
+}  // namespace mlmc

@@ -1,0 +1,159 @@
+"""GPU parity of every hot-path step against the CPU oracle (through the C-ABI).
+
+Tolerances
+  xi, index maps            bit-exact (integer/bit work and fixed op sequences)
+  kappa                     relative 1e-13 (fp64 MFMA contraction order differs)
+  operator apply, V-cycle   1e-13 of the row scale |kappa| |u| h (fp64 summation order)
+  per-sample QoI            relative 1e-8 (fp64 path), 1e-7 (mixed path), both
+                            solvers taken to true relative residual 1e-12
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_2111_11788_amd as mm
+from oracle import fe, field, gmg, mlmc as omlmc, pcg, rng
+from workloads import C1, C2, Workload, element_field, grid_vector
+
+
+def _wl(**kw):
+    base = dict(name="t", n0=4, levels=3, sigma2=1.0, corr_len=0.5, n_modes=8, qoi=0, rtol=1e-12,
+                max_iter=3000, solver=0, precision=0, batch=16)
+    base.update(kw)
+    return Workload(**base)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    mm.lib()
+    return torch.device("cuda")
+
+
+@pytest.mark.parametrize("seed,level,first,count,M", [
+    (20211123, 0, 0, 7, 8), (1, 3, 1000, 33, 13), (2**63 + 5, 1, 2**40, 5, 64), (7, 2, 0, 3, 1),
+    (99, 0, 5, 64, 512)])
+def test_xi_bit_exact(dev, seed, level, first, count, M):
+    ctx = mm.Context(_wl(seed=seed, n_modes=M, levels=4), arena_bytes=64 << 20)
+    xi = ctx.draw_xi(level, first, count).cpu().numpy()
+    want = rng.draw_xi(seed, level, first, count, M)
+    assert xi.shape == want.shape
+    bad = np.nonzero(xi.view(np.uint64) != want.view(np.uint64))
+    assert bad[0].size == 0, f"{bad[0].size} mismatches, first at {bad[0][0]},{bad[1][0]}: " \
+                             f"{xi[bad][0]!r} vs {want[bad][0]!r}"
+
+
+@pytest.mark.parametrize("corr,M,sigma2", [(0.5, 8, 1.0), (0.3, 64, 1.0), (0.2, 128, 1.0), (0.1, 512, 2.0)])
+def test_modes_match_oracle(dev, corr, M, sigma2):
+    ctx = mm.Context(_wl(corr_len=corr, n_modes=M, sigma2=sigma2), arena_bytes=64 << 20)
+    tri, lam = ctx.modes()
+    from oracle import kl
+    t2, l2, *_ = kl.select_modes(corr, sigma2, M)
+    assert np.array_equal(tri, t2)
+    assert np.allclose(lam, l2, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("n,M,corr,count", [(4, 8, 0.5, 3), (8, 13, 0.3, 70), (16, 64, 0.3, 17), (32, 130, 0.2, 5)])
+def test_field_matches_oracle(dev, n, M, corr, count):
+    wl = _wl(n0=n, levels=1, n_modes=M, corr_len=corr)
+    ctx = mm.Context(wl, arena_bytes=64 << 20)
+    xi = ctx.draw_xi(0, 3, count)
+    k, k32 = ctx.field(n, xi, want32=True)
+    want = field.kappa(n, corr, 1.0, M, rng.draw_xi(wl.seed, 0, 3, count, M))
+    got = k.cpu().numpy()
+    rel = np.abs(got - want) / want
+    assert rel.max() < 1e-13, rel.max()
+    assert np.array_equal(k32.cpu().numpy(), got.astype(np.float32))
+
+
+@pytest.mark.parametrize("n,B", [(4, 3), (8, 5), (16, 2), (32, 1)])
+def test_apply_matches_csr(dev, n, B):
+    kap = element_field(n, B, seed=100 + n)
+    u = grid_vector(n, B, seed=200 + n)
+    ctx = mm.Context(_wl(n0=n, levels=1), arena_bytes=64 << 20)
+    kt = torch.tensor(kap, device=dev)
+    ug = mm.to_grid(torch.tensor(u, device=dev), n)
+    yg = ctx.apply(n, kt, ug)
+    y = mm.from_grid(yg, n).cpu().numpy()
+    # boundary / padding entries stay zero
+    mask = np.ones(yg.shape[1], dtype=bool)
+    mask[mm.interior_positions(n)] = False
+    assert np.all(yg.cpu().numpy()[:, mask] == 0.0)
+    for b in range(B):
+        A = fe.assemble(n, kap[b])
+        want = A @ u[b]
+        scale = np.abs(A).max() * 27 * np.abs(u[b]).max()
+        assert np.abs(y[b] - want).max() <= 1e-14 * scale
+
+
+@pytest.mark.parametrize("n,B,deg", [(4, 2, 2), (8, 3, 2), (16, 2, 3), (32, 1, 1)])
+def test_vcycle_matches_oracle(dev, n, B, deg):
+    kap = element_field(n, B, seed=300 + n, spread=1.5)
+    r = grid_vector(n, B, seed=400 + n)
+    ctx = mm.Context(_wl(n0=n, levels=1), cheb_degree=deg, arena_bytes=256 << 20)
+    z = mm.from_grid(ctx.vcycle(n, torch.tensor(kap, device=dev), mm.to_grid(torch.tensor(r, device=dev), n)), n)
+    z = z.cpu().numpy()
+    for b in range(B):
+        H = gmg.Hierarchy(n, kap[b])
+        want = H.vcycle(r[b], deg, 4.0, 2.0)
+        assert np.abs(z[b] - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def _oracle_q(n, kap, qoi, rtol=1e-12):
+    q, it, rel, u = omlmc.solve_qoi(n, kap, qoi, rtol, 20000)
+    return q
+
+
+@pytest.mark.parametrize("precision,solver,tol", [(0, 0, 1e-8), (1, 0, 1e-7), (0, 1, 1e-8)])
+@pytest.mark.parametrize("n,B,qoi", [(8, 5, 0), (16, 3, 1), (32, 2, 1)])
+def test_solve_qoi_matches_oracle(dev, precision, solver, tol, n, B, qoi):
+    wl = _wl(n0=n, levels=1, qoi=qoi, precision=precision, solver=solver, n_modes=16, corr_len=0.3)
+    ctx = mm.Context(wl, arena_bytes=512 << 20)
+    xi = ctx.draw_xi(0, 11, B)
+    kap = ctx.field(n, xi)
+    u, it = ctx.solve(n, kap)
+    q = ctx.qoi(n, u).cpu().numpy()
+    kap_o = field.kappa(n, wl.corr_len, wl.sigma2, wl.n_modes, rng.draw_xi(wl.seed, 0, 11, B, wl.n_modes))
+    for b in range(B):
+        want = _oracle_q(n, kap_o[b], qoi)
+        assert abs(q[b] - want) <= tol * abs(want), (b, q[b], want, it[b])
+    # the returned solution meets the true-residual tolerance of the oracle's operator
+    uc = mm.from_grid(u, n).cpu().numpy()
+    bvec = fe.load_constant(n)
+    for b in range(B):
+        res = bvec - fe.assemble(n, kap_o[b]) @ uc[b]
+        assert np.linalg.norm(res) <= 1.5e-12 * np.linalg.norm(bvec)
+
+
+def test_gmg_iterations_are_few(dev):
+    wl = _wl(n0=32, levels=1, n_modes=64, corr_len=0.3, rtol=1e-8, precision=0)
+    ctx = mm.Context(wl, arena_bytes=512 << 20)
+    kap = ctx.field(32, ctx.draw_xi(0, 0, 4))
+    _, it = ctx.solve(32, kap)
+    assert it.max() <= 12, it
+
+
+def test_sample_level_c1_matches_oracle(dev):
+    wl = _wl(n0=4, levels=3, n_modes=8, corr_len=0.5, solver=1, rtol=1e-12, batch=8)
+    ctx = mm.Context(wl, arena_bytes=256 << 20)
+    for level, count in ((0, 10), (1, 6), (2, 3)):
+        y, qf, qc, it = ctx.sample_level(level, 2, count)
+        yo, qfo, qco, _ = omlmc.sample_level(wl, level, 2, count, rtol=1e-12, max_iter=20000)
+        assert np.all(np.abs(qf - qfo) <= 1e-8 * np.abs(qfo))
+        assert np.all(np.abs(qc - qco) <= 1e-8 * np.abs(qco) + 1e-300)
+        assert np.all(np.abs(y - yo) <= 1e-8 * np.abs(qfo))
+    est = ctx.get_estimate()
+    assert [l["n"] for l in est["levels"]] == [10, 6, 3]
+
+
+def test_batch_composition_does_not_change_results(dev):
+    # a sample solved alone and inside a batch gives the same bits
+    wl = _wl(n0=16, levels=2, n_modes=32, corr_len=0.3, rtol=1e-10, precision=1, batch=7)
+    ctx = mm.Context(wl, arena_bytes=512 << 20)
+    y, qf, qc, it = ctx.sample_level(1, 0, 7)
+    ctx1 = mm.Context(wl, arena_bytes=512 << 20, max_batch=1)
+    y1, qf1, qc1, it1 = ctx1.sample_level(1, 3, 1)
+    assert qf1[0] == qf[3] and qc1[0] == qc[3] and it1[0] == it[3]
