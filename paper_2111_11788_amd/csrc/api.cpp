@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "grid.hpp"
 #include "kernels.hpp"
 #include "kl_host.hpp"
 
@@ -83,13 +84,13 @@ struct Level {
 struct StateBufs {
   SolveState s{};
   void carve(Carver& cv, int B, int n) {
-    s.nchunk = krylov_chunks(n);
+    s.pstride = max_parts(n, B);
     s.rz = cv.take<double>(B);
     s.alpha = cv.take<double>(B);
     s.beta = cv.take<double>(B);
     s.rr = cv.take<double>(B);
     s.bb = cv.take<double>(B);
-    s.partial = cv.take<double>((size_t)B * s.nchunk);
+    s.partial = cv.take<double>((size_t)B * s.pstride);
     s.active = cv.take<int>(B);
     s.iters = cv.take<int>(B);
     s.nactive = cv.take<int>(1);
@@ -454,18 +455,19 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
   const double sz = sizeof(T), d = dofs(n) * B, e = elems(n) * B;
   hipStream_t st = ctx->st;
   const size_t S0 = grid_stride(n);
+  uint32_t np = 0;
   T* z = nullptr;
   if (int rc = precondition<T>(ctx, L, B, r, &z, S.active)) return rc;
-  LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T, T>(n, B, r, z, S, st)));
-  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RZ_INIT, 0.0, S, nullptr, st));
+  LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RZ_INIT, 0.0, np, S, nullptr, st));
   HIPCHK(hipMemcpyAsync(p, z, (size_t)B * S0 * sizeof(T), hipMemcpyDeviceToDevice, st));
   const double tol2 = tol * tol;
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
-    LAUNCH(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, st));
-    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA, 0.0, S, nullptr, st));
-    LAUNCH(kid<T>(MLMC_K_PCG_UPDATE), 6 * d * sz, launch_pcg_update<T>(n, B, x, p, r, q, S, st));
-    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, tol2, S, nullptr, st));
+    LAUNCH(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, &np, st));
+    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA, 0.0, np, S, nullptr, st));
+    LAUNCH(kid<T>(MLMC_K_PCG_UPDATE), 6 * d * sz, launch_pcg_update<T>(n, B, x, p, r, q, S, &np, st));
+    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, tol2, np, S, nullptr, st));
     if (it >= 2) {
       int na = 0;
       if (int rc = count_active(ctx, S, B, &na)) return rc;
@@ -473,8 +475,8 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
     }
     if (it == max_iter) break;
     if (int rc = precondition<T>(ctx, L, B, r, &z, S.active)) return rc;
-    LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T, T>(n, B, r, z, S, st)));
-    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BETA, 0.0, S, nullptr, st));
+    LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
+    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BETA, 0.0, np, S, nullptr, st));
     LAUNCH(kid<T>(MLMC_K_PCG_DIRECTION), 3 * d * sz, launch_pcg_direction<T>(n, B, z, p, S, st));
   }
   *done_iters = std::min(it, max_iter);
@@ -490,6 +492,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
   const size_t S0 = grid_stride(n);
   const double d = dofs(n) * B, e = elems(n) * B;
   SolveState& O = w.outer.s;
+  uint32_t np = 0;
   LAUNCH(MLMC_K_MISC, 0, launch_set_active(B, O, 1, st));
   HIPCHK(hipMemsetAsync(O.iters, 0, B * sizeof(int), st));
   int total_it = 0;
@@ -501,16 +504,16 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
              launch_coarsen<double>(L[l - 1].n, B, L[l - 1].kap, L[l].kap, st));
     LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, u, 0.0, nullptr, st));
     LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, w.r, h3, nullptr, st));
-    LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double, double>(n, B, w.r, w.r, O, st)));
-    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, O, nullptr, st));
+    LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double>(n, B, w.r, w.r, O, &np, st)));
+    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
     for (int round = 0; round < 4 && total_it < ctx->cfg.max_iter; ++round) {
       int it = 0;
       if (int rc = pcg<double>(ctx, L, B, O, u, w.r, w.p, w.q, rtol, ctx->cfg.max_iter - total_it, &it)) return rc;
       total_it += it;
       // confirm with the true residual; samples above tolerance continue
       LAUNCH(MLMC_K_MISC, 0, launch_set_active(B, O, 1, st));
-      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r, O, st));
-      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, O, nullptr, st));
+      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r, O, &np, st));
+      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
       int na = 0;
       if (int rc = count_active(ctx, O, B, &na)) return rc;
       if (na == 0) break;
@@ -524,22 +527,22 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
              launch_coarsen<float>(L[l - 1].n, B, L[l - 1].kap, L[l].kap, st));
     LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, u, 0.0, nullptr, st));
     LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, w.r64, h3, nullptr, st));
-    LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double, double>(n, B, w.r64, w.r64, O, st)));
-    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, O, nullptr, st));
+    LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double>(n, B, w.r64, w.r64, O, &np, st)));
+    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
     HIPCHK(hipMemsetAsync(I.iters, 0, B * sizeof(int), st));
     for (int outer = 0; outer < kMaxOuter && total_it < ctx->cfg.max_iter; ++outer) {
       LAUNCH(MLMC_K_MISC, d * 12, launch_demote(n, B, w.r64, w.rin, O, st));
       HIPCHK(hipMemcpyAsync(I.active, O.active, B * sizeof(int), hipMemcpyDeviceToDevice, st));
       LAUNCH(MLMC_K_MISC, d * 4, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
-      LAUNCH(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, (launch_dot<float, float>(n, B, w.rin, w.rin, I, st)));
-      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, I, nullptr, st));
+      LAUNCH(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, (launch_dot<float>(n, B, w.rin, w.rin, I, &np, st)));
+      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, I, nullptr, st));
       int it = 0;
       if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it, &it))
         return rc;
       total_it += it;
       LAUNCH(MLMC_K_MISC, d * 20, launch_add_correction(n, B, u, w.d, O, st));
-      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r64, O, st));
-      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, O, nullptr, st));
+      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r64, O, &np, st));
+      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
       int na = 0;
       if (int rc = count_active(ctx, O, B, &na)) return rc;
       if (na == 0) break;
@@ -558,8 +561,9 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
 }
 
 int qoi_impl(mlmc_ctx* ctx, SolveState& S, int n, int B, const double* u, double* q) {
-  LAUNCH(MLMC_K_QOI, dofs(n) * B * 8, launch_qoi_partial(n, B, ctx->cfg.qoi, u, S, ctx->st));
-  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_STORE, 0.0, S, q, ctx->st));
+  uint32_t np = 0;
+  LAUNCH(MLMC_K_QOI, dofs(n) * B * 8, launch_qoi_partial(n, B, ctx->cfg.qoi, u, S, &np, ctx->st));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_STORE, 0.0, np, S, q, ctx->st));
   return MLMC_OK;
 }
 

@@ -9,9 +9,10 @@
 // v_mfma_f64_16x16x4_f64 with the xi tile.  exp (and the optional fp32 copy)
 // is applied in the epilogue, so g never round-trips through memory.
 //
-// Operand layout of v_mfma_f64_16x16x4_f64 (64 lanes): lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; it holds D[4 (l / 16) + r][l % 16]
-// in accumulator element r.  Rows = samples, columns = elements, K = modes.
+// Operand layout of v_mfma_f64_16x16x4_f64 (64 lanes, checked on gfx950 with a
+// probe of encoded operands): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator element r of lane l holds D[l / 16 + 4 r][l % 16].
+// Rows = samples, columns = elements, K = modes.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(256) k_field(int n, int M, int64_t count,
     const int64_t e = e0 + 64 * we + 16 * t + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t s = s0 + 16 * ws + 4 * (lane >> 4) + r;
+      const int64_t s = s0 + 16 * ws + (lane >> 4) + 4 * r;
       if (s < count && e < ne) {
         const double k = exp(acc[t][r]);
         kappa[s * ne + e] = k;

@@ -22,15 +22,15 @@ struct SolveState {
   double* beta;
   double* rr;       // ||r||^2
   double* bb;       // ||b||^2
-  double* partial;  // [B][nchunk] partial sums of the current reduction
+  double* partial;  // [B][pstride] partial sums of the current reduction
   int* active;      // 1 while the sample iterates
   int* iters;       // iterations done
   int* nactive;     // single counter (device) of active samples
-  int nchunk;       // partial sums per sample
+  uint32_t pstride; // capacity of partial sums per sample
 };
 
-// stencil.hip -- grid-layout kernels on an n^3 mesh for `B` samples; `active`
-// (may be null) skips samples whose flag is 0.
+// Grid-layout kernels on an n^3 mesh for `B` samples; `active` (may be null)
+// skips samples whose flag is 0.  Device pointers must be 16-byte aligned.
 template <class T>
 hipError_t launch_apply(int n, int B, const T* kap, const T* u, T* y, const int* active, hipStream_t st);
 template <class T>
@@ -56,21 +56,22 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st);
 template <class T>
 hipError_t launch_fill_interior(int n, int B, T* v, double value, const int* active, hipStream_t st);
 
-// krylov.hip -- PCG building blocks, fp64 scalars and partial sums.
-int krylov_chunks(int n);
+// PCG building blocks, fp64 scalars and partial sums.  Launchers that write
+// partial sums report in *nparts how many per sample they wrote.
 template <class T>
 hipError_t launch_pcg_apply_dot(int n, int B, const T* kap, const T* p, T* q, SolveState s,
-                                hipStream_t st);
+                                uint32_t* nparts, hipStream_t st);
 template <class T>
 hipError_t launch_pcg_update(int n, int B, T* x, const T* p, T* r, const T* q, SolveState s,
-                             hipStream_t st);
-template <class Ta, class Tb>
-hipError_t launch_dot(int n, int B, const Ta* a, const Tb* b, SolveState s, hipStream_t st);
+                             uint32_t* nparts, hipStream_t st);
+template <class T>
+hipError_t launch_dot(int n, int B, const T* a, const T* b, SolveState s, uint32_t* nparts,
+                      hipStream_t st);
 template <class T>
 hipError_t launch_pcg_direction(int n, int B, const T* z, T* p, SolveState s, hipStream_t st);
 // outer residual of the refinement loop: r = b - A x in fp64 plus ||r||^2 partials
 hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x,
-                                double* r, SolveState s, hipStream_t st);
+                                double* r, SolveState s, uint32_t* nparts, hipStream_t st);
 // x64 += d (fp32 correction) on active samples
 hipError_t launch_add_correction(int n, int B, double* x, const float* d, SolveState s,
                                  hipStream_t st);
@@ -85,12 +86,13 @@ enum ReduceOp : int {
   RED_BETA = 4,     // beta = sum / rz; rz = sum
   RED_STORE = 5     // out[b] = sum
 };
-hipError_t launch_reduce(int B, int op, double tol2, SolveState s, double* out, hipStream_t st);
+hipError_t launch_reduce(int B, int op, double tol2, uint32_t nparts, SolveState s, double* out,
+                         hipStream_t st);
 hipError_t launch_count_active(int B, SolveState s, hipStream_t st);
 hipError_t launch_set_active(int B, SolveState s, int value, hipStream_t st);
 
-// qoi.hip: partial sums of w . u into s.partial (reduce with RED_STORE)
+// partial sums of w . u into s.partial (reduce with RED_STORE)
 hipError_t launch_qoi_partial(int n, int B, int qoi, const double* u, SolveState s,
-                              hipStream_t st);
+                              uint32_t* nparts, hipStream_t st);
 
 }  // namespace mlmc

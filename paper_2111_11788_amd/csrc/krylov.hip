@@ -3,40 +3,21 @@
 // QoI reduction.  Vectors may be fp32 or fp64; every dot product and every
 // scalar is accumulated in fp64.
 //
+// The streaming kernels walk the flat range of planes 1..n-1 of each sample
+// (boundary positions included: they hold zero in every vector, so updates
+// keep them zero) in 16-byte vectors, several per thread.
+//
 // Reductions are deterministic and per sample: each workgroup (one chunk of
 // one sample) reduces its values in a fixed tree and writes one partial sum;
 // k_reduce then sums a sample's partials in a fixed order.  A sample's scalars
 // therefore never depend on which other samples share the batch.
 #include "common.hpp"
+#include "grid.hpp"
 #include "kernels.hpp"
 
 namespace mlmc {
 namespace {
 
-__device__ __forceinline__ int ilog2(int n) { return 31 - __clz(n); }
-
-struct Node {
-  uint32_t b, c, s;
-  bool ok;
-};
-
-__device__ __forceinline__ Node node_of_thread(int n, uint32_t nchunk) {
-  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
-  Node nd;
-  nd.b = logical / nchunk;
-  nd.c = logical - nd.b * nchunk;
-  const uint32_t n2 = (uint32_t)n * n;
-  const uint32_t p = n2 + nd.c * kBlock + threadIdx.x;
-  const uint32_t lg = (uint32_t)ilog2(n);
-  const uint32_t i = p & (n - 1), j = (p >> lg) & (n - 1);
-  nd.ok = (p < n2 * (uint32_t)n) && i != 0 && j != 0;
-  nd.s = p;
-  return nd;
-}
-
-uint32_t chunks_of(int n) { return (uint32_t)(((size_t)(n - 1) * n * n + kBlock - 1) / kBlock); }
-
-// Sum over the workgroup; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -51,135 +32,188 @@ __device__ __forceinline__ double block_sum(double v) {
   return t;
 }
 
-template <class T>
-__device__ __forceinline__ T q1_apply(const T* __restrict__ u, const T* __restrict__ kap, int n,
-                                      uint32_t s, T h) {
-  const int n2 = n * n;
-  const uint32_t e0 = s - (uint32_t)(1 + n + n2);
-  const T u0 = u[s];
-  T ks = T(0), far = T(0);
-#pragma unroll
-  for (int sz = 0; sz < 2; ++sz)
-#pragma unroll
-    for (int sy = 0; sy < 2; ++sy)
-#pragma unroll
-      for (int sx = 0; sx < 2; ++sx) {
-        const T kv = kap[e0 + sx + n * sy + n2 * sz];
-        const int ox = sx ? 1 : -1, oy = sy ? n : -n, oz = sz ? n2 : -n2;
-        const T f = (u[s + ox + oy] + u[s + ox + oz]) + (u[s + oy + oz] + u[s + ox + oy + oz]);
-        ks += kv;
-        far += kv * f;
-      }
-  return h * (ks * u0 * (T(1) / T(3)) - far * (T(1) / T(12)));
-}
+template <class T, int V>
+struct Vec {
+  typedef T type __attribute__((ext_vector_type(V)));
+};
 
-// q = A p and the partial sums of p . q
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_pcg_apply_dot(int n, uint32_t nchunk, size_t stride, T h,
-                                                          const T* __restrict__ kap, const T* __restrict__ p,
-                                                          T* __restrict__ q, SolveState st) {
-  const Node nd = node_of_thread(n, nchunk);
-  if (!st.active[nd.b]) return;
-  double v = 0.0;
-  if (nd.ok) {
-    const size_t g = nd.b * stride + nd.s;
-    const T aq = q1_apply(p + nd.b * stride, kap + nd.b * (size_t)n * n * n, n, nd.s, h);
-    q[g] = aq;
-    v = (double)p[g] * (double)aq;
-  }
-  v = block_sum(v);
-  if (threadIdx.x == 0) st.partial[(size_t)nd.b * st.nchunk + nd.c] = v;
+// Range of 16-byte vectors [lo, hi) of workgroup chunk c, and the sample.
+struct Span {
+  uint32_t b, c;
+  size_t lo, hi;
+};
+
+__device__ __forceinline__ Span span_of(const SGeom& g) {
+  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
+  Span s;
+  s.b = logical / g.chunks;
+  s.c = logical - s.b * g.chunks;
+  const uint32_t per = (g.vecs + g.chunks - 1) / g.chunks;
+  s.lo = (size_t)s.c * per;
+  s.hi = s.lo + per;
+  if (s.hi > g.vecs) s.hi = g.vecs;
+  return s;
 }
 
 // x += alpha p, r -= alpha q, partial sums of r . r
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_pcg_update(int n, uint32_t nchunk, size_t stride,
-                                                       T* __restrict__ x, const T* __restrict__ p,
-                                                       T* __restrict__ r, const T* __restrict__ q,
-                                                       SolveState st) {
-  const Node nd = node_of_thread(n, nchunk);
-  if (!st.active[nd.b]) return;
-  double v = 0.0;
-  if (nd.ok) {
-    const size_t g = nd.b * stride + nd.s;
-    const T a = (T)st.alpha[nd.b];
-    x[g] += a * p[g];
-    const T rn = r[g] - a * q[g];
-    r[g] = rn;
-    v = (double)rn * (double)rn;
+__global__ void __launch_bounds__(kBlock) k_pcg_update(SGeom g, size_t stride, T* __restrict__ x,
+                                                       const T* __restrict__ p, T* __restrict__ r,
+                                                       const T* __restrict__ q, SolveState st) {
+  constexpr int V = 16 / sizeof(T);
+  typedef typename Vec<T, V>::type vt;
+  const Span sp = span_of(g);
+  if (!st.active[sp.b]) return;
+  const size_t base = (size_t)sp.b * stride + (size_t)g.n * g.n;
+  vt* xv = reinterpret_cast<vt*>(x + base);
+  const vt* pv = reinterpret_cast<const vt*>(p + base);
+  vt* rv = reinterpret_cast<vt*>(r + base);
+  const vt* qv = reinterpret_cast<const vt*>(q + base);
+  const T a = (T)st.alpha[sp.b];
+  double acc = 0.0;
+  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) {
+    xv[t] = xv[t] + a * pv[t];
+    const vt rn = rv[t] - a * qv[t];
+    rv[t] = rn;
+#pragma unroll
+    for (int c = 0; c < V; ++c) acc += (double)rn[c] * (double)rn[c];
   }
-  v = block_sum(v);
-  if (threadIdx.x == 0) st.partial[(size_t)nd.b * st.nchunk + nd.c] = v;
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) st.partial[(size_t)sp.b * st.pstride + sp.c] = acc;
 }
 
-template <class Ta, class Tb>
-__global__ void __launch_bounds__(kBlock) k_dot(int n, uint32_t nchunk, size_t stride,
-                                                const Ta* __restrict__ a, const Tb* __restrict__ b,
-                                                SolveState st) {
-  const Node nd = node_of_thread(n, nchunk);
-  if (!st.active[nd.b]) return;
-  double v = 0.0;
-  if (nd.ok) {
-    const size_t g = nd.b * stride + nd.s;
-    v = (double)a[g] * (double)b[g];
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dot(SGeom g, size_t stride, const T* __restrict__ a,
+                                                const T* __restrict__ b, SolveState st) {
+  constexpr int V = 16 / sizeof(T);
+  typedef typename Vec<T, V>::type vt;
+  const Span sp = span_of(g);
+  if (!st.active[sp.b]) return;
+  const size_t base = (size_t)sp.b * stride + (size_t)g.n * g.n;
+  const vt* av = reinterpret_cast<const vt*>(a + base);
+  const vt* bv = reinterpret_cast<const vt*>(b + base);
+  double acc = 0.0;
+  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) {
+    const vt x = av[t], y = bv[t];
+#pragma unroll
+    for (int c = 0; c < V; ++c) acc += (double)x[c] * (double)y[c];
   }
-  v = block_sum(v);
-  if (threadIdx.x == 0) st.partial[(size_t)nd.b * st.nchunk + nd.c] = v;
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) st.partial[(size_t)sp.b * st.pstride + sp.c] = acc;
 }
 
 // p = z + beta p
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_pcg_direction(int n, uint32_t nchunk, size_t stride,
-                                                          const T* __restrict__ z, T* __restrict__ p,
-                                                          SolveState st) {
-  const Node nd = node_of_thread(n, nchunk);
-  if (!st.active[nd.b] || !nd.ok) return;
-  const size_t g = nd.b * stride + nd.s;
-  p[g] = z[g] + (T)st.beta[nd.b] * p[g];
+__global__ void __launch_bounds__(kBlock) k_pcg_direction(SGeom g, size_t stride, const T* __restrict__ z,
+                                                          T* __restrict__ p, SolveState st) {
+  constexpr int V = 16 / sizeof(T);
+  typedef typename Vec<T, V>::type vt;
+  const Span sp = span_of(g);
+  if (!st.active[sp.b]) return;
+  const size_t base = (size_t)sp.b * stride + (size_t)g.n * g.n;
+  const vt* zv = reinterpret_cast<const vt*>(z + base);
+  vt* pv = reinterpret_cast<vt*>(p + base);
+  const T be = (T)st.beta[sp.b];
+  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) pv[t] = zv[t] + be * pv[t];
 }
 
-__global__ void __launch_bounds__(kBlock) k_true_residual(int n, uint32_t nchunk, size_t stride, double h,
-                                                          const double* __restrict__ kap, double bconst,
-                                                          const double* __restrict__ x, double* __restrict__ r,
-                                                          SolveState st) {
-  const Node nd = node_of_thread(n, nchunk);
-  if (!st.active[nd.b]) return;
-  double v = 0.0;
-  if (nd.ok) {
-    const size_t g = nd.b * stride + nd.s;
-    const double rv = bconst - q1_apply(x + nd.b * stride, kap + nd.b * (size_t)n * n * n, n, nd.s, h);
-    r[g] = rv;
-    v = rv * rv;
+// x64 += d32 (4 values per step)
+__global__ void __launch_bounds__(kBlock) k_add_correction(SGeom g, size_t stride, double* __restrict__ x,
+                                                           const float* __restrict__ d, SolveState st) {
+  typedef Vec<double, 2>::type d2;
+  typedef Vec<float, 4>::type f4;
+  const Span sp = span_of(g);
+  if (!st.active[sp.b]) return;
+  const size_t base = (size_t)sp.b * stride + (size_t)g.n * g.n;
+  d2* xv = reinterpret_cast<d2*>(x + base);
+  const f4* dv = reinterpret_cast<const f4*>(d + base);
+  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) {
+    const f4 dd = dv[t];
+    d2 a = xv[2 * t], b = xv[2 * t + 1];
+    a.x += (double)dd.x; a.y += (double)dd.y;
+    b.x += (double)dd.z; b.y += (double)dd.w;
+    xv[2 * t] = a;
+    xv[2 * t + 1] = b;
   }
-  v = block_sum(v);
-  if (threadIdx.x == 0) st.partial[(size_t)nd.b * st.nchunk + nd.c] = v;
 }
 
-__global__ void __launch_bounds__(kBlock) k_add_correction(int n, uint32_t nchunk, size_t stride,
-                                                           double* __restrict__ x, const float* __restrict__ d,
-                                                           SolveState st) {
-  const Node nd = node_of_thread(n, nchunk);
-  if (!st.active[nd.b] || !nd.ok) return;
-  const size_t g = nd.b * stride + nd.s;
-  x[g] += (double)d[g];
+// r32 = (float) r64 (4 values per step)
+__global__ void __launch_bounds__(kBlock) k_demote(SGeom g, size_t stride, const double* __restrict__ r,
+                                                   float* __restrict__ r32, SolveState st) {
+  typedef Vec<double, 2>::type d2;
+  typedef Vec<float, 4>::type f4;
+  const Span sp = span_of(g);
+  if (!st.active[sp.b]) return;
+  const size_t base = (size_t)sp.b * stride + (size_t)g.n * g.n;
+  const d2* rv = reinterpret_cast<const d2*>(r + base);
+  f4* ov = reinterpret_cast<f4*>(r32 + base);
+  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) {
+    const d2 a = rv[2 * t], b = rv[2 * t + 1];
+    f4 o;
+    o.x = (float)a.x; o.y = (float)a.y; o.z = (float)b.x; o.w = (float)b.y;
+    ov[t] = o;
+  }
 }
 
-__global__ void __launch_bounds__(kBlock) k_demote(int n, uint32_t nchunk, size_t stride,
-                                                   const double* __restrict__ r, float* __restrict__ r32,
-                                                   SolveState st) {
-  const Node nd = node_of_thread(n, nchunk);
-  if (!st.active[nd.b] || !nd.ok) return;
-  const size_t g = nd.b * stride + nd.s;
-  r32[g] = (float)r[g];
+// interior positions := value (boundary positions of the range stay 0)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fill_interior(SGeom g, size_t stride, T* __restrict__ v, T value,
+                                                          const int* __restrict__ active) {
+  constexpr int V = 16 / sizeof(T);
+  typedef typename Vec<T, V>::type vt;
+  const Span sp = span_of(g);
+  if (active && !active[sp.b]) return;
+  const int n = g.n;
+  const size_t n2 = (size_t)n * n;
+  vt* out = reinterpret_cast<vt*>(v + (size_t)sp.b * stride + n2);
+  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) {
+    vt o;
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      const size_t pos = t * V + c;      // offset from plane 1
+      const int i = (int)(pos % n), j = (int)((pos / n) % n);
+      o[c] = (i != 0 && j != 0) ? value : T(0);
+    }
+    out[t] = o;
+  }
+}
+
+// QoI weights: domain average h^3; subcube [1/4,3/4]^3 average
+// h^3 prod_d c(i_d) with c = 2 strictly inside, 1 on the faces, 0 outside
+// (the number of subcube elements touching the node along each axis).
+__global__ void __launch_bounds__(kBlock) k_qoi_partial(SGeom g, size_t stride, int qoi, const double* __restrict__ u,
+                                                        SolveState st) {
+  const Span sp = span_of(g);
+  const int n = g.n;
+  const size_t n2 = (size_t)n * n;
+  const double* ub = u + (size_t)sp.b * stride + n2;
+  const double h = 1.0 / n, h3 = h * h * h;
+  const int lo = n / 4, hi = 3 * n / 4;
+  double acc = 0.0;
+  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const size_t pos = 2 * t + c;
+      const int i = (int)(pos % n), j = (int)((pos / n) % n), k = 1 + (int)(pos / n2);
+      double w = h3;
+      if (qoi == 1) {
+        auto cw = [&](int x) { return (x < lo || x > hi) ? 0.0 : ((x == lo || x == hi) ? 1.0 : 2.0); };
+        w *= cw(i) * cw(j) * cw(k);
+      }
+      acc += w * ub[pos];    // boundary positions hold 0
+    }
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) st.partial[(size_t)sp.b * st.pstride + sp.c] = acc;
 }
 
 // one workgroup per sample: fixed-order sum of its partials, then the scalar op
-__global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, SolveState st, double* out) {
+__global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t nparts, SolveState st, double* out) {
   const int b = blockIdx.x;
   if (op != RED_STORE && op != RED_BB && !st.active[b]) return;
-  const double* p = st.partial + (size_t)b * st.nchunk;
+  const double* p = st.partial + (size_t)b * st.pstride;
   double v = 0.0;
-  for (int c = threadIdx.x; c < st.nchunk; c += kBlock) v += p[c];
+  for (uint32_t c = threadIdx.x; c < nparts; c += kBlock) v += p[c];
   v = block_sum(v);
   if (threadIdx.x != 0) return;
   switch (op) {
@@ -207,77 +241,56 @@ __global__ void k_set_active(int B, SolveState st, int value) {
   if (b < B) st.active[b] = value;
 }
 
-// QoI weights: domain average h^3; subcube [1/4,3/4]^3 average
-// h^3 prod_d c(i_d) with c = 2 strictly inside, 1 on the faces, 0 outside
-// (the number of subcube elements touching the node along each axis).
-__global__ void __launch_bounds__(kBlock) k_qoi_partial(int n, uint32_t nchunk, size_t stride, int qoi,
-                                                        const double* __restrict__ u, SolveState st) {
-  const Node nd = node_of_thread(n, nchunk);
-  double v = 0.0;
-  if (nd.ok) {
-    const int lg = ilog2(n);
-    const int i = nd.s & (n - 1), j = (nd.s >> lg) & (n - 1), k = nd.s >> (2 * lg);
-    const double h = 1.0 / n;
-    double w = h * h * h;
-    if (qoi == 1) {
-      const int lo = n / 4, hi = 3 * n / 4;
-      auto c = [&](int t) { return (t < lo || t > hi) ? 0.0 : ((t == lo || t == hi) ? 1.0 : 2.0); };
-      w *= c(i) * c(j) * c(k);
-    }
-    v = w * u[nd.b * stride + nd.s];
-  }
-  v = block_sum(v);
-  if (threadIdx.x == 0) st.partial[(size_t)nd.b * st.nchunk + nd.c] = v;
-}
-
-inline dim3 grid_of(int n, int B) { return dim3(chunks_of(n) * (uint32_t)B); }
+template <class T>
+inline dim3 sgrid(const SGeom& g, int B) { return dim3(g.chunks * (uint32_t)B); }
 
 }  // namespace
 
-int krylov_chunks(int n) { return (int)chunks_of(n); }
-
 template <class T>
-hipError_t launch_pcg_apply_dot(int n, int B, const T* kap, const T* p, T* q, SolveState s, hipStream_t st) {
-  k_pcg_apply_dot<T><<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), T(1) / T(n), kap, p, q, s);
+hipError_t launch_pcg_update(int n, int B, T* x, const T* p, T* r, const T* q, SolveState s, uint32_t* nparts,
+                             hipStream_t st) {
+  const SGeom g = sgeom<T>(n);
+  if (nparts) *nparts = g.chunks;
+  k_pcg_update<T><<<sgrid<T>(g, B), kBlock, 0, st>>>(g, grid_stride(n), x, p, r, q, s);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_pcg_update(int n, int B, T* x, const T* p, T* r, const T* q, SolveState s, hipStream_t st) {
-  k_pcg_update<T><<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), x, p, r, q, s);
-  return hipGetLastError();
-}
-
-template <class Ta, class Tb>
-hipError_t launch_dot(int n, int B, const Ta* a, const Tb* b, SolveState s, hipStream_t st) {
-  k_dot<Ta, Tb><<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), a, b, s);
+hipError_t launch_dot(int n, int B, const T* a, const T* b, SolveState s, uint32_t* nparts, hipStream_t st) {
+  const SGeom g = sgeom<T>(n);
+  if (nparts) *nparts = g.chunks;
+  k_dot<T><<<sgrid<T>(g, B), kBlock, 0, st>>>(g, grid_stride(n), a, b, s);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_pcg_direction(int n, int B, const T* z, T* p, SolveState s, hipStream_t st) {
-  k_pcg_direction<T><<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), z, p, s);
-  return hipGetLastError();
-}
-
-hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x, double* r,
-                                SolveState s, hipStream_t st) {
-  k_true_residual<<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), 1.0 / n, kap, bconst, x, r, s);
+  const SGeom g = sgeom<T>(n);
+  k_pcg_direction<T><<<sgrid<T>(g, B), kBlock, 0, st>>>(g, grid_stride(n), z, p, s);
   return hipGetLastError();
 }
 
 hipError_t launch_add_correction(int n, int B, double* x, const float* d, SolveState s, hipStream_t st) {
-  k_add_correction<<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), x, d, s);
+  const SGeom g = sgeom<float>(n);   // units of 4 values
+  k_add_correction<<<sgrid<float>(g, B), kBlock, 0, st>>>(g, grid_stride(n), x, d, s);
   return hipGetLastError();
 }
 
 hipError_t launch_demote(int n, int B, const double* r, float* r32, SolveState s, hipStream_t st) {
-  k_demote<<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), r, r32, s);
+  const SGeom g = sgeom<float>(n);
+  k_demote<<<sgrid<float>(g, B), kBlock, 0, st>>>(g, grid_stride(n), r, r32, s);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(int B, int op, double tol2, SolveState s, double* out, hipStream_t st) {
-  k_reduce<<<dim3(B), kBlock, 0, st>>>(op, tol2, s, out);
+template <class T>
+hipError_t launch_fill_interior(int n, int B, T* v, double value, const int* active, hipStream_t st) {
+  const SGeom g = sgeom<T>(n);
+  k_fill_interior<T><<<sgrid<T>(g, B), kBlock, 0, st>>>(g, grid_stride(n), v, T(value), active);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(int B, int op, double tol2, uint32_t nparts, SolveState s, double* out, hipStream_t st) {
+  k_reduce<<<dim3(B), kBlock, 0, st>>>(op, tol2, nparts, s, out);
   return hipGetLastError();
 }
 
@@ -291,21 +304,23 @@ hipError_t launch_set_active(int B, SolveState s, int value, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_qoi_partial(int n, int B, int qoi, const double* u, SolveState s, hipStream_t st) {
-  k_qoi_partial<<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), qoi, u, s);
+hipError_t launch_qoi_partial(int n, int B, int qoi, const double* u, SolveState s, uint32_t* nparts,
+                              hipStream_t st) {
+  const SGeom g = sgeom<double>(n);
+  if (nparts) *nparts = g.chunks;
+  k_qoi_partial<<<sgrid<double>(g, B), kBlock, 0, st>>>(g, grid_stride(n), qoi, u, s);
   return hipGetLastError();
 }
 
-template hipError_t launch_pcg_apply_dot<float>(int, int, const float*, const float*, float*, SolveState, hipStream_t);
-template hipError_t launch_pcg_apply_dot<double>(int, int, const double*, const double*, double*, SolveState,
-                                                 hipStream_t);
 template hipError_t launch_pcg_update<float>(int, int, float*, const float*, float*, const float*, SolveState,
-                                             hipStream_t);
+                                             uint32_t*, hipStream_t);
 template hipError_t launch_pcg_update<double>(int, int, double*, const double*, double*, const double*, SolveState,
-                                              hipStream_t);
-template hipError_t launch_dot<float, float>(int, int, const float*, const float*, SolveState, hipStream_t);
-template hipError_t launch_dot<double, double>(int, int, const double*, const double*, SolveState, hipStream_t);
+                                              uint32_t*, hipStream_t);
+template hipError_t launch_dot<float>(int, int, const float*, const float*, SolveState, uint32_t*, hipStream_t);
+template hipError_t launch_dot<double>(int, int, const double*, const double*, SolveState, uint32_t*, hipStream_t);
 template hipError_t launch_pcg_direction<float>(int, int, const float*, float*, SolveState, hipStream_t);
 template hipError_t launch_pcg_direction<double>(int, int, const double*, double*, SolveState, hipStream_t);
+template hipError_t launch_fill_interior<float>(int, int, float*, double, const int*, hipStream_t);
+template hipError_t launch_fill_interior<double>(int, int, double*, double, const int*, hipStream_t);
 
 }  // namespace mlmc

@@ -4,18 +4,29 @@
 //   (A u)_i = h sum_{e owns i} kappa_e sum_b Khat[a_i(e)][b] u_b
 // with Khat the unit-cube Q1 stiffness.  Khat[a][b] is 1/3 for a = b, 0 when
 // a and b share an edge, and -1/12 when they differ in two or three
-// coordinates, so for element e seen from node i (local corner pointing along
-// signs (sx, sy, sz)) the row reduces to
+// coordinates, so for element e seen from node i (its far corner along signs
+// (sx, sy, sz)) the row reduces to
 //   kappa_e [ u_i / 3 - (u_(sx,sy,0) + u_(sx,0,sz) + u_(0,sy,sz) + u_(sx,sy,sz)) / 12 ]
 // i.e. 20 neighbour values (12 edge, 8 corner) and the 8 element coefficients
 // per node; face neighbours never enter.  The Jacobi diagonal is
-// D_i = (h/3) sum_{e owns i} kappa_e, computed from the same 8 coefficients.
+// D_i = (h/3) sum_{e owns i} kappa_e, from the same 8 coefficients.
 //
-// Multigrid pieces: Chebyshev-Jacobi smoothing step (three-term recurrence),
-// full-weighting restriction P^T and trilinear prolongation P between the n
-// and n/2 grids, exact solve of the single unknown of the 2^3 mesh, and the
-// 8-child mean of kappa for the rediscretised coarse operators.
+// z-marching engine: a thread owns V consecutive nodes of one row (one
+// 16-byte vector: 4 floats or 2 doubles) and walks up the planes of a chunk,
+// keeping the 3 x 3 x (V+2) window of u (planes k-1..k+1, rows j-1..j+1) and
+// the 2 x 2 x (V+1) window of kappa in registers.  Each plane step loads one
+// new u plane (3 row vectors + 2 halo values per row) and one kappa plane (2
+// row vectors + 1 halo value per row): ~3 vector loads per node in fp32
+// instead of 29 scalar ones, so the kernel is limited by HBM rather than by
+// the L1/TA path.  The epilogue (apply, residual, Chebyshev step, PCG apply
+// with its dot product, fp64 outer residual) consumes A u and D per node.
+//
+// Multigrid pieces: full-weighting restriction P^T and trilinear
+// prolongation P between the n and n/2 grids, exact solve of the single
+// unknown of the 2^3 mesh, and the 8-child mean of kappa for the
+// rediscretised coarse operators.
 #include "common.hpp"
+#include "grid.hpp"
 #include "kernels.hpp"
 
 namespace mlmc {
@@ -23,19 +34,263 @@ namespace {
 
 __device__ __forceinline__ int ilog2(int n) { return 31 - __clz(n); }
 
-struct Node {
-  uint32_t b;     // sample
-  uint32_t s;     // position inside the sample's grid block
-  bool ok;        // interior node
+__device__ __forceinline__ double block_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __shared__ double wsum[kBlock / 64];
+  const int nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < nw; ++w) t += wsum[w];
+  return t;
+}
+
+template <class T, int V>
+struct Vec {
+  typedef T type __attribute__((ext_vector_type(V)));
 };
 
-// 1D grid of nchunk * B workgroups, each covering 256 consecutive positions of
-// the interior planes 1..n-1 of one sample.
+template <class T, int V>
+__device__ __forceinline__ void vload(const T* p, T* dst) {
+  typedef typename Vec<T, V>::type vt;
+  const vt v = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+  for (int q = 0; q < V; ++q) dst[q] = v[q];
+}
+
+template <class T, int V>
+__device__ __forceinline__ void vstore(T* p, const T* src) {
+  typedef typename Vec<T, V>::type vt;
+  vt v;
+#pragma unroll
+  for (int q = 0; q < V; ++q) v[q] = src[q];
+  *reinterpret_cast<vt*>(p) = v;
+}
+
+// ------------------------------------------------------------ epilogues
+// Each epilogue sees, for the V nodes i0 .. i0+V-1 at position `pos` (index
+// of node i0 in the batch array), A u, D and the centre values of u; `ok[v]`
+// is false for the boundary node i = 0.  Stores write 0 there.
+
+template <class T, int V>
+struct EpiApply {
+  static constexpr bool kReduce = false;
+  T* y;
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double&) const {
+    T o[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = ok[v] ? au[v] : T(0);
+    vstore<T, V>(y + pos, o);
+  }
+};
+
+template <class T, int V>
+struct EpiResidual {
+  static constexpr bool kReduce = false;
+  const T* b;
+  T* r;
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double&) const {
+    T bv[V], o[V];
+    vload<T, V>(b + pos, bv);
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = ok[v] ? bv[v] - au[v] : T(0);
+    vstore<T, V>(r + pos, o);
+  }
+};
+
+// out = x + c1 (x - xo) + c2 D^-1 (b - A x); without xo the previous iterate is 0
+template <class T, int V, bool USE_XO>
+struct EpiCheb {
+  static constexpr bool kReduce = false;
+  const T* b;
+  const T* xo;
+  T* out;
+  T c1, c2;
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double&) const {
+    T bv[V], xov[V], o[V];
+    vload<T, V>(b + pos, bv);
+    if (USE_XO) vload<T, V>(xo + pos, xov);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const T prev = USE_XO ? uc[v] - xov[v] : uc[v];
+      o[v] = ok[v] ? uc[v] + c1 * prev + c2 * (bv[v] - au[v]) / dg[v] : T(0);
+    }
+    vstore<T, V>(out + pos, o);
+  }
+};
+
+// q = A p, accumulate p . q
+template <class T, int V>
+struct EpiPcgApply {
+  static constexpr bool kReduce = true;
+  T* q;
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
+    T o[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      o[v] = ok[v] ? au[v] : T(0);
+      acc += (double)uc[v] * (double)o[v];
+    }
+    vstore<T, V>(q + pos, o);
+  }
+};
+
+// r = bconst - A x (fp64 outer residual), accumulate r . r
+template <class T, int V>
+struct EpiTrueResidual {
+  static constexpr bool kReduce = true;
+  T bconst;
+  T* r;
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
+    T o[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      o[v] = ok[v] ? bconst - au[v] : T(0);
+      acc += (double)o[v] * (double)o[v];
+    }
+    vstore<T, V>(r + pos, o);
+  }
+};
+
+// x0 = 0 Chebyshev step: out = c2 D^-1 b (needs only the kappa window)
+template <class T, int V>
+struct EpiChebZero {
+  static constexpr bool kReduce = false;
+  const T* b;
+  T* out;
+  T c2;
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double&) const {
+    T bv[V], o[V];
+    vload<T, V>(b + pos, bv);
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = ok[v] ? c2 * bv[v] / dg[v] : T(0);
+    vstore<T, V>(out + pos, o);
+  }
+};
+
+// --------------------------------------------------------- z-march engine
+template <class T, int V, bool NEED_U, class Epi>
+__global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, const T* __restrict__ u,
+                                                const T* __restrict__ kap, const int* __restrict__ active,
+                                                double* __restrict__ partial, uint32_t pstride, Epi epi) {
+  const uint32_t per = g.parts();
+  const uint32_t lin = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = lin / per;
+  const uint32_t part = lin - b * per;
+  if (active && !active[b]) return;
+  const int rb = (int)(part % (uint32_t)g.row_blocks), zb = (int)(part / (uint32_t)g.row_blocks);
+  const int n = g.n, n2 = n * n;
+  const int gx = (int)threadIdx.x % g.G, jr = (int)threadIdx.x / g.G;
+  const int j = 1 + rb * g.rows + jr;
+  const int i0 = gx * V;
+  const int k0 = 1 + zb * g.zlen;
+  int k1 = k0 + g.zlen;
+  if (k1 > n) k1 = n;
+  const bool valid = jr < g.rows && j <= n - 1 && k0 < k1;
+  double acc = 0.0;
+  if (valid) {
+    const T* ub = u + (size_t)b * stride;
+    const T* kb = kap + (size_t)b * n2 * n;
+    bool ok[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) ok[v] = (i0 + v) != 0;
+    T U[3][3][V + 2];
+    T K[2][2][V + 1];
+    auto load_u = [&](int p, int kk) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const T* row = ub + (size_t)n * (j - 1 + r) + (size_t)n2 * kk;
+        U[p][r][0] = i0 > 0 ? row[i0 - 1] : T(0);
+        vload<T, V>(row + i0, &U[p][r][1]);
+        U[p][r][V + 1] = row[i0 + V];   // position n is the next row's zero
+      }
+    };
+    auto load_k = [&](int q, int ez) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const T* row = kb + (size_t)n * (j - 1 + r) + (size_t)n2 * ez;
+        K[q][r][0] = i0 > 0 ? row[i0 - 1] : T(0);
+        vload<T, V>(row + i0, &K[q][r][1]);
+      }
+    };
+    if (NEED_U) {
+      load_u(0, k0 - 1);
+      load_u(1, k0);
+    }
+    load_k(0, k0 - 1);
+    const T third = T(1) / T(3), twelfth = T(1) / T(12);
+    for (int k = k0; k < k1; ++k) {
+      if (NEED_U) load_u(2, k + 1);
+      load_k(1, k);
+      T au[V], dg[V], uc[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        T ks = T(0), far = T(0);
+#pragma unroll
+        for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+          for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+            for (int sx = 0; sx < 2; ++sx) {
+              const T kv = K[sz][sy][v + sx];
+              ks += kv;
+              if (NEED_U) {
+                const T f = (U[1][2 * sy][v + 2 * sx] + U[2 * sz][1][v + 2 * sx]) +
+                            (U[2 * sz][2 * sy][v + 1] + U[2 * sz][2 * sy][v + 2 * sx]);
+                far += kv * f;
+              }
+            }
+        uc[v] = NEED_U ? U[1][1][v + 1] : T(0);
+        au[v] = h * (ks * uc[v] * third - far * twelfth);
+        dg[v] = h * ks * third;
+      }
+      epi((size_t)b * stride + i0 + (size_t)n * j + (size_t)n2 * k, au, dg, uc, ok, acc);
+      if (NEED_U) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < V + 2; ++c) {
+            U[0][r][c] = U[1][r][c];
+            U[1][r][c] = U[2][r][c];
+          }
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < V + 1; ++c) K[0][r][c] = K[1][r][c];
+    }
+  }
+  if (Epi::kReduce) {
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[(size_t)b * pstride + part] = acc;
+  }
+}
+
+template <class T, bool NEED_U, class Epi>
+hipError_t zlaunch(int n, int B, const T* u, const T* kap, const int* active, double* partial, uint32_t pstride,
+                   Epi epi, uint32_t* nparts, hipStream_t st) {
+  constexpr int V = ZV<T>::V;
+  const ZGeom g = zgeom<T>(n, B);
+  if (nparts) *nparts = g.parts();
+  const uint32_t blocks = g.parts() * (uint32_t)B;
+  k_zmarch<T, V, NEED_U, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(g, grid_stride(n), T(1) / T(n), u, kap,
+                                                                       active, partial, pstride, epi);
+  return hipGetLastError();
+}
+
+// --------------------------------------------- fallback for meshes below V
+// One thread per node (used for fp32 on the 2^3 mesh only).
+struct Node {
+  uint32_t b, s;
+  bool ok;
+};
+
 __device__ __forceinline__ Node node_of_thread(int n, uint32_t nchunk) {
-  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
   Node nd;
-  nd.b = logical / nchunk;
-  const uint32_t c = logical - nd.b * nchunk;
+  nd.b = blockIdx.x / nchunk;
+  const uint32_t c = blockIdx.x - nd.b * nchunk;
   const uint32_t n2 = (uint32_t)n * n;
   const uint32_t p = n2 + c * kBlock + threadIdx.x;
   const uint32_t lg = (uint32_t)ilog2(n);
@@ -45,16 +300,13 @@ __device__ __forceinline__ Node node_of_thread(int n, uint32_t nchunk) {
   return nd;
 }
 
-inline uint32_t chunks_of(int n) {
-  return (uint32_t)(((size_t)(n - 1) * n * n + kBlock - 1) / kBlock);
-}
+inline uint32_t chunks_of(int n) { return (uint32_t)(((size_t)(n - 1) * n * n + kBlock - 1) / kBlock); }
 
-// (A u)_s and the diagonal at interior position s of an n^3 grid block.
 template <class T>
-__device__ __forceinline__ void q1_row(const T* __restrict__ u, const T* __restrict__ kap, int n,
-                                       uint32_t s, T h, T& au, T& diag) {
+__device__ __forceinline__ void q1_row(const T* __restrict__ u, const T* __restrict__ kap, int n, uint32_t s, T h,
+                                       T& au, T& diag) {
   const int n2 = n * n;
-  const uint32_t e0 = s - (uint32_t)(1 + n + n2);     // element (i-1, j-1, k-1)
+  const uint32_t e0 = s - (uint32_t)(1 + n + n2);
   const T u0 = u[s];
   T ks = T(0), far = T(0);
 #pragma unroll
@@ -69,129 +321,134 @@ __device__ __forceinline__ void q1_row(const T* __restrict__ u, const T* __restr
         ks += kv;
         far += kv * f;
       }
-  const T third = T(1) / T(3), twelfth = T(1) / T(12);
-  au = h * (ks * u0 * third - far * twelfth);
-  diag = h * ks * third;
+  au = h * (ks * u0 * (T(1) / T(3)) - far * (T(1) / T(12)));
+  diag = h * ks * (T(1) / T(3));
 }
 
+// mode 0 apply, 1 residual, 2 cheb zero, 3 cheb (no xo), 4 cheb with xo, 5 pcg apply+dot
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_apply(int n, uint32_t nchunk, size_t stride, T h,
+__global__ void __launch_bounds__(kBlock) k_small(int mode, int n, uint32_t nchunk, size_t stride, T h,
                                                   const T* __restrict__ kap, const T* __restrict__ u,
-                                                  T* __restrict__ y, const int* __restrict__ active) {
+                                                  const T* __restrict__ b, const T* xo, T* out, T c1, T c2,
+                                                  const int* __restrict__ active, double* partial,
+                                                  uint32_t pstride) {
   const Node nd = node_of_thread(n, nchunk);
   if (active && !active[nd.b]) return;
-  if (!nd.ok) return;
-  const size_t ne = (size_t)n * n * n;
-  T au, dg;
-  q1_row(u + nd.b * stride, kap + nd.b * ne, n, nd.s, h, au, dg);
-  y[nd.b * stride + nd.s] = au;
-}
-
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_residual(int n, uint32_t nchunk, size_t stride, T h,
-                                                     const T* __restrict__ kap, const T* __restrict__ b,
-                                                     const T* __restrict__ x, T* __restrict__ r,
-                                                     const int* __restrict__ active) {
-  const Node nd = node_of_thread(n, nchunk);
-  if (active && !active[nd.b]) return;
-  if (!nd.ok) return;
-  const size_t ne = (size_t)n * n * n;
-  T ax, dg;
-  q1_row(x + nd.b * stride, kap + nd.b * ne, n, nd.s, h, ax, dg);
-  const size_t g = nd.b * stride + nd.s;
-  r[g] = b[g] - ax;
-}
-
-// D_i from the 8 element coefficients around interior position s
-template <class T>
-__device__ __forceinline__ T q1_diag(const T* __restrict__ kap, int n, uint32_t s, T h) {
-  const int n2 = n * n;
-  const uint32_t e0 = s - (uint32_t)(1 + n + n2);
-  T ks = T(0);
-#pragma unroll
-  for (int sz = 0; sz < 2; ++sz)
-#pragma unroll
-    for (int sy = 0; sy < 2; ++sy)
-#pragma unroll
-      for (int sx = 0; sx < 2; ++sx) ks += kap[e0 + sx + n * sy + n2 * sz];
-  return h * ks * (T(1) / T(3));
-}
-
-template <class T, bool ZERO_X, bool USE_XO>
-__global__ void __launch_bounds__(kBlock) k_cheb(int n, uint32_t nchunk, size_t stride, T h,
-                                                 const T* __restrict__ kap, const T* __restrict__ b,
-                                                 const T* __restrict__ x, const T* xo, T* out, T c1, T c2,
-                                                 const int* __restrict__ active) {
-  const Node nd = node_of_thread(n, nchunk);
-  if (active && !active[nd.b]) return;
-  if (!nd.ok) return;
-  const size_t ne = (size_t)n * n * n;
-  const size_t g = nd.b * stride + nd.s;
-  const T* kb = kap + nd.b * ne;
-  if (ZERO_X) {
-    out[g] = c2 * b[g] / q1_diag(kb, n, nd.s, h);
-  } else {
-    T ax, dg;
-    q1_row(x + nd.b * stride, kb, n, nd.s, h, ax, dg);
-    const T xv = x[g];
-    // without a previous iterate the three-term step takes x_{k-1} = 0
-    const T prev = USE_XO ? xv - xo[g] : xv;
-    out[g] = xv + c1 * prev + c2 * (b[g] - ax) / dg;
+  double acc = 0.0;
+  if (nd.ok) {
+    const size_t ne = (size_t)n * n * n;
+    const size_t g = nd.b * stride + nd.s;
+    T au = T(0), dg = T(0);
+    q1_row(u ? u + nd.b * stride : b + nd.b * stride, kap + nd.b * ne, n, nd.s, h, au, dg);
+    switch (mode) {
+      case 0: out[g] = au; break;
+      case 1: out[g] = b[g] - au; break;
+      case 2: out[g] = c2 * b[g] / dg; break;
+      case 3: out[g] = u[g] + c1 * u[g] + c2 * (b[g] - au) / dg; break;
+      case 4: out[g] = u[g] + c1 * (u[g] - xo[g]) + c2 * (b[g] - au) / dg; break;
+      default: out[g] = au; acc = (double)u[g] * (double)au; break;
+    }
+  }
+  if (mode == 5) {
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[(size_t)nd.b * pstride + (blockIdx.x - nd.b * nchunk)] = acc;
   }
 }
 
+template <class T>
+hipError_t small_launch(int mode, int n, int B, const T* kap, const T* u, const T* b, const T* xo, T* out, double c1,
+                        double c2, const int* active, double* partial, uint32_t pstride, uint32_t* nparts,
+                        hipStream_t st) {
+  const uint32_t nc = chunks_of(n);
+  if (nparts) *nparts = nc;
+  k_small<T><<<dim3(nc * (uint32_t)B), kBlock, 0, st>>>(mode, n, nc, grid_stride(n), T(1) / T(n), kap, u, b, xo, out,
+                                                       T(c1), T(c2), active, partial, pstride);
+  return hipGetLastError();
+}
+
+template <class T>
+inline bool use_small(int n) { return n < ZV<T>::V || n < 2; }
+
+// ------------------------------------------------------ transfer kernels
 // full weighting: coarse node (I,J,K) gathers fine (2I+dx, 2J+dy, 2K+dz) with
 // weights prod_d (dx == 0 ? 1 : 1/2)
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_restrict(int nc, uint32_t nchunk, size_t sc, size_t sf,
                                                      const T* __restrict__ rf, T* __restrict__ bc,
                                                      const int* __restrict__ active) {
-  const Node nd = node_of_thread(nc, nchunk);
-  if (active && !active[nd.b]) return;
-  if (!nd.ok) return;
-  const int nf = 2 * nc, lg = ilog2(nc);
-  const uint32_t I = nd.s & (nc - 1), J = (nd.s >> lg) & (nc - 1), K = nd.s >> (2 * lg);
-  const T* r = rf + nd.b * sf;
+  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = logical / nchunk, c = logical - b * nchunk;
+  if (active && !active[b]) return;
+  const uint32_t n2 = (uint32_t)nc * nc;
+  const uint32_t p = n2 + c * kBlock + threadIdx.x;
+  const int lg = ilog2(nc);
+  const uint32_t I = p & (nc - 1), J = (p >> lg) & (nc - 1), K = p >> (2 * lg);
+  if (!(p < n2 * (uint32_t)nc && I != 0 && J != 0)) return;
+  const int nf = 2 * nc;
+  const T* r = rf + b * sf;
   const int f2 = nf * nf;
-  const uint32_t c = 2 * I + nf * 2 * J + f2 * 2 * K;
+  const uint32_t cidx = 2 * I + nf * 2 * J + f2 * 2 * K;
   T acc = T(0);
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz) {
     T az = T(0);
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
-      const uint32_t row = c + nf * dy + f2 * dz;
+      const uint32_t row = cidx + nf * dy + f2 * dz;
       const T ay = T(0.5) * (r[row - 1] + r[row + 1]) + r[row];
       az += (dy == 0 ? T(1) : T(0.5)) * ay;
     }
     acc += (dz == 0 ? T(1) : T(0.5)) * az;
   }
-  bc[nd.b * sc + nd.s] = acc;
+  bc[b * sc + p] = acc;
 }
 
-// trilinear interpolation from the n/2 grid, added to the fine values
-template <class T>
+// trilinear interpolation from the n/2 grid added to the fine values; a
+// thread owns V consecutive fine nodes of one row (vector load/store of xf).
+template <class T, int V>
 __global__ void __launch_bounds__(kBlock) k_prolong_add(int nf, uint32_t nchunk, size_t sf, size_t sc,
                                                         const T* __restrict__ xc, T* __restrict__ xf,
                                                         const int* __restrict__ active) {
-  const Node nd = node_of_thread(nf, nchunk);
-  if (active && !active[nd.b]) return;
-  if (!nd.ok) return;
-  const int nc = nf / 2, lg = ilog2(nf);
-  const uint32_t i = nd.s & (nf - 1), j = (nd.s >> lg) & (nf - 1), k = nd.s >> (2 * lg);
-  const uint32_t i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
-  const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
-  const T* c = xc + nd.b * sc;
-  const int c2 = nc * nc;
-  auto row = [&](uint32_t jj, uint32_t kk) -> T {
-    const uint32_t base = nc * jj + c2 * kk;
-    return (i & 1) ? wi * (c[base + i0] + c[base + i1]) : c[base + i0];
+  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = logical / nchunk, c = logical - b * nchunk;
+  if (active && !active[b]) return;
+  const uint32_t n2 = (uint32_t)nf * nf;
+  const uint32_t p = n2 + (c * kBlock + threadIdx.x) * V;   // first of V fine positions
+  if (p >= n2 * (uint32_t)nf) return;
+  const int lg = ilog2(nf);
+  const uint32_t i0 = p & (nf - 1), j = (p >> lg) & (nf - 1), k = p >> (2 * lg);
+  if (j == 0) return;
+  const int nc = nf / 2, c2 = nc * nc;
+  const T* cb = xc + b * sc;
+  // coarse x values covering fine i0-1 .. i0+V: coarse i0/2 .. i0/2 + V/2
+  const uint32_t jl = j >> 1, jh = (j + 1) >> 1, kl = k >> 1, kh = (k + 1) >> 1;
+  const T wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+  T cx[V / 2 + 1];
+#pragma unroll
+  for (int q = 0; q <= V / 2; ++q) cx[q] = T(0);
+  auto add_row = [&](uint32_t jj, uint32_t kk, T w) {
+    const T* row = cb + nc * jj + c2 * kk + (i0 >> 1);
+#pragma unroll
+    for (int q = 0; q <= V / 2; ++q) cx[q] += w * row[q];
   };
-  auto plane = [&](uint32_t kk) -> T {
-    return (j & 1) ? wj * (row(j0, kk) + row(j1, kk)) : row(j0, kk);
-  };
-  const T v = (k & 1) ? wk * (plane(k0) + plane(k1)) : plane(k0);
-  xf[nd.b * sf + nd.s] += v;
+  // rows/planes: even index -> one coarse line with weight 1, odd -> two with 1/2
+  if (k & 1) {
+    if (j & 1) { add_row(jl, kl, wj * wk); add_row(jh, kl, wj * wk); add_row(jl, kh, wj * wk); add_row(jh, kh, wj * wk); }
+    else { add_row(jl, kl, wk); add_row(jl, kh, wk); }
+  } else {
+    if (j & 1) { add_row(jl, kl, wj); add_row(jh, kl, wj); }
+    else add_row(jl, kl, T(1));
+  }
+  T xv[V];
+  vload<T, V>(xf + b * sf + p, xv);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const uint32_t i = i0 + v;
+    if (i == 0) continue;
+    const int q = v >> 1;   // coarse offset of i >> 1 relative to i0 >> 1
+    xv[v] += (i & 1) ? T(0.5) * (cx[q] + cx[q + 1]) : cx[q];
+  }
+  vstore<T, V>(xf + b * sf + p, xv);
 }
 
 // 2^3 mesh: one unknown at node (1,1,1), A_11 = (h/3) sum of the 8 kappa, h = 1/2
@@ -223,68 +480,73 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(int nc, int64_t total, const
 }
 
 template <class Ts, class Td>
-__global__ void __launch_bounds__(kBlock) k_convert(size_t count, const Ts* __restrict__ src,
-                                                    Td* __restrict__ dst) {
+__global__ void __launch_bounds__(kBlock) k_convert(size_t count, const Ts* __restrict__ src, Td* __restrict__ dst) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < count) dst[t] = (Td)src[t];
 }
-
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_fill_interior(int n, uint32_t nchunk, size_t stride,
-                                                          T* __restrict__ v, T value,
-                                                          const int* __restrict__ active) {
-  const Node nd = node_of_thread(n, nchunk);
-  if (active && !active[nd.b]) return;
-  if (!nd.ok) return;
-  v[nd.b * stride + nd.s] = value;
-}
-
-inline dim3 grid_of(int n, int B) { return dim3(chunks_of(n) * (uint32_t)B); }
 
 }  // namespace
 
 template <class T>
 hipError_t launch_apply(int n, int B, const T* kap, const T* u, T* y, const int* active, hipStream_t st) {
-  k_apply<T><<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), T(1) / T(n), kap, u, y, active);
-  return hipGetLastError();
+  if (use_small<T>(n))
+    return small_launch<T>(0, n, B, kap, u, nullptr, nullptr, y, 0, 0, active, nullptr, 0, nullptr, st);
+  return zlaunch<T, true>(n, B, u, kap, active, nullptr, 0, EpiApply<T, ZV<T>::V>{y}, nullptr, st);
 }
 
 template <class T>
 hipError_t launch_residual(int n, int B, const T* kap, const T* b, const T* x, T* r, const int* active,
                            hipStream_t st) {
-  k_residual<T><<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), T(1) / T(n), kap, b, x, r,
-                                                  active);
-  return hipGetLastError();
+  if (use_small<T>(n))
+    return small_launch<T>(1, n, B, kap, x, b, nullptr, r, 0, 0, active, nullptr, 0, nullptr, st);
+  return zlaunch<T, true>(n, B, x, kap, active, nullptr, 0, EpiResidual<T, ZV<T>::V>{b, r}, nullptr, st);
 }
 
 template <class T>
 hipError_t launch_cheb(int n, int B, const T* kap, const T* b, const T* x, const T* xo, T* out, double c1,
                        double c2, bool zero_x, bool use_xo, const int* active, hipStream_t st) {
-  const dim3 g = grid_of(n, B);
-  const uint32_t nc = chunks_of(n);
-  const size_t sd = grid_stride(n);
-  const T h = T(1) / T(n);
+  constexpr int V = ZV<T>::V;
+  if (use_small<T>(n))
+    return small_launch<T>(zero_x ? 2 : (use_xo ? 4 : 3), n, B, kap, zero_x ? nullptr : x, b, xo, out, c1, c2,
+                           active, nullptr, 0, nullptr, st);
   if (zero_x)
-    k_cheb<T, true, false><<<g, kBlock, 0, st>>>(n, nc, sd, h, kap, b, x, xo, out, T(c1), T(c2), active);
-  else if (use_xo)
-    k_cheb<T, false, true><<<g, kBlock, 0, st>>>(n, nc, sd, h, kap, b, x, xo, out, T(c1), T(c2), active);
-  else
-    k_cheb<T, false, false><<<g, kBlock, 0, st>>>(n, nc, sd, h, kap, b, x, xo, out, T(c1), T(c2), active);
-  return hipGetLastError();
+    return zlaunch<T, false>(n, B, nullptr, kap, active, nullptr, 0, EpiChebZero<T, V>{b, out, T(c2)}, nullptr, st);
+  if (use_xo)
+    return zlaunch<T, true>(n, B, x, kap, active, nullptr, 0, EpiCheb<T, V, true>{b, xo, out, T(c1), T(c2)},
+                            nullptr, st);
+  return zlaunch<T, true>(n, B, x, kap, active, nullptr, 0, EpiCheb<T, V, false>{b, xo, out, T(c1), T(c2)}, nullptr,
+                          st);
+}
+
+template <class T>
+hipError_t launch_pcg_apply_dot(int n, int B, const T* kap, const T* p, T* q, SolveState s, uint32_t* nparts,
+                                hipStream_t st) {
+  if (use_small<T>(n))
+    return small_launch<T>(5, n, B, kap, p, nullptr, nullptr, q, 0, 0, s.active, s.partial, s.pstride, nparts, st);
+  return zlaunch<T, true>(n, B, p, kap, s.active, s.partial, s.pstride, EpiPcgApply<T, ZV<T>::V>{q}, nparts, st);
+}
+
+hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x, double* r,
+                                SolveState s, uint32_t* nparts, hipStream_t st) {
+  return zlaunch<double, true>(n, B, x, kap, s.active, s.partial, s.pstride,
+                               EpiTrueResidual<double, ZV<double>::V>{bconst, r}, nparts, st);
 }
 
 template <class T>
 hipError_t launch_restrict(int nf, int B, const T* rf, T* bc, const int* active, hipStream_t st) {
   const int nc = nf / 2;
-  k_restrict<T><<<grid_of(nc, B), kBlock, 0, st>>>(nc, chunks_of(nc), grid_stride(nc), grid_stride(nf), rf, bc,
-                                                   active);
+  const uint32_t ch = chunks_of(nc);
+  k_restrict<T><<<dim3(ch * (uint32_t)B), kBlock, 0, st>>>(nc, ch, grid_stride(nc), grid_stride(nf), rf, bc, active);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_prolong_add(int nf, int B, const T* xc, T* xf, const int* active, hipStream_t st) {
-  k_prolong_add<T><<<grid_of(nf, B), kBlock, 0, st>>>(nf, chunks_of(nf), grid_stride(nf), grid_stride(nf / 2),
-                                                      xc, xf, active);
+  constexpr int V = 4;   // 4 fine nodes per thread (needs nf >= 4)
+  const size_t pos = (size_t)(nf - 1) * nf * nf / V;
+  const uint32_t ch = (uint32_t)((pos + kBlock - 1) / kBlock);
+  k_prolong_add<T, V><<<dim3(ch * (uint32_t)B), kBlock, 0, st>>>(nf, ch, grid_stride(nf), grid_stride(nf / 2), xc,
+                                                                 xf, active);
   return hipGetLastError();
 }
 
@@ -309,23 +571,18 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st) 
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_fill_interior(int n, int B, T* v, double value, const int* active, hipStream_t st) {
-  k_fill_interior<T><<<grid_of(n, B), kBlock, 0, st>>>(n, chunks_of(n), grid_stride(n), v, T(value), active);
-  return hipGetLastError();
-}
-
 #define MLMC_INST(T)                                                                                    \
   template hipError_t launch_apply<T>(int, int, const T*, const T*, T*, const int*, hipStream_t);      \
   template hipError_t launch_residual<T>(int, int, const T*, const T*, const T*, T*, const int*,       \
                                          hipStream_t);                                                 \
   template hipError_t launch_cheb<T>(int, int, const T*, const T*, const T*, const T*, T*, double,     \
                                      double, bool, bool, const int*, hipStream_t);                     \
+  template hipError_t launch_pcg_apply_dot<T>(int, int, const T*, const T*, T*, SolveState, uint32_t*, \
+                                              hipStream_t);                                            \
   template hipError_t launch_restrict<T>(int, int, const T*, T*, const int*, hipStream_t);             \
   template hipError_t launch_prolong_add<T>(int, int, const T*, T*, const int*, hipStream_t);          \
   template hipError_t launch_coarsest<T>(int, const T*, const T*, T*, const int*, hipStream_t);        \
-  template hipError_t launch_coarsen<T>(int, int, const T*, T*, hipStream_t);                          \
-  template hipError_t launch_fill_interior<T>(int, int, T*, double, const int*, hipStream_t);
+  template hipError_t launch_coarsen<T>(int, int, const T*, T*, hipStream_t);
 MLMC_INST(float)
 MLMC_INST(double)
 #undef MLMC_INST
