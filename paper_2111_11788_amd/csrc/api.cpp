@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -202,6 +203,8 @@ struct mlmc_ctx {
   int64_t k_launch[2 * MLMC_K_COUNT] = {0};   // [precision][kernel]
   double k_ms[2 * MLMC_K_COUNT] = {0}, k_bytes[2 * MLMC_K_COUNT] = {0};
   int* h_nactive = nullptr;
+  int zvar[2] = {0, 0};           // z-march kernel variant for fp64 / fp32
+  int vsmall_n0[2] = {8, 16};     // mesh at which the single-kernel coarse V-cycle takes over (0: off)
 };
 
 static std::string g_create_error;
@@ -264,6 +267,8 @@ int launch(mlmc_ctx* ctx, int id, double bytes, F&& f) {
 // profiling slot of kernel `id` in the precision of T (fp32 slots follow the fp64 ones)
 template <class T>
 constexpr int kid(int id) { return id + (sizeof(T) == 4 ? MLMC_K_COUNT : 0); }
+template <class T>
+int zv(const mlmc_ctx* ctx) { return ctx->zvar[sizeof(T) == 4 ? 1 : 0]; }
 
 inline double dofs(int n) { return (double)(n - 1) * (n - 1) * (n - 1); }
 inline double elems(int n) { return (double)n * n * n; }
@@ -382,31 +387,47 @@ int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float
 }
 
 // One V-cycle on levels l.. of L; returns the buffer that holds the result.
+// With `dot` the last smoothing step of level l also writes the partial sums
+// of b . result (*dot_np per sample).
 template <class T>
 int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T* x, T* xo, T* t,
-           const int* active, T** result) {
+           const int* active, T** result, SolveState* dot = nullptr, uint32_t* dot_np = nullptr) {
   const int n = L[l].n;
   const double sz = sizeof(T);
   const double d = dofs(n) * B, e = elems(n) * B;
   hipStream_t st = ctx->st;
+  const int var = zv<T>(ctx);
   if (n == 2) {
     LAUNCH(kid<T>(MLMC_K_COARSEST), B * (8 + 2) * sz, launch_coarsest<T>(B, L[l].kap, b, x, active, st));
     *result = x;
+    if (dot) FAIL(MLMC_E_INVALID, "fused r.z needs a mesh n >= 4");
     return MLMC_OK;
   }
   const ChebCoeffs& ch = ctx->cheb;
   const T* kap = L[l].kap;
+  const int small = ctx->vsmall_n0[sizeof(T) == 4 ? 1 : 0];
+  if (small && n <= small && n >= 4) {
+    // the rest of the V-cycle in one kernel (coarse data in LDS)
+    const T* kl[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (size_t q = l; q < L.size() && q - l < 4; ++q) kl[q - l] = L[q].kap;
+    LAUNCH(kid<T>(MLMC_K_COARSEST), (2 * d + e * 8.0 / 7.0) * sz,
+           launch_vsmall<T>(n, B, ch.degree, ch.c1, ch.c2, kl, b, x, active, st));
+    *result = x;
+    return MLMC_OK;
+  }
   LAUNCH(kid<T>(MLMC_K_CHEB_ZERO), (2 * d + e) * sz,
-         launch_cheb<T>(n, B, kap, b, nullptr, nullptr, x, 0.0, ch.c2[0], true, false, active, st));
+         launch_cheb<T>(n, B, kap, b, nullptr, nullptr, x, 0.0, ch.c2[0], true, false, active, st, nullptr, nullptr,
+                        var));
   T* cur = x;
   T* oth = xo;
   for (int s = 1; s < ch.degree; ++s) {
     const bool use_xo = s > 1;
     LAUNCH(kid<T>(use_xo ? MLMC_K_CHEB_XO : MLMC_K_CHEB), ((use_xo ? 4 : 3) * d + e) * sz,
-           launch_cheb<T>(n, B, kap, b, cur, oth, oth, ch.c1[s], ch.c2[s], false, use_xo, active, st));
+           launch_cheb<T>(n, B, kap, b, cur, oth, oth, ch.c1[s], ch.c2[s], false, use_xo, active, st, nullptr,
+                          nullptr, var));
     std::swap(cur, oth);
   }
-  LAUNCH(kid<T>(MLMC_K_RESIDUAL), (3 * d + e) * sz, launch_residual<T>(n, B, kap, b, cur, t, active, st));
+  LAUNCH(kid<T>(MLMC_K_RESIDUAL), (3 * d + e) * sz, launch_residual<T>(n, B, kap, b, cur, t, active, st, var));
   Level<T>& nx = L[l + 1];
   const double dc = dofs(n / 2) * B;
   LAUNCH(kid<T>(MLMC_K_RESTRICT), (d + dc) * sz, launch_restrict<T>(n, B, t, nx.b, active, st));
@@ -415,27 +436,33 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
   LAUNCH(kid<T>(MLMC_K_PROLONG), (2 * d + dc) * sz, launch_prolong_add<T>(n, B, xc, cur, active, st));
   for (int s = 0; s < ch.degree; ++s) {
     const bool use_xo = s > 0;
+    const bool last = s == ch.degree - 1;
     LAUNCH(kid<T>(use_xo ? MLMC_K_CHEB_XO : MLMC_K_CHEB), ((use_xo ? 4 : 3) * d + e) * sz,
-           launch_cheb<T>(n, B, kap, b, cur, oth, oth, s == 0 ? 0.0 : ch.c1[s], ch.c2[s], false, use_xo,
-                          active, st));
+           launch_cheb<T>(n, B, kap, b, cur, oth, oth, s == 0 ? 0.0 : ch.c1[s], ch.c2[s], false, use_xo, active, st,
+                          last ? dot : nullptr, last ? dot_np : nullptr, var));
     std::swap(cur, oth);
   }
   *result = cur;
   return MLMC_OK;
 }
 
+// z = M^-1 r.  When *fused_np is set on return, the partial sums of r . z
+// are already in S.partial (GMG path); otherwise the caller computes them.
 template <class T>
-int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T** z, const int* active) {
+int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T** z, SolveState& S,
+                 uint32_t* fused_np) {
   const int n = L[0].n;
+  *fused_np = 0;
   if (L.size() == 1 || n == 2) {
-    if (n == 2) return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, active, z);
+    if (n == 2) return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, S.active, z);
     // Jacobi: z = D^-1 r
     LAUNCH(kid<T>(MLMC_K_CHEB_ZERO), (2 * dofs(n) + elems(n)) * B * sizeof(T),
-           launch_cheb<T>(n, B, L[0].kap, r, nullptr, nullptr, L[0].x, 0.0, 1.0, true, false, active, ctx->st));
+           launch_cheb<T>(n, B, L[0].kap, r, nullptr, nullptr, L[0].x, 0.0, 1.0, true, false, S.active, ctx->st,
+                          nullptr, nullptr, zv<T>(ctx)));
     *z = L[0].x;
     return MLMC_OK;
   }
-  return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, active, z);
+  return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, S.active, z, &S, fused_np);
 }
 
 int count_active(mlmc_ctx* ctx, SolveState& s, int B, int* out) {
@@ -454,17 +481,17 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
   const int n = L[0].n;
   const double sz = sizeof(T), d = dofs(n) * B, e = elems(n) * B;
   hipStream_t st = ctx->st;
-  const size_t S0 = grid_stride(n);
+  const int var = zv<T>(ctx);
   uint32_t np = 0;
   T* z = nullptr;
-  if (int rc = precondition<T>(ctx, L, B, r, &z, S.active)) return rc;
-  LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
+  if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
+  if (!np) LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RZ_INIT, 0.0, np, S, nullptr, st));
-  HIPCHK(hipMemcpyAsync(p, z, (size_t)B * S0 * sizeof(T), hipMemcpyDeviceToDevice, st));
+  LAUNCH(kid<T>(MLMC_K_PCG_DIRECTION), 2 * d * sz, launch_copy<T>(n, B, z, p, S, st));
   const double tol2 = tol * tol;
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
-    LAUNCH(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, &np, st));
+    LAUNCH(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, &np, st, var));
     LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA, 0.0, np, S, nullptr, st));
     LAUNCH(kid<T>(MLMC_K_PCG_UPDATE), 6 * d * sz, launch_pcg_update<T>(n, B, x, p, r, q, S, &np, st));
     LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, tol2, np, S, nullptr, st));
@@ -474,8 +501,8 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
       if (na == 0) break;
     }
     if (it == max_iter) break;
-    if (int rc = precondition<T>(ctx, L, B, r, &z, S.active)) return rc;
-    LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
+    if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
+    if (!np) LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
     LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BETA, 0.0, np, S, nullptr, st));
     LAUNCH(kid<T>(MLMC_K_PCG_DIRECTION), 3 * d * sz, launch_pcg_direction<T>(n, B, z, p, S, st));
   }
@@ -484,7 +511,9 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
 }
 
 // Solve A(kap) u = h^3 for B samples on the n^3 mesh into u (grid layout).
-int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv) {
+// kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
+int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
+               bool kap32_ready = false) {
   const int n = w.n, B = w.B;
   hipStream_t st = ctx->st;
   const double h = 1.0 / n, h3 = h * h * h;
@@ -512,7 +541,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       total_it += it;
       // confirm with the true residual; samples above tolerance continue
       LAUNCH(MLMC_K_MISC, 0, launch_set_active(B, O, 1, st));
-      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r, O, &np, st));
+      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r, O, &np, st, zv<double>(ctx)));
       LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
       int na = 0;
       if (int rc = count_active(ctx, O, B, &na)) return rc;
@@ -521,7 +550,8 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
   } else {
     auto& L = w.L32;
     SolveState& I = w.inner.s;
-    LAUNCH(MLMC_K_MISC, e * 12, (launch_convert<double, float>((size_t)B * elem_count(n), kap, L[0].kap, st)));
+    if (!kap32_ready)
+      LAUNCH(MLMC_K_MISC, e * 12, (launch_convert<double, float>((size_t)B * elem_count(n), kap, L[0].kap, st)));
     for (size_t l = 1; l < L.size(); ++l)
       LAUNCH(kid<float>(MLMC_K_COARSEN), (elems(L[l - 1].n) + elems(L[l].n)) * B * 4,
              launch_coarsen<float>(L[l - 1].n, B, L[l - 1].kap, L[l].kap, st));
@@ -541,7 +571,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
         return rc;
       total_it += it;
       LAUNCH(MLMC_K_MISC, d * 20, launch_add_correction(n, B, u, w.d, O, st));
-      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r64, O, &np, st));
+      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r64, O, &np, st, zv<double>(ctx)));
       LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
       int na = 0;
       if (int rc = count_active(ctx, O, B, &na)) return rc;
@@ -594,6 +624,9 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   ctx->modes = kl_select(cfg->corr_len, cfg->sigma2, cfg->n_modes);
   ctx->K1 = (int)ctx->modes.omega.size();
   ctx->cheb = cheb_coeffs(ctx->cfg.cheb_degree, kChebHi / kChebRatio, kChebHi);
+  if (const char* zvs = std::getenv("MLMC_ZVAR")) ctx->zvar[0] = ctx->zvar[1] = std::atoi(zvs);
+  if (const char* vs = std::getenv("MLMC_VSMALL"))
+    if (std::atoi(vs) == 0) ctx->vsmall_n0[0] = ctx->vsmall_n0[1] = 0;
   ctx->stats.assign(cfg->levels, Running{});
   const size_t need = persistent_bytes(cfg, ctx->K1);
   if (need > cfg->arena_bytes) {
@@ -753,14 +786,15 @@ int mlmc_sample_level(mlmc_ctx* ctx, int32_t level, uint64_t first, uint64_t cou
     const uint64_t start = first + done;
     LAUNCH(MLMC_K_XI, (double)B * ctx->cfg.n_modes * 8,
            launch_draw_xi(ctx->cfg.seed, level, start, B, ctx->cfg.n_modes, w.xi, ctx->st));
-    if (int rc = field_impl(ctx, nf, B, w.xi, w.kf, nullptr)) return rc;
+    const bool mixed = ctx->cfg.precision == MLMC_PREC_MIXED;
+    if (int rc = field_impl(ctx, nf, B, w.xi, w.kf, mixed ? w.wf.L32[0].kap : nullptr)) return rc;
     bool conv = false;
-    if (int rc = solve_impl(ctx, w.wf, w.kf, w.uf, iters ? iters + done : nullptr, &conv)) return rc;
+    if (int rc = solve_impl(ctx, w.wf, w.kf, w.uf, iters ? iters + done : nullptr, &conv, mixed)) return rc;
     all_conv = all_conv && conv;
     if (int rc = qoi_impl(ctx, w.wf.outer.s, nf, B, w.uf, w.qf)) return rc;
     if (level > 0) {
-      if (int rc = field_impl(ctx, nf / 2, B, w.xi, w.kc, nullptr)) return rc;
-      if (int rc = solve_impl(ctx, w.wc, w.kc, w.uc, nullptr, &conv)) return rc;
+      if (int rc = field_impl(ctx, nf / 2, B, w.xi, w.kc, mixed ? w.wc.L32[0].kap : nullptr)) return rc;
+      if (int rc = solve_impl(ctx, w.wc, w.kc, w.uc, nullptr, &conv, mixed)) return rc;
       all_conv = all_conv && conv;
       if (int rc = qoi_impl(ctx, w.wc.outer.s, nf / 2, B, w.uc, w.qc)) return rc;
     }

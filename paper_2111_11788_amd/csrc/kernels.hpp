@@ -31,18 +31,24 @@ struct SolveState {
 
 // Grid-layout kernels on an n^3 mesh for `B` samples; `active` (may be null)
 // skips samples whose flag is 0.  Device pointers must be 16-byte aligned.
+// z-march variants (bit flags), chosen per context by measurement
+enum : int { ZVAR_PREFETCH = 1 };
+
 template <class T>
-hipError_t launch_apply(int n, int B, const T* kap, const T* u, T* y, const int* active, hipStream_t st);
+hipError_t launch_apply(int n, int B, const T* kap, const T* u, T* y, const int* active, hipStream_t st,
+                        int var = 0);
 template <class T>
 hipError_t launch_residual(int n, int B, const T* kap, const T* b, const T* x, T* r,
-                           const int* active, hipStream_t st);
+                           const int* active, hipStream_t st, int var = 0);
 // Chebyshev step.  zero_x: out = c2 D^-1 b (x0 = 0).  Otherwise
 // out = x + c1 (x - xo) + c2 D^-1 (b - A x), where use_xo == 0 takes xo = 0.
-// out may alias xo, never x.
+// out may alias xo, never x.  With `dot` (non-zero-x steps on meshes n >= 4)
+// the kernel also writes partial sums of b . out into dot->partial.
 template <class T>
 hipError_t launch_cheb(int n, int B, const T* kap, const T* b, const T* x, const T* xo, T* out,
                        double c1, double c2, bool zero_x, bool use_xo, const int* active,
-                       hipStream_t st);
+                       hipStream_t st, SolveState* dot = nullptr, uint32_t* nparts = nullptr,
+                       int var = 0);
 template <class T>
 hipError_t launch_restrict(int nf, int B, const T* rf, T* bc, const int* active, hipStream_t st);
 template <class T>
@@ -56,11 +62,21 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st);
 template <class T>
 hipError_t launch_fill_interior(int n, int B, T* v, double value, const int* active, hipStream_t st);
 
+// vsmall.hip -- the whole V-cycle from an n0^3 mesh (n0 <= 16) down to 2^3 in
+// one kernel, one workgroup per sample, all coarse data in LDS.
+// kap_levels[l] is the kappa of mesh n0 >> l; b, x are grid-layout n0 vectors.
+template <class T>
+size_t vsmall_lds_bytes(int n0);
+template <class T>
+hipError_t launch_vsmall(int n0, int B, int degree, const double* c1, const double* c2,
+                         const T* const* kap_levels, const T* b, T* x, const int* active,
+                         hipStream_t st);
+
 // PCG building blocks, fp64 scalars and partial sums.  Launchers that write
 // partial sums report in *nparts how many per sample they wrote.
 template <class T>
 hipError_t launch_pcg_apply_dot(int n, int B, const T* kap, const T* p, T* q, SolveState s,
-                                uint32_t* nparts, hipStream_t st);
+                                uint32_t* nparts, hipStream_t st, int var = 0);
 template <class T>
 hipError_t launch_pcg_update(int n, int B, T* x, const T* p, T* r, const T* q, SolveState s,
                              uint32_t* nparts, hipStream_t st);
@@ -71,7 +87,11 @@ template <class T>
 hipError_t launch_pcg_direction(int n, int B, const T* z, T* p, SolveState s, hipStream_t st);
 // outer residual of the refinement loop: r = b - A x in fp64 plus ||r||^2 partials
 hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x,
-                                double* r, SolveState s, uint32_t* nparts, hipStream_t st);
+                                double* r, SolveState s, uint32_t* nparts, hipStream_t st,
+                                int var = 0);
+// p = z on active samples (vectorized copy of the planes 1..n-1 range)
+template <class T>
+hipError_t launch_copy(int n, int B, const T* z, T* p, SolveState s, hipStream_t st);
 // x64 += d (fp32 correction) on active samples
 hipError_t launch_add_correction(int n, int B, double* x, const float* d, SolveState s,
                                  hipStream_t st);

@@ -117,6 +117,20 @@ __global__ void __launch_bounds__(kBlock) k_pcg_direction(SGeom g, size_t stride
   for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) pv[t] = zv[t] + be * pv[t];
 }
 
+// p = z
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_copy(SGeom g, size_t stride, const T* __restrict__ z, T* __restrict__ p,
+                                                 SolveState st) {
+  constexpr int V = 16 / sizeof(T);
+  typedef typename Vec<T, V>::type vt;
+  const Span sp = span_of(g);
+  if (!st.active[sp.b]) return;
+  const size_t base = (size_t)sp.b * stride + (size_t)g.n * g.n;
+  const vt* zv = reinterpret_cast<const vt*>(z + base);
+  vt* pv = reinterpret_cast<vt*>(p + base);
+  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) pv[t] = zv[t];
+}
+
 // x64 += d32 (4 values per step)
 __global__ void __launch_bounds__(kBlock) k_add_correction(SGeom g, size_t stride, double* __restrict__ x,
                                                            const float* __restrict__ d, SolveState st) {
@@ -270,6 +284,13 @@ hipError_t launch_pcg_direction(int n, int B, const T* z, T* p, SolveState s, hi
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_copy(int n, int B, const T* z, T* p, SolveState s, hipStream_t st) {
+  const SGeom g = sgeom<T>(n);
+  k_copy<T><<<sgrid<T>(g, B), kBlock, 0, st>>>(g, grid_stride(n), z, p, s);
+  return hipGetLastError();
+}
+
 hipError_t launch_add_correction(int n, int B, double* x, const float* d, SolveState s, hipStream_t st) {
   const SGeom g = sgeom<float>(n);   // units of 4 values
   k_add_correction<<<sgrid<float>(g, B), kBlock, 0, st>>>(g, grid_stride(n), x, d, s);
@@ -320,6 +341,8 @@ template hipError_t launch_dot<float>(int, int, const float*, const float*, Solv
 template hipError_t launch_dot<double>(int, int, const double*, const double*, SolveState, uint32_t*, hipStream_t);
 template hipError_t launch_pcg_direction<float>(int, int, const float*, float*, SolveState, hipStream_t);
 template hipError_t launch_pcg_direction<double>(int, int, const double*, double*, SolveState, hipStream_t);
+template hipError_t launch_copy<float>(int, int, const float*, float*, SolveState, hipStream_t);
+template hipError_t launch_copy<double>(int, int, const double*, double*, SolveState, hipStream_t);
 template hipError_t launch_fill_interior<float>(int, int, float*, double, const int*, hipStream_t);
 template hipError_t launch_fill_interior<double>(int, int, double*, double, const int*, hipStream_t);
 

@@ -100,15 +100,17 @@ struct EpiResidual {
   }
 };
 
-// out = x + c1 (x - xo) + c2 D^-1 (b - A x); without xo the previous iterate is 0
-template <class T, int V, bool USE_XO>
+// out = x + c1 (x - xo) + c2 D^-1 (b - A x); without xo the previous iterate is
+// 0.  DOT also accumulates b . out (the r . z of the enclosing PCG when this is
+// the last smoothing step of the finest level).
+template <class T, int V, bool USE_XO, bool DOT>
 struct EpiCheb {
-  static constexpr bool kReduce = false;
+  static constexpr bool kReduce = DOT;
   const T* b;
   const T* xo;
   T* out;
   T c1, c2;
-  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double&) const {
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
     T bv[V], xov[V], o[V];
     vload<T, V>(b + pos, bv);
     if (USE_XO) vload<T, V>(xo + pos, xov);
@@ -116,6 +118,7 @@ struct EpiCheb {
     for (int v = 0; v < V; ++v) {
       const T prev = USE_XO ? uc[v] - xov[v] : uc[v];
       o[v] = ok[v] ? uc[v] + c1 * prev + c2 * (bv[v] - au[v]) / dg[v] : T(0);
+      if (DOT) acc += (double)bv[v] * (double)o[v];
     }
     vstore<T, V>(out + pos, o);
   }
@@ -171,7 +174,9 @@ struct EpiChebZero {
 };
 
 // --------------------------------------------------------- z-march engine
-template <class T, int V, bool NEED_U, class Epi>
+// PF: issue the loads of the next plane step before computing the current one
+// (one more plane of registers, more memory-level parallelism per wave).
+template <class T, int V, bool NEED_U, bool PF, class Epi>
 __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, const T* __restrict__ u,
                                                 const T* __restrict__ kap, const int* __restrict__ active,
                                                 double* __restrict__ partial, uint32_t pstride, Epi epi) {
@@ -198,32 +203,61 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
     for (int v = 0; v < V; ++v) ok[v] = (i0 + v) != 0;
     T U[3][3][V + 2];
     T K[2][2][V + 1];
-    auto load_u = [&](int p, int kk) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const T* row = ub + (size_t)n * (j - 1 + r) + (size_t)n2 * kk;
-        U[p][r][0] = i0 > 0 ? row[i0 - 1] : T(0);
-        vload<T, V>(row + i0, &U[p][r][1]);
-        U[p][r][V + 1] = row[i0 + V];   // position n is the next row's zero
-      }
+    T PU[PF ? 3 : 1][V + 2];
+    T PK[PF ? 2 : 1][V + 1];
+    auto load_urow = [&](T* dst, int r, int kk) {
+      const T* row = ub + (size_t)n * (j - 1 + r) + (size_t)n2 * kk;
+      dst[0] = i0 > 0 ? row[i0 - 1] : T(0);
+      vload<T, V>(row + i0, dst + 1);
+      dst[V + 1] = row[i0 + V];   // position n is the next row's zero
     };
-    auto load_k = [&](int q, int ez) {
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const T* row = kb + (size_t)n * (j - 1 + r) + (size_t)n2 * ez;
-        K[q][r][0] = i0 > 0 ? row[i0 - 1] : T(0);
-        vload<T, V>(row + i0, &K[q][r][1]);
-      }
+    auto load_krow = [&](T* dst, int r, int ez) {
+      const T* row = kb + (size_t)n * (j - 1 + r) + (size_t)n2 * ez;
+      dst[0] = i0 > 0 ? row[i0 - 1] : T(0);
+      vload<T, V>(row + i0, dst + 1);
     };
     if (NEED_U) {
-      load_u(0, k0 - 1);
-      load_u(1, k0);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        load_urow(U[0][r], r, k0 - 1);
+        load_urow(U[1][r], r, k0);
+      }
     }
-    load_k(0, k0 - 1);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) load_krow(K[0][r], r, k0 - 1);
+    if (PF) {
+      if (NEED_U)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) load_urow(PU[r], r, k0 + 1);
+#pragma unroll
+      for (int r = 0; r < 2; ++r) load_krow(PK[r], r, k0);
+    }
     const T third = T(1) / T(3), twelfth = T(1) / T(12);
     for (int k = k0; k < k1; ++k) {
-      if (NEED_U) load_u(2, k + 1);
-      load_k(1, k);
+      if (PF) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < V + 2; ++c)
+            if (NEED_U) U[2][r][c] = PU[r][c];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int c = 0; c < V + 1; ++c) K[1][r][c] = PK[r][c];
+        if (k + 1 < k1) {
+          if (NEED_U)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) load_urow(PU[r], r, k + 2);
+#pragma unroll
+          for (int r = 0; r < 2; ++r) load_krow(PK[r], r, k + 1);
+        }
+      } else {
+        if (NEED_U)
+#pragma unroll
+          for (int r = 0; r < 3; ++r) load_urow(U[2][r], r, k + 1);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) load_krow(K[1][r], r, k);
+      }
       T au[V], dg[V], uc[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
@@ -270,13 +304,17 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
 
 template <class T, bool NEED_U, class Epi>
 hipError_t zlaunch(int n, int B, const T* u, const T* kap, const int* active, double* partial, uint32_t pstride,
-                   Epi epi, uint32_t* nparts, hipStream_t st) {
+                   Epi epi, uint32_t* nparts, int var, hipStream_t st) {
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
-  k_zmarch<T, V, NEED_U, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(g, grid_stride(n), T(1) / T(n), u, kap,
-                                                                       active, partial, pstride, epi);
+  if (var & ZVAR_PREFETCH)
+    k_zmarch<T, V, NEED_U, true, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
+        g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi);
+  else
+    k_zmarch<T, V, NEED_U, false, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
+        g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi);
   return hipGetLastError();
 }
 
@@ -371,7 +409,9 @@ inline bool use_small(int n) { return n < ZV<T>::V || n < 2; }
 
 // ------------------------------------------------------ transfer kernels
 // full weighting: coarse node (I,J,K) gathers fine (2I+dx, 2J+dy, 2K+dz) with
-// weights prod_d (dx == 0 ? 1 : 1/2)
+// weights prod_d (dx == 0 ? 1 : 1/2).  A thread owns two coarse nodes I0, I0+1
+// (I0 even) of one coarse row: per fine row it needs fine x 2I0-1 .. 2I0+3, one
+// aligned 4-vector and one halo value.
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_restrict(int nc, uint32_t nchunk, size_t sc, size_t sf,
                                                      const T* __restrict__ rf, T* __restrict__ bc,
@@ -380,27 +420,29 @@ __global__ void __launch_bounds__(kBlock) k_restrict(int nc, uint32_t nchunk, si
   const uint32_t b = logical / nchunk, c = logical - b * nchunk;
   if (active && !active[b]) return;
   const uint32_t n2 = (uint32_t)nc * nc;
-  const uint32_t p = n2 + c * kBlock + threadIdx.x;
+  const uint32_t p = n2 + 2 * (c * kBlock + threadIdx.x);
+  if (p >= n2 * (uint32_t)nc) return;
   const int lg = ilog2(nc);
-  const uint32_t I = p & (nc - 1), J = (p >> lg) & (nc - 1), K = p >> (2 * lg);
-  if (!(p < n2 * (uint32_t)nc && I != 0 && J != 0)) return;
+  const uint32_t I0 = p & (nc - 1), J = (p >> lg) & (nc - 1), K = p >> (2 * lg);
+  if (J == 0) return;
   const int nf = 2 * nc;
   const T* r = rf + b * sf;
-  const int f2 = nf * nf;
-  const uint32_t cidx = 2 * I + nf * 2 * J + f2 * 2 * K;
-  T acc = T(0);
+  const size_t f2 = (size_t)nf * nf;
+  T a0 = T(0), a1 = T(0);
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
-    T az = T(0);
+  for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
-      const uint32_t row = cidx + nf * dy + f2 * dz;
-      const T ay = T(0.5) * (r[row - 1] + r[row + 1]) + r[row];
-      az += (dy == 0 ? T(1) : T(0.5)) * ay;
+      const T w = (dy == 0 ? T(1) : T(0.5)) * (dz == 0 ? T(1) : T(0.5));
+      const T* row = r + (size_t)nf * (2 * J + dy) + f2 * (2 * K + dz) + 2 * I0;
+      T f[5];
+      f[0] = I0 > 0 ? row[-1] : T(0);
+      vload<T, 4>(row, f + 1);
+      a0 += w * (T(0.5) * (f[0] + f[2]) + f[1]);
+      a1 += w * (T(0.5) * (f[2] + f[4]) + f[3]);
     }
-    acc += (dz == 0 ? T(1) : T(0.5)) * az;
-  }
-  bc[b * sc + p] = acc;
+  T o[2] = {I0 > 0 ? a0 : T(0), a1};
+  vstore<T, 2>(bc + b * sc + p, o);
 }
 
 // trilinear interpolation from the n/2 grid added to the fine values; a
@@ -488,54 +530,67 @@ __global__ void __launch_bounds__(kBlock) k_convert(size_t count, const Ts* __re
 }  // namespace
 
 template <class T>
-hipError_t launch_apply(int n, int B, const T* kap, const T* u, T* y, const int* active, hipStream_t st) {
+hipError_t launch_apply(int n, int B, const T* kap, const T* u, T* y, const int* active, hipStream_t st, int var) {
   if (use_small<T>(n))
     return small_launch<T>(0, n, B, kap, u, nullptr, nullptr, y, 0, 0, active, nullptr, 0, nullptr, st);
-  return zlaunch<T, true>(n, B, u, kap, active, nullptr, 0, EpiApply<T, ZV<T>::V>{y}, nullptr, st);
+  return zlaunch<T, true>(n, B, u, kap, active, nullptr, 0, EpiApply<T, ZV<T>::V>{y}, nullptr, var, st);
 }
 
 template <class T>
 hipError_t launch_residual(int n, int B, const T* kap, const T* b, const T* x, T* r, const int* active,
-                           hipStream_t st) {
+                           hipStream_t st, int var) {
   if (use_small<T>(n))
     return small_launch<T>(1, n, B, kap, x, b, nullptr, r, 0, 0, active, nullptr, 0, nullptr, st);
-  return zlaunch<T, true>(n, B, x, kap, active, nullptr, 0, EpiResidual<T, ZV<T>::V>{b, r}, nullptr, st);
+  return zlaunch<T, true>(n, B, x, kap, active, nullptr, 0, EpiResidual<T, ZV<T>::V>{b, r}, nullptr, var, st);
 }
 
 template <class T>
 hipError_t launch_cheb(int n, int B, const T* kap, const T* b, const T* x, const T* xo, T* out, double c1,
-                       double c2, bool zero_x, bool use_xo, const int* active, hipStream_t st) {
+                       double c2, bool zero_x, bool use_xo, const int* active, hipStream_t st, SolveState* dot,
+                       uint32_t* nparts, int var) {
   constexpr int V = ZV<T>::V;
-  if (use_small<T>(n))
+  if (use_small<T>(n)) {
+    if (dot) return hipErrorInvalidValue;   // the fused r.z is only used on meshes with n >= V
     return small_launch<T>(zero_x ? 2 : (use_xo ? 4 : 3), n, B, kap, zero_x ? nullptr : x, b, xo, out, c1, c2,
                            active, nullptr, 0, nullptr, st);
-  if (zero_x)
-    return zlaunch<T, false>(n, B, nullptr, kap, active, nullptr, 0, EpiChebZero<T, V>{b, out, T(c2)}, nullptr, st);
+  }
+  if (zero_x) {
+    if (dot) return hipErrorInvalidValue;
+    return zlaunch<T, false>(n, B, nullptr, kap, active, nullptr, 0, EpiChebZero<T, V>{b, out, T(c2)}, nullptr, var,
+                             st);
+  }
+  if (dot) {
+    if (use_xo)
+      return zlaunch<T, true>(n, B, x, kap, active, dot->partial, dot->pstride,
+                              EpiCheb<T, V, true, true>{b, xo, out, T(c1), T(c2)}, nparts, var, st);
+    return zlaunch<T, true>(n, B, x, kap, active, dot->partial, dot->pstride,
+                            EpiCheb<T, V, false, true>{b, xo, out, T(c1), T(c2)}, nparts, var, st);
+  }
   if (use_xo)
-    return zlaunch<T, true>(n, B, x, kap, active, nullptr, 0, EpiCheb<T, V, true>{b, xo, out, T(c1), T(c2)},
-                            nullptr, st);
-  return zlaunch<T, true>(n, B, x, kap, active, nullptr, 0, EpiCheb<T, V, false>{b, xo, out, T(c1), T(c2)}, nullptr,
-                          st);
+    return zlaunch<T, true>(n, B, x, kap, active, nullptr, 0, EpiCheb<T, V, true, false>{b, xo, out, T(c1), T(c2)},
+                            nullptr, var, st);
+  return zlaunch<T, true>(n, B, x, kap, active, nullptr, 0, EpiCheb<T, V, false, false>{b, xo, out, T(c1), T(c2)},
+                          nullptr, var, st);
 }
 
 template <class T>
 hipError_t launch_pcg_apply_dot(int n, int B, const T* kap, const T* p, T* q, SolveState s, uint32_t* nparts,
-                                hipStream_t st) {
+                                hipStream_t st, int var) {
   if (use_small<T>(n))
     return small_launch<T>(5, n, B, kap, p, nullptr, nullptr, q, 0, 0, s.active, s.partial, s.pstride, nparts, st);
-  return zlaunch<T, true>(n, B, p, kap, s.active, s.partial, s.pstride, EpiPcgApply<T, ZV<T>::V>{q}, nparts, st);
+  return zlaunch<T, true>(n, B, p, kap, s.active, s.partial, s.pstride, EpiPcgApply<T, ZV<T>::V>{q}, nparts, var, st);
 }
 
 hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x, double* r,
-                                SolveState s, uint32_t* nparts, hipStream_t st) {
+                                SolveState s, uint32_t* nparts, hipStream_t st, int var) {
   return zlaunch<double, true>(n, B, x, kap, s.active, s.partial, s.pstride,
-                               EpiTrueResidual<double, ZV<double>::V>{bconst, r}, nparts, st);
+                               EpiTrueResidual<double, ZV<double>::V>{bconst, r}, nparts, var, st);
 }
 
 template <class T>
 hipError_t launch_restrict(int nf, int B, const T* rf, T* bc, const int* active, hipStream_t st) {
   const int nc = nf / 2;
-  const uint32_t ch = chunks_of(nc);
+  const uint32_t ch = (uint32_t)(((size_t)(nc - 1) * nc * nc / 2 + kBlock - 1) / kBlock);
   k_restrict<T><<<dim3(ch * (uint32_t)B), kBlock, 0, st>>>(nc, ch, grid_stride(nc), grid_stride(nf), rf, bc, active);
   return hipGetLastError();
 }
@@ -572,13 +627,14 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st) 
 }
 
 #define MLMC_INST(T)                                                                                    \
-  template hipError_t launch_apply<T>(int, int, const T*, const T*, T*, const int*, hipStream_t);      \
+  template hipError_t launch_apply<T>(int, int, const T*, const T*, T*, const int*, hipStream_t, int); \
   template hipError_t launch_residual<T>(int, int, const T*, const T*, const T*, T*, const int*,       \
-                                         hipStream_t);                                                 \
+                                         hipStream_t, int);                                            \
   template hipError_t launch_cheb<T>(int, int, const T*, const T*, const T*, const T*, T*, double,     \
-                                     double, bool, bool, const int*, hipStream_t);                     \
+                                     double, bool, bool, const int*, hipStream_t, SolveState*,         \
+                                     uint32_t*, int);                                                  \
   template hipError_t launch_pcg_apply_dot<T>(int, int, const T*, const T*, T*, SolveState, uint32_t*, \
-                                              hipStream_t);                                            \
+                                              hipStream_t, int);                                       \
   template hipError_t launch_restrict<T>(int, int, const T*, T*, const int*, hipStream_t);             \
   template hipError_t launch_prolong_add<T>(int, int, const T*, T*, const int*, hipStream_t);          \
   template hipError_t launch_coarsest<T>(int, const T*, const T*, T*, const int*, hipStream_t);        \

@@ -89,8 +89,12 @@ def test_apply_matches_csr(dev, n, B):
         assert np.abs(y[b] - want).max() <= 1e-14 * scale
 
 
+@pytest.mark.parametrize("vsmall", ["1", "0"])
 @pytest.mark.parametrize("n,B,deg", [(4, 2, 2), (8, 3, 2), (16, 2, 3), (32, 1, 1)])
-def test_vcycle_matches_oracle(dev, n, B, deg):
+def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, monkeypatch):
+    # vsmall "1": coarse levels (8^3 and below in fp64) in the single-kernel
+    # V-cycle; "0": every level through the level-by-level kernels
+    monkeypatch.setenv("MLMC_VSMALL", vsmall)
     kap = element_field(n, B, seed=300 + n, spread=1.5)
     r = grid_vector(n, B, seed=400 + n)
     ctx = mm.Context(_wl(n0=n, levels=1), cheb_degree=deg, arena_bytes=256 << 20)
@@ -107,9 +111,11 @@ def _oracle_q(n, kap, qoi, rtol=1e-12):
     return q
 
 
-@pytest.mark.parametrize("precision,solver,tol", [(0, 0, 1e-8), (1, 0, 1e-7), (0, 1, 1e-8)])
+@pytest.mark.parametrize("precision,solver,tol,vsmall", [(0, 0, 1e-8, "1"), (1, 0, 1e-7, "1"), (0, 1, 1e-8, "1"),
+                                                         (1, 0, 1e-7, "0")])
 @pytest.mark.parametrize("n,B,qoi", [(8, 5, 0), (16, 3, 1), (32, 2, 1)])
-def test_solve_qoi_matches_oracle(dev, precision, solver, tol, n, B, qoi):
+def test_solve_qoi_matches_oracle(dev, precision, solver, tol, vsmall, n, B, qoi, monkeypatch):
+    monkeypatch.setenv("MLMC_VSMALL", vsmall)
     wl = _wl(n0=n, levels=1, qoi=qoi, precision=precision, solver=solver, n_modes=16, corr_len=0.3)
     ctx = mm.Context(wl, arena_bytes=512 << 20)
     xi = ctx.draw_xi(0, 11, B)
