@@ -183,6 +183,28 @@ int mlmc_qoi(mlmc_ctx* ctx, int32_t n, int64_t count, const double* u, double* q
 int mlmc_sample_level(mlmc_ctx* ctx, int32_t level, uint64_t first, uint64_t count,
                       double* y, double* q_fine, double* q_coarse, int32_t* iters);
 
+typedef struct mlmc_estimate_opts {
+  double eps;             /* target RMSE (absolute) of the estimator, > 0 */
+  int32_t n_pilot;        /* pilot samples per level before allocating, >= 2 */
+  int32_t cost_model;     /* 0: measured GPU seconds per sample; 1: interior DOFs of the pair */
+  double extra_fraction;  /* N_l is multiplied by (1 + extra_fraction), >= 0 (Sec. 2.3) */
+  int32_t max_rounds;     /* allocation rounds: re-estimate V_l after each top-up, >= 1 */
+} mlmc_estimate_opts;
+
+/* Multilevel estimate to a target RMSE on the context's fixed level set
+ * (L = levels - 1): draw n_pilot samples per level (continuing each level's
+ * sample indices after those already accumulated), estimate V(Y_l) by the
+ * 1/N sample variance (eq. sample_variance) and the cost C_l, take
+ *   N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_i sqrt(V_i C_i) (1 + extra))
+ * (eq. mlmc_num_samples), N_l >= n_pilot, and top every level up to N_l;
+ * repeat with the updated variances for max_rounds rounds or until no level
+ * needs more samples.  n_per_level (host, `levels` entries, may be NULL)
+ * receives the final N_l; out receives the estimator.  The statistical error
+ * sum_l V_l / N_l then targets eps^2 / 2 (the bias half of eq. mlmc_error is
+ * not estimated).  Errors: as mlmc_sample_level. */
+int mlmc_estimate(mlmc_ctx* ctx, const mlmc_estimate_opts* opts, uint64_t* n_per_level,
+                  mlmc_estimate_out* out);
+
 /* Running statistics of every level and the estimator of eq. mlmc_average
  * with the statistical error sum_l V(Y_l)/N_l (Sec. 2.2). */
 int mlmc_get_estimate(const mlmc_ctx* ctx, mlmc_estimate_out* out);

@@ -115,3 +115,41 @@ def run_mlmc(wl, n_per_level: Sequence[int]):
         ys.append(Y)
     qt, v, vq = estimator(stats)
     return qt, v, vq, stats, ys
+
+
+def estimate(wl, eps: float, n_pilot: int, max_rounds: int = 3, extra_fraction: float = 0.0):
+    """Pilot, optimal allocation (eq. mlmc_num_samples) and top-up on the fixed
+    level set, with the deterministic cost model C_l = interior DOFs of the
+    pair.  Round 0 draws n_pilot samples per level; each later round tops
+    every level up to max(N_l, n_pilot) from the current 1/N variances.
+    Returns (N_l list, Qtilde, V(Qtilde), stats)."""
+    L = wl.levels
+    stats = [RunningStats() for _ in range(L)]
+    target = [n_pilot] * L
+    for rnd in range(max_rounds + 1):
+        more = False
+        for l in range(L):
+            have = stats[l].n
+            if target[l] > have:
+                more = True
+                Y, _, _, _ = sample_level(wl, l, have, target[l] - have)
+                for y in Y:
+                    stats[l].push(float(y))
+        if not more and rnd > 0:
+            break
+        if rnd == max_rounds:
+            break
+        V = [s.var for s in stats]
+        C = [level_cost(wl, l) for l in range(L)]
+        tot = sum(math.sqrt(v * c) for v, c in zip(V, C))
+        want = [max(int(math.ceil(2.0 / (eps * eps) * math.sqrt(v / c) * tot * (1.0 + extra_fraction))), n_pilot)
+                for v, c in zip(V, C)]
+        grow = False
+        for l in range(L):
+            if want[l] > target[l]:
+                target[l] = want[l]
+                grow = True
+        if not grow:
+            break
+    qt, v, vq = estimator(stats)
+    return [s.n for s in stats], qt, vq, stats

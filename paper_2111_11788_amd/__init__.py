@@ -27,8 +27,8 @@ KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "
 # exported symbols of include/mlmc.h (checked by the CPU test suite)
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
            "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_vcycle", "mlmc_solve", "mlmc_qoi",
-           "mlmc_sample_level", "mlmc_get_estimate", "mlmc_reset_stats", "mlmc_set_profiling",
-           "mlmc_kernel_time"]
+           "mlmc_sample_level", "mlmc_estimate", "mlmc_get_estimate", "mlmc_reset_stats",
+           "mlmc_set_profiling", "mlmc_kernel_time"]
 
 
 class MLMCError(RuntimeError):
@@ -49,6 +49,11 @@ class Config(ctypes.Structure):
 class LevelStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("mean", ctypes.c_double), ("m2", ctypes.c_double),
                 ("var", ctypes.c_double), ("cost", ctypes.c_double)]
+
+
+class EstimateOpts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("n_pilot", ctypes.c_int32), ("cost_model", ctypes.c_int32),
+                ("extra_fraction", ctypes.c_double), ("max_rounds", ctypes.c_int32)]
 
 
 class EstimateOut(ctypes.Structure):
@@ -83,6 +88,7 @@ def lib():
         "mlmc_qoi": (ctypes.c_int, [P, I32, I64, P, P]),
         "mlmc_sample_level": (ctypes.c_int, [P, I32, U64, U64, P, P, P, P]),
         "mlmc_get_estimate": (ctypes.c_int, [P, ctypes.POINTER(EstimateOut)]),
+        "mlmc_estimate": (ctypes.c_int, [P, ctypes.POINTER(EstimateOpts), P, ctypes.POINTER(EstimateOut)]),
         "mlmc_reset_stats": (ctypes.c_int, [P]),
         "mlmc_set_profiling": (ctypes.c_int, [P, I32]),
         "mlmc_kernel_time": (ctypes.c_int, [P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(D),
@@ -210,12 +216,25 @@ class Context:
                                             qc.ctypes.data, it.ctypes.data))
         return y, qf, qc, it
 
-    def get_estimate(self):
-        out = EstimateOut()
-        self._check(lib().mlmc_get_estimate(self.h, ctypes.byref(out)))
+    @staticmethod
+    def _estimate_dict(out):
         lv = [dict(n=out.level[l].n, mean=out.level[l].mean, m2=out.level[l].m2, var=out.level[l].var,
                    cost=out.level[l].cost) for l in range(out.levels)]
         return dict(qtilde=out.qtilde, var_qtilde=out.var_qtilde, levels=lv)
+
+    def get_estimate(self):
+        out = EstimateOut()
+        self._check(lib().mlmc_get_estimate(self.h, ctypes.byref(out)))
+        return self._estimate_dict(out)
+
+    def estimate(self, eps: float, n_pilot: int = 32, cost_model: int = 0, extra_fraction: float = 0.0,
+                 max_rounds: int = 3):
+        """Pilot + optimal allocation + top-up (mlmc_estimate); returns (N_l, estimate dict)."""
+        opts = EstimateOpts(eps, n_pilot, cost_model, extra_fraction, max_rounds)
+        nl = np.zeros(self.cfg.levels, dtype=np.uint64)
+        out = EstimateOut()
+        self._check(lib().mlmc_estimate(self.h, ctypes.byref(opts), nl.ctypes.data, ctypes.byref(out)))
+        return nl, self._estimate_dict(out)
 
     def reset_stats(self):
         self._check(lib().mlmc_reset_stats(self.h))

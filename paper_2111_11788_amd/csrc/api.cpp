@@ -12,6 +12,7 @@
 #include "mlmc.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -107,6 +108,16 @@ struct SolveWork {
   double* r64 = nullptr;                                    // fp64 refinement residual
   float *d = nullptr, *rin = nullptr, *p32 = nullptr, *q32 = nullptr;  // fp32 inner PCG
   StateBufs outer, inner;
+  // captured PCG iteration per precision (0: fp64, 1: fp32); tied to the buffers above
+  hipGraphExec_t iter_exec[2] = {nullptr, nullptr};
+
+  void release_graphs() {
+    for (auto& g : iter_exec)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  }
 
   void carve(Carver& cv, int n_, int B_, int prec, int solv) {
     n = n_; B = B_; precision = prec; solver = solv;
@@ -170,6 +181,9 @@ struct ProfRec {
 struct Running {
   uint64_t n = 0;
   double mean = 0.0, m2 = 0.0, cost = 0.0;
+  double seconds = 0.0;     // wall time spent sampling this level
+  uint64_t timed = 0;       // samples covered by `seconds`
+  uint64_t next = 0;        // next unused sample index of the level
   void push(double y) {
     n += 1;
     const double d = y - mean;
@@ -205,6 +219,9 @@ struct mlmc_ctx {
   int* h_nactive = nullptr;
   int zvar[2] = {0, 0};           // z-march kernel variant for fp64 / fp32
   int vsmall_n0[2] = {8, 16};     // mesh at which the single-kernel coarse V-cycle takes over (0: off)
+  bool use_graphs = true;         // replay the PCG iteration from a captured hipGraph
+  bool own_stream = false;        // the context created st itself
+  int graph_batch = 2;            // graph launches per convergence check
 };
 
 static std::string g_create_error;
@@ -319,6 +336,7 @@ int ensure_solve_work(mlmc_ctx* ctx, int n, int B) {
     FAIL(MLMC_E_NOMEM, "arena too small for a solve of " + std::to_string(B) + " samples on " +
                            std::to_string(n) + "^3: need " + std::to_string(dry.top) + " bytes");
   }
+  ctx->sw.release_graphs();
   ctx->sw = SolveWork{};
   ctx->sw.carve(cv, n, B, ctx->cfg.precision, ctx->cfg.solver);
   HIPCHK(hipMemsetAsync((char*)ctx->cfg.arena + ctx->persistent_top, 0, cv.top - ctx->persistent_top, ctx->st));
@@ -362,6 +380,8 @@ int ensure_batch_work(mlmc_ctx* ctx, int level, int B) {
   cv.cap = ctx->cfg.arena_bytes;
   cv.top = ctx->persistent_top;
   cv.dry = false;
+  ctx->bw.wf.release_graphs();
+  ctx->bw.wc.release_graphs();
   ctx->bw = BatchWork{};
   carve_batch(cv, ctx->bw, ctx->cfg, level, B);
   HIPCHK(hipMemsetAsync((char*)ctx->cfg.arena + ctx->persistent_top, 0, cv.top - ctx->persistent_top, ctx->st));
@@ -475,13 +495,40 @@ int count_active(mlmc_ctx* ctx, SolveState& s, int B, int* out) {
 
 // PCG on the current iterate x with residual r (both already set, S.active
 // and S.bb set).  Stops per sample at ||r|| <= tol ||b|| (recurrence).
+// One PCG iteration after the initial preconditioning: q = A p, alpha, x and r
+// updates with the convergence test, z = M^-1 r, beta, p = z + beta p, and
+// the count of samples still active copied to pinned host memory.
 template <class T>
-int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q, double tol,
-        int max_iter, int* done_iters) {
+int pcg_iteration(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q,
+                  double tol2) {
   const int n = L[0].n;
   const double sz = sizeof(T), d = dofs(n) * B, e = elems(n) * B;
   hipStream_t st = ctx->st;
   const int var = zv<T>(ctx);
+  uint32_t np = 0;
+  T* z = nullptr;
+  LAUNCH(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, &np, st, var));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA, 0.0, np, S, nullptr, st));
+  LAUNCH(kid<T>(MLMC_K_PCG_UPDATE), 6 * d * sz, launch_pcg_update<T>(n, B, x, p, r, q, S, &np, st));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, tol2, np, S, nullptr, st));
+  if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
+  if (!np) LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BETA, 0.0, np, S, nullptr, st));
+  LAUNCH(kid<T>(MLMC_K_PCG_DIRECTION), 3 * d * sz, launch_pcg_direction<T>(n, B, z, p, S, st));
+  LAUNCH(MLMC_K_MISC, 0, launch_count_active(B, S, st));
+  HIPCHK(hipMemcpyAsync(ctx->h_nactive, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+  return MLMC_OK;
+}
+
+// PCG on the current iterate x with residual r (both already set, S.active
+// and S.bb set).  Stops per sample at ||r|| <= tol ||b|| (recurrence).
+// `graph` caches the captured iteration for this work space (may be null).
+template <class T>
+int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q, double tol,
+        int max_iter, int* done_iters, hipGraphExec_t* graph) {
+  const int n = L[0].n;
+  const double sz = sizeof(T), d = dofs(n) * B;
+  hipStream_t st = ctx->st;
   uint32_t np = 0;
   T* z = nullptr;
   if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
@@ -489,28 +536,39 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RZ_INIT, 0.0, np, S, nullptr, st));
   LAUNCH(kid<T>(MLMC_K_PCG_DIRECTION), 2 * d * sz, launch_copy<T>(n, B, z, p, S, st));
   const double tol2 = tol * tol;
-  int it = 0;
-  for (it = 1; it <= max_iter; ++it) {
-    LAUNCH(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, &np, st, var));
-    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA, 0.0, np, S, nullptr, st));
-    LAUNCH(kid<T>(MLMC_K_PCG_UPDATE), 6 * d * sz, launch_pcg_update<T>(n, B, x, p, r, q, S, &np, st));
-    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, tol2, np, S, nullptr, st));
-    if (it >= 2) {
-      int na = 0;
-      if (int rc = count_active(ctx, S, B, &na)) return rc;
-      if (na == 0) break;
+  const bool use_graph = graph && ctx->use_graphs && !ctx->profiling;
+  if (use_graph && !*graph) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int rc = pcg_iteration<T>(ctx, L, B, S, x, r, p, q, tol2);
+    const hipError_t ec = hipStreamEndCapture(st, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
     }
-    if (it == max_iter) break;
-    if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
-    if (!np) LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
-    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BETA, 0.0, np, S, nullptr, st));
-    LAUNCH(kid<T>(MLMC_K_PCG_DIRECTION), 3 * d * sz, launch_pcg_direction<T>(n, B, z, p, S, st));
+    HIPCHK(ec);
+    const hipError_t ei = hipGraphInstantiate(graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIPCHK(ei);
   }
-  *done_iters = std::min(it, max_iter);
+  int it = 0;
+  while (it < max_iter) {
+    const int k = use_graph ? std::min(ctx->graph_batch, max_iter - it) : 1;
+    for (int j = 0; j < k; ++j) {
+      if (use_graph) {
+        HIPCHK(hipGraphLaunch(*graph, st));
+      } else if (int rc = pcg_iteration<T>(ctx, L, B, S, x, r, p, q, tol2)) {
+        return rc;
+      }
+    }
+    it += k;
+    HIPCHK(hipStreamSynchronize(st));
+    if (*ctx->h_nactive == 0) break;
+  }
+  *done_iters = it;
   return MLMC_OK;
 }
 
-// Solve A(kap) u = h^3 for B samples on the n^3 mesh into u (grid layout).
 // kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
 int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
                bool kap32_ready = false) {
@@ -537,7 +595,9 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
     LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
     for (int round = 0; round < 4 && total_it < ctx->cfg.max_iter; ++round) {
       int it = 0;
-      if (int rc = pcg<double>(ctx, L, B, O, u, w.r, w.p, w.q, rtol, ctx->cfg.max_iter - total_it, &it)) return rc;
+      if (int rc = pcg<double>(ctx, L, B, O, u, w.r, w.p, w.q, rtol, ctx->cfg.max_iter - total_it, &it,
+                              &w.iter_exec[0]))
+        return rc;
       total_it += it;
       // confirm with the true residual; samples above tolerance continue
       LAUNCH(MLMC_K_MISC, 0, launch_set_active(B, O, 1, st));
@@ -567,7 +627,8 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       LAUNCH(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, (launch_dot<float>(n, B, w.rin, w.rin, I, &np, st)));
       LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, I, nullptr, st));
       int it = 0;
-      if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it, &it))
+      if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it, &it,
+                             &w.iter_exec[1]))
         return rc;
       total_it += it;
       LAUNCH(MLMC_K_MISC, d * 20, launch_add_correction(n, B, u, w.d, O, st));
@@ -621,16 +682,29 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   ctx->cfg = *cfg;
   if (ctx->cfg.cheb_degree == 0) ctx->cfg.cheb_degree = 2;
   ctx->st = (hipStream_t)cfg->stream;
+  if (!ctx->st) {
+    // graphs cannot be captured on the legacy null stream: use a blocking stream
+    // of default priority (ordered with the null stream both ways)
+    if (hipStreamCreate(&ctx->st) != hipSuccess) {
+      g_create_error = "cannot create a stream";
+      delete ctx;
+      return MLMC_E_DEVICE;
+    }
+    ctx->own_stream = true;
+  }
   ctx->modes = kl_select(cfg->corr_len, cfg->sigma2, cfg->n_modes);
   ctx->K1 = (int)ctx->modes.omega.size();
   ctx->cheb = cheb_coeffs(ctx->cfg.cheb_degree, kChebHi / kChebRatio, kChebHi);
   if (const char* zvs = std::getenv("MLMC_ZVAR")) ctx->zvar[0] = ctx->zvar[1] = std::atoi(zvs);
+  if (const char* gs = std::getenv("MLMC_GRAPHS"))
+    if (std::atoi(gs) == 0) ctx->use_graphs = false;
   if (const char* vs = std::getenv("MLMC_VSMALL"))
     if (std::atoi(vs) == 0) ctx->vsmall_n0[0] = ctx->vsmall_n0[1] = 0;
   ctx->stats.assign(cfg->levels, Running{});
   const size_t need = persistent_bytes(cfg, ctx->K1);
   if (need > cfg->arena_bytes) {
     g_create_error = "arena smaller than the " + std::to_string(need) + " bytes of KL tables";
+    if (ctx->own_stream) hipStreamDestroy(ctx->st);
     delete ctx;
     return MLMC_E_NOMEM;
   }
@@ -659,6 +733,7 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   if (e != hipSuccess) {
     g_create_error = std::string("HIP error during create: ") + hipGetErrorString(e);
     if (ctx->h_nactive) hipHostFree(ctx->h_nactive);
+    if (ctx->own_stream) hipStreamDestroy(ctx->st);
     delete ctx;
     return MLMC_E_DEVICE;
   }
@@ -675,7 +750,11 @@ void mlmc_destroy(mlmc_ctx* ctx) {
     hipEventDestroy(r.b);
   }
   for (auto e : ctx->event_pool) hipEventDestroy(e);
+  ctx->sw.release_graphs();
+  ctx->bw.wf.release_graphs();
+  ctx->bw.wc.release_graphs();
   if (ctx->h_nactive) hipHostFree(ctx->h_nactive);
+  if (ctx->own_stream) hipStreamDestroy(ctx->st);
   delete ctx;
 }
 
@@ -778,7 +857,7 @@ int mlmc_sample_level(mlmc_ctx* ctx, int32_t level, uint64_t first, uint64_t cou
   if (ctx->cfg.qoi == 1 && ((nf % 4) || (level > 0 && (nf / 2) % 4)))
     FAIL(MLMC_E_INVALID, "subcube QoI needs 4 | n on both meshes");
   bool all_conv = true, finite = true;
-  std::vector<double> hqf, hqc;
+  const auto t_start = std::chrono::steady_clock::now();
   for (uint64_t done = 0; done < count;) {
     const int B = (int)std::min<uint64_t>(count - done, (uint64_t)ctx->cfg.max_batch);
     if (int rc = ensure_batch_work(ctx, level, B)) return rc;
@@ -812,6 +891,12 @@ int mlmc_sample_level(mlmc_ctx* ctx, int32_t level, uint64_t first, uint64_t cou
     ctx->stats[level].cost = cost;
     done += (uint64_t)B;
   }
+  if (count) {
+    Running& r = ctx->stats[level];
+    r.seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    r.timed += count;
+    r.next = std::max(r.next, first + count);
+  }
   if (!finite) FAIL(MLMC_E_NONFINITE, "non-finite QoI");
   if (!all_conv) FAIL(MLMC_E_NOCONV, "some samples did not reach rtol within max_iter");
   return MLMC_OK;
@@ -832,6 +917,68 @@ int mlmc_get_estimate(const mlmc_ctx* ctx, mlmc_estimate_out* out) {
     out->qtilde += r.mean;
     if (r.n) out->var_qtilde += o.var / (double)r.n;
   }
+  return MLMC_OK;
+}
+
+int mlmc_estimate(mlmc_ctx* ctx, const mlmc_estimate_opts* o, uint64_t* n_per_level, mlmc_estimate_out* out) {
+  if (!ctx) return MLMC_E_INVALID;
+  if (!o || !(o->eps > 0.0) || o->n_pilot < 2 || o->cost_model < 0 || o->cost_model > 1 || !(o->extra_fraction >= 0.0) ||
+      o->max_rounds < 1)
+    FAIL(MLMC_E_INVALID, "bad estimate options");
+  const int L = ctx->cfg.levels;
+  auto cost_of = [&](int l) {
+    const Running& r = ctx->stats[l];
+    if (o->cost_model == 1 || r.timed == 0) {
+      const int nf = ctx->cfg.n0 << l;
+      return dofs(nf) + (l > 0 ? dofs(nf / 2) : 0.0);
+    }
+    return r.seconds / (double)r.timed;
+  };
+  std::vector<uint64_t> target(L, 0);
+  // pilot
+  for (int l = 0; l < L; ++l) {
+    const uint64_t have = ctx->stats[l].n;
+    target[l] = std::max<uint64_t>(have, (uint64_t)o->n_pilot);
+  }
+  for (int round = 0; round <= o->max_rounds; ++round) {
+    bool more = false;
+    for (int l = 0; l < L; ++l) {
+      const uint64_t have = ctx->stats[l].n;
+      if (target[l] > have) {
+        more = true;
+        const uint64_t need = target[l] - have;
+        std::vector<double> y(need), qf(need), qc(need);
+        const int rc = mlmc_sample_level(ctx, l, ctx->stats[l].next, need, y.data(), qf.data(), qc.data(), nullptr);
+        if (rc != MLMC_OK && rc != MLMC_E_NOCONV) return rc;
+      }
+    }
+    if (!more && round > 0) break;
+    if (round == o->max_rounds) break;
+    // eq. mlmc_num_samples on the current estimates
+    double tot = 0.0;
+    std::vector<double> V(L), C(L);
+    for (int l = 0; l < L; ++l) {
+      const Running& r = ctx->stats[l];
+      V[l] = r.n ? r.m2 / (double)r.n : 0.0;
+      C[l] = cost_of(l);
+      tot += std::sqrt(V[l] * C[l]);
+    }
+    bool grow = false;
+    for (int l = 0; l < L; ++l) {
+      const double nl = 2.0 / (o->eps * o->eps) * std::sqrt(V[l] / C[l]) * tot * (1.0 + o->extra_fraction);
+      const uint64_t want = std::max<uint64_t>((uint64_t)std::ceil(nl), (uint64_t)o->n_pilot);
+      if (want > target[l]) {
+        target[l] = want;
+        grow = true;
+      }
+    }
+    if (!grow) break;
+  }
+  for (int l = 0; l < L; ++l) {
+    ctx->stats[l].cost = cost_of(l);
+    if (n_per_level) n_per_level[l] = ctx->stats[l].n;
+  }
+  if (out) return mlmc_get_estimate(ctx, out);
   return MLMC_OK;
 }
 

@@ -163,3 +163,47 @@ def test_batch_composition_does_not_change_results(dev):
     ctx1 = mm.Context(wl, arena_bytes=512 << 20, max_batch=1)
     y1, qf1, qc1, it1 = ctx1.sample_level(1, 3, 1)
     assert qf1[0] == qf[3] and qc1[0] == qc[3] and it1[0] == it[3]
+
+
+def test_estimate_allocation_matches_oracle(dev):
+    # pilot + eq. mlmc_num_samples + top-up, deterministic DOF cost model
+    wl = _wl(n0=4, levels=3, n_modes=8, corr_len=0.5, solver=0, rtol=1e-12, batch=64, precision=0)
+    eps = 6e-4
+    ctx = mm.Context(wl, arena_bytes=256 << 20)
+    nl, est = ctx.estimate(eps, n_pilot=8, cost_model=1, max_rounds=3)
+    n_o, qt_o, vq_o, st_o = omlmc.estimate(wl, eps, 8, max_rounds=3)
+    assert [int(x) for x in nl] == n_o
+    assert abs(est["qtilde"] - qt_o) <= 1e-8 * abs(qt_o)
+    assert est["var_qtilde"] == pytest.approx(vq_o, rel=1e-6)
+    for l in range(3):
+        assert est["levels"][l]["var"] == pytest.approx(st_o[l].var, rel=1e-6)
+    # the allocation brings the statistical error near eps^2 / 2
+    assert est["var_qtilde"] <= 1.5 * eps ** 2 / 2
+
+
+def test_estimate_resumes_sample_indices(dev):
+    # estimating in two calls draws the same samples as one call
+    wl = _wl(n0=4, levels=2, n_modes=8, corr_len=0.5, rtol=1e-12, batch=64)
+    a = mm.Context(wl, arena_bytes=256 << 20)
+    y0, qf0, _, _ = a.sample_level(0, 0, 5)
+    nl, est = a.estimate(1e-3, n_pilot=12, cost_model=1, max_rounds=1)
+    b = mm.Context(wl, arena_bytes=256 << 20)
+    y1, _, _, _ = b.sample_level(0, 0, int(nl[0]))
+    assert np.array_equal(y1[:5], y0)
+    assert est["levels"][0]["mean"] == pytest.approx(y1.mean(), rel=1e-12)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_eager(dev, precision, monkeypatch):
+    # the captured PCG iteration gives the same bits as eager launches, over
+    # several solves in a row (graph replays with eager work in between)
+    wl = _wl(n0=16, levels=2, n_modes=32, corr_len=0.3, rtol=1e-10, precision=precision, batch=5)
+    monkeypatch.setenv("MLMC_GRAPHS", "1")
+    g = mm.Context(wl, arena_bytes=512 << 20)
+    got = [g.sample_level(1, 5 * k, 5) for k in range(3)]
+    monkeypatch.setenv("MLMC_GRAPHS", "0")
+    e = mm.Context(wl, arena_bytes=512 << 20)
+    want = [e.sample_level(1, 5 * k, 5) for k in range(3)]
+    for a, b in zip(got, want):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
