@@ -205,12 +205,90 @@ typedef struct mlmc_estimate_opts {
 int mlmc_estimate(mlmc_ctx* ctx, const mlmc_estimate_opts* opts, uint64_t* n_per_level,
                   mlmc_estimate_out* out);
 
+/* ------------------------------------------------------------- tuning */
+
+/* Execution choices that change speed, not the discrete solution each solve
+ * converges to (iteration counts and last bits may change). */
+typedef struct mlmc_tuning {
+  int32_t zvar_fp32;      /* stencil kernel variant bits for fp32 (1: prefetch next plane) */
+  int32_t zvar_fp64;      /* same for fp64 */
+  int32_t vsmall_fp32;    /* mesh from which the coarse V-cycle runs as one LDS kernel (0: off) */
+  int32_t vsmall_fp64;    /* same for fp64 (at most 8) */
+  int32_t cheb_degree;    /* Chebyshev smoothing degree per half V-cycle, 1..8 */
+  int32_t max_batch;      /* samples per batched solve */
+  int32_t graph_batch;    /* captured PCG iterations replayed per convergence check (0: no graphs) */
+  double seconds;         /* mlmc_autotune: measured seconds per sample of the chosen setting */
+} mlmc_tuning;
+
+int mlmc_get_tuning(const mlmc_ctx* ctx, mlmc_tuning* out);
+/* Errors: MLMC_E_INVALID for a value out of range. */
+int mlmc_set_tuning(mlmc_ctx* ctx, const mlmc_tuning* t);
+
+/* Autotuner: time whole batched solves of `batch` samples of `level` (draw,
+ * field, solve, QoI; statistics are not touched) while changing one choice
+ * at a time (coordinate descent over Chebyshev degree, stencil variant,
+ * coarse-kernel threshold, graph batching and batch size), keep the setting
+ * with the least time per sample, apply it to the context and return it in
+ * *best (may be NULL).  The arena must hold a batch of `batch` samples. */
+int mlmc_autotune(mlmc_ctx* ctx, int32_t level, int32_t batch, mlmc_tuning* best);
+
 /* Running statistics of every level and the estimator of eq. mlmc_average
  * with the statistical error sum_l V(Y_l)/N_l (Sec. 2.2). */
 int mlmc_get_estimate(const mlmc_ctx* ctx, mlmc_estimate_out* out);
 
 /* Clear the running statistics of every level. */
 int mlmc_reset_stats(mlmc_ctx* ctx);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct mlmc_sample_result {
+  int32_t status;       /* MLMC_OK, MLMC_E_NOCONV or MLMC_E_NONFINITE */
+  int32_t level;
+  uint64_t sample;
+  double y;             /* Q_l - Q_{l-1} (Q_0 at level 0) */
+  double q_fine, q_coarse;
+  int32_t iters;        /* fp32 inner PCG iterations of the fine solve */
+  double latency_s;     /* completion - submission, host monotonic clock */
+  double queue_s;       /* admission into a slot - submission */
+} mlmc_sample_result;
+
+typedef struct mlmc_serve_stats_out {
+  uint64_t completed;   /* requests finished since the server started */
+  double sample_dofs;   /* interior unknowns of the finished solves */
+  double busy_seconds;  /* last completion - first submission */
+  int32_t queued;       /* solves waiting for a slot */
+  int32_t running;      /* solves in slots */
+  int32_t slots[16];    /* pool capacity per mesh n0 << m */
+  int32_t occupied[16];
+} mlmc_serve_stats_out;
+
+/* Start serving: the arena after the KL tables is split into one resident
+ * pool per mesh n0 << m with slots_per_mesh[m] slots (NULL: an equal share of
+ * the budget per mesh, at most 4096 slots each).  Every slot holds one solve's
+ * kappa, fp32 multigrid hierarchy and solver vectors until it finishes.  A
+ * host thread and a stream per pool advance all occupied slots one solver
+ * step at a time and admit queued solves into free slots between steps
+ * (continuous batching).  The solver is the mixed-precision GMG-PCG.  While
+ * serving, the batch entry points (sample_level, solve, vcycle, qoi,
+ * estimate, autotune) return MLMC_E_INVALID.  Errors: MLMC_E_NOMEM when the
+ * arena cannot hold the requested pools. */
+int mlmc_serve_start(mlmc_ctx* ctx, const int32_t* slots_per_mesh);
+
+/* Stop serving; requests not finished are dropped.  Idempotent. */
+int mlmc_serve_stop(mlmc_ctx* ctx);
+
+/* Queue one MLMC sample (the paper's unit of work, a DoSample duty of Sec.
+ * 4.2, for one sample index): the n_l solve and, for level > 0, the n_{l-1}
+ * solve on the same xi (Sec. 2.2).  *ticket identifies it for mlmc_poll.
+ * Thread-safe.  Errors: MLMC_E_BUDGET if a needed mesh has no slots. */
+int mlmc_submit(mlmc_ctx* ctx, int32_t level, uint64_t sample_id, uint64_t* ticket);
+
+/* MLMC_PENDING while the request runs; MLMC_OK with *out filled (the ticket
+ * is then consumed); MLMC_E_INVALID for an unknown ticket.  Thread-safe. */
+int mlmc_poll(mlmc_ctx* ctx, uint64_t ticket, mlmc_sample_result* out);
+
+/* Counters of the running server.  Thread-safe. */
+int mlmc_serve_stats(mlmc_ctx* ctx, mlmc_serve_stats_out* out);
 
 /* ----------------------------------------------------------- diagnostics */
 

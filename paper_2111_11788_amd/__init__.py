@@ -28,7 +28,8 @@ KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
            "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_vcycle", "mlmc_solve", "mlmc_qoi",
            "mlmc_sample_level", "mlmc_estimate", "mlmc_get_estimate", "mlmc_reset_stats",
-           "mlmc_set_profiling", "mlmc_kernel_time"]
+           "mlmc_set_profiling", "mlmc_kernel_time", "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
+           "mlmc_serve_start", "mlmc_serve_stop", "mlmc_submit", "mlmc_poll", "mlmc_serve_stats"]
 
 
 class MLMCError(RuntimeError):
@@ -49,6 +50,30 @@ class Config(ctypes.Structure):
 class LevelStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("mean", ctypes.c_double), ("m2", ctypes.c_double),
                 ("var", ctypes.c_double), ("cost", ctypes.c_double)]
+
+
+class SampleResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("level", ctypes.c_int32), ("sample", ctypes.c_uint64),
+                ("y", ctypes.c_double), ("q_fine", ctypes.c_double), ("q_coarse", ctypes.c_double),
+                ("iters", ctypes.c_int32), ("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("sample_dofs", ctypes.c_double), ("busy_seconds", ctypes.c_double),
+                ("queued", ctypes.c_int32), ("running", ctypes.c_int32), ("slots", ctypes.c_int32 * 16),
+                ("occupied", ctypes.c_int32 * 16)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("zvar_fp32", ctypes.c_int32), ("zvar_fp64", ctypes.c_int32), ("vsmall_fp32", ctypes.c_int32),
+                ("vsmall_fp64", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("graph_batch", ctypes.c_int32), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class EstimateOpts(ctypes.Structure):
@@ -91,6 +116,14 @@ def lib():
         "mlmc_estimate": (ctypes.c_int, [P, ctypes.POINTER(EstimateOpts), P, ctypes.POINTER(EstimateOut)]),
         "mlmc_reset_stats": (ctypes.c_int, [P]),
         "mlmc_set_profiling": (ctypes.c_int, [P, I32]),
+        "mlmc_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
+        "mlmc_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
+        "mlmc_autotune": (ctypes.c_int, [P, I32, I32, ctypes.POINTER(Tuning)]),
+        "mlmc_serve_start": (ctypes.c_int, [P, P]),
+        "mlmc_serve_stop": (ctypes.c_int, [P]),
+        "mlmc_submit": (ctypes.c_int, [P, I32, U64, ctypes.POINTER(U64)]),
+        "mlmc_poll": (ctypes.c_int, [P, U64, ctypes.POINTER(SampleResult)]),
+        "mlmc_serve_stats": (ctypes.c_int, [P, ctypes.POINTER(ServeStats)]),
         "mlmc_kernel_time": (ctypes.c_int, [P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(D),
                                             ctypes.POINTER(D)]),
     }
@@ -238,6 +271,74 @@ class Context:
 
     def reset_stats(self):
         self._check(lib().mlmc_reset_stats(self.h))
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        self._check(lib().mlmc_get_tuning(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        self._check(lib().mlmc_get_tuning(self.h, ctypes.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, v)
+        self._check(lib().mlmc_set_tuning(self.h, ctypes.byref(t)))
+
+    def autotune(self, level: int, batch: int) -> dict:
+        t = Tuning()
+        self._check(lib().mlmc_autotune(self.h, level, batch, ctypes.byref(t)))
+        return t.as_dict()
+
+    # --- serving (continuous batching) ----------------------------------------
+    def serve_start(self, slots_per_mesh=None):
+        arr = None
+        if slots_per_mesh is not None:
+            arr = np.ascontiguousarray(slots_per_mesh, dtype=np.int32)
+        self._check(lib().mlmc_serve_start(self.h, None if arr is None else arr.ctypes.data))
+        self._slots = arr
+
+    def serve_stop(self):
+        self._check(lib().mlmc_serve_stop(self.h))
+
+    def submit(self, level: int, sample: int) -> int:
+        t = ctypes.c_uint64()
+        self._check(lib().mlmc_submit(self.h, level, sample, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else the result dict."""
+        r = SampleResult()
+        rc = lib().mlmc_poll(self.h, ticket, ctypes.byref(r))
+        if rc == MLMC_PENDING:
+            return None
+        self._check(rc)
+        return r.as_dict()
+
+    def serve_stats(self) -> dict:
+        s = ServeStats()
+        self._check(lib().mlmc_serve_stats(self.h, ctypes.byref(s)))
+        return dict(completed=s.completed, sample_dofs=s.sample_dofs, busy_seconds=s.busy_seconds,
+                    queued=s.queued, running=s.running, slots=list(s.slots), occupied=list(s.occupied))
+
+    def wait(self, tickets, timeout: float = 120.0, sleep: float = 2e-4):
+        """Poll until every ticket is done; returns {ticket: result}."""
+        import time
+        out, todo = {}, list(tickets)
+        t0 = time.monotonic()
+        while todo:
+            rest = []
+            for t in todo:
+                r = self.poll(t)
+                if r is None:
+                    rest.append(t)
+                else:
+                    out[t] = r
+            todo = rest
+            if todo:
+                if time.monotonic() - t0 > timeout:
+                    raise TimeoutError(f"{len(todo)} requests still pending")
+                time.sleep(sleep)
+        return out
 
     def set_profiling(self, on: bool):
         self._check(lib().mlmc_set_profiling(self.h, 1 if on else 0))

@@ -1,0 +1,512 @@
+// Engine of the MLMC library (see engine.hpp).
+//
+// Whole path of one batch (Sec. 2.2: a level-l sample evaluates the n_l and
+// n_{l-1} meshes on one draw and contributes Y_l = Q_l - Q_{l-1}):
+//   xi (Philox) -> kappa on each mesh (MFMA KLE) -> GMG-PCG solve per mesh ->
+//   QoI -> Y -> running statistics of the level.
+// Solver: conjugate gradients preconditioned by one V-cycle (Chebyshev-Jacobi
+// smoothing, rediscretised coarse operators down to the 2^3 mesh).  Mixed
+// precision runs that PCG in fp32 vectors (fp64 scalars) as the inner solver
+// of an fp64 iterative refinement whose residual b - A x is formed in fp64.
+#include "engine.hpp"
+
+namespace mlmc {
+namespace eng {
+
+hipEvent_t take_event(mlmc_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  hipEventCreate(&e);
+  return e;
+}
+
+// Launch wrapper: optional event timing and algorithmic-byte accounting.
+
+int validate(const mlmc_config* c, std::string& why) {
+  if (!c) { why = "config is NULL"; return MLMC_E_INVALID; }
+  if (c->n0 < 2 || !is_pow2(c->n0)) { why = "n0 must be a power of two >= 2"; return MLMC_E_INVALID; }
+  if (c->levels < 1 || c->levels > 16) { why = "levels must be in 1..16"; return MLMC_E_INVALID; }
+  if (((int64_t)c->n0 << (c->levels - 1)) > 1024) { why = "finest mesh above 1024^3"; return MLMC_E_INVALID; }
+  if (!(c->sigma2 >= 0.0) || !(c->corr_len > 0.0)) { why = "need sigma2 >= 0 and corr_len > 0"; return MLMC_E_INVALID; }
+  if (c->n_modes < 1 || c->n_modes > 4096) { why = "n_modes must be in 1..4096"; return MLMC_E_INVALID; }
+  if (c->qoi != 0 && c->qoi != 1) { why = "unknown qoi"; return MLMC_E_INVALID; }
+  // the subcube QoI needs 4 | n on every mesh that is solved
+  if (c->qoi == 1 && c->n0 < 4) { why = "subcube QoI needs n0 >= 4"; return MLMC_E_INVALID; }
+  if (!(c->rtol > 0.0) || c->max_iter < 1) { why = "need rtol > 0 and max_iter >= 1"; return MLMC_E_INVALID; }
+  if (c->precision != 0 && c->precision != 1) { why = "unknown precision"; return MLMC_E_INVALID; }
+  if (c->solver != 0 && c->solver != 1) { why = "unknown solver"; return MLMC_E_INVALID; }
+  if (c->cheb_degree < 0 || c->cheb_degree > 8) { why = "cheb_degree must be in 0..8"; return MLMC_E_INVALID; }
+  if (c->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
+  if (c->arena_bytes && !c->arena) { why = "arena_bytes > 0 with a NULL arena"; return MLMC_E_INVALID; }
+  if (((uintptr_t)c->arena) % 256) { why = "arena must be 256-byte aligned"; return MLMC_E_INVALID; }
+  return MLMC_OK;
+}
+
+size_t persistent_bytes(const mlmc_config* c, int K1) {
+  Carver cv;
+  cv.take<double>(c->n_modes);
+  cv.take<int>(3 * (size_t)c->n_modes);
+  for (int l = 0; l < c->levels; ++l) cv.take<double>((size_t)(c->n0 << l) * K1);
+  return cv.top;
+}
+
+// Carve a solve work space for (n, B) unless the cached one matches.
+int ensure_solve_work(mlmc_ctx* ctx, int n, int B) {
+  const auto key = std::make_tuple(0, n, B, ctx->cfg.precision * 2 + ctx->cfg.solver);
+  if (ctx->ws_kind == 0 && ctx->ws_key == key) return MLMC_OK;
+  Carver cv;
+  cv.base = (char*)ctx->cfg.arena;
+  cv.cap = ctx->cfg.arena_bytes;
+  cv.top = ctx->persistent_top;
+  cv.dry = false;
+  Carver dry = cv;
+  dry.dry = true;
+  SolveWork probe;
+  probe.carve(dry, n, B, ctx->cfg.precision, ctx->cfg.solver);
+  if (dry.top > cv.cap) {
+    ctx->ws_kind = -1;
+    FAIL(MLMC_E_NOMEM, "arena too small for a solve of " + std::to_string(B) + " samples on " +
+                           std::to_string(n) + "^3: need " + std::to_string(dry.top) + " bytes");
+  }
+  ctx->sw.release_graphs();
+  ctx->sw = SolveWork{};
+  ctx->sw.carve(cv, n, B, ctx->cfg.precision, ctx->cfg.solver);
+  HIPCHK(hipMemsetAsync((char*)ctx->cfg.arena + ctx->persistent_top, 0, cv.top - ctx->persistent_top, ctx->st));
+  ctx->ws_kind = 0;
+  ctx->ws_key = key;
+  return MLMC_OK;
+}
+
+void carve_batch(Carver& cv, BatchWork& w, const mlmc_config& c, int level, int B) {
+  const int nf = c.n0 << level;
+  w.level = level;
+  w.B = B;
+  w.xi = cv.take<double>((size_t)B * c.n_modes);
+  w.kf = cv.take<double>((size_t)B * elem_count(nf));
+  w.uf = cv.take<double>((size_t)B * grid_stride(nf));
+  w.qf = cv.take<double>(B);
+  w.qc = cv.take<double>(B);
+  w.wf.carve(cv, nf, B, c.precision, c.solver);
+  if (level > 0) {
+    const int nc = nf / 2;
+    w.kc = cv.take<double>((size_t)B * elem_count(nc));
+    w.uc = cv.take<double>((size_t)B * grid_stride(nc));
+    w.wc.carve(cv, nc, B, c.precision, c.solver);
+  }
+}
+
+int ensure_batch_work(mlmc_ctx* ctx, int level, int B) {
+  const auto key = std::make_tuple(1, level, B, 0);
+  if (ctx->ws_kind == 1 && ctx->ws_key == key) return MLMC_OK;
+  Carver dry;
+  dry.top = ctx->persistent_top;
+  BatchWork probe;
+  carve_batch(dry, probe, ctx->cfg, level, B);
+  if (dry.top > ctx->cfg.arena_bytes) {
+    ctx->ws_kind = -1;
+    FAIL(MLMC_E_NOMEM, "arena too small for a batch of " + std::to_string(B) + " samples at level " +
+                           std::to_string(level) + ": need " + std::to_string(dry.top) + " bytes");
+  }
+  Carver cv;
+  cv.base = (char*)ctx->cfg.arena;
+  cv.cap = ctx->cfg.arena_bytes;
+  cv.top = ctx->persistent_top;
+  cv.dry = false;
+  ctx->bw.wf.release_graphs();
+  ctx->bw.wc.release_graphs();
+  ctx->bw = BatchWork{};
+  carve_batch(cv, ctx->bw, ctx->cfg, level, B);
+  HIPCHK(hipMemsetAsync((char*)ctx->cfg.arena + ctx->persistent_top, 0, cv.top - ctx->persistent_top, ctx->st));
+  ctx->ws_kind = 1;
+  ctx->ws_key = key;
+  return MLMC_OK;
+}
+
+int ensure_tables(mlmc_ctx* ctx, int n, double** tab) {
+  auto it = ctx->d_tab.find(n);
+  if (it == ctx->d_tab.end()) FAIL(MLMC_E_INVALID, "mesh " + std::to_string(n) + " is not a level mesh");
+  *tab = it->second;
+  return MLMC_OK;
+}
+
+int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float* kap32) {
+  double* tab = nullptr;
+  if (int rc = ensure_tables(ctx, n, &tab)) return rc;
+  const int M = ctx->cfg.n_modes;
+  LAUNCH(MLMC_K_FIELD, (double)B * elems(n) * (8.0 + (kap32 ? 4.0 : 0.0)) + (double)B * M * 8.0,
+         launch_field(n, M, B, xi, ctx->d_sqrtlam, ctx->d_triples, tab, ctx->K1, kap, kap32, ctx->st));
+  return MLMC_OK;
+}
+
+// One V-cycle on levels l.. of L; returns the buffer that holds the result.
+// With `dot` the last smoothing step of level l also writes the partial sums
+// of b . result (*dot_np per sample).
+template <class T>
+int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T* x, T* xo, T* t,
+           const int* active, T** result, SolveState* dot, uint32_t* dot_np) {
+  const int n = L[l].n;
+  const double sz = sizeof(T);
+  const double d = dofs(n) * B, e = elems(n) * B;
+  hipStream_t st = ctx->st;
+  const int var = zv<T>(ctx);
+  if (n == 2) {
+    LAUNCH(kid<T>(MLMC_K_COARSEST), B * (8 + 2) * sz, launch_coarsest<T>(B, L[l].kap, b, x, active, st));
+    *result = x;
+    if (dot) FAIL(MLMC_E_INVALID, "fused r.z needs a mesh n >= 4");
+    return MLMC_OK;
+  }
+  const ChebCoeffs& ch = ctx->cheb;
+  const T* kap = L[l].kap;
+  const int small = ctx->vsmall_n0[sizeof(T) == 4 ? 1 : 0];
+  if (small && n <= small && n >= 4) {
+    // the rest of the V-cycle in one kernel (coarse data in LDS)
+    const T* kl[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (size_t q = l; q < L.size() && q - l < 4; ++q) kl[q - l] = L[q].kap;
+    LAUNCH(kid<T>(MLMC_K_COARSEST), (2 * d + e * 8.0 / 7.0) * sz,
+           launch_vsmall<T>(n, B, ch.degree, ch.c1, ch.c2, kl, b, x, active, st));
+    *result = x;
+    return MLMC_OK;
+  }
+  LAUNCH(kid<T>(MLMC_K_CHEB_ZERO), (2 * d + e) * sz,
+         launch_cheb<T>(n, B, kap, b, nullptr, nullptr, x, 0.0, ch.c2[0], true, false, active, st, nullptr, nullptr,
+                        var));
+  T* cur = x;
+  T* oth = xo;
+  for (int s = 1; s < ch.degree; ++s) {
+    const bool use_xo = s > 1;
+    LAUNCH(kid<T>(use_xo ? MLMC_K_CHEB_XO : MLMC_K_CHEB), ((use_xo ? 4 : 3) * d + e) * sz,
+           launch_cheb<T>(n, B, kap, b, cur, oth, oth, ch.c1[s], ch.c2[s], false, use_xo, active, st, nullptr,
+                          nullptr, var));
+    std::swap(cur, oth);
+  }
+  LAUNCH(kid<T>(MLMC_K_RESIDUAL), (3 * d + e) * sz, launch_residual<T>(n, B, kap, b, cur, t, active, st, var));
+  Level<T>& nx = L[l + 1];
+  const double dc = dofs(n / 2) * B;
+  LAUNCH(kid<T>(MLMC_K_RESTRICT), (d + dc) * sz, launch_restrict<T>(n, B, t, nx.b, active, st));
+  T* xc = nullptr;
+  if (int rc = vcycle<T>(ctx, L, l + 1, B, nx.b, nx.x, nx.xo, nx.t, active, &xc)) return rc;
+  LAUNCH(kid<T>(MLMC_K_PROLONG), (2 * d + dc) * sz, launch_prolong_add<T>(n, B, xc, cur, active, st));
+  for (int s = 0; s < ch.degree; ++s) {
+    const bool use_xo = s > 0;
+    const bool last = s == ch.degree - 1;
+    LAUNCH(kid<T>(use_xo ? MLMC_K_CHEB_XO : MLMC_K_CHEB), ((use_xo ? 4 : 3) * d + e) * sz,
+           launch_cheb<T>(n, B, kap, b, cur, oth, oth, s == 0 ? 0.0 : ch.c1[s], ch.c2[s], false, use_xo, active, st,
+                          last ? dot : nullptr, last ? dot_np : nullptr, var));
+    std::swap(cur, oth);
+  }
+  *result = cur;
+  return MLMC_OK;
+}
+
+// z = M^-1 r.  When *fused_np is set on return, the partial sums of r . z
+// are already in S.partial (GMG path); otherwise the caller computes them.
+template <class T>
+int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T** z, SolveState& S,
+                 uint32_t* fused_np) {
+  const int n = L[0].n;
+  *fused_np = 0;
+  if (L.size() == 1 || n == 2) {
+    if (n == 2) return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, S.active, z);
+    // Jacobi: z = D^-1 r
+    LAUNCH(kid<T>(MLMC_K_CHEB_ZERO), (2 * dofs(n) + elems(n)) * B * sizeof(T),
+           launch_cheb<T>(n, B, L[0].kap, r, nullptr, nullptr, L[0].x, 0.0, 1.0, true, false, S.active, ctx->st,
+                          nullptr, nullptr, zv<T>(ctx)));
+    *z = L[0].x;
+    return MLMC_OK;
+  }
+  return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, S.active, z, &S, fused_np);
+}
+
+int count_active(mlmc_ctx* ctx, SolveState& s, int B, int* out) {
+  LAUNCH(MLMC_K_MISC, 0, launch_count_active(B, s, ctx->st));
+  HIPCHK(hipMemcpyAsync(ctx->h_nactive, s.nactive, sizeof(int), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  *out = *ctx->h_nactive;
+  return MLMC_OK;
+}
+
+// PCG on the current iterate x with residual r (both already set, S.active
+// and S.bb set).  Stops per sample at ||r|| <= tol ||b|| (recurrence).
+// One PCG iteration after the initial preconditioning: q = A p, alpha, x and r
+// updates with the convergence test, z = M^-1 r, beta, p = z + beta p, and
+// the count of samples still active copied to pinned host memory.
+template <class T>
+int pcg_iteration(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q,
+                  double tol2, int rr_op, bool count) {
+  const int n = L[0].n;
+  const double sz = sizeof(T), d = dofs(n) * B, e = elems(n) * B;
+  hipStream_t st = ctx->st;
+  const int var = zv<T>(ctx);
+  uint32_t np = 0;
+  T* z = nullptr;
+  LAUNCH(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, &np, st, var));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA, 0.0, np, S, nullptr, st));
+  LAUNCH(kid<T>(MLMC_K_PCG_UPDATE), 6 * d * sz, launch_pcg_update<T>(n, B, x, p, r, q, S, &np, st));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, rr_op, tol2, np, S, nullptr, st));
+  if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
+  if (!np) LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BETA, 0.0, np, S, nullptr, st));
+  LAUNCH(kid<T>(MLMC_K_PCG_DIRECTION), 3 * d * sz, launch_pcg_direction<T>(n, B, z, p, S, st));
+  if (count) {
+    LAUNCH(MLMC_K_MISC, 0, launch_count_active(B, S, st));
+    HIPCHK(hipMemcpyAsync(ctx->h_nactive, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  return MLMC_OK;
+}
+
+// PCG on the current iterate x with residual r (both already set, S.active
+// and S.bb set).  Stops per sample at ||r|| <= tol ||b|| (recurrence).
+// `graph` caches the captured iteration for this work space (may be null).
+template <class T>
+int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q, double tol,
+        int max_iter, int* done_iters, hipGraphExec_t* graph) {
+  const int n = L[0].n;
+  const double sz = sizeof(T), d = dofs(n) * B;
+  hipStream_t st = ctx->st;
+  uint32_t np = 0;
+  T* z = nullptr;
+  if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
+  if (!np) LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RZ_INIT, 0.0, np, S, nullptr, st));
+  LAUNCH(kid<T>(MLMC_K_PCG_DIRECTION), 2 * d * sz, launch_copy<T>(n, B, z, p, S, st));
+  const double tol2 = tol * tol;
+  const bool use_graph = graph && ctx->use_graphs && !ctx->profiling;
+  if (use_graph && !*graph) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int rc = pcg_iteration<T>(ctx, L, B, S, x, r, p, q, tol2);
+    const hipError_t ec = hipStreamEndCapture(st, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    HIPCHK(ec);
+    const hipError_t ei = hipGraphInstantiate(graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIPCHK(ei);
+  }
+  int it = 0;
+  while (it < max_iter) {
+    const int k = use_graph ? std::min(ctx->graph_batch, max_iter - it) : 1;
+    for (int j = 0; j < k; ++j) {
+      if (use_graph) {
+        HIPCHK(hipGraphLaunch(*graph, st));
+      } else if (int rc = pcg_iteration<T>(ctx, L, B, S, x, r, p, q, tol2)) {
+        return rc;
+      }
+    }
+    it += k;
+    HIPCHK(hipStreamSynchronize(st));
+    if (*ctx->h_nactive == 0) break;
+  }
+  *done_iters = it;
+  return MLMC_OK;
+}
+
+// kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
+int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
+               bool kap32_ready) {
+  const int n = w.n, B = w.B;
+  hipStream_t st = ctx->st;
+  const double h = 1.0 / n, h3 = h * h * h;
+  const double rtol = ctx->cfg.rtol;
+  const size_t S0 = grid_stride(n);
+  const double d = dofs(n) * B, e = elems(n) * B;
+  SolveState& O = w.outer.s;
+  uint32_t np = 0;
+  LAUNCH(MLMC_K_MISC, 0, launch_set_active(B, O, 1, st));
+  HIPCHK(hipMemsetAsync(O.iters, 0, B * sizeof(int), st));
+  int total_it = 0;
+  if (w.precision == MLMC_PREC_FP64) {
+    auto& L = w.L64;
+    L[0].kap = const_cast<double*>(kap);
+    for (size_t l = 1; l < L.size(); ++l)
+      LAUNCH(MLMC_K_COARSEN, (elems(L[l - 1].n) + elems(L[l].n)) * B * 8,
+             launch_coarsen<double>(L[l - 1].n, B, L[l - 1].kap, L[l].kap, st));
+    LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, u, 0.0, nullptr, st));
+    LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, w.r, h3, nullptr, st));
+    LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double>(n, B, w.r, w.r, O, &np, st)));
+    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
+    for (int round = 0; round < 4 && total_it < ctx->cfg.max_iter; ++round) {
+      int it = 0;
+      if (int rc = pcg<double>(ctx, L, B, O, u, w.r, w.p, w.q, rtol, ctx->cfg.max_iter - total_it, &it,
+                              &w.iter_exec[0]))
+        return rc;
+      total_it += it;
+      // confirm with the true residual; samples above tolerance continue
+      LAUNCH(MLMC_K_MISC, 0, launch_set_active(B, O, 1, st));
+      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r, O, &np, st, zv<double>(ctx)));
+      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
+      int na = 0;
+      if (int rc = count_active(ctx, O, B, &na)) return rc;
+      if (na == 0) break;
+    }
+  } else {
+    auto& L = w.L32;
+    SolveState& I = w.inner.s;
+    if (!kap32_ready)
+      LAUNCH(MLMC_K_MISC, e * 12, (launch_convert<double, float>((size_t)B * elem_count(n), kap, L[0].kap, st)));
+    for (size_t l = 1; l < L.size(); ++l)
+      LAUNCH(kid<float>(MLMC_K_COARSEN), (elems(L[l - 1].n) + elems(L[l].n)) * B * 4,
+             launch_coarsen<float>(L[l - 1].n, B, L[l - 1].kap, L[l].kap, st));
+    LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, u, 0.0, nullptr, st));
+    LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, w.r64, h3, nullptr, st));
+    LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double>(n, B, w.r64, w.r64, O, &np, st)));
+    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
+    HIPCHK(hipMemsetAsync(I.iters, 0, B * sizeof(int), st));
+    for (int outer = 0; outer < kMaxOuter && total_it < ctx->cfg.max_iter; ++outer) {
+      LAUNCH(MLMC_K_MISC, d * 12, launch_demote(n, B, w.r64, w.rin, O, st));
+      HIPCHK(hipMemcpyAsync(I.active, O.active, B * sizeof(int), hipMemcpyDeviceToDevice, st));
+      LAUNCH(MLMC_K_MISC, d * 4, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
+      LAUNCH(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, (launch_dot<float>(n, B, w.rin, w.rin, I, &np, st)));
+      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, I, nullptr, st));
+      int it = 0;
+      if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it, &it,
+                             &w.iter_exec[1]))
+        return rc;
+      total_it += it;
+      LAUNCH(MLMC_K_MISC, d * 20, launch_add_correction(n, B, u, w.d, O, st));
+      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r64, O, &np, st, zv<double>(ctx)));
+      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
+      int na = 0;
+      if (int rc = count_active(ctx, O, B, &na)) return rc;
+      if (na == 0) break;
+    }
+    // report inner iterations as the sample's iteration count
+    HIPCHK(hipMemcpyAsync(O.iters, I.iters, B * sizeof(int), hipMemcpyDeviceToDevice, st));
+  }
+  std::vector<int> act(B);
+  HIPCHK(hipMemcpyAsync(act.data(), O.active, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (iters_host) HIPCHK(hipMemcpyAsync(iters_host, O.iters, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bool ok = true;
+  for (int b = 0; b < B; ++b) ok = ok && act[b] == 0;
+  *all_conv = ok;
+  return MLMC_OK;
+}
+
+int qoi_impl(mlmc_ctx* ctx, SolveState& S, int n, int B, const double* u, double* q) {
+  uint32_t np = 0;
+  LAUNCH(MLMC_K_QOI, dofs(n) * B * 8, launch_qoi_partial(n, B, ctx->cfg.qoi, u, S, &np, ctx->st));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_STORE, 0.0, np, S, q, ctx->st));
+  return MLMC_OK;
+}
+
+bool mesh_of_config(const mlmc_ctx* ctx, int n) { return ctx->d_tab.count(n) > 0; }
+
+// Draw, field, solve(s) and QoI for samples first..first+count-1 of `level`;
+// outputs to host arrays; statistics folded in when `record`.
+int run_level(mlmc_ctx* ctx, int level, uint64_t first, uint64_t count, double* y, double* q_fine, double* q_coarse,
+              int32_t* iters, bool record) {
+  const int nf = ctx->cfg.n0 << level;
+  bool all_conv = true, finite = true;
+  const auto t_start = std::chrono::steady_clock::now();
+  for (uint64_t done = 0; done < count;) {
+    const int B = (int)std::min<uint64_t>(count - done, (uint64_t)ctx->cfg.max_batch);
+    if (int rc = ensure_batch_work(ctx, level, B)) return rc;
+    BatchWork& w = ctx->bw;
+    const uint64_t start = first + done;
+    LAUNCH(MLMC_K_XI, (double)B * ctx->cfg.n_modes * 8,
+           launch_draw_xi(ctx->cfg.seed, level, start, B, ctx->cfg.n_modes, w.xi, ctx->st));
+    const bool mixed = ctx->cfg.precision == MLMC_PREC_MIXED;
+    if (int rc = field_impl(ctx, nf, B, w.xi, w.kf, mixed ? w.wf.L32[0].kap : nullptr)) return rc;
+    bool conv = false;
+    if (int rc = solve_impl(ctx, w.wf, w.kf, w.uf, iters ? iters + done : nullptr, &conv, mixed)) return rc;
+    all_conv = all_conv && conv;
+    if (int rc = qoi_impl(ctx, w.wf.outer.s, nf, B, w.uf, w.qf)) return rc;
+    if (level > 0) {
+      if (int rc = field_impl(ctx, nf / 2, B, w.xi, w.kc, mixed ? w.wc.L32[0].kap : nullptr)) return rc;
+      if (int rc = solve_impl(ctx, w.wc, w.kc, w.uc, nullptr, &conv, mixed)) return rc;
+      all_conv = all_conv && conv;
+      if (int rc = qoi_impl(ctx, w.wc.outer.s, nf / 2, B, w.uc, w.qc)) return rc;
+    }
+    HIPCHK(hipMemcpyAsync(q_fine + done, w.qf, B * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+    if (level > 0)
+      HIPCHK(hipMemcpyAsync(q_coarse + done, w.qc, B * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    const double cost = dofs(nf) + (level > 0 ? dofs(nf / 2) : 0.0);
+    for (int b = 0; b < B; ++b) {
+      if (level == 0) q_coarse[done + b] = 0.0;
+      y[done + b] = q_fine[done + b] - q_coarse[done + b];
+      finite = finite && std::isfinite(y[done + b]);
+      if (record) ctx->stats[level].push(y[done + b]);
+    }
+    if (record) ctx->stats[level].cost = cost;
+    done += (uint64_t)B;
+  }
+  if (count && record) {
+    Running& r = ctx->stats[level];
+    r.seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    r.timed += count;
+    r.next = std::max(r.next, first + count);
+  }
+  if (!finite) FAIL(MLMC_E_NONFINITE, "non-finite QoI");
+  if (!all_conv) FAIL(MLMC_E_NOCONV, "some samples did not reach rtol within max_iter");
+  return MLMC_OK;
+}
+
+int check_tuning(const mlmc_tuning* t, std::string& why) {
+  if (!t) { why = "NULL tuning"; return MLMC_E_INVALID; }
+  if (t->zvar_fp32 < 0 || t->zvar_fp32 > 1 || t->zvar_fp64 < 0 || t->zvar_fp64 > 1) { why = "zvar must be 0 or 1"; return MLMC_E_INVALID; }
+  auto okv = [](int v, int mx) { return v == 0 || (v >= 4 && v <= mx && (v & (v - 1)) == 0); };
+  if (!okv(t->vsmall_fp32, 16) || !okv(t->vsmall_fp64, 8)) { why = "vsmall must be 0 or 4..16 (fp64 4..8), a power of two"; return MLMC_E_INVALID; }
+  if (t->cheb_degree < 1 || t->cheb_degree > 8) { why = "cheb_degree must be in 1..8"; return MLMC_E_INVALID; }
+  if (t->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
+  if (t->graph_batch < 0 || t->graph_batch > 16) { why = "graph_batch must be in 0..16"; return MLMC_E_INVALID; }
+  return MLMC_OK;
+}
+
+mlmc_tuning current_tuning(const mlmc_ctx* ctx) {
+  mlmc_tuning t{};
+  t.zvar_fp64 = ctx->zvar[0];
+  t.zvar_fp32 = ctx->zvar[1];
+  t.vsmall_fp64 = ctx->vsmall_n0[0];
+  t.vsmall_fp32 = ctx->vsmall_n0[1];
+  t.cheb_degree = ctx->cheb.degree;
+  t.max_batch = ctx->cfg.max_batch;
+  t.graph_batch = ctx->use_graphs ? ctx->graph_batch : 0;
+  t.seconds = 0.0;
+  return t;
+}
+
+void apply_tuning(mlmc_ctx* ctx, const mlmc_tuning& t) {
+  ctx->zvar[0] = t.zvar_fp64;
+  ctx->zvar[1] = t.zvar_fp32;
+  ctx->vsmall_n0[0] = t.vsmall_fp64;
+  ctx->vsmall_n0[1] = t.vsmall_fp32;
+  if (t.cheb_degree != ctx->cheb.degree) {
+    ctx->cfg.cheb_degree = t.cheb_degree;
+    ctx->cheb = cheb_coeffs(t.cheb_degree, kChebHi / kChebRatio, kChebHi);
+  }
+  ctx->cfg.max_batch = t.max_batch;
+  ctx->use_graphs = t.graph_batch > 0;
+  ctx->graph_batch = std::max(1, t.graph_batch);
+  // captured graphs bake in kernel choices: drop them
+  ctx->sw.release_graphs();
+  ctx->bw.wf.release_graphs();
+  ctx->bw.wc.release_graphs();
+}
+
+template int vcycle<float>(mlmc_ctx*, std::vector<Level<float>>&, int, int, const float*, float*, float*, float*,
+                           const int*, float**, SolveState*, uint32_t*);
+template int vcycle<double>(mlmc_ctx*, std::vector<Level<double>>&, int, int, const double*, double*, double*,
+                            double*, const int*, double**, SolveState*, uint32_t*);
+template int precondition<float>(mlmc_ctx*, std::vector<Level<float>>&, int, const float*, float**, SolveState&,
+                                 uint32_t*);
+template int precondition<double>(mlmc_ctx*, std::vector<Level<double>>&, int, const double*, double**, SolveState&,
+                                  uint32_t*);
+template int pcg_iteration<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*,
+                                  float*, double, int, bool);
+template int pcg_iteration<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*,
+                                   double*, double*, double, int, bool);
+template int pcg<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*, float*,
+                        double, int, int*, hipGraphExec_t*);
+template int pcg<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*, double*,
+                         double*, double, int, int*, hipGraphExec_t*);
+
+}  // namespace eng
+}  // namespace mlmc

@@ -1,0 +1,328 @@
+// Internal engine of the MLMC library: context, arena carving, batched
+// GMG-PCG solves (fp64 and fp32-in-fp64 refinement), the whole-path sample
+// runner and the tuning knobs.  Shared by the C-ABI (api.cpp) and the serving
+// loop (serve.cpp); not part of the public interface.
+#pragma once
+
+#include "mlmc.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "common.hpp"
+#include "grid.hpp"
+#include "kernels.hpp"
+#include "kl_host.hpp"
+
+struct mlmc_server;
+
+namespace mlmc {
+namespace eng {
+
+
+constexpr double kChebHi = 2.0;      // Gershgorin bound of D^-1 A for this operator
+constexpr double kChebRatio = 4.0;   // smoothing interval [hi / ratio, hi]
+constexpr double kInnerRtol = 1e-4;  // fp32 inner solve tolerance (mixed precision)
+constexpr int kMaxOuter = 30;
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+inline int ilog2i(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
+inline bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// Bump carver over the caller's arena; a dry run only counts bytes.
+struct Carver {
+  char* base = nullptr;
+  size_t top = 0, cap = 0;
+  bool dry = true;
+  template <class T>
+  T* take(size_t count) {
+    const size_t bytes = align256(count * sizeof(T));
+    T* p = dry ? nullptr : reinterpret_cast<T*>(base + top);
+    top += bytes;
+    return p;
+  }
+};
+
+struct ChebCoeffs {
+  int degree = 2;
+  double c1[16] = {0}, c2[16] = {0};
+};
+
+// Three-term Chebyshev semi-iteration on [lo, hi] (Saad, Iterative Methods, Alg. 12.1)
+inline ChebCoeffs cheb_coeffs(int degree, double lo, double hi) {
+  ChebCoeffs c;
+  c.degree = degree;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  c.c1[0] = 0.0;
+  c.c2[0] = 1.0 / theta;
+  double rho = 1.0 / sigma;
+  for (int s = 1; s < degree; ++s) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    c.c1[s] = rn * rho;
+    c.c2[s] = 2.0 * rn / delta;
+    rho = rn;
+  }
+  return c;
+}
+
+template <class T>
+struct Level {
+  int n = 0;
+  T* kap = nullptr;
+  T *b = nullptr, *x = nullptr, *xo = nullptr, *t = nullptr;
+};
+
+struct StateBufs {
+  SolveState s{};
+  void carve(Carver& cv, int B, int n) {
+    s.pstride = max_parts(n, B);
+    s.rz = cv.take<double>(B);
+    s.alpha = cv.take<double>(B);
+    s.beta = cv.take<double>(B);
+    s.rr = cv.take<double>(B);
+    s.bb = cv.take<double>(B);
+    s.partial = cv.take<double>((size_t)B * s.pstride);
+    s.active = cv.take<int>(B);
+    s.iters = cv.take<int>(B);
+    s.nactive = cv.take<int>(1);
+  }
+};
+
+// Work space of one batched solve on an n^3 mesh.
+struct SolveWork {
+  int n = 0, B = 0, precision = 0, solver = 0;
+  std::vector<Level<double>> L64;   // fp64 hierarchy (level 0 kappa is the caller's)
+  std::vector<Level<float>> L32;    // fp32 hierarchy (mixed precision)
+  double *r = nullptr, *p = nullptr, *q = nullptr;          // fp64 PCG
+  double* r64 = nullptr;                                    // fp64 refinement residual
+  float *d = nullptr, *rin = nullptr, *p32 = nullptr, *q32 = nullptr;  // fp32 inner PCG
+  StateBufs outer, inner;
+  // captured PCG iteration per precision (0: fp64, 1: fp32); tied to the buffers above
+  hipGraphExec_t iter_exec[2] = {nullptr, nullptr};
+
+  void release_graphs() {
+    for (auto& g : iter_exec)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  }
+
+  void carve(Carver& cv, int n_, int B_, int prec, int solv) {
+    n = n_; B = B_; precision = prec; solver = solv;
+    const int nl = solv == MLMC_SOLVER_GMG_PCG ? std::max(1, ilog2i(n)) : 1;
+    const size_t S0 = grid_stride(n);
+    outer.carve(cv, B, n);
+    if (prec == MLMC_PREC_FP64) {
+      r = cv.take<double>(B * S0);
+      p = cv.take<double>(B * S0);
+      q = cv.take<double>(B * S0);
+      L64.assign(nl, Level<double>{});
+      for (int l = 0; l < nl; ++l) {
+        const int nn = n >> l;
+        const size_t S = grid_stride(nn);
+        L64[l].n = nn;
+        if (l > 0) {
+          L64[l].kap = cv.take<double>(B * elem_count(nn));
+          L64[l].b = cv.take<double>(B * S);
+        }
+        L64[l].x = cv.take<double>(B * S);
+        L64[l].xo = cv.take<double>(B * S);
+        if (nl > 1 || l > 0) L64[l].t = cv.take<double>(B * S);
+      }
+    } else {
+      inner.carve(cv, B, n);
+      r64 = cv.take<double>(B * S0);
+      d = cv.take<float>(B * S0);
+      rin = cv.take<float>(B * S0);
+      p32 = cv.take<float>(B * S0);
+      q32 = cv.take<float>(B * S0);
+      L32.assign(nl, Level<float>{});
+      for (int l = 0; l < nl; ++l) {
+        const int nn = n >> l;
+        const size_t S = grid_stride(nn);
+        L32[l].n = nn;
+        L32[l].kap = cv.take<float>(B * elem_count(nn));
+        if (l > 0) L32[l].b = cv.take<float>(B * S);
+        L32[l].x = cv.take<float>(B * S);
+        L32[l].xo = cv.take<float>(B * S);
+        if (nl > 1 || l > 0) L32[l].t = cv.take<float>(B * S);
+      }
+    }
+  }
+};
+
+// Work space of one batch of sample_level: draws, fields, solutions, QoIs.
+struct BatchWork {
+  int level = -1, B = 0;
+  double* xi = nullptr;
+  double *kf = nullptr, *kc = nullptr, *uf = nullptr, *uc = nullptr;
+  double *qf = nullptr, *qc = nullptr;
+  SolveWork wf, wc;
+};
+
+struct ProfRec {
+  int id;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+struct Running {
+  uint64_t n = 0;
+  double mean = 0.0, m2 = 0.0, cost = 0.0;
+  double seconds = 0.0;     // wall time spent sampling this level
+  uint64_t timed = 0;       // samples covered by `seconds`
+  uint64_t next = 0;        // next unused sample index of the level
+  void push(double y) {
+    n += 1;
+    const double d = y - mean;
+    mean += d / (double)n;
+    m2 += d * (y - mean);
+  }
+};
+
+}  // namespace eng
+}  // namespace mlmc
+
+using namespace mlmc;
+using namespace mlmc::eng;
+
+struct mlmc_ctx {
+  mlmc_config cfg{};
+  hipStream_t st = nullptr;
+  std::string err;
+  KLModes modes;
+  int K1 = 0;
+  double* d_sqrtlam = nullptr;
+  int* d_triples = nullptr;
+  std::map<int, double*> d_tab;
+  size_t persistent_top = 0;
+  ChebCoeffs cheb;
+  // cached work space (one at a time)
+  int ws_kind = -1;              // 0: solve work, 1: batch work
+  std::tuple<int, int, int, int> ws_key{-1, -1, -1, -1};
+  SolveWork sw;
+  BatchWork bw;
+  std::vector<Running> stats;
+  bool profiling = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> event_pool;
+  int64_t k_launch[2 * MLMC_K_COUNT] = {0};   // [precision][kernel]
+  double k_ms[2 * MLMC_K_COUNT] = {0}, k_bytes[2 * MLMC_K_COUNT] = {0};
+  int* h_nactive = nullptr;
+  int zvar[2] = {0, 0};           // z-march kernel variant for fp64 / fp32
+  int vsmall_n0[2] = {8, 16};     // mesh at which the single-kernel coarse V-cycle takes over (0: off)
+  bool use_graphs = true;         // replay the PCG iteration from a captured hipGraph
+  bool own_stream = false;        // the context created st itself
+  int graph_batch = 2;            // graph launches per convergence check
+  mlmc_server* server = nullptr;  // serving pools and threads while serving
+};
+
+#define FAIL(code, msg)      \
+  do {                       \
+    ctx->err = (msg);        \
+    return (code);           \
+  } while (0)
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ctx->err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " #expr; \
+      return MLMC_E_DEVICE;                                                          \
+    }                                                                                \
+  } while (0)
+
+namespace mlmc {
+namespace eng {
+
+hipEvent_t take_event(mlmc_ctx* ctx);
+
+template <class F>
+int launch(mlmc_ctx* ctx, int id, double bytes, F&& f) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (ctx->profiling) {
+    a = take_event(ctx);
+    b = take_event(ctx);
+    hipEventRecord(a, ctx->st);
+  }
+  const hipError_t e = f();
+  if (e != hipSuccess) {
+    ctx->err = std::string("kernel launch failed: ") + hipGetErrorString(e);
+    return MLMC_E_DEVICE;
+  }
+  if (ctx->profiling) {
+    hipEventRecord(b, ctx->st);
+    ctx->prof.push_back(ProfRec{id, a, b, bytes});
+  }
+  return MLMC_OK;
+}
+
+}  // namespace eng
+}  // namespace mlmc
+
+#define LAUNCH(id, bytes, call)                          \
+  do {                                                   \
+    int rc_ = launch(ctx, (id), (double)(bytes), [&] { return (call); }); \
+    if (rc_) return rc_;                                 \
+  } while (0)
+
+namespace mlmc {
+namespace eng {
+
+// profiling slot of kernel `id` in the precision of T (fp32 slots follow the fp64 ones)
+template <class T>
+constexpr int kid(int id) { return id + (sizeof(T) == 4 ? MLMC_K_COUNT : 0); }
+template <class T>
+int zv(const mlmc_ctx* ctx) { return ctx->zvar[sizeof(T) == 4 ? 1 : 0]; }
+
+inline double dofs(int n) { return (double)(n - 1) * (n - 1) * (n - 1); }
+inline double elems(int n) { return (double)n * n * n; }
+
+int validate(const mlmc_config* c, std::string& why);
+size_t persistent_bytes(const mlmc_config* c, int K1);
+int ensure_solve_work(mlmc_ctx* ctx, int n, int B);
+void carve_batch(Carver& cv, BatchWork& w, const mlmc_config& c, int level, int B);
+int ensure_batch_work(mlmc_ctx* ctx, int level, int B);
+int ensure_tables(mlmc_ctx* ctx, int n, double** tab);
+int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float* kap32);
+// One V-cycle on levels l.. of L; returns the buffer that holds the result.
+// With `dot` the last smoothing step of level l also writes the partial sums
+// of b . result (*dot_np per sample).
+template <class T>
+int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T* x, T* xo, T* t,
+           const int* active, T** result, SolveState* dot = nullptr, uint32_t* dot_np = nullptr);
+// z = M^-1 r.  When *fused_np is set on return, the partial sums of r . z
+// are already in S.partial (GMG path); otherwise the caller computes them.
+template <class T>
+int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T** z, SolveState& S,
+                 uint32_t* fused_np);
+int count_active(mlmc_ctx* ctx, SolveState& s, int B, int* out);
+template <class T>
+int pcg_iteration(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q,
+                  double tol2, int rr_op = RED_RR, bool count = true);
+template <class T>
+int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q, double tol,
+        int max_iter, int* done_iters, hipGraphExec_t* graph);
+// kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
+int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
+               bool kap32_ready = false);
+int qoi_impl(mlmc_ctx* ctx, SolveState& S, int n, int B, const double* u, double* q);
+bool mesh_of_config(const mlmc_ctx* ctx, int n);
+int run_level(mlmc_ctx* ctx, int level, uint64_t first, uint64_t count, double* y, double* q_fine, double* q_coarse,
+              int32_t* iters, bool record);
+int check_tuning(const mlmc_tuning* t, std::string& why);
+mlmc_tuning current_tuning(const mlmc_ctx* ctx);
+void apply_tuning(mlmc_ctx* ctx, const mlmc_tuning& t);
+
+}  // namespace eng
+}  // namespace mlmc

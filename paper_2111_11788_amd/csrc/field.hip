@@ -12,7 +12,8 @@
 // Operand layout of v_mfma_f64_16x16x4_f64 (64 lanes, checked on gfx950 with a
 // probe of encoded operands): lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator element r of lane l holds D[l / 16 + 4 r][l % 16].
-// Rows = samples, columns = elements, K = modes.
+// Rows = samples, columns = elements, K = modes.  An optional row map sends
+// row r to batch slot rowmap[r] (xi read from and kappa written to that slot).
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -31,7 +32,8 @@ __global__ void __launch_bounds__(256) k_field(int n, int M, int64_t count,
                                                const double* __restrict__ sqrtlam,
                                                const int* __restrict__ triples,
                                                const double* __restrict__ tab, int K1,
-                                               double* __restrict__ kappa, float* __restrict__ kappa32) {
+                                               double* __restrict__ kappa, float* __restrict__ kappa32,
+                                               const int* __restrict__ rowmap) {
   constexpr int WS = BS / 16;          // waves along samples
   constexpr int WE = 4 / WS;           // waves along elements
   constexpr int BE = 64 * WE;          // elements per workgroup
@@ -55,7 +57,8 @@ __global__ void __launch_bounds__(256) k_field(int n, int M, int64_t count,
       const int r = q / kKc, c = q % kKc;
       const int64_t s = s0 + r;
       const int m = m0 + c;
-      xs[r][c] = (s < count && m < M) ? xi[s * M + m] * sqrtlam[m] : 0.0;
+      const int64_t row = (s < count && rowmap) ? rowmap[s] : s;
+      xs[r][c] = (s < count && m < M) ? xi[row * M + m] * sqrtlam[m] : 0.0;
     }
     for (int q = tid; q < BE * kKc; q += 256) {
       const int r = q / kKc, c = q % kKc;
@@ -89,9 +92,10 @@ __global__ void __launch_bounds__(256) k_field(int n, int M, int64_t count,
     for (int r = 0; r < 4; ++r) {
       const int64_t s = s0 + 16 * ws + (lane >> 4) + 4 * r;
       if (s < count && e < ne) {
+        const int64_t row = rowmap ? rowmap[s] : s;
         const double k = exp(acc[t][r]);
-        kappa[s * ne + e] = k;
-        if (kappa32) kappa32[s * ne + e] = (float)k;
+        kappa[row * ne + e] = k;
+        if (kappa32) kappa32[row * ne + e] = (float)k;
       }
     }
   }
@@ -101,15 +105,15 @@ __global__ void __launch_bounds__(256) k_field(int n, int M, int64_t count,
 
 hipError_t launch_field(int n, int M, int64_t count, const double* xi, const double* sqrtlam,
                         const int* triples, const double* tab, int K1, double* kappa,
-                        float* kappa32, hipStream_t st) {
+                        float* kappa32, hipStream_t st, const int* rowmap) {
   if (count <= 0) return hipSuccess;
   const int64_t ne = (int64_t)n * n * n;
   if (count >= 48) {
     dim3 grid((unsigned)((ne + 63) / 64), (unsigned)((count + 63) / 64));
-    k_field<64><<<grid, dim3(256), 0, st>>>(n, M, count, xi, sqrtlam, triples, tab, K1, kappa, kappa32);
+    k_field<64><<<grid, dim3(256), 0, st>>>(n, M, count, xi, sqrtlam, triples, tab, K1, kappa, kappa32, rowmap);
   } else {
     dim3 grid((unsigned)((ne + 255) / 256), (unsigned)((count + 15) / 16));
-    k_field<16><<<grid, dim3(256), 0, st>>>(n, M, count, xi, sqrtlam, triples, tab, K1, kappa, kappa32);
+    k_field<16><<<grid, dim3(256), 0, st>>>(n, M, count, xi, sqrtlam, triples, tab, K1, kappa, kappa32, rowmap);
   }
   return hipGetLastError();
 }

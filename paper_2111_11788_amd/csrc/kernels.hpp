@@ -9,11 +9,15 @@ namespace mlmc {
 // rng.hip
 hipError_t launch_draw_xi(uint64_t seed, int level, uint64_t first, int64_t count, int M,
                           double* xi, hipStream_t st);
+// row r: sample ids[r] of level lv[r] into row slots[r] of xi
+hipError_t launch_draw_xi_rows(uint64_t seed, int64_t count, int M, const uint64_t* ids, const int* lv,
+                               const int* slots, double* xi, hipStream_t st);
 
 // field.hip: kappa[b][e] = exp(sum_m xi[b][m] sqrtlam[m] tab[ex][t0] tab[ey][t1] tab[ez][t2])
+// rowmap (may be null): row r reads xi row rowmap[r] and writes kappa slot rowmap[r]
 hipError_t launch_field(int n, int M, int64_t count, const double* xi, const double* sqrtlam,
                         const int* triples, const double* tab, int K1, double* kappa,
-                        float* kappa32, hipStream_t st);
+                        float* kappa32, hipStream_t st, const int* rowmap = nullptr);
 
 // Per-sample scalar state of a batched Krylov solve (device arrays of B entries).
 struct SolveState {
@@ -27,7 +31,11 @@ struct SolveState {
   int* iters;       // iterations done
   int* nactive;     // single counter (device) of active samples
   uint32_t pstride; // capacity of partial sums per sample
+  int* phase;       // serving: per-slot phase (PHASE_*), may be null
 };
+
+// per-slot phases of a served batch
+enum : int { PHASE_FREE = 0, PHASE_INNER = 1, PHASE_TRANSITION = 2, PHASE_RESTART = 3, PHASE_DONE = 4 };
 
 // Grid-layout kernels on an n^3 mesh for `B` samples; `active` (may be null)
 // skips samples whose flag is 0.  Device pointers must be 16-byte aligned.
@@ -56,7 +64,7 @@ hipError_t launch_prolong_add(int nf, int B, const T* xc, T* xf, const int* acti
 template <class T>
 hipError_t launch_coarsest(int B, const T* kap, const T* b, T* x, const int* active, hipStream_t st);
 template <class T>
-hipError_t launch_coarsen(int nf, int B, const T* kf, T* kc, hipStream_t st);
+hipError_t launch_coarsen(int nf, int B, const T* kf, T* kc, hipStream_t st, const int* active = nullptr);
 template <class Ts, class Td>
 hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st);
 template <class T>
@@ -104,7 +112,9 @@ enum ReduceOp : int {
   RED_RR = 2,       // rr = sum; converged when rr <= tol2 * bb -> active = 0
   RED_RZ_INIT = 3,  // rz = sum
   RED_BETA = 4,     // beta = sum / rz; rz = sum
-  RED_STORE = 5     // out[b] = sum
+  RED_STORE = 5,    // out[b] = sum (ignores the active mask)
+  RED_RR_INNER = 6, // rr = sum; converged -> phase TRANSITION
+  RED_RR_OUTER = 7  // rr = sum; phase DONE if converged else RESTART
 };
 hipError_t launch_reduce(int B, int op, double tol2, uint32_t nparts, SolveState s, double* out,
                          hipStream_t st);
@@ -113,6 +123,10 @@ hipError_t launch_set_active(int B, SolveState s, int value, hipStream_t st);
 
 // partial sums of w . u into s.partial (reduce with RED_STORE)
 hipError_t launch_qoi_partial(int n, int B, int qoi, const double* u, SolveState s,
-                              uint32_t* nparts, hipStream_t st);
+                              uint32_t* nparts, hipStream_t st, bool masked = false);
+hipError_t launch_phase_masks(int S, const int* phase, int* inner, int* trans, int* restart, int* done,
+                              hipStream_t st);
+hipError_t launch_set_phase_list(int count, const int* slots, int* phase, int value, hipStream_t st);
+hipError_t launch_set_phase_mask(int S, const int* mask, int* phase, int value, int* zero, hipStream_t st);
 
 }  // namespace mlmc

@@ -196,8 +196,9 @@ __global__ void __launch_bounds__(kBlock) k_fill_interior(SGeom g, size_t stride
 // h^3 prod_d c(i_d) with c = 2 strictly inside, 1 on the faces, 0 outside
 // (the number of subcube elements touching the node along each axis).
 __global__ void __launch_bounds__(kBlock) k_qoi_partial(SGeom g, size_t stride, int qoi, const double* __restrict__ u,
-                                                        SolveState st) {
+                                                        SolveState st, bool masked) {
   const Span sp = span_of(g);
+  if (masked && !st.active[sp.b]) return;
   const int n = g.n;
   const size_t n2 = (size_t)n * n;
   const double* ub = u + (size_t)sp.b * stride + n2;
@@ -224,7 +225,7 @@ __global__ void __launch_bounds__(kBlock) k_qoi_partial(SGeom g, size_t stride, 
 // one workgroup per sample: fixed-order sum of its partials, then the scalar op
 __global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t nparts, SolveState st, double* out) {
   const int b = blockIdx.x;
-  if (op != RED_STORE && op != RED_BB && !st.active[b]) return;
+  if (op != RED_STORE && st.active && !st.active[b]) return;
   const double* p = st.partial + (size_t)b * st.pstride;
   double v = 0.0;
   for (uint32_t c = threadIdx.x; c < nparts; c += kBlock) v += p[c];
@@ -239,7 +240,43 @@ __global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t
       break;
     case RED_RZ_INIT: st.rz[b] = v; break;
     case RED_BETA: st.beta[b] = v / st.rz[b]; st.rz[b] = v; break;
+    case RED_RR_INNER:
+      st.rr[b] = v;
+      if (v <= tol2 * st.bb[b]) st.phase[b] = PHASE_TRANSITION;
+      break;
+    case RED_RR_OUTER:
+      st.rr[b] = v;
+      st.phase[b] = v <= tol2 * st.bb[b] ? PHASE_DONE : PHASE_RESTART;
+      break;
     default: out[b] = v; break;
+  }
+}
+
+// per-slot masks of the serving phases
+__global__ void k_phase_masks(int S, const int* __restrict__ phase, int* __restrict__ inner, int* __restrict__ trans,
+                              int* __restrict__ restart, int* __restrict__ done) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= S) return;
+  const int ph = phase[b];
+  inner[b] = ph == PHASE_INNER;
+  trans[b] = ph == PHASE_TRANSITION;
+  restart[b] = ph == PHASE_RESTART;
+  done[b] = ph == PHASE_DONE;
+}
+
+// phase[slots[r]] = value for r < count
+__global__ void k_set_phase_list(int count, const int* __restrict__ slots, int* __restrict__ phase, int value) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < count) phase[slots[r]] = value;
+}
+
+// phase[b] = value where mask[b]; optionally also zero an int array there
+__global__ void k_set_phase_mask(int S, const int* __restrict__ mask, int* __restrict__ phase, int value,
+                                 int* __restrict__ zero) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < S && mask[b]) {
+    phase[b] = value;
+    if (zero) zero[b] = 0;
   }
 }
 
@@ -326,10 +363,27 @@ hipError_t launch_set_active(int B, SolveState s, int value, hipStream_t st) {
 }
 
 hipError_t launch_qoi_partial(int n, int B, int qoi, const double* u, SolveState s, uint32_t* nparts,
-                              hipStream_t st) {
+                              hipStream_t st, bool masked) {
   const SGeom g = sgeom<double>(n);
   if (nparts) *nparts = g.chunks;
-  k_qoi_partial<<<sgrid<double>(g, B), kBlock, 0, st>>>(g, grid_stride(n), qoi, u, s);
+  k_qoi_partial<<<sgrid<double>(g, B), kBlock, 0, st>>>(g, grid_stride(n), qoi, u, s, masked);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase_masks(int S, const int* phase, int* inner, int* trans, int* restart, int* done,
+                              hipStream_t st) {
+  k_phase_masks<<<dim3((S + kBlock - 1) / kBlock), kBlock, 0, st>>>(S, phase, inner, trans, restart, done);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_phase_list(int count, const int* slots, int* phase, int value, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  k_set_phase_list<<<dim3((count + kBlock - 1) / kBlock), kBlock, 0, st>>>(count, slots, phase, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_phase_mask(int S, const int* mask, int* phase, int value, int* zero, hipStream_t st) {
+  k_set_phase_mask<<<dim3((S + kBlock - 1) / kBlock), kBlock, 0, st>>>(S, mask, phase, value, zero);
   return hipGetLastError();
 }
 

@@ -108,17 +108,10 @@ __device__ void fixed_sincos_2pi(double u, const TrigCoeffs& tc, double* sv, dou
   }
 }
 
-// One thread per (sample, Philox block); xi row-major [count][M].
-__global__ void __launch_bounds__(kBlock) k_draw_xi(uint64_t seed, uint64_t level, uint64_t first,
-                                                    int64_t count, int M, double* __restrict__ xi) {
-  const int nblk = (M + 3) >> 2;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= count * nblk) return;
-  const int64_t s = tid / nblk;
-  const int j = (int)(tid - s * nblk);
-  const Block4 b = philox4x64_10(first + (uint64_t)s, level, (uint64_t)j, 0ull, seed, 0ull);
+// The four normals of Philox block (sample, level, j): two Box-Muller pairs.
+__device__ __forceinline__ void block_normals(uint64_t seed, uint64_t sample, uint64_t level, int j, double* z) {
+  const Block4 b = philox4x64_10(sample, level, (uint64_t)j, 0ull, seed, 0ull);
   const TrigCoeffs tc = trig_coeffs();
-  double z[4];
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     const double ua = to_uniform(b.w[2 * p]), ub = to_uniform(b.w[2 * p + 1]);
@@ -128,13 +121,53 @@ __global__ void __launch_bounds__(kBlock) k_draw_xi(uint64_t seed, uint64_t leve
     z[2 * p] = rad * cv;
     z[2 * p + 1] = rad * sv;
   }
+}
+
+// One thread per (sample, Philox block); xi row-major [count][M].
+__global__ void __launch_bounds__(kBlock) k_draw_xi(uint64_t seed, uint64_t level, uint64_t first,
+                                                    int64_t count, int M, double* __restrict__ xi) {
+  const int nblk = (M + 3) >> 2;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= count * nblk) return;
+  const int64_t s = tid / nblk;
+  const int j = (int)(tid - s * nblk);
+  double z[4];
+  block_normals(seed, first + (uint64_t)s, level, j, z);
   double* out = xi + s * M + 4 * j;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
     if (4 * j + q < M) out[q] = z[q];
 }
 
+// Serving form: row r draws sample ids[r] of level lv[r] into row slots[r] of xi.
+__global__ void __launch_bounds__(kBlock) k_draw_xi_rows(uint64_t seed, int64_t count, int M,
+                                                         const uint64_t* __restrict__ ids,
+                                                         const int* __restrict__ lv,
+                                                         const int* __restrict__ slots,
+                                                         double* __restrict__ xi) {
+  const int nblk = (M + 3) >> 2;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= count * nblk) return;
+  const int64_t r = tid / nblk;
+  const int j = (int)(tid - r * nblk);
+  double z[4];
+  block_normals(seed, ids[r], (uint64_t)lv[r], j, z);
+  double* out = xi + (int64_t)slots[r] * M + 4 * j;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (4 * j + q < M) out[q] = z[q];
+}
+
 }  // namespace
+
+hipError_t launch_draw_xi_rows(uint64_t seed, int64_t count, int M, const uint64_t* ids, const int* lv,
+                               const int* slots, double* xi, hipStream_t st) {
+  const int64_t total = count * ((M + 3) / 4);
+  if (total <= 0) return hipSuccess;
+  k_draw_xi_rows<<<dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st>>>(seed, count, M, ids, lv,
+                                                                                           slots, xi);
+  return hipGetLastError();
+}
 
 hipError_t launch_draw_xi(uint64_t seed, int level, uint64_t first, int64_t count, int M,
                           double* xi, hipStream_t st) {

@@ -508,11 +508,12 @@ __global__ void k_coarsest(int B, size_t stride, const T* __restrict__ kap, cons
 
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_coarsen(int nc, int64_t total, const T* __restrict__ kf,
-                                                    T* __restrict__ kc) {
+                                                    T* __restrict__ kc, const int* __restrict__ active) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
   const int64_t nce = (int64_t)nc * nc * nc;
   const int64_t b = t / nce, E = t - b * nce;
+  if (active && !active[b]) return;
   const int nf = 2 * nc;
   const int EX = (int)(E % nc), EY = (int)((E / nc) % nc), EZ = (int)(E / ((int64_t)nc * nc));
   const T* f = kf + b * nce * 8 + 2 * EX + (int64_t)nf * 2 * EY + (int64_t)nf * nf * 2 * EZ;
@@ -612,10 +613,10 @@ hipError_t launch_coarsest(int B, const T* kap, const T* b, T* x, const int* act
 }
 
 template <class T>
-hipError_t launch_coarsen(int nf, int B, const T* kf, T* kc, hipStream_t st) {
+hipError_t launch_coarsen(int nf, int B, const T* kf, T* kc, hipStream_t st, const int* active) {
   const int nc = nf / 2;
   const int64_t total = (int64_t)B * nc * nc * nc;
-  k_coarsen<T><<<dim3((unsigned)((total + kBlock - 1) / kBlock)), kBlock, 0, st>>>(nc, total, kf, kc);
+  k_coarsen<T><<<dim3((unsigned)((total + kBlock - 1) / kBlock)), kBlock, 0, st>>>(nc, total, kf, kc, active);
   return hipGetLastError();
 }
 
@@ -638,7 +639,7 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st) 
   template hipError_t launch_restrict<T>(int, int, const T*, T*, const int*, hipStream_t);             \
   template hipError_t launch_prolong_add<T>(int, int, const T*, T*, const int*, hipStream_t);          \
   template hipError_t launch_coarsest<T>(int, const T*, const T*, T*, const int*, hipStream_t);        \
-  template hipError_t launch_coarsen<T>(int, int, const T*, T*, hipStream_t);
+  template hipError_t launch_coarsen<T>(int, int, const T*, T*, hipStream_t, const int*);
 MLMC_INST(float)
 MLMC_INST(double)
 #undef MLMC_INST

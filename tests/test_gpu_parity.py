@@ -207,3 +207,18 @@ def test_graph_replay_matches_eager(dev, precision, monkeypatch):
     for a, b in zip(got, want):
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
+
+
+def test_autotune_keeps_parity(dev):
+    # the tuned execution choices change speed, not the solution
+    wl = _wl(n0=16, levels=2, n_modes=16, corr_len=0.3, rtol=1e-12, precision=1, batch=8)
+    ctx = mm.Context(wl, arena_bytes=1 << 30)
+    best = ctx.autotune(1, 8)
+    assert best["seconds"] > 0 and 1 <= best["cheb_degree"] <= 3
+    assert ctx.tuning()["cheb_degree"] == best["cheb_degree"]
+    y, qf, qc, it = ctx.sample_level(1, 0, 4)
+    yo, qfo, qco, _ = omlmc.sample_level(wl, 1, 0, 4, rtol=1e-12, max_iter=20000)
+    assert np.all(np.abs(qf - qfo) <= 1e-7 * np.abs(qfo))
+    assert np.all(np.abs(qc - qco) <= 1e-7 * np.abs(qco))
+    with pytest.raises(mm.MLMCError):
+        ctx.set_tuning(cheb_degree=0)

@@ -1,0 +1,80 @@
+"""Serving (continuous batching) through the C-ABI: results against the
+oracle, alone-vs-mixed bit equality, admission by budget."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_2111_11788_amd as mm
+from oracle import mlmc as omlmc
+from workloads import Workload
+
+
+def _wl(**kw):
+    base = dict(name="serve", n0=8, levels=3, sigma2=1.0, corr_len=0.3, n_modes=32, qoi=0, rtol=1e-10,
+                max_iter=400, solver=0, precision=1, batch=8)
+    base.update(kw)
+    return Workload(**base)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda")
+
+
+def test_served_samples_match_oracle(dev):
+    wl = _wl()
+    ctx = mm.Context(wl, arena_bytes=1 << 30)
+    ctx.serve_start([8, 8, 4])
+    reqs = [(0, 3), (1, 4), (2, 5), (2, 6), (1, 7), (0, 8)]
+    tickets = {ctx.submit(l, s): (l, s) for l, s in reqs}
+    res = ctx.wait(tickets.keys())
+    ctx.serve_stop()
+    for t, (l, s) in tickets.items():
+        r = res[t]
+        assert r["status"] == 0 and r["level"] == l and r["sample"] == s
+        y, qf, qc, _ = omlmc.sample_level(wl, l, s, 1, rtol=1e-12, max_iter=20000)
+        assert abs(r["q_fine"] - qf[0]) <= 1e-7 * abs(qf[0])
+        if l > 0:
+            assert abs(r["q_coarse"] - qc[0]) <= 1e-7 * abs(qc[0])
+        assert abs(r["y"] - (r["q_fine"] - r["q_coarse"])) == 0.0
+        assert r["latency_s"] >= r["queue_s"] >= 0.0
+
+
+def test_alone_and_in_the_mix_are_identical(dev):
+    wl = _wl()
+    ctx = mm.Context(wl, arena_bytes=1 << 30)
+    ctx.serve_start([16, 16, 6])
+    alone = ctx.wait([ctx.submit(2, 11)])
+    (a,) = alone.values()
+    # a burst of mixed levels that keeps every pool busy, with the same sample inside
+    rng = np.random.default_rng(5)
+    burst = [(int(l), int(s)) for l, s in zip(rng.integers(0, 3, 60), rng.integers(0, 1000, 60))]
+    burst.insert(17, (2, 11))
+    tickets = [ctx.submit(l, s) for l, s in burst]
+    res = ctx.wait(tickets)
+    ctx.serve_stop()
+    b = res[tickets[17]]
+    for k in ("y", "q_fine", "q_coarse", "iters"):
+        assert a[k] == b[k], k
+    assert all(r["status"] == 0 for r in res.values())
+
+
+def test_budget_refusal_and_stop(dev):
+    wl = _wl()
+    ctx = mm.Context(wl, arena_bytes=1 << 30)
+    ctx.serve_start([4, 4, 0])          # no slots for the 32^3 mesh
+    with pytest.raises(mm.MLMCError) as e:
+        ctx.submit(2, 0)
+    assert e.value.code == -3
+    t = ctx.submit(1, 0)                # 16^3 + 8^3 still served
+    assert ctx.wait([t])[t]["status"] == 0
+    # batch entry points are refused while serving
+    with pytest.raises(mm.MLMCError):
+        ctx.sample_level(0, 0, 1)
+    ctx.serve_stop()
+    y, _, _, _ = ctx.sample_level(0, 0, 2)   # and work again afterwards
+    assert np.all(np.isfinite(y))
