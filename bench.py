@@ -47,7 +47,8 @@ def cpu_baseline(wl, samples: int):
     """The oracle (assembled CSR + Jacobi-PCG, fp64) on `samples` samples of
     the workload, one single-threaded process per core."""
     import multiprocessing as mp
-    cores = max(1, min(samples, os.cpu_count() or 1, 16))
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(samples, avail, 16))
     t0 = time.perf_counter()
     ctx = mp.get_context("spawn")
     with ctx.Pool(cores) as pool:
@@ -58,16 +59,17 @@ def cpu_baseline(wl, samples: int):
             "sample": f"{samples} samples of the 64^3 workload (level 0, indices 0..{samples - 1}), "
                       f"assembled CSR + Jacobi-PCG to rel.res 1e-8, {cores} processes x 1 thread",
             "wall_s": round(wall, 3), "mean_sample_s": round(sum(r[0] for r in res) / samples, 3),
-            "cpu": platform.processor() or platform.machine()}
+            "cpu": platform.processor() or platform.machine(), "cpu_count": os.cpu_count(), "affinity": avail}
 
 
-def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bool):
+def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bool, autotune: bool = False):
     import numpy as np
     import torch
     import paper_2111_11788_amd as mm
 
     ctx = mm.Context(wl, precision=precision, max_batch=batch)
     dofs = (wl.n0 - 1) ** 3
+    tuning = ctx.autotune(0, batch) if autotune else ctx.tuning()
     first = 0
     for _ in range(warmup):
         ctx.sample_level(0, first, batch)
@@ -82,7 +84,7 @@ def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bo
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     out = {"value": steps * batch * dofs / wall, "ms_per_step": 1e3 * wall / steps,
-           "iters_mean": float(np.mean(its)), "iters_max": int(np.max(its))}
+           "iters_mean": float(np.mean(its)), "iters_max": int(np.max(its)), "tuning": tuning}
     if profile:
         ctx.set_profiling(True)
         ctx.sample_level(0, first, batch)
@@ -107,6 +109,153 @@ def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bo
     return out
 
 
+def run_c3(args):
+    """Time-to-eps of the 5-level MLMC workload (pilot + optimal allocation)."""
+    import numpy as np
+    import torch
+    import paper_2111_11788_amd as mm
+    import workloads
+    wl = workloads.C3
+    ctx = mm.Context(wl, max_batch=1024, arena_bytes=40 << 30)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nl, est = ctx.estimate(wl.eps, n_pilot=32, cost_model=0, max_rounds=3)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dofs = sum(int(nl[l]) * ((wl.n(l) - 1) ** 3 + ((wl.n(l) // 2 - 1) ** 3 if l else 0)) for l in range(wl.levels))
+    return {"metric": "time-to-eps", "value": wall, "unit": "s", "higher_is_better": False,
+            "config": {"workload": wl.name, "meshes": [wl.n(l) for l in range(wl.levels)], "eps": wl.eps,
+                       "n_pilot": 32, "n_modes": wl.n_modes, "corr_len": wl.corr_len, "precision": "mixed"},
+            "n_per_level": [int(x) for x in nl], "qtilde": est["qtilde"], "var_qtilde": est["var_qtilde"],
+            "eps2_over_2": wl.eps ** 2 / 2, "var_per_level": [l["var"] for l in est["levels"]],
+            "sample_dofs_per_s": dofs / wall, "dtype": "f32+f64", "data": "synthetic"}
+
+
+def run_c4(args):
+    """Serving: Poisson arrivals over levels 16^3..256^3 weighted 16^(4-l)."""
+    import numpy as np
+    import torch
+    import paper_2111_11788_amd as mm
+    import workloads
+    wl = workloads.C4
+    weights = np.array([16.0 ** (wl.levels - 1 - l) for l in range(wl.levels)])
+    weights /= weights.sum()
+    slots = [int(x) for x in args.slots.split(",")] if args.slots else [2048, 1024, 128, 8, 2]
+    ctx = mm.Context(wl, arena_bytes=int(args.arena_gb * 2**30))
+    ctx.serve_start(slots)
+    rng = np.random.default_rng(4)
+    dofs = [(wl.n(l) - 1) ** 3 + ((wl.n(l) // 2 - 1) ** 3 if l else 0) for l in range(wl.levels)]
+    next_id = [0] * wl.levels
+
+    def draw(k):
+        lv = rng.choice(wl.levels, size=k, p=weights)
+        out = []
+        for l in lv:
+            out.append((int(l), next_id[l]))
+            next_id[l] += 1
+        return out
+
+    def submit(rs):
+        return ctx.submit_batch([l for l, _ in rs], [s for _, s in rs])
+
+    # warm-up, then closed-loop saturation: a burst of requests, all in flight
+    ctx.wait(submit(draw(2000)), timeout=600)
+    reqs = draw(args.burst)
+    t0 = time.perf_counter()
+    res = ctx.wait(submit(reqs), timeout=600)
+    sat_wall = time.perf_counter() - t0
+    sat_rate = len(reqs) / sat_wall
+    sat_dofs = sum(dofs[l] for l, _ in reqs) / sat_wall
+    out = {"metric": "serving p50/p99 latency and sample-DOFs/s", "unit": "s",
+           "config": {"workload": wl.name, "meshes": [wl.n(l) for l in range(wl.levels)], "slots": slots,
+                      "level_weights": weights.tolist(), "n_modes": wl.n_modes, "kle": "fp64 MFMA",
+                      "precision": "mixed"},
+           "saturation": {"requests_per_s": sat_rate, "sample_dofs_per_s": sat_dofs, "requests": len(reqs)},
+           "rates": []}
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * sat_rate
+        n = int(args.serve_seconds * rate)
+        reqs = draw(n)
+        arrive = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        tickets, res = [], {}
+        t0 = time.perf_counter()
+        i = 0
+        while i < n:
+            # submit every request whose arrival time has passed, drain finished ones
+            now = time.perf_counter() - t0
+            j = int(np.searchsorted(arrive, now, side="right"))
+            if j > i:
+                tickets.extend(int(t) for t in submit(reqs[i:j]))
+                i = j
+            for r in ctx.drain(timeout=0.0):
+                res[r["ticket"]] = r
+        left = [t for t in tickets if t not in res]
+        res.update(ctx.wait(left, timeout=600))
+        wall = time.perf_counter() - t0
+        lat = np.array([res[t]["latency_s"] for t in tickets])
+        lv = np.array([l for l, _ in reqs])
+        per = {}
+        for l in range(wl.levels):
+            m = lv == l
+            if m.sum():
+                per[str(l)] = {"n": int(m.sum()), "p50_ms": 1e3 * float(np.percentile(lat[m], 50)),
+                               "p99_ms": 1e3 * float(np.percentile(lat[m], 99))}
+        out["rates"].append({"fraction_of_saturation": frac, "offered_requests_per_s": rate, "requests": n,
+                             "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                             "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                             "sample_dofs_per_s": sum(dofs[l] for l, _ in reqs) / wall, "per_level": per,
+                             "all_ok": all(res[t]["status"] == 0 for t in tickets)})
+    ctx.serve_stop()
+    return out
+
+
+def run_c5(args):
+    """256^3 stress: batches of 4, 8, 16; iterations, GB/s, QoI vs the oracle on 2 samples."""
+    import numpy as np
+    import torch
+    import paper_2111_11788_amd as mm
+    import workloads
+    wl = workloads.C5
+    gold = None
+    gp = os.path.join(ROOT, "tests", "golden", "c5_stress_qoi.json")
+    if os.path.exists(gp):
+        gold = json.load(open(gp))
+    out = {"metric": "MLMC sample-DOFs solved/s at rel.res 1e-8", "unit": "sample-DOFs/s",
+           "config": {"workload": wl.name, "mesh": "256^3", "sigma2": wl.sigma2, "corr_len": wl.corr_len,
+                      "n_modes": wl.n_modes, "precision": "mixed"}, "batches": []}
+    for B in (4, 8, 16):
+        ctx = mm.Context(wl, max_batch=B)
+        y, qf, qc, it = ctx.sample_level(0, 0, B)       # warm-up (carve, graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y, qf, qc, it = ctx.sample_level(0, 0, B)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ctx.set_profiling(True)
+        ctx.sample_level(0, 0, B)
+        rows = []
+        for name in mm.KERNELS:
+            for p in (0, 1):
+                n, ms, by = ctx.kernel_time(name, p)
+                if n:
+                    rows.append((ms, name, p, n, by))
+        ctx.set_profiling(False)
+        rows.sort(reverse=True)
+        ms, name, p, n, by = rows[0]
+        rec = {"batch": B, "ms": 1e3 * wall, "sample_dofs_per_s": B * 255 ** 3 / wall,
+               "iters": [int(x) for x in it], "dominant": f"{name} ({'f32' if p else 'f64'})",
+               "dominant_GBps": by / (ms * 1e-3) / 1e9}
+        if gold:
+            rec["qoi_vs_oracle"] = [{"sample": g["index"], "gpu": float(qf[g["index"]]), "oracle": g["q"],
+                                     "rel_err": abs(float(qf[g["index"]]) - g["q"]) / abs(g["q"])}
+                                    for g in gold["samples"]]
+        out["batches"].append(rec)
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,19 +263,30 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--mode", choices=["c2", "c3", "c4", "c5"], default="c2",
+                    help="c2: the throughput line (default); c3: time-to-eps; c4: serving; c5: 256^3 stress")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the fp64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=16)
+    ap.add_argument("--slots", default="", help="c4: slots per mesh, comma separated")
+    ap.add_argument("--arena-gb", type=float, default=40.0)
+    ap.add_argument("--burst", type=int, default=20000)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); samples are independent, "
               "so a multi-GPU run is N copies of this one on disjoint sample ranges", file=sys.stderr)
         sys.exit(2)
+    if args.mode != "c2":
+        fn = {"c3": run_c3, "c4": run_c4, "c5": run_c5}[args.mode]
+        print(json.dumps(fn(args)))
+        return
 
     import workloads
     wl = workloads.C2
     prec = 1 if args.precision == "mixed" else 0
-    main_run = run_gpu(wl, prec, args.steps, args.warmup, args.batch, profile=True)
+    main_run = run_gpu(wl, prec, args.steps, args.warmup, args.batch, profile=True, autotune=not args.no_autotune)
     fp64 = None
     if prec == 1 and not args.no_fp64:
         fp64 = run_gpu(wl, 0, max(1, args.steps // 2), 1, args.batch, profile=False)
@@ -140,9 +300,10 @@ def main():
         "config": {"workload": wl.name, "mesh": f"{wl.n0}^3 Q1 hexahedra", "samples_per_step": args.batch,
                    "dofs_per_sample": (wl.n0 - 1) ** 3, "n_modes": wl.n_modes, "corr_len": wl.corr_len,
                    "sigma2": wl.sigma2, "qoi": "subcube [1/4,3/4]^3 average", "rtol": wl.rtol,
-                   "solver": "GMG-PCG (Chebyshev-Jacobi deg 2, V-cycle to 2^3)",
+                   "solver": "GMG-PCG (Chebyshev-Jacobi smoothing, V-cycle to 2^3)",
                    "precision": "fp32 GMG-PCG inside fp64 refinement" if prec == 1 else "fp64"},
         "iterations": {"mean": main_run["iters_mean"], "max": main_run["iters_max"]},
+        "tuning": main_run["tuning"],
         "roofline": main_run.get("roofline"),
         "kernels": main_run.get("kernels"),
         "fp64_path": None if fp64 is None else {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],

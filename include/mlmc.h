@@ -242,6 +242,7 @@ int mlmc_reset_stats(mlmc_ctx* ctx);
 /* ---------------------------------------------------------------- serving */
 
 typedef struct mlmc_sample_result {
+  uint64_t ticket;
   int32_t status;       /* MLMC_OK, MLMC_E_NOCONV or MLMC_E_NONFINITE */
   int32_t level;
   uint64_t sample;
@@ -286,6 +287,18 @@ int mlmc_submit(mlmc_ctx* ctx, int32_t level, uint64_t sample_id, uint64_t* tick
 /* MLMC_PENDING while the request runs; MLMC_OK with *out filled (the ticket
  * is then consumed); MLMC_E_INVALID for an unknown ticket.  Thread-safe. */
 int mlmc_poll(mlmc_ctx* ctx, uint64_t ticket, mlmc_sample_result* out);
+
+/* Queue `count` samples at once (levels[i], samples[i]); tickets (host,
+ * `count` entries) receive their tickets.  Thread-safe.  On an error no
+ * request of the call is queued. */
+int mlmc_submit_batch(mlmc_ctx* ctx, int32_t count, const int32_t* levels, const uint64_t* samples,
+                      uint64_t* tickets);
+
+/* Wait up to timeout_s seconds for finished requests and move up to `max`
+ * of them, in completion order, into out (host array); *n receives the
+ * number returned (0 on timeout).  Returned tickets are consumed.
+ * Thread-safe. */
+int mlmc_drain(mlmc_ctx* ctx, mlmc_sample_result* out, int32_t max, int32_t* n, double timeout_s);
 
 /* Counters of the running server.  Thread-safe. */
 int mlmc_serve_stats(mlmc_ctx* ctx, mlmc_serve_stats_out* out);

@@ -29,7 +29,8 @@ SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride",
            "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_vcycle", "mlmc_solve", "mlmc_qoi",
            "mlmc_sample_level", "mlmc_estimate", "mlmc_get_estimate", "mlmc_reset_stats",
            "mlmc_set_profiling", "mlmc_kernel_time", "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
-           "mlmc_serve_start", "mlmc_serve_stop", "mlmc_submit", "mlmc_poll", "mlmc_serve_stats"]
+           "mlmc_serve_start", "mlmc_serve_stop", "mlmc_submit", "mlmc_submit_batch", "mlmc_poll", "mlmc_drain",
+           "mlmc_serve_stats"]
 
 
 class MLMCError(RuntimeError):
@@ -53,7 +54,7 @@ class LevelStats(ctypes.Structure):
 
 
 class SampleResult(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int32), ("level", ctypes.c_int32), ("sample", ctypes.c_uint64),
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("level", ctypes.c_int32), ("sample", ctypes.c_uint64),
                 ("y", ctypes.c_double), ("q_fine", ctypes.c_double), ("q_coarse", ctypes.c_double),
                 ("iters", ctypes.c_int32), ("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double)]
 
@@ -123,6 +124,8 @@ def lib():
         "mlmc_serve_stop": (ctypes.c_int, [P]),
         "mlmc_submit": (ctypes.c_int, [P, I32, U64, ctypes.POINTER(U64)]),
         "mlmc_poll": (ctypes.c_int, [P, U64, ctypes.POINTER(SampleResult)]),
+        "mlmc_submit_batch": (ctypes.c_int, [P, I32, P, P, P]),
+        "mlmc_drain": (ctypes.c_int, [P, P, I32, ctypes.POINTER(I32), D]),
         "mlmc_serve_stats": (ctypes.c_int, [P, ctypes.POINTER(ServeStats)]),
         "mlmc_kernel_time": (ctypes.c_int, [P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(D),
                                             ctypes.POINTER(D)]),
@@ -320,24 +323,33 @@ class Context:
         return dict(completed=s.completed, sample_dofs=s.sample_dofs, busy_seconds=s.busy_seconds,
                     queued=s.queued, running=s.running, slots=list(s.slots), occupied=list(s.occupied))
 
-    def wait(self, tickets, timeout: float = 120.0, sleep: float = 2e-4):
-        """Poll until every ticket is done; returns {ticket: result}."""
+    def submit_batch(self, levels, samples):
+        lv = np.ascontiguousarray(levels, dtype=np.int32)
+        sm = np.ascontiguousarray(samples, dtype=np.uint64)
+        tk = np.zeros(len(lv), dtype=np.uint64)
+        self._check(lib().mlmc_submit_batch(self.h, len(lv), lv.ctypes.data, sm.ctypes.data, tk.ctypes.data))
+        return tk
+
+    def drain(self, max_results: int = 4096, timeout: float = 0.05):
+        """Finished results (completion order), waiting up to `timeout` s for the first."""
+        buf = (SampleResult * max_results)()
+        n = ctypes.c_int32()
+        self._check(lib().mlmc_drain(self.h, buf, max_results, ctypes.byref(n), timeout))
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def wait(self, tickets, timeout: float = 120.0):
+        """Drain until every ticket is done; returns {ticket: result}."""
         import time
-        out, todo = {}, list(tickets)
+        want = set(int(t) for t in tickets)
+        out = {}
         t0 = time.monotonic()
-        while todo:
-            rest = []
-            for t in todo:
-                r = self.poll(t)
-                if r is None:
-                    rest.append(t)
-                else:
-                    out[t] = r
-            todo = rest
-            if todo:
-                if time.monotonic() - t0 > timeout:
-                    raise TimeoutError(f"{len(todo)} requests still pending")
-                time.sleep(sleep)
+        while want:
+            for r in self.drain(timeout=0.05):
+                if r["ticket"] in want:
+                    want.discard(r["ticket"])
+                out[r["ticket"]] = r
+            if want and time.monotonic() - t0 > timeout:
+                raise TimeoutError(f"{len(want)} requests still pending")
         return out
 
     def set_profiling(self, on: bool):

@@ -99,6 +99,8 @@ struct mlmc_server {
   std::mutex mu;
   std::condition_variable cv;
   std::unordered_map<uint64_t, Request> reqs;
+  std::deque<uint64_t> finished;               // completion order, not yet drained
+  std::condition_variable done_cv;
   uint64_t next_ticket = 1;
   bool stopping = false;
   int error = MLMC_OK;
@@ -282,6 +284,7 @@ void pool_loop(mlmc_server* srv, Pool* p) {
           r.t_done = t;
           srv->completed++;
           srv->last_done = t;
+          srv->finished.push_back(j.ticket);
         }
       }
       if (stuck) {
@@ -292,7 +295,21 @@ void pool_loop(mlmc_server* srv, Pool* p) {
       p->occupied--;
     }
     srv->cv.notify_all();
+    srv->done_cv.notify_all();
   }
+}
+
+void fill_result(const Request& r, uint64_t ticket, mlmc_sample_result* out) {
+  out->ticket = ticket;
+  out->status = r.status;
+  out->level = r.level;
+  out->sample = r.sample;
+  out->q_fine = r.qf;
+  out->q_coarse = r.level > 0 ? r.qc : 0.0;
+  out->y = out->q_fine - out->q_coarse;
+  out->iters = r.iters;
+  out->latency_s = r.t_done - r.t_submit;
+  out->queue_s = (r.t_admit >= 0 ? r.t_admit : r.t_done) - r.t_submit;
 }
 
 }  // namespace
@@ -390,6 +407,7 @@ int mlmc_serve_stop(mlmc_ctx* ctx) {
     srv->stopping = true;
   }
   srv->cv.notify_all();
+  srv->done_cv.notify_all();
   for (auto& p : srv->pools) {
     if (p->th.joinable()) p->th.join();
     if (p->sub.st) {
@@ -409,29 +427,41 @@ int mlmc_serve_stop(mlmc_ctx* ctx) {
   return MLMC_OK;
 }
 
-int mlmc_submit(mlmc_ctx* ctx, int32_t level, uint64_t sample_id, uint64_t* ticket) {
-  if (!ctx || !ticket) return MLMC_E_INVALID;
+int mlmc_submit_batch(mlmc_ctx* ctx, int32_t count, const int32_t* levels, const uint64_t* samples,
+                      uint64_t* tickets) {
+  if (!ctx || count < 0 || (count > 0 && (!levels || !samples || !tickets))) return MLMC_E_INVALID;
   mlmc_server* srv = ctx->server;
   if (!srv) return MLMC_E_INVALID;
-  if (level < 0 || level >= ctx->cfg.levels) return MLMC_E_INVALID;
   std::lock_guard<std::mutex> lk(srv->mu);
   if (srv->error) return srv->error;
   if (srv->stopping) return MLMC_E_INVALID;
-  Pool& pf = *srv->pools[level];
-  if (pf.S == 0 || (level > 0 && srv->pools[level - 1]->S == 0)) return MLMC_E_BUDGET;
-  const uint64_t t = srv->next_ticket++;
-  Request r;
-  r.level = level;
-  r.sample = sample_id;
-  r.t_submit = srv->now();
-  r.pending = level > 0 ? 2 : 1;
-  srv->reqs.emplace(t, r);
-  if (srv->first_submit < 0) srv->first_submit = r.t_submit;
-  pf.queue.push_back(Job{t, level, sample_id, true});
-  if (level > 0) srv->pools[level - 1]->queue.push_back(Job{t, level, sample_id, false});
-  *ticket = t;
+  for (int i = 0; i < count; ++i) {
+    const int level = levels[i];
+    if (level < 0 || level >= ctx->cfg.levels) return MLMC_E_INVALID;
+    if (srv->pools[level]->S == 0 || (level > 0 && srv->pools[level - 1]->S == 0)) return MLMC_E_BUDGET;
+  }
+  const double now = srv->now();
+  for (int i = 0; i < count; ++i) {
+    const int level = levels[i];
+    const uint64_t t = srv->next_ticket++;
+    Request r;
+    r.level = level;
+    r.sample = samples[i];
+    r.t_submit = now;
+    r.pending = level > 0 ? 2 : 1;
+    srv->reqs.emplace(t, r);
+    srv->pools[level]->queue.push_back(Job{t, level, samples[i], true});
+    if (level > 0) srv->pools[level - 1]->queue.push_back(Job{t, level, samples[i], false});
+    tickets[i] = t;
+  }
+  if (count && srv->first_submit < 0) srv->first_submit = now;
   srv->cv.notify_all();
   return MLMC_OK;
+}
+
+int mlmc_submit(mlmc_ctx* ctx, int32_t level, uint64_t sample_id, uint64_t* ticket) {
+  if (!ticket) return MLMC_E_INVALID;
+  return mlmc_submit_batch(ctx, 1, &level, &sample_id, ticket);
 }
 
 int mlmc_poll(mlmc_ctx* ctx, uint64_t ticket, mlmc_sample_result* out) {
@@ -443,17 +473,31 @@ int mlmc_poll(mlmc_ctx* ctx, uint64_t ticket, mlmc_sample_result* out) {
   if (it == srv->reqs.end()) return srv->error ? srv->error : MLMC_E_INVALID;
   const Request& r = it->second;
   if (!r.done) return srv->error ? srv->error : MLMC_PENDING;
-  out->status = r.status;
-  out->level = r.level;
-  out->sample = r.sample;
-  out->q_fine = r.qf;
-  out->q_coarse = r.level > 0 ? r.qc : 0.0;
-  out->y = out->q_fine - out->q_coarse;
-  out->iters = r.iters;
-  out->latency_s = r.t_done - r.t_submit;
-  out->queue_s = (r.t_admit >= 0 ? r.t_admit : r.t_done) - r.t_submit;
+  fill_result(r, ticket, out);
   srv->reqs.erase(it);
   return MLMC_OK;
+}
+
+int mlmc_drain(mlmc_ctx* ctx, mlmc_sample_result* out, int32_t max, int32_t* n, double timeout_s) {
+  if (!ctx || !out || !n || max < 1) return MLMC_E_INVALID;
+  *n = 0;
+  mlmc_server* srv = ctx->server;
+  if (!srv) return MLMC_E_INVALID;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  srv->done_cv.wait_for(lk, std::chrono::duration<double>(std::max(0.0, timeout_s)),
+                        [&] { return !srv->finished.empty() || srv->error || srv->stopping; });
+  int k = 0;
+  while (k < max && !srv->finished.empty()) {
+    const uint64_t t = srv->finished.front();
+    srv->finished.pop_front();
+    auto it = srv->reqs.find(t);
+    if (it == srv->reqs.end()) continue;   // already taken by mlmc_poll
+    fill_result(it->second, t, out + k);
+    srv->reqs.erase(it);
+    ++k;
+  }
+  *n = k;
+  return srv->error;
 }
 
 int mlmc_serve_stats(mlmc_ctx* ctx, mlmc_serve_stats_out* out) {
