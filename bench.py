@@ -29,6 +29,43 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+# HBM bytes per launch of each kernel class, from two rocprofv3 counter passes
+# over one sample_level pass of this workload (FETCH_SIZE x 2.0 + WRITE_SIZE x
+# 1.0 KiB, the factors read off a 1 GiB copy kernel in the same runs), averaged
+# over every launch of the class like the roofline's achieved rate.  They stand
+# for the kernels only while these sources and this tuning are unchanged; the
+# per-kernel table and the commands are in the committed counter summary.
+TRAFFIC = {
+    "profile": "profiles/batched-64cube-1024_hbm_traffic.txt",
+    "tuning": {"zvar_fp32": 0, "zvar_fp64": 0, "vsmall_fp32": 0, "vsmall_fp64": 0, "cheb_degree": 1,
+               "max_batch": 1024, "graph_batch": 0},
+    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "9d396ea4811a5cbf",
+                  "kernels.hpp": "1329d8f4fc368afe", "krylov.hip": "43366de07857d672",
+                  "stencil.hip": "a1e6bdb9f510a528"},
+    "bytes_per_launch": {
+        "PCG_UPDATE (f32)": 5433421547, "PCG_DIRECTION (f32)": 2112800183, "RESIDUAL (f32)": 726304811,
+        "CHEB (f32)": 723953032, "CHEB_ZERO (f32)": 531851174, "PCG_APPLY (f32)": 2872205939,
+        "PROLONG (f32)": 363713391, "RESTRICT (f32)": 191025761, "TRUE_RESIDUAL (f64)": 6794866098,
+    },
+}
+
+
+def measured_traffic(kernel: str, tuning: dict):
+    """Counter-measured HBM bytes per launch of `kernel`, or None when the
+    kernel sources or the tuning differ from those the counters were taken on."""
+    import hashlib
+    by = TRAFFIC["bytes_per_launch"].get(kernel)
+    if by is None:
+        return None
+    if any(tuning.get(k) != v for k, v in TRAFFIC["tuning"].items()):
+        return None
+    src = os.path.join(ROOT, "paper_2111_11788_amd", "csrc")
+    for name, want in TRAFFIC["sha256_16"].items():
+        with open(os.path.join(src, name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != want:
+                return None
+    return by
 METRIC = "MLMC sample-DOFs solved/s at rel.res 1e-8"
 
 
@@ -62,14 +99,32 @@ def cpu_baseline(wl, samples: int):
             "cpu": platform.processor() or platform.machine(), "cpu_count": os.cpu_count(), "affinity": avail}
 
 
-def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bool, autotune: bool = False):
+def copy_probe(mib: int):
+    """A plain copy kernel of known size (reads and writes `mib` MiB once):
+    the yardstick that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bool, autotune: bool = False,
+            tuning: dict | None = None, probe_mib: int = 0):
     import numpy as np
     import torch
     import paper_2111_11788_amd as mm
 
     ctx = mm.Context(wl, precision=precision, max_batch=batch)
     dofs = (wl.n0 - 1) ** 3
-    tuning = ctx.autotune(0, batch) if autotune else ctx.tuning()
+    if tuning:
+        ctx.set_tuning(**{k: v for k, v in tuning.items() if k != "seconds"})
+        tuning = ctx.tuning()
+    else:
+        tuning = ctx.autotune(0, batch) if autotune else ctx.tuning()
+    if probe_mib:
+        copy_probe(probe_mib)
     first = 0
     for _ in range(warmup):
         ctx.sample_level(0, first, batch)
@@ -99,10 +154,14 @@ def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bo
         ms, name, dt, n, by = rows[0]
         avg_ms = ms / n
         achieved = by / n / (avg_ms * 1e-3) / 1e9
-        out["roofline"] = {"bound": "hbm", "kernel": f"{name} ({dt})", "achieved": round(achieved, 1),
+        label = f"{name} ({dt})"
+        traffic = measured_traffic(label, tuning)
+        out["roofline"] = {"bound": "hbm", "kernel": label, "achieved": round(achieved, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                           "traffic": None, "launches": n, "avg_launch_us": round(1e3 * avg_ms, 2),
-                           "bytes_per_launch": by / n}
+                           "traffic": traffic, "launches": n, "avg_launch_us": round(1e3 * avg_ms, 2),
+                           "bytes_per_launch": by / n,
+                           "traffic_over_algorithmic": None if traffic is None else round(traffic / (by / n), 4),
+                           "traffic_source": TRAFFIC["profile"] if traffic is not None else None}
         out["kernels"] = [{"kernel": f"{r[1]} ({r[2]})", "ms": round(r[0], 3), "launches": r[3],
                            "GBps": round(r[4] / (r[0] * 1e-3) / 1e9, 1) if r[0] > 0 else None} for r in rows[:12]]
     ctx.close()
@@ -266,6 +325,10 @@ def main():
     ap.add_argument("--mode", choices=["c2", "c3", "c4", "c5"], default="c2",
                     help="c2: the throughput line (default); c3: time-to-eps; c4: serving; c5: 256^3 stress")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default="", help="JSON tuning to apply instead of autotuning "
+                    "(e.g. the 'tuning' object of an earlier line)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain copy of this many MiB first (counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the fp64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=16)
@@ -286,7 +349,10 @@ def main():
     import workloads
     wl = workloads.C2
     prec = 1 if args.precision == "mixed" else 0
-    main_run = run_gpu(wl, prec, args.steps, args.warmup, args.batch, profile=True, autotune=not args.no_autotune)
+    tuning = json.loads(args.tuning) if args.tuning else None
+    main_run = run_gpu(wl, prec, args.steps, args.warmup, args.batch, profile=True,
+                       autotune=not args.no_autotune and tuning is None, tuning=tuning,
+                       probe_mib=args.copy_probe_mib)
     fp64 = None
     if prec == 1 and not args.no_fp64:
         fp64 = run_gpu(wl, 0, max(1, args.steps // 2), 1, args.batch, profile=False)

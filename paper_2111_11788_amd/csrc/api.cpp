@@ -75,6 +75,7 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   if (e != hipSuccess) {
     g_create_error = std::string("HIP error during create: ") + hipGetErrorString(e);
     if (ctx->h_nactive) hipHostFree(ctx->h_nactive);
+  if (ctx->prof_counts) hipFree(ctx->prof_counts);
     if (ctx->own_stream) hipStreamDestroy(ctx->st);
     delete ctx;
     return MLMC_E_DEVICE;
@@ -97,6 +98,7 @@ void mlmc_destroy(mlmc_ctx* ctx) {
   ctx->bw.wf.release_graphs();
   ctx->bw.wc.release_graphs();
   if (ctx->h_nactive) hipHostFree(ctx->h_nactive);
+  if (ctx->prof_counts) hipFree(ctx->prof_counts);
   if (ctx->own_stream) hipStreamDestroy(ctx->st);
   delete ctx;
 }
@@ -381,6 +383,8 @@ int mlmc_set_profiling(mlmc_ctx* ctx, int32_t on) {
     ctx->event_pool.push_back(r.b);
   }
   ctx->prof.clear();
+  ctx->prof_used = 0;
+  if (on && !ctx->prof_counts) HIPCHK(hipMalloc(&ctx->prof_counts, mlmc_ctx::kProfCap * sizeof(int)));
   std::fill(std::begin(ctx->k_launch), std::end(ctx->k_launch), 0);
   std::fill(std::begin(ctx->k_ms), std::end(ctx->k_ms), 0.0);
   std::fill(std::begin(ctx->k_bytes), std::end(ctx->k_bytes), 0.0);
@@ -392,12 +396,17 @@ int mlmc_kernel_time(mlmc_ctx* ctx, int32_t kernel_id, int32_t precision, int64_
                      double* bytes) {
   if (!ctx || kernel_id < 0 || kernel_id >= MLMC_K_COUNT || precision < 0 || precision > 1) return MLMC_E_INVALID;
   HIPCHK(hipStreamSynchronize(ctx->st));
+  std::vector<int> cnt(ctx->prof_used);
+  if (ctx->prof_used)
+    HIPCHK(hipMemcpy(cnt.data(), ctx->prof_counts, cnt.size() * sizeof(int), hipMemcpyDeviceToHost));
+  ctx->prof_used = 0;
   for (auto& r : ctx->prof) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
     ctx->k_launch[r.id] += 1;
     ctx->k_ms[r.id] += ms;
-    ctx->k_bytes[r.id] += r.bytes;
+    // masked launches: only the active samples' bytes move
+    ctx->k_bytes[r.id] += r.cnt >= 0 && r.B > 0 ? r.bytes * cnt[r.cnt] / r.B : r.bytes;
     ctx->event_pool.push_back(r.a);
     ctx->event_pool.push_back(r.b);
   }

@@ -154,7 +154,7 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
   hipStream_t st = ctx->st;
   const int var = zv<T>(ctx);
   if (n == 2) {
-    LAUNCH(kid<T>(MLMC_K_COARSEST), B * (8 + 2) * sz, launch_coarsest<T>(B, L[l].kap, b, x, active, st));
+    LAUNCHM(kid<T>(MLMC_K_COARSEST), B * (8 + 2) * sz, active, B, launch_coarsest<T>(B, L[l].kap, b, x, active, st));
     *result = x;
     if (dot) FAIL(MLMC_E_INVALID, "fused r.z needs a mesh n >= 4");
     return MLMC_OK;
@@ -166,34 +166,34 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
     // the rest of the V-cycle in one kernel (coarse data in LDS)
     const T* kl[4] = {nullptr, nullptr, nullptr, nullptr};
     for (size_t q = l; q < L.size() && q - l < 4; ++q) kl[q - l] = L[q].kap;
-    LAUNCH(kid<T>(MLMC_K_COARSEST), (2 * d + e * 8.0 / 7.0) * sz,
+    LAUNCHM(kid<T>(MLMC_K_COARSEST), (2 * d + e * 8.0 / 7.0) * sz, active, B,
            launch_vsmall<T>(n, B, ch.degree, ch.c1, ch.c2, kl, b, x, active, st));
     *result = x;
     return MLMC_OK;
   }
-  LAUNCH(kid<T>(MLMC_K_CHEB_ZERO), (2 * d + e) * sz,
+  LAUNCHM(kid<T>(MLMC_K_CHEB_ZERO), (2 * d + e) * sz, active, B,
          launch_cheb<T>(n, B, kap, b, nullptr, nullptr, x, 0.0, ch.c2[0], true, false, active, st, nullptr, nullptr,
                         var));
   T* cur = x;
   T* oth = xo;
   for (int s = 1; s < ch.degree; ++s) {
     const bool use_xo = s > 1;
-    LAUNCH(kid<T>(use_xo ? MLMC_K_CHEB_XO : MLMC_K_CHEB), ((use_xo ? 4 : 3) * d + e) * sz,
+    LAUNCHM(kid<T>(use_xo ? MLMC_K_CHEB_XO : MLMC_K_CHEB), ((use_xo ? 4 : 3) * d + e) * sz, active, B,
            launch_cheb<T>(n, B, kap, b, cur, oth, oth, ch.c1[s], ch.c2[s], false, use_xo, active, st, nullptr,
                           nullptr, var));
     std::swap(cur, oth);
   }
-  LAUNCH(kid<T>(MLMC_K_RESIDUAL), (3 * d + e) * sz, launch_residual<T>(n, B, kap, b, cur, t, active, st, var));
+  LAUNCHM(kid<T>(MLMC_K_RESIDUAL), (3 * d + e) * sz, active, B, launch_residual<T>(n, B, kap, b, cur, t, active, st, var));
   Level<T>& nx = L[l + 1];
   const double dc = dofs(n / 2) * B;
-  LAUNCH(kid<T>(MLMC_K_RESTRICT), (d + dc) * sz, launch_restrict<T>(n, B, t, nx.b, active, st));
+  LAUNCHM(kid<T>(MLMC_K_RESTRICT), (d + dc) * sz, active, B, launch_restrict<T>(n, B, t, nx.b, active, st));
   T* xc = nullptr;
   if (int rc = vcycle<T>(ctx, L, l + 1, B, nx.b, nx.x, nx.xo, nx.t, active, &xc)) return rc;
-  LAUNCH(kid<T>(MLMC_K_PROLONG), (2 * d + dc) * sz, launch_prolong_add<T>(n, B, xc, cur, active, st));
+  LAUNCHM(kid<T>(MLMC_K_PROLONG), (2 * d + dc) * sz, active, B, launch_prolong_add<T>(n, B, xc, cur, active, st));
   for (int s = 0; s < ch.degree; ++s) {
     const bool use_xo = s > 0;
     const bool last = s == ch.degree - 1;
-    LAUNCH(kid<T>(use_xo ? MLMC_K_CHEB_XO : MLMC_K_CHEB), ((use_xo ? 4 : 3) * d + e) * sz,
+    LAUNCHM(kid<T>(use_xo ? MLMC_K_CHEB_XO : MLMC_K_CHEB), ((use_xo ? 4 : 3) * d + e) * sz, active, B,
            launch_cheb<T>(n, B, kap, b, cur, oth, oth, s == 0 ? 0.0 : ch.c1[s], ch.c2[s], false, use_xo, active, st,
                           last ? dot : nullptr, last ? dot_np : nullptr, var));
     std::swap(cur, oth);
@@ -212,7 +212,7 @@ int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T**
   if (L.size() == 1 || n == 2) {
     if (n == 2) return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, S.active, z);
     // Jacobi: z = D^-1 r
-    LAUNCH(kid<T>(MLMC_K_CHEB_ZERO), (2 * dofs(n) + elems(n)) * B * sizeof(T),
+    LAUNCHM(kid<T>(MLMC_K_CHEB_ZERO), (2 * dofs(n) + elems(n)) * B * sizeof(T), S.active, B,
            launch_cheb<T>(n, B, L[0].kap, r, nullptr, nullptr, L[0].x, 0.0, 1.0, true, false, S.active, ctx->st,
                           nullptr, nullptr, zv<T>(ctx)));
     *z = L[0].x;
@@ -243,14 +243,14 @@ int pcg_iteration(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S,
   const int var = zv<T>(ctx);
   uint32_t np = 0;
   T* z = nullptr;
-  LAUNCH(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, &np, st, var));
+  LAUNCHM(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, S.active, B, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, &np, st, var));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA, 0.0, np, S, nullptr, st));
-  LAUNCH(kid<T>(MLMC_K_PCG_UPDATE), 6 * d * sz, launch_pcg_update<T>(n, B, x, p, r, q, S, &np, st));
+  LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE), 6 * d * sz, S.active, B, launch_pcg_update<T>(n, B, x, p, r, q, S, &np, st));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, rr_op, tol2, np, S, nullptr, st));
   if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
-  if (!np) LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
+  if (!np) LAUNCHM(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, S.active, B, (launch_dot<T>(n, B, r, z, S, &np, st)));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BETA, 0.0, np, S, nullptr, st));
-  LAUNCH(kid<T>(MLMC_K_PCG_DIRECTION), 3 * d * sz, launch_pcg_direction<T>(n, B, z, p, S, st));
+  LAUNCHM(kid<T>(MLMC_K_PCG_DIRECTION), 3 * d * sz, S.active, B, launch_pcg_direction<T>(n, B, z, p, S, st));
   if (count) {
     LAUNCH(MLMC_K_MISC, 0, launch_count_active(B, S, st));
     HIPCHK(hipMemcpyAsync(ctx->h_nactive, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -270,9 +270,9 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
   uint32_t np = 0;
   T* z = nullptr;
   if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
-  if (!np) LAUNCH(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, (launch_dot<T>(n, B, r, z, S, &np, st)));
+  if (!np) LAUNCHM(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, S.active, B, (launch_dot<T>(n, B, r, z, S, &np, st)));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RZ_INIT, 0.0, np, S, nullptr, st));
-  LAUNCH(kid<T>(MLMC_K_PCG_DIRECTION), 2 * d * sz, launch_copy<T>(n, B, z, p, S, st));
+  LAUNCHM(kid<T>(MLMC_K_PCG_DIRECTION), 2 * d * sz, S.active, B, launch_copy<T>(n, B, z, p, S, st));
   const double tol2 = tol * tol;
   const bool use_graph = graph && ctx->use_graphs && !ctx->profiling;
   if (use_graph && !*graph) {
@@ -339,7 +339,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       total_it += it;
       // confirm with the true residual; samples above tolerance continue
       LAUNCH(MLMC_K_MISC, 0, launch_set_active(B, O, 1, st));
-      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r, O, &np, st, zv<double>(ctx)));
+      LAUNCHM(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, O.active, B, launch_true_residual(n, B, kap, h3, u, w.r, O, &np, st, zv<double>(ctx)));
       LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
       int na = 0;
       if (int rc = count_active(ctx, O, B, &na)) return rc;
@@ -359,18 +359,18 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
     LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
     HIPCHK(hipMemsetAsync(I.iters, 0, B * sizeof(int), st));
     for (int outer = 0; outer < kMaxOuter && total_it < ctx->cfg.max_iter; ++outer) {
-      LAUNCH(MLMC_K_MISC, d * 12, launch_demote(n, B, w.r64, w.rin, O, st));
+      LAUNCHM(MLMC_K_MISC, d * 12, O.active, B, launch_demote(n, B, w.r64, w.rin, O, st));
       HIPCHK(hipMemcpyAsync(I.active, O.active, B * sizeof(int), hipMemcpyDeviceToDevice, st));
-      LAUNCH(MLMC_K_MISC, d * 4, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
-      LAUNCH(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, (launch_dot<float>(n, B, w.rin, w.rin, I, &np, st)));
+      LAUNCHM(MLMC_K_MISC, d * 4, O.active, B, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
+      LAUNCHM(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, I.active, B, (launch_dot<float>(n, B, w.rin, w.rin, I, &np, st)));
       LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, I, nullptr, st));
       int it = 0;
       if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it, &it,
                              &w.iter_exec[1]))
         return rc;
       total_it += it;
-      LAUNCH(MLMC_K_MISC, d * 20, launch_add_correction(n, B, u, w.d, O, st));
-      LAUNCH(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, launch_true_residual(n, B, kap, h3, u, w.r64, O, &np, st, zv<double>(ctx)));
+      LAUNCHM(MLMC_K_MISC, d * 20, O.active, B, launch_add_correction(n, B, u, w.d, O, st));
+      LAUNCHM(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, O.active, B, launch_true_residual(n, B, kap, h3, u, w.r64, O, &np, st, zv<double>(ctx)));
       LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
       int na = 0;
       if (int rc = count_active(ctx, O, B, &na)) return rc;

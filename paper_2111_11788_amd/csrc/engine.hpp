@@ -170,10 +170,13 @@ struct BatchWork {
   SolveWork wf, wc;
 };
 
+// One timed launch.  `cnt` >= 0 indexes the device count of active samples
+// taken just before a masked launch: its bytes count the active share only.
 struct ProfRec {
   int id;
   hipEvent_t a, b;
   double bytes;
+  int cnt, B;
 };
 
 struct Running {
@@ -216,6 +219,9 @@ struct mlmc_ctx {
   bool profiling = false;
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> event_pool;
+  int* prof_counts = nullptr;     // device: active-sample counts of masked timed launches
+  int prof_used = 0;
+  static constexpr int kProfCap = 1 << 16;
   int64_t k_launch[2 * MLMC_K_COUNT] = {0};   // [precision][kernel]
   double k_ms[2 * MLMC_K_COUNT] = {0}, k_bytes[2 * MLMC_K_COUNT] = {0};
   int* h_nactive = nullptr;
@@ -248,9 +254,18 @@ namespace eng {
 hipEvent_t take_event(mlmc_ctx* ctx);
 
 template <class F>
-int launch(mlmc_ctx* ctx, int id, double bytes, F&& f) {
+int launch(mlmc_ctx* ctx, int id, double bytes, const int* mask, int B, F&& f) {
   hipEvent_t a = nullptr, b = nullptr;
+  int cnt = -1;
   if (ctx->profiling) {
+    if (mask && ctx->prof_counts && ctx->prof_used < mlmc_ctx::kProfCap) {
+      cnt = ctx->prof_used++;
+      const hipError_t ec = launch_count_mask(mask, B, ctx->prof_counts + cnt, ctx->st);
+      if (ec != hipSuccess) {
+        ctx->err = std::string("kernel launch failed: ") + hipGetErrorString(ec);
+        return MLMC_E_DEVICE;
+      }
+    }
     a = take_event(ctx);
     b = take_event(ctx);
     hipEventRecord(a, ctx->st);
@@ -262,7 +277,7 @@ int launch(mlmc_ctx* ctx, int id, double bytes, F&& f) {
   }
   if (ctx->profiling) {
     hipEventRecord(b, ctx->st);
-    ctx->prof.push_back(ProfRec{id, a, b, bytes});
+    ctx->prof.push_back(ProfRec{id, a, b, bytes, cnt, B});
   }
   return MLMC_OK;
 }
@@ -272,7 +287,14 @@ int launch(mlmc_ctx* ctx, int id, double bytes, F&& f) {
 
 #define LAUNCH(id, bytes, call)                          \
   do {                                                   \
-    int rc_ = launch(ctx, (id), (double)(bytes), [&] { return (call); }); \
+    int rc_ = launch(ctx, (id), (double)(bytes), nullptr, 0, [&] { return (call); }); \
+    if (rc_) return rc_;                                 \
+  } while (0)
+
+// A launch whose kernel skips the samples with mask[b] == 0 (B samples).
+#define LAUNCHM(id, bytes, mask, nb, call)               \
+  do {                                                   \
+    int rc_ = launch(ctx, (id), (double)(bytes), (mask), (nb), [&] { return (call); }); \
     if (rc_) return rc_;                                 \
   } while (0)
 

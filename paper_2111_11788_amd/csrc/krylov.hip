@@ -287,6 +287,13 @@ __global__ void k_count_active(int B, SolveState st) {
   if (threadIdx.x == 0) *st.nactive = v;
 }
 
+__global__ void k_count_mask(const int* __restrict__ mask, int B, int* __restrict__ out) {
+  int v = 0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) v += mask[b] != 0;
+  v = (int)block_sum((double)v);
+  if (threadIdx.x == 0) *out = v;
+}
+
 __global__ void k_set_active(int B, SolveState st, int value) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < B) st.active[b] = value;
@@ -354,6 +361,11 @@ hipError_t launch_reduce(int B, int op, double tol2, uint32_t nparts, SolveState
 
 hipError_t launch_count_active(int B, SolveState s, hipStream_t st) {
   k_count_active<<<1, kBlock, 0, st>>>(B, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_mask(const int* mask, int B, int* out, hipStream_t st) {
+  k_count_mask<<<1, kBlock, 0, st>>>(mask, B, out);
   return hipGetLastError();
 }
 
