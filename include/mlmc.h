@@ -308,7 +308,8 @@ int mlmc_serve_stats(mlmc_ctx* ctx, mlmc_serve_stats_out* out);
 /* Enable (1) or disable (0) per-kernel event timing on the context stream
  * (clears the counters), and read the launch count, total event-timed
  * milliseconds and total algorithmic bytes (bytes a kernel must move at
- * minimum: every distinct vector read or written once) of kernel `kernel_id`
+ * minimum: every distinct vector read or written once, for the samples still
+ * active when the kernel was launched) of kernel `kernel_id`
  * (MLMC_K_*) in `precision` (0: fp64 instance, 1: fp32 instance) since
  * timing was enabled. */
 enum {

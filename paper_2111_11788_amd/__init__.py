@@ -62,6 +62,14 @@ class SampleResult(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+# the same record as a NumPy dtype (C alignment), for draining many results at once
+SAMPLE_RESULT_DTYPE = np.dtype([("ticket", np.uint64), ("status", np.int32), ("level", np.int32),
+                                ("sample", np.uint64), ("y", np.float64), ("q_fine", np.float64),
+                                ("q_coarse", np.float64), ("iters", np.int32), ("latency_s", np.float64),
+                                ("queue_s", np.float64)], align=True)
+assert SAMPLE_RESULT_DTYPE.itemsize == ctypes.sizeof(SampleResult)
+
+
 class ServeStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint64), ("sample_dofs", ctypes.c_double), ("busy_seconds", ctypes.c_double),
                 ("queued", ctypes.c_int32), ("running", ctypes.c_int32), ("slots", ctypes.c_int32 * 16),
@@ -336,6 +344,13 @@ class Context:
         n = ctypes.c_int32()
         self._check(lib().mlmc_drain(self.h, buf, max_results, ctypes.byref(n), timeout))
         return [buf[i].as_dict() for i in range(n.value)]
+
+    def drain_array(self, max_results: int = 16384, timeout: float = 0.0) -> np.ndarray:
+        """Like drain, as a structured array of SAMPLE_RESULT_DTYPE (no per-result Python objects)."""
+        buf = np.empty(max_results, dtype=SAMPLE_RESULT_DTYPE)
+        n = ctypes.c_int32()
+        self._check(lib().mlmc_drain(self.h, buf.ctypes.data, max_results, ctypes.byref(n), timeout))
+        return buf[:n.value].copy()
 
     def wait(self, tickets, timeout: float = 120.0):
         """Drain until every ticket is done; returns {ticket: result}."""

@@ -56,6 +56,7 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   cv.dry = false;
   ctx->d_sqrtlam = cv.take<double>(cfg->n_modes);
   ctx->d_triples = cv.take<int>(3 * (size_t)cfg->n_modes);
+  ctx->prof_counts = cv.take<int>(mlmc_ctx::kProfCap);
   std::vector<double> sq(cfg->n_modes);
   for (int m = 0; m < cfg->n_modes; ++m) sq[m] = std::sqrt(ctx->modes.lambda[m]);
   hipError_t e = hipMemcpyAsync(ctx->d_sqrtlam, sq.data(), sq.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st);
@@ -75,7 +76,6 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   if (e != hipSuccess) {
     g_create_error = std::string("HIP error during create: ") + hipGetErrorString(e);
     if (ctx->h_nactive) hipHostFree(ctx->h_nactive);
-  if (ctx->prof_counts) hipFree(ctx->prof_counts);
     if (ctx->own_stream) hipStreamDestroy(ctx->st);
     delete ctx;
     return MLMC_E_DEVICE;
@@ -98,7 +98,6 @@ void mlmc_destroy(mlmc_ctx* ctx) {
   ctx->bw.wf.release_graphs();
   ctx->bw.wc.release_graphs();
   if (ctx->h_nactive) hipHostFree(ctx->h_nactive);
-  if (ctx->prof_counts) hipFree(ctx->prof_counts);
   if (ctx->own_stream) hipStreamDestroy(ctx->st);
   delete ctx;
 }
@@ -384,7 +383,6 @@ int mlmc_set_profiling(mlmc_ctx* ctx, int32_t on) {
   }
   ctx->prof.clear();
   ctx->prof_used = 0;
-  if (on && !ctx->prof_counts) HIPCHK(hipMalloc(&ctx->prof_counts, mlmc_ctx::kProfCap * sizeof(int)));
   std::fill(std::begin(ctx->k_launch), std::end(ctx->k_launch), 0);
   std::fill(std::begin(ctx->k_ms), std::end(ctx->k_ms), 0.0);
   std::fill(std::begin(ctx->k_bytes), std::end(ctx->k_bytes), 0.0);

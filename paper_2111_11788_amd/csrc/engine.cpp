@@ -50,6 +50,7 @@ size_t persistent_bytes(const mlmc_config* c, int K1) {
   Carver cv;
   cv.take<double>(c->n_modes);
   cv.take<int>(3 * (size_t)c->n_modes);
+  cv.take<int>(mlmc_ctx::kProfCap);
   for (int l = 0; l < c->levels; ++l) cv.take<double>((size_t)(c->n0 << l) * K1);
   return cv.top;
 }

@@ -219,7 +219,7 @@ struct mlmc_ctx {
   bool profiling = false;
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> event_pool;
-  int* prof_counts = nullptr;     // device: active-sample counts of masked timed launches
+  int* prof_counts = nullptr;     // device (persistent arena): active-sample counts of masked timed launches
   int prof_used = 0;
   static constexpr int kProfCap = 1 << 16;
   int64_t k_launch[2 * MLMC_K_COUNT] = {0};   // [precision][kernel]

@@ -78,3 +78,26 @@ def test_budget_refusal_and_stop(dev):
     ctx.serve_stop()
     y, _, _, _ = ctx.sample_level(0, 0, 2)   # and work again afterwards
     assert np.all(np.isfinite(y))
+
+
+def test_submit_batch_and_drain_array_match_single_submits(dev):
+    wl = _wl()
+    ctx = mm.Context(wl, arena_bytes=1 << 30)
+    ctx.serve_start([8, 8, 4])
+    levels = np.array([0, 1, 2, 1, 0, 2, 0], dtype=np.int32)
+    samples = np.array([40, 41, 42, 43, 44, 45, 46], dtype=np.uint64)
+    tk = ctx.submit_batch(levels, samples)
+    assert len(set(int(t) for t in tk)) == len(tk)
+    got = []
+    while sum(len(g) for g in got) < len(tk):
+        got.append(ctx.drain_array(timeout=0.05))
+    arr = np.concatenate(got)
+    assert sorted(int(t) for t in arr["ticket"]) == sorted(int(t) for t in tk)
+    # the same samples one at a time give the same bits
+    single = ctx.wait([ctx.submit(int(l), int(s)) for l, s in zip(levels, samples)])
+    ctx.serve_stop()
+    by_sample = {(int(r["level"]), int(r["sample"])): r for r in single.values()}
+    for r in arr:
+        s = by_sample[(int(r["level"]), int(r["sample"]))]
+        assert r["status"] == 0 and s["status"] == 0
+        assert r["y"] == s["y"] and r["q_fine"] == s["q_fine"] and r["iters"] == s["iters"]
