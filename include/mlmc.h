@@ -217,8 +217,14 @@ typedef struct mlmc_tuning {
   int32_t cheb_degree;    /* Chebyshev smoothing degree per half V-cycle, 1..8 */
   int32_t max_batch;      /* samples per batched solve */
   int32_t graph_batch;    /* captured PCG iterations replayed per convergence check (0: no graphs) */
+  int32_t fuse;           /* MLMC_FUSE_* bits: kernel fusions in use (default: all) */
   double seconds;         /* mlmc_autotune: measured seconds per sample of the chosen setting */
 } mlmc_tuning;
+
+/* Fusion bits of mlmc_tuning.fuse. */
+enum {
+  MLMC_FUSE_PROLONG = 1   /* coarse-grid correction applied inside the first post-smoothing step */
+};
 
 int mlmc_get_tuning(const mlmc_ctx* ctx, mlmc_tuning* out);
 /* Errors: MLMC_E_INVALID for a value out of range. */
@@ -316,7 +322,7 @@ enum {
   MLMC_K_XI = 0, MLMC_K_FIELD, MLMC_K_APPLY, MLMC_K_CHEB_ZERO, MLMC_K_CHEB, MLMC_K_CHEB_XO,
   MLMC_K_RESIDUAL, MLMC_K_RESTRICT, MLMC_K_PROLONG, MLMC_K_COARSEST, MLMC_K_COARSEN,
   MLMC_K_PCG_APPLY, MLMC_K_PCG_UPDATE, MLMC_K_PCG_DOT, MLMC_K_PCG_DIRECTION,
-  MLMC_K_TRUE_RESIDUAL, MLMC_K_REDUCE, MLMC_K_QOI, MLMC_K_MISC, MLMC_K_COUNT
+  MLMC_K_TRUE_RESIDUAL, MLMC_K_REDUCE, MLMC_K_QOI, MLMC_K_MISC, MLMC_K_CHEB_PROLONG, MLMC_K_COUNT
 };
 int mlmc_set_profiling(mlmc_ctx* ctx, int32_t on);
 int mlmc_kernel_time(mlmc_ctx* ctx, int32_t kernel_id, int32_t precision, int64_t* launches,

@@ -22,7 +22,7 @@ ERRORS = {-1: "MLMC_E_INVALID", -2: "MLMC_E_NOMEM", -3: "MLMC_E_BUDGET", -4: "ML
           -5: "MLMC_E_NONFINITE", -6: "MLMC_E_DEVICE"}
 KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "RESTRICT", "PROLONG",
            "COARSEST", "COARSEN", "PCG_APPLY", "PCG_UPDATE", "PCG_DOT", "PCG_DIRECTION", "TRUE_RESIDUAL",
-           "REDUCE", "QOI", "MISC"]
+           "REDUCE", "QOI", "MISC", "CHEB_PROLONG"]
 
 # exported symbols of include/mlmc.h (checked by the CPU test suite)
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
@@ -79,7 +79,7 @@ class ServeStats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("zvar_fp32", ctypes.c_int32), ("zvar_fp64", ctypes.c_int32), ("vsmall_fp32", ctypes.c_int32),
                 ("vsmall_fp64", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("graph_batch", ctypes.c_int32), ("seconds", ctypes.c_double)]
+                ("graph_batch", ctypes.c_int32), ("fuse", ctypes.c_int32), ("seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -190,8 +190,23 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
   LAUNCHM(kid<T>(MLMC_K_RESTRICT), (d + dc) * sz, active, B, launch_restrict<T>(n, B, t, nx.b, active, st));
   T* xc = nullptr;
   if (int rc = vcycle<T>(ctx, L, l + 1, B, nx.b, nx.x, nx.xo, nx.t, active, &xc)) return rc;
-  LAUNCHM(kid<T>(MLMC_K_PROLONG), (2 * d + dc) * sz, active, B, launch_prolong_add<T>(n, B, xc, cur, active, st));
-  for (int s = 0; s < ch.degree; ++s) {
+  int s0 = 0;
+  if (ctx->fuse & MLMC_FUSE_PROLONG) {
+    // first post-smoothing step reads cur + P xc; with more steps to come the
+    // corrected iterate is kept in t (free after the restriction) as their
+    // previous iterate
+    const bool last = ch.degree == 1;
+    T* save = last ? nullptr : t;
+    LAUNCHM(kid<T>(MLMC_K_CHEB_PROLONG), ((last ? 3 : 4) * d + dc + e) * sz, active, B,
+            launch_cheb_prolong<T>(n, B, kap, b, cur, xc, oth, save, ch.c2[0], active, st, last ? dot : nullptr,
+                                   last ? dot_np : nullptr));
+    cur = oth;
+    oth = t;
+    s0 = 1;
+  } else {
+    LAUNCHM(kid<T>(MLMC_K_PROLONG), (2 * d + dc) * sz, active, B, launch_prolong_add<T>(n, B, xc, cur, active, st));
+  }
+  for (int s = s0; s < ch.degree; ++s) {
     const bool use_xo = s > 0;
     const bool last = s == ch.degree - 1;
     LAUNCHM(kid<T>(use_xo ? MLMC_K_CHEB_XO : MLMC_K_CHEB), ((use_xo ? 4 : 3) * d + e) * sz, active, B,
@@ -458,6 +473,7 @@ int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (t->cheb_degree < 1 || t->cheb_degree > 8) { why = "cheb_degree must be in 1..8"; return MLMC_E_INVALID; }
   if (t->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
   if (t->graph_batch < 0 || t->graph_batch > 16) { why = "graph_batch must be in 0..16"; return MLMC_E_INVALID; }
+  if (t->fuse & ~MLMC_FUSE_PROLONG) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
   return MLMC_OK;
 }
 
@@ -470,6 +486,7 @@ mlmc_tuning current_tuning(const mlmc_ctx* ctx) {
   t.cheb_degree = ctx->cheb.degree;
   t.max_batch = ctx->cfg.max_batch;
   t.graph_batch = ctx->use_graphs ? ctx->graph_batch : 0;
+  t.fuse = ctx->fuse;
   t.seconds = 0.0;
   return t;
 }
@@ -486,6 +503,7 @@ void apply_tuning(mlmc_ctx* ctx, const mlmc_tuning& t) {
   ctx->cfg.max_batch = t.max_batch;
   ctx->use_graphs = t.graph_batch > 0;
   ctx->graph_batch = std::max(1, t.graph_batch);
+  ctx->fuse = t.fuse;
   // captured graphs bake in kernel choices: drop them
   ctx->sw.release_graphs();
   ctx->bw.wf.release_graphs();

@@ -57,6 +57,14 @@ hipError_t launch_cheb(int n, int B, const T* kap, const T* b, const T* x, const
                        double c1, double c2, bool zero_x, bool use_xo, const int* active,
                        hipStream_t st, SolveState* dot = nullptr, uint32_t* nparts = nullptr,
                        int var = 0);
+// First post-smoothing step fused with the coarse-grid correction:
+// out = y + c2 D^-1 (b - A y) with y = x + P xc (xc on the n/2 mesh, P the
+// trilinear prolongation), n >= 4.  save (may be null) receives y.  out and
+// save must not alias x, xc or each other.  `dot` as in launch_cheb.
+template <class T>
+hipError_t launch_cheb_prolong(int n, int B, const T* kap, const T* b, const T* x, const T* xc, T* out, T* save,
+                               double c2, const int* active, hipStream_t st, SolveState* dot = nullptr,
+                               uint32_t* nparts = nullptr);
 template <class T>
 hipError_t launch_restrict(int nf, int B, const T* rf, T* bc, const int* active, hipStream_t st);
 template <class T>

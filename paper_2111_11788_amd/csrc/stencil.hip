@@ -103,6 +103,8 @@ struct EpiResidual {
 // out = x + c1 (x - xo) + c2 D^-1 (b - A x); without xo the previous iterate is
 // 0.  DOT also accumulates b . out (the r . z of the enclosing PCG when this is
 // the last smoothing step of the finest level).
+// `save` (may be null) receives the iterate the step started from (used when
+// that iterate was formed on the fly, see PRO below).
 template <class T, int V, bool USE_XO, bool DOT>
 struct EpiCheb {
   static constexpr bool kReduce = DOT;
@@ -110,6 +112,7 @@ struct EpiCheb {
   const T* xo;
   T* out;
   T c1, c2;
+  T* save = nullptr;
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
     T bv[V], xov[V], o[V];
     vload<T, V>(b + pos, bv);
@@ -121,6 +124,12 @@ struct EpiCheb {
       if (DOT) acc += (double)bv[v] * (double)o[v];
     }
     vstore<T, V>(out + pos, o);
+    if (save) {
+      T sv[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) sv[v] = ok[v] ? uc[v] : T(0);
+      vstore<T, V>(save + pos, sv);
+    }
   }
 };
 
@@ -173,13 +182,29 @@ struct EpiChebZero {
   }
 };
 
+// N consecutive values (N = 1 or an aligned vector)
+template <class T, int N>
+__device__ __forceinline__ void nload(const T* p, T* dst) {
+  if constexpr (N == 1) dst[0] = *p;
+  else vload<T, N>(p, dst);
+}
+
 // --------------------------------------------------------- z-march engine
 // PF: issue the loads of the next plane step before computing the current one
 // (one more plane of registers, more memory-level parallelism per wave).
-template <class T, int V, bool NEED_U, bool PF, class Epi>
+// PRO: the operand is u + P xc, with xc on the n/2 mesh (stride cstride) and P
+// the trilinear prolongation: the coarse-grid correction of a V-cycle is
+// applied while its first post-smoothing step reads the iterate, instead of
+// by a separate pass that reads and writes the fine vector.  A sliding window
+// of two coarse planes x three coarse rows (the parents of the thread's three
+// fine rows) is kept in registers; a new coarse plane is loaded every second
+// fine plane.
+template <class T, int V, bool NEED_U, bool PF, bool PRO, class Epi>
 __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, const T* __restrict__ u,
                                                 const T* __restrict__ kap, const int* __restrict__ active,
-                                                double* __restrict__ partial, uint32_t pstride, Epi epi) {
+                                                double* __restrict__ partial, uint32_t pstride, Epi epi,
+                                                const T* __restrict__ xc, size_t cstride) {
+  static_assert(!(PRO && (PF || !NEED_U)), "the fused prolongation uses the plain u window");
   const uint32_t per = g.parts();
   const uint32_t lin = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t b = lin / per;
@@ -216,11 +241,80 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
       dst[0] = i0 > 0 ? row[i0 - 1] : T(0);
       vload<T, V>(row + i0, dst + 1);
     };
+    // ---- fused prolongation (PRO)
+    // Coarse values I0-1 .. I0+V/2 (I0 = i0/2) of coarse rows JA .. JA+2,
+    // JA = (j-1)/2 rounded down; the third row is needed only for even j.
+    // Fine row j-1+r, fine plane kk: even index -> one coarse line, odd ->
+    // the mean of two; positions outside the interior read coarse zeros.
+    constexpr int CW = V / 2 + 2;
+    T C[2][3][PRO ? CW : 1];
+    int cK = 0;
+    const int nc = n >> 1, nc2 = nc * nc;
+    const bool jodd = (j & 1) != 0;
+    const int JA = (j - 1) >> 1;
+    const T* cb = PRO ? xc + (size_t)b * cstride : nullptr;
+    auto load_cplane = [&](int slot, int K) {
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        T* dst = C[slot][s];
+        if (K > nc || (s == 2 && jodd)) {
+#pragma unroll
+          for (int q = 0; q < CW; ++q) dst[q] = T(0);
+          continue;
+        }
+        const T* row = cb + (size_t)nc * (JA + s) + (size_t)nc2 * K + (i0 >> 1);
+        dst[0] = i0 > 0 ? row[-1] : T(0);
+        nload<T, V / 2>(row, dst + 1);
+        dst[V / 2 + 1] = row[V / 2];
+      }
+    };
+    auto cshift = [&](int kk) {   // make the window hold coarse planes kk/2 and kk/2 + 1
+      if ((kk >> 1) > cK) {
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+          for (int q = 0; q < CW; ++q) C[0][s][q] = C[1][s][q];
+        ++cK;
+        load_cplane(1, cK + 1);
+      }
+    };
+    auto add_pro = [&](T (*rows)[V + 2], int kk) {   // rows[r] += (P xc)(row j-1+r, plane kk)
+      const bool kodd = (kk & 1) != 0;
+      T P[3][CW];
+#pragma unroll
+      for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int q = 0; q < CW; ++q) P[s][q] = kodd ? T(0.5) * (C[0][s][q] + C[1][s][q]) : C[0][s][q];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        T L[CW];
+#pragma unroll
+        for (int q = 0; q < CW; ++q) {
+          const T mid01 = T(0.5) * (P[0][q] + P[1][q]), mid12 = T(0.5) * (P[1][q] + P[2][q]);
+          const T a = r == 0 ? P[0][q] : (r == 1 ? mid01 : P[1][q]);    // j odd
+          const T c = r == 0 ? mid01 : (r == 1 ? P[1][q] : mid12);      // j even
+          L[q] = jodd ? a : c;
+        }
+#pragma unroll
+        for (int t = 0; t < V + 2; ++t)
+          rows[r][t] += (t & 1) ? L[(t + 1) / 2] : T(0.5) * (L[t / 2] + L[t / 2 + 1]);
+      }
+    };
+    if (PRO) {
+      cK = (k0 - 1) >> 1;
+      load_cplane(0, cK);
+      load_cplane(1, cK + 1);
+    }
     if (NEED_U) {
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         load_urow(U[0][r], r, k0 - 1);
         load_urow(U[1][r], r, k0);
+      }
+      if (PRO) {
+        add_pro(U[0], k0 - 1);
+        cshift(k0);
+        add_pro(U[1], k0);
       }
     }
 #pragma unroll
@@ -252,9 +346,14 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
           for (int r = 0; r < 2; ++r) load_krow(PK[r], r, k + 1);
         }
       } else {
-        if (NEED_U)
+        if (NEED_U) {
 #pragma unroll
           for (int r = 0; r < 3; ++r) load_urow(U[2][r], r, k + 1);
+          if (PRO) {
+            cshift(k + 1);
+            add_pro(U[2], k + 1);
+          }
+        }
 #pragma unroll
         for (int r = 0; r < 2; ++r) load_krow(K[1][r], r, k);
       }
@@ -310,11 +409,24 @@ hipError_t zlaunch(int n, int B, const T* u, const T* kap, const int* active, do
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
   if (var & ZVAR_PREFETCH)
-    k_zmarch<T, V, NEED_U, true, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
-        g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi);
+    k_zmarch<T, V, NEED_U, true, false, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
+        g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, nullptr, 0);
   else
-    k_zmarch<T, V, NEED_U, false, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
-        g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi);
+    k_zmarch<T, V, NEED_U, false, false, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
+        g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, nullptr, 0);
+  return hipGetLastError();
+}
+
+// the operand is u + P xc (xc on the n/2 mesh); plain window only
+template <class T, class Epi>
+hipError_t zlaunch_pro(int n, int B, const T* u, const T* xc, const T* kap, const int* active, double* partial,
+                       uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st) {
+  constexpr int V = ZV<T>::V;
+  const ZGeom g = zgeom<T>(n, B);
+  if (nparts) *nparts = g.parts();
+  const uint32_t blocks = g.parts() * (uint32_t)B;
+  k_zmarch<T, V, true, false, true, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
+      g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, grid_stride(n / 2));
   return hipGetLastError();
 }
 
@@ -575,6 +687,18 @@ hipError_t launch_cheb(int n, int B, const T* kap, const T* b, const T* x, const
 }
 
 template <class T>
+hipError_t launch_cheb_prolong(int n, int B, const T* kap, const T* b, const T* x, const T* xc, T* out, T* save,
+                               double c2, const int* active, hipStream_t st, SolveState* dot, uint32_t* nparts) {
+  constexpr int V = ZV<T>::V;
+  if (use_small<T>(n) || n < 4) return hipErrorInvalidValue;
+  if (dot)
+    return zlaunch_pro<T>(n, B, x, xc, kap, active, dot->partial, dot->pstride,
+                          EpiCheb<T, V, false, true>{b, nullptr, out, T(0), T(c2), save}, nparts, st);
+  return zlaunch_pro<T>(n, B, x, xc, kap, active, nullptr, 0,
+                        EpiCheb<T, V, false, false>{b, nullptr, out, T(0), T(c2), save}, nullptr, st);
+}
+
+template <class T>
 hipError_t launch_pcg_apply_dot(int n, int B, const T* kap, const T* p, T* q, SolveState s, uint32_t* nparts,
                                 hipStream_t st, int var) {
   if (use_small<T>(n))
@@ -634,6 +758,8 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st) 
   template hipError_t launch_cheb<T>(int, int, const T*, const T*, const T*, const T*, T*, double,     \
                                      double, bool, bool, const int*, hipStream_t, SolveState*,         \
                                      uint32_t*, int);                                                  \
+  template hipError_t launch_cheb_prolong<T>(int, int, const T*, const T*, const T*, const T*, T*, T*,   \
+                                             double, const int*, hipStream_t, SolveState*, uint32_t*);  \
   template hipError_t launch_pcg_apply_dot<T>(int, int, const T*, const T*, T*, SolveState, uint32_t*, \
                                               hipStream_t, int);                                       \
   template hipError_t launch_restrict<T>(int, int, const T*, T*, const int*, hipStream_t);             \

@@ -89,21 +89,45 @@ def test_apply_matches_csr(dev, n, B):
         assert np.abs(y[b] - want).max() <= 1e-14 * scale
 
 
+@pytest.mark.parametrize("fuse", [1, 0])
 @pytest.mark.parametrize("vsmall", ["1", "0"])
 @pytest.mark.parametrize("n,B,deg", [(4, 2, 2), (8, 3, 2), (16, 2, 3), (32, 1, 1)])
-def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, monkeypatch):
+def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, fuse, monkeypatch):
     # vsmall "1": coarse levels (8^3 and below in fp64) in the single-kernel
-    # V-cycle; "0": every level through the level-by-level kernels
+    # V-cycle; "0": every level through the level-by-level kernels.
+    # fuse 1: the coarse-grid correction is applied inside the first
+    # post-smoothing step; 0: by its own prolongation pass
     monkeypatch.setenv("MLMC_VSMALL", vsmall)
     kap = element_field(n, B, seed=300 + n, spread=1.5)
     r = grid_vector(n, B, seed=400 + n)
     ctx = mm.Context(_wl(n0=n, levels=1), cheb_degree=deg, arena_bytes=256 << 20)
+    ctx.set_tuning(fuse=fuse)
     z = mm.from_grid(ctx.vcycle(n, torch.tensor(kap, device=dev), mm.to_grid(torch.tensor(r, device=dev), n)), n)
     z = z.cpu().numpy()
     for b in range(B):
         H = gmg.Hierarchy(n, kap[b])
         want = H.vcycle(r[b], deg, 4.0, 2.0)
         assert np.abs(z[b] - want).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("deg", [1, 2])
+def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg):
+    # fp32 V-cycles (the mixed path) with and without the fused correction
+    n, B = 32, 3
+    wl = _wl(n0=n, levels=1, qoi=1, precision=1, solver=0, n_modes=16, corr_len=0.3)
+    qs = []
+    for fuse in (1, 0):
+        ctx = mm.Context(wl, cheb_degree=deg, arena_bytes=512 << 20)
+        ctx.set_tuning(fuse=fuse, vsmall_fp32=0, vsmall_fp64=0)
+        xi = ctx.draw_xi(0, 21, B)
+        kap = ctx.field(n, xi)
+        u, it = ctx.solve(n, kap)
+        qs.append(ctx.qoi(n, u).cpu().numpy())
+        kap_h = kap.cpu().numpy()
+    for b in range(B):
+        want = _oracle_q(n, kap_h[b], 1)
+        for q in qs:
+            assert abs(q[b] - want) <= 1e-7 * abs(want)
 
 
 def _oracle_q(n, kap, qoi, rtol=1e-12):
