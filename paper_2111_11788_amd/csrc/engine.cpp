@@ -147,8 +147,16 @@ int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float
 // With `dot` the last smoothing step of level l also writes the partial sums
 // of b . result (*dot_np per sample).
 template <class T>
+bool zero_step_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L) {
+  if (!(ctx->fuse & MLMC_FUSE_UPDATE) || L.size() < 2) return false;
+  const int n = L[0].n;
+  const int small = ctx->vsmall_n0[sizeof(T) == 4 ? 1 : 0];
+  return n >= 4 && n >= ZV<T>::V && !(small && n <= small);
+}
+
+template <class T>
 int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T* x, T* xo, T* t,
-           const int* active, T** result, SolveState* dot, uint32_t* dot_np) {
+           const int* active, T** result, SolveState* dot, uint32_t* dot_np, bool zero_done) {
   const int n = L[l].n;
   const double sz = sizeof(T);
   const double d = dofs(n) * B, e = elems(n) * B;
@@ -172,9 +180,10 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
     *result = x;
     return MLMC_OK;
   }
-  LAUNCHM(kid<T>(MLMC_K_CHEB_ZERO), (2 * d + e) * sz, active, B,
-         launch_cheb<T>(n, B, kap, b, nullptr, nullptr, x, 0.0, ch.c2[0], true, false, active, st, nullptr, nullptr,
-                        var));
+  if (!zero_done)
+    LAUNCHM(kid<T>(MLMC_K_CHEB_ZERO), (2 * d + e) * sz, active, B,
+            launch_cheb<T>(n, B, kap, b, nullptr, nullptr, x, 0.0, ch.c2[0], true, false, active, st, nullptr,
+                           nullptr, var));
   T* cur = x;
   T* oth = xo;
   for (int s = 1; s < ch.degree; ++s) {
@@ -222,7 +231,7 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
 // are already in S.partial (GMG path); otherwise the caller computes them.
 template <class T>
 int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T** z, SolveState& S,
-                 uint32_t* fused_np) {
+                 uint32_t* fused_np, bool zero_done) {
   const int n = L[0].n;
   *fused_np = 0;
   if (L.size() == 1 || n == 2) {
@@ -234,7 +243,7 @@ int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T**
     *z = L[0].x;
     return MLMC_OK;
   }
-  return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, S.active, z, &S, fused_np);
+  return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, S.active, z, &S, fused_np, zero_done);
 }
 
 int count_active(mlmc_ctx* ctx, SolveState& s, int B, int* out) {
@@ -261,9 +270,14 @@ int pcg_iteration(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S,
   T* z = nullptr;
   LAUNCHM(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, S.active, B, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, &np, st, var));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA, 0.0, np, S, nullptr, st));
-  LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE), 6 * d * sz, S.active, B, launch_pcg_update<T>(n, B, x, p, r, q, S, &np, st));
+  const bool fz = zero_step_fusable<T>(ctx, L);
+  if (fz)
+    LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE_ZERO), (7 * d + e) * sz, S.active, B,
+            launch_pcg_update_zero<T>(n, B, L[0].kap, x, p, r, q, L[0].x, ctx->cheb.c2[0], S, &np, st, var));
+  else
+    LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE), 6 * d * sz, S.active, B, launch_pcg_update<T>(n, B, x, p, r, q, S, &np, st));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, rr_op, tol2, np, S, nullptr, st));
-  if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
+  if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np, fz)) return rc;
   if (!np) LAUNCHM(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, S.active, B, (launch_dot<T>(n, B, r, z, S, &np, st)));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BETA, 0.0, np, S, nullptr, st));
   LAUNCHM(kid<T>(MLMC_K_PCG_DIRECTION), 3 * d * sz, S.active, B, launch_pcg_direction<T>(n, B, z, p, S, st));
@@ -473,7 +487,7 @@ int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (t->cheb_degree < 1 || t->cheb_degree > 8) { why = "cheb_degree must be in 1..8"; return MLMC_E_INVALID; }
   if (t->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
   if (t->graph_batch < 0 || t->graph_batch > 16) { why = "graph_batch must be in 0..16"; return MLMC_E_INVALID; }
-  if (t->fuse & ~MLMC_FUSE_PROLONG) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
+  if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
   return MLMC_OK;
 }
 
@@ -511,13 +525,15 @@ void apply_tuning(mlmc_ctx* ctx, const mlmc_tuning& t) {
 }
 
 template int vcycle<float>(mlmc_ctx*, std::vector<Level<float>>&, int, int, const float*, float*, float*, float*,
-                           const int*, float**, SolveState*, uint32_t*);
+                           const int*, float**, SolveState*, uint32_t*, bool);
 template int vcycle<double>(mlmc_ctx*, std::vector<Level<double>>&, int, int, const double*, double*, double*,
-                            double*, const int*, double**, SolveState*, uint32_t*);
+                            double*, const int*, double**, SolveState*, uint32_t*, bool);
 template int precondition<float>(mlmc_ctx*, std::vector<Level<float>>&, int, const float*, float**, SolveState&,
-                                 uint32_t*);
+                                 uint32_t*, bool);
 template int precondition<double>(mlmc_ctx*, std::vector<Level<double>>&, int, const double*, double**, SolveState&,
-                                  uint32_t*);
+                                  uint32_t*, bool);
+template bool zero_step_fusable<float>(const mlmc_ctx*, const std::vector<Level<float>>&);
+template bool zero_step_fusable<double>(const mlmc_ctx*, const std::vector<Level<double>>&);
 template int pcg_iteration<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*,
                                   float*, double, int, bool);
 template int pcg_iteration<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*,

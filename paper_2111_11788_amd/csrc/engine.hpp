@@ -230,7 +230,7 @@ struct mlmc_ctx {
   bool use_graphs = true;         // replay the PCG iteration from a captured hipGraph
   bool own_stream = false;        // the context created st itself
   int graph_batch = 2;            // graph launches per convergence check
-  int fuse = MLMC_FUSE_PROLONG;   // MLMC_FUSE_* bits in use
+  int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE;   // MLMC_FUSE_* bits in use
   mlmc_server* server = nullptr;  // serving pools and threads while serving
 };
 
@@ -320,15 +320,21 @@ int ensure_tables(mlmc_ctx* ctx, int n, double** tab);
 int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float* kap32);
 // One V-cycle on levels l.. of L; returns the buffer that holds the result.
 // With `dot` the last smoothing step of level l also writes the partial sums
-// of b . result (*dot_np per sample).
+// of b . result (*dot_np per sample).  zero_done: x already holds the first
+// (zero-iterate) smoothing step of level l (see zero_step_fusable).
 template <class T>
 int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T* x, T* xo, T* t,
-           const int* active, T** result, SolveState* dot = nullptr, uint32_t* dot_np = nullptr);
+           const int* active, T** result, SolveState* dot = nullptr, uint32_t* dot_np = nullptr,
+           bool zero_done = false);
 // z = M^-1 r.  When *fused_np is set on return, the partial sums of r . z
 // are already in S.partial (GMG path); otherwise the caller computes them.
 template <class T>
 int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T** z, SolveState& S,
-                 uint32_t* fused_np);
+                 uint32_t* fused_np, bool zero_done = false);
+// Whether the preconditioner's first smoothing step on the finest level runs
+// through the level-by-level kernels, so a PCG update can produce it.
+template <class T>
+bool zero_step_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L);
 int count_active(mlmc_ctx* ctx, SolveState& s, int B, int* out);
 template <class T>
 int pcg_iteration(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q,

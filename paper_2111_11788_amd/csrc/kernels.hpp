@@ -65,6 +65,12 @@ template <class T>
 hipError_t launch_cheb_prolong(int n, int B, const T* kap, const T* b, const T* x, const T* xc, T* out, T* save,
                                double c2, const int* active, hipStream_t st, SolveState* dot = nullptr,
                                uint32_t* nparts = nullptr);
+// x += alpha p, r -= alpha q (alpha = s.alpha[b]), partial sums of r . r into
+// s.partial, and z = c2 D^-1 r: a PCG update fused with the zero-iterate
+// Chebyshev step of the following V-cycle (n >= 4).
+template <class T>
+hipError_t launch_pcg_update_zero(int n, int B, const T* kap, T* x, const T* p, T* r, const T* q, T* z, double c2,
+                                  SolveState s, uint32_t* nparts, hipStream_t st, int var = 0);
 template <class T>
 hipError_t launch_restrict(int nf, int B, const T* rf, T* bc, const int* active, hipStream_t st);
 template <class T>

@@ -77,6 +77,7 @@ __device__ __forceinline__ void vstore(T* p, const T* src) {
 template <class T, int V>
 struct EpiApply {
   static constexpr bool kReduce = false;
+  static constexpr bool kBegin = false;
   T* y;
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double&) const {
     T o[V];
@@ -89,6 +90,7 @@ struct EpiApply {
 template <class T, int V>
 struct EpiResidual {
   static constexpr bool kReduce = false;
+  static constexpr bool kBegin = false;
   const T* b;
   T* r;
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double&) const {
@@ -108,6 +110,7 @@ struct EpiResidual {
 template <class T, int V, bool USE_XO, bool DOT>
 struct EpiCheb {
   static constexpr bool kReduce = DOT;
+  static constexpr bool kBegin = false;
   const T* b;
   const T* xo;
   T* out;
@@ -137,6 +140,7 @@ struct EpiCheb {
 template <class T, int V>
 struct EpiPcgApply {
   static constexpr bool kReduce = true;
+  static constexpr bool kBegin = false;
   T* q;
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
     T o[V];
@@ -153,6 +157,7 @@ struct EpiPcgApply {
 template <class T, int V>
 struct EpiTrueResidual {
   static constexpr bool kReduce = true;
+  static constexpr bool kBegin = false;
   T bconst;
   T* r;
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
@@ -170,6 +175,7 @@ struct EpiTrueResidual {
 template <class T, int V>
 struct EpiChebZero {
   static constexpr bool kReduce = false;
+  static constexpr bool kBegin = false;
   const T* b;
   T* out;
   T c2;
@@ -188,6 +194,41 @@ __device__ __forceinline__ void nload(const T* p, T* dst) {
   if constexpr (N == 1) dst[0] = *p;
   else vload<T, N>(p, dst);
 }
+
+// PCG update fused with the first Chebyshev step (zero iterate) of the
+// preconditioner that follows it: x += alpha p, r -= alpha q, sum r.r, and
+// z = c2 D^-1 r with the updated r (needs only the kappa window).
+template <class T, int V>
+struct EpiPcgUpdateZero {
+  static constexpr bool kReduce = true;
+  static constexpr bool kBegin = true;
+  T* x;
+  const T* p;
+  T* r;
+  const T* q;
+  T* z;
+  const double* alpha;
+  T c2;
+  T a = T(0);
+  __device__ void begin(uint32_t b) { a = (T)alpha[b]; }
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
+    T xv[V], pv[V], rv[V], qv[V], zo[V];
+    vload<T, V>(x + pos, xv);
+    vload<T, V>(p + pos, pv);
+    vload<T, V>(r + pos, rv);
+    vload<T, V>(q + pos, qv);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      xv[v] = xv[v] + a * pv[v];
+      rv[v] = rv[v] - a * qv[v];
+      acc += (double)rv[v] * (double)rv[v];
+      zo[v] = ok[v] ? c2 * rv[v] / dg[v] : T(0);
+    }
+    vstore<T, V>(x + pos, xv);
+    vstore<T, V>(r + pos, rv);
+    vstore<T, V>(z + pos, zo);
+  }
+};
 
 // --------------------------------------------------------- z-march engine
 // PF: issue the loads of the next plane step before computing the current one
@@ -220,6 +261,7 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
   if (k1 > n) k1 = n;
   const bool valid = jr < g.rows && j <= n - 1 && k0 < k1;
   double acc = 0.0;
+  if constexpr (Epi::kBegin) epi.begin(b);
   if (valid) {
     const T* ub = u + (size_t)b * stride;
     const T* kb = kap + (size_t)b * n2 * n;
@@ -699,6 +741,14 @@ hipError_t launch_cheb_prolong(int n, int B, const T* kap, const T* b, const T* 
 }
 
 template <class T>
+hipError_t launch_pcg_update_zero(int n, int B, const T* kap, T* x, const T* p, T* r, const T* q, T* z, double c2,
+                                  SolveState s, uint32_t* nparts, hipStream_t st, int var) {
+  if (use_small<T>(n)) return hipErrorInvalidValue;
+  return zlaunch<T, false>(n, B, nullptr, kap, s.active, s.partial, s.pstride,
+                           EpiPcgUpdateZero<T, ZV<T>::V>{x, p, r, q, z, s.alpha, T(c2)}, nparts, var, st);
+}
+
+template <class T>
 hipError_t launch_pcg_apply_dot(int n, int B, const T* kap, const T* p, T* q, SolveState s, uint32_t* nparts,
                                 hipStream_t st, int var) {
   if (use_small<T>(n))
@@ -760,6 +810,8 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st) 
                                      uint32_t*, int);                                                  \
   template hipError_t launch_cheb_prolong<T>(int, int, const T*, const T*, const T*, const T*, T*, T*,   \
                                              double, const int*, hipStream_t, SolveState*, uint32_t*);  \
+  template hipError_t launch_pcg_update_zero<T>(int, int, const T*, T*, const T*, T*, const T*, T*,     \
+                                                double, SolveState, uint32_t*, hipStream_t, int);      \
   template hipError_t launch_pcg_apply_dot<T>(int, int, const T*, const T*, T*, SolveState, uint32_t*, \
                                               hipStream_t, int);                                       \
   template hipError_t launch_restrict<T>(int, int, const T*, T*, const int*, hipStream_t);             \

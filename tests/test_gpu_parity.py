@@ -112,11 +112,12 @@ def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, fuse, monkeypatch):
 
 @pytest.mark.parametrize("deg", [1, 2])
 def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg):
-    # fp32 V-cycles (the mixed path) with and without the fused correction
+    # fp32 V-cycles (the mixed path) with and without the fused correction and
+    # the PCG update fused with the first smoothing step
     n, B = 32, 3
     wl = _wl(n0=n, levels=1, qoi=1, precision=1, solver=0, n_modes=16, corr_len=0.3)
     qs = []
-    for fuse in (1, 0):
+    for fuse in (3, 2, 1, 0):   # both fusions, update only, prolongation only, none
         ctx = mm.Context(wl, cheb_degree=deg, arena_bytes=512 << 20)
         ctx.set_tuning(fuse=fuse, vsmall_fp32=0, vsmall_fp64=0)
         xi = ctx.draw_xi(0, 21, B)
