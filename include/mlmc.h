@@ -210,7 +210,9 @@ int mlmc_estimate(mlmc_ctx* ctx, const mlmc_estimate_opts* opts, uint64_t* n_per
 /* Execution choices that change speed, not the discrete solution each solve
  * converges to (iteration counts and last bits may change). */
 typedef struct mlmc_tuning {
-  int32_t zvar_fp32;      /* stencil kernel variant bits for fp32 (1: prefetch next plane) */
+  int32_t zvar_fp32;      /* stencil kernel variant bits for fp32: 0 register window, 1 with the next
+                             plane prefetched, 2 LDS-tiled planes, 4 LDS-tiled planes also for the
+                             step that applies the coarse-grid correction (default 2) */
   int32_t zvar_fp64;      /* same for fp64 */
   int32_t vsmall_fp32;    /* mesh from which the coarse V-cycle runs as one LDS kernel (0: off) */
   int32_t vsmall_fp64;    /* same for fp64 (at most 8) */

@@ -265,7 +265,11 @@ int mlmc_autotune(mlmc_ctx* ctx, int32_t level, int32_t batch, mlmc_tuning* best
     mlmc_tuning c = best; c.cheb_degree = deg;
     if (int rc = trial(c)) return rc;
   }
-  { mlmc_tuning c = best; c.zvar_fp32 ^= 1; c.zvar_fp64 ^= 1; if (int rc = trial(c)) return rc; }
+  for (int zv : {0, 1, 2, 6}) {
+    if (zv == base.zvar_fp32) continue;
+    mlmc_tuning c = best; c.zvar_fp32 = zv; c.zvar_fp64 = zv;
+    if (int rc = trial(c)) return rc;
+  }
   for (int v : {16, 8, 0}) {
     if (v == best.vsmall_fp32) continue;
     mlmc_tuning c = best; c.vsmall_fp32 = v; c.vsmall_fp64 = std::min(v, 8);

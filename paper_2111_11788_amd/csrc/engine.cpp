@@ -208,7 +208,7 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
     T* save = last ? nullptr : t;
     LAUNCHM(kid<T>(MLMC_K_CHEB_PROLONG), ((last ? 3 : 4) * d + dc + e) * sz, active, B,
             launch_cheb_prolong<T>(n, B, kap, b, cur, xc, oth, save, ch.c2[0], active, st, last ? dot : nullptr,
-                                   last ? dot_np : nullptr));
+                                   last ? dot_np : nullptr, var));
     cur = oth;
     oth = t;
     s0 = 1;
@@ -481,7 +481,7 @@ int run_level(mlmc_ctx* ctx, int level, uint64_t first, uint64_t count, double* 
 
 int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (!t) { why = "NULL tuning"; return MLMC_E_INVALID; }
-  if (t->zvar_fp32 < 0 || t->zvar_fp32 > 1 || t->zvar_fp64 < 0 || t->zvar_fp64 > 1) { why = "zvar must be 0 or 1"; return MLMC_E_INVALID; }
+  if (t->zvar_fp32 < 0 || t->zvar_fp32 > 7 || t->zvar_fp64 < 0 || t->zvar_fp64 > 7) { why = "zvar bits must be in 0..7"; return MLMC_E_INVALID; }
   auto okv = [](int v, int mx) { return v == 0 || (v >= 4 && v <= mx && (v & (v - 1)) == 0); };
   if (!okv(t->vsmall_fp32, 16) || !okv(t->vsmall_fp64, 8)) { why = "vsmall must be 0 or 4..16 (fp64 4..8), a power of two"; return MLMC_E_INVALID; }
   if (t->cheb_degree < 1 || t->cheb_degree > 8) { why = "cheb_degree must be in 1..8"; return MLMC_E_INVALID; }

@@ -225,7 +225,7 @@ struct mlmc_ctx {
   int64_t k_launch[2 * MLMC_K_COUNT] = {0};   // [precision][kernel]
   double k_ms[2 * MLMC_K_COUNT] = {0}, k_bytes[2 * MLMC_K_COUNT] = {0};
   int* h_nactive = nullptr;
-  int zvar[2] = {0, 0};           // z-march kernel variant for fp64 / fp32
+  int zvar[2] = {ZVAR_LDS, ZVAR_LDS};   // stencil engine variant bits for fp64 / fp32
   int vsmall_n0[2] = {8, 16};     // mesh at which the single-kernel coarse V-cycle takes over (0: off)
   bool use_graphs = true;         // replay the PCG iteration from a captured hipGraph
   bool own_stream = false;        // the context created st itself

@@ -40,7 +40,11 @@ enum : int { PHASE_FREE = 0, PHASE_INNER = 1, PHASE_TRANSITION = 2, PHASE_RESTAR
 // Grid-layout kernels on an n^3 mesh for `B` samples; `active` (may be null)
 // skips samples whose flag is 0.  Device pointers must be 16-byte aligned.
 // z-march variants (bit flags), chosen per context by measurement
-enum : int { ZVAR_PREFETCH = 1 };
+// stencil engine variant bits: register window (0), register window with the
+// next plane prefetched (ZVAR_PREFETCH), LDS-tiled planes for the plain kernels
+// (ZVAR_LDS) and for the step that applies the coarse-grid correction
+// (ZVAR_LDS_PRO)
+enum : int { ZVAR_PREFETCH = 1, ZVAR_LDS = 2, ZVAR_LDS_PRO = 4 };
 
 template <class T>
 hipError_t launch_apply(int n, int B, const T* kap, const T* u, T* y, const int* active, hipStream_t st,
@@ -64,7 +68,7 @@ hipError_t launch_cheb(int n, int B, const T* kap, const T* b, const T* x, const
 template <class T>
 hipError_t launch_cheb_prolong(int n, int B, const T* kap, const T* b, const T* x, const T* xc, T* out, T* save,
                                double c2, const int* active, hipStream_t st, SolveState* dot = nullptr,
-                               uint32_t* nparts = nullptr);
+                               uint32_t* nparts = nullptr, int var = 0);
 // x += alpha p, r -= alpha q (alpha = s.alpha[b]), partial sums of r . r into
 // s.partial, and z = c2 D^-1 r: a PCG update fused with the zero-iterate
 // Chebyshev step of the following V-cycle (n >= 4).

@@ -69,6 +69,13 @@ __device__ __forceinline__ void vstore(T* p, const T* src) {
   *reinterpret_cast<vt*>(p) = v;
 }
 
+// 1 / D for the Jacobi scaling: the hardware reciprocal in fp32 (1 ulp; the
+// smoother only needs a fixed diagonal scaling, and it is the same one in
+// every smoothing step, so the V-cycle stays symmetric), a correctly rounded
+// division in fp64.
+__device__ __forceinline__ float inv_diag(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double inv_diag(double d) { return 1.0 / d; }
+
 // ------------------------------------------------------------ epilogues
 // Each epilogue sees, for the V nodes i0 .. i0+V-1 at position `pos` (index
 // of node i0 in the batch array), A u, D and the centre values of u; `ok[v]`
@@ -123,7 +130,7 @@ struct EpiCheb {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const T prev = USE_XO ? uc[v] - xov[v] : uc[v];
-      o[v] = ok[v] ? uc[v] + c1 * prev + c2 * (bv[v] - au[v]) / dg[v] : T(0);
+      o[v] = ok[v] ? uc[v] + c1 * prev + c2 * (bv[v] - au[v]) * inv_diag(dg[v]) : T(0);
       if (DOT) acc += (double)bv[v] * (double)o[v];
     }
     vstore<T, V>(out + pos, o);
@@ -183,7 +190,7 @@ struct EpiChebZero {
     T bv[V], o[V];
     vload<T, V>(b + pos, bv);
 #pragma unroll
-    for (int v = 0; v < V; ++v) o[v] = ok[v] ? c2 * bv[v] / dg[v] : T(0);
+    for (int v = 0; v < V; ++v) o[v] = ok[v] ? c2 * bv[v] * inv_diag(dg[v]) : T(0);
     vstore<T, V>(out + pos, o);
   }
 };
@@ -222,7 +229,7 @@ struct EpiPcgUpdateZero {
       xv[v] = xv[v] + a * pv[v];
       rv[v] = rv[v] - a * qv[v];
       acc += (double)rv[v] * (double)rv[v];
-      zo[v] = ok[v] ? c2 * rv[v] / dg[v] : T(0);
+      zo[v] = ok[v] ? c2 * rv[v] * inv_diag(dg[v]) : T(0);
     }
     vstore<T, V>(x + pos, xv);
     vstore<T, V>(r + pos, rv);
@@ -443,9 +450,302 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
   }
 }
 
+// ------------------------------------------------- LDS-tiled z-march engine
+// One workgroup owns `rows` node rows (all n columns) of one sample and walks
+// a chunk of planes.  Each plane step stages the next u plane ((rows + 2)
+// rows: the tile and its two halo rows) and the next kappa plane ((rows + 1)
+// element rows) into LDS rings with coalesced 16-byte loads that were issued
+// one step earlier into registers, so the loads of plane k+2 are in flight
+// while plane k is computed.  Every u and kappa value is read from HBM/L2
+// once per workgroup (the register engine reads each u row three times), and
+// the thread state is small, which leaves room for more waves.  The
+// arithmetic per node is the register engine's.
+//
+// LDS rows: u row = [.., u(-1) = 0 at V-1, u(0..n-1) at V.., u(n) = 0 at V+n],
+// stride n + 2V; kappa row = [.., 0 at V-1, kappa(0..n-1) at V..], stride n + V
+// (the zero cells are written once and never overwritten).  u plane kk lives
+// in ring slot kk mod 3, kappa plane ez in slot ez mod 2.  PRO adds P xc to
+// each staged u vector (same operation order as the register engine).
+template <class T>
+__host__ __device__ inline int zlds_urs(int n) { return n + 2 * ZV<T>::V; }
+template <class T>
+__host__ __device__ inline int zlds_krs(int n) { return n + ZV<T>::V; }
+template <class T>
+inline size_t zlds_bytes(const ZGeom& g) {
+  return ((size_t)3 * (g.rows + 2) * zlds_urs<T>(g.n) + (size_t)2 * (g.rows + 1) * zlds_krs<T>(g.n)) * sizeof(T);
+}
+
+template <class T, int V, bool NEED_U, bool PRO, class Epi>
+__global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const T* __restrict__ u,
+                                              const T* __restrict__ kap, const int* __restrict__ active,
+                                              double* __restrict__ partial, uint32_t pstride, Epi epi,
+                                              const T* __restrict__ xc, size_t cstride) {
+  static_assert(!PRO || NEED_U, "the fused prolongation needs the u operand");
+  typedef typename Vec<T, V>::type vt;
+  extern __shared__ __align__(16) unsigned char zsmem[];
+  const uint32_t per = g.parts();
+  const uint32_t lin = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = lin / per;
+  const uint32_t part = lin - b * per;
+  if (active && !active[b]) return;   // uniform over the workgroup
+  const int rb = (int)(part % (uint32_t)g.row_blocks), zb = (int)(part / (uint32_t)g.row_blocks);
+  const int n = g.n, n2 = n * n, G = g.G, R = g.rows;
+  const int UR = R + 2, KR = R + 1;
+  const int URS = zlds_urs<T>(n), KRS = zlds_krs<T>(n);
+  T* Ul = reinterpret_cast<T*>(zsmem);        // [3][UR][URS]
+  T* Kl = Ul + 3 * UR * URS;                   // [2][KR][KRS]
+  const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
+  const int j0 = 1 + rb * R;
+  const int k0 = 1 + zb * g.zlen;
+  int k1 = k0 + g.zlen;
+  if (k1 > n) k1 = n;
+  const int gx = tid % G, jr = tid / G;
+  const int j = j0 + jr, i0 = gx * V;
+  const bool valid = jr < R && j <= n - 1 && k0 < k1;
+  const T* ub = NEED_U ? u + (size_t)b * stride : nullptr;
+  const T* kb = kap + (size_t)b * n2 * n;
+  const T* cb = PRO ? xc + (size_t)b * cstride : nullptr;
+  const int nc = n >> 1, nc2 = nc * nc;
+  if constexpr (Epi::kBegin) epi.begin(b);
+
+  // zero cells (i = -1, i = n of u; ex = -1 of kappa) of every ring row
+  for (int q = tid; q < 3 * UR; q += nthr) {
+    Ul[q * URS + V - 1] = T(0);
+    Ul[q * URS + V + n] = T(0);
+  }
+  for (int q = tid; q < 2 * KR; q += nthr) Kl[q * KRS + V - 1] = T(0);
+
+  // staging: up to two 16-byte vectors per thread per plane for u and kappa;
+  // a thread stages the same (row, column) positions on every plane
+  vt pu[2], pk[2];
+  // PRO: per staged vector, the coarse values I0 .. I0+V/2 of its parent rows
+  // Jlo = jj/2, Jhi = (jj+1)/2 on coarse planes cK and cK+1 (the parents of
+  // fine planes 2cK and 2cK+1), refreshed every second fine plane
+  constexpr int CQ = V / 2 + 1;
+  T CWin[2][2][2][PRO ? CQ : 1];   // [vector][plane][row][q]
+  int cK = 0;
+  auto load_cplane = [&](int slot, int K) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      const int jj = j0 - 1 + r;
+      const bool use = v < UR * G && jj <= n && K <= nc;
+#pragma unroll
+      for (int jy = 0; jy < 2; ++jy) {
+        if (!use) {
+#pragma unroll
+          for (int q = 0; q < CQ; ++q) CWin[m][slot][jy][q] = T(0);
+          continue;
+        }
+        const int JJ = jy ? (jj + 1) >> 1 : jj >> 1;
+        const T* row = cb + (size_t)nc2 * K + (size_t)nc * JJ + c * (V / 2);
+        nload<T, V / 2>(row, CWin[m][slot][jy]);
+        CWin[m][slot][jy][V / 2] = row[V / 2];
+      }
+    }
+  };
+  if (PRO) {
+    cK = (k0 - 1) >> 1;
+    load_cplane(0, cK);
+    load_cplane(1, cK + 1);
+  }
+  auto fetch_u = [&](int kk) {
+    if (PRO && (kk >> 1) > cK) {   // fine planes are staged in increasing order
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int jy = 0; jy < 2; ++jy)
+#pragma unroll
+          for (int q = 0; q < CQ; ++q) CWin[m][0][jy][q] = CWin[m][1][jy][q];
+      ++cK;
+      load_cplane(1, cK + 1);
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      const int jj = j0 - 1 + r;
+      if (v < UR * G && jj <= n) pu[m] = *reinterpret_cast<const vt*>(ub + (size_t)n2 * kk + (size_t)n * jj + c * V);
+    }
+  };
+  // store the plane kk fetched last (the loads were in flight meanwhile);
+  // PRO adds the correction here, from the coarse window fetched with it
+  auto store_u = [&](int slot, int kk) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      const int jj = j0 - 1 + r;
+      if (v < UR * G && jj <= n) {
+        if (PRO) {
+          // fine nodes c*V .. c*V+V-1 of row jj, plane kk
+          const bool kodd = (kk & 1) != 0, jodd = (jj & 1) != 0;
+          T L[CQ];
+#pragma unroll
+          for (int q = 0; q < CQ; ++q) {
+            const T P0 = kodd ? T(0.5) * (CWin[m][0][0][q] + CWin[m][1][0][q]) : CWin[m][0][0][q];
+            const T P1 = kodd ? T(0.5) * (CWin[m][0][1][q] + CWin[m][1][1][q]) : CWin[m][0][1][q];
+            L[q] = jodd ? T(0.5) * (P0 + P1) : P0;
+          }
+#pragma unroll
+          for (int t = 0; t < V; ++t)
+            pu[m][t] += (t & 1) ? T(0.5) * (L[(t - 1) / 2] + L[(t + 1) / 2]) : L[t / 2];
+        }
+        *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + V + c * V) = pu[m];
+      }
+    }
+  };
+  auto fetch_k = [&](int ez) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      const int ey = j0 - 1 + r;
+      if (v < KR * G && ey <= n - 1)
+        pk[m] = *reinterpret_cast<const vt*>(kb + (size_t)n2 * ez + (size_t)n * ey + c * V);
+    }
+  };
+  auto store_k = [&](int slot) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      if (v < KR * G && j0 - 1 + r <= n - 1)
+        *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + V + c * V) = pk[m];
+    }
+  };
+
+  double acc = 0.0;
+  if (k0 < k1) {
+    // prologue: u planes k0-1, k0, k0+1 and kappa planes k0-1, k0 into LDS;
+    // then the loads of u plane k0+2 and kappa plane k0+1 are left in flight
+    if (NEED_U) {
+      fetch_u(k0 - 1); store_u((k0 - 1) % 3, k0 - 1);
+      fetch_u(k0); store_u(k0 % 3, k0);
+      fetch_u(k0 + 1); store_u((k0 + 1) % 3, k0 + 1);
+    }
+    fetch_k(k0 - 1); store_k((k0 - 1) & 1);
+    fetch_k(k0); store_k(k0 & 1);
+    if (NEED_U && k0 + 2 <= k1) fetch_u(k0 + 2);
+    if (k0 + 1 < k1) fetch_k(k0 + 1);
+    __syncthreads();
+    bool ok[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) ok[v] = (i0 + v) != 0;
+    int sm = (k0 - 1) % 3, s0 = k0 % 3, sp = (k0 + 1) % 3;   // u slots of planes k-1, k, k+1
+    int km = (k0 - 1) & 1, kc = k0 & 1;                          // kappa slots of planes k-1, k
+    const T third = T(1) / T(3), twelfth = T(1) / T(12);
+    for (int k = k0; k < k1; ++k) {
+      if (valid) {
+        // The same 20-neighbour sum as the register engine, gathered one u
+        // plane at a time (planes k-1 and k+1: the centre row and the rows
+        // j-1, j+1; plane k: rows j-1, j+1 and the centre values) so that only
+        // one plane of the window is live.
+        T K[2][2][V + 1];
+        const int ks[2] = {km, kc};
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy) {
+            const T* row = Kl + (ks[dz] * KR + jr + dy) * KRS + V + i0;
+            K[dz][dy][0] = row[-1];
+            vload<T, V>(row, K[dz][dy] + 1);
+          }
+        T far[V], ksum[V], uc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          far[v] = T(0);
+          ksum[v] = T(0);
+#pragma unroll
+          for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+            for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+              for (int sx = 0; sx < 2; ++sx) ksum[v] += K[sz][sy][v + sx];
+          uc[v] = T(0);
+        }
+        if (NEED_U) {
+#pragma unroll
+          for (int sz = 0; sz < 2; ++sz) {
+            const T* P = Ul + ((sz ? sp : sm) * UR + jr) * URS + V + i0;
+            T R[3][V + 2];
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+              R[dy][0] = P[dy * URS - 1];
+              vload<T, V>(P + dy * URS, R[dy] + 1);
+              R[dy][V + 1] = P[dy * URS + V];
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+              for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+                for (int sx = 0; sx < 2; ++sx)
+                  far[v] += K[sz][sy][v + sx] * (R[1][v + 2 * sx] + (R[2 * sy][v + 1] + R[2 * sy][v + 2 * sx]));
+          }
+          {
+            const T* P = Ul + (s0 * UR + jr) * URS + V + i0;
+            T R0[V + 2], R2[V + 2];
+            R0[0] = P[-1];
+            vload<T, V>(P, R0 + 1);
+            R0[V + 1] = P[V];
+            vload<T, V>(P + URS, uc);
+            R2[0] = P[2 * URS - 1];
+            vload<T, V>(P + 2 * URS, R2 + 1);
+            R2[V + 1] = P[2 * URS + V];
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+              for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+                for (int sx = 0; sx < 2; ++sx)
+                  far[v] += (K[0][sy][v + sx] + K[1][sy][v + sx]) * (sy ? R2 : R0)[v + 2 * sx];
+          }
+        }
+        T au[V], dg[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          au[v] = h * (ksum[v] * uc[v] * third - far[v] * twelfth);
+          dg[v] = h * ksum[v] * third;
+        }
+        epi((size_t)b * stride + i0 + (size_t)n * j + (size_t)n2 * k, au, dg, uc, ok, acc);
+      }
+      if (k + 1 < k1) {
+        __syncthreads();   // every thread is done with u plane k-1 and kappa plane k-1
+        if (NEED_U && k + 2 <= k1) store_u(sm, k + 2);   // plane k+2 takes the slot of plane k-1
+        store_k(km);                               // kappa plane k+1 takes the slot of plane k-1
+        if (NEED_U && k + 3 <= k1) fetch_u(k + 3);
+        if (k + 2 < k1) fetch_k(k + 2);
+        __syncthreads();
+        const int t = sm; sm = s0; s0 = sp; sp = t;
+        const int tk = km; km = kc; kc = tk;
+      }
+    }
+  }
+  if (Epi::kReduce) {
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[(size_t)b * pstride + part] = acc;
+  }
+}
+
+template <class T, bool NEED_U, bool PRO, class Epi>
+hipError_t zlaunch_lds(int n, int B, const T* u, const T* xc, const T* kap, const int* active, double* partial,
+                       uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st) {
+  constexpr int V = ZV<T>::V;
+  const ZGeom g = zgeom<T>(n, B);
+  if (nparts) *nparts = g.parts();
+  const uint32_t blocks = g.parts() * (uint32_t)B;
+  k_zlds<T, V, NEED_U, PRO, Epi><<<dim3(blocks), dim3(g.threads), zlds_bytes<T>(g), st>>>(
+      g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, PRO ? grid_stride(n / 2) : 0);
+  return hipGetLastError();
+}
+
 template <class T, bool NEED_U, class Epi>
 hipError_t zlaunch(int n, int B, const T* u, const T* kap, const int* active, double* partial, uint32_t pstride,
                    Epi epi, uint32_t* nparts, int var, hipStream_t st) {
+  if (var & ZVAR_LDS)
+    return zlaunch_lds<T, NEED_U, false, Epi>(n, B, u, nullptr, kap, active, partial, pstride, epi, nparts, st);
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
   if (nparts) *nparts = g.parts();
@@ -459,10 +759,12 @@ hipError_t zlaunch(int n, int B, const T* u, const T* kap, const int* active, do
   return hipGetLastError();
 }
 
-// the operand is u + P xc (xc on the n/2 mesh); plain window only
+// the operand is u + P xc (xc on the n/2 mesh); plain register window or LDS
 template <class T, class Epi>
 hipError_t zlaunch_pro(int n, int B, const T* u, const T* xc, const T* kap, const int* active, double* partial,
-                       uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st) {
+                       uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st, int var) {
+  if (var & ZVAR_LDS_PRO)
+    return zlaunch_lds<T, true, true, Epi>(n, B, u, xc, kap, active, partial, pstride, epi, nparts, st);
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
   if (nparts) *nparts = g.parts();
@@ -730,14 +1032,15 @@ hipError_t launch_cheb(int n, int B, const T* kap, const T* b, const T* x, const
 
 template <class T>
 hipError_t launch_cheb_prolong(int n, int B, const T* kap, const T* b, const T* x, const T* xc, T* out, T* save,
-                               double c2, const int* active, hipStream_t st, SolveState* dot, uint32_t* nparts) {
+                               double c2, const int* active, hipStream_t st, SolveState* dot, uint32_t* nparts,
+                               int var) {
   constexpr int V = ZV<T>::V;
   if (use_small<T>(n) || n < 4) return hipErrorInvalidValue;
   if (dot)
     return zlaunch_pro<T>(n, B, x, xc, kap, active, dot->partial, dot->pstride,
-                          EpiCheb<T, V, false, true>{b, nullptr, out, T(0), T(c2), save}, nparts, st);
+                          EpiCheb<T, V, false, true>{b, nullptr, out, T(0), T(c2), save}, nparts, st, var);
   return zlaunch_pro<T>(n, B, x, xc, kap, active, nullptr, 0,
-                        EpiCheb<T, V, false, false>{b, nullptr, out, T(0), T(c2), save}, nullptr, st);
+                        EpiCheb<T, V, false, false>{b, nullptr, out, T(0), T(c2), save}, nullptr, st, var);
 }
 
 template <class T>
@@ -809,7 +1112,8 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st) 
                                      double, bool, bool, const int*, hipStream_t, SolveState*,         \
                                      uint32_t*, int);                                                  \
   template hipError_t launch_cheb_prolong<T>(int, int, const T*, const T*, const T*, const T*, T*, T*,   \
-                                             double, const int*, hipStream_t, SolveState*, uint32_t*);  \
+                                             double, const int*, hipStream_t, SolveState*, uint32_t*,   \
+                                             int);                                                      \
   template hipError_t launch_pcg_update_zero<T>(int, int, const T*, T*, const T*, T*, const T*, T*,     \
                                                 double, SolveState, uint32_t*, hipStream_t, int);      \
   template hipError_t launch_pcg_apply_dot<T>(int, int, const T*, const T*, T*, SolveState, uint32_t*, \

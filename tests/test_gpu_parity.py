@@ -69,11 +69,14 @@ def test_field_matches_oracle(dev, n, M, corr, count):
     assert np.array_equal(k32.cpu().numpy(), got.astype(np.float32))
 
 
+@pytest.mark.parametrize("zvar", [0, 1, 2])
 @pytest.mark.parametrize("n,B", [(4, 3), (8, 5), (16, 2), (32, 1)])
-def test_apply_matches_csr(dev, n, B):
+def test_apply_matches_csr(dev, n, B, zvar):
+    # zvar: register-window stencil engine (0), with prefetch (1), LDS-tiled (2)
     kap = element_field(n, B, seed=100 + n)
     u = grid_vector(n, B, seed=200 + n)
     ctx = mm.Context(_wl(n0=n, levels=1), arena_bytes=64 << 20)
+    ctx.set_tuning(zvar_fp64=zvar, zvar_fp32=zvar)
     kt = torch.tensor(kap, device=dev)
     ug = mm.to_grid(torch.tensor(u, device=dev), n)
     yg = ctx.apply(n, kt, ug)
@@ -89,10 +92,11 @@ def test_apply_matches_csr(dev, n, B):
         assert np.abs(y[b] - want).max() <= 1e-14 * scale
 
 
+@pytest.mark.parametrize("zvar", [0, 6])
 @pytest.mark.parametrize("fuse", [1, 0])
 @pytest.mark.parametrize("vsmall", ["1", "0"])
 @pytest.mark.parametrize("n,B,deg", [(4, 2, 2), (8, 3, 2), (16, 2, 3), (32, 1, 1)])
-def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, fuse, monkeypatch):
+def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, fuse, zvar, monkeypatch):
     # vsmall "1": coarse levels (8^3 and below in fp64) in the single-kernel
     # V-cycle; "0": every level through the level-by-level kernels.
     # fuse 1: the coarse-grid correction is applied inside the first
@@ -101,7 +105,7 @@ def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, fuse, monkeypatch):
     kap = element_field(n, B, seed=300 + n, spread=1.5)
     r = grid_vector(n, B, seed=400 + n)
     ctx = mm.Context(_wl(n0=n, levels=1), cheb_degree=deg, arena_bytes=256 << 20)
-    ctx.set_tuning(fuse=fuse)
+    ctx.set_tuning(fuse=fuse, zvar_fp64=zvar, zvar_fp32=zvar)
     z = mm.from_grid(ctx.vcycle(n, torch.tensor(kap, device=dev), mm.to_grid(torch.tensor(r, device=dev), n)), n)
     z = z.cpu().numpy()
     for b in range(B):
@@ -110,8 +114,9 @@ def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, fuse, monkeypatch):
         assert np.abs(z[b] - want).max() <= 1e-12 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("zvar", [0, 2, 6])
 @pytest.mark.parametrize("deg", [1, 2])
-def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg):
+def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg, zvar):
     # fp32 V-cycles (the mixed path) with and without the fused correction and
     # the PCG update fused with the first smoothing step
     n, B = 32, 3
@@ -119,7 +124,7 @@ def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg):
     qs = []
     for fuse in (3, 2, 1, 0):   # both fusions, update only, prolongation only, none
         ctx = mm.Context(wl, cheb_degree=deg, arena_bytes=512 << 20)
-        ctx.set_tuning(fuse=fuse, vsmall_fp32=0, vsmall_fp64=0)
+        ctx.set_tuning(fuse=fuse, vsmall_fp32=0, vsmall_fp64=0, zvar_fp32=zvar, zvar_fp64=zvar)
         xi = ctx.draw_xi(0, 21, B)
         kap = ctx.field(n, xi)
         u, it = ctx.solve(n, kap)
