@@ -227,6 +227,22 @@ def run_c4(args):
     weights = np.array([16.0 ** (wl.levels - 1 - l) for l in range(wl.levels)])
     weights /= weights.sum()
     slots = [int(x) for x in args.slots.split(",")] if args.slots else [2048, 1024, 128, 8, 2]
+    # the bf16 KLE against the fp64 KLE on the same samples (64 per mesh 16^3..64^3)
+    kle_check = None
+    if wl.precision == 2:
+        kle_check = []
+        for l in range(3):
+            qs = []
+            for prec in (1, 2):
+                c = mm.Context(wl, precision=prec, max_batch=64)
+                _, qf, _, _ = c.sample_level(l, 0, 64)
+                qs.append(np.asarray(qf))
+                c.close()
+                del c
+            rel = np.abs(qs[1] - qs[0]) / np.abs(qs[0])
+            kle_check.append({"mesh": wl.n(l), "samples": 64, "qoi_rel_dev_max": float(rel.max()),
+                              "qoi_rel_dev_mean": float(rel.mean())})
+        torch.cuda.empty_cache()
     ctx = mm.Context(wl, arena_bytes=int(args.arena_gb * 2**30))
     ctx.serve_start(slots)
     rng = np.random.default_rng(4)
@@ -281,8 +297,10 @@ def run_c4(args):
     sat_dofs = dofs_done / args.sat_seconds
     out = {"metric": "serving p50/p99 latency and sample-DOFs/s", "unit": "s",
            "config": {"workload": wl.name, "meshes": [wl.n(l) for l in range(wl.levels)], "slots": slots,
-                      "level_weights": weights.tolist(), "n_modes": wl.n_modes, "kle": "fp64 MFMA",
+                      "level_weights": weights.tolist(), "n_modes": wl.n_modes,
+                      "kle": "bf16 MFMA, fp32 accumulate" if wl.precision == 2 else "fp64 MFMA",
                       "precision": "mixed"},
+           "kle_bf16_vs_fp64": kle_check,
            "saturation": {"requests_per_s": sat_rate, "sample_dofs_per_s": sat_dofs, "clients": clients,
                           "seconds": args.sat_seconds, "kind": "closed loop"},
            "rates": []}

@@ -56,7 +56,13 @@ enum {
 };
 
 enum { MLMC_QOI_DOMAIN_AVERAGE = 0, MLMC_QOI_SUBCUBE_AVERAGE = 1 };
-enum { MLMC_PREC_FP64 = 0, MLMC_PREC_MIXED = 1 };
+/* FP64: every step in fp64.  MIXED: fp32 operator, smoother and multigrid
+ * inside fp64 iterative refinement (fp64 outer residual with the fp64 kappa,
+ * fp64 dot products, recurrences and statistics).  MIXED_BF16KLE: MIXED, and
+ * the KLE contraction with bf16 operands and fp32 accumulation on MFMA -- a
+ * perturbation of the coefficient field itself (|g - g_fp64| <= ~2^-7 sum_m
+ * |sqrt(lambda_m) xi_m phi_m|), reported against the fp64 result. */
+enum { MLMC_PREC_FP64 = 0, MLMC_PREC_MIXED = 1, MLMC_PREC_MIXED_BF16KLE = 2 };
 enum { MLMC_SOLVER_GMG_PCG = 0, MLMC_SOLVER_JACOBI_PCG = 1 };
 
 typedef struct mlmc_config {
@@ -134,7 +140,8 @@ int mlmc_draw_xi(mlmc_ctx* ctx, int32_t level, uint64_t first, int64_t count, do
 /* K2 -- kappa (device, element layout, fp64) = exp(sum_m sqrt(lambda_m)
  * phi_m(c_e) xi_m) at the element centroids c_e of the n^3 mesh, for `count`
  * samples whose xi (device, [count][n_modes]) is given.  Log-normal KLE
- * coefficient of Sec. 5.2; the contraction runs on fp64 MFMA.
+ * coefficient of Sec. 5.2; the contraction runs on fp64 MFMA (on bf16 MFMA
+ * with fp32 accumulation under MLMC_PREC_MIXED_BF16KLE).
  * kappa32 (device, may be NULL) receives the same values rounded to fp32. */
 int mlmc_field(mlmc_ctx* ctx, int32_t n, int64_t count, const double* xi,
                double* kappa, float* kappa32);
@@ -226,7 +233,8 @@ typedef struct mlmc_tuning {
 /* Fusion bits of mlmc_tuning.fuse. */
 enum {
   MLMC_FUSE_PROLONG = 1,  /* coarse-grid correction applied inside the first post-smoothing step */
-  MLMC_FUSE_UPDATE = 2    /* PCG x/r update fused with the first smoothing step of the next V-cycle */
+  MLMC_FUSE_UPDATE = 2,   /* PCG x/r update fused with the first smoothing step of the next V-cycle */
+  MLMC_FUSE_REFINE = 4    /* mixed precision: correction, fp64 residual and its demotion in one pass */
 };
 
 int mlmc_get_tuning(const mlmc_ctx* ctx, mlmc_tuning* out);

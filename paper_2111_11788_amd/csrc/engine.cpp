@@ -37,7 +37,7 @@ int validate(const mlmc_config* c, std::string& why) {
   // the subcube QoI needs 4 | n on every mesh that is solved
   if (c->qoi == 1 && c->n0 < 4) { why = "subcube QoI needs n0 >= 4"; return MLMC_E_INVALID; }
   if (!(c->rtol > 0.0) || c->max_iter < 1) { why = "need rtol > 0 and max_iter >= 1"; return MLMC_E_INVALID; }
-  if (c->precision != 0 && c->precision != 1) { why = "unknown precision"; return MLMC_E_INVALID; }
+  if (c->precision < MLMC_PREC_FP64 || c->precision > MLMC_PREC_MIXED_BF16KLE) { why = "unknown precision"; return MLMC_E_INVALID; }
   if (c->solver != 0 && c->solver != 1) { why = "unknown solver"; return MLMC_E_INVALID; }
   if (c->cheb_degree < 0 || c->cheb_degree > 8) { why = "cheb_degree must be in 0..8"; return MLMC_E_INVALID; }
   if (c->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
@@ -139,7 +139,8 @@ int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float
   if (int rc = ensure_tables(ctx, n, &tab)) return rc;
   const int M = ctx->cfg.n_modes;
   LAUNCH(MLMC_K_FIELD, (double)B * elems(n) * (8.0 + (kap32 ? 4.0 : 0.0)) + (double)B * M * 8.0,
-         launch_field(n, M, B, xi, ctx->d_sqrtlam, ctx->d_triples, tab, ctx->K1, kap, kap32, ctx->st));
+         launch_field(n, M, B, xi, ctx->d_sqrtlam, ctx->d_triples, tab, ctx->K1, kap, kap32, ctx->st, nullptr,
+                      ctx->cfg.precision == MLMC_PREC_MIXED_BF16KLE));
   return MLMC_OK;
 }
 
@@ -383,28 +384,71 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
     for (size_t l = 1; l < L.size(); ++l)
       LAUNCH(kid<float>(MLMC_K_COARSEN), (elems(L[l - 1].n) + elems(L[l].n)) * B * 4,
              launch_coarsen<float>(L[l - 1].n, B, L[l - 1].kap, L[l].kap, st));
-    LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, u, 0.0, nullptr, st));
-    LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, w.r64, h3, nullptr, st));
-    LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double>(n, B, w.r64, w.r64, O, &np, st)));
-    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
     HIPCHK(hipMemsetAsync(I.iters, 0, B * sizeof(int), st));
-    for (int outer = 0; outer < kMaxOuter && total_it < ctx->cfg.max_iter; ++outer) {
-      LAUNCHM(MLMC_K_MISC, d * 12, O.active, B, launch_demote(n, B, w.r64, w.rin, O, st));
-      HIPCHK(hipMemcpyAsync(I.active, O.active, B * sizeof(int), hipMemcpyDeviceToDevice, st));
-      LAUNCHM(MLMC_K_MISC, d * 4, O.active, B, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
-      LAUNCHM(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, I.active, B, (launch_dot<float>(n, B, w.rin, w.rin, I, &np, st)));
-      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, I, nullptr, st));
-      int it = 0;
-      if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it, &it,
-                             &w.iter_exec[1]))
-        return rc;
-      total_it += it;
-      LAUNCHM(MLMC_K_MISC, d * 20, O.active, B, launch_add_correction(n, B, u, w.d, O, st));
-      LAUNCHM(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, O.active, B, launch_true_residual(n, B, kap, h3, u, w.r64, O, &np, st, zv<double>(ctx)));
-      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
-      int na = 0;
-      if (int rc = count_active(ctx, O, B, &na)) return rc;
-      if (na == 0) break;
+    if (ctx->fuse & MLMC_FUSE_REFINE) {
+      // Each refinement step writes u + d into the other of two fp64 buffers
+      // (its neighbours' u is still being read), the residual of the result
+      // demoted to fp32 as the next inner right-hand side, and its fp64 norm;
+      // `alt` records which buffer holds each sample's last iterate.
+      LAUNCH(MLMC_K_MISC, d * 4, launch_fill_interior<float>(n, B, w.rin, h3, nullptr, st));
+      LAUNCH(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, (launch_dot<float>(n, B, w.rin, w.rin, O, &np, st)));
+      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
+      HIPCHK(hipMemsetAsync(w.alt, 0, B * sizeof(int), st));
+      double* bufs[2] = {u, w.r64};
+      const double* ucur = nullptr;   // zero iterate
+      int next = 0;
+      for (int outer = 0; outer < kMaxOuter && total_it < ctx->cfg.max_iter; ++outer) {
+        HIPCHK(hipMemcpyAsync(I.active, O.active, B * sizeof(int), hipMemcpyDeviceToDevice, st));
+        // inner ||b||^2 = the sums just reduced for the outer residual
+        SolveState Ib = I;
+        Ib.partial = O.partial;
+        Ib.pstride = O.pstride;
+        LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, Ib, nullptr, st));
+        LAUNCHM(MLMC_K_MISC, d * 4, O.active, B, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
+        int it = 0;
+        if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it,
+                               &it, &w.iter_exec[1]))
+          return rc;
+        total_it += it;
+        double* uout = bufs[next];
+        LAUNCHM(MLMC_K_TRUE_RESIDUAL, ((ucur ? 8 : 0) + 4 + 8 + 4) * d + 8 * e, O.active, B,
+                launch_refine(n, B, kap, h3, ucur, w.d, uout, w.rin, O, &np, st, zv<double>(ctx)));
+        LAUNCH(MLMC_K_MISC, 0, launch_set_phase_mask(B, O.active, w.alt, next, nullptr, st));
+        LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
+        ucur = uout;
+        next ^= 1;
+        int na = 0;
+        if (int rc = count_active(ctx, O, B, &na)) return rc;
+        if (na == 0) break;
+      }
+      SolveState moved = O;
+      moved.active = w.alt;
+      LAUNCH(MLMC_K_MISC, 0, launch_copy<double>(n, B, w.r64, u, moved, st));
+    } else {
+      LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, u, 0.0, nullptr, st));
+      LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, w.r64, h3, nullptr, st));
+      LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double>(n, B, w.r64, w.r64, O, &np, st)));
+      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
+      for (int outer = 0; outer < kMaxOuter && total_it < ctx->cfg.max_iter; ++outer) {
+        LAUNCHM(MLMC_K_MISC, d * 12, O.active, B, launch_demote(n, B, w.r64, w.rin, O, st));
+        HIPCHK(hipMemcpyAsync(I.active, O.active, B * sizeof(int), hipMemcpyDeviceToDevice, st));
+        LAUNCHM(MLMC_K_MISC, d * 4, O.active, B, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
+        LAUNCHM(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, I.active, B,
+                (launch_dot<float>(n, B, w.rin, w.rin, I, &np, st)));
+        LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, I, nullptr, st));
+        int it = 0;
+        if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it, &it,
+                               &w.iter_exec[1]))
+          return rc;
+        total_it += it;
+        LAUNCHM(MLMC_K_MISC, d * 20, O.active, B, launch_add_correction(n, B, u, w.d, O, st));
+        LAUNCHM(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, O.active, B,
+                launch_true_residual(n, B, kap, h3, u, w.r64, O, &np, st, zv<double>(ctx)));
+        LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
+        int na = 0;
+        if (int rc = count_active(ctx, O, B, &na)) return rc;
+        if (na == 0) break;
+      }
     }
     // report inner iterations as the sample's iteration count
     HIPCHK(hipMemcpyAsync(O.iters, I.iters, B * sizeof(int), hipMemcpyDeviceToDevice, st));
@@ -442,7 +486,7 @@ int run_level(mlmc_ctx* ctx, int level, uint64_t first, uint64_t count, double* 
     const uint64_t start = first + done;
     LAUNCH(MLMC_K_XI, (double)B * ctx->cfg.n_modes * 8,
            launch_draw_xi(ctx->cfg.seed, level, start, B, ctx->cfg.n_modes, w.xi, ctx->st));
-    const bool mixed = ctx->cfg.precision == MLMC_PREC_MIXED;
+    const bool mixed = ctx->cfg.precision != MLMC_PREC_FP64;
     if (int rc = field_impl(ctx, nf, B, w.xi, w.kf, mixed ? w.wf.L32[0].kap : nullptr)) return rc;
     bool conv = false;
     if (int rc = solve_impl(ctx, w.wf, w.kf, w.uf, iters ? iters + done : nullptr, &conv, mixed)) return rc;
@@ -487,7 +531,7 @@ int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (t->cheb_degree < 1 || t->cheb_degree > 8) { why = "cheb_degree must be in 1..8"; return MLMC_E_INVALID; }
   if (t->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
   if (t->graph_batch < 0 || t->graph_batch > 16) { why = "graph_batch must be in 0..16"; return MLMC_E_INVALID; }
-  if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
+  if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
   return MLMC_OK;
 }
 

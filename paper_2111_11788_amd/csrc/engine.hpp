@@ -105,6 +105,7 @@ struct SolveWork {
   double *r = nullptr, *p = nullptr, *q = nullptr;          // fp64 PCG
   double* r64 = nullptr;                                    // fp64 refinement residual
   float *d = nullptr, *rin = nullptr, *p32 = nullptr, *q32 = nullptr;  // fp32 inner PCG
+  int* alt = nullptr;   // mixed: 1 where the sample's last refined iterate is in r64 (second buffer)
   StateBufs outer, inner;
   // captured PCG iteration per precision (0: fp64, 1: fp32); tied to the buffers above
   hipGraphExec_t iter_exec[2] = {nullptr, nullptr};
@@ -141,6 +142,7 @@ struct SolveWork {
       }
     } else {
       inner.carve(cv, B, n);
+      alt = cv.take<int>(B);
       r64 = cv.take<double>(B * S0);
       d = cv.take<float>(B * S0);
       rin = cv.take<float>(B * S0);
@@ -230,7 +232,7 @@ struct mlmc_ctx {
   bool use_graphs = true;         // replay the PCG iteration from a captured hipGraph
   bool own_stream = false;        // the context created st itself
   int graph_batch = 2;            // graph launches per convergence check
-  int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE;   // MLMC_FUSE_* bits in use
+  int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE;   // MLMC_FUSE_* bits in use
   mlmc_server* server = nullptr;  // serving pools and threads while serving
 };
 

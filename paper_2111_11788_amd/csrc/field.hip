@@ -40,19 +40,27 @@ __global__ void __launch_bounds__(256) k_field(int n, int M, int64_t count,
   __shared__ double xs[BS][kKc + 1];
   __shared__ double ph[BE][kKc + 1];
 
-  const int64_t ne = (int64_t)n * n * n;
-  const int64_t e0 = (int64_t)blockIdx.x * BE;
+  // The tile's BE elements are consecutive and n is a power of two, so the
+  // tile covers TR = max(1, BE / n) whole or partial x-rows; the y-z factor
+  // phi_j(y) phi_k(z) of a mode is shared by every element of a row.
+  // TR = min(BE / n, n^2) <= 32 over all powers of two n (n = 8: 32 rows)
+  __shared__ double wyz[32][kKc];
+  const int ne = n * n * n;                  // <= 2^27 for the meshes in use
+  const int e0 = (int)blockIdx.x * BE;
   const int64_t s0 = (int64_t)blockIdx.y * BS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ws = wave % WS, we = wave / WS;
-  const int n2 = n * n;
+  const int lg = 31 - __clz(n);
+  const int TR = BE > n ? (BE / n < n * n ? BE / n : n * n) : 1;
+  const int row0 = e0 >> lg;                 // first x-row (ey + n ez) of the tile
 
   d4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
   for (int m0 = 0; m0 < M; m0 += kKc) {
-    // stage Xi (scaled by sqrt(lambda)) and the Phi tile
+    // stage Xi (scaled by sqrt(lambda)), the y-z factors of the tile rows,
+    // then the Phi tile = phi_i(x) * y-z factor
     for (int q = tid; q < BS * kKc; q += 256) {
       const int r = q / kKc, c = q % kKc;
       const int64_t s = s0 + r;
@@ -60,16 +68,24 @@ __global__ void __launch_bounds__(256) k_field(int n, int M, int64_t count,
       const int64_t row = (s < count && rowmap) ? rowmap[s] : s;
       xs[r][c] = (s < count && m < M) ? xi[row * M + m] * sqrtlam[m] : 0.0;
     }
+    for (int q = tid; q < TR * kKc; q += 256) {
+      const int tr = q / kKc, c = q % kKc;
+      const int m = m0 + c;
+      const int xr = row0 + tr;              // x-row index ey + n ez
+      double v = 0.0;
+      if (m < M && xr < n * n) {
+        const int ey = xr & (n - 1), ez = xr >> lg;
+        v = tab[ey * K1 + triples[3 * m + 1]] * tab[ez * K1 + triples[3 * m + 2]];
+      }
+      wyz[tr][c] = v;
+    }
+    __syncthreads();
     for (int q = tid; q < BE * kKc; q += 256) {
       const int r = q / kKc, c = q % kKc;
-      const int64_t e = e0 + r;
+      const int e = e0 + r;
       const int m = m0 + c;
       double v = 0.0;
-      if (e < ne && m < M) {
-        const int ex = (int)(e % n), ey = (int)((e / n) % n), ez = (int)(e / n2);
-        const int* t3 = triples + 3 * m;
-        v = tab[ex * K1 + t3[0]] * tab[ey * K1 + t3[1]] * tab[ez * K1 + t3[2]];
-      }
+      if (e < ne && m < M) v = tab[(e & (n - 1)) * K1 + triples[3 * m]] * wyz[(e >> lg) - row0][c];
       ph[r][c] = v;
     }
     __syncthreads();
@@ -87,15 +103,111 @@ __global__ void __launch_bounds__(256) k_field(int n, int M, int64_t count,
 
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int64_t e = e0 + 64 * we + 16 * t + (lane & 15);
+    const int64_t e = (int64_t)e0 + 64 * we + 16 * t + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t s = s0 + 16 * ws + (lane >> 4) + 4 * r;
       if (s < count && e < ne) {
         const int64_t row = rowmap ? rowmap[s] : s;
         const double k = exp(acc[t][r]);
-        kappa[row * ne + e] = k;
-        if (kappa32) kappa32[row * ne + e] = (float)k;
+        kappa[row * (int64_t)ne + e] = k;
+        if (kappa32) kappa32[row * (int64_t)ne + e] = (float)k;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- bf16 MFMA
+// The same contraction with bf16 operands and fp32 accumulation on
+// v_mfma_f32_16x16x32_bf16 (gfx950): lane l supplies A[l % 16][8 (l / 16) + v]
+// and B[8 (l / 16) + v][l % 16], v = 0..7, and accumulator element r holds
+// D[4 (l / 16) + r][l % 16] (checked on gfx950 with a probe of one-hot
+// operands).  Xi sqrt(lambda) and Phi are formed in fp64 and rounded to bf16
+// (unit roundoff 2^-8), so |g - g_exact| <= (2 u + u^2 + M 2^-24) sum_m
+// |Xi_m Phi_m|; kappa = exp(g) is evaluated in fp64 from the fp32 sum.  This
+// changes the coefficient field itself (a model perturbation of up to ~1% in
+// kappa for |g| of a few units), not just the route to it.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int kKb = 32;        // modes per stage (one MFMA k-step)
+constexpr int kKbPad = 40;     // LDS row pitch in bf16 (16-byte aligned rows)
+
+template <int BS>
+__global__ void __launch_bounds__(256) k_field_bf16(int n, int M, int64_t count,
+                                                    const double* __restrict__ xi,
+                                                    const double* __restrict__ sqrtlam,
+                                                    const int* __restrict__ triples,
+                                                    const double* __restrict__ tab, int K1,
+                                                    double* __restrict__ kappa, float* __restrict__ kappa32,
+                                                    const int* __restrict__ rowmap) {
+  constexpr int WS = BS / 16;
+  constexpr int WE = 4 / WS;
+  constexpr int BE = 64 * WE;
+  __shared__ __align__(16) __bf16 xs[BS][kKbPad];
+  __shared__ __align__(16) __bf16 ph[BE][kKbPad];
+  __shared__ double wyz[32][kKb];
+  const int ne = n * n * n;
+  const int e0 = (int)blockIdx.x * BE;
+  const int64_t s0 = (int64_t)blockIdx.y * BS;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ws = wave % WS, we = wave / WS;
+  const int lg = 31 - __clz(n);
+  const int TR = BE > n ? (BE / n < n * n ? BE / n : n * n) : 1;
+  const int row0 = e0 >> lg;
+
+  f4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int m0 = 0; m0 < M; m0 += kKb) {
+    for (int q = tid; q < BS * kKb; q += 256) {
+      const int r = q / kKb, c = q % kKb;
+      const int64_t s = s0 + r;
+      const int m = m0 + c;
+      const int64_t row = (s < count && rowmap) ? rowmap[s] : s;
+      xs[r][c] = (__bf16)(float)((s < count && m < M) ? xi[row * M + m] * sqrtlam[m] : 0.0);
+    }
+    for (int q = tid; q < TR * kKb; q += 256) {
+      const int tr = q / kKb, c = q % kKb;
+      const int m = m0 + c;
+      const int xr = row0 + tr;
+      double v = 0.0;
+      if (m < M && xr < n * n) {
+        const int ey = xr & (n - 1), ez = xr >> lg;
+        v = tab[ey * K1 + triples[3 * m + 1]] * tab[ez * K1 + triples[3 * m + 2]];
+      }
+      wyz[tr][c] = v;
+    }
+    __syncthreads();
+    for (int q = tid; q < BE * kKb; q += 256) {
+      const int r = q / kKb, c = q % kKb;
+      const int e = e0 + r;
+      const int m = m0 + c;
+      double v = 0.0;
+      if (e < ne && m < M) v = tab[(e & (n - 1)) * K1 + triples[3 * m]] * wyz[(e >> lg) - row0][c];
+      ph[r][c] = (__bf16)(float)v;
+    }
+    __syncthreads();
+    const bf8 a = *reinterpret_cast<const bf8*>(&xs[16 * ws + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bf8 b = *reinterpret_cast<const bf8*>(&ph[64 * we + 16 * t + (lane & 15)][8 * (lane >> 4)]);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t e = (int64_t)e0 + 64 * we + 16 * t + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t s = s0 + 16 * ws + 4 * (lane >> 4) + r;
+      if (s < count && e < ne) {
+        const int64_t row = rowmap ? rowmap[s] : s;
+        const double k = exp((double)acc[t][r]);
+        kappa[row * (int64_t)ne + e] = k;
+        if (kappa32) kappa32[row * (int64_t)ne + e] = (float)k;
       }
     }
   }
@@ -105,9 +217,21 @@ __global__ void __launch_bounds__(256) k_field(int n, int M, int64_t count,
 
 hipError_t launch_field(int n, int M, int64_t count, const double* xi, const double* sqrtlam,
                         const int* triples, const double* tab, int K1, double* kappa,
-                        float* kappa32, hipStream_t st, const int* rowmap) {
+                        float* kappa32, hipStream_t st, const int* rowmap, bool bf16) {
   if (count <= 0) return hipSuccess;
   const int64_t ne = (int64_t)n * n * n;
+  if (bf16) {
+    if (count >= 48) {
+      dim3 grid((unsigned)((ne + 63) / 64), (unsigned)((count + 63) / 64));
+      k_field_bf16<64><<<grid, dim3(256), 0, st>>>(n, M, count, xi, sqrtlam, triples, tab, K1, kappa, kappa32,
+                                                   rowmap);
+    } else {
+      dim3 grid((unsigned)((ne + 255) / 256), (unsigned)((count + 15) / 16));
+      k_field_bf16<16><<<grid, dim3(256), 0, st>>>(n, M, count, xi, sqrtlam, triples, tab, K1, kappa, kappa32,
+                                                   rowmap);
+    }
+    return hipGetLastError();
+  }
   if (count >= 48) {
     dim3 grid((unsigned)((ne + 63) / 64), (unsigned)((count + 63) / 64));
     k_field<64><<<grid, dim3(256), 0, st>>>(n, M, count, xi, sqrtlam, triples, tab, K1, kappa, kappa32, rowmap);

@@ -15,9 +15,10 @@ hipError_t launch_draw_xi_rows(uint64_t seed, int64_t count, int M, const uint64
 
 // field.hip: kappa[b][e] = exp(sum_m xi[b][m] sqrtlam[m] tab[ex][t0] tab[ey][t1] tab[ez][t2])
 // rowmap (may be null): row r reads xi row rowmap[r] and writes kappa slot rowmap[r]
+// bf16: the contraction with bf16 operands and fp32 accumulation
 hipError_t launch_field(int n, int M, int64_t count, const double* xi, const double* sqrtlam,
                         const int* triples, const double* tab, int K1, double* kappa,
-                        float* kappa32, hipStream_t st, const int* rowmap = nullptr);
+                        float* kappa32, hipStream_t st, const int* rowmap = nullptr, bool bf16 = false);
 
 // Per-sample scalar state of a batched Krylov solve (device arrays of B entries).
 struct SolveState {
@@ -112,6 +113,11 @@ hipError_t launch_dot(int n, int B, const T* a, const T* b, SolveState s, uint32
 template <class T>
 hipError_t launch_pcg_direction(int n, int B, const T* z, T* p, SolveState s, hipStream_t st);
 // outer residual of the refinement loop: r = b - A x in fp64 plus ||r||^2 partials
+// One fp64 refinement step with the inner correction applied on the fly:
+// uout = u + d (u may be null: zero), rin = fp32(bconst - A uout), partial sums
+// of (bconst - A uout) . itself in fp64.  uout must not alias u or d.
+hipError_t launch_refine(int n, int B, const double* kap, double bconst, const double* u, const float* d,
+                         double* uout, float* rin, SolveState s, uint32_t* nparts, hipStream_t st, int var = 0);
 hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x,
                                 double* r, SolveState s, uint32_t* nparts, hipStream_t st,
                                 int var = 0);

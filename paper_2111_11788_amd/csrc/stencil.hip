@@ -178,6 +178,32 @@ struct EpiTrueResidual {
   }
 };
 
+// fp64 refinement step with the correction applied on the fly: the operand
+// is u_new = u + d (fp32 d), and the kernel writes u_new to a second buffer,
+// the fp64 residual r = bconst - A u_new demoted to fp32 (the next inner
+// right-hand side), and the fp64 partial sums of r . r.
+template <class T, int V>
+struct EpiRefine {
+  static constexpr bool kReduce = true;
+  static constexpr bool kBegin = false;
+  T bconst;
+  T* uout;
+  float* rin;
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
+    T us[V];
+    float f[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const T r = ok[v] ? bconst - au[v] : T(0);
+      acc += (double)r * (double)r;
+      f[v] = (float)r;
+      us[v] = ok[v] ? uc[v] : T(0);
+    }
+    vstore<T, V>(uout + pos, us);
+    vstore<float, V>(rin + pos, f);
+  }
+};
+
 // x0 = 0 Chebyshev step: out = c2 D^-1 b (needs only the kappa window)
 template <class T, int V>
 struct EpiChebZero {
@@ -247,12 +273,16 @@ struct EpiPcgUpdateZero {
 // of two coarse planes x three coarse rows (the parents of the thread's three
 // fine rows) is kept in registers; a new coarse plane is loaded every second
 // fine plane.
-template <class T, int V, bool NEED_U, bool PF, bool PRO, class Epi>
+// ADDD: the operand is u + d with d an fp32 vector in the same layout (u may
+// be null: zero).
+template <class T, int V, bool NEED_U, bool PF, bool PRO, bool ADDD, class Epi>
 __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, const T* __restrict__ u,
                                                 const T* __restrict__ kap, const int* __restrict__ active,
                                                 double* __restrict__ partial, uint32_t pstride, Epi epi,
-                                                const T* __restrict__ xc, size_t cstride) {
+                                                const T* __restrict__ xc, size_t cstride,
+                                                const float* __restrict__ dadd) {
   static_assert(!(PRO && (PF || !NEED_U)), "the fused prolongation uses the plain u window");
+  static_assert(!(ADDD && (PF || PRO || !NEED_U)), "the added vector uses the plain u window");
   const uint32_t per = g.parts();
   const uint32_t lin = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t b = lin / per;
@@ -270,7 +300,8 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
   double acc = 0.0;
   if constexpr (Epi::kBegin) epi.begin(b);
   if (valid) {
-    const T* ub = u + (size_t)b * stride;
+    const T* ub = u ? u + (size_t)b * stride : nullptr;
+    const float* db = ADDD ? dadd + (size_t)b * stride : nullptr;
     const T* kb = kap + (size_t)b * n2 * n;
     bool ok[V];
 #pragma unroll
@@ -280,10 +311,25 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
     T PU[PF ? 3 : 1][V + 2];
     T PK[PF ? 2 : 1][V + 1];
     auto load_urow = [&](T* dst, int r, int kk) {
-      const T* row = ub + (size_t)n * (j - 1 + r) + (size_t)n2 * kk;
-      dst[0] = i0 > 0 ? row[i0 - 1] : T(0);
-      vload<T, V>(row + i0, dst + 1);
-      dst[V + 1] = row[i0 + V];   // position n is the next row's zero
+      const size_t off = (size_t)n * (j - 1 + r) + (size_t)n2 * kk;
+      if (!ADDD || ub) {
+        const T* row = ub + off;
+        dst[0] = i0 > 0 ? row[i0 - 1] : T(0);
+        vload<T, V>(row + i0, dst + 1);
+        dst[V + 1] = row[i0 + V];   // position n is the next row's zero
+      } else {
+#pragma unroll
+        for (int c = 0; c < V + 2; ++c) dst[c] = T(0);
+      }
+      if (ADDD) {
+        const float* drow = db + off;
+        float dv[V];
+        vload<float, V>(drow + i0, dv);
+        dst[0] += i0 > 0 ? (T)drow[i0 - 1] : T(0);
+#pragma unroll
+        for (int v = 0; v < V; ++v) dst[1 + v] += (T)dv[v];
+        dst[V + 1] += (T)drow[i0 + V];
+      }
     };
     auto load_krow = [&](T* dst, int r, int ez) {
       const T* row = kb + (size_t)n * (j - 1 + r) + (size_t)n2 * ez;
@@ -475,12 +521,15 @@ inline size_t zlds_bytes(const ZGeom& g) {
   return ((size_t)3 * (g.rows + 2) * zlds_urs<T>(g.n) + (size_t)2 * (g.rows + 1) * zlds_krs<T>(g.n)) * sizeof(T);
 }
 
-template <class T, int V, bool NEED_U, bool PRO, class Epi>
+template <class T, int V, bool NEED_U, bool PRO, bool ADDD, class Epi>
 __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const T* __restrict__ u,
                                               const T* __restrict__ kap, const int* __restrict__ active,
                                               double* __restrict__ partial, uint32_t pstride, Epi epi,
-                                              const T* __restrict__ xc, size_t cstride) {
+                                              const T* __restrict__ xc, size_t cstride,
+                                              const float* __restrict__ dadd) {
   static_assert(!PRO || NEED_U, "the fused prolongation needs the u operand");
+  static_assert(!ADDD || (NEED_U && !PRO), "the added vector needs the plain u operand");
+  typedef typename Vec<float, V>::type fvt;
   typedef typename Vec<T, V>::type vt;
   extern __shared__ __align__(16) unsigned char zsmem[];
   const uint32_t per = g.parts();
@@ -502,7 +551,8 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   const int gx = tid % G, jr = tid / G;
   const int j = j0 + jr, i0 = gx * V;
   const bool valid = jr < R && j <= n - 1 && k0 < k1;
-  const T* ub = NEED_U ? u + (size_t)b * stride : nullptr;
+  const T* ub = (NEED_U && u) ? u + (size_t)b * stride : nullptr;
+  const float* db = ADDD ? dadd + (size_t)b * stride : nullptr;
   const T* kb = kap + (size_t)b * n2 * n;
   const T* cb = PRO ? xc + (size_t)b * cstride : nullptr;
   const int nc = n >> 1, nc2 = nc * nc;
@@ -518,6 +568,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   // staging: up to two 16-byte vectors per thread per plane for u and kappa;
   // a thread stages the same (row, column) positions on every plane
   vt pu[2], pk[2];
+  fvt pd[ADDD ? 2 : 1];
   // PRO: per staged vector, the coarse values I0 .. I0+V/2 of its parent rows
   // Jlo = jj/2, Jhi = (jj+1)/2 on coarse planes cK and cK+1 (the parents of
   // fine planes 2cK and 2cK+1), refreshed every second fine plane
@@ -566,7 +617,12 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
       const int v = tid + m * nthr;
       const int r = v / G, c = v - (v / G) * G;
       const int jj = j0 - 1 + r;
-      if (v < UR * G && jj <= n) pu[m] = *reinterpret_cast<const vt*>(ub + (size_t)n2 * kk + (size_t)n * jj + c * V);
+      if (v < UR * G && jj <= n) {
+        const size_t off = (size_t)n2 * kk + (size_t)n * jj + c * V;
+        if (!ADDD || ub) pu[m] = *reinterpret_cast<const vt*>(ub + off);
+        else pu[m] = vt{};
+        if (ADDD) pd[ADDD ? m : 0] = *reinterpret_cast<const fvt*>(db + off);
+      }
     }
   };
   // store the plane kk fetched last (the loads were in flight meanwhile);
@@ -591,6 +647,10 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
 #pragma unroll
           for (int t = 0; t < V; ++t)
             pu[m][t] += (t & 1) ? T(0.5) * (L[(t - 1) / 2] + L[(t + 1) / 2]) : L[t / 2];
+        }
+        if (ADDD) {
+#pragma unroll
+          for (int t = 0; t < V; ++t) pu[m][t] += (T)pd[ADDD ? m : 0][t];
         }
         *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + V + c * V) = pu[m];
       }
@@ -729,15 +789,16 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   }
 }
 
-template <class T, bool NEED_U, bool PRO, class Epi>
+template <class T, bool NEED_U, bool PRO, class Epi, bool ADDD = false>
 hipError_t zlaunch_lds(int n, int B, const T* u, const T* xc, const T* kap, const int* active, double* partial,
-                       uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st) {
+                       uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st, const float* dadd = nullptr) {
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
-  k_zlds<T, V, NEED_U, PRO, Epi><<<dim3(blocks), dim3(g.threads), zlds_bytes<T>(g), st>>>(
-      g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, PRO ? grid_stride(n / 2) : 0);
+  k_zlds<T, V, NEED_U, PRO, ADDD, Epi><<<dim3(blocks), dim3(g.threads), zlds_bytes<T>(g), st>>>(
+      g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, PRO ? grid_stride(n / 2) : 0,
+      dadd);
   return hipGetLastError();
 }
 
@@ -751,11 +812,27 @@ hipError_t zlaunch(int n, int B, const T* u, const T* kap, const int* active, do
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
   if (var & ZVAR_PREFETCH)
-    k_zmarch<T, V, NEED_U, true, false, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
-        g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, nullptr, 0);
+    k_zmarch<T, V, NEED_U, true, false, false, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
+        g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, nullptr, 0, nullptr);
   else
-    k_zmarch<T, V, NEED_U, false, false, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
-        g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, nullptr, 0);
+    k_zmarch<T, V, NEED_U, false, false, false, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
+        g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, nullptr, 0, nullptr);
+  return hipGetLastError();
+}
+
+// the operand is u + d (d fp32, same layout; u may be null)
+template <class T, class Epi>
+hipError_t zlaunch_addd(int n, int B, const T* u, const float* d, const T* kap, const int* active, double* partial,
+                        uint32_t pstride, Epi epi, uint32_t* nparts, int var, hipStream_t st) {
+  if (var & ZVAR_LDS)
+    return zlaunch_lds<T, true, false, Epi, true>(n, B, u, nullptr, kap, active, partial, pstride, epi, nparts, st,
+                                                  d);
+  constexpr int V = ZV<T>::V;
+  const ZGeom g = zgeom<T>(n, B);
+  if (nparts) *nparts = g.parts();
+  const uint32_t blocks = g.parts() * (uint32_t)B;
+  k_zmarch<T, V, true, false, false, true, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
+      g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, nullptr, 0, d);
   return hipGetLastError();
 }
 
@@ -769,8 +846,8 @@ hipError_t zlaunch_pro(int n, int B, const T* u, const T* xc, const T* kap, cons
   const ZGeom g = zgeom<T>(n, B);
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
-  k_zmarch<T, V, true, false, true, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
-      g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, grid_stride(n / 2));
+  k_zmarch<T, V, true, false, true, false, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
+      g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, grid_stride(n / 2), nullptr);
   return hipGetLastError();
 }
 
@@ -1057,6 +1134,12 @@ hipError_t launch_pcg_apply_dot(int n, int B, const T* kap, const T* p, T* q, So
   if (use_small<T>(n))
     return small_launch<T>(5, n, B, kap, p, nullptr, nullptr, q, 0, 0, s.active, s.partial, s.pstride, nparts, st);
   return zlaunch<T, true>(n, B, p, kap, s.active, s.partial, s.pstride, EpiPcgApply<T, ZV<T>::V>{q}, nparts, var, st);
+}
+
+hipError_t launch_refine(int n, int B, const double* kap, double bconst, const double* u, const float* d,
+                         double* uout, float* rin, SolveState s, uint32_t* nparts, hipStream_t st, int var) {
+  return zlaunch_addd<double>(n, B, u, d, kap, s.active, s.partial, s.pstride,
+                              EpiRefine<double, ZV<double>::V>{bconst, uout, rin}, nparts, var, st);
 }
 
 hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x, double* r,

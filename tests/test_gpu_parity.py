@@ -69,6 +69,33 @@ def test_field_matches_oracle(dev, n, M, corr, count):
     assert np.array_equal(k32.cpu().numpy(), got.astype(np.float32))
 
 
+@pytest.mark.parametrize("n,M,corr,count", [(16, 64, 0.2, 20), (8, 256, 0.2, 70), (32, 40, 0.3, 3)])
+def test_bf16_field_within_its_rounding_bound(dev, n, M, corr, count):
+    # bf16 operands (unit roundoff u = 2^-8) and fp32 accumulation: the log-field
+    # differs from the fp64 one by at most (2u + u^2 + M 2^-24) sum_m |terms|
+    # (plus the double rounding fp64 -> fp32 -> bf16 of each operand, 2^-24);
+    # count 70 takes the 64-sample tile, 20 and 3 the 16-sample tile
+    wl = _wl(n0=n, levels=1, n_modes=M, corr_len=corr, precision=2)
+    ctx = mm.Context(wl, arena_bytes=64 << 20)
+    xi = ctx.draw_xi(0, 5, count)
+    k, k32 = ctx.field(n, xi, want32=True)
+    got = np.log(k.cpu().numpy())
+    xih = rng.draw_xi(wl.seed, 0, 5, count, M)
+    g = field.log_field(n, corr, 1.0, M, xih)
+    tab, triples, lam3 = field.centroid_tables(n, corr, 1.0, M)
+    u = 2.0 ** -8
+    fac = 2 * (u + 2.0 ** -24) + (u + 2.0 ** -24) ** 2 + M * 2.0 ** -24
+    for ez in range(n):
+        terms = np.abs(xih) @ np.abs(field.mode_plane(tab, triples, lam3, ez)).T   # [count, n^2]
+        sl = slice(ez * n * n, (ez + 1) * n * n)
+        err = np.abs(got[:, sl] - g[:, sl])
+        assert np.all(err <= fac * terms + 1e-12), (ez, (err / terms).max())
+    assert np.array_equal(k32.cpu().numpy(), k.cpu().numpy().astype(np.float32))
+    # the perturbation is real but small: relative kappa error of the order of the bound
+    rel = np.abs(np.exp(got - g) - 1.0)
+    assert rel.max() < 0.05
+
+
 @pytest.mark.parametrize("zvar", [0, 1, 2])
 @pytest.mark.parametrize("n,B", [(4, 3), (8, 5), (16, 2), (32, 1)])
 def test_apply_matches_csr(dev, n, B, zvar):
@@ -122,7 +149,7 @@ def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg, zvar):
     n, B = 32, 3
     wl = _wl(n0=n, levels=1, qoi=1, precision=1, solver=0, n_modes=16, corr_len=0.3)
     qs = []
-    for fuse in (3, 2, 1, 0):   # both fusions, update only, prolongation only, none
+    for fuse in (7, 3, 4, 2, 1, 0):   # every fusion bit alone, all, none
         ctx = mm.Context(wl, cheb_degree=deg, arena_bytes=512 << 20)
         ctx.set_tuning(fuse=fuse, vsmall_fp32=0, vsmall_fp64=0, zvar_fp32=zvar, zvar_fp64=zvar)
         xi = ctx.draw_xi(0, 21, B)

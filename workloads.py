@@ -68,7 +68,7 @@ C3 = Workload("mlmc-5level-8-128", n0=8, levels=5, sigma2=1.0, corr_len=0.2,
 
 # Serving mix 16^3 .. 256^3, M = 256, level weights proportional to 16^(4-l).
 C4 = Workload("serving-16-256", n0=16, levels=5, sigma2=1.0, corr_len=0.2,
-              n_modes=256, qoi=0, rtol=1e-8, solver=0, precision=1)
+              n_modes=256, qoi=0, rtol=1e-8, solver=0, precision=2)
 
 # Largest single-GPU stress: 256^3, sigma2 = 2, corr 0.1, M = 512, batches of 4..16.
 C5 = Workload("stress-256cube", n0=256, levels=1, sigma2=2.0, corr_len=0.1,
