@@ -38,21 +38,24 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # per-kernel table and the commands are in the committed counter summary.
 TRAFFIC = {
     "profile": "profiles/batched-64cube-1024_hbm_traffic.txt",
-    "tuning": {"zvar_fp32": 0, "zvar_fp64": 0, "vsmall_fp32": 0, "vsmall_fp64": 0, "cheb_degree": 1,
-               "max_batch": 1024, "graph_batch": 0},
-    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "9d396ea4811a5cbf",
-                  "kernels.hpp": "1329d8f4fc368afe", "krylov.hip": "43366de07857d672",
-                  "stencil.hip": "a1e6bdb9f510a528"},
+    "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 8, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 0, "fuse": 7},
+    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "9d396ea4811a5cbf", "kernels.hpp": "859cb816756d085c", "krylov.hip": "43366de07857d672", "stencil.hip": "338d4362785e3f7d"},
     "bytes_per_launch": {
-        "PCG_UPDATE (f32)": 5433421547, "PCG_DIRECTION (f32)": 2112800183, "RESIDUAL (f32)": 726304811,
-        "CHEB (f32)": 723953032, "CHEB_ZERO (f32)": 531851174, "PCG_APPLY (f32)": 2872205939,
-        "PROLONG (f32)": 363713391, "RESTRICT (f32)": 191025761, "TRUE_RESIDUAL (f64)": 6794866098,
+        "PCG_UPDATE_ZERO (f32)": 6860238689,
+        "CHEB_PROLONG (f32)": 1186485217,
+        "PCG_DIRECTION (f32)": 2031669016,
+        "RESIDUAL (f32)": 1130625514,
+        "CHEB_ZERO (f32)": 366974966,
+        "PCG_APPLY (f32)": 2667414564,
+        "RESTRICT (f32)": 305600674,
+        "TRUE_RESIDUAL (f64)": 7580913435,
     },
 }
 
 
 TRAFFIC_TUNING_KEYS = {
-    "PCG_UPDATE (f32)": ["max_batch"], "PCG_DIRECTION (f32)": ["max_batch"],
+    "PCG_UPDATE (f32)": ["max_batch", "fuse"], "PCG_DIRECTION (f32)": ["max_batch"],
+    "PCG_UPDATE_ZERO (f32)": ["max_batch", "zvar_fp32", "fuse"],
     "PCG_APPLY (f32)": ["max_batch", "zvar_fp32"], "TRUE_RESIDUAL (f64)": ["max_batch", "zvar_fp64"],
 }
 

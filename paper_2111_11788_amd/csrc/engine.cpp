@@ -394,7 +394,11 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       LAUNCH(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, (launch_dot<float>(n, B, w.rin, w.rin, O, &np, st)));
       LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
       HIPCHK(hipMemsetAsync(w.alt, 0, B * sizeof(int), st));
+      // the buffer written by the expected last step is u, so usually no copy
+      // back is needed (steps ~ log(rtol) / log(inner rtol))
+      const int expect = std::max(1, (int)std::ceil(std::log(rtol) / std::log(kInnerRtol) - 1e-9));
       double* bufs[2] = {u, w.r64};
+      if ((expect - 1) % 2 == 1) std::swap(bufs[0], bufs[1]);
       const double* ucur = nullptr;   // zero iterate
       int next = 0;
       for (int outer = 0; outer < kMaxOuter && total_it < ctx->cfg.max_iter; ++outer) {
@@ -413,7 +417,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
         double* uout = bufs[next];
         LAUNCHM(MLMC_K_TRUE_RESIDUAL, ((ucur ? 8 : 0) + 4 + 8 + 4) * d + 8 * e, O.active, B,
                 launch_refine(n, B, kap, h3, ucur, w.d, uout, w.rin, O, &np, st, zv<double>(ctx)));
-        LAUNCH(MLMC_K_MISC, 0, launch_set_phase_mask(B, O.active, w.alt, next, nullptr, st));
+        LAUNCH(MLMC_K_MISC, 0, launch_set_phase_mask(B, O.active, w.alt, uout == w.r64 ? 1 : 0, nullptr, st));
         LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
         ucur = uout;
         next ^= 1;
