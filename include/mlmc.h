@@ -234,7 +234,8 @@ typedef struct mlmc_tuning {
 enum {
   MLMC_FUSE_PROLONG = 1,  /* coarse-grid correction applied inside the first post-smoothing step */
   MLMC_FUSE_UPDATE = 2,   /* PCG x/r update fused with the first smoothing step of the next V-cycle */
-  MLMC_FUSE_REFINE = 4    /* mixed precision: correction, fp64 residual and its demotion in one pass */
+  MLMC_FUSE_REFINE = 4,   /* mixed precision: correction, fp64 residual and its demotion in one pass */
+  MLMC_FUSE_RESTRICT = 8  /* V-cycle residual restricted to the coarse mesh without being stored */
 };
 
 int mlmc_get_tuning(const mlmc_ctx* ctx, mlmc_tuning* out);
@@ -334,7 +335,7 @@ enum {
   MLMC_K_RESIDUAL, MLMC_K_RESTRICT, MLMC_K_PROLONG, MLMC_K_COARSEST, MLMC_K_COARSEN,
   MLMC_K_PCG_APPLY, MLMC_K_PCG_UPDATE, MLMC_K_PCG_DOT, MLMC_K_PCG_DIRECTION,
   MLMC_K_TRUE_RESIDUAL, MLMC_K_REDUCE, MLMC_K_QOI, MLMC_K_MISC, MLMC_K_CHEB_PROLONG,
-  MLMC_K_PCG_UPDATE_ZERO, MLMC_K_COUNT
+  MLMC_K_PCG_UPDATE_ZERO, MLMC_K_RESIDUAL_RESTRICT, MLMC_K_COUNT
 };
 int mlmc_set_profiling(mlmc_ctx* ctx, int32_t on);
 int mlmc_kernel_time(mlmc_ctx* ctx, int32_t kernel_id, int32_t precision, int64_t* launches,

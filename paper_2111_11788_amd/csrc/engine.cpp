@@ -194,10 +194,17 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
                           nullptr, var));
     std::swap(cur, oth);
   }
-  LAUNCHM(kid<T>(MLMC_K_RESIDUAL), (3 * d + e) * sz, active, B, launch_residual<T>(n, B, kap, b, cur, t, active, st, var));
   Level<T>& nx = L[l + 1];
   const double dc = dofs(n / 2) * B;
-  LAUNCHM(kid<T>(MLMC_K_RESTRICT), (d + dc) * sz, active, B, launch_restrict<T>(n, B, t, nx.b, active, st));
+  if ((ctx->fuse & MLMC_FUSE_RESTRICT) && resr_usable<T>(n, B)) {
+    // the residual goes straight into the coarse right-hand side
+    LAUNCHM(kid<T>(MLMC_K_RESIDUAL_RESTRICT), (2 * d + e + dc) * sz, active, B,
+            launch_residual_restrict<T>(n, B, kap, b, cur, nx.b, active, st));
+  } else {
+    LAUNCHM(kid<T>(MLMC_K_RESIDUAL), (3 * d + e) * sz, active, B,
+            launch_residual<T>(n, B, kap, b, cur, t, active, st, var));
+    LAUNCHM(kid<T>(MLMC_K_RESTRICT), (d + dc) * sz, active, B, launch_restrict<T>(n, B, t, nx.b, active, st));
+  }
   T* xc = nullptr;
   if (int rc = vcycle<T>(ctx, L, l + 1, B, nx.b, nx.x, nx.xo, nx.t, active, &xc)) return rc;
   int s0 = 0;
@@ -535,7 +542,7 @@ int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (t->cheb_degree < 1 || t->cheb_degree > 8) { why = "cheb_degree must be in 1..8"; return MLMC_E_INVALID; }
   if (t->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
   if (t->graph_batch < 0 || t->graph_batch > 16) { why = "graph_batch must be in 0..16"; return MLMC_E_INVALID; }
-  if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
+  if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
   return MLMC_OK;
 }
 

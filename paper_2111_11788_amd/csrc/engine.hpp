@@ -232,7 +232,7 @@ struct mlmc_ctx {
   bool use_graphs = true;         // replay the PCG iteration from a captured hipGraph
   bool own_stream = false;        // the context created st itself
   int graph_batch = 2;            // graph launches per convergence check
-  int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE;   // MLMC_FUSE_* bits in use
+  int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT;   // MLMC_FUSE_* bits
   mlmc_server* server = nullptr;  // serving pools and threads while serving
 };
 

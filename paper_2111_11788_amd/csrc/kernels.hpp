@@ -78,6 +78,13 @@ hipError_t launch_pcg_update_zero(int n, int B, const T* kap, T* x, const T* p, 
                                   SolveState s, uint32_t* nparts, hipStream_t st, int var = 0);
 template <class T>
 hipError_t launch_restrict(int nf, int B, const T* rf, T* bc, const int* active, hipStream_t st);
+// bc = P^T (b - A x) on the n/2 mesh (full weighting of the residual, which is
+// never stored); usable when resr_usable(n, B) (LDS-tiled, n >= 4)
+template <class T>
+bool resr_usable(int n, int B);
+template <class T>
+hipError_t launch_residual_restrict(int n, int B, const T* kap, const T* b, const T* x, T* bc, const int* active,
+                                   hipStream_t st);
 template <class T>
 hipError_t launch_prolong_add(int nf, int B, const T* xc, T* xf, const int* active, hipStream_t st);
 template <class T>

@@ -789,6 +789,232 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   }
 }
 
+// ------------------------------------- residual fused with the restriction
+// bc = P^T (b - A x) on the n/2 mesh without writing the fine residual.  The
+// workgroup's LDS tile is the one of k_zlds plus one row: it evaluates the
+// residual t on its node rows j0 .. j0+R (row j0+R is the first row of the next
+// tile, recomputed here) and on planes k0 .. k1 (plane k1 likewise), one
+// plane at a time into LDS.  Every coarse node (I, J, K) with 2J in
+// [j0+1, j0+R-1] and 2K in [k0+1, k1-1] has its whole 3x3x3 support in that
+// range (j0 and k0 are odd, R and the chunk length even), so each coarse node
+// is produced by exactly one workgroup: a thread owning (I, J) adds the
+// in-plane full-weighting sum of t, weighted 1/2 from odd fine planes and 1
+// from even ones, and stores the coarse value when plane 2K+1 is done.
+template <class T>
+inline size_t resr_bytes(const ZGeom& g) {
+  return ((size_t)3 * (g.rows + 3) * zlds_urs<T>(g.n) + (size_t)2 * (g.rows + 2) * zlds_krs<T>(g.n) +
+          (size_t)(g.rows + 1) * zlds_urs<T>(g.n)) * sizeof(T);
+}
+
+// usable when every tile and chunk starts on an odd index and the staging
+// fits two vectors per thread
+template <class T>
+inline bool resr_ok(const ZGeom& g) {
+  return g.n >= 4 && g.rows % 2 == 0 && (g.zc == 1 || g.zlen % 2 == 0) &&
+         (g.rows + 3) * g.G <= 2 * g.threads && (g.rows + 1) * g.G <= 2 * g.threads;
+}
+
+template <class T, int V>
+__global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const T* __restrict__ x,
+                                              const T* __restrict__ bf, const T* __restrict__ kap,
+                                              const int* __restrict__ active, T* __restrict__ bc, size_t cstride) {
+  typedef typename Vec<T, V>::type vt;
+  extern __shared__ __align__(16) unsigned char zsmem[];
+  const uint32_t per = g.parts();
+  const uint32_t lin = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = lin / per;
+  const uint32_t part = lin - b * per;
+  if (active && !active[b]) return;   // uniform over the workgroup
+  const int rb = (int)(part % (uint32_t)g.row_blocks), zb = (int)(part / (uint32_t)g.row_blocks);
+  const int n = g.n, n2 = n * n, G = g.G, R = g.rows;
+  const int UR = R + 3, KR = R + 2, TR = R + 1;
+  const int URS = zlds_urs<T>(n), KRS = zlds_krs<T>(n);
+  T* Ul = reinterpret_cast<T*>(zsmem);        // [3][UR][URS]: u rows j0-1 .. j0+R+1
+  T* Kl = Ul + 3 * UR * URS;                   // [2][KR][KRS]: kappa rows j0-1 .. j0+R
+  T* Tl = Kl + 2 * KR * KRS;                   // [TR][URS]:    t rows j0 .. j0+R
+  const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
+  const int j0 = 1 + rb * R;
+  const int k0 = 1 + zb * g.zlen;
+  int k1 = k0 + g.zlen;
+  if (k1 > n) k1 = n;
+  const int kt1 = k1 < n - 1 ? k1 : n - 1;    // last residual plane
+  const T* ub = x + (size_t)b * stride;
+  const T* bb = bf + (size_t)b * stride;
+  const T* kb = kap + (size_t)b * n2 * n;
+  const int nc = n >> 1, nc2 = nc * nc;
+
+  for (int q = tid; q < 3 * UR; q += nthr) {
+    Ul[q * URS + V - 1] = T(0);
+    Ul[q * URS + V + n] = T(0);
+  }
+  for (int q = tid; q < 2 * KR; q += nthr) Kl[q * KRS + V - 1] = T(0);
+
+  vt pu[2], pk[2];
+  auto fetch_u = [&](int kk) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      const int jj = j0 - 1 + r;
+      if (v < UR * G && jj <= n) pu[m] = *reinterpret_cast<const vt*>(ub + (size_t)n2 * kk + (size_t)n * jj + c * V);
+    }
+  };
+  auto store_u = [&](int slot) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + V + c * V) = pu[m];
+    }
+  };
+  auto fetch_k = [&](int ez) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      const int ey = j0 - 1 + r;
+      if (v < KR * G && ey <= n - 1)
+        pk[m] = *reinterpret_cast<const vt*>(kb + (size_t)n2 * ez + (size_t)n * ey + c * V);
+    }
+  };
+  auto store_k = [&](int slot) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      if (v < KR * G && j0 - 1 + r <= n - 1)
+        *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + V + c * V) = pk[m];
+    }
+  };
+
+  // coarse node owned by this thread: coarse row Jf + (tid / nc), column tid % nc
+  const int Jf = (j0 + 1) >> 1;
+  const int Jlast = (j0 + R - 1) >> 1 < nc - 1 ? (j0 + R - 1) >> 1 : nc - 1;
+  const int cJ = Jf + tid / nc, cI = tid % nc;
+  const bool owner = tid < (R / 2) * nc && cJ <= Jlast;
+  T cacc = T(0);
+
+  if (k0 < k1) {
+    fetch_u(k0 - 1); store_u((k0 - 1) % 3);
+    fetch_u(k0); store_u(k0 % 3);
+    fetch_u(k0 + 1); store_u((k0 + 1) % 3);
+    fetch_k(k0 - 1); store_k((k0 - 1) & 1);
+    fetch_k(k0); store_k(k0 & 1);
+    if (k0 + 2 <= kt1 + 1) fetch_u(k0 + 2);
+    if (k0 + 1 <= kt1) fetch_k(k0 + 1);
+    __syncthreads();
+    int sm = (k0 - 1) % 3, s0 = k0 % 3, sp = (k0 + 1) % 3;
+    int km = (k0 - 1) & 1, kc = k0 & 1;
+    const T third = T(1) / T(3), twelfth = T(1) / T(12);
+    for (int kk = k0; kk <= kt1; ++kk) {
+      // residual of rows j0 .. j0+R on plane kk into LDS
+      for (int task = tid; task < TR * G; task += nthr) {
+        const int jr = task / G, gx = task - (task / G) * G;
+        const int j = j0 + jr, i0 = gx * V;
+        if (j > n - 1) continue;
+        T K[2][2][V + 1];
+        const int ks[2] = {km, kc};
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy) {
+            const T* row = Kl + (ks[dz] * KR + jr + dy) * KRS + V + i0;
+            K[dz][dy][0] = row[-1];
+            vload<T, V>(row, K[dz][dy] + 1);
+          }
+        T far[V], ksum[V], uc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          far[v] = T(0);
+          ksum[v] = T(0);
+#pragma unroll
+          for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+            for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+              for (int sx = 0; sx < 2; ++sx) ksum[v] += K[sz][sy][v + sx];
+        }
+#pragma unroll
+        for (int sz = 0; sz < 2; ++sz) {
+          const T* P = Ul + ((sz ? sp : sm) * UR + jr) * URS + V + i0;
+          T Rw[3][V + 2];
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy) {
+            Rw[dy][0] = P[dy * URS - 1];
+            vload<T, V>(P + dy * URS, Rw[dy] + 1);
+            Rw[dy][V + 1] = P[dy * URS + V];
+          }
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+              for (int sx = 0; sx < 2; ++sx)
+                far[v] += K[sz][sy][v + sx] * (Rw[1][v + 2 * sx] + (Rw[2 * sy][v + 1] + Rw[2 * sy][v + 2 * sx]));
+        }
+        {
+          const T* P = Ul + (s0 * UR + jr) * URS + V + i0;
+          T R0[V + 2], R2[V + 2];
+          R0[0] = P[-1];
+          vload<T, V>(P, R0 + 1);
+          R0[V + 1] = P[V];
+          vload<T, V>(P + URS, uc);
+          R2[0] = P[2 * URS - 1];
+          vload<T, V>(P + 2 * URS, R2 + 1);
+          R2[V + 1] = P[2 * URS + V];
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+              for (int sx = 0; sx < 2; ++sx)
+                far[v] += (K[0][sy][v + sx] + K[1][sy][v + sx]) * (sy ? R2 : R0)[v + 2 * sx];
+        }
+        T bv[V], t[V];
+        vload<T, V>(bb + i0 + (size_t)n * j + (size_t)n2 * kk, bv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const T au = h * (ksum[v] * uc[v] * third - far[v] * twelfth);
+          t[v] = (i0 + v) != 0 ? bv[v] - au : T(0);
+        }
+        vstore<T, V>(Tl + jr * URS + V + i0, t);
+      }
+      __syncthreads();
+      // in-plane full weighting of t at the owned coarse node, folded over planes
+      if (owner) {
+        T r2 = T(0);
+        if (cI > 0) {
+          const int jr = 2 * cJ - j0;   // tile row of fine row 2J
+#pragma unroll
+          for (int dy = -1; dy <= 1; ++dy) {
+            const T* row = Tl + (jr + dy) * URS + V + 2 * cI;
+            r2 += (dy == 0 ? T(1) : T(0.5)) * (T(0.5) * (row[-1] + row[1]) + row[0]);
+          }
+        }
+        if (kk & 1) {
+          // odd plane 2K+1 closes coarse plane K (from the second odd plane on)
+          // and opens plane K+1
+          const int K = (kk - 1) >> 1;
+          if (kk > k0 && K <= nc - 1) bc[(size_t)b * cstride + cI + (size_t)nc * cJ + (size_t)nc2 * K] = cacc + T(0.5) * r2;
+          cacc = T(0.5) * r2;
+        } else {
+          cacc += r2;
+        }
+      }
+      if (kk + 1 <= kt1) {
+        // planes kk-1 (u) and kk-1 (kappa) are no longer read
+        store_u(sm);                       // u plane kk+2
+        store_k(km);                       // kappa plane kk+1
+        if (kk + 3 <= kt1 + 1) fetch_u(kk + 3);
+        if (kk + 2 <= kt1) fetch_k(kk + 2);
+      }
+      __syncthreads();
+      const int tu = sm; sm = s0; s0 = sp; sp = tu;
+      const int tk = km; km = kc; kc = tk;
+    }
+  }
+}
+
 template <class T, bool NEED_U, bool PRO, class Epi, bool ADDD = false>
 hipError_t zlaunch_lds(int n, int B, const T* u, const T* xc, const T* kap, const int* active, double* partial,
                        uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st, const float* dadd = nullptr) {
@@ -1149,6 +1375,21 @@ hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, 
 }
 
 template <class T>
+bool resr_usable(int n, int B) { return resr_ok<T>(zgeom<T>(n, B)); }
+
+template <class T>
+hipError_t launch_residual_restrict(int n, int B, const T* kap, const T* b, const T* x, T* bc, const int* active,
+                                   hipStream_t st) {
+  constexpr int V = ZV<T>::V;
+  const ZGeom g = zgeom<T>(n, B);
+  if (!resr_ok<T>(g)) return hipErrorInvalidValue;
+  const uint32_t blocks = g.parts() * (uint32_t)B;
+  k_resr<T, V><<<dim3(blocks), dim3(g.threads), resr_bytes<T>(g), st>>>(g, grid_stride(n), T(1) / T(n), x, b, kap,
+                                                                        active, bc, grid_stride(n / 2));
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_restrict(int nf, int B, const T* rf, T* bc, const int* active, hipStream_t st) {
   const int nc = nf / 2;
   const uint32_t ch = (uint32_t)(((size_t)(nc - 1) * nc * nc / 2 + kBlock - 1) / kBlock);
@@ -1202,6 +1443,9 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st) 
   template hipError_t launch_pcg_apply_dot<T>(int, int, const T*, const T*, T*, SolveState, uint32_t*, \
                                               hipStream_t, int);                                       \
   template hipError_t launch_restrict<T>(int, int, const T*, T*, const int*, hipStream_t);             \
+  template bool resr_usable<T>(int, int);                                                              \
+  template hipError_t launch_residual_restrict<T>(int, int, const T*, const T*, const T*, T*, const int*, \
+                                                  hipStream_t);                                        \
   template hipError_t launch_prolong_add<T>(int, int, const T*, T*, const int*, hipStream_t);          \
   template hipError_t launch_coarsest<T>(int, const T*, const T*, T*, const int*, hipStream_t);        \
   template hipError_t launch_coarsen<T>(int, int, const T*, T*, hipStream_t, const int*);

@@ -120,7 +120,7 @@ def test_apply_matches_csr(dev, n, B, zvar):
 
 
 @pytest.mark.parametrize("zvar", [0, 6])
-@pytest.mark.parametrize("fuse", [1, 0])
+@pytest.mark.parametrize("fuse", [9, 0])
 @pytest.mark.parametrize("vsmall", ["1", "0"])
 @pytest.mark.parametrize("n,B,deg", [(4, 2, 2), (8, 3, 2), (16, 2, 3), (32, 1, 1)])
 def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, fuse, zvar, monkeypatch):
@@ -149,7 +149,7 @@ def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg, zvar):
     n, B = 32, 3
     wl = _wl(n0=n, levels=1, qoi=1, precision=1, solver=0, n_modes=16, corr_len=0.3)
     qs = []
-    for fuse in (7, 3, 4, 2, 1, 0):   # every fusion bit alone, all, none
+    for fuse in (15, 8, 4, 2, 1, 0):   # every fusion bit alone, all, none
         ctx = mm.Context(wl, cheb_degree=deg, arena_bytes=512 << 20)
         ctx.set_tuning(fuse=fuse, vsmall_fp32=0, vsmall_fp64=0, zvar_fp32=zvar, zvar_fp64=zvar)
         xi = ctx.draw_xi(0, 21, B)
