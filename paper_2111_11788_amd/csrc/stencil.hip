@@ -221,6 +221,56 @@ struct EpiChebZero {
   }
 };
 
+// One LDS row segment of the u window: the thread's V values by one vector
+// read, the halos i0-1 and i0+V from the neighbouring lanes of the same row
+// (the G lanes of a row are consecutive lanes of one wave when G <= 64; the
+// row ends are the zero cells u(-1) = u(n) = 0).  With shuf false (a row
+// wider than a wave) the halos are read from LDS.  Scalar halo reads at a
+// 16-byte lane stride would put all lanes of a wave on a quarter of the LDS
+// banks.
+// whole-wave DPP shifts (GFX9 wave_shr:1 / wave_shl:1, full VALU rate):
+// lane l receives lane l-1 (from_prev) or lane l+1 (from_next), 0 at the ends
+__device__ __forceinline__ int dpp_prev_i(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_next_i(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ float from_prev(float x) { return __int_as_float(dpp_prev_i(__float_as_int(x))); }
+__device__ __forceinline__ float from_next(float x) { return __int_as_float(dpp_next_i(__float_as_int(x))); }
+__device__ __forceinline__ double from_prev(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = dpp_prev_i((int)(v & 0xffffffffll)), hi = dpp_prev_i((int)(v >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_next(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = dpp_next_i((int)(v & 0xffffffffll)), hi = dpp_next_i((int)(v >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <class T, int V>
+__device__ __forceinline__ void lds_urow(const T* row, T* dst, int gx, int G, bool shuf) {
+  vload<T, V>(row, dst + 1);
+  if (shuf) {
+    const T l = from_prev(dst[V]);
+    const T r = from_next(dst[1]);
+    dst[0] = gx == 0 ? T(0) : l;
+    dst[V + 1] = gx == G - 1 ? T(0) : r;
+  } else {
+    dst[0] = row[-1];
+    dst[V + 1] = row[V];
+  }
+}
+
+// kappa row segment: element i0-1 (zero cell for i0 = 0) and i0 .. i0+V-1
+template <class T, int V>
+__device__ __forceinline__ void lds_krow(const T* row, T* dst, int gx, int G, bool shuf) {
+  vload<T, V>(row, dst + 1);
+  if (shuf) {
+    const T l = from_prev(dst[V]);
+    dst[0] = gx == 0 ? T(0) : l;
+  } else {
+    dst[0] = row[-1];
+  }
+}
+
 // N consecutive values (N = 1 or an aligned vector)
 template <class T, int N>
 __device__ __forceinline__ void nload(const T* p, T* dst) {
@@ -551,6 +601,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   const int gx = tid % G, jr = tid / G;
   const int j = j0 + jr, i0 = gx * V;
   const bool valid = jr < R && j <= n - 1 && k0 < k1;
+  const bool shuf = G <= 64;
   const T* ub = (NEED_U && u) ? u + (size_t)b * stride : nullptr;
   const float* db = ADDD ? dadd + (size_t)b * stride : nullptr;
   const T* kb = kap + (size_t)b * n2 * n;
@@ -707,11 +758,8 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-          for (int dy = 0; dy < 2; ++dy) {
-            const T* row = Kl + (ks[dz] * KR + jr + dy) * KRS + V + i0;
-            K[dz][dy][0] = row[-1];
-            vload<T, V>(row, K[dz][dy] + 1);
-          }
+          for (int dy = 0; dy < 2; ++dy)
+            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy) * KRS + V + i0, K[dz][dy], gx, G, shuf);
         T far[V], ksum[V], uc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -731,11 +779,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
             const T* P = Ul + ((sz ? sp : sm) * UR + jr) * URS + V + i0;
             T R[3][V + 2];
 #pragma unroll
-            for (int dy = 0; dy < 3; ++dy) {
-              R[dy][0] = P[dy * URS - 1];
-              vload<T, V>(P + dy * URS, R[dy] + 1);
-              R[dy][V + 1] = P[dy * URS + V];
-            }
+            for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + dy * URS, R[dy], gx, G, shuf);
 #pragma unroll
             for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -747,13 +791,9 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
           {
             const T* P = Ul + (s0 * UR + jr) * URS + V + i0;
             T R0[V + 2], R2[V + 2];
-            R0[0] = P[-1];
-            vload<T, V>(P, R0 + 1);
-            R0[V + 1] = P[V];
+            lds_urow<T, V>(P, R0, gx, G, shuf);
             vload<T, V>(P + URS, uc);
-            R2[0] = P[2 * URS - 1];
-            vload<T, V>(P + 2 * URS, R2 + 1);
-            R2[V + 1] = P[2 * URS + V];
+            lds_urow<T, V>(P + 2 * URS, R2, gx, G, shuf);
 #pragma unroll
             for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -838,6 +878,9 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
   int k1 = k0 + g.zlen;
   if (k1 > n) k1 = n;
   const int kt1 = k1 < n - 1 ? k1 : n - 1;    // last residual plane
+  // halos from LDS here: measured faster than the DPP exchange for this kernel
+  // (its extra-row tasks leave most of a wave idle around the exchange)
+  const bool shuf = false;
   const T* ub = x + (size_t)b * stride;
   const T* bb = bf + (size_t)b * stride;
   const T* kb = kap + (size_t)b * n2 * n;
@@ -917,11 +960,8 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-          for (int dy = 0; dy < 2; ++dy) {
-            const T* row = Kl + (ks[dz] * KR + jr + dy) * KRS + V + i0;
-            K[dz][dy][0] = row[-1];
-            vload<T, V>(row, K[dz][dy] + 1);
-          }
+          for (int dy = 0; dy < 2; ++dy)
+            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy) * KRS + V + i0, K[dz][dy], gx, G, shuf);
         T far[V], ksum[V], uc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -939,11 +979,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
           const T* P = Ul + ((sz ? sp : sm) * UR + jr) * URS + V + i0;
           T Rw[3][V + 2];
 #pragma unroll
-          for (int dy = 0; dy < 3; ++dy) {
-            Rw[dy][0] = P[dy * URS - 1];
-            vload<T, V>(P + dy * URS, Rw[dy] + 1);
-            Rw[dy][V + 1] = P[dy * URS + V];
-          }
+          for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + dy * URS, Rw[dy], gx, G, shuf);
 #pragma unroll
           for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -955,13 +991,9 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
         {
           const T* P = Ul + (s0 * UR + jr) * URS + V + i0;
           T R0[V + 2], R2[V + 2];
-          R0[0] = P[-1];
-          vload<T, V>(P, R0 + 1);
-          R0[V + 1] = P[V];
+          lds_urow<T, V>(P, R0, gx, G, shuf);
           vload<T, V>(P + URS, uc);
-          R2[0] = P[2 * URS - 1];
-          vload<T, V>(P + 2 * URS, R2 + 1);
-          R2[V + 1] = P[2 * URS + V];
+          lds_urow<T, V>(P + 2 * URS, R2, gx, G, shuf);
 #pragma unroll
           for (int v = 0; v < V; ++v)
 #pragma unroll
