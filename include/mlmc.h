@@ -226,7 +226,7 @@ typedef struct mlmc_tuning {
   int32_t cheb_degree;    /* Chebyshev smoothing degree per half V-cycle, 1..8 */
   int32_t max_batch;      /* samples per batched solve */
   int32_t graph_batch;    /* captured PCG iterations replayed per convergence check (0: no graphs) */
-  int32_t fuse;           /* MLMC_FUSE_* bits: kernel fusions in use (default: all) */
+  int32_t fuse;           /* MLMC_FUSE_* bits: kernel fusions in use (default: all but PRESMOOTH) */
   double seconds;         /* mlmc_autotune: measured seconds per sample of the chosen setting */
 } mlmc_tuning;
 
@@ -235,7 +235,14 @@ enum {
   MLMC_FUSE_PROLONG = 1,  /* coarse-grid correction applied inside the first post-smoothing step */
   MLMC_FUSE_UPDATE = 2,   /* PCG x/r update fused with the first smoothing step of the next V-cycle */
   MLMC_FUSE_REFINE = 4,   /* mixed precision: correction, fp64 residual and its demotion in one pass */
-  MLMC_FUSE_RESTRICT = 8  /* V-cycle residual restricted to the coarse mesh without being stored */
+  MLMC_FUSE_RESTRICT = 8, /* V-cycle residual restricted to the coarse mesh without being stored */
+  MLMC_FUSE_PRESMOOTH = 16, /* Chebyshev degree 1 with the LDS engine (zvar bit 2) and PROLONG and
+                              RESTRICT on: the zero-start pre-smoothing step c D^-1 b of each V-cycle
+                              level is formed inside the residual and the correction steps, never
+                              stored (supersedes UPDATE on those levels) */
+  MLMC_FUSE_DIRECTION = 32 /* LDS engine: the PCG direction p = z + beta p is formed inside the operator
+                              apply q = A p, which also applies the previous step's x += alpha p (two
+                              direction buffers); the last x update of a solve runs after it */
 };
 
 int mlmc_get_tuning(const mlmc_ctx* ctx, mlmc_tuning* out);

@@ -275,7 +275,8 @@ int mlmc_autotune(mlmc_ctx* ctx, int32_t level, int32_t batch, mlmc_tuning* best
     mlmc_tuning c = best; c.vsmall_fp32 = v; c.vsmall_fp64 = std::min(v, 8);
     if (int rc = trial(c)) return rc;
   }
-  for (int f : {MLMC_FUSE_PROLONG, MLMC_FUSE_UPDATE, MLMC_FUSE_REFINE, MLMC_FUSE_RESTRICT}) {
+  for (int f : {MLMC_FUSE_PROLONG, MLMC_FUSE_UPDATE, MLMC_FUSE_REFINE, MLMC_FUSE_RESTRICT, MLMC_FUSE_PRESMOOTH,
+                MLMC_FUSE_DIRECTION}) {
     mlmc_tuning c = best; c.fuse ^= f;
     if (int rc = trial(c)) return rc;
   }

@@ -148,11 +148,19 @@ int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float
 // With `dot` the last smoothing step of level l also writes the partial sums
 // of b . result (*dot_np per sample).
 template <class T>
-bool zero_step_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L) {
+bool presmooth_level(const mlmc_ctx* ctx, int n, int B) {
+  const int f = ctx->fuse;
+  const int small = ctx->vsmall_n0[sizeof(T) == 4 ? 1 : 0];
+  return (f & MLMC_FUSE_PRESMOOTH) && (f & MLMC_FUSE_PROLONG) && (f & MLMC_FUSE_RESTRICT) && ctx->cheb.degree == 1 &&
+         (zv<T>(ctx) & ZVAR_LDS) && !(small && n <= small) && presmooth_usable<T>(n, B);
+}
+
+template <class T>
+bool zero_step_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int B) {
   if (!(ctx->fuse & MLMC_FUSE_UPDATE) || L.size() < 2) return false;
   const int n = L[0].n;
   const int small = ctx->vsmall_n0[sizeof(T) == 4 ? 1 : 0];
-  return n >= 4 && n >= ZV<T>::V && !(small && n <= small);
+  return n >= 4 && n >= ZV<T>::V && !(small && n <= small) && !presmooth_level<T>(ctx, n, B);
 }
 
 template <class T>
@@ -178,6 +186,21 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
     for (size_t q = l; q < L.size() && q - l < 4; ++q) kl[q - l] = L[q].kap;
     LAUNCHM(kid<T>(MLMC_K_COARSEST), (2 * d + e * 8.0 / 7.0) * sz, active, B,
            launch_vsmall<T>(n, B, ch.degree, ch.c1, ch.c2, kl, b, x, active, st));
+    *result = x;
+    return MLMC_OK;
+  }
+  if (!zero_done && L.size() > (size_t)l + 1 && presmooth_level<T>(ctx, n, B)) {
+    // one Chebyshev step on each side of the coarse-grid correction, the
+    // first (from the zero iterate, c D^-1 b) formed inside both kernels that
+    // read it instead of being stored
+    Level<T>& nx = L[l + 1];
+    const double dc = dofs(n / 2) * B;
+    LAUNCHM(kid<T>(MLMC_K_RESIDUAL_RESTRICT), (d + e + dc) * sz, active, B,
+            launch_residual_restrict<T>(n, B, kap, b, nullptr, nx.b, active, st, true, ch.c2[0]));
+    T* xc = nullptr;
+    if (int rc = vcycle<T>(ctx, L, l + 1, B, nx.b, nx.x, nx.xo, nx.t, active, &xc)) return rc;
+    LAUNCHM(kid<T>(MLMC_K_CHEB_PROLONG), (2 * d + dc + e) * sz, active, B,
+            launch_cheb_prolong_presmoothed<T>(n, B, kap, b, xc, x, ch.c2[0], active, st, dot, dot_np));
     *result = x;
     return MLMC_OK;
   }
@@ -278,7 +301,7 @@ int pcg_iteration(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S,
   T* z = nullptr;
   LAUNCHM(kid<T>(MLMC_K_PCG_APPLY), (2 * d + e) * sz, S.active, B, launch_pcg_apply_dot<T>(n, B, L[0].kap, p, q, S, &np, st, var));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA, 0.0, np, S, nullptr, st));
-  const bool fz = zero_step_fusable<T>(ctx, L);
+  const bool fz = zero_step_fusable<T>(ctx, L, B);
   if (fz)
     LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE_ZERO), (7 * d + e) * sz, S.active, B,
             launch_pcg_update_zero<T>(n, B, L[0].kap, x, p, r, q, L[0].x, ctx->cheb.c2[0], S, &np, st, var));
@@ -296,23 +319,111 @@ int pcg_iteration(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S,
   return MLMC_OK;
 }
 
+template <class T>
+bool dir_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int B) {
+  return (ctx->fuse & MLMC_FUSE_DIRECTION) && (zv<T>(ctx) & ZVAR_LDS) && dir_usable<T>(L[0].n, B);
+}
+
+template <class T>
+int pcg_dir_begin(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, const T* r, const int* mask) {
+  const int n = L[0].n;
+  const double sz = sizeof(T), d = dofs(n) * B, e = elems(n) * B;
+  SolveState m = S;
+  m.active = const_cast<int*>(mask);
+  LAUNCH(MLMC_K_MISC, 0, launch_dir_begin(B, m, ctx->st));
+  if (zero_step_fusable<T>(ctx, L, B))
+    LAUNCHM(kid<T>(MLMC_K_CHEB_ZERO), (2 * d + e) * sz, mask, B,
+            launch_cheb<T>(n, B, L[0].kap, r, nullptr, nullptr, L[0].x, 0.0, ctx->cheb.c2[0], true, false, mask,
+                           ctx->st, nullptr, nullptr, zv<T>(ctx)));
+  return MLMC_OK;
+}
+
+template <class T>
+int pcg_iteration_dir(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p0, T* p1,
+                      T* q, double tol2, int rr_op, bool count, bool first) {
+  const int n = L[0].n;
+  const double sz = sizeof(T), d = dofs(n) * B, e = elems(n) * B;
+  hipStream_t st = ctx->st;
+  const int var = zv<T>(ctx);
+  const bool fz = zero_step_fusable<T>(ctx, L, B);
+  uint32_t np = 0;
+  T* z = nullptr;
+  if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np, fz)) return rc;
+  if (!np) LAUNCHM(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, S.active, B, (launch_dot<T>(n, B, r, z, S, &np, st)));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BETA_DIR, 0.0, np, S, nullptr, st));
+  // reads z, kappa (and p_old, x); writes p, q (and x)
+  LAUNCHM(kid<T>(MLMC_K_PCG_APPLY), ((first ? 3 : 6) * d + e) * sz, S.active, B,
+          launch_pcg_dir_apply<T>(n, B, L[0].kap, z, x, p0, p1, q, S.pstate, S, &np, st));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA_DIR, 0.0, np, S, nullptr, st));
+  if (fz)
+    LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE_ZERO), (4 * d + e) * sz, S.active, B,
+            launch_pcg_rupdate_zero<T>(n, B, L[0].kap, r, q, L[0].x, ctx->cheb.c2[0], S, &np, st, var));
+  else
+    LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE), 3 * d * sz, S.active, B, launch_pcg_rupdate<T>(n, B, r, q, S, &np, st));
+  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, rr_op, tol2, np, S, nullptr, st));
+  if (count) {
+    LAUNCH(MLMC_K_MISC, 0, launch_count_active(B, S, st));
+    HIPCHK(hipMemcpyAsync(ctx->h_nactive, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  return MLMC_OK;
+}
+
 // PCG on the current iterate x with residual r (both already set, S.active
 // and S.bb set).  Stops per sample at ||r|| <= tol ||b|| (recurrence).
 // `graph` caches the captured iteration for this work space (may be null).
 template <class T>
 int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q, double tol,
-        int max_iter, int* done_iters, hipGraphExec_t* graph) {
+        int max_iter, int* done_iters, hipGraphExec_t* graph, T* p2) {
   const int n = L[0].n;
   const double sz = sizeof(T), d = dofs(n) * B;
   hipStream_t st = ctx->st;
+  const double tol2 = tol * tol;
+  const bool use_graph = graph && ctx->use_graphs && !ctx->profiling;
+  if (p2 && dir_fusable<T>(ctx, L, B)) {
+    if (int rc = pcg_dir_begin<T>(ctx, L, B, S, r, S.active)) return rc;
+    int it = 0;
+    if (max_iter > 0) {
+      if (int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2, RED_RR, true, true)) return rc;
+      it = 1;
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    if (use_graph && !*graph && it < max_iter && *ctx->h_nactive > 0) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      const int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2);
+      const hipError_t ec = hipStreamEndCapture(st, &g);
+      if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+      }
+      HIPCHK(ec);
+      const hipError_t ei = hipGraphInstantiate(graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIPCHK(ei);
+    }
+    while (it < max_iter && *ctx->h_nactive > 0) {
+      const int k = use_graph ? std::min(ctx->graph_batch, max_iter - it) : 1;
+      for (int j = 0; j < k; ++j) {
+        if (use_graph) {
+          HIPCHK(hipGraphLaunch(*graph, st));
+        } else if (int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2)) {
+          return rc;
+        }
+      }
+      it += k;
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    // the update the last step still owes its iterate
+    LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE), 3 * d * sz, S.began, B, launch_pcg_finish<T>(n, B, x, p, p2, S.began, S, st));
+    *done_iters = it;
+    return MLMC_OK;
+  }
   uint32_t np = 0;
   T* z = nullptr;
   if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np)) return rc;
   if (!np) LAUNCHM(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, S.active, B, (launch_dot<T>(n, B, r, z, S, &np, st)));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RZ_INIT, 0.0, np, S, nullptr, st));
   LAUNCHM(kid<T>(MLMC_K_PCG_DIRECTION), 2 * d * sz, S.active, B, launch_copy<T>(n, B, z, p, S, st));
-  const double tol2 = tol * tol;
-  const bool use_graph = graph && ctx->use_graphs && !ctx->profiling;
   if (use_graph && !*graph) {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -372,7 +483,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
     for (int round = 0; round < 4 && total_it < ctx->cfg.max_iter; ++round) {
       int it = 0;
       if (int rc = pcg<double>(ctx, L, B, O, u, w.r, w.p, w.q, rtol, ctx->cfg.max_iter - total_it, &it,
-                              &w.iter_exec[0]))
+                              &w.iter_exec[0], w.p2))
         return rc;
       total_it += it;
       // confirm with the true residual; samples above tolerance continue
@@ -418,7 +529,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
         LAUNCHM(MLMC_K_MISC, d * 4, O.active, B, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
         int it = 0;
         if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it,
-                               &it, &w.iter_exec[1]))
+                               &it, &w.iter_exec[1], w.p32b))
           return rc;
         total_it += it;
         double* uout = bufs[next];
@@ -449,7 +560,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
         LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, I, nullptr, st));
         int it = 0;
         if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it, &it,
-                               &w.iter_exec[1]))
+                               &w.iter_exec[1], w.p32b))
           return rc;
         total_it += it;
         LAUNCHM(MLMC_K_MISC, d * 20, O.active, B, launch_add_correction(n, B, u, w.d, O, st));
@@ -542,7 +653,8 @@ int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (t->cheb_degree < 1 || t->cheb_degree > 8) { why = "cheb_degree must be in 1..8"; return MLMC_E_INVALID; }
   if (t->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
   if (t->graph_batch < 0 || t->graph_batch > 16) { why = "graph_batch must be in 0..16"; return MLMC_E_INVALID; }
-  if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
+  if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
+                   MLMC_FUSE_DIRECTION)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
   return MLMC_OK;
 }
 
@@ -587,16 +699,25 @@ template int precondition<float>(mlmc_ctx*, std::vector<Level<float>>&, int, con
                                  uint32_t*, bool);
 template int precondition<double>(mlmc_ctx*, std::vector<Level<double>>&, int, const double*, double**, SolveState&,
                                   uint32_t*, bool);
-template bool zero_step_fusable<float>(const mlmc_ctx*, const std::vector<Level<float>>&);
-template bool zero_step_fusable<double>(const mlmc_ctx*, const std::vector<Level<double>>&);
+template bool zero_step_fusable<float>(const mlmc_ctx*, const std::vector<Level<float>>&, int);
+template bool zero_step_fusable<double>(const mlmc_ctx*, const std::vector<Level<double>>&, int);
 template int pcg_iteration<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*,
                                   float*, double, int, bool);
 template int pcg_iteration<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*,
                                    double*, double*, double, int, bool);
 template int pcg<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*, float*,
-                        double, int, int*, hipGraphExec_t*);
+                        double, int, int*, hipGraphExec_t*, float*);
 template int pcg<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*, double*,
-                         double*, double, int, int*, hipGraphExec_t*);
+                         double*, double, int, int*, hipGraphExec_t*, double*);
+template bool dir_fusable<float>(const mlmc_ctx*, const std::vector<Level<float>>&, int);
+template bool dir_fusable<double>(const mlmc_ctx*, const std::vector<Level<double>>&, int);
+template int pcg_dir_begin<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, const float*, const int*);
+template int pcg_dir_begin<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, const double*,
+                                   const int*);
+template int pcg_iteration_dir<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*,
+                                      float*, float*, double, int, bool, bool);
+template int pcg_iteration_dir<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*,
+                                       double*, double*, double*, double, int, bool, bool);
 
 }  // namespace eng
 }  // namespace mlmc

@@ -94,6 +94,8 @@ struct StateBufs {
     s.active = cv.take<int>(B);
     s.iters = cv.take<int>(B);
     s.nactive = cv.take<int>(1);
+    s.pstate = cv.take<int>(B);
+    s.began = cv.take<int>(B);
   }
 };
 
@@ -102,9 +104,9 @@ struct SolveWork {
   int n = 0, B = 0, precision = 0, solver = 0;
   std::vector<Level<double>> L64;   // fp64 hierarchy (level 0 kappa is the caller's)
   std::vector<Level<float>> L32;    // fp32 hierarchy (mixed precision)
-  double *r = nullptr, *p = nullptr, *q = nullptr;          // fp64 PCG
+  double *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;   // fp64 PCG (p2: second direction buffer)
   double* r64 = nullptr;                                    // fp64 refinement residual
-  float *d = nullptr, *rin = nullptr, *p32 = nullptr, *q32 = nullptr;  // fp32 inner PCG
+  float *d = nullptr, *rin = nullptr, *p32 = nullptr, *p32b = nullptr, *q32 = nullptr;  // fp32 inner PCG
   int* alt = nullptr;   // mixed: 1 where the sample's last refined iterate is in r64 (second buffer)
   StateBufs outer, inner;
   // captured PCG iteration per precision (0: fp64, 1: fp32); tied to the buffers above
@@ -126,6 +128,7 @@ struct SolveWork {
     if (prec == MLMC_PREC_FP64) {
       r = cv.take<double>(B * S0);
       p = cv.take<double>(B * S0);
+      p2 = cv.take<double>(B * S0);
       q = cv.take<double>(B * S0);
       L64.assign(nl, Level<double>{});
       for (int l = 0; l < nl; ++l) {
@@ -147,6 +150,7 @@ struct SolveWork {
       d = cv.take<float>(B * S0);
       rin = cv.take<float>(B * S0);
       p32 = cv.take<float>(B * S0);
+      p32b = cv.take<float>(B * S0);
       q32 = cv.take<float>(B * S0);
       L32.assign(nl, Level<float>{});
       for (int l = 0; l < nl; ++l) {
@@ -232,7 +236,10 @@ struct mlmc_ctx {
   bool use_graphs = true;         // replay the PCG iteration from a captured hipGraph
   bool own_stream = false;        // the context created st itself
   int graph_batch = 2;            // graph launches per convergence check
-  int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT;   // MLMC_FUSE_* bits
+  // MLMC_FUSE_* bits in use: all but PRESMOOTH, which measured slower on the
+  // 64^3 batch (its LDS engines take more LDS and registers) and is left to
+  // the autotuner
+  int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_DIRECTION;
   mlmc_server* server = nullptr;  // serving pools and threads while serving
 };
 
@@ -336,14 +343,33 @@ int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T**
 // Whether the preconditioner's first smoothing step on the finest level runs
 // through the level-by-level kernels, so a PCG update can produce it.
 template <class T>
-bool zero_step_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L);
+bool zero_step_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int B);
 int count_active(mlmc_ctx* ctx, SolveState& s, int B, int* out);
 template <class T>
 int pcg_iteration(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q,
                   double tol2, int rr_op = RED_RR, bool count = true);
+// Whether the PCG on this hierarchy runs with the direction fused into the
+// operator apply (MLMC_FUSE_DIRECTION and the LDS engine usable on L[0]).
+template <class T>
+bool dir_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int B);
+// One fused-direction PCG iteration: z = M^-1 r and beta; p = z + beta p
+// (buffers p0/p1 by S.pstate), q = A p, alpha, and the previous x += alpha p;
+// r -= alpha q with the convergence test.  The start of a solve sets S.pstate
+// (launch_dir_begin) and, when the zero step is fused into the update, the
+// zero-iterate smoothing step of the first V-cycle.  `first`: only for the
+// byte count of the apply (no previous direction is read).
+template <class T>
+int pcg_iteration_dir(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p0, T* p1,
+                      T* q, double tol2, int rr_op = RED_RR, bool count = true, bool first = false);
+// Start of a fused-direction solve on the active samples (see pcg_iteration_dir).
+template <class T>
+int pcg_dir_begin(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, const T* r, const int* mask);
+// PCG of x (residual r) to ||r|| <= tol ||b||.  With p2 (a second direction
+// buffer) and dir_fusable, the fused-direction iteration runs and x gets its
+// last update before return.
 template <class T>
 int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q, double tol,
-        int max_iter, int* done_iters, hipGraphExec_t* graph);
+        int max_iter, int* done_iters, hipGraphExec_t* graph, T* p2 = nullptr);
 // kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
 int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
                bool kap32_ready = false);

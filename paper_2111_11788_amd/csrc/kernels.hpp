@@ -33,6 +33,8 @@ struct SolveState {
   int* nactive;     // single counter (device) of active samples
   uint32_t pstride; // capacity of partial sums per sample
   int* phase;       // serving: per-slot phase (PHASE_*), may be null
+  int* pstate;      // fused-direction PCG: bit 0 = buffer of the current direction, bit 1 = no step taken yet
+  int* began;       // fused-direction PCG: samples active when the solve started
 };
 
 // per-slot phases of a served batch
@@ -82,9 +84,21 @@ hipError_t launch_restrict(int nf, int B, const T* rf, T* bc, const int* active,
 // never stored); usable when resr_usable(n, B) (LDS-tiled, n >= 4)
 template <class T>
 bool resr_usable(int n, int B);
+// presmooth: the operand x is not read but formed on the fly as c2 D^-1 b (the
+// zero-start Chebyshev step of a V-cycle level), i.e. bc = P^T (b - A c2 D^-1 b);
+// usable when presmooth_usable(n, B)
 template <class T>
 hipError_t launch_residual_restrict(int n, int B, const T* kap, const T* b, const T* x, T* bc, const int* active,
-                                   hipStream_t st);
+                                   hipStream_t st, bool presmooth = false, double c2 = 0.0);
+template <class T>
+bool presmooth_usable(int n, int B);
+// launch_cheb_prolong with the pre-smoothed iterate formed on the fly:
+// out = y + c2 D^-1 (b - A y), y = c2 D^-1 b + P xc (one Chebyshev step on each
+// side of the coarse-grid correction, the first from a zero iterate)
+template <class T>
+hipError_t launch_cheb_prolong_presmoothed(int n, int B, const T* kap, const T* b, const T* xc, T* out, double c2,
+                                           const int* active, hipStream_t st, SolveState* dot = nullptr,
+                                           uint32_t* nparts = nullptr);
 template <class T>
 hipError_t launch_prolong_add(int nf, int B, const T* xc, T* xf, const int* active, hipStream_t st);
 template <class T>
@@ -117,6 +131,28 @@ hipError_t launch_pcg_update(int n, int B, T* x, const T* p, T* r, const T* q, S
 template <class T>
 hipError_t launch_dot(int n, int B, const T* a, const T* b, SolveState s, uint32_t* nparts,
                       hipStream_t st);
+// fused-direction PCG (direction buffers p0, p1 selected per sample by s.pstate):
+// r -= alpha q with the partial sums of r . r
+template <class T>
+hipError_t launch_pcg_rupdate(int n, int B, T* r, const T* q, SolveState s, uint32_t* nparts, hipStream_t st);
+// x += alpha p on samples with mask[b] that took a step (the update still owed)
+template <class T>
+hipError_t launch_pcg_finish(int n, int B, T* x, const T* p0, const T* p1, const int* mask, SolveState s,
+                             hipStream_t st);
+// began = active; pstate = first direction in buffer 0 on active samples
+hipError_t launch_dir_begin(int B, SolveState s, hipStream_t st);
+// p = z + beta p_old formed while staging, written to the other buffer, q = A p,
+// partial sums of p . q, and the previous x += alpha p_old (LDS engine, n >= 4,
+// when dir_usable)
+template <class T>
+bool dir_usable(int n, int B);
+template <class T>
+hipError_t launch_pcg_dir_apply(int n, int B, const T* kap, const T* z, T* x, T* p0, T* p1, T* q, const int* pstate,
+                                SolveState s, uint32_t* nparts, hipStream_t st);
+// r -= alpha q, partial sums of r . r, z = c2 D^-1 r (no iterate update)
+template <class T>
+hipError_t launch_pcg_rupdate_zero(int n, int B, const T* kap, T* r, const T* q, T* z, double c2, SolveState s,
+                                   uint32_t* nparts, hipStream_t st, int var = 0);
 template <class T>
 hipError_t launch_pcg_direction(int n, int B, const T* z, T* p, SolveState s, hipStream_t st);
 // outer residual of the refinement loop: r = b - A x in fp64 plus ||r||^2 partials
@@ -145,7 +181,9 @@ enum ReduceOp : int {
   RED_BETA = 4,     // beta = sum / rz; rz = sum
   RED_STORE = 5,    // out[b] = sum (ignores the active mask)
   RED_RR_INNER = 6, // rr = sum; converged -> phase TRANSITION
-  RED_RR_OUTER = 7  // rr = sum; phase DONE if converged else RESTART
+  RED_RR_OUTER = 7, // rr = sum; phase DONE if converged else RESTART
+  RED_BETA_DIR = 8, // fused direction: beta = sum / rz (not on a first direction); rz = sum
+  RED_ALPHA_DIR = 9 // fused direction: alpha = rz / sum; iters += 1; next direction buffer, first cleared
 };
 hipError_t launch_reduce(int B, int op, double tol2, uint32_t nparts, SolveState s, double* out,
                          hipStream_t st);

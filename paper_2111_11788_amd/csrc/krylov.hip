@@ -82,6 +82,50 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(SGeom g, size_t stride, T
   if (threadIdx.x == 0) st.partial[(size_t)sp.b * st.pstride + sp.c] = acc;
 }
 
+// r -= alpha q, partial sums of r . r (the iterate is updated by the fused
+// direction step one iteration later)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_pcg_rupdate(SGeom g, size_t stride, T* __restrict__ r,
+                                                        const T* __restrict__ q, SolveState st) {
+  constexpr int V = 16 / sizeof(T);
+  typedef typename Vec<T, V>::type vt;
+  const Span sp = span_of(g);
+  if (!st.active[sp.b]) return;
+  const size_t base = (size_t)sp.b * stride + (size_t)g.n * g.n;
+  vt* rv = reinterpret_cast<vt*>(r + base);
+  const vt* qv = reinterpret_cast<const vt*>(q + base);
+  const T a = (T)st.alpha[sp.b];
+  double acc = 0.0;
+  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) {
+    const vt rn = rv[t] - a * qv[t];
+    rv[t] = rn;
+#pragma unroll
+    for (int c = 0; c < V; ++c) acc += (double)rn[c] * (double)rn[c];
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) st.partial[(size_t)sp.b * st.pstride + sp.c] = acc;
+}
+
+// the update a fused-direction solve still owes its iterate: x += alpha p
+// with p the sample's current direction (buffer pstate & 1), on samples with
+// mask[b] that took at least one step (pstate bit 1 clear)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_pcg_finish(SGeom g, size_t stride, T* __restrict__ x,
+                                                       const T* __restrict__ p0, const T* __restrict__ p1,
+                                                       const int* __restrict__ mask, SolveState st) {
+  constexpr int V = 16 / sizeof(T);
+  typedef typename Vec<T, V>::type vt;
+  const Span sp = span_of(g);
+  if (!mask[sp.b]) return;
+  const int ps = st.pstate[sp.b];
+  if (ps & 2) return;
+  const size_t base = (size_t)sp.b * stride + (size_t)g.n * g.n;
+  vt* xv = reinterpret_cast<vt*>(x + base);
+  const vt* pv = reinterpret_cast<const vt*>(((ps & 1) ? p1 : p0) + base);
+  const T a = (T)st.alpha[sp.b];
+  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) xv[t] = xv[t] + a * pv[t];
+}
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_dot(SGeom g, size_t stride, const T* __restrict__ a,
                                                 const T* __restrict__ b, SolveState st) {
@@ -240,6 +284,15 @@ __global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t
       break;
     case RED_RZ_INIT: st.rz[b] = v; break;
     case RED_BETA: st.beta[b] = v / st.rz[b]; st.rz[b] = v; break;
+    case RED_BETA_DIR:
+      if (!(st.pstate[b] & 2)) st.beta[b] = v / st.rz[b];
+      st.rz[b] = v;
+      break;
+    case RED_ALPHA_DIR:
+      st.alpha[b] = st.rz[b] / v;
+      st.iters[b] += 1;
+      st.pstate[b] = (st.pstate[b] & 1) ^ 1;
+      break;
     case RED_RR_INNER:
       st.rr[b] = v;
       if (v <= tol2 * st.bb[b]) st.phase[b] = PHASE_TRANSITION;
@@ -294,6 +347,16 @@ __global__ void k_count_mask(const int* __restrict__ mask, int B, int* __restric
   if (threadIdx.x == 0) *out = v;
 }
 
+// a fused-direction solve starts: direction buffer 0, first direction, on
+// active samples; the active set is remembered for the final update
+__global__ void k_dir_begin(int B, SolveState st) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int a = st.active[b];
+  st.began[b] = a;
+  if (a) st.pstate[b] = 2;
+}
+
 __global__ void k_set_active(int B, SolveState st, int value) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < B) st.active[b] = value;
@@ -310,6 +373,27 @@ hipError_t launch_pcg_update(int n, int B, T* x, const T* p, T* r, const T* q, S
   const SGeom g = sgeom<T>(n);
   if (nparts) *nparts = g.chunks;
   k_pcg_update<T><<<sgrid<T>(g, B), kBlock, 0, st>>>(g, grid_stride(n), x, p, r, q, s);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_pcg_rupdate(int n, int B, T* r, const T* q, SolveState s, uint32_t* nparts, hipStream_t st) {
+  const SGeom g = sgeom<T>(n);
+  if (nparts) *nparts = g.chunks;
+  k_pcg_rupdate<T><<<sgrid<T>(g, B), kBlock, 0, st>>>(g, grid_stride(n), r, q, s);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_pcg_finish(int n, int B, T* x, const T* p0, const T* p1, const int* mask, SolveState s,
+                             hipStream_t st) {
+  const SGeom g = sgeom<T>(n);
+  k_pcg_finish<T><<<sgrid<T>(g, B), kBlock, 0, st>>>(g, grid_stride(n), x, p0, p1, mask, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_dir_begin(int B, SolveState s, hipStream_t st) {
+  k_dir_begin<<<dim3((B + kBlock - 1) / kBlock), kBlock, 0, st>>>(B, s);
   return hipGetLastError();
 }
 
@@ -403,6 +487,12 @@ template hipError_t launch_pcg_update<float>(int, int, float*, const float*, flo
                                              uint32_t*, hipStream_t);
 template hipError_t launch_pcg_update<double>(int, int, double*, const double*, double*, const double*, SolveState,
                                               uint32_t*, hipStream_t);
+template hipError_t launch_pcg_rupdate<float>(int, int, float*, const float*, SolveState, uint32_t*, hipStream_t);
+template hipError_t launch_pcg_rupdate<double>(int, int, double*, const double*, SolveState, uint32_t*, hipStream_t);
+template hipError_t launch_pcg_finish<float>(int, int, float*, const float*, const float*, const int*, SolveState,
+                                             hipStream_t);
+template hipError_t launch_pcg_finish<double>(int, int, double*, const double*, const double*, const int*, SolveState,
+                                              hipStream_t);
 template hipError_t launch_dot<float>(int, int, const float*, const float*, SolveState, uint32_t*, hipStream_t);
 template hipError_t launch_dot<double>(int, int, const double*, const double*, SolveState, uint32_t*, hipStream_t);
 template hipError_t launch_pcg_direction<float>(int, int, const float*, float*, SolveState, hipStream_t);

@@ -173,7 +173,9 @@ int step(Pool& p) {
   const double h = 1.0 / n;
   auto& L = p.w.L32;
   uint32_t np = 0;
+  const bool dir = dir_fusable<float>(ctx, L, S);
   // restart the inner solve: rin = (float) r64, d = 0, z = M^-1 rin, p = z
+  // (with the fused direction, the first iteration forms z and p)
   if (int rc = masks(p)) return rc;
   {
     SolveState ir = view(p.w.inner.s, p.m_restart, p.phase);
@@ -182,26 +184,39 @@ int step(Pool& p) {
     SRV_LAUNCH(launch_fill_interior<float>(n, S, p.w.d, 0.0, p.m_restart, st));
     SRV_LAUNCH(launch_dot<float>(n, S, p.w.rin, p.w.rin, ir, &np, st));
     SRV_LAUNCH(launch_reduce(S, RED_BB, 0.0, np, ir, nullptr, st));
-    float* z = nullptr;
-    np = 0;
-    if (int rc = precondition<float>(ctx, L, S, p.w.rin, &z, ir, &np)) return rc;
-    if (!np) SRV_LAUNCH(launch_dot<float>(n, S, p.w.rin, z, ir, &np, st));
-    SRV_LAUNCH(launch_reduce(S, RED_RZ_INIT, 0.0, np, ir, nullptr, st));
-    SRV_LAUNCH(launch_copy<float>(n, S, z, p.w.p32, ir, st));
+    if (dir) {
+      // the first iteration preconditions rin itself
+      if (int rc = pcg_dir_begin<float>(ctx, L, S, ir, p.w.rin, p.m_restart)) return rc;
+    } else {
+      float* z = nullptr;
+      np = 0;
+      if (int rc = precondition<float>(ctx, L, S, p.w.rin, &z, ir, &np)) return rc;
+      if (!np) SRV_LAUNCH(launch_dot<float>(n, S, p.w.rin, z, ir, &np, st));
+      SRV_LAUNCH(launch_reduce(S, RED_RZ_INIT, 0.0, np, ir, nullptr, st));
+      SRV_LAUNCH(launch_copy<float>(n, S, z, p.w.p32, ir, st));
+    }
     SRV_LAUNCH(launch_set_phase_mask(S, p.m_restart, p.phase, PHASE_INNER, nullptr, st));
   }
   // one inner iteration
   if (int rc = masks(p)) return rc;
   {
     SolveState ii = view(p.w.inner.s, p.w.inner.s.active, p.phase);
-    if (int rc = pcg_iteration<float>(ctx, L, S, ii, p.w.d, p.w.rin, p.w.p32, p.w.q32, kInnerTol * kInnerTol,
-                                      RED_RR_INNER, false))
+    const double tol2 = kInnerTol * kInnerTol;
+    if (dir) {
+      if (int rc = pcg_iteration_dir<float>(ctx, L, S, ii, p.w.d, p.w.rin, p.w.p32, p.w.p32b, p.w.q32, tol2,
+                                            RED_RR_INNER, false))
+        return rc;
+    } else if (int rc = pcg_iteration<float>(ctx, L, S, ii, p.w.d, p.w.rin, p.w.p32, p.w.q32, tol2, RED_RR_INNER,
+                                             false)) {
       return rc;
+    }
   }
   // fp64 refinement of converged inner solves
   if (int rc = masks(p)) return rc;
   {
     SolveState ot = view(p.w.outer.s, p.m_trans, p.phase);
+    if (dir)   // the update the inner solve's last step still owes d
+      SRV_LAUNCH(launch_pcg_finish<float>(n, S, p.w.d, p.w.p32, p.w.p32b, p.m_trans, p.w.inner.s, st));
     SRV_LAUNCH(launch_add_correction(n, S, p.u, p.w.d, ot, st));
     SRV_LAUNCH(launch_true_residual(n, S, p.kap64, h * h * h, p.u, p.w.r64, ot, &np, st, zv<double>(ctx)));
     SRV_LAUNCH(launch_reduce(S, RED_RR_OUTER, ctx->cfg.rtol * ctx->cfg.rtol, np, ot, nullptr, st));
@@ -371,6 +386,7 @@ int mlmc_serve_start(mlmc_ctx* ctx, const int32_t* slots_per_mesh) {
     p.sub.zvar[1] = ctx->zvar[1];
     p.sub.vsmall_n0[0] = ctx->vsmall_n0[0];
     p.sub.vsmall_n0[1] = ctx->vsmall_n0[1];
+    p.sub.fuse = ctx->fuse;
     p.sub.use_graphs = false;
     if (hipStreamCreate(&p.sub.st) != hipSuccess) rc = MLMC_E_DEVICE;
     p.sub.own_stream = true;

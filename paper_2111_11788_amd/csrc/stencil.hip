@@ -313,6 +313,83 @@ struct EpiPcgUpdateZero {
   }
 };
 
+// PCG update without the iterate (the fused direction step applies x += alpha p
+// one iteration later): r -= alpha q, sum r.r, and z = c2 D^-1 r with the
+// updated r (the zero-iterate step of the following V-cycle).
+template <class T, int V>
+struct EpiPcgRUpdateZero {
+  static constexpr bool kReduce = true;
+  static constexpr bool kBegin = true;
+  T* r;
+  const T* q;
+  T* z;
+  const double* alpha;
+  T c2;
+  T a = T(0);
+  __device__ void begin(uint32_t b) { a = (T)alpha[b]; }
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
+    T rv[V], qv[V], zo[V];
+    vload<T, V>(r + pos, rv);
+    vload<T, V>(q + pos, qv);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      rv[v] = rv[v] - a * qv[v];
+      acc += (double)rv[v] * (double)rv[v];
+      zo[v] = ok[v] ? c2 * rv[v] * inv_diag(dg[v]) : T(0);
+    }
+    vstore<T, V>(r + pos, rv);
+    vstore<T, V>(z + pos, zo);
+  }
+};
+
+// The conjugate direction fused with the operator apply (operand OP_DIR:
+// p = z + beta p_old staged on the fly): writes p into the other direction
+// buffer (neighbouring workgroups still read p_old), q = A p, the partial
+// sums of p . q, and applies the previous iteration's x += alpha p_old (alpha
+// is still that iteration's value when this kernel runs).  On a sample's
+// first direction there is no previous update.
+template <class T, int V>
+struct EpiDirApply {
+  static constexpr bool kReduce = true;
+  static constexpr bool kBegin = true;
+  T* x;
+  T* p0;
+  T* p1;
+  T* q;
+  const int* pstate;
+  const double* alpha;
+  T a = T(0);
+  const T* pold = nullptr;
+  T* pnew = nullptr;
+  bool prev = false;
+  __device__ void begin(uint32_t b) {
+    const int ps = pstate[b];
+    prev = (ps & 2) == 0;
+    a = (T)alpha[b];
+    pold = (ps & 1) ? p1 : p0;
+    pnew = (ps & 1) ? p0 : p1;
+  }
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
+    T pn[V], o[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      pn[v] = ok[v] ? uc[v] : T(0);
+      o[v] = ok[v] ? au[v] : T(0);
+      acc += (double)pn[v] * (double)o[v];
+    }
+    vstore<T, V>(pnew + pos, pn);
+    vstore<T, V>(q + pos, o);
+    if (prev) {
+      T xv[V], pv[V];
+      vload<T, V>(x + pos, xv);
+      vload<T, V>(pold + pos, pv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) xv[v] = xv[v] + a * pv[v];
+      vstore<T, V>(x + pos, xv);
+    }
+  }
+};
+
 // --------------------------------------------------------- z-march engine
 // PF: issue the loads of the next plane step before computing the current one
 // (one more plane of registers, more memory-level parallelism per wave).
@@ -560,25 +637,105 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
 // LDS rows: u row = [.., u(-1) = 0 at V-1, u(0..n-1) at V.., u(n) = 0 at V+n],
 // stride n + 2V; kappa row = [.., 0 at V-1, kappa(0..n-1) at V..], stride n + V
 // (the zero cells are written once and never overwritten).  u plane kk lives
-// in ring slot kk mod 3, kappa plane ez in slot ez mod 2.  PRO adds P xc to
+// in ring slot kk mod 3, kappa plane ez in slot ez mod KP.  PRO adds P xc to
 // each staged u vector (same operation order as the register engine).
+//
+// Operand modes (the value staged for a u position):
+//   OP_PLAIN  u
+//   OP_ADDD   u + d (fp32 d in the same layout; u may be null: zero)
+//   OP_Z1     c2 D^-1 u: the first smoothing step from a zero iterate of a
+//             V-cycle whose right-hand side is u, formed while staging so
+//             that step is never stored.  D of a staged node needs the kappa
+//             planes kk-1, kk of its u plane and one more element row on
+//             each side, so the kappa ring holds KP = 4 planes (staged three
+//             planes ahead of the computed one instead of one) and R + 3 rows.
+//   OP_DIR    z + beta p_old: the next conjugate direction, from z = u and the
+//             sample's current direction p_old (the buffer p[pstate & 1]);
+//             for a sample's first direction (pstate & 2) p_old is not read and
+//             the operand is z.
+enum : int { OP_PLAIN = 0, OP_ADDD = 1, OP_Z1 = 2, OP_DIR = 3 };
+
+template <class T>
+struct OpArgs {
+  const float* d = nullptr;       // OP_ADDD
+  T c2 = T(0);                    // OP_Z1
+  const T* p0 = nullptr;          // OP_DIR: the two direction buffers
+  const T* p1 = nullptr;
+  const int* pstate = nullptr;    // OP_DIR: per sample, bit 0 = buffer of p_old, bit 1 = first direction
+  const double* beta = nullptr;   // OP_DIR
+};
+
+template <int OP> struct ZOp {
+  static constexpr int KOFF = OP == OP_Z1 ? 1 : 0;   // extra kappa rows on each side
+  static constexpr int KP = OP == OP_Z1 ? 4 : 2;     // kappa ring planes
+  static constexpr int LEAD = OP == OP_Z1 ? 3 : 1;   // kappa plane stored at step k: k + LEAD
+};
+
 template <class T>
 __host__ __device__ inline int zlds_urs(int n) { return n + 2 * ZV<T>::V; }
 template <class T>
 __host__ __device__ inline int zlds_krs(int n) { return n + ZV<T>::V; }
-template <class T>
+// LDS of a k_zlds workgroup: u ring of 3 planes x (rows + 2) rows, kappa
+// ring of KP planes x (rows + 1 + 2 KOFF) rows
+template <class T, int OP = OP_PLAIN>
 inline size_t zlds_bytes(const ZGeom& g) {
-  return ((size_t)3 * (g.rows + 2) * zlds_urs<T>(g.n) + (size_t)2 * (g.rows + 1) * zlds_krs<T>(g.n)) * sizeof(T);
+  return ((size_t)3 * (g.rows + 2) * zlds_urs<T>(g.n) +
+          (size_t)ZOp<OP>::KP * (g.rows + 1 + 2 * ZOp<OP>::KOFF) * zlds_krs<T>(g.n)) * sizeof(T);
+}
+// the staging covers every row with two vectors per thread
+// and the rings fit the 64 KiB of LDS a workgroup may take without opting in
+template <class T, int OP = OP_PLAIN>
+inline bool zlds_ok(const ZGeom& g) {
+  return (g.rows + 2) * g.G <= 2 * g.threads && (g.rows + 1 + 2 * ZOp<OP>::KOFF) * g.G <= 2 * g.threads &&
+         zlds_bytes<T, OP>(g) <= 65536;
 }
 
-template <class T, int V, bool NEED_U, bool PRO, bool ADDD, class Epi>
+// c2 D^-1 b for the V staged nodes c*V .. c*V+V-1 of row jj, plane kk, in u
+// (b on entry); D from the kappa ring (element planes kk-1, kk in slots s0,
+// s1; element row ey in ring row ey - krow0) with the operation order of the
+// stencil kernels' diagonal and of EpiChebZero, so the value is the one that
+// step would have stored; 0 on boundary nodes.  The branch is uniform over
+// the lanes of a row, which is what the DPP halo exchange needs.
+template <class T, int V>
+__device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int KRS, int krow0, int s0, int s1, int jj,
+                                        int kk, int n, int c, int G, bool shuf, T h, T c2) {
+  if (jj < 1 || jj > n - 1 || kk < 1 || kk > n - 1) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) u[v] = T(0);
+    return;
+  }
+  T K[2][2][V + 1];
+  const int sl[2] = {s0, s1};
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+      lds_krow<T, V>(Kl + (sl[dz] * KR + jj - 1 + dy - krow0) * KRS + V + c * V, K[dz][dy], c, G, shuf);
+  const T third = T(1) / T(3);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    T ks = T(0);
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+      for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) ks += K[sz][sy][v + sx];
+    const T dg = h * ks * third;
+    u[v] = (c * V + v) != 0 ? c2 * u[v] * inv_diag(dg) : T(0);
+  }
+}
+
+template <class T, int V, bool NEED_U, bool PRO, int OP, class Epi>
 __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const T* __restrict__ u,
                                               const T* __restrict__ kap, const int* __restrict__ active,
                                               double* __restrict__ partial, uint32_t pstride, Epi epi,
-                                              const T* __restrict__ xc, size_t cstride,
-                                              const float* __restrict__ dadd) {
+                                              const T* __restrict__ xc, size_t cstride, OpArgs<T> op) {
   static_assert(!PRO || NEED_U, "the fused prolongation needs the u operand");
-  static_assert(!ADDD || (NEED_U && !PRO), "the added vector needs the plain u operand");
+  static_assert(OP == OP_PLAIN || NEED_U, "operand modes need the u operand");
+  static_assert(OP != OP_ADDD || !PRO, "the added vector needs the plain u operand");
+  constexpr bool ADDD = OP == OP_ADDD, Z1 = OP == OP_Z1, DIR = OP == OP_DIR;
+  constexpr int KOFF = ZOp<OP>::KOFF, KP = ZOp<OP>::KP, LEAD = ZOp<OP>::LEAD;
   typedef typename Vec<float, V>::type fvt;
   typedef typename Vec<T, V>::type vt;
   extern __shared__ __align__(16) unsigned char zsmem[];
@@ -589,24 +746,38 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   if (active && !active[b]) return;   // uniform over the workgroup
   const int rb = (int)(part % (uint32_t)g.row_blocks), zb = (int)(part / (uint32_t)g.row_blocks);
   const int n = g.n, n2 = n * n, G = g.G, R = g.rows;
-  const int UR = R + 2, KR = R + 1;
+  const int UR = R + 2, KR = R + 1 + 2 * KOFF;
   const int URS = zlds_urs<T>(n), KRS = zlds_krs<T>(n);
-  T* Ul = reinterpret_cast<T*>(zsmem);        // [3][UR][URS]
-  T* Kl = Ul + 3 * UR * URS;                   // [2][KR][KRS]
+  T* Ul = reinterpret_cast<T*>(zsmem);        // [3][UR][URS]:  u rows j0-1 .. j0+R
+  T* Kl = Ul + 3 * UR * URS;                   // [KP][KR][KRS]: kappa rows krow0 ..
   const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
   const int j0 = 1 + rb * R;
+  const int krow0 = j0 - 1 - KOFF;
   const int k0 = 1 + zb * g.zlen;
   int k1 = k0 + g.zlen;
   if (k1 > n) k1 = n;
+  // last kappa plane staged: the computed planes need k1-1; OP_Z1 also forms
+  // the operand on u plane k1
+  const int kmax = Z1 ? (k1 < n - 1 ? k1 : n - 1) : k1 - 1;
   const int gx = tid % G, jr = tid / G;
   const int j = j0 + jr, i0 = gx * V;
   const bool valid = jr < R && j <= n - 1 && k0 < k1;
   const bool shuf = G <= 64;
   const T* ub = (NEED_U && u) ? u + (size_t)b * stride : nullptr;
-  const float* db = ADDD ? dadd + (size_t)b * stride : nullptr;
+  const float* db = ADDD ? op.d + (size_t)b * stride : nullptr;
   const T* kb = kap + (size_t)b * n2 * n;
   const T* cb = PRO ? xc + (size_t)b * cstride : nullptr;
   const int nc = n >> 1, nc2 = nc * nc;
+  // OP_DIR: the sample's previous direction (absent for its first one) and beta
+  bool dir_prev = false;
+  T dbeta = T(0);
+  const T* pob = nullptr;
+  if constexpr (DIR) {
+    const int ps = op.pstate[b];
+    dir_prev = (ps & 2) == 0;
+    dbeta = (T)op.beta[b];
+    pob = ((ps & 1) ? op.p1 : op.p0) + (size_t)b * stride;
+  }
   if constexpr (Epi::kBegin) epi.begin(b);
 
   // zero cells (i = -1, i = n of u; ex = -1 of kappa) of every ring row
@@ -614,12 +785,13 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
     Ul[q * URS + V - 1] = T(0);
     Ul[q * URS + V + n] = T(0);
   }
-  for (int q = tid; q < 2 * KR; q += nthr) Kl[q * KRS + V - 1] = T(0);
+  for (int q = tid; q < KP * KR; q += nthr) Kl[q * KRS + V - 1] = T(0);
 
   // staging: up to two 16-byte vectors per thread per plane for u and kappa;
   // a thread stages the same (row, column) positions on every plane
   vt pu[2], pk[2];
   fvt pd[ADDD ? 2 : 1];
+  vt pp[DIR ? 2 : 1];
   // PRO: per staged vector, the coarse values I0 .. I0+V/2 of its parent rows
   // Jlo = jj/2, Jhi = (jj+1)/2 on coarse planes cK and cK+1 (the parents of
   // fine planes 2cK and 2cK+1), refreshed every second fine plane
@@ -673,18 +845,30 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         if (!ADDD || ub) pu[m] = *reinterpret_cast<const vt*>(ub + off);
         else pu[m] = vt{};
         if (ADDD) pd[ADDD ? m : 0] = *reinterpret_cast<const fvt*>(db + off);
+        if (DIR && dir_prev) pp[DIR ? m : 0] = *reinterpret_cast<const vt*>(pob + off);
       }
     }
   };
-  // store the plane kk fetched last (the loads were in flight meanwhile);
-  // PRO adds the correction here, from the coarse window fetched with it
-  auto store_u = [&](int slot, int kk) {
+  // form the operand of the plane kk fetched last, in registers (the loads
+  // were in flight meanwhile): OP_Z1 from kappa planes kk-1, kk (already in
+  // the ring), then PRO adds the correction from the coarse window fetched
+  // with it.  Done before the barrier that precedes put_u, so it overlaps the
+  // other waves' stencil work instead of stalling the workgroup.
+  auto prep_u = [&](int kk) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = tid + m * nthr;
       const int r = v / G, c = v - (v / G) * G;
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) {
+        if (Z1) {
+          T w[V];
+#pragma unroll
+          for (int t = 0; t < V; ++t) w[t] = pu[m][t];
+          z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, G, shuf, h, op.c2);
+#pragma unroll
+          for (int t = 0; t < V; ++t) pu[m][t] = w[t];
+        }
         if (PRO) {
           // fine nodes c*V .. c*V+V-1 of row jj, plane kk
           const bool kodd = (kk & 1) != 0, jodd = (jj & 1) != 0;
@@ -703,49 +887,75 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
 #pragma unroll
           for (int t = 0; t < V; ++t) pu[m][t] += (T)pd[ADDD ? m : 0][t];
         }
-        *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + V + c * V) = pu[m];
+        if (DIR && dir_prev) pu[m] = pu[m] + dbeta * pp[DIR ? m : 0];
       }
     }
+  };
+  auto put_u = [&](int slot) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + V + c * V) = pu[m];
+    }
+  };
+  auto store_u = [&](int slot, int kk) {
+    prep_u(kk);
+    put_u(slot);
   };
   auto fetch_k = [&](int ez) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = tid + m * nthr;
       const int r = v / G, c = v - (v / G) * G;
-      const int ey = j0 - 1 + r;
-      if (v < KR * G && ey <= n - 1)
+      const int ey = krow0 + r;
+      if (v < KR * G && ey >= 0 && ey <= n - 1)
         pk[m] = *reinterpret_cast<const vt*>(kb + (size_t)n2 * ez + (size_t)n * ey + c * V);
     }
   };
-  auto store_k = [&](int slot) {
+  auto store_k = [&](int ez) {
+    const int slot = ez & (KP - 1);
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = tid + m * nthr;
       const int r = v / G, c = v - (v / G) * G;
-      if (v < KR * G && j0 - 1 + r <= n - 1)
+      const int ey = krow0 + r;
+      if (v < KR * G && ey >= 0 && ey <= n - 1)
         *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + V + c * V) = pk[m];
     }
   };
 
   double acc = 0.0;
   if (k0 < k1) {
-    // prologue: u planes k0-1, k0, k0+1 and kappa planes k0-1, k0 into LDS;
-    // then the loads of u plane k0+2 and kappa plane k0+1 are left in flight
-    if (NEED_U) {
+    // prologue: u planes k0-1, k0, k0+1 and kappa planes up to k0 + LEAD - 1
+    // into LDS; then the loads of u plane k0+2 and kappa plane k0 + LEAD are
+    // left in flight
+    if (Z1) {
+      // the operand of u plane kk needs kappa planes kk-1, kk
+      for (int ez = k0 - 2; ez <= k0 + 1; ++ez)
+        if (ez >= 0 && ez <= kmax) { fetch_k(ez); store_k(ez); }
+      __syncthreads();
       fetch_u(k0 - 1); store_u((k0 - 1) % 3, k0 - 1);
       fetch_u(k0); store_u(k0 % 3, k0);
       fetch_u(k0 + 1); store_u((k0 + 1) % 3, k0 + 1);
+      __syncthreads();   // kappa plane k0-2 is no longer read: its slot takes plane k0+2
+      if (k0 + 2 <= kmax) { fetch_k(k0 + 2); store_k(k0 + 2); }
+    } else {
+      if (NEED_U) {
+        fetch_u(k0 - 1); store_u((k0 - 1) % 3, k0 - 1);
+        fetch_u(k0); store_u(k0 % 3, k0);
+        fetch_u(k0 + 1); store_u((k0 + 1) % 3, k0 + 1);
+      }
+      fetch_k(k0 - 1); store_k(k0 - 1);
+      fetch_k(k0); store_k(k0);
     }
-    fetch_k(k0 - 1); store_k((k0 - 1) & 1);
-    fetch_k(k0); store_k(k0 & 1);
     if (NEED_U && k0 + 2 <= k1) fetch_u(k0 + 2);
-    if (k0 + 1 < k1) fetch_k(k0 + 1);
+    if (k0 + LEAD <= kmax) fetch_k(k0 + LEAD);
     __syncthreads();
     bool ok[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) ok[v] = (i0 + v) != 0;
     int sm = (k0 - 1) % 3, s0 = k0 % 3, sp = (k0 + 1) % 3;   // u slots of planes k-1, k, k+1
-    int km = (k0 - 1) & 1, kc = k0 & 1;                          // kappa slots of planes k-1, k
     const T third = T(1) / T(3), twelfth = T(1) / T(12);
     for (int k = k0; k < k1; ++k) {
       if (valid) {
@@ -754,12 +964,12 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         // j-1, j+1; plane k: rows j-1, j+1 and the centre values) so that only
         // one plane of the window is live.
         T K[2][2][V + 1];
-        const int ks[2] = {km, kc};
+        const int ks[2] = {(k - 1) & (KP - 1), k & (KP - 1)};
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
           for (int dy = 0; dy < 2; ++dy)
-            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy) * KRS + V + i0, K[dz][dy], gx, G, shuf);
+            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy + KOFF) * KRS + V + i0, K[dz][dy], gx, G, shuf);
         T far[V], ksum[V], uc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -812,14 +1022,17 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         epi((size_t)b * stride + i0 + (size_t)n * j + (size_t)n2 * k, au, dg, uc, ok, acc);
       }
       if (k + 1 < k1) {
-        __syncthreads();   // every thread is done with u plane k-1 and kappa plane k-1
-        if (NEED_U && k + 2 <= k1) store_u(sm, k + 2);   // plane k+2 takes the slot of plane k-1
-        store_k(km);                               // kappa plane k+1 takes the slot of plane k-1
+        // u plane k+2 (OP_Z1: from kappa planes k+1, k+2, stored in earlier
+        // steps; kappa plane k+3 takes the slot of plane k-1 below)
+        if (NEED_U && k + 2 <= k1) prep_u(k + 2);
+        // every thread is done with u plane k-1 and kappa plane k-1
+        __syncthreads();
+        if (NEED_U && k + 2 <= k1) put_u(sm);   // plane k+2 takes the slot of plane k-1
+        if (k + LEAD <= kmax) store_k(k + LEAD);
         if (NEED_U && k + 3 <= k1) fetch_u(k + 3);
-        if (k + 2 < k1) fetch_k(k + 2);
+        if (k + LEAD + 1 <= kmax) fetch_k(k + LEAD + 1);
         __syncthreads();
         const int t = sm; sm = s0; s0 = sp; sp = t;
-        const int tk = km; km = kc; kc = tk;
       }
     }
   }
@@ -840,25 +1053,37 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
 // is produced by exactly one workgroup: a thread owning (I, J) adds the
 // in-plane full-weighting sum of t, weighted 1/2 from odd fine planes and 1
 // from even ones, and stores the coarse value when plane 2K+1 is done.
-template <class T>
+// With Z1 the operand x is c2 D^-1 b, formed while staging (see OP_Z1), so a
+// V-cycle level's zero-start pre-smoothing step costs no pass of its own.
+template <class T, bool Z1 = false>
 inline size_t resr_bytes(const ZGeom& g) {
-  return ((size_t)3 * (g.rows + 3) * zlds_urs<T>(g.n) + (size_t)2 * (g.rows + 2) * zlds_krs<T>(g.n) +
+  constexpr int KOFF = Z1 ? 1 : 0, KP = Z1 ? 4 : 2;
+  return ((size_t)3 * (g.rows + 3) * zlds_urs<T>(g.n) + (size_t)KP * (g.rows + 2 + 2 * KOFF) * zlds_krs<T>(g.n) +
           (size_t)(g.rows + 1) * zlds_urs<T>(g.n)) * sizeof(T);
 }
 
+// Geometry of k_resr: the tiles of k_zlds.  (Adding threads so that the
+// extra residual row of a full tile takes no second pass measured slower on
+// the 64^3 batch: 320 threads, 9.8 -> 15.6 ms per step.)
+template <class T>
+inline ZGeom resr_geom(int n, int B) { return zgeom<T>(n, B); }
+
 // usable when every tile and chunk starts on an odd index and the staging
 // fits two vectors per thread
-template <class T>
+template <class T, bool Z1 = false>
 inline bool resr_ok(const ZGeom& g) {
   return g.n >= 4 && g.rows % 2 == 0 && (g.zc == 1 || g.zlen % 2 == 0) &&
-         (g.rows + 3) * g.G <= 2 * g.threads && (g.rows + 1) * g.G <= 2 * g.threads;
+         g.threads <= 256 && (g.rows + 3) * g.G <= 2 * g.threads && (g.rows + 2 + (Z1 ? 2 : 0)) * g.G <= 2 * g.threads &&
+         resr_bytes<T, Z1>(g) <= 65536;
 }
 
-template <class T, int V>
+template <class T, int V, bool Z1>
 __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const T* __restrict__ x,
                                               const T* __restrict__ bf, const T* __restrict__ kap,
-                                              const int* __restrict__ active, T* __restrict__ bc, size_t cstride) {
+                                              const int* __restrict__ active, T* __restrict__ bc, size_t cstride,
+                                              T c2) {
   typedef typename Vec<T, V>::type vt;
+  constexpr int KOFF = Z1 ? 1 : 0, KP = Z1 ? 4 : 2, LEAD = Z1 ? 3 : 1;
   extern __shared__ __align__(16) unsigned char zsmem[];
   const uint32_t per = g.parts();
   const uint32_t lin = xcd_remap(blockIdx.x, gridDim.x);
@@ -867,21 +1092,26 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
   if (active && !active[b]) return;   // uniform over the workgroup
   const int rb = (int)(part % (uint32_t)g.row_blocks), zb = (int)(part / (uint32_t)g.row_blocks);
   const int n = g.n, n2 = n * n, G = g.G, R = g.rows;
-  const int UR = R + 3, KR = R + 2, TR = R + 1;
+  const int UR = R + 3, KR = R + 2 + 2 * KOFF, TR = R + 1;
   const int URS = zlds_urs<T>(n), KRS = zlds_krs<T>(n);
-  T* Ul = reinterpret_cast<T*>(zsmem);        // [3][UR][URS]: u rows j0-1 .. j0+R+1
-  T* Kl = Ul + 3 * UR * URS;                   // [2][KR][KRS]: kappa rows j0-1 .. j0+R
-  T* Tl = Kl + 2 * KR * KRS;                   // [TR][URS]:    t rows j0 .. j0+R
+  T* Ul = reinterpret_cast<T*>(zsmem);        // [3][UR][URS]:  u rows j0-1 .. j0+R+1
+  T* Kl = Ul + 3 * UR * URS;                   // [KP][KR][KRS]: kappa rows j0-1-KOFF .. j0+R+KOFF
+  T* Tl = Kl + KP * KR * KRS;                  // [TR][URS]:     t rows j0 .. j0+R
   const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
   const int j0 = 1 + rb * R;
+  const int krow0 = j0 - 1 - KOFF;
   const int k0 = 1 + zb * g.zlen;
   int k1 = k0 + g.zlen;
   if (k1 > n) k1 = n;
   const int kt1 = k1 < n - 1 ? k1 : n - 1;    // last residual plane
-  // halos from LDS here: measured faster than the DPP exchange for this kernel
-  // (its extra-row tasks leave most of a wave idle around the exchange)
+  // last kappa plane staged: the residual planes need kt1; Z1 also forms the
+  // operand on u plane kt1 + 1
+  const int kmax = Z1 ? (kt1 + 1 < n - 1 ? kt1 + 1 : n - 1) : kt1;
+  // halos from LDS in the residual: measured faster than the DPP exchange for
+  // this kernel (its extra-row tasks leave most of a wave idle around the
+  // exchange); the Z1 staging rows are whole waves and use DPP
   const bool shuf = false;
-  const T* ub = x + (size_t)b * stride;
+  const T* ub = (Z1 ? bf : x) + (size_t)b * stride;
   const T* bb = bf + (size_t)b * stride;
   const T* kb = kap + (size_t)b * n2 * n;
   const int nc = n >> 1, nc2 = nc * nc;
@@ -890,7 +1120,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
     Ul[q * URS + V - 1] = T(0);
     Ul[q * URS + V + n] = T(0);
   }
-  for (int q = tid; q < 2 * KR; q += nthr) Kl[q * KRS + V - 1] = T(0);
+  for (int q = tid; q < KP * KR; q += nthr) Kl[q * KRS + V - 1] = T(0);
 
   vt pu[2], pk[2];
   auto fetch_u = [&](int kk) {
@@ -902,7 +1132,26 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
       if (v < UR * G && jj <= n) pu[m] = *reinterpret_cast<const vt*>(ub + (size_t)n2 * kk + (size_t)n * jj + c * V);
     }
   };
-  auto store_u = [&](int slot) {
+  // Z1: the operand of the plane kk fetched last, in registers, before the
+  // barrier that precedes put_u (see k_zlds)
+  auto prep_u = [&](int kk) {
+    if (!Z1) return;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v / G, c = v - (v / G) * G;
+      const int jj = j0 - 1 + r;
+      if (v < UR * G && jj <= n) {
+        T w[V];
+#pragma unroll
+        for (int t = 0; t < V; ++t) w[t] = pu[m][t];
+        z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, G, G <= 64, h, c2);
+#pragma unroll
+        for (int t = 0; t < V; ++t) pu[m][t] = w[t];
+      }
+    }
+  };
+  auto put_u = [&](int slot) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = tid + m * nthr;
@@ -910,22 +1159,28 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
       if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + V + c * V) = pu[m];
     }
   };
+  auto store_u = [&](int slot, int kk) {
+    prep_u(kk);
+    put_u(slot);
+  };
   auto fetch_k = [&](int ez) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = tid + m * nthr;
       const int r = v / G, c = v - (v / G) * G;
-      const int ey = j0 - 1 + r;
-      if (v < KR * G && ey <= n - 1)
+      const int ey = krow0 + r;
+      if (v < KR * G && ey >= 0 && ey <= n - 1)
         pk[m] = *reinterpret_cast<const vt*>(kb + (size_t)n2 * ez + (size_t)n * ey + c * V);
     }
   };
-  auto store_k = [&](int slot) {
+  auto store_k = [&](int ez) {
+    const int slot = ez & (KP - 1);
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = tid + m * nthr;
       const int r = v / G, c = v - (v / G) * G;
-      if (v < KR * G && j0 - 1 + r <= n - 1)
+      const int ey = krow0 + r;
+      if (v < KR * G && ey >= 0 && ey <= n - 1)
         *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + V + c * V) = pk[m];
     }
   };
@@ -938,18 +1193,29 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
   T cacc = T(0);
 
   if (k0 < k1) {
-    fetch_u(k0 - 1); store_u((k0 - 1) % 3);
-    fetch_u(k0); store_u(k0 % 3);
-    fetch_u(k0 + 1); store_u((k0 + 1) % 3);
-    fetch_k(k0 - 1); store_k((k0 - 1) & 1);
-    fetch_k(k0); store_k(k0 & 1);
+    if (Z1) {
+      for (int ez = k0 - 2; ez <= k0 + 1; ++ez)
+        if (ez >= 0 && ez <= kmax) { fetch_k(ez); store_k(ez); }
+      __syncthreads();
+      fetch_u(k0 - 1); store_u((k0 - 1) % 3, k0 - 1);
+      fetch_u(k0); store_u(k0 % 3, k0);
+      fetch_u(k0 + 1); store_u((k0 + 1) % 3, k0 + 1);
+      __syncthreads();   // kappa plane k0-2 is no longer read: its slot takes plane k0+2
+      if (k0 + 2 <= kmax) { fetch_k(k0 + 2); store_k(k0 + 2); }
+    } else {
+      fetch_u(k0 - 1); store_u((k0 - 1) % 3, k0 - 1);
+      fetch_u(k0); store_u(k0 % 3, k0);
+      fetch_u(k0 + 1); store_u((k0 + 1) % 3, k0 + 1);
+      fetch_k(k0 - 1); store_k(k0 - 1);
+      fetch_k(k0); store_k(k0);
+    }
     if (k0 + 2 <= kt1 + 1) fetch_u(k0 + 2);
-    if (k0 + 1 <= kt1) fetch_k(k0 + 1);
+    if (k0 + LEAD <= kmax) fetch_k(k0 + LEAD);
     __syncthreads();
     int sm = (k0 - 1) % 3, s0 = k0 % 3, sp = (k0 + 1) % 3;
-    int km = (k0 - 1) & 1, kc = k0 & 1;
     const T third = T(1) / T(3), twelfth = T(1) / T(12);
     for (int kk = k0; kk <= kt1; ++kk) {
+      const int km = (kk - 1) & (KP - 1), kc = kk & (KP - 1);
       // residual of rows j0 .. j0+R on plane kk into LDS
       for (int task = tid; task < TR * G; task += nthr) {
         const int jr = task / G, gx = task - (task / G) * G;
@@ -961,7 +1227,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
           for (int dy = 0; dy < 2; ++dy)
-            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy) * KRS + V + i0, K[dz][dy], gx, G, shuf);
+            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy + KOFF) * KRS + V + i0, K[dz][dy], gx, G, shuf);
         T far[V], ksum[V], uc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1011,6 +1277,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
         }
         vstore<T, V>(Tl + jr * URS + V + i0, t);
       }
+      if (kk + 1 <= kt1) prep_u(kk + 2);   // kappa planes kk+1, kk+2 are in the ring
       __syncthreads();
       // in-plane full weighting of t at the owned coarse node, folded over planes
       if (owner) {
@@ -1034,37 +1301,42 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
         }
       }
       if (kk + 1 <= kt1) {
-        // planes kk-1 (u) and kk-1 (kappa) are no longer read
-        store_u(sm);                       // u plane kk+2
-        store_k(km);                       // kappa plane kk+1
+        // u plane kk-1 and kappa plane kk-1 are no longer read
+        put_u(sm);   // u plane kk+2
+        if (kk + LEAD <= kmax) store_k(kk + LEAD);
         if (kk + 3 <= kt1 + 1) fetch_u(kk + 3);
-        if (kk + 2 <= kt1) fetch_k(kk + 2);
+        if (kk + LEAD + 1 <= kmax) fetch_k(kk + LEAD + 1);
       }
       __syncthreads();
       const int tu = sm; sm = s0; s0 = sp; sp = tu;
-      const int tk = km; km = kc; kc = tk;
     }
   }
 }
 
-template <class T, bool NEED_U, bool PRO, class Epi, bool ADDD = false>
+template <class T, bool NEED_U, bool PRO, int OP, class Epi>
 hipError_t zlaunch_lds(int n, int B, const T* u, const T* xc, const T* kap, const int* active, double* partial,
-                       uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st, const float* dadd = nullptr) {
+                       uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st, OpArgs<T> op = {}) {
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
+  if (!zlds_ok<T, OP>(g)) return hipErrorInvalidValue;
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
-  k_zlds<T, V, NEED_U, PRO, ADDD, Epi><<<dim3(blocks), dim3(g.threads), zlds_bytes<T>(g), st>>>(
-      g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, PRO ? grid_stride(n / 2) : 0,
-      dadd);
+  k_zlds<T, V, NEED_U, PRO, OP, Epi><<<dim3(blocks), dim3(g.threads), zlds_bytes<T, OP>(g), st>>>(
+      g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, PRO ? grid_stride(n / 2) : 0, op);
   return hipGetLastError();
 }
+
+// the LDS engine when selected and its staging covers the tile (the register
+// engine otherwise)
+template <class T>
+inline bool use_lds(int n, int B, int var, int bit) { return (var & bit) && zlds_ok<T>(zgeom<T>(n, B)); }
 
 template <class T, bool NEED_U, class Epi>
 hipError_t zlaunch(int n, int B, const T* u, const T* kap, const int* active, double* partial, uint32_t pstride,
                    Epi epi, uint32_t* nparts, int var, hipStream_t st) {
-  if (var & ZVAR_LDS)
-    return zlaunch_lds<T, NEED_U, false, Epi>(n, B, u, nullptr, kap, active, partial, pstride, epi, nparts, st);
+  if (use_lds<T>(n, B, var, ZVAR_LDS))
+    return zlaunch_lds<T, NEED_U, false, OP_PLAIN, Epi>(n, B, u, nullptr, kap, active, partial, pstride, epi, nparts,
+                                                        st);
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
   if (nparts) *nparts = g.parts();
@@ -1082,9 +1354,12 @@ hipError_t zlaunch(int n, int B, const T* u, const T* kap, const int* active, do
 template <class T, class Epi>
 hipError_t zlaunch_addd(int n, int B, const T* u, const float* d, const T* kap, const int* active, double* partial,
                         uint32_t pstride, Epi epi, uint32_t* nparts, int var, hipStream_t st) {
-  if (var & ZVAR_LDS)
-    return zlaunch_lds<T, true, false, Epi, true>(n, B, u, nullptr, kap, active, partial, pstride, epi, nparts, st,
-                                                  d);
+  if (use_lds<T>(n, B, var, ZVAR_LDS)) {
+    OpArgs<T> op;
+    op.d = d;
+    return zlaunch_lds<T, true, false, OP_ADDD, Epi>(n, B, u, nullptr, kap, active, partial, pstride, epi, nparts, st,
+                                                     op);
+  }
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
   if (nparts) *nparts = g.parts();
@@ -1098,8 +1373,8 @@ hipError_t zlaunch_addd(int n, int B, const T* u, const float* d, const T* kap, 
 template <class T, class Epi>
 hipError_t zlaunch_pro(int n, int B, const T* u, const T* xc, const T* kap, const int* active, double* partial,
                        uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st, int var) {
-  if (var & ZVAR_LDS_PRO)
-    return zlaunch_lds<T, true, true, Epi>(n, B, u, xc, kap, active, partial, pstride, epi, nparts, st);
+  if (use_lds<T>(n, B, var, ZVAR_LDS_PRO))
+    return zlaunch_lds<T, true, true, OP_PLAIN, Epi>(n, B, u, xc, kap, active, partial, pstride, epi, nparts, st);
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
   if (nparts) *nparts = g.parts();
@@ -1379,11 +1654,58 @@ hipError_t launch_cheb_prolong(int n, int B, const T* kap, const T* b, const T* 
 }
 
 template <class T>
+bool presmooth_usable(int n, int B) {
+  const ZGeom g = zgeom<T>(n, B);
+  return n >= 4 && !use_small<T>(n) && resr_ok<T, true>(resr_geom<T>(n, B)) && zlds_ok<T, OP_Z1>(g);
+}
+
+template <class T>
+hipError_t launch_cheb_prolong_presmoothed(int n, int B, const T* kap, const T* b, const T* xc, T* out, double c2,
+                                           const int* active, hipStream_t st, SolveState* dot, uint32_t* nparts) {
+  constexpr int V = ZV<T>::V;
+  if (!presmooth_usable<T>(n, B)) return hipErrorInvalidValue;
+  OpArgs<T> op;
+  op.c2 = T(c2);
+  if (dot)
+    return zlaunch_lds<T, true, true, OP_Z1>(n, B, b, xc, kap, active, dot->partial, dot->pstride,
+                                             EpiCheb<T, V, false, true>{b, nullptr, out, T(0), T(c2)}, nparts, st, op);
+  return zlaunch_lds<T, true, true, OP_Z1>(n, B, b, xc, kap, active, nullptr, 0,
+                                           EpiCheb<T, V, false, false>{b, nullptr, out, T(0), T(c2)}, nullptr, st, op);
+}
+
+template <class T>
 hipError_t launch_pcg_update_zero(int n, int B, const T* kap, T* x, const T* p, T* r, const T* q, T* z, double c2,
                                   SolveState s, uint32_t* nparts, hipStream_t st, int var) {
   if (use_small<T>(n)) return hipErrorInvalidValue;
   return zlaunch<T, false>(n, B, nullptr, kap, s.active, s.partial, s.pstride,
                            EpiPcgUpdateZero<T, ZV<T>::V>{x, p, r, q, z, s.alpha, T(c2)}, nparts, var, st);
+}
+
+template <class T>
+bool dir_usable(int n, int B) {
+  const ZGeom g = zgeom<T>(n, B);
+  return n >= 4 && !use_small<T>(n) && zlds_ok<T, OP_DIR>(g);
+}
+
+template <class T>
+hipError_t launch_pcg_dir_apply(int n, int B, const T* kap, const T* z, T* x, T* p0, T* p1, T* q, const int* pstate,
+                                SolveState s, uint32_t* nparts, hipStream_t st) {
+  if (!dir_usable<T>(n, B)) return hipErrorInvalidValue;
+  OpArgs<T> op;
+  op.p0 = p0;
+  op.p1 = p1;
+  op.pstate = pstate;
+  op.beta = s.beta;
+  return zlaunch_lds<T, true, false, OP_DIR>(n, B, z, nullptr, kap, s.active, s.partial, s.pstride,
+                                             EpiDirApply<T, ZV<T>::V>{x, p0, p1, q, pstate, s.alpha}, nparts, st, op);
+}
+
+template <class T>
+hipError_t launch_pcg_rupdate_zero(int n, int B, const T* kap, T* r, const T* q, T* z, double c2, SolveState s,
+                                   uint32_t* nparts, hipStream_t st, int var) {
+  if (use_small<T>(n)) return hipErrorInvalidValue;
+  return zlaunch<T, false>(n, B, nullptr, kap, s.active, s.partial, s.pstride,
+                           EpiPcgRUpdateZero<T, ZV<T>::V>{r, q, z, s.alpha, T(c2)}, nparts, var, st);
 }
 
 template <class T>
@@ -1407,17 +1729,23 @@ hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, 
 }
 
 template <class T>
-bool resr_usable(int n, int B) { return resr_ok<T>(zgeom<T>(n, B)); }
+bool resr_usable(int n, int B) { return resr_ok<T>(resr_geom<T>(n, B)); }
 
 template <class T>
 hipError_t launch_residual_restrict(int n, int B, const T* kap, const T* b, const T* x, T* bc, const int* active,
-                                   hipStream_t st) {
+                                   hipStream_t st, bool presmooth, double c2) {
   constexpr int V = ZV<T>::V;
-  const ZGeom g = zgeom<T>(n, B);
-  if (!resr_ok<T>(g)) return hipErrorInvalidValue;
+  const ZGeom g = resr_geom<T>(n, B);
   const uint32_t blocks = g.parts() * (uint32_t)B;
-  k_resr<T, V><<<dim3(blocks), dim3(g.threads), resr_bytes<T>(g), st>>>(g, grid_stride(n), T(1) / T(n), x, b, kap,
-                                                                        active, bc, grid_stride(n / 2));
+  if (presmooth) {
+    if (!presmooth_usable<T>(n, B)) return hipErrorInvalidValue;
+    k_resr<T, V, true><<<dim3(blocks), dim3(g.threads), resr_bytes<T, true>(g), st>>>(
+        g, grid_stride(n), T(1) / T(n), nullptr, b, kap, active, bc, grid_stride(n / 2), T(c2));
+    return hipGetLastError();
+  }
+  if (!resr_ok<T>(g)) return hipErrorInvalidValue;
+  k_resr<T, V, false><<<dim3(blocks), dim3(g.threads), resr_bytes<T, false>(g), st>>>(
+      g, grid_stride(n), T(1) / T(n), x, b, kap, active, bc, grid_stride(n / 2), T(0));
   return hipGetLastError();
 }
 
@@ -1477,7 +1805,15 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st) 
   template hipError_t launch_restrict<T>(int, int, const T*, T*, const int*, hipStream_t);             \
   template bool resr_usable<T>(int, int);                                                              \
   template hipError_t launch_residual_restrict<T>(int, int, const T*, const T*, const T*, T*, const int*, \
-                                                  hipStream_t);                                        \
+                                                  hipStream_t, bool, double);                          \
+  template bool presmooth_usable<T>(int, int);                                                         \
+  template bool dir_usable<T>(int, int);                                                               \
+  template hipError_t launch_pcg_dir_apply<T>(int, int, const T*, const T*, T*, T*, T*, T*, const int*,  \
+                                              SolveState, uint32_t*, hipStream_t);                     \
+  template hipError_t launch_pcg_rupdate_zero<T>(int, int, const T*, T*, const T*, T*, double, SolveState, \
+                                                 uint32_t*, hipStream_t, int);                         \
+  template hipError_t launch_cheb_prolong_presmoothed<T>(int, int, const T*, const T*, const T*, T*, double, \
+                                                         const int*, hipStream_t, SolveState*, uint32_t*); \
   template hipError_t launch_prolong_add<T>(int, int, const T*, T*, const int*, hipStream_t);          \
   template hipError_t launch_coarsest<T>(int, const T*, const T*, T*, const int*, hipStream_t);        \
   template hipError_t launch_coarsen<T>(int, int, const T*, T*, hipStream_t, const int*);

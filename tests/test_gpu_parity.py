@@ -141,6 +141,28 @@ def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, fuse, zvar, monkeypatch):
         assert np.abs(z[b] - want).max() <= 1e-12 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("n,B", [(8, 3), (16, 2), (32, 3), (64, 2)])
+def test_presmoothed_vcycle_matches_oracle_and_stored_step(dev, n, B, monkeypatch):
+    # Chebyshev degree 1: the zero-start pre-smoothing step formed inside the
+    # residual-restriction and correction kernels (fuse bit 16) gives the V-cycle
+    # of the oracle, and the same bits as storing that step (both LDS engines);
+    # the fp32 form is covered by the mixed solves below
+    monkeypatch.setenv("MLMC_VSMALL", "0")
+    kap = element_field(n, B, seed=500 + n, spread=1.5)
+    r = grid_vector(n, B, seed=600 + n)
+    outs = []
+    for fuse in (1 | 8 | 16, 1 | 8):
+        ctx = mm.Context(_wl(n0=n, levels=1), cheb_degree=1, arena_bytes=512 << 20)
+        ctx.set_tuning(fuse=fuse, zvar_fp64=6, zvar_fp32=6, vsmall_fp32=0, vsmall_fp64=0)
+        outs.append(ctx.vcycle(n, torch.tensor(kap, device=dev), mm.to_grid(torch.tensor(r, device=dev), n)))
+    assert torch.equal(outs[0], outs[1])
+    z = mm.from_grid(outs[0], n).cpu().numpy()
+    for b in range(B):
+        H = gmg.Hierarchy(n, kap[b])
+        want = H.vcycle(r[b], 1, 4.0, 2.0)
+        assert np.abs(z[b] - want).max() <= 1e-12 * np.abs(want).max()
+
+
 @pytest.mark.parametrize("zvar", [0, 2, 6])
 @pytest.mark.parametrize("deg", [1, 2])
 def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg, zvar):
@@ -149,7 +171,7 @@ def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg, zvar):
     n, B = 32, 3
     wl = _wl(n0=n, levels=1, qoi=1, precision=1, solver=0, n_modes=16, corr_len=0.3)
     qs = []
-    for fuse in (15, 8, 4, 2, 1, 0):   # every fusion bit alone, all, none
+    for fuse in (63, 47, 34, 32, 31, 25, 15, 8, 4, 2, 1, 0):   # every fusion bit alone, all, none, mixes
         ctx = mm.Context(wl, cheb_degree=deg, arena_bytes=512 << 20)
         ctx.set_tuning(fuse=fuse, vsmall_fp32=0, vsmall_fp64=0, zvar_fp32=zvar, zvar_fp64=zvar)
         xi = ctx.draw_xi(0, 21, B)
@@ -168,13 +190,17 @@ def _oracle_q(n, kap, qoi, rtol=1e-12):
     return q
 
 
+@pytest.mark.parametrize("fuse", [None, 0, 32])
 @pytest.mark.parametrize("precision,solver,tol,vsmall", [(0, 0, 1e-8, "1"), (1, 0, 1e-7, "1"), (0, 1, 1e-8, "1"),
                                                          (1, 0, 1e-7, "0")])
 @pytest.mark.parametrize("n,B,qoi", [(8, 5, 0), (16, 3, 1), (32, 2, 1)])
-def test_solve_qoi_matches_oracle(dev, precision, solver, tol, vsmall, n, B, qoi, monkeypatch):
+def test_solve_qoi_matches_oracle(dev, precision, solver, tol, vsmall, n, B, qoi, fuse, monkeypatch):
+    # fuse None: the default fusions; 0: none; 32: the direction fused into the apply alone
     monkeypatch.setenv("MLMC_VSMALL", vsmall)
     wl = _wl(n0=n, levels=1, qoi=qoi, precision=precision, solver=solver, n_modes=16, corr_len=0.3)
     ctx = mm.Context(wl, arena_bytes=512 << 20)
+    if fuse is not None:
+        ctx.set_tuning(fuse=fuse)
     xi = ctx.draw_xi(0, 11, B)
     kap = ctx.field(n, xi)
     u, it = ctx.solve(n, kap)

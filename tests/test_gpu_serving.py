@@ -25,9 +25,13 @@ def dev():
     return torch.device("cuda")
 
 
-def test_served_samples_match_oracle(dev):
+@pytest.mark.parametrize("fuse", [None, 0])
+def test_served_samples_match_oracle(dev, fuse):
+    # fuse None: the default fusions (direction fused into the apply); 0: none
     wl = _wl()
     ctx = mm.Context(wl, arena_bytes=1 << 30)
+    if fuse is not None:
+        ctx.set_tuning(fuse=fuse)
     ctx.serve_start([8, 8, 4])
     reqs = [(0, 3), (1, 4), (2, 5), (2, 6), (1, 7), (0, 8)]
     tickets = {ctx.submit(l, s): (l, s) for l, s in reqs}
