@@ -219,14 +219,14 @@ int mlmc_estimate(mlmc_ctx* ctx, const mlmc_estimate_opts* opts, uint64_t* n_per
 typedef struct mlmc_tuning {
   int32_t zvar_fp32;      /* stencil kernel variant bits for fp32: 0 register window, 1 with the next
                              plane prefetched, 2 LDS-tiled planes, 4 LDS-tiled planes also for the
-                             step that applies the coarse-grid correction (default 2) */
-  int32_t zvar_fp64;      /* same for fp64 */
+                             step that applies the coarse-grid correction (default 6) */
+  int32_t zvar_fp64;      /* same for fp64 (default 2) */
   int32_t vsmall_fp32;    /* mesh from which the coarse V-cycle runs as one LDS kernel (0: off) */
   int32_t vsmall_fp64;    /* same for fp64 (at most 8) */
   int32_t cheb_degree;    /* Chebyshev smoothing degree per half V-cycle, 1..8 */
   int32_t max_batch;      /* samples per batched solve */
   int32_t graph_batch;    /* captured PCG iterations replayed per convergence check (0: no graphs) */
-  int32_t fuse;           /* MLMC_FUSE_* bits: kernel fusions in use (default: all but PRESMOOTH) */
+  int32_t fuse;           /* MLMC_FUSE_* bits: kernel fusions in use (default: all) */
   double seconds;         /* mlmc_autotune: measured seconds per sample of the chosen setting */
 } mlmc_tuning;
 

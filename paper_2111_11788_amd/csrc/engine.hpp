@@ -231,15 +231,15 @@ struct mlmc_ctx {
   int64_t k_launch[2 * MLMC_K_COUNT] = {0};   // [precision][kernel]
   double k_ms[2 * MLMC_K_COUNT] = {0}, k_bytes[2 * MLMC_K_COUNT] = {0};
   int* h_nactive = nullptr;
-  int zvar[2] = {ZVAR_LDS, ZVAR_LDS};   // stencil engine variant bits for fp64 / fp32
+  // stencil engine variant bits for fp64 / fp32 (fp32: the LDS engine also for
+  // the corrected post-smoothing step, measured faster on the 64^3 batch)
+  int zvar[2] = {ZVAR_LDS, ZVAR_LDS | ZVAR_LDS_PRO};
   int vsmall_n0[2] = {8, 16};     // mesh at which the single-kernel coarse V-cycle takes over (0: off)
   bool use_graphs = true;         // replay the PCG iteration from a captured hipGraph
   bool own_stream = false;        // the context created st itself
   int graph_batch = 2;            // graph launches per convergence check
-  // MLMC_FUSE_* bits in use: all but PRESMOOTH, which measured slower on the
-  // 64^3 batch (its LDS engines take more LDS and registers) and is left to
-  // the autotuner
-  int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_DIRECTION;
+  int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
+             MLMC_FUSE_DIRECTION;   // MLMC_FUSE_* bits in use
   mlmc_server* server = nullptr;  // serving pools and threads while serving
 };
 

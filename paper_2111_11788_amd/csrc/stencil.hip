@@ -79,13 +79,18 @@ __device__ __forceinline__ double inv_diag(double d) { return 1.0 / d; }
 // ------------------------------------------------------------ epilogues
 // Each epilogue sees, for the V nodes i0 .. i0+V-1 at position `pos` (index
 // of node i0 in the batch array), A u, D and the centre values of u; `ok[v]`
-// is false for the boundary node i = 0.  Stores write 0 there.
+// is false for the boundary node i = 0.  Stores write 0 there.  The vectors
+// an epilogue reads at its own nodes are loaded by pre(pos) into its members:
+// the engines call it one plane step ahead (LDS engine), or before the loads
+// of the stencil window (register engine), so those loads are in flight while
+// the stencil is computed instead of being waited for right after it.
 
 template <class T, int V>
 struct EpiApply {
   static constexpr bool kReduce = false;
   static constexpr bool kBegin = false;
   T* y;
+  __device__ void pre(size_t) {}
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double&) const {
     T o[V];
 #pragma unroll
@@ -100,9 +105,10 @@ struct EpiResidual {
   static constexpr bool kBegin = false;
   const T* b;
   T* r;
+  T bv[V];
+  __device__ void pre(size_t pos) { vload<T, V>(b + pos, bv); }
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double&) const {
-    T bv[V], o[V];
-    vload<T, V>(b + pos, bv);
+    T o[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) o[v] = ok[v] ? bv[v] - au[v] : T(0);
     vstore<T, V>(r + pos, o);
@@ -123,10 +129,13 @@ struct EpiCheb {
   T* out;
   T c1, c2;
   T* save = nullptr;
-  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
-    T bv[V], xov[V], o[V];
+  T bv[V], xov[V];
+  __device__ void pre(size_t pos) {
     vload<T, V>(b + pos, bv);
     if (USE_XO) vload<T, V>(xo + pos, xov);
+  }
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
+    T o[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const T prev = USE_XO ? uc[v] - xov[v] : uc[v];
@@ -149,6 +158,7 @@ struct EpiPcgApply {
   static constexpr bool kReduce = true;
   static constexpr bool kBegin = false;
   T* q;
+  __device__ void pre(size_t) {}
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
     T o[V];
 #pragma unroll
@@ -167,6 +177,7 @@ struct EpiTrueResidual {
   static constexpr bool kBegin = false;
   T bconst;
   T* r;
+  __device__ void pre(size_t) {}
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
     T o[V];
 #pragma unroll
@@ -189,6 +200,7 @@ struct EpiRefine {
   T bconst;
   T* uout;
   float* rin;
+  __device__ void pre(size_t) {}
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
     T us[V];
     float f[V];
@@ -212,9 +224,10 @@ struct EpiChebZero {
   const T* b;
   T* out;
   T c2;
+  T bv[V];
+  __device__ void pre(size_t pos) { vload<T, V>(b + pos, bv); }
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double&) const {
-    T bv[V], o[V];
-    vload<T, V>(b + pos, bv);
+    T o[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) o[v] = ok[v] ? c2 * bv[v] * inv_diag(dg[v]) : T(0);
     vstore<T, V>(out + pos, o);
@@ -293,13 +306,16 @@ struct EpiPcgUpdateZero {
   const double* alpha;
   T c2;
   T a = T(0);
+  T xv[V], pv[V], rv[V], qv[V];
   __device__ void begin(uint32_t b) { a = (T)alpha[b]; }
-  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
-    T xv[V], pv[V], rv[V], qv[V], zo[V];
+  __device__ void pre(size_t pos) {
     vload<T, V>(x + pos, xv);
     vload<T, V>(p + pos, pv);
     vload<T, V>(r + pos, rv);
     vload<T, V>(q + pos, qv);
+  }
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) {
+    T zo[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       xv[v] = xv[v] + a * pv[v];
@@ -326,11 +342,14 @@ struct EpiPcgRUpdateZero {
   const double* alpha;
   T c2;
   T a = T(0);
+  T rv[V], qv[V];
   __device__ void begin(uint32_t b) { a = (T)alpha[b]; }
-  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
-    T rv[V], qv[V], zo[V];
+  __device__ void pre(size_t pos) {
     vload<T, V>(r + pos, rv);
     vload<T, V>(q + pos, qv);
+  }
+  __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) {
+    T zo[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       rv[v] = rv[v] - a * qv[v];
@@ -362,6 +381,13 @@ struct EpiDirApply {
   const T* pold = nullptr;
   T* pnew = nullptr;
   bool prev = false;
+  T xv[V], pv[V];
+  __device__ void pre(size_t pos) {
+    if (prev) {
+      vload<T, V>(x + pos, xv);
+      vload<T, V>(pold + pos, pv);
+    }
+  }
   __device__ void begin(uint32_t b) {
     const int ps = pstate[b];
     prev = (ps & 2) == 0;
@@ -380,12 +406,10 @@ struct EpiDirApply {
     vstore<T, V>(pnew + pos, pn);
     vstore<T, V>(q + pos, o);
     if (prev) {
-      T xv[V], pv[V];
-      vload<T, V>(x + pos, xv);
-      vload<T, V>(pold + pos, pv);
+      T xn[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) xv[v] = xv[v] + a * pv[v];
-      vstore<T, V>(x + pos, xv);
+      for (int v = 0; v < V; ++v) xn[v] = xv[v] + a * pv[v];
+      vstore<T, V>(x + pos, xn);
     }
   }
 };
@@ -550,6 +574,7 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
     }
     const T third = T(1) / T(3), twelfth = T(1) / T(12);
     for (int k = k0; k < k1; ++k) {
+      epi.pre((size_t)b * stride + i0 + (size_t)n * j + (size_t)n2 * k);
       if (PF) {
 #pragma unroll
         for (int r = 0; r < 3; ++r)
@@ -683,10 +708,11 @@ inline size_t zlds_bytes(const ZGeom& g) {
           (size_t)ZOp<OP>::KP * (g.rows + 1 + 2 * ZOp<OP>::KOFF) * zlds_krs<T>(g.n)) * sizeof(T);
 }
 // the staging covers every row with two vectors per thread
-// and the rings fit the 64 KiB of LDS a workgroup may take without opting in
+// and the rings fit the 64 KiB of LDS a workgroup may take without opting in;
+// a row is at most one wave (its halos move by DPP)
 template <class T, int OP = OP_PLAIN>
 inline bool zlds_ok(const ZGeom& g) {
-  return (g.rows + 2) * g.G <= 2 * g.threads && (g.rows + 1 + 2 * ZOp<OP>::KOFF) * g.G <= 2 * g.threads &&
+  return g.G <= 64 && (g.rows + 2) * g.G <= 2 * g.threads && (g.rows + 1 + 2 * ZOp<OP>::KOFF) * g.G <= 2 * g.threads &&
          zlds_bytes<T, OP>(g) <= 65536;
 }
 
@@ -762,7 +788,8 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   const int gx = tid % G, jr = tid / G;
   const int j = j0 + jr, i0 = gx * V;
   const bool valid = jr < R && j <= n - 1 && k0 < k1;
-  const bool shuf = G <= 64;
+  // a row fits in one wave (zlds_ok): halos by DPP, no branch in the gather
+  constexpr bool shuf = true;
   const T* ub = (NEED_U && u) ? u + (size_t)b * stride : nullptr;
   const float* db = ADDD ? op.d + (size_t)b * stride : nullptr;
   const T* kb = kap + (size_t)b * n2 * n;
@@ -792,6 +819,12 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   vt pu[2], pk[2];
   fvt pd[ADDD ? 2 : 1];
   vt pp[DIR ? 2 : 1];
+  // staged u vector m of this thread: the first nthr by thread id, the rest
+  // (a tile taller than the workgroup) by the last threads, so that extra
+  // work (the OP_Z1 / PRO operand) does not pile onto wave 0, which stages the
+  // extra kappa vectors; ubase is a multiple of G, so a row stays in one wave
+  const int ubase = 2 * nthr - UR * G;
+  auto uv = [&](int m) { return m == 0 ? tid : (tid >= ubase ? nthr + tid - ubase : 1 << 30); };
   // PRO: per staged vector, the coarse values I0 .. I0+V/2 of its parent rows
   // Jlo = jj/2, Jhi = (jj+1)/2 on coarse planes cK and cK+1 (the parents of
   // fine planes 2cK and 2cK+1), refreshed every second fine plane
@@ -801,7 +834,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   auto load_cplane = [&](int slot, int K) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const int v = tid + m * nthr;
+      const int v = uv(m);
       const int r = v / G, c = v - (v / G) * G;
       const int jj = j0 - 1 + r;
       const bool use = v < UR * G && jj <= n && K <= nc;
@@ -837,7 +870,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
     }
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const int v = tid + m * nthr;
+      const int v = uv(m);
       const int r = v / G, c = v - (v / G) * G;
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) {
@@ -857,7 +890,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   auto prep_u = [&](int kk) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const int v = tid + m * nthr;
+      const int v = uv(m);
       const int r = v / G, c = v - (v / G) * G;
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) {
@@ -894,7 +927,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   auto put_u = [&](int slot) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const int v = tid + m * nthr;
+      const int v = uv(m);
       const int r = v / G, c = v - (v / G) * G;
       if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + V + c * V) = pu[m];
     }
@@ -949,6 +982,10 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
       fetch_k(k0 - 1); store_k(k0 - 1);
       fetch_k(k0); store_k(k0);
     }
+    // the epilogue's own operands of plane k0 first: waiting for them later
+    // then leaves the staging loads behind them in flight
+    const size_t pos0 = (size_t)b * stride + i0 + (size_t)n * j + (size_t)n2 * k0;
+    if (valid) epi.pre(pos0);
     if (NEED_U && k0 + 2 <= k1) fetch_u(k0 + 2);
     if (k0 + LEAD <= kmax) fetch_k(k0 + LEAD);
     __syncthreads();
@@ -1019,7 +1056,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
           au[v] = h * (ksum[v] * uc[v] * third - far[v] * twelfth);
           dg[v] = h * ksum[v] * third;
         }
-        epi((size_t)b * stride + i0 + (size_t)n * j + (size_t)n2 * k, au, dg, uc, ok, acc);
+        epi(pos0 + (size_t)n2 * (k - k0), au, dg, uc, ok, acc);
       }
       if (k + 1 < k1) {
         // u plane k+2 (OP_Z1: from kappa planes k+1, k+2, stored in earlier
@@ -1029,6 +1066,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         __syncthreads();
         if (NEED_U && k + 2 <= k1) put_u(sm);   // plane k+2 takes the slot of plane k-1
         if (k + LEAD <= kmax) store_k(k + LEAD);
+        if (valid) epi.pre(pos0 + (size_t)n2 * (k + 1 - k0));
         if (NEED_U && k + 3 <= k1) fetch_u(k + 3);
         if (k + LEAD + 1 <= kmax) fetch_k(k + LEAD + 1);
         __syncthreads();
@@ -1074,7 +1112,7 @@ template <class T, bool Z1 = false>
 inline bool resr_ok(const ZGeom& g) {
   return g.n >= 4 && g.rows % 2 == 0 && (g.zc == 1 || g.zlen % 2 == 0) &&
          g.threads <= 256 && (g.rows + 3) * g.G <= 2 * g.threads && (g.rows + 2 + (Z1 ? 2 : 0)) * g.G <= 2 * g.threads &&
-         resr_bytes<T, Z1>(g) <= 65536;
+         (g.rows + 1) * g.G <= 2 * g.threads - (g.threads >= 192 ? g.threads / 2 : 0) && resr_bytes<T, Z1>(g) <= 65536;
 }
 
 template <class T, int V, bool Z1>
@@ -1123,10 +1161,13 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
   for (int q = tid; q < KP * KR; q += nthr) Kl[q * KRS + V - 1] = T(0);
 
   vt pu[2], pk[2];
+  // staged u vector m: extras on the last threads (see k_zlds)
+  const int ubase = 2 * nthr - UR * G;
+  auto uv = [&](int m) { return m == 0 ? tid : (tid >= ubase ? nthr + tid - ubase : 1 << 30); };
   auto fetch_u = [&](int kk) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const int v = tid + m * nthr;
+      const int v = uv(m);
       const int r = v / G, c = v - (v / G) * G;
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) pu[m] = *reinterpret_cast<const vt*>(ub + (size_t)n2 * kk + (size_t)n * jj + c * V);
@@ -1138,7 +1179,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
     if (!Z1) return;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const int v = tid + m * nthr;
+      const int v = uv(m);
       const int r = v / G, c = v - (v / G) * G;
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) {
@@ -1154,7 +1195,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
   auto put_u = [&](int slot) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const int v = tid + m * nthr;
+      const int v = uv(m);
       const int r = v / G, c = v - (v / G) * G;
       if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + V + c * V) = pu[m];
     }
@@ -1184,6 +1225,8 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
         *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + V + c * V) = pk[m];
     }
   };
+
+  const int tbase = nthr >= 192 ? nthr / 2 : 0;
 
   // coarse node owned by this thread: coarse row Jf + (tid / nc), column tid % nc
   const int Jf = (j0 + 1) >> 1;
@@ -1217,7 +1260,13 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
     for (int kk = k0; kk <= kt1; ++kk) {
       const int km = (kk - 1) & (KP - 1), kc = kk & (KP - 1);
       // residual of rows j0 .. j0+R on plane kk into LDS
-      for (int task = tid; task < TR * G; task += nthr) {
+      // tasks: one per thread, the extra rows of a full tile (TR * G - nthr
+      // tasks, at most nthr) on the threads from tbase on, i.e. not on the
+      // waves that stage the extra u and kappa vectors
+#pragma unroll 1
+      for (int q = 0; q < 2; ++q) {
+        const int task = q == 0 ? tid : (tid >= tbase ? nthr + tid - tbase : TR * G);
+        if (task >= TR * G) continue;
         const int jr = task / G, gx = task - (task / G) * G;
         const int j = j0 + jr, i0 = gx * V;
         if (j > n - 1) continue;
