@@ -325,12 +325,13 @@ bool dir_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int B) {
 }
 
 template <class T>
-int pcg_dir_begin(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, const T* r, const int* mask) {
+int pcg_dir_begin(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, const T* r, const int* mask,
+                  bool fresh) {
   const int n = L[0].n;
   const double sz = sizeof(T), d = dofs(n) * B, e = elems(n) * B;
   SolveState m = S;
   m.active = const_cast<int*>(mask);
-  LAUNCH(MLMC_K_MISC, 0, launch_dir_begin(B, m, ctx->st));
+  LAUNCH(MLMC_K_MISC, 0, launch_dir_begin(B, m, fresh, ctx->st));
   if (zero_step_fusable<T>(ctx, L, B))
     LAUNCHM(kid<T>(MLMC_K_CHEB_ZERO), (2 * d + e) * sz, mask, B,
             launch_cheb<T>(n, B, L[0].kap, r, nullptr, nullptr, L[0].x, 0.0, ctx->cheb.c2[0], true, false, mask,
@@ -373,14 +374,14 @@ int pcg_iteration_dir(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState
 // `graph` caches the captured iteration for this work space (may be null).
 template <class T>
 int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q, double tol,
-        int max_iter, int* done_iters, hipGraphExec_t* graph, T* p2) {
+        int max_iter, int* done_iters, hipGraphExec_t* graph, T* p2, bool fresh, bool defer) {
   const int n = L[0].n;
   const double sz = sizeof(T), d = dofs(n) * B;
   hipStream_t st = ctx->st;
   const double tol2 = tol * tol;
   const bool use_graph = graph && ctx->use_graphs && !ctx->profiling;
   if (p2 && dir_fusable<T>(ctx, L, B)) {
-    if (int rc = pcg_dir_begin<T>(ctx, L, B, S, r, S.active)) return rc;
+    if (int rc = pcg_dir_begin<T>(ctx, L, B, S, r, S.active, fresh)) return rc;
     int it = 0;
     if (max_iter > 0) {
       if (int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2, RED_RR, true, true)) return rc;
@@ -413,8 +414,9 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
       it += k;
       HIPCHK(hipStreamSynchronize(st));
     }
-    // the update the last step still owes its iterate
-    LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE), 3 * d * sz, S.began, B, launch_pcg_finish<T>(n, B, x, p, p2, S.began, S, st));
+    // the update the last step still owes its iterate (unless its consumer applies it)
+    if (!defer)
+      LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE), 3 * d * sz, S.began, B, launch_pcg_finish<T>(n, B, x, p, p2, S.began, S, st));
     *done_iters = it;
     return MLMC_OK;
   }
@@ -519,6 +521,10 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       if ((expect - 1) % 2 == 1) std::swap(bufs[0], bufs[1]);
       const double* ucur = nullptr;   // zero iterate
       int next = 0;
+      // fused direction: the inner correction starts fresh (no fill), and the
+      // update its last step owes is applied by the refinement step
+      const bool dir = dir_fusable<float>(ctx, L, B);
+      const bool owed = dir && refine_owed_usable(n, B, zv<double>(ctx));
       for (int outer = 0; outer < kMaxOuter && total_it < ctx->cfg.max_iter; ++outer) {
         HIPCHK(hipMemcpyAsync(I.active, O.active, B * sizeof(int), hipMemcpyDeviceToDevice, st));
         // inner ||b||^2 = the sums just reduced for the outer residual
@@ -526,15 +532,20 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
         Ib.partial = O.partial;
         Ib.pstride = O.pstride;
         LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, Ib, nullptr, st));
-        LAUNCHM(MLMC_K_MISC, d * 4, O.active, B, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
+        if (!dir)
+          LAUNCHM(MLMC_K_MISC, d * 4, O.active, B, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
         int it = 0;
         if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it,
-                               &it, &w.iter_exec[1], w.p32b))
+                               &it, &w.iter_exec[1], w.p32b, dir, owed))
           return rc;
         total_it += it;
         double* uout = bufs[next];
-        LAUNCHM(MLMC_K_TRUE_RESIDUAL, ((ucur ? 8 : 0) + 4 + 8 + 4) * d + 8 * e, O.active, B,
-                launch_refine(n, B, kap, h3, ucur, w.d, uout, w.rin, O, &np, st, zv<double>(ctx)));
+        if (owed)   // reads u, d, p and kappa; writes u + d, rin
+          LAUNCHM(MLMC_K_TRUE_RESIDUAL, ((ucur ? 8 : 0) + 4 + 4 + 8 + 4) * d + 8 * e, O.active, B,
+                  launch_refine_owed(n, B, kap, h3, ucur, w.d, w.p32, w.p32b, I, uout, w.rin, O, &np, st));
+        else
+          LAUNCHM(MLMC_K_TRUE_RESIDUAL, ((ucur ? 8 : 0) + 4 + 8 + 4) * d + 8 * e, O.active, B,
+                  launch_refine(n, B, kap, h3, ucur, w.d, uout, w.rin, O, &np, st, zv<double>(ctx)));
         LAUNCH(MLMC_K_MISC, 0, launch_set_phase_mask(B, O.active, w.alt, uout == w.r64 ? 1 : 0, nullptr, st));
         LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
         ucur = uout;
@@ -554,13 +565,15 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       for (int outer = 0; outer < kMaxOuter && total_it < ctx->cfg.max_iter; ++outer) {
         LAUNCHM(MLMC_K_MISC, d * 12, O.active, B, launch_demote(n, B, w.r64, w.rin, O, st));
         HIPCHK(hipMemcpyAsync(I.active, O.active, B * sizeof(int), hipMemcpyDeviceToDevice, st));
-        LAUNCHM(MLMC_K_MISC, d * 4, O.active, B, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
+        const bool dir = dir_fusable<float>(ctx, L, B);   // a fused-direction correction starts fresh
+        if (!dir)
+          LAUNCHM(MLMC_K_MISC, d * 4, O.active, B, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
         LAUNCHM(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, I.active, B,
                 (launch_dot<float>(n, B, w.rin, w.rin, I, &np, st)));
         LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, I, nullptr, st));
         int it = 0;
         if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it, &it,
-                               &w.iter_exec[1], w.p32b))
+                               &w.iter_exec[1], w.p32b, dir, false))
           return rc;
         total_it += it;
         LAUNCHM(MLMC_K_MISC, d * 20, O.active, B, launch_add_correction(n, B, u, w.d, O, st));
@@ -706,14 +719,15 @@ template int pcg_iteration<float>(mlmc_ctx*, std::vector<Level<float>>&, int, So
 template int pcg_iteration<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*,
                                    double*, double*, double, int, bool);
 template int pcg<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*, float*,
-                        double, int, int*, hipGraphExec_t*, float*);
+                        double, int, int*, hipGraphExec_t*, float*, bool, bool);
 template int pcg<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*, double*,
-                         double*, double, int, int*, hipGraphExec_t*, double*);
+                         double*, double, int, int*, hipGraphExec_t*, double*, bool, bool);
 template bool dir_fusable<float>(const mlmc_ctx*, const std::vector<Level<float>>&, int);
 template bool dir_fusable<double>(const mlmc_ctx*, const std::vector<Level<double>>&, int);
-template int pcg_dir_begin<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, const float*, const int*);
+template int pcg_dir_begin<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, const float*, const int*,
+                                  bool);
 template int pcg_dir_begin<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, const double*,
-                                   const int*);
+                                   const int*, bool);
 template int pcg_iteration_dir<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*,
                                       float*, float*, double, int, bool, bool);
 template int pcg_iteration_dir<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*,

@@ -361,15 +361,21 @@ bool dir_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int B);
 template <class T>
 int pcg_iteration_dir(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p0, T* p1,
                       T* q, double tol2, int rr_op = RED_RR, bool count = true, bool first = false);
-// Start of a fused-direction solve on the active samples (see pcg_iteration_dir).
+// Start of a fused-direction solve on the samples with mask[b] (see
+// pcg_iteration_dir); fresh: x holds no value yet (it is written, not updated,
+// by its first update, so it needs no zero fill).
 template <class T>
-int pcg_dir_begin(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, const T* r, const int* mask);
+int pcg_dir_begin(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, const T* r, const int* mask,
+                  bool fresh);
 // PCG of x (residual r) to ||r|| <= tol ||b||.  With p2 (a second direction
-// buffer) and dir_fusable, the fused-direction iteration runs and x gets its
-// last update before return.
+// buffer) and dir_fusable, the fused-direction iteration runs (fresh as in
+// pcg_dir_begin) and x gets its last update before return unless `defer`, in
+// which case the caller applies it (S.pstate, S.alpha and the direction
+// buffers describe it).
 template <class T>
 int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q, double tol,
-        int max_iter, int* done_iters, hipGraphExec_t* graph, T* p2 = nullptr);
+        int max_iter, int* done_iters, hipGraphExec_t* graph, T* p2 = nullptr, bool fresh = false,
+        bool defer = false);
 // kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
 int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
                bool kap32_ready = false);

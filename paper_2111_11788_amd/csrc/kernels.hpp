@@ -33,7 +33,8 @@ struct SolveState {
   int* nactive;     // single counter (device) of active samples
   uint32_t pstride; // capacity of partial sums per sample
   int* phase;       // serving: per-slot phase (PHASE_*), may be null
-  int* pstate;      // fused-direction PCG: bit 0 = buffer of the current direction, bit 1 = no step taken yet
+  int* pstate;      // fused-direction PCG: bit 0 = buffer of the current direction, bit 1 = no step taken yet,
+                    // bit 2 = the iterate holds no value yet (written, not updated, by its first update)
   int* began;       // fused-direction PCG: samples active when the solve started
 };
 
@@ -139,8 +140,9 @@ hipError_t launch_pcg_rupdate(int n, int B, T* r, const T* q, SolveState s, uint
 template <class T>
 hipError_t launch_pcg_finish(int n, int B, T* x, const T* p0, const T* p1, const int* mask, SolveState s,
                              hipStream_t st);
-// began = active; pstate = first direction in buffer 0 on active samples
-hipError_t launch_dir_begin(int B, SolveState s, hipStream_t st);
+// began = active; pstate = first direction in buffer 0 on active samples (fresh:
+// the iterate holds no value yet; it is written, not updated, by its first update)
+hipError_t launch_dir_begin(int B, SolveState s, bool fresh, hipStream_t st);
 // p = z + beta p_old formed while staging, written to the other buffer, q = A p,
 // partial sums of p . q, and the previous x += alpha p_old (LDS engine, n >= 4,
 // when dir_usable)
@@ -161,6 +163,14 @@ hipError_t launch_pcg_direction(int n, int B, const T* z, T* p, SolveState s, hi
 // of (bconst - A uout) . itself in fp64.  uout must not alias u or d.
 hipError_t launch_refine(int n, int B, const double* kap, double bconst, const double* u, const float* d,
                          double* uout, float* rin, SolveState s, uint32_t* nparts, hipStream_t st, int var = 0);
+// launch_refine with the update the fused-direction inner solve still owes d
+// applied on the fly: the correction is d + alpha p (alpha p for a fresh d),
+// p the inner state's current direction (buffers p0/p1, inner.pstate,
+// inner.alpha).  Usable when refine_owed_usable(n, B, var).
+bool refine_owed_usable(int n, int B, int var);
+hipError_t launch_refine_owed(int n, int B, const double* kap, double bconst, const double* u, const float* d,
+                              const float* p0, const float* p1, SolveState inner, double* uout, float* rin,
+                              SolveState s, uint32_t* nparts, hipStream_t st);
 hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x,
                                 double* r, SolveState s, uint32_t* nparts, hipStream_t st,
                                 int var = 0);

@@ -108,7 +108,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_rupdate(SGeom g, size_t stride, 
 
 // the update a fused-direction solve still owes its iterate: x += alpha p
 // with p the sample's current direction (buffer pstate & 1), on samples with
-// mask[b] that took at least one step (pstate bit 1 clear)
+// mask[b] that took at least one step (pstate bit 1 clear); x = alpha p when
+// the iterate was never written (pstate bit 2: a fresh correction)
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_pcg_finish(SGeom g, size_t stride, T* __restrict__ x,
                                                        const T* __restrict__ p0, const T* __restrict__ p1,
@@ -123,7 +124,11 @@ __global__ void __launch_bounds__(kBlock) k_pcg_finish(SGeom g, size_t stride, T
   vt* xv = reinterpret_cast<vt*>(x + base);
   const vt* pv = reinterpret_cast<const vt*>(((ps & 1) ? p1 : p0) + base);
   const T a = (T)st.alpha[sp.b];
-  for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) xv[t] = xv[t] + a * pv[t];
+  if (ps & 4) {
+    for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) xv[t] = a * pv[t];
+  } else {
+    for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) xv[t] = xv[t] + a * pv[t];
+  }
 }
 
 template <class T>
@@ -288,11 +293,15 @@ __global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t
       if (!(st.pstate[b] & 2)) st.beta[b] = v / st.rz[b];
       st.rz[b] = v;
       break;
-    case RED_ALPHA_DIR:
+    case RED_ALPHA_DIR: {
+      // next direction buffer; first cleared; the fresh bit survives the first
+      // step (which does not touch x) and is cleared by the one that writes x
+      const int ps = st.pstate[b];
       st.alpha[b] = st.rz[b] / v;
       st.iters[b] += 1;
-      st.pstate[b] = (st.pstate[b] & 1) ^ 1;
+      st.pstate[b] = ((ps & 1) ^ 1) | ((ps & 2) ? (ps & 4) : 0);
       break;
+    }
     case RED_RR_INNER:
       st.rr[b] = v;
       if (v <= tol2 * st.bb[b]) st.phase[b] = PHASE_TRANSITION;
@@ -347,14 +356,16 @@ __global__ void k_count_mask(const int* __restrict__ mask, int B, int* __restric
   if (threadIdx.x == 0) *out = v;
 }
 
-// a fused-direction solve starts: direction buffer 0, first direction, on
-// active samples; the active set is remembered for the final update
-__global__ void k_dir_begin(int B, SolveState st) {
+// a fused-direction solve starts: direction buffer 0, first direction (and
+// with `fresh` an iterate that holds no value yet and is written, not updated,
+// by the first step that touches it), on active samples; the active set is
+// remembered for the final update
+__global__ void k_dir_begin(int B, SolveState st, int fresh) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const int a = st.active[b];
   st.began[b] = a;
-  if (a) st.pstate[b] = 2;
+  if (a) st.pstate[b] = fresh ? 6 : 2;
 }
 
 __global__ void k_set_active(int B, SolveState st, int value) {
@@ -392,8 +403,8 @@ hipError_t launch_pcg_finish(int n, int B, T* x, const T* p0, const T* p1, const
   return hipGetLastError();
 }
 
-hipError_t launch_dir_begin(int B, SolveState s, hipStream_t st) {
-  k_dir_begin<<<dim3((B + kBlock - 1) / kBlock), kBlock, 0, st>>>(B, s);
+hipError_t launch_dir_begin(int B, SolveState s, bool fresh, hipStream_t st) {
+  k_dir_begin<<<dim3((B + kBlock - 1) / kBlock), kBlock, 0, st>>>(B, s, fresh ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -181,12 +181,13 @@ int step(Pool& p) {
     SolveState ir = view(p.w.inner.s, p.m_restart, p.phase);
     SolveState orr = view(p.w.outer.s, p.m_restart, p.phase);
     SRV_LAUNCH(launch_demote(n, S, p.w.r64, p.w.rin, orr, st));
-    SRV_LAUNCH(launch_fill_interior<float>(n, S, p.w.d, 0.0, p.m_restart, st));
+    if (!dir)   // a fused-direction correction starts fresh
+      SRV_LAUNCH(launch_fill_interior<float>(n, S, p.w.d, 0.0, p.m_restart, st));
     SRV_LAUNCH(launch_dot<float>(n, S, p.w.rin, p.w.rin, ir, &np, st));
     SRV_LAUNCH(launch_reduce(S, RED_BB, 0.0, np, ir, nullptr, st));
     if (dir) {
       // the first iteration preconditions rin itself
-      if (int rc = pcg_dir_begin<float>(ctx, L, S, ir, p.w.rin, p.m_restart)) return rc;
+      if (int rc = pcg_dir_begin<float>(ctx, L, S, ir, p.w.rin, p.m_restart, true)) return rc;
     } else {
       float* z = nullptr;
       np = 0;

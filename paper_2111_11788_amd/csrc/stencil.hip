@@ -366,7 +366,8 @@ struct EpiPcgRUpdateZero {
 // buffer (neighbouring workgroups still read p_old), q = A p, the partial
 // sums of p . q, and applies the previous iteration's x += alpha p_old (alpha
 // is still that iteration's value when this kernel runs).  On a sample's
-// first direction there is no previous update.
+// first direction there is no previous update, and an iterate marked fresh
+// (pstate bit 2) is written rather than updated.
 template <class T, int V>
 struct EpiDirApply {
   static constexpr bool kReduce = true;
@@ -380,17 +381,18 @@ struct EpiDirApply {
   T a = T(0);
   const T* pold = nullptr;
   T* pnew = nullptr;
-  bool prev = false;
+  bool prev = false, fresh = false;
   T xv[V], pv[V];
   __device__ void pre(size_t pos) {
     if (prev) {
-      vload<T, V>(x + pos, xv);
+      if (!fresh) vload<T, V>(x + pos, xv);
       vload<T, V>(pold + pos, pv);
     }
   }
   __device__ void begin(uint32_t b) {
     const int ps = pstate[b];
     prev = (ps & 2) == 0;
+    fresh = (ps & 4) != 0;
     a = (T)alpha[b];
     pold = (ps & 1) ? p1 : p0;
     pnew = (ps & 1) ? p0 : p1;
@@ -406,9 +408,10 @@ struct EpiDirApply {
     vstore<T, V>(pnew + pos, pn);
     vstore<T, V>(q + pos, o);
     if (prev) {
+      // a fresh iterate is written, not updated (it holds no value yet)
       T xn[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) xn[v] = xv[v] + a * pv[v];
+      for (int v = 0; v < V; ++v) xn[v] = fresh ? a * pv[v] : xv[v] + a * pv[v];
       vstore<T, V>(x + pos, xn);
     }
   }
@@ -667,7 +670,8 @@ __global__ void __launch_bounds__(256) k_zmarch(ZGeom g, size_t stride, T h, con
 //
 // Operand modes (the value staged for a u position):
 //   OP_PLAIN  u
-//   OP_ADDD   u + d (fp32 d in the same layout; u may be null: zero)
+//   OP_ADDD   u + d (fp32 d in the same layout; u may be null: zero), with d
+//             optionally completed by the update its solve still owes
 //   OP_Z1     c2 D^-1 u: the first smoothing step from a zero iterate of a
 //             V-cycle whose right-hand side is u, formed while staging so
 //             that step is never stored.  D of a staged node needs the kappa
@@ -683,6 +687,14 @@ enum : int { OP_PLAIN = 0, OP_ADDD = 1, OP_Z1 = 2, OP_DIR = 3 };
 template <class T>
 struct OpArgs {
   const float* d = nullptr;       // OP_ADDD
+  // OP_ADDD: the update a fused-direction solve still owes d (may be null):
+  // d + alpha p with p the solve's current direction (fp32 buffers q0/q1 by
+  // dstate bit 0); alpha p alone when d was never written (dstate bit 2); none
+  // when the solve took no step (bit 1)
+  const float* q0 = nullptr;
+  const float* q1 = nullptr;
+  const int* dstate = nullptr;
+  const double* dalpha = nullptr;
   T c2 = T(0);                    // OP_Z1
   const T* p0 = nullptr;          // OP_DIR: the two direction buffers
   const T* p1 = nullptr;
@@ -730,24 +742,28 @@ __device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int KRS, int 
     for (int v = 0; v < V; ++v) u[v] = T(0);
     return;
   }
-  T K[2][2][V + 1];
+  // the 8-element sum accumulated one kappa row at a time, in the order
+  // (sz, sy, sx) of the stencil kernels, so few values are live
   const int sl[2] = {s0, s1};
+  T ks[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) ks[v] = T(0);
 #pragma unroll
   for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-    for (int dy = 0; dy < 2; ++dy)
-      lds_krow<T, V>(Kl + (sl[dz] * KR + jj - 1 + dy - krow0) * KRS + V + c * V, K[dz][dy], c, G, shuf);
+    for (int dy = 0; dy < 2; ++dy) {
+      T K[V + 1];
+      lds_krow<T, V>(Kl + (sl[dz] * KR + jj - 1 + dy - krow0) * KRS + V + c * V, K, c, G, shuf);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        ks[v] += K[v];
+        ks[v] += K[v + 1];
+      }
+    }
   const T third = T(1) / T(3);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    T ks = T(0);
-#pragma unroll
-    for (int sz = 0; sz < 2; ++sz)
-#pragma unroll
-      for (int sy = 0; sy < 2; ++sy)
-#pragma unroll
-        for (int sx = 0; sx < 2; ++sx) ks += K[sz][sy][v + sx];
-    const T dg = h * ks * third;
+    const T dg = h * ks[v] * third;
     u[v] = (c * V + v) != 0 ? c2 * u[v] * inv_diag(dg) : T(0);
   }
 }
@@ -805,6 +821,19 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
     dbeta = (T)op.beta[b];
     pob = ((ps & 1) ? op.p1 : op.p0) + (size_t)b * stride;
   }
+  // OP_ADDD with an owed update: whether d is read, whether alpha p is added
+  bool d_read = true, d_owe = false;
+  float d_a = 0.0f;
+  const float* dqb = nullptr;
+  if constexpr (ADDD) {
+    if (op.dstate) {
+      const int ps = op.dstate[b];
+      d_owe = (ps & 2) == 0;
+      d_read = (ps & 4) == 0;
+      d_a = (float)op.dalpha[b];
+      dqb = ((ps & 1) ? op.q1 : op.q0) + (size_t)b * stride;
+    }
+  }
   if constexpr (Epi::kBegin) epi.begin(b);
 
   // zero cells (i = -1, i = n of u; ex = -1 of kappa) of every ring row
@@ -817,7 +846,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   // staging: up to two 16-byte vectors per thread per plane for u and kappa;
   // a thread stages the same (row, column) positions on every plane
   vt pu[2], pk[2];
-  fvt pd[ADDD ? 2 : 1];
+  fvt pd[ADDD ? 2 : 1], pq[ADDD ? 2 : 1];
   vt pp[DIR ? 2 : 1];
   // staged u vector m of this thread: the first nthr by thread id, the rest
   // (a tile taller than the workgroup) by the last threads, so that extra
@@ -877,7 +906,10 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         const size_t off = (size_t)n2 * kk + (size_t)n * jj + c * V;
         if (!ADDD || ub) pu[m] = *reinterpret_cast<const vt*>(ub + off);
         else pu[m] = vt{};
-        if (ADDD) pd[ADDD ? m : 0] = *reinterpret_cast<const fvt*>(db + off);
+        if (ADDD) {
+          pd[ADDD ? m : 0] = d_read ? *reinterpret_cast<const fvt*>(db + off) : fvt{};
+          if (d_owe) pq[ADDD ? m : 0] = *reinterpret_cast<const fvt*>(dqb + off);
+        }
         if (DIR && dir_prev) pp[DIR ? m : 0] = *reinterpret_cast<const vt*>(pob + off);
       }
     }
@@ -917,8 +949,11 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
             pu[m][t] += (t & 1) ? T(0.5) * (L[(t - 1) / 2] + L[(t + 1) / 2]) : L[t / 2];
         }
         if (ADDD) {
+          // the completed correction in fp32, as the separate update would store it
+          fvt dd = pd[ADDD ? m : 0];
+          if (d_owe) dd = d_read ? dd + d_a * pq[ADDD ? m : 0] : d_a * pq[ADDD ? m : 0];
 #pragma unroll
-          for (int t = 0; t < V; ++t) pu[m][t] += (T)pd[ADDD ? m : 0][t];
+          for (int t = 0; t < V; ++t) pu[m][t] += (T)dd[t];
         }
         if (DIR && dir_prev) pu[m] = pu[m] + dbeta * pp[DIR ? m : 0];
       }
@@ -1110,7 +1145,7 @@ inline ZGeom resr_geom(int n, int B) { return zgeom<T>(n, B); }
 // fits two vectors per thread
 template <class T, bool Z1 = false>
 inline bool resr_ok(const ZGeom& g) {
-  return g.n >= 4 && g.rows % 2 == 0 && (g.zc == 1 || g.zlen % 2 == 0) &&
+  return g.n >= 4 && g.G <= 64 && g.rows % 2 == 0 && (g.zc == 1 || g.zlen % 2 == 0) &&
          g.threads <= 256 && (g.rows + 3) * g.G <= 2 * g.threads && (g.rows + 2 + (Z1 ? 2 : 0)) * g.G <= 2 * g.threads &&
          (g.rows + 1) * g.G <= 2 * g.threads - (g.threads >= 192 ? g.threads / 2 : 0) && resr_bytes<T, Z1>(g) <= 65536;
 }
@@ -1145,10 +1180,10 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
   // last kappa plane staged: the residual planes need kt1; Z1 also forms the
   // operand on u plane kt1 + 1
   const int kmax = Z1 ? (kt1 + 1 < n - 1 ? kt1 + 1 : n - 1) : kt1;
-  // halos from LDS in the residual: measured faster than the DPP exchange for
-  // this kernel (its extra-row tasks leave most of a wave idle around the
-  // exchange); the Z1 staging rows are whole waves and use DPP
-  const bool shuf = false;
+  // halos by DPP (a row fits in one wave: resr_ok); with the extra rows of a
+  // tile spread over the waves this measured faster than LDS halo reads
+  // (8.7 vs 9.4 ms per 64^3 x 1024 step)
+  constexpr bool shuf = true;
   const T* ub = (Z1 ? bf : x) + (size_t)b * stride;
   const T* bb = bf + (size_t)b * stride;
   const T* kb = kap + (size_t)b * n2 * n;
@@ -1186,7 +1221,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
         T w[V];
 #pragma unroll
         for (int t = 0; t < V; ++t) w[t] = pu[m][t];
-        z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, G, G <= 64, h, c2);
+        z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, G, true, h, c2);
 #pragma unroll
         for (int t = 0; t < V; ++t) pu[m][t] = w[t];
       }
@@ -1769,6 +1804,24 @@ hipError_t launch_refine(int n, int B, const double* kap, double bconst, const d
                          double* uout, float* rin, SolveState s, uint32_t* nparts, hipStream_t st, int var) {
   return zlaunch_addd<double>(n, B, u, d, kap, s.active, s.partial, s.pstride,
                               EpiRefine<double, ZV<double>::V>{bconst, uout, rin}, nparts, var, st);
+}
+
+bool refine_owed_usable(int n, int B, int var) {
+  return use_lds<double>(n, B, var, ZVAR_LDS) && zlds_ok<double, OP_ADDD>(zgeom<double>(n, B));
+}
+
+hipError_t launch_refine_owed(int n, int B, const double* kap, double bconst, const double* u, const float* d,
+                              const float* p0, const float* p1, SolveState inner, double* uout, float* rin,
+                              SolveState s, uint32_t* nparts, hipStream_t st) {
+  if (!zlds_ok<double, OP_ADDD>(zgeom<double>(n, B))) return hipErrorInvalidValue;
+  OpArgs<double> op;
+  op.d = d;
+  op.q0 = p0;
+  op.q1 = p1;
+  op.dstate = inner.pstate;
+  op.dalpha = inner.alpha;
+  return zlaunch_lds<double, true, false, OP_ADDD>(n, B, u, nullptr, kap, s.active, s.partial, s.pstride,
+                                                   EpiRefine<double, ZV<double>::V>{bconst, uout, rin}, nparts, st, op);
 }
 
 hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x, double* r,

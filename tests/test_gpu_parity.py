@@ -163,17 +163,18 @@ def test_presmoothed_vcycle_matches_oracle_and_stored_step(dev, n, B, monkeypatc
         assert np.abs(z[b] - want).max() <= 1e-12 * np.abs(want).max()
 
 
-@pytest.mark.parametrize("zvar", [0, 2, 6])
+@pytest.mark.parametrize("zvar32,zvar64", [(0, 0), (2, 2), (6, 6), (6, 0)])
 @pytest.mark.parametrize("deg", [1, 2])
-def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg, zvar):
-    # fp32 V-cycles (the mixed path) with and without the fused correction and
-    # the PCG update fused with the first smoothing step
+def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg, zvar32, zvar64):
+    # fp32 V-cycles (the mixed path) with and without each fusion; (6, 0): the
+    # fused-direction inner solve with the register-engine fp64 refinement, so
+    # its owed update runs as a separate pass instead of inside the refinement
     n, B = 32, 3
     wl = _wl(n0=n, levels=1, qoi=1, precision=1, solver=0, n_modes=16, corr_len=0.3)
     qs = []
     for fuse in (63, 47, 34, 32, 31, 25, 15, 8, 4, 2, 1, 0):   # every fusion bit alone, all, none, mixes
         ctx = mm.Context(wl, cheb_degree=deg, arena_bytes=512 << 20)
-        ctx.set_tuning(fuse=fuse, vsmall_fp32=0, vsmall_fp64=0, zvar_fp32=zvar, zvar_fp64=zvar)
+        ctx.set_tuning(fuse=fuse, vsmall_fp32=0, vsmall_fp64=0, zvar_fp32=zvar32, zvar_fp64=zvar64)
         xi = ctx.draw_xi(0, 21, B)
         kap = ctx.field(n, xi)
         u, it = ctx.solve(n, kap)
