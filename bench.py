@@ -38,25 +38,21 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # per-kernel table and the commands are in the committed counter summary.
 TRAFFIC = {
     "profile": "profiles/batched-64cube-1024_hbm_traffic.txt",
-    "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 8, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 0, "fuse": 7},
-    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "9d396ea4811a5cbf", "kernels.hpp": "859cb816756d085c", "krylov.hip": "43366de07857d672", "stencil.hip": "338d4362785e3f7d"},
+    "tuning": {"zvar_fp32": 6, "zvar_fp64": 2, "vsmall_fp32": 8, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 2, "fuse": 63},
+    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "9d396ea4811a5cbf", "kernels.hpp": "9ad33281e9e850ae", "krylov.hip": "73e38165b8c483f0", "stencil.hip": "5d48ee6d62bec43f"},
     "bytes_per_launch": {
-        "PCG_UPDATE_ZERO (f32)": 6860238689,
-        "CHEB_PROLONG (f32)": 1186485217,
-        "PCG_DIRECTION (f32)": 2031669016,
-        "RESIDUAL (f32)": 1130625514,
-        "CHEB_ZERO (f32)": 366974966,
-        "PCG_APPLY (f32)": 2667414564,
-        "RESTRICT (f32)": 305600674,
-        "TRUE_RESIDUAL (f64)": 7580913435,
+        "PCG_UPDATE (f32)": 2593373209,
+        "CHEB_PROLONG (f32)": 1213012996,
+        "RESIDUAL_RESTRICT (f32)": 804029378,
+        "PCG_APPLY (f32)": 6000536618,
+        "TRUE_RESIDUAL (f64)": 8672847598,
     },
 }
 
 
 TRAFFIC_TUNING_KEYS = {
-    "PCG_UPDATE (f32)": ["max_batch", "fuse"], "PCG_DIRECTION (f32)": ["max_batch"],
-    "PCG_UPDATE_ZERO (f32)": ["max_batch", "zvar_fp32", "fuse"],
-    "PCG_APPLY (f32)": ["max_batch", "zvar_fp32"], "TRUE_RESIDUAL (f64)": ["max_batch", "zvar_fp64"],
+    "PCG_UPDATE (f32)": ["max_batch", "fuse"],
+    "PCG_APPLY (f32)": ["max_batch", "zvar_fp32", "fuse"], "TRUE_RESIDUAL (f64)": ["max_batch", "zvar_fp64", "fuse"],
 }
 
 
