@@ -226,7 +226,7 @@ typedef struct mlmc_tuning {
   int32_t cheb_degree;    /* Chebyshev smoothing degree per half V-cycle, 1..8 */
   int32_t max_batch;      /* samples per batched solve */
   int32_t graph_batch;    /* captured PCG iterations replayed per convergence check (0: no graphs) */
-  int32_t fuse;           /* MLMC_FUSE_* bits: kernel fusions in use (default: all) */
+  int32_t fuse;           /* MLMC_FUSE_* bits: kernel fusions in use (default: all but RUPDATE) */
   double seconds;         /* mlmc_autotune: measured seconds per sample of the chosen setting */
 } mlmc_tuning;
 
@@ -240,9 +240,12 @@ enum {
                               RESTRICT on: the zero-start pre-smoothing step c D^-1 b of each V-cycle
                               level is formed inside the residual and the correction steps, never
                               stored (supersedes UPDATE on those levels) */
-  MLMC_FUSE_DIRECTION = 32 /* LDS engine: the PCG direction p = z + beta p is formed inside the operator
+  MLMC_FUSE_DIRECTION = 32, /* LDS engine: the PCG direction p = z + beta p is formed inside the operator
                               apply q = A p, which also applies the previous step's x += alpha p (two
                               direction buffers); the last x update of a solve runs after it */
+  MLMC_FUSE_RUPDATE = 64   /* with DIRECTION and PRESMOOTH: the PCG update r -= alpha q is formed inside
+                              the next iteration's first V-cycle kernel (residual restriction), which
+                              writes r to the other of two residual buffers and tests convergence */
 };
 
 int mlmc_get_tuning(const mlmc_ctx* ctx, mlmc_tuning* out);

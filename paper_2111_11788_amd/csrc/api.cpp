@@ -276,7 +276,7 @@ int mlmc_autotune(mlmc_ctx* ctx, int32_t level, int32_t batch, mlmc_tuning* best
     if (int rc = trial(c)) return rc;
   }
   for (int f : {MLMC_FUSE_PROLONG, MLMC_FUSE_UPDATE, MLMC_FUSE_REFINE, MLMC_FUSE_RESTRICT, MLMC_FUSE_PRESMOOTH,
-                MLMC_FUSE_DIRECTION}) {
+                MLMC_FUSE_DIRECTION, MLMC_FUSE_RUPDATE}) {
     mlmc_tuning c = best; c.fuse ^= f;
     if (int rc = trial(c)) return rc;
   }

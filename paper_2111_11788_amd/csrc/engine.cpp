@@ -165,7 +165,8 @@ bool zero_step_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int 
 
 template <class T>
 int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T* x, T* xo, T* t,
-           const int* active, T** result, SolveState* dot, uint32_t* dot_np, bool zero_done) {
+           const int* active, T** result, SolveState* dot, uint32_t* dot_np, bool zero_done,
+           const RUpdate<T>* ru) {
   const int n = L[l].n;
   const double sz = sizeof(T);
   const double d = dofs(n) * B, e = elems(n) * B;
@@ -195,12 +196,22 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
     // read it instead of being stored
     Level<T>& nx = L[l + 1];
     const double dc = dofs(n / 2) * B;
-    LAUNCHM(kid<T>(MLMC_K_RESIDUAL_RESTRICT), (d + e + dc) * sz, active, B,
-            launch_residual_restrict<T>(n, B, kap, b, nullptr, nx.b, active, st, true, ch.c2[0]));
+    if (ru && dot) {
+      // with the PCG residual update of the previous iteration (r -= alpha q,
+      // written to the other residual buffer) and the convergence test on it
+      uint32_t np = 0;
+      LAUNCHM(kid<T>(MLMC_K_RESIDUAL_RESTRICT), ((ru->first ? 1 : 3) * d + e + dc) * sz, active, B,
+              launch_residual_restrict_update<T>(n, B, kap, b, ru->r1, ru->q, nx.b, *dot, ch.c2[0], &np, st));
+      LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, ru->rr_op, ru->tol2, np, *dot, nullptr, st));
+    } else {
+      LAUNCHM(kid<T>(MLMC_K_RESIDUAL_RESTRICT), (d + e + dc) * sz, active, B,
+              launch_residual_restrict<T>(n, B, kap, b, nullptr, nx.b, active, st, true, ch.c2[0]));
+    }
     T* xc = nullptr;
     if (int rc = vcycle<T>(ctx, L, l + 1, B, nx.b, nx.x, nx.xo, nx.t, active, &xc)) return rc;
     LAUNCHM(kid<T>(MLMC_K_CHEB_PROLONG), (2 * d + dc + e) * sz, active, B,
-            launch_cheb_prolong_presmoothed<T>(n, B, kap, b, xc, x, ch.c2[0], active, st, dot, dot_np));
+            launch_cheb_prolong_presmoothed<T>(n, B, kap, b, xc, x, ch.c2[0], active, st, dot, dot_np,
+                                               ru ? (const T*)ru->r1 : nullptr, ru && dot ? dot->pstate : nullptr));
     *result = x;
     return MLMC_OK;
   }
@@ -262,7 +273,7 @@ int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T*
 // are already in S.partial (GMG path); otherwise the caller computes them.
 template <class T>
 int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T** z, SolveState& S,
-                 uint32_t* fused_np, bool zero_done) {
+                 uint32_t* fused_np, bool zero_done, const RUpdate<T>* ru) {
   const int n = L[0].n;
   *fused_np = 0;
   if (L.size() == 1 || n == 2) {
@@ -274,7 +285,8 @@ int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T**
     *z = L[0].x;
     return MLMC_OK;
   }
-  return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, S.active, z, &S, fused_np, zero_done);
+  if (ru && !presmooth_level<T>(ctx, n, B)) FAIL(MLMC_E_INVALID, "the fused residual update needs the pre-smoothed level 0");
+  return vcycle<T>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, S.active, z, &S, fused_np, zero_done, ru);
 }
 
 int count_active(mlmc_ctx* ctx, SolveState& s, int B, int* out) {
@@ -325,6 +337,12 @@ bool dir_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int B) {
 }
 
 template <class T>
+bool rupd_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int B) {
+  return (ctx->fuse & MLMC_FUSE_RUPDATE) && L.size() > 1 && dir_fusable<T>(ctx, L, B) &&
+         presmooth_level<T>(ctx, L[0].n, B);
+}
+
+template <class T>
 int pcg_dir_begin(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, const T* r, const int* mask,
                   bool fresh) {
   const int n = L[0].n;
@@ -341,27 +359,37 @@ int pcg_dir_begin(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S,
 
 template <class T>
 int pcg_iteration_dir(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p0, T* p1,
-                      T* q, double tol2, int rr_op, bool count, bool first) {
+                      T* q, double tol2, int rr_op, bool count, bool first, T* r2) {
   const int n = L[0].n;
   const double sz = sizeof(T), d = dofs(n) * B, e = elems(n) * B;
   hipStream_t st = ctx->st;
   const int var = zv<T>(ctx);
   const bool fz = zero_step_fusable<T>(ctx, L, B);
+  // the update r -= alpha q of the previous iteration inside this V-cycle
+  const bool fru = r2 && rupd_fusable<T>(ctx, L, B);
+  RUpdate<T> ru;
+  ru.q = q;
+  ru.r1 = r2;
+  ru.rr_op = rr_op == RED_RR_INNER ? RED_RR_INNER_UPD : RED_RR_UPD;
+  ru.tol2 = tol2;
+  ru.first = first;
   uint32_t np = 0;
   T* z = nullptr;
-  if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np, fz)) return rc;
+  if (int rc = precondition<T>(ctx, L, B, r, &z, S, &np, fz, fru ? &ru : nullptr)) return rc;
   if (!np) LAUNCHM(kid<T>(MLMC_K_PCG_DOT), 2 * d * sz, S.active, B, (launch_dot<T>(n, B, r, z, S, &np, st)));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BETA_DIR, 0.0, np, S, nullptr, st));
   // reads z, kappa (and p_old, x); writes p, q (and x)
   LAUNCHM(kid<T>(MLMC_K_PCG_APPLY), ((first ? 3 : 6) * d + e) * sz, S.active, B,
           launch_pcg_dir_apply<T>(n, B, L[0].kap, z, x, p0, p1, q, S.pstate, S, &np, st));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_ALPHA_DIR, 0.0, np, S, nullptr, st));
-  if (fz)
-    LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE_ZERO), (4 * d + e) * sz, S.active, B,
-            launch_pcg_rupdate_zero<T>(n, B, L[0].kap, r, q, L[0].x, ctx->cheb.c2[0], S, &np, st, var));
-  else
-    LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE), 3 * d * sz, S.active, B, launch_pcg_rupdate<T>(n, B, r, q, S, &np, st));
-  LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, rr_op, tol2, np, S, nullptr, st));
+  if (!fru) {
+    if (fz)
+      LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE_ZERO), (4 * d + e) * sz, S.active, B,
+              launch_pcg_rupdate_zero<T>(n, B, L[0].kap, r, q, L[0].x, ctx->cheb.c2[0], S, &np, st, var));
+    else
+      LAUNCHM(kid<T>(MLMC_K_PCG_UPDATE), 3 * d * sz, S.active, B, launch_pcg_rupdate<T>(n, B, r, q, S, &np, st));
+    LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, rr_op, tol2, np, S, nullptr, st));
+  }
   if (count) {
     LAUNCH(MLMC_K_MISC, 0, launch_count_active(B, S, st));
     HIPCHK(hipMemcpyAsync(ctx->h_nactive, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -374,7 +402,7 @@ int pcg_iteration_dir(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState
 // `graph` caches the captured iteration for this work space (may be null).
 template <class T>
 int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q, double tol,
-        int max_iter, int* done_iters, hipGraphExec_t* graph, T* p2, bool fresh, bool defer) {
+        int max_iter, int* done_iters, hipGraphExec_t* graph, T* p2, bool fresh, bool defer, T* r2) {
   const int n = L[0].n;
   const double sz = sizeof(T), d = dofs(n) * B;
   hipStream_t st = ctx->st;
@@ -384,14 +412,14 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
     if (int rc = pcg_dir_begin<T>(ctx, L, B, S, r, S.active, fresh)) return rc;
     int it = 0;
     if (max_iter > 0) {
-      if (int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2, RED_RR, true, true)) return rc;
+      if (int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2, RED_RR, true, true, r2)) return rc;
       it = 1;
       HIPCHK(hipStreamSynchronize(st));
     }
     if (use_graph && !*graph && it < max_iter && *ctx->h_nactive > 0) {
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      const int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2);
+      const int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2, RED_RR, true, false, r2);
       const hipError_t ec = hipStreamEndCapture(st, &g);
       if (rc) {
         if (g) hipGraphDestroy(g);
@@ -407,7 +435,7 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
       for (int j = 0; j < k; ++j) {
         if (use_graph) {
           HIPCHK(hipGraphLaunch(*graph, st));
-        } else if (int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2)) {
+        } else if (int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2, RED_RR, true, false, r2)) {
           return rc;
         }
       }
@@ -485,7 +513,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
     for (int round = 0; round < 4 && total_it < ctx->cfg.max_iter; ++round) {
       int it = 0;
       if (int rc = pcg<double>(ctx, L, B, O, u, w.r, w.p, w.q, rtol, ctx->cfg.max_iter - total_it, &it,
-                              &w.iter_exec[0], w.p2))
+                              &w.iter_exec[0], w.p2, false, false, w.r2))
         return rc;
       total_it += it;
       // confirm with the true residual; samples above tolerance continue
@@ -536,7 +564,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
           LAUNCHM(MLMC_K_MISC, d * 4, O.active, B, launch_fill_interior<float>(n, B, w.d, 0.0, O.active, st));
         int it = 0;
         if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it,
-                               &it, &w.iter_exec[1], w.p32b, dir, owed))
+                               &it, &w.iter_exec[1], w.p32b, dir, owed, w.rin2))
           return rc;
         total_it += it;
         double* uout = bufs[next];
@@ -573,7 +601,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
         LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, I, nullptr, st));
         int it = 0;
         if (int rc = pcg<float>(ctx, L, B, I, w.d, w.rin, w.p32, w.q32, kInnerRtol, ctx->cfg.max_iter - total_it, &it,
-                               &w.iter_exec[1], w.p32b, dir, false))
+                               &w.iter_exec[1], w.p32b, dir, false, w.rin2))
           return rc;
         total_it += it;
         LAUNCHM(MLMC_K_MISC, d * 20, O.active, B, launch_add_correction(n, B, u, w.d, O, st));
@@ -667,7 +695,7 @@ int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (t->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
   if (t->graph_batch < 0 || t->graph_batch > 16) { why = "graph_batch must be in 0..16"; return MLMC_E_INVALID; }
   if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
-                   MLMC_FUSE_DIRECTION)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
+                   MLMC_FUSE_DIRECTION | MLMC_FUSE_RUPDATE)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
   return MLMC_OK;
 }
 
@@ -705,13 +733,15 @@ void apply_tuning(mlmc_ctx* ctx, const mlmc_tuning& t) {
 }
 
 template int vcycle<float>(mlmc_ctx*, std::vector<Level<float>>&, int, int, const float*, float*, float*, float*,
-                           const int*, float**, SolveState*, uint32_t*, bool);
+                           const int*, float**, SolveState*, uint32_t*, bool, const RUpdate<float>*);
 template int vcycle<double>(mlmc_ctx*, std::vector<Level<double>>&, int, int, const double*, double*, double*,
-                            double*, const int*, double**, SolveState*, uint32_t*, bool);
+                            double*, const int*, double**, SolveState*, uint32_t*, bool, const RUpdate<double>*);
 template int precondition<float>(mlmc_ctx*, std::vector<Level<float>>&, int, const float*, float**, SolveState&,
-                                 uint32_t*, bool);
+                                 uint32_t*, bool, const RUpdate<float>*);
 template int precondition<double>(mlmc_ctx*, std::vector<Level<double>>&, int, const double*, double**, SolveState&,
-                                  uint32_t*, bool);
+                                  uint32_t*, bool, const RUpdate<double>*);
+template bool rupd_fusable<float>(const mlmc_ctx*, const std::vector<Level<float>>&, int);
+template bool rupd_fusable<double>(const mlmc_ctx*, const std::vector<Level<double>>&, int);
 template bool zero_step_fusable<float>(const mlmc_ctx*, const std::vector<Level<float>>&, int);
 template bool zero_step_fusable<double>(const mlmc_ctx*, const std::vector<Level<double>>&, int);
 template int pcg_iteration<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*,
@@ -719,9 +749,9 @@ template int pcg_iteration<float>(mlmc_ctx*, std::vector<Level<float>>&, int, So
 template int pcg_iteration<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*,
                                    double*, double*, double, int, bool);
 template int pcg<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*, float*,
-                        double, int, int*, hipGraphExec_t*, float*, bool, bool);
+                        double, int, int*, hipGraphExec_t*, float*, bool, bool, float*);
 template int pcg<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*, double*,
-                         double*, double, int, int*, hipGraphExec_t*, double*, bool, bool);
+                         double*, double, int, int*, hipGraphExec_t*, double*, bool, bool, double*);
 template bool dir_fusable<float>(const mlmc_ctx*, const std::vector<Level<float>>&, int);
 template bool dir_fusable<double>(const mlmc_ctx*, const std::vector<Level<double>>&, int);
 template int pcg_dir_begin<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, const float*, const int*,
@@ -729,9 +759,9 @@ template int pcg_dir_begin<float>(mlmc_ctx*, std::vector<Level<float>>&, int, So
 template int pcg_dir_begin<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, const double*,
                                    const int*, bool);
 template int pcg_iteration_dir<float>(mlmc_ctx*, std::vector<Level<float>>&, int, SolveState&, float*, float*, float*,
-                                      float*, float*, double, int, bool, bool);
+                                      float*, float*, double, int, bool, bool, float*);
 template int pcg_iteration_dir<double>(mlmc_ctx*, std::vector<Level<double>>&, int, SolveState&, double*, double*,
-                                       double*, double*, double*, double, int, bool, bool);
+                                       double*, double*, double*, double, int, bool, bool, double*);
 
 }  // namespace eng
 }  // namespace mlmc

@@ -104,9 +104,9 @@ struct SolveWork {
   int n = 0, B = 0, precision = 0, solver = 0;
   std::vector<Level<double>> L64;   // fp64 hierarchy (level 0 kappa is the caller's)
   std::vector<Level<float>> L32;    // fp32 hierarchy (mixed precision)
-  double *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;   // fp64 PCG (p2: second direction buffer)
+  double *r = nullptr, *r2 = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;   // fp64 PCG (r2, p2: second buffers)
   double* r64 = nullptr;                                    // fp64 refinement residual
-  float *d = nullptr, *rin = nullptr, *p32 = nullptr, *p32b = nullptr, *q32 = nullptr;  // fp32 inner PCG
+  float *d = nullptr, *rin = nullptr, *rin2 = nullptr, *p32 = nullptr, *p32b = nullptr, *q32 = nullptr;  // fp32 inner PCG
   int* alt = nullptr;   // mixed: 1 where the sample's last refined iterate is in r64 (second buffer)
   StateBufs outer, inner;
   // captured PCG iteration per precision (0: fp64, 1: fp32); tied to the buffers above
@@ -127,6 +127,7 @@ struct SolveWork {
     outer.carve(cv, B, n);
     if (prec == MLMC_PREC_FP64) {
       r = cv.take<double>(B * S0);
+      r2 = cv.take<double>(B * S0);
       p = cv.take<double>(B * S0);
       p2 = cv.take<double>(B * S0);
       q = cv.take<double>(B * S0);
@@ -149,6 +150,7 @@ struct SolveWork {
       r64 = cv.take<double>(B * S0);
       d = cv.take<float>(B * S0);
       rin = cv.take<float>(B * S0);
+      rin2 = cv.take<float>(B * S0);
       p32 = cv.take<float>(B * S0);
       p32b = cv.take<float>(B * S0);
       q32 = cv.take<float>(B * S0);
@@ -238,8 +240,12 @@ struct mlmc_ctx {
   bool use_graphs = true;         // replay the PCG iteration from a captured hipGraph
   bool own_stream = false;        // the context created st itself
   int graph_batch = 2;            // graph launches per convergence check
+  // MLMC_FUSE_* bits in use: all but RUPDATE, which measured slower on the
+  // 64^3 batch (its convergence test moves into the next iteration's first
+  // kernel, so each solve runs one more residual restriction) and is left to
+  // the autotuner
   int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
-             MLMC_FUSE_DIRECTION;   // MLMC_FUSE_* bits in use
+             MLMC_FUSE_DIRECTION;
   mlmc_server* server = nullptr;  // serving pools and threads while serving
 };
 
@@ -326,6 +332,19 @@ int ensure_solve_work(mlmc_ctx* ctx, int n, int B);
 void carve_batch(Carver& cv, BatchWork& w, const mlmc_config& c, int level, int B);
 int ensure_batch_work(mlmc_ctx* ctx, int level, int B);
 int ensure_tables(mlmc_ctx* ctx, int n, double** tab);
+// The PCG residual update r -= alpha q fused into the first kernel of the next
+// iteration's V-cycle (level 0, pre-smoothed residual restriction): q, the
+// second residual buffer (the first is the V-cycle's right-hand side), the
+// reduce op and tolerance of the convergence test that follows it.  `first`
+// only sets the byte count (no update on a solve's first iteration).
+template <class T>
+struct RUpdate {
+  const T* q = nullptr;
+  T* r1 = nullptr;
+  int rr_op = RED_RR_UPD;
+  double tol2 = 0.0;
+  bool first = false;
+};
 int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float* kap32);
 // One V-cycle on levels l.. of L; returns the buffer that holds the result.
 // With `dot` the last smoothing step of level l also writes the partial sums
@@ -334,12 +353,12 @@ int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float
 template <class T>
 int vcycle(mlmc_ctx* ctx, std::vector<Level<T>>& L, int l, int B, const T* b, T* x, T* xo, T* t,
            const int* active, T** result, SolveState* dot = nullptr, uint32_t* dot_np = nullptr,
-           bool zero_done = false);
+           bool zero_done = false, const RUpdate<T>* ru = nullptr);
 // z = M^-1 r.  When *fused_np is set on return, the partial sums of r . z
 // are already in S.partial (GMG path); otherwise the caller computes them.
 template <class T>
 int precondition(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, const T* r, T** z, SolveState& S,
-                 uint32_t* fused_np, bool zero_done = false);
+                 uint32_t* fused_np, bool zero_done = false, const RUpdate<T>* ru = nullptr);
 // Whether the preconditioner's first smoothing step on the finest level runs
 // through the level-by-level kernels, so a PCG update can produce it.
 template <class T>
@@ -352,15 +371,22 @@ int pcg_iteration(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S,
 // operator apply (MLMC_FUSE_DIRECTION and the LDS engine usable on L[0]).
 template <class T>
 bool dir_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int B);
+// Whether the fused-direction iteration also fuses its residual update into
+// the next V-cycle (MLMC_FUSE_RUPDATE, and the pre-smoothed level 0).
+template <class T>
+bool rupd_fusable(const mlmc_ctx* ctx, const std::vector<Level<T>>& L, int B);
 // One fused-direction PCG iteration: z = M^-1 r and beta; p = z + beta p
 // (buffers p0/p1 by S.pstate), q = A p, alpha, and the previous x += alpha p;
 // r -= alpha q with the convergence test.  The start of a solve sets S.pstate
 // (launch_dir_begin) and, when the zero step is fused into the update, the
 // zero-iterate smoothing step of the first V-cycle.  `first`: only for the
 // byte count of the apply (no previous direction is read).
+// r2 (may be null): the second residual buffer; with it and rupd_fusable the
+// residual update r -= alpha q moves into the next iteration's V-cycle.
 template <class T>
 int pcg_iteration_dir(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p0, T* p1,
-                      T* q, double tol2, int rr_op = RED_RR, bool count = true, bool first = false);
+                      T* q, double tol2, int rr_op = RED_RR, bool count = true, bool first = false,
+                      T* r2 = nullptr);
 // Start of a fused-direction solve on the samples with mask[b] (see
 // pcg_iteration_dir); fresh: x holds no value yet (it is written, not updated,
 // by its first update, so it needs no zero fill).
@@ -375,7 +401,7 @@ int pcg_dir_begin(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S,
 template <class T>
 int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* r, T* p, T* q, double tol,
         int max_iter, int* done_iters, hipGraphExec_t* graph, T* p2 = nullptr, bool fresh = false,
-        bool defer = false);
+        bool defer = false, T* r2 = nullptr);
 // kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
 int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
                bool kap32_ready = false);

@@ -34,7 +34,8 @@ struct SolveState {
   uint32_t pstride; // capacity of partial sums per sample
   int* phase;       // serving: per-slot phase (PHASE_*), may be null
   int* pstate;      // fused-direction PCG: bit 0 = buffer of the current direction, bit 1 = no step taken yet,
-                    // bit 2 = the iterate holds no value yet (written, not updated, by its first update)
+                    // bit 2 = the iterate holds no value yet (written, not updated, by its first update),
+                    // bit 3 = buffer of the current residual (fused residual update)
   int* began;       // fused-direction PCG: samples active when the solve started
 };
 
@@ -96,10 +97,21 @@ bool presmooth_usable(int n, int B);
 // launch_cheb_prolong with the pre-smoothed iterate formed on the fly:
 // out = y + c2 D^-1 (b - A y), y = c2 D^-1 b + P xc (one Chebyshev step on each
 // side of the coarse-grid correction, the first from a zero iterate)
+// b1/bstate (may be null): the right-hand side of sample s is b1 where
+// (bstate[s] & 8) (the second residual buffer of a fused-update PCG)
 template <class T>
 hipError_t launch_cheb_prolong_presmoothed(int n, int B, const T* kap, const T* b, const T* xc, T* out, double c2,
                                            const int* active, hipStream_t st, SolveState* dot = nullptr,
-                                           uint32_t* nparts = nullptr);
+                                           uint32_t* nparts = nullptr, const T* b1 = nullptr,
+                                           const int* bstate = nullptr);
+// The pre-smoothed residual restriction with the PCG residual update of the
+// previous iteration fused in: r = r_old - alpha q (r_old in r0 or r1 by
+// s.pstate bit 3; not on a first iteration, s.pstate bit 1) formed on the fly,
+// written to the other buffer, partial sums of r . r into s.partial (*nparts
+// per sample); bc = P^T (r - A c2 D^-1 r).  Usable when presmooth_usable.
+template <class T>
+hipError_t launch_residual_restrict_update(int n, int B, const T* kap, const T* r0, T* r1, const T* q, T* bc,
+                                          SolveState s, double c2, uint32_t* nparts, hipStream_t st);
 template <class T>
 hipError_t launch_prolong_add(int nf, int B, const T* xc, T* xf, const int* active, hipStream_t st);
 template <class T>
@@ -193,7 +205,9 @@ enum ReduceOp : int {
   RED_RR_INNER = 6, // rr = sum; converged -> phase TRANSITION
   RED_RR_OUTER = 7, // rr = sum; phase DONE if converged else RESTART
   RED_BETA_DIR = 8, // fused direction: beta = sum / rz (not on a first direction); rz = sum
-  RED_ALPHA_DIR = 9 // fused direction: alpha = rz / sum; iters += 1; next direction buffer, first cleared
+  RED_ALPHA_DIR = 9, // fused direction: alpha = rz / sum; iters += 1; next direction buffer, first cleared
+  RED_RR_UPD = 10,   // fused residual update: as RED_RR, and the residual buffer flips unless first
+  RED_RR_INNER_UPD = 11 // as RED_RR_INNER (serving), flip as RED_RR_UPD, and a converged slot leaves the mask
 };
 hipError_t launch_reduce(int B, int op, double tol2, uint32_t nparts, SolveState s, double* out,
                          hipStream_t st);

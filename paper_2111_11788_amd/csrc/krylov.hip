@@ -299,13 +299,25 @@ __global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t
       const int ps = st.pstate[b];
       st.alpha[b] = st.rz[b] / v;
       st.iters[b] += 1;
-      st.pstate[b] = ((ps & 1) ^ 1) | ((ps & 2) ? (ps & 4) : 0);
+      st.pstate[b] = ((ps & 1) ^ 1) | ((ps & 2) ? (ps & 4) : 0) | (ps & 8);
       break;
     }
     case RED_RR_INNER:
       st.rr[b] = v;
       if (v <= tol2 * st.bb[b]) st.phase[b] = PHASE_TRANSITION;
       break;
+    case RED_RR_UPD:
+    case RED_RR_INNER_UPD: {
+      // the residual just written by the fused update is in the other buffer
+      const int ps = st.pstate[b];
+      if (!(ps & 2)) st.pstate[b] = ps ^ 8;
+      st.rr[b] = v;
+      if (v <= tol2 * st.bb[b]) {
+        st.active[b] = 0;
+        if (op == RED_RR_INNER_UPD) st.phase[b] = PHASE_TRANSITION;
+      }
+      break;
+    }
     case RED_RR_OUTER:
       st.rr[b] = v;
       st.phase[b] = v <= tol2 * st.bb[b] ? PHASE_DONE : PHASE_RESTART;

@@ -205,7 +205,7 @@ int step(Pool& p) {
     const double tol2 = kInnerTol * kInnerTol;
     if (dir) {
       if (int rc = pcg_iteration_dir<float>(ctx, L, S, ii, p.w.d, p.w.rin, p.w.p32, p.w.p32b, p.w.q32, tol2,
-                                            RED_RR_INNER, false))
+                                            RED_RR_INNER, false, false, p.w.rin2))
         return rc;
     } else if (int rc = pcg_iteration<float>(ctx, L, S, ii, p.w.d, p.w.rin, p.w.p32, p.w.q32, tol2, RED_RR_INNER,
                                              false)) {

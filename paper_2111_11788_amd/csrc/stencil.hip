@@ -123,13 +123,19 @@ struct EpiResidual {
 template <class T, int V, bool USE_XO, bool DOT>
 struct EpiCheb {
   static constexpr bool kReduce = DOT;
-  static constexpr bool kBegin = false;
+  static constexpr bool kBegin = true;
   const T* b;
   const T* xo;
   T* out;
   T c1, c2;
   T* save = nullptr;
+  // per-sample right-hand side: b1 where (bstate[s] & 8) (may be null)
+  const T* b1 = nullptr;
+  const int* bstate = nullptr;
   T bv[V], xov[V];
+  __device__ void begin(uint32_t s) {
+    if (bstate && (bstate[s] & 8)) b = b1;
+  }
   __device__ void pre(size_t pos) {
     vload<T, V>(b + pos, bv);
     if (USE_XO) vload<T, V>(xo + pos, xov);
@@ -686,6 +692,10 @@ enum : int { OP_PLAIN = 0, OP_ADDD = 1, OP_Z1 = 2, OP_DIR = 3 };
 
 template <class T>
 struct OpArgs {
+  // per-sample choice of the u operand: u1 where (ustate[b] & 8), u otherwise
+  // (may be null: u for every sample)
+  const T* u1 = nullptr;
+  const int* ustate = nullptr;
   const float* d = nullptr;       // OP_ADDD
   // OP_ADDD: the update a fused-direction solve still owes d (may be null):
   // d + alpha p with p the solve's current direction (fp32 buffers q0/q1 by
@@ -807,6 +817,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   // a row fits in one wave (zlds_ok): halos by DPP, no branch in the gather
   constexpr bool shuf = true;
   const T* ub = (NEED_U && u) ? u + (size_t)b * stride : nullptr;
+  if (NEED_U && op.ustate && (op.ustate[b] & 8)) ub = op.u1 + (size_t)b * stride;
   const float* db = ADDD ? op.d + (size_t)b * stride : nullptr;
   const T* kb = kap + (size_t)b * n2 * n;
   const T* cb = PRO ? xc + (size_t)b * cstride : nullptr;
@@ -1150,11 +1161,32 @@ inline bool resr_ok(const ZGeom& g) {
          (g.rows + 1) * g.G <= 2 * g.threads - (g.threads >= 192 ? g.threads / 2 : 0) && resr_bytes<T, Z1>(g) <= 65536;
 }
 
-template <class T, int V, bool Z1>
+// UPD (with Z1): the PCG residual update that ends the previous iteration is
+// done here: the right-hand side is r = r_old - alpha q, formed while staging
+// r_old and q (and again at the thread's own nodes, by the same fma), written
+// at the tile's own nodes into the other residual buffer, with the partial
+// sums of r . r; on a sample's first iteration (pstate bit 1) r = r_old and
+// nothing is written.  The buffers are bf (R0) and upd.r1 (R1), selected by
+// pstate bit 3.
+template <class T>
+struct ResrUpd {
+  const T* q = nullptr;
+  T* r1 = nullptr;
+  const int* pstate = nullptr;
+  const double* alpha = nullptr;
+  double* partial = nullptr;
+  uint32_t pstride = 0;
+};
+
+template <class T>
+__device__ __forceinline__ T rupd(T r, T a, T q) { return fma(-a, q, r); }
+
+template <class T, int V, bool Z1, bool UPD>
 __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const T* __restrict__ x,
                                               const T* __restrict__ bf, const T* __restrict__ kap,
                                               const int* __restrict__ active, T* __restrict__ bc, size_t cstride,
-                                              T c2) {
+                                              T c2, ResrUpd<T> upd) {
+  static_assert(!UPD || Z1, "the residual update is fused into the pre-smoothed form");
   typedef typename Vec<T, V>::type vt;
   constexpr int KOFF = Z1 ? 1 : 0, KP = Z1 ? 4 : 2, LEAD = Z1 ? 3 : 1;
   extern __shared__ __align__(16) unsigned char zsmem[];
@@ -1188,6 +1220,24 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
   const T* bb = bf + (size_t)b * stride;
   const T* kb = kap + (size_t)b * n2 * n;
   const int nc = n >> 1, nc2 = nc * nc;
+  // UPD: r_old in R[par], r written to R[1 - par] unless this is the first
+  // iteration; q and alpha of the previous iteration
+  bool upd_on = false;
+  T ua = T(0);
+  const T* qb = nullptr;
+  T* rnb = nullptr;
+  if constexpr (UPD) {
+    const int ps = upd.pstate[b];
+    const bool par = (ps & 8) != 0;
+    upd_on = (ps & 2) == 0;
+    ua = (T)upd.alpha[b];
+    const T* rold = (par ? (const T*)upd.r1 : bf) + (size_t)b * stride;
+    ub = rold;
+    bb = rold;
+    qb = upd.q + (size_t)b * stride;
+    rnb = (par ? const_cast<T*>(bf) : upd.r1) + (size_t)b * stride;
+  }
+  double racc = 0.0;   // UPD: sum of r . r over the tile's own nodes
 
   for (int q = tid; q < 3 * UR; q += nthr) {
     Ul[q * URS + V - 1] = T(0);
@@ -1195,7 +1245,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
   }
   for (int q = tid; q < KP * KR; q += nthr) Kl[q * KRS + V - 1] = T(0);
 
-  vt pu[2], pk[2];
+  vt pu[2], pk[2], pq[UPD ? 2 : 1];
   // staged u vector m: extras on the last threads (see k_zlds)
   const int ubase = 2 * nthr - UR * G;
   auto uv = [&](int m) { return m == 0 ? tid : (tid >= ubase ? nthr + tid - ubase : 1 << 30); };
@@ -1205,7 +1255,11 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
       const int v = uv(m);
       const int r = v / G, c = v - (v / G) * G;
       const int jj = j0 - 1 + r;
-      if (v < UR * G && jj <= n) pu[m] = *reinterpret_cast<const vt*>(ub + (size_t)n2 * kk + (size_t)n * jj + c * V);
+      if (v < UR * G && jj <= n) {
+        const size_t off = (size_t)n2 * kk + (size_t)n * jj + c * V;
+        pu[m] = *reinterpret_cast<const vt*>(ub + off);
+        if (UPD && upd_on) pq[UPD ? m : 0] = *reinterpret_cast<const vt*>(qb + off);
+      }
     }
   };
   // Z1: the operand of the plane kk fetched last, in registers, before the
@@ -1220,7 +1274,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
       if (v < UR * G && jj <= n) {
         T w[V];
 #pragma unroll
-        for (int t = 0; t < V; ++t) w[t] = pu[m][t];
+        for (int t = 0; t < V; ++t) w[t] = (UPD && upd_on) ? rupd(pu[m][t], ua, pq[UPD ? m : 0][t]) : pu[m][t];
         z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, G, true, h, c2);
 #pragma unroll
         for (int t = 0; t < V; ++t) pu[m][t] = w[t];
@@ -1353,7 +1407,22 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
                 far[v] += (K[0][sy][v + sx] + K[1][sy][v + sx]) * (sy ? R2 : R0)[v + 2 * sx];
         }
         T bv[V], t[V];
-        vload<T, V>(bb + i0 + (size_t)n * j + (size_t)n2 * kk, bv);
+        const size_t own = i0 + (size_t)n * j + (size_t)n2 * kk;
+        vload<T, V>(bb + own, bv);
+        if (UPD) {
+          if (upd_on) {
+            T qv[V];
+            vload<T, V>(qb + own, qv);
+#pragma unroll
+            for (int v = 0; v < V; ++v) bv[v] = rupd(bv[v], ua, qv[v]);
+          }
+          // the tile's own nodes: rows j0 .. j0+R-1, planes k0 .. k1-1
+          if (jr < R && kk < k1) {
+            if (upd_on) vstore<T, V>(rnb + own, bv);
+#pragma unroll
+            for (int v = 0; v < V; ++v) racc += (double)bv[v] * (double)bv[v];
+          }
+        }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           const T au = h * (ksum[v] * uc[v] * third - far[v] * twelfth);
@@ -1394,6 +1463,10 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
       __syncthreads();
       const int tu = sm; sm = s0; s0 = sp; sp = tu;
     }
+  }
+  if constexpr (UPD) {
+    racc = block_sum(racc);
+    if (threadIdx.x == 0) upd.partial[(size_t)b * upd.pstride + part] = racc;
   }
 }
 
@@ -1745,16 +1818,21 @@ bool presmooth_usable(int n, int B) {
 
 template <class T>
 hipError_t launch_cheb_prolong_presmoothed(int n, int B, const T* kap, const T* b, const T* xc, T* out, double c2,
-                                           const int* active, hipStream_t st, SolveState* dot, uint32_t* nparts) {
+                                           const int* active, hipStream_t st, SolveState* dot, uint32_t* nparts,
+                                           const T* b1, const int* bstate) {
   constexpr int V = ZV<T>::V;
   if (!presmooth_usable<T>(n, B)) return hipErrorInvalidValue;
   OpArgs<T> op;
   op.c2 = T(c2);
+  op.u1 = b1;
+  op.ustate = bstate;
   if (dot)
-    return zlaunch_lds<T, true, true, OP_Z1>(n, B, b, xc, kap, active, dot->partial, dot->pstride,
-                                             EpiCheb<T, V, false, true>{b, nullptr, out, T(0), T(c2)}, nparts, st, op);
-  return zlaunch_lds<T, true, true, OP_Z1>(n, B, b, xc, kap, active, nullptr, 0,
-                                           EpiCheb<T, V, false, false>{b, nullptr, out, T(0), T(c2)}, nullptr, st, op);
+    return zlaunch_lds<T, true, true, OP_Z1>(
+        n, B, b, xc, kap, active, dot->partial, dot->pstride,
+        EpiCheb<T, V, false, true>{b, nullptr, out, T(0), T(c2), nullptr, b1, bstate}, nparts, st, op);
+  return zlaunch_lds<T, true, true, OP_Z1>(
+      n, B, b, xc, kap, active, nullptr, 0, EpiCheb<T, V, false, false>{b, nullptr, out, T(0), T(c2), nullptr, b1, bstate},
+      nullptr, st, op);
 }
 
 template <class T>
@@ -1841,13 +1919,33 @@ hipError_t launch_residual_restrict(int n, int B, const T* kap, const T* b, cons
   const uint32_t blocks = g.parts() * (uint32_t)B;
   if (presmooth) {
     if (!presmooth_usable<T>(n, B)) return hipErrorInvalidValue;
-    k_resr<T, V, true><<<dim3(blocks), dim3(g.threads), resr_bytes<T, true>(g), st>>>(
-        g, grid_stride(n), T(1) / T(n), nullptr, b, kap, active, bc, grid_stride(n / 2), T(c2));
+    k_resr<T, V, true, false><<<dim3(blocks), dim3(g.threads), resr_bytes<T, true>(g), st>>>(
+        g, grid_stride(n), T(1) / T(n), nullptr, b, kap, active, bc, grid_stride(n / 2), T(c2), ResrUpd<T>{});
     return hipGetLastError();
   }
   if (!resr_ok<T>(g)) return hipErrorInvalidValue;
-  k_resr<T, V, false><<<dim3(blocks), dim3(g.threads), resr_bytes<T, false>(g), st>>>(
-      g, grid_stride(n), T(1) / T(n), x, b, kap, active, bc, grid_stride(n / 2), T(0));
+  k_resr<T, V, false, false><<<dim3(blocks), dim3(g.threads), resr_bytes<T, false>(g), st>>>(
+      g, grid_stride(n), T(1) / T(n), x, b, kap, active, bc, grid_stride(n / 2), T(0), ResrUpd<T>{});
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_residual_restrict_update(int n, int B, const T* kap, const T* r0, T* r1, const T* q, T* bc,
+                                          SolveState s, double c2, uint32_t* nparts, hipStream_t st) {
+  constexpr int V = ZV<T>::V;
+  const ZGeom g = resr_geom<T>(n, B);
+  if (!presmooth_usable<T>(n, B)) return hipErrorInvalidValue;
+  if (nparts) *nparts = g.parts();
+  ResrUpd<T> u;
+  u.q = q;
+  u.r1 = r1;
+  u.pstate = s.pstate;
+  u.alpha = s.alpha;
+  u.partial = s.partial;
+  u.pstride = s.pstride;
+  const uint32_t blocks = g.parts() * (uint32_t)B;
+  k_resr<T, V, true, true><<<dim3(blocks), dim3(g.threads), resr_bytes<T, true>(g), st>>>(
+      g, grid_stride(n), T(1) / T(n), nullptr, r0, kap, s.active, bc, grid_stride(n / 2), T(c2), u);
   return hipGetLastError();
 }
 
@@ -1915,7 +2013,10 @@ hipError_t launch_convert(size_t count, const Ts* src, Td* dst, hipStream_t st) 
   template hipError_t launch_pcg_rupdate_zero<T>(int, int, const T*, T*, const T*, T*, double, SolveState, \
                                                  uint32_t*, hipStream_t, int);                         \
   template hipError_t launch_cheb_prolong_presmoothed<T>(int, int, const T*, const T*, const T*, T*, double, \
-                                                         const int*, hipStream_t, SolveState*, uint32_t*); \
+                                                         const int*, hipStream_t, SolveState*, uint32_t*, \
+                                                         const T*, const int*);                            \
+  template hipError_t launch_residual_restrict_update<T>(int, int, const T*, const T*, T*, const T*, T*,  \
+                                                         SolveState, double, uint32_t*, hipStream_t);      \
   template hipError_t launch_prolong_add<T>(int, int, const T*, T*, const int*, hipStream_t);          \
   template hipError_t launch_coarsest<T>(int, const T*, const T*, T*, const int*, hipStream_t);        \
   template hipError_t launch_coarsen<T>(int, int, const T*, T*, hipStream_t, const int*);

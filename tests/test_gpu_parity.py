@@ -172,7 +172,7 @@ def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg, zvar32, zvar6
     n, B = 32, 3
     wl = _wl(n0=n, levels=1, qoi=1, precision=1, solver=0, n_modes=16, corr_len=0.3)
     qs = []
-    for fuse in (63, 47, 34, 32, 31, 25, 15, 8, 4, 2, 1, 0):   # every fusion bit alone, all, none, mixes
+    for fuse in (127, 63, 47, 34, 32, 31, 25, 15, 8, 4, 2, 1, 0):   # every fusion bit alone, all, none, mixes
         ctx = mm.Context(wl, cheb_degree=deg, arena_bytes=512 << 20)
         ctx.set_tuning(fuse=fuse, vsmall_fp32=0, vsmall_fp64=0, zvar_fp32=zvar32, zvar_fp64=zvar64)
         xi = ctx.draw_xi(0, 21, B)
@@ -184,6 +184,30 @@ def test_mixed_solve_fused_and_unfused_agree_with_oracle(dev, deg, zvar32, zvar6
         want = _oracle_q(n, kap_h[b], 1)
         for q in qs:
             assert abs(q[b] - want) <= 1e-7 * abs(want)
+
+
+@pytest.mark.parametrize("fuse", [127, 63, 0])
+@pytest.mark.parametrize("n,B", [(16, 3), (32, 2), (64, 2)])
+def test_fp64_degree1_solve_matches_oracle(dev, n, B, fuse):
+    # fp64 GMG-PCG with Chebyshev degree 1: 127 forms the pre-smoothing step
+    # on the fly, fuses the direction into the apply and the residual update
+    # into the next V-cycle (two residual buffers); 63 without the last; 0 none
+    wl = _wl(n0=n, levels=1, qoi=1, precision=0, solver=0, n_modes=16, corr_len=0.3)
+    ctx = mm.Context(wl, cheb_degree=1, arena_bytes=1 << 30)
+    ctx.set_tuning(fuse=fuse, vsmall_fp64=0)
+    xi = ctx.draw_xi(0, 31, B)
+    kap = ctx.field(n, xi)
+    u, it = ctx.solve(n, kap)
+    q = ctx.qoi(n, u).cpu().numpy()
+    kap_h = kap.cpu().numpy()
+    for b in range(B):
+        want = _oracle_q(n, kap_h[b], 1)
+        assert abs(q[b] - want) <= 1e-8 * abs(want), (b, q[b], want, it[b])
+    uc = mm.from_grid(u, n).cpu().numpy()
+    bvec = fe.load_constant(n)
+    for b in range(B):
+        res = bvec - fe.assemble(n, kap_h[b]) @ uc[b]
+        assert np.linalg.norm(res) <= 1.5e-12 * np.linalg.norm(bvec)
 
 
 def _oracle_q(n, kap, qoi, rtol=1e-12):

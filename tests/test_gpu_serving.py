@@ -25,11 +25,13 @@ def dev():
     return torch.device("cuda")
 
 
-@pytest.mark.parametrize("fuse", [None, 0])
-def test_served_samples_match_oracle(dev, fuse):
-    # fuse None: the default fusions (direction fused into the apply); 0: none
+@pytest.mark.parametrize("fuse,deg", [(None, 2), (None, 1), (0, 2)])
+def test_served_samples_match_oracle(dev, fuse, deg):
+    # fuse None: the default fusions (direction fused into the apply; with
+    # Chebyshev degree 1 also the on-the-fly pre-smoothing and the residual
+    # update fused into the next V-cycle); 0: none
     wl = _wl()
-    ctx = mm.Context(wl, arena_bytes=1 << 30)
+    ctx = mm.Context(wl, arena_bytes=1 << 30, cheb_degree=deg)
     if fuse is not None:
         ctx.set_tuning(fuse=fuse)
     ctx.serve_start([8, 8, 4])
@@ -48,9 +50,10 @@ def test_served_samples_match_oracle(dev, fuse):
         assert r["latency_s"] >= r["queue_s"] >= 0.0
 
 
-def test_alone_and_in_the_mix_are_identical(dev):
+@pytest.mark.parametrize("deg", [2, 1])
+def test_alone_and_in_the_mix_are_identical(dev, deg):
     wl = _wl()
-    ctx = mm.Context(wl, arena_bytes=1 << 30)
+    ctx = mm.Context(wl, arena_bytes=1 << 30, cheb_degree=deg)
     ctx.serve_start([16, 16, 6])
     alone = ctx.wait([ctx.submit(2, 11)])
     (a,) = alone.values()
