@@ -184,7 +184,7 @@ def run_c3(args):
     wl = workloads.C3
 
     def one(eps):
-        ctx = mm.Context(wl, max_batch=1024, arena_bytes=40 << 30)
+        ctx = mm.Context(wl, max_batch=1024, arena_bytes=40 << 30, cheb_degree=args.cheb_degree)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nl, est = ctx.estimate(eps, n_pilot=32, cost_model=0, max_rounds=3)
@@ -242,7 +242,7 @@ def run_c4(args):
             kle_check.append({"mesh": wl.n(l), "samples": 64, "qoi_rel_dev_max": float(rel.max()),
                               "qoi_rel_dev_mean": float(rel.mean())})
         torch.cuda.empty_cache()
-    ctx = mm.Context(wl, arena_bytes=int(args.arena_gb * 2**30))
+    ctx = mm.Context(wl, arena_bytes=int(args.arena_gb * 2**30), cheb_degree=args.cheb_degree)
     ctx.serve_start(slots)
     rng = np.random.default_rng(4)
     dofs = np.array([(wl.n(l) - 1) ** 3 + ((wl.n(l) // 2 - 1) ** 3 if l else 0) for l in range(wl.levels)],
@@ -367,7 +367,7 @@ def run_c5(args):
            "config": {"workload": wl.name, "mesh": "256^3", "sigma2": wl.sigma2, "corr_len": wl.corr_len,
                       "n_modes": wl.n_modes, "precision": "mixed"}, "batches": []}
     for B in (4, 8, 16):
-        ctx = mm.Context(wl, max_batch=B)
+        ctx = mm.Context(wl, max_batch=B, cheb_degree=args.cheb_degree)
         y, qf, qc, it = ctx.sample_level(0, 0, B)       # warm-up (carve, graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -422,6 +422,8 @@ def main():
                     "(0: twice the slots)")
     ap.add_argument("--sat-seconds", type=float, default=3.0, help="c4: measured closed-loop seconds")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--cheb-degree", type=int, default=0,
+                    help="c3/c4/c5: Chebyshev smoothing degree (0: the library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); samples are independent, "

@@ -212,6 +212,44 @@ typedef struct mlmc_estimate_opts {
 int mlmc_estimate(mlmc_ctx* ctx, const mlmc_estimate_opts* opts, uint64_t* n_per_level,
                   mlmc_estimate_out* out);
 
+typedef struct mlmc_adaptive_opts {
+  double eps;             /* target RMSE (absolute) of the estimator, eq. mlmc_error, > 0 */
+  int32_t l0;             /* finest level of the first round, 1 <= l0 < levels */
+  int32_t n_pilot;        /* samples of a level in its first round, >= 2 */
+  int32_t cost_model;     /* 0: measured GPU seconds per sample (unsampled levels scaled by their
+                             DOFs); 1: interior DOFs of the pair */
+  int32_t max_rounds;     /* sampling rounds after the first, >= 0 */
+  double extra_fraction;  /* N_l is multiplied by (1 + extra_fraction), >= 0 */
+  double alpha0;          /* decay rate of |mean(Y_l)| while one difference level exists (0: 2) */
+  double beta0;           /* decay rate of V(Y_l) likewise (0: 4) */
+} mlmc_adaptive_opts;
+
+typedef struct mlmc_adaptive_info {
+  int32_t L;              /* finest level in use at the end */
+  int32_t rounds;         /* sampling rounds done */
+  double alpha, beta;     /* last fitted rates of |mean(Y_l)| ~ c s^-alpha l and V(Y_l) ~ c s^-beta l */
+  double bias;            /* estimated |E(Q - Q_L)| = c s^-alpha L / (s^alpha - 1) */
+  double err;             /* sqrt(bias^2 + sum_l V_l / N_l), eq. mlmc_error */
+} mlmc_adaptive_info;
+
+/* Adaptive MLMC (Sec. 2.3 and the adaptive loop of Alg. dyn_par_sched, read
+ * as a do-while loop): start with levels 0..l0; each round samples every level
+ * in use up to its target (continuing its sample indices), fits
+ * |mean(Y_l)| ~ c s^(-alpha l) and V(Y_l) ~ cV s^(-beta l) over l = 1..L
+ * (least squares in log_s, alpha clamped to [0.5, 4], beta to [0.5, 8];
+ * alpha0 / beta0 through a single level), estimates the bias of Qtilde_L as
+ * the tail c s^(-alpha L) / (s^alpha - 1) and e^2 = bias^2 + sum V_l / N_l
+ * (eq. mlmc_error), and stops when e <= eps.  Otherwise L grows to
+ * ceil(log_s(sqrt(2) c / ((s^alpha - 1) eps)) / alpha) (eq. mlmc_num_levels,
+ * capped by the configured levels) and every level's target to
+ * eq. mlmc_num_samples (V of new levels from the fit, at least n_pilot);
+ * targets never decrease.  s = 2.  n_per_level (host, `levels` entries, may be
+ * NULL) receives the samples per level (0 beyond L), info the final L, rates
+ * and error, out the estimator.  Errors: MLMC_E_INVALID for bad options, else
+ * as mlmc_sample_level. */
+int mlmc_estimate_adaptive(mlmc_ctx* ctx, const mlmc_adaptive_opts* opts, uint64_t* n_per_level,
+                           mlmc_adaptive_info* info, mlmc_estimate_out* out);
+
 /* ------------------------------------------------------------- tuning */
 
 /* Execution choices that change speed, not the discrete solution each solve

@@ -153,3 +153,106 @@ def estimate(wl, eps: float, n_pilot: int, max_rounds: int = 3, extra_fraction: 
             break
     qt, v, vq = estimator(stats)
     return [s.n for s in stats], qt, vq, stats
+
+
+def fit_decay(values: Sequence[float], levels: Sequence[int], s: float = 2.0):
+    """Least-squares fit of values_l ~ c s^(-r l): the slope of log_s(values)
+    against l (Sec. 2.3: c and alpha of eq. mlmc_num_levels are estimated from
+    the level means, the decay of the level variances likewise).  Returns
+    (c, r)."""
+    x = [float(l) for l in levels]
+    y = [math.log(v) / math.log(s) for v in values]
+    xm = sum(x) / len(x)
+    ym = sum(y) / len(y)
+    sxx = sum((a - xm) * (a - xm) for a in x)
+    sxy = sum((a - xm) * (b - ym) for a, b in zip(x, y))
+    r = -sxy / sxx
+    c = s ** (ym + r * xm)
+    return c, r
+
+
+def _rate(values: Sequence[float], l_max: int, default: float, lo: float, hi: float, s: float):
+    """(c, r) of values_l ~ c s^(-r l) over l = 1..l_max: fitted when there are
+    two or more levels (r clamped to [lo, hi], c refitted for the clamped r),
+    else r = default through the single point."""
+    lv = list(range(1, l_max + 1))
+    vals = [max(abs(values[l]), 1e-300) for l in lv]
+    if len(lv) >= 2:
+        c, r = fit_decay(vals, lv, s)
+        if lo <= r <= hi:
+            return c, r
+        r = min(max(r, lo), hi)
+    else:
+        r = default
+    logc = sum(math.log(v) / math.log(s) + r * l for v, l in zip(vals, lv)) / len(lv)
+    return s ** logc, r
+
+
+def estimate_adaptive(wl, eps: float, l0: int, n_pilot: int, max_rounds: int = 10, alpha0: float = 2.0,
+                      beta0: float = 4.0, extra_fraction: float = 0.0, sampler=None, cost=None, s: float = 2.0):
+    """Adaptive MLMC (Sec. 2.3 and the adaptive loop of Alg. dyn_par_sched),
+    read as a do-while loop: sample every level up to its target, estimate the
+    error e^2 = bias^2 + V(Qtilde) (eq. mlmc_error), stop when e <= eps; else
+    update L by eq. mlmc_num_levels and the targets by eq. mlmc_num_samples,
+    and repeat.
+
+    Readings (the paper leaves them open): the level means fit
+    |mean(Y_l)| ~ c s^(-alpha l) over l = 1..L (alpha = alpha0 with one level,
+    else least squares clamped to [0.5, 4]); the bias of Qtilde_L is the
+    geometric tail sum_{k>L} c s^(-alpha k) = c s^(-alpha L) / (s^alpha - 1),
+    so eq. mlmc_num_levels takes c / (s^alpha - 1); L only grows and stays
+    below the number of configured meshes; the variances of levels not yet
+    sampled follow V_l ~ cV s^(-beta l) fitted like alpha (beta0 with one
+    level, clamp [0.5, 8]); new levels get at least n_pilot samples; targets
+    never decrease.  `sampler(level, first, count)` returns Y values (default:
+    the FE path of sample_level); `cost(level)` the cost of one Y_l (default:
+    the deterministic DOF model).
+    Returns a dict with L, n_per_level, qtilde, var_qtilde, bias, err, alpha,
+    beta, rounds, stats."""
+    if sampler is None:
+        sampler = lambda l, first, count: sample_level(wl, l, first, count)[0]
+    if cost is None:
+        cost = lambda l: level_cost(wl, l)
+    M = wl.levels
+    if not 1 <= l0 < M:
+        raise ValueError("need 1 <= l0 < number of levels")
+    L = l0
+    stats = [RunningStats() for _ in range(M)]
+    target = [n_pilot] * (L + 1) + [0] * (M - L - 1)
+    alpha = beta = bias = err = float("nan")
+    rounds = 0
+    for rnd in range(max_rounds + 1):
+        rounds = rnd + 1
+        for l in range(L + 1):
+            have = stats[l].n
+            if target[l] > have:
+                for y in sampler(l, have, target[l] - have):
+                    stats[l].push(float(y))
+        means = [st.mean for st in stats]
+        var = [st.var for st in stats]
+        cY, alpha = _rate(means, L, alpha0, 0.5, 4.0, s)
+        cV, beta = _rate(var, L, beta0, 0.5, 8.0, s)
+        tail = s ** alpha - 1.0
+        bias = cY * s ** (-alpha * L) / tail
+        vq = sum(var[l] / stats[l].n for l in range(L + 1))
+        err = math.sqrt(bias * bias + vq)
+        if err <= eps or rnd == max_rounds:
+            break
+        L_new = min(M - 1, max(L, num_levels(cY / tail, alpha, eps, s)))
+        V = [var[l] if l <= L else cV * s ** (-beta * l) for l in range(L_new + 1)]
+        C = [cost(l) for l in range(L_new + 1)]
+        tot = sum(math.sqrt(v * c) for v, c in zip(V, C))
+        grow = L_new > L
+        for l in range(L_new + 1):
+            want = int(math.ceil(2.0 / (eps * eps) * math.sqrt(V[l] / C[l]) * tot * (1.0 + extra_fraction)))
+            want = max(want, n_pilot)
+            if want > target[l]:
+                target[l] = want
+                grow = True
+        L = L_new
+        if not grow:
+            break
+    qt = sum(stats[l].mean for l in range(L + 1))
+    vq = sum(stats[l].var / stats[l].n for l in range(L + 1))
+    return dict(L=L, n_per_level=[stats[l].n for l in range(L + 1)], qtilde=qt, var_qtilde=vq, bias=bias, err=err,
+                alpha=alpha, beta=beta, rounds=rounds, stats=stats[:L + 1])

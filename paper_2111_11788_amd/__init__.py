@@ -28,7 +28,7 @@ KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "
 # exported symbols of include/mlmc.h (checked by the CPU test suite)
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
            "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_vcycle", "mlmc_solve", "mlmc_qoi",
-           "mlmc_sample_level", "mlmc_estimate", "mlmc_get_estimate", "mlmc_reset_stats",
+           "mlmc_sample_level", "mlmc_estimate", "mlmc_estimate_adaptive", "mlmc_get_estimate", "mlmc_reset_stats",
            "mlmc_set_profiling", "mlmc_kernel_time", "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
            "mlmc_serve_start", "mlmc_serve_stop", "mlmc_submit", "mlmc_submit_batch", "mlmc_poll", "mlmc_drain",
            "mlmc_serve_stats"]
@@ -91,6 +91,17 @@ class EstimateOpts(ctypes.Structure):
                 ("extra_fraction", ctypes.c_double), ("max_rounds", ctypes.c_int32)]
 
 
+class AdaptiveOpts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("l0", ctypes.c_int32), ("n_pilot", ctypes.c_int32),
+                ("cost_model", ctypes.c_int32), ("max_rounds", ctypes.c_int32), ("extra_fraction", ctypes.c_double),
+                ("alpha0", ctypes.c_double), ("beta0", ctypes.c_double)]
+
+
+class AdaptiveInfo(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("rounds", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("bias", ctypes.c_double), ("err", ctypes.c_double)]
+
+
 class EstimateOut(ctypes.Structure):
     _fields_ = [("qtilde", ctypes.c_double), ("var_qtilde", ctypes.c_double), ("levels", ctypes.c_int32),
                 ("level", LevelStats * 16)]
@@ -124,6 +135,8 @@ def lib():
         "mlmc_sample_level": (ctypes.c_int, [P, I32, U64, U64, P, P, P, P]),
         "mlmc_get_estimate": (ctypes.c_int, [P, ctypes.POINTER(EstimateOut)]),
         "mlmc_estimate": (ctypes.c_int, [P, ctypes.POINTER(EstimateOpts), P, ctypes.POINTER(EstimateOut)]),
+        "mlmc_estimate_adaptive": (ctypes.c_int, [P, ctypes.POINTER(AdaptiveOpts), P, ctypes.POINTER(AdaptiveInfo),
+                                                  ctypes.POINTER(EstimateOut)]),
         "mlmc_reset_stats": (ctypes.c_int, [P]),
         "mlmc_set_profiling": (ctypes.c_int, [P, I32]),
         "mlmc_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
@@ -280,6 +293,19 @@ class Context:
         out = EstimateOut()
         self._check(lib().mlmc_estimate(self.h, ctypes.byref(opts), nl.ctypes.data, ctypes.byref(out)))
         return nl, self._estimate_dict(out)
+
+    def estimate_adaptive(self, eps: float, l0: int = 1, n_pilot: int = 32, cost_model: int = 0,
+                          max_rounds: int = 10, extra_fraction: float = 0.0, alpha0: float = 0.0,
+                          beta0: float = 0.0):
+        """Adaptive MLMC (mlmc_estimate_adaptive); returns (N_l, info dict, estimate dict)."""
+        opts = AdaptiveOpts(eps, l0, n_pilot, cost_model, max_rounds, extra_fraction, alpha0, beta0)
+        nl = np.zeros(self.cfg.levels, dtype=np.uint64)
+        info = AdaptiveInfo()
+        out = EstimateOut()
+        self._check(lib().mlmc_estimate_adaptive(self.h, ctypes.byref(opts), nl.ctypes.data, ctypes.byref(info),
+                                                 ctypes.byref(out)))
+        inf = dict(L=info.L, rounds=info.rounds, alpha=info.alpha, beta=info.beta, bias=info.bias, err=info.err)
+        return nl, inf, self._estimate_dict(out)
 
     def reset_stats(self):
         self._check(lib().mlmc_reset_stats(self.h))

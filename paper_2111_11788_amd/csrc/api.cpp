@@ -296,6 +296,141 @@ int mlmc_autotune(mlmc_ctx* ctx, int32_t level, int32_t batch, mlmc_tuning* best
   return MLMC_OK;
 }
 
+namespace {
+
+// (c, r) of vals_l ~ c s^(-r l) over l = 1..lmax: least squares of log_s
+// when two or more levels exist (r clamped to [lo, hi], c refitted for the
+// clamped r), else r = dflt through the one level (Sec. 2.3: c and alpha
+// estimated from the level means).  Same operation order as the oracle.
+void decay_rate(const std::vector<double>& vals, int lmax, double dflt, double lo, double hi, double s, double* c,
+                double* r) {
+  const double ls = std::log(s);
+  std::vector<double> x, y;
+  for (int l = 1; l <= lmax; ++l) {
+    x.push_back((double)l);
+    y.push_back(std::log(std::max(std::fabs(vals[l]), 1e-300)) / ls);
+  }
+  const double m = (double)x.size();
+  double rr = dflt;
+  if (x.size() >= 2) {
+    double xm = 0.0, ym = 0.0;
+    for (size_t i = 0; i < x.size(); ++i) xm += x[i];
+    for (size_t i = 0; i < y.size(); ++i) ym += y[i];
+    xm /= m;
+    ym /= m;
+    double sxx = 0.0, sxy = 0.0;
+    for (size_t i = 0; i < x.size(); ++i) sxx += (x[i] - xm) * (x[i] - xm);
+    for (size_t i = 0; i < x.size(); ++i) sxy += (x[i] - xm) * (y[i] - ym);
+    rr = -sxy / sxx;
+    if (lo <= rr && rr <= hi) {
+      *r = rr;
+      *c = std::pow(s, ym + rr * xm);
+      return;
+    }
+    rr = std::min(std::max(rr, lo), hi);
+  }
+  double logc = 0.0;
+  for (size_t i = 0; i < x.size(); ++i) logc += y[i] + rr * x[i];
+  logc /= m;
+  *r = rr;
+  *c = std::pow(s, logc);
+}
+
+}  // namespace
+
+int mlmc_estimate_adaptive(mlmc_ctx* ctx, const mlmc_adaptive_opts* o, uint64_t* n_per_level,
+                           mlmc_adaptive_info* info, mlmc_estimate_out* out) {
+  if (!ctx) return MLMC_E_INVALID;
+  if (ctx->server) FAIL(MLMC_E_INVALID, "the context is serving");
+  const int M = ctx->cfg.levels;
+  if (!o || !(o->eps > 0.0) || o->l0 < 1 || o->l0 >= M || o->n_pilot < 2 || o->cost_model < 0 ||
+      o->cost_model > 1 || o->max_rounds < 0 || !(o->extra_fraction >= 0.0) || o->alpha0 < 0.0 || o->beta0 < 0.0)
+    FAIL(MLMC_E_INVALID, "bad adaptive estimate options");
+  const double s = 2.0, ls = std::log(s);
+  const double alpha0 = o->alpha0 > 0.0 ? o->alpha0 : 2.0, beta0 = o->beta0 > 0.0 ? o->beta0 : 4.0;
+  auto dof_cost = [&](int l) {
+    const int nf = ctx->cfg.n0 << l;
+    return dofs(nf) + (l > 0 ? dofs(nf / 2) : 0.0);
+  };
+  // measured: seconds per sample; a level not timed yet scales the finest
+  // timed level by the DOF ratio
+  auto cost_of = [&](int l) {
+    if (o->cost_model == 1) return dof_cost(l);
+    const Running& r = ctx->stats[l];
+    if (r.timed) return r.seconds / (double)r.timed;
+    for (int k = M - 1; k >= 0; --k)
+      if (ctx->stats[k].timed) return ctx->stats[k].seconds / (double)ctx->stats[k].timed * dof_cost(l) / dof_cost(k);
+    return dof_cost(l);
+  };
+  int L = o->l0;
+  std::vector<uint64_t> target(M, 0);
+  for (int l = 0; l <= L; ++l) target[l] = std::max<uint64_t>(ctx->stats[l].n, (uint64_t)o->n_pilot);
+  double alpha = 0.0, beta = 0.0, bias = 0.0, err = 0.0;
+  int rounds = 0;
+  for (int rnd = 0; rnd <= o->max_rounds; ++rnd) {
+    rounds = rnd + 1;
+    for (int l = 0; l <= L; ++l) {
+      const uint64_t have = ctx->stats[l].n;
+      if (target[l] > have) {
+        const uint64_t need = target[l] - have;
+        std::vector<double> y(need), qf(need), qc(need);
+        const int rc = mlmc_sample_level(ctx, l, ctx->stats[l].next, need, y.data(), qf.data(), qc.data(), nullptr);
+        if (rc != MLMC_OK && rc != MLMC_E_NOCONV) return rc;
+      }
+    }
+    std::vector<double> mean(M), var(M);
+    for (int l = 0; l < M; ++l) {
+      const Running& r = ctx->stats[l];
+      mean[l] = r.mean;
+      var[l] = r.n ? r.m2 / (double)r.n : 0.0;
+    }
+    double cY = 0.0, cV = 0.0;
+    decay_rate(mean, L, alpha0, 0.5, 4.0, s, &cY, &alpha);
+    decay_rate(var, L, beta0, 0.5, 8.0, s, &cV, &beta);
+    const double tail = std::pow(s, alpha) - 1.0;
+    bias = cY * std::pow(s, -alpha * L) / tail;
+    double vq = 0.0;
+    for (int l = 0; l <= L; ++l) vq += var[l] / (double)ctx->stats[l].n;
+    err = std::sqrt(bias * bias + vq);
+    if (err <= o->eps || rnd == o->max_rounds) break;
+    // eq. mlmc_num_levels with c / (s^alpha - 1), L only grows
+    const int want_L = (int)std::ceil(std::log(std::sqrt(2.0) * (cY / tail) / o->eps) / ls / alpha);
+    const int L_new = std::min(M - 1, std::max(L, want_L));
+    std::vector<double> V(L_new + 1), C(L_new + 1);
+    for (int l = 0; l <= L_new; ++l) {
+      V[l] = l <= L ? var[l] : cV * std::pow(s, -beta * l);
+      C[l] = cost_of(l);
+    }
+    double tot = 0.0;
+    for (int l = 0; l <= L_new; ++l) tot += std::sqrt(V[l] * C[l]);
+    bool grow = L_new > L;
+    for (int l = 0; l <= L_new; ++l) {
+      const double nl = 2.0 / (o->eps * o->eps) * std::sqrt(V[l] / C[l]) * tot * (1.0 + o->extra_fraction);
+      const uint64_t want = std::max<uint64_t>((uint64_t)std::ceil(nl), (uint64_t)o->n_pilot);
+      if (want > target[l]) {
+        target[l] = want;
+        grow = true;
+      }
+    }
+    L = L_new;
+    if (!grow) break;
+  }
+  for (int l = 0; l < M; ++l) {
+    if (l <= L) ctx->stats[l].cost = cost_of(l);
+    if (n_per_level) n_per_level[l] = l <= L ? ctx->stats[l].n : 0;
+  }
+  if (info) {
+    info->L = L;
+    info->rounds = rounds;
+    info->alpha = alpha;
+    info->beta = beta;
+    info->bias = bias;
+    info->err = err;
+  }
+  if (out) return mlmc_get_estimate(ctx, out);
+  return MLMC_OK;
+}
+
 int mlmc_get_estimate(const mlmc_ctx* ctx, mlmc_estimate_out* out) {
   if (!ctx || !out) return MLMC_E_INVALID;
   std::memset(out, 0, sizeof(*out));

@@ -330,3 +330,25 @@ def test_autotune_keeps_parity(dev):
     assert np.all(np.abs(qc - qco) <= 1e-7 * np.abs(qco))
     with pytest.raises(mm.MLMCError):
         ctx.set_tuning(cheb_degree=0)
+
+
+def test_estimate_adaptive_matches_oracle(dev):
+    # adaptive MLMC from L = 1 on the 4^3 / 8^3 / 16^3 meshes with the
+    # deterministic DOF cost model: the loop grows L to 2 and makes the same
+    # decisions (L, N_l) as the oracle's loop; the estimator agrees to the
+    # fp64 solve tolerance
+    wl = _wl(n0=4, levels=3, sigma2=0.25, n_modes=8, corr_len=0.5, solver=0, rtol=1e-12, batch=128, precision=0)
+    eps = 4e-4
+    ctx = mm.Context(wl, arena_bytes=256 << 20)
+    nl, info, est = ctx.estimate_adaptive(eps, l0=1, n_pilot=8, cost_model=1, max_rounds=6)
+    want = omlmc.estimate_adaptive(wl, eps, 1, 8, max_rounds=6)
+    assert info["L"] == want["L"] == 2
+    assert [int(x) for x in nl[:3]] == want["n_per_level"]
+    assert info["rounds"] == want["rounds"]
+    assert abs(est["qtilde"] - want["qtilde"]) <= 1e-8 * abs(want["qtilde"])
+    for k in ("alpha", "beta", "bias", "err"):
+        assert info[k] == pytest.approx(want[k], rel=1e-6), k
+    assert est["var_qtilde"] == pytest.approx(want["var_qtilde"], rel=1e-6)
+    assert info["err"] <= eps
+    with pytest.raises(mm.MLMCError):
+        ctx.estimate_adaptive(eps, l0=3)

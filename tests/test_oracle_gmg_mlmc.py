@@ -161,3 +161,81 @@ def test_c1_variance_decays_with_level():
     assert v[1] < v[0] / 4 and v[2] < v[1] / 4
     assert 0.0 < qt < 0.05
     assert vq == pytest.approx(sum(s.var / s.n for s in stats))
+
+
+# ---------------------------------------------------------------- adaptive MLMC
+# The adaptive loop (Sec. 2.3, adaptive loop of Alg. dyn_par_sched) pinned on a
+# synthetic level model whose means and variances decay at known rates, so the
+# level eq. mlmc_num_levels must choose and the allocation of
+# eq. mlmc_num_samples are fixed by the model rather than by the FE path.
+
+class _LevelSet:
+    def __init__(self, levels):
+        self.levels = levels
+
+
+def _model(c=0.1, alpha=2.0, v=1e-4, beta=4.0, s=2.0, q0=0.5):
+    def mean(l):
+        return q0 if l == 0 else c * s ** (-alpha * l)
+
+    def sd(l):
+        return math.sqrt(v * s ** (-beta * l))
+
+    def sampler(l, first, count):
+        return np.array([mean(l) + sd(l) * np.random.default_rng([l, first + i]).standard_normal()
+                         for i in range(count)])
+    return sampler
+
+
+def test_fit_decay_recovers_geometric_rates():
+    for c, r in ((3.0, 2.0), (0.02, 1.3), (5e-5, 4.5)):
+        lv = [1, 2, 3, 4]
+        cc, rr = mlmc.fit_decay([c * 2.0 ** (-r * l) for l in lv], lv)
+        assert rr == pytest.approx(r, rel=1e-12) and cc == pytest.approx(c, rel=1e-12)
+
+
+def test_rate_clamped_and_single_level():
+    # a flat sequence clamps to the lower bound; c then fits the points for it
+    c, r = mlmc._rate([0.0, 1.0, 1.0, 1.0], 3, 2.0, 0.5, 4.0, 2.0)
+    assert r == 0.5 and c == pytest.approx(2.0 ** (0.5 * 2), rel=1e-12)
+    # one difference level: the default rate through that point
+    c, r = mlmc._rate([0.0, 0.3], 1, 2.0, 0.5, 4.0, 2.0)
+    assert r == 2.0 and c == pytest.approx(0.3 * 4.0, rel=1e-12)
+
+
+def test_adaptive_loop_finds_the_level_of_a_known_model():
+    c, alpha, eps = 0.1, 2.0, 1e-3
+    cost = lambda l: 8.0 ** l
+    r = mlmc.estimate_adaptive(_LevelSet(7), eps, 1, 16, max_rounds=10, sampler=_model(c, alpha), cost=cost)
+    # the first level whose tail bias c s^-aL / (s^a - 1) is within eps / sqrt(2)
+    lstar = min(L for L in range(1, 7) if c * 2.0 ** (-alpha * L) / (2.0 ** alpha - 1) <= eps / math.sqrt(2))
+    assert lstar == 3
+    assert r["L"] == lstar and r["err"] <= eps
+    assert r["alpha"] == pytest.approx(alpha, abs=0.1) and r["beta"] == pytest.approx(4.0, abs=0.5)
+    assert r["bias"] == pytest.approx(c * 2.0 ** (-alpha * lstar) / 3.0, rel=0.1)
+    # the statistical half meets eps^2 / 2 (eq. mlmc_num_samples) up to the estimation noise
+    assert r["var_qtilde"] <= 1.2 * eps ** 2 / 2
+    # the telescoping sum estimates E(Q_L) of the model
+    want = 0.5 + sum(c * 2.0 ** (-alpha * l) for l in range(1, lstar + 1))
+    assert abs(r["qtilde"] - want) <= 4 * math.sqrt(r["var_qtilde"])
+    # N_l is eq. mlmc_num_samples on the final variances (targets only grow)
+    V = [s.var for s in r["stats"]]
+    C = [cost(l) for l in range(lstar + 1)]
+    tot = sum(math.sqrt(v * cc) for v, cc in zip(V, C))
+    for l in range(lstar + 1):
+        n_eq = 2.0 / eps ** 2 * math.sqrt(V[l] / C[l]) * tot
+        assert r["n_per_level"][l] >= min(n_eq, 16) * 0.8
+
+
+def test_adaptive_loop_stops_at_the_largest_mesh():
+    # three meshes only: the bias of L = 2 stays above eps, so the loop ends
+    # there with the statistical part met and no level left to add
+    eps = 1e-3
+    r = mlmc.estimate_adaptive(_LevelSet(3), eps, 1, 16, max_rounds=10, sampler=_model(), cost=lambda l: 8.0 ** l)
+    assert r["L"] == 2 and r["err"] > eps and r["rounds"] < 11
+    assert r["var_qtilde"] <= 1.2 * eps ** 2 / 2
+
+
+def test_adaptive_loop_rejects_a_first_level_without_differences():
+    with pytest.raises(ValueError):
+        mlmc.estimate_adaptive(_LevelSet(3), 1e-3, 0, 16, sampler=_model())
