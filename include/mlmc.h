@@ -78,7 +78,9 @@ typedef struct mlmc_config {
   int32_t precision;   /* MLMC_PREC_* */
   int32_t solver;      /* MLMC_SOLVER_* */
   int32_t cheb_degree; /* Chebyshev smoothing degree per half V-cycle, 1..8 (0: 2) */
-  int32_t max_batch;   /* largest number of samples solved together, >= 1 */
+  int32_t max_batch;   /* samples solved together on the finest mesh, >= 1; a coarser level takes
+                          as many as cost the same interior DOFs (at most 65536, and what the
+                          arena holds) */
   void* arena;         /* device memory owned by the caller, 256-byte aligned */
   size_t arena_bytes;  /* size of the arena: the HBM budget of the context */
   void* stream;        /* hipStream_t for all device work of the context */
@@ -185,7 +187,9 @@ int mlmc_qoi(mlmc_ctx* ctx, int32_t n, int64_t count, const double* u, double* q
  * doubles; iters (host, may be NULL) gets the fine-mesh iteration counts.
  * The samples are also folded into the context's running statistics of the
  * level (count, mean, M2 by the Chan et al. merge in sample order).
- * Work is split into batches of at most max_batch samples.
+ * Work is split into batches: max_batch samples on the finest configured
+ * mesh, proportionally more on coarser levels (same DOFs per batch, at most
+ * 65536 samples, what the arena holds; never fewer than max_batch).
  * Errors: MLMC_E_NOMEM if the arena cannot hold one batch, MLMC_E_NOCONV. */
 int mlmc_sample_level(mlmc_ctx* ctx, int32_t level, uint64_t first, uint64_t count,
                       double* y, double* q_fine, double* q_coarse, int32_t* iters);

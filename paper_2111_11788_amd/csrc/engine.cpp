@@ -635,6 +635,33 @@ int qoi_impl(mlmc_ctx* ctx, SolveState& S, int n, int B, const double* u, double
 
 bool mesh_of_config(const mlmc_ctx* ctx, int n) { return ctx->d_tab.count(n) > 0; }
 
+// Batch size of a level (dynamic batch size): max_batch samples on the finest
+// configured mesh and, on a coarser level, as many samples as take the same
+// number of DOFs (at most kMaxLevelBatch, and halved while the arena cannot
+// hold the batch), so the small meshes of the coarse levels are not solved in
+// launch-bound slices of max_batch samples.  Never below max_batch (or the
+// remaining count): the arena must hold that much, as before.
+int level_batch(mlmc_ctx* ctx, int level, uint64_t remaining) {
+  const int top = ctx->cfg.levels - 1;
+  auto pair = [&](int l) {
+    const int nf = ctx->cfg.n0 << l;
+    return dofs(nf) + (l > 0 ? dofs(nf / 2) : 0.0);
+  };
+  const uint64_t base = std::min<uint64_t>(remaining, (uint64_t)ctx->cfg.max_batch);
+  double cap = (double)ctx->cfg.max_batch * std::max(1.0, pair(top) / pair(level));
+  cap = std::min(cap, (double)kMaxLevelBatch);
+  uint64_t B = std::max<uint64_t>(base, std::min<uint64_t>(remaining, (uint64_t)cap));
+  while (B > base) {
+    Carver dry;
+    dry.top = ctx->persistent_top;
+    BatchWork probe;
+    carve_batch(dry, probe, ctx->cfg, level, (int)B);
+    if (dry.top <= ctx->cfg.arena_bytes) break;
+    B = std::max(base, B / 2);
+  }
+  return (int)B;
+}
+
 // Draw, field, solve(s) and QoI for samples first..first+count-1 of `level`;
 // outputs to host arrays; statistics folded in when `record`.
 int run_level(mlmc_ctx* ctx, int level, uint64_t first, uint64_t count, double* y, double* q_fine, double* q_coarse,
@@ -643,7 +670,7 @@ int run_level(mlmc_ctx* ctx, int level, uint64_t first, uint64_t count, double* 
   bool all_conv = true, finite = true;
   const auto t_start = std::chrono::steady_clock::now();
   for (uint64_t done = 0; done < count;) {
-    const int B = (int)std::min<uint64_t>(count - done, (uint64_t)ctx->cfg.max_batch);
+    const int B = level_batch(ctx, level, count - done);
     if (int rc = ensure_batch_work(ctx, level, B)) return rc;
     BatchWork& w = ctx->bw;
     const uint64_t start = first + done;

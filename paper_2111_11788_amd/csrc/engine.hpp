@@ -33,6 +33,7 @@ constexpr double kChebHi = 2.0;      // Gershgorin bound of D^-1 A for this oper
 constexpr double kChebRatio = 4.0;   // smoothing interval [hi / ratio, hi]
 constexpr double kInnerRtol = 1e-4;  // fp32 inner solve tolerance (mixed precision)
 constexpr int kMaxOuter = 30;
+constexpr int kMaxLevelBatch = 65536;   // samples per batch on a coarse level (see level_batch)
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 inline int ilog2i(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
