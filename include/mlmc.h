@@ -121,6 +121,17 @@ const char* mlmc_last_error(const mlmc_ctx* ctx);
 /* Entries per sample in the grid layout of an n^3 mesh (>= (n+1) n^2). */
 size_t mlmc_grid_stride(int32_t n);
 
+/* The node numbering of the grid layout on mesh n (the interior unknowns of
+ * the Q1 space, Sec. 2.1): out (host, mlmc_grid_stride(n) entries) receives,
+ * for every position of a sample's grid vector, the interior unknown
+ * g = (i-1) + (n-1)((j-1) + (n-1)(k-1)) stored there, or -1 where the layout
+ * holds no unknown.  Computed on the device with the layout's index
+ * arithmetic, in scratch space of the arena (the cached work space is carved
+ * again by the next call that needs it).  For parity tests.
+ * Errors: MLMC_E_INVALID (n not a power of two in 2..1024, NULL out, serving),
+ * MLMC_E_NOMEM. */
+int mlmc_node_map(mlmc_ctx* ctx, int32_t n, int32_t* out);
+
 /* Arena bytes needed by mlmc_sample_level for `batch` samples of `level`
  * under the configuration (without creating a context). */
 size_t mlmc_workspace_bytes(const mlmc_config* cfg, int32_t level, int32_t batch);

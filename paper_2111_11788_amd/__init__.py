@@ -29,6 +29,7 @@ KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
            "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_vcycle", "mlmc_solve", "mlmc_qoi",
            "mlmc_sample_level", "mlmc_estimate", "mlmc_estimate_adaptive", "mlmc_get_estimate", "mlmc_reset_stats",
+           "mlmc_node_map",
            "mlmc_set_profiling", "mlmc_kernel_time", "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
            "mlmc_serve_start", "mlmc_serve_stop", "mlmc_submit", "mlmc_submit_batch", "mlmc_poll", "mlmc_drain",
            "mlmc_serve_stats"]
@@ -138,6 +139,7 @@ def lib():
         "mlmc_estimate_adaptive": (ctypes.c_int, [P, ctypes.POINTER(AdaptiveOpts), P, ctypes.POINTER(AdaptiveInfo),
                                                   ctypes.POINTER(EstimateOut)]),
         "mlmc_reset_stats": (ctypes.c_int, [P]),
+        "mlmc_node_map": (ctypes.c_int, [P, I32, P]),
         "mlmc_set_profiling": (ctypes.c_int, [P, I32]),
         "mlmc_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
         "mlmc_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
@@ -309,6 +311,12 @@ class Context:
 
     def reset_stats(self):
         self._check(lib().mlmc_reset_stats(self.h))
+
+    def node_map(self, n: int) -> np.ndarray:
+        """The device's interior-unknown number at every grid position of mesh n (-1: none)."""
+        out = np.empty(grid_stride(n), dtype=np.int32)
+        self._check(lib().mlmc_node_map(self.h, n, out.ctypes.data))
+        return out
 
     def tuning(self) -> dict:
         t = Tuning()

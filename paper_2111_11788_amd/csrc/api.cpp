@@ -115,6 +115,26 @@ size_t mlmc_workspace_bytes(const mlmc_config* cfg, int32_t level, int32_t batch
   return dry.top;
 }
 
+int mlmc_node_map(mlmc_ctx* ctx, int32_t n, int32_t* out) {
+  if (!ctx) return MLMC_E_INVALID;
+  if (ctx->server) FAIL(MLMC_E_INVALID, "the context is serving");
+  if (n < 2 || n > 1024 || !is_pow2(n) || !out) FAIL(MLMC_E_INVALID, "bad node map arguments");
+  const size_t S = grid_stride(n);
+  if (ctx->persistent_top + align256(S * sizeof(int32_t)) > ctx->cfg.arena_bytes)
+    FAIL(MLMC_E_NOMEM, "arena too small for the node map");
+  // scratch right after the persistent tables: the cached work space there is
+  // dropped and carved (and cleared) again when next needed
+  ctx->sw.release_graphs();
+  ctx->bw.wf.release_graphs();
+  ctx->bw.wc.release_graphs();
+  ctx->ws_kind = -1;
+  int32_t* d = reinterpret_cast<int32_t*>((char*)ctx->cfg.arena + ctx->persistent_top);
+  LAUNCH(MLMC_K_MISC, 0, launch_node_map(n, d, ctx->st));
+  HIPCHK(hipMemcpyAsync(out, d, S * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return MLMC_OK;
+}
+
 int mlmc_modes(const mlmc_ctx* ctx, int32_t* triples, double* lambda) {
   if (!ctx) return MLMC_E_INVALID;
   const int M = ctx->cfg.n_modes;

@@ -33,6 +33,12 @@ inline ZGeom zgeom(int n, int B) {
   constexpr int V = ZV<T>::V;
   g.n = n;
   g.G = n / V;
+  if (g.G < 1) {   // a row narrower than one vector: no z-march geometry (callers check G)
+    g.rows = 0;
+    g.row_blocks = 0;
+    g.zlen = 0;
+    return g;
+  }
   const int rowthreads = (n - 1) * g.G;
   g.threads = rowthreads >= 256 ? 256 : ((rowthreads + 63) / 64) * 64;
   g.rows = g.threads / g.G;

@@ -212,6 +212,8 @@ enum ReduceOp : int {
 hipError_t launch_reduce(int B, int op, double tol2, uint32_t nparts, SolveState s, double* out,
                          hipStream_t st);
 hipError_t launch_count_active(int B, SolveState s, hipStream_t st);
+// out[p] (one sample's grid stride) = interior unknown at position p, or -1
+hipError_t launch_node_map(int n, int32_t* out, hipStream_t st);
 // out[0] = number of b < B with mask[b] != 0 (one workgroup)
 hipError_t launch_count_mask(const int* mask, int B, int* out, hipStream_t st);
 hipError_t launch_set_active(int B, SolveState s, int value, hipStream_t st);

@@ -326,6 +326,18 @@ __global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t
   }
 }
 
+// out[p] = the interior unknown at grid position p of a sample, or -1
+__global__ void __launch_bounds__(kBlock) k_node_map(int n, size_t stride, int32_t* __restrict__ out) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= stride) return;
+  const size_t n2 = (size_t)n * n;
+  const int i = (int)(p % n), j = (int)((p / n) % n);
+  const size_t k = p / n2;
+  const int m = n - 1;
+  const bool interior = i >= 1 && j >= 1 && k >= 1 && k <= (size_t)m;
+  out[p] = interior ? (int32_t)((i - 1) + (size_t)m * ((j - 1) + (size_t)m * (k - 1))) : -1;
+}
+
 // per-slot masks of the serving phases
 __global__ void k_phase_masks(int S, const int* __restrict__ phase, int* __restrict__ inner, int* __restrict__ trans,
                               int* __restrict__ restart, int* __restrict__ done) {
@@ -463,6 +475,12 @@ hipError_t launch_fill_interior(int n, int B, T* v, double value, const int* act
 
 hipError_t launch_reduce(int B, int op, double tol2, uint32_t nparts, SolveState s, double* out, hipStream_t st) {
   k_reduce<<<dim3(B), kBlock, 0, st>>>(op, tol2, nparts, s, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_map(int n, int32_t* out, hipStream_t st) {
+  const size_t stride = grid_stride(n);
+  k_node_map<<<dim3((unsigned)((stride + kBlock - 1) / kBlock)), kBlock, 0, st>>>(n, stride, out);
   return hipGetLastError();
 }
 

@@ -734,7 +734,7 @@ inline size_t zlds_bytes(const ZGeom& g) {
 // a row is at most one wave (its halos move by DPP)
 template <class T, int OP = OP_PLAIN>
 inline bool zlds_ok(const ZGeom& g) {
-  return g.G <= 64 && (g.rows + 2) * g.G <= 2 * g.threads && (g.rows + 1 + 2 * ZOp<OP>::KOFF) * g.G <= 2 * g.threads &&
+  return g.G >= 1 && g.G <= 64 && (g.rows + 2) * g.G <= 2 * g.threads && (g.rows + 1 + 2 * ZOp<OP>::KOFF) * g.G <= 2 * g.threads &&
          zlds_bytes<T, OP>(g) <= 65536;
 }
 
@@ -1156,7 +1156,7 @@ inline ZGeom resr_geom(int n, int B) { return zgeom<T>(n, B); }
 // fits two vectors per thread
 template <class T, bool Z1 = false>
 inline bool resr_ok(const ZGeom& g) {
-  return g.n >= 4 && g.G <= 64 && g.rows % 2 == 0 && (g.zc == 1 || g.zlen % 2 == 0) &&
+  return g.n >= 4 && g.G >= 1 && g.G <= 64 && g.rows % 2 == 0 && (g.zc == 1 || g.zlen % 2 == 0) &&
          g.threads <= 256 && (g.rows + 3) * g.G <= 2 * g.threads && (g.rows + 2 + (Z1 ? 2 : 0)) * g.G <= 2 * g.threads &&
          (g.rows + 1) * g.G <= 2 * g.threads - (g.threads >= 192 ? g.threads / 2 : 0) && resr_bytes<T, Z1>(g) <= 65536;
 }
@@ -1496,6 +1496,7 @@ hipError_t zlaunch(int n, int B, const T* u, const T* kap, const int* active, do
                                                         st);
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
+  if (g.G < 1) return hipErrorInvalidValue;
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
   if (var & ZVAR_PREFETCH)
@@ -1519,6 +1520,7 @@ hipError_t zlaunch_addd(int n, int B, const T* u, const float* d, const T* kap, 
   }
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
+  if (g.G < 1) return hipErrorInvalidValue;
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
   k_zmarch<T, V, true, false, false, true, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(
@@ -1534,6 +1536,7 @@ hipError_t zlaunch_pro(int n, int B, const T* u, const T* xc, const T* kap, cons
     return zlaunch_lds<T, true, true, OP_PLAIN, Epi>(n, B, u, xc, kap, active, partial, pstride, epi, nparts, st);
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
+  if (g.G < 1) return hipErrorInvalidValue;
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
   k_zmarch<T, V, true, false, true, false, Epi><<<dim3(blocks), dim3(g.threads), 0, st>>>(

@@ -46,6 +46,25 @@ def test_xi_bit_exact(dev, seed, level, first, count, M):
                              f"{xi[bad][0]!r} vs {want[bad][0]!r}"
 
 
+@pytest.mark.parametrize("n", [2, 4, 8, 16, 32, 64])
+def test_node_map_bit_exact(dev, n):
+    # the device's grid layout holds interior unknown g = (i-1) + (n-1)((j-1) + (n-1)(k-1))
+    # of the oracle's numbering at position i + n j + n^2 k, and nothing elsewhere
+    ctx = mm.Context(_wl(n0=4, levels=1), arena_bytes=64 << 20)
+    got = ctx.node_map(n)
+    ijk = fe.interior_ijk(n)
+    want = np.full(mm.grid_stride(n), -1, dtype=np.int32)
+    want[ijk[:, 0] + n * ijk[:, 1] + n * n * ijk[:, 2]] = np.arange(len(ijk), dtype=np.int32)
+    assert np.array_equal(got, want)
+    # the binding's marshalling uses the same positions
+    assert np.array_equal(np.nonzero(got >= 0)[0][np.argsort(got[got >= 0])], mm.interior_positions(n))
+    # a solve after the scratch use still works (the work space is carved again)
+    if n == 8:
+        kap = ctx.field(4, ctx.draw_xi(0, 0, 2))
+        u, it = ctx.solve(4, kap)
+        assert np.all(np.isfinite(u.cpu().numpy()))
+
+
 @pytest.mark.parametrize("corr,M,sigma2", [(0.5, 8, 1.0), (0.3, 64, 1.0), (0.2, 128, 1.0), (0.1, 512, 2.0)])
 def test_modes_match_oracle(dev, corr, M, sigma2):
     ctx = mm.Context(_wl(corr_len=corr, n_modes=M, sigma2=sigma2), arena_bytes=64 << 20)
