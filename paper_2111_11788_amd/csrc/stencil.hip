@@ -242,11 +242,11 @@ struct EpiChebZero {
 
 // One LDS row segment of the u window: the thread's V values by one vector
 // read, the halos i0-1 and i0+V from the neighbouring lanes of the same row
-// (the G lanes of a row are consecutive lanes of one wave when G <= 64; the
-// row ends are the zero cells u(-1) = u(n) = 0).  With shuf false (a row
-// wider than a wave) the halos are read from LDS.  Scalar halo reads at a
-// 16-byte lane stride would put all lanes of a wave on a quarter of the LDS
-// banks.
+// (the G <= 64 lanes of a row are consecutive lanes of one wave; the row
+// ends are zero: u(-1) = u(n) = 0).  LDS rows are dense (n values, no halo
+// cells): scalar halo reads at a 16-byte lane stride would put all lanes of
+// a wave on a quarter of the LDS banks, and the padding would cost the LDS
+// that a fourth workgroup per CU needs.
 // whole-wave DPP shifts (GFX9 wave_shr:1 / wave_shl:1, full VALU rate):
 // lane l receives lane l-1 (from_prev) or lane l+1 (from_next), 0 at the ends
 __device__ __forceinline__ int dpp_prev_i(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true); }
@@ -265,29 +265,20 @@ __device__ __forceinline__ double from_next(double x) {
 }
 
 template <class T, int V>
-__device__ __forceinline__ void lds_urow(const T* row, T* dst, int gx, int G, bool shuf) {
+__device__ __forceinline__ void lds_urow(const T* row, T* dst, int gx, int G) {
   vload<T, V>(row, dst + 1);
-  if (shuf) {
-    const T l = from_prev(dst[V]);
-    const T r = from_next(dst[1]);
-    dst[0] = gx == 0 ? T(0) : l;
-    dst[V + 1] = gx == G - 1 ? T(0) : r;
-  } else {
-    dst[0] = row[-1];
-    dst[V + 1] = row[V];
-  }
+  const T l = from_prev(dst[V]);
+  const T r = from_next(dst[1]);
+  dst[0] = gx == 0 ? T(0) : l;
+  dst[V + 1] = gx == G - 1 ? T(0) : r;
 }
 
-// kappa row segment: element i0-1 (zero cell for i0 = 0) and i0 .. i0+V-1
+// kappa row segment: element i0-1 (zero for i0 = 0) and i0 .. i0+V-1
 template <class T, int V>
-__device__ __forceinline__ void lds_krow(const T* row, T* dst, int gx, int G, bool shuf) {
+__device__ __forceinline__ void lds_krow(const T* row, T* dst, int gx) {
   vload<T, V>(row, dst + 1);
-  if (shuf) {
-    const T l = from_prev(dst[V]);
-    dst[0] = gx == 0 ? T(0) : l;
-  } else {
-    dst[0] = row[-1];
-  }
+  const T l = from_prev(dst[V]);
+  dst[0] = gx == 0 ? T(0) : l;
 }
 
 // N consecutive values (N = 1 or an aligned vector)
@@ -718,10 +709,11 @@ template <int OP> struct ZOp {
   static constexpr int LEAD = OP == OP_Z1 ? 3 : 1;   // kappa plane stored at step k: k + LEAD
 };
 
+// LDS row strides: dense rows of n values (u) and n elements (kappa)
 template <class T>
-__host__ __device__ inline int zlds_urs(int n) { return n + 2 * ZV<T>::V; }
+__host__ __device__ inline int zlds_urs(int n) { return n; }
 template <class T>
-__host__ __device__ inline int zlds_krs(int n) { return n + ZV<T>::V; }
+__host__ __device__ inline int zlds_krs(int n) { return n; }
 // LDS of a k_zlds workgroup: u ring of 3 planes x (rows + 2) rows, kappa
 // ring of KP planes x (rows + 1 + 2 KOFF) rows
 template <class T, int OP = OP_PLAIN>
@@ -746,7 +738,7 @@ inline bool zlds_ok(const ZGeom& g) {
 // the lanes of a row, which is what the DPP halo exchange needs.
 template <class T, int V>
 __device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int KRS, int krow0, int s0, int s1, int jj,
-                                        int kk, int n, int c, int G, bool shuf, T h, T c2) {
+                                        int kk, int n, int c, T h, T c2) {
   if (jj < 1 || jj > n - 1 || kk < 1 || kk > n - 1) {
 #pragma unroll
     for (int v = 0; v < V; ++v) u[v] = T(0);
@@ -763,7 +755,7 @@ __device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int KRS, int 
 #pragma unroll
     for (int dy = 0; dy < 2; ++dy) {
       T K[V + 1];
-      lds_krow<T, V>(Kl + (sl[dz] * KR + jj - 1 + dy - krow0) * KRS + V + c * V, K, c, G, shuf);
+      lds_krow<T, V>(Kl + (sl[dz] * KR + jj - 1 + dy - krow0) * KRS + c * V, K, c);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         ks[v] += K[v];
@@ -815,7 +807,6 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   const int j = j0 + jr, i0 = gx * V;
   const bool valid = jr < R && j <= n - 1 && k0 < k1;
   // a row fits in one wave (zlds_ok): halos by DPP, no branch in the gather
-  constexpr bool shuf = true;
   const T* ub = (NEED_U && u) ? u + (size_t)b * stride : nullptr;
   if (NEED_U && op.ustate && (op.ustate[b] & 8)) ub = op.u1 + (size_t)b * stride;
   const float* db = ADDD ? op.d + (size_t)b * stride : nullptr;
@@ -846,13 +837,6 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
     }
   }
   if constexpr (Epi::kBegin) epi.begin(b);
-
-  // zero cells (i = -1, i = n of u; ex = -1 of kappa) of every ring row
-  for (int q = tid; q < 3 * UR; q += nthr) {
-    Ul[q * URS + V - 1] = T(0);
-    Ul[q * URS + V + n] = T(0);
-  }
-  for (int q = tid; q < KP * KR; q += nthr) Kl[q * KRS + V - 1] = T(0);
 
   // staging: up to two 16-byte vectors per thread per plane for u and kappa;
   // a thread stages the same (row, column) positions on every plane
@@ -941,7 +925,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
           T w[V];
 #pragma unroll
           for (int t = 0; t < V; ++t) w[t] = pu[m][t];
-          z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, G, shuf, h, op.c2);
+          z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, h, op.c2);
 #pragma unroll
           for (int t = 0; t < V; ++t) pu[m][t] = w[t];
         }
@@ -975,7 +959,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
     for (int m = 0; m < 2; ++m) {
       const int v = uv(m);
       const int r = v / G, c = v - (v / G) * G;
-      if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + V + c * V) = pu[m];
+      if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + c * V) = pu[m];
     }
   };
   auto store_u = [&](int slot, int kk) {
@@ -1000,7 +984,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
       const int r = v / G, c = v - (v / G) * G;
       const int ey = krow0 + r;
       if (v < KR * G && ey >= 0 && ey <= n - 1)
-        *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + V + c * V) = pk[m];
+        *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + c * V) = pk[m];
     }
   };
 
@@ -1052,7 +1036,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
           for (int dy = 0; dy < 2; ++dy)
-            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy + KOFF) * KRS + V + i0, K[dz][dy], gx, G, shuf);
+            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy + KOFF) * KRS + i0, K[dz][dy], gx);
         T far[V], ksum[V], uc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1069,10 +1053,10 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         if (NEED_U) {
 #pragma unroll
           for (int sz = 0; sz < 2; ++sz) {
-            const T* P = Ul + ((sz ? sp : sm) * UR + jr) * URS + V + i0;
+            const T* P = Ul + ((sz ? sp : sm) * UR + jr) * URS + i0;
             T R[3][V + 2];
 #pragma unroll
-            for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + dy * URS, R[dy], gx, G, shuf);
+            for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + dy * URS, R[dy], gx, G);
 #pragma unroll
             for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -1082,11 +1066,11 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
                   far[v] += K[sz][sy][v + sx] * (R[1][v + 2 * sx] + (R[2 * sy][v + 1] + R[2 * sy][v + 2 * sx]));
           }
           {
-            const T* P = Ul + (s0 * UR + jr) * URS + V + i0;
+            const T* P = Ul + (s0 * UR + jr) * URS + i0;
             T R0[V + 2], R2[V + 2];
-            lds_urow<T, V>(P, R0, gx, G, shuf);
+            lds_urow<T, V>(P, R0, gx, G);
             vload<T, V>(P + URS, uc);
-            lds_urow<T, V>(P + 2 * URS, R2, gx, G, shuf);
+            lds_urow<T, V>(P + 2 * URS, R2, gx, G);
 #pragma unroll
             for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -1181,8 +1165,13 @@ struct ResrUpd {
 template <class T>
 __device__ __forceinline__ T rupd(T r, T a, T q) { return fma(-a, q, r); }
 
+// fp32 without the update: held to 128 VGPRs (no spill), so that four
+// workgroups fit a CU with the 39 KB of LDS of the pre-smoothed form
 template <class T, int V, bool Z1, bool UPD>
-__global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const T* __restrict__ x,
+constexpr int resr_min_waves() { return sizeof(T) == 4 && !UPD ? 4 : 1; }
+
+template <class T, int V, bool Z1, bool UPD>
+__global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr(ZGeom g, size_t stride, T h, const T* __restrict__ x,
                                               const T* __restrict__ bf, const T* __restrict__ kap,
                                               const int* __restrict__ active, T* __restrict__ bc, size_t cstride,
                                               T c2, ResrUpd<T> upd) {
@@ -1215,7 +1204,6 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
   // halos by DPP (a row fits in one wave: resr_ok); with the extra rows of a
   // tile spread over the waves this measured faster than LDS halo reads
   // (8.7 vs 9.4 ms per 64^3 x 1024 step)
-  constexpr bool shuf = true;
   const T* ub = (Z1 ? bf : x) + (size_t)b * stride;
   const T* bb = bf + (size_t)b * stride;
   const T* kb = kap + (size_t)b * n2 * n;
@@ -1238,12 +1226,6 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
     rnb = (par ? const_cast<T*>(bf) : upd.r1) + (size_t)b * stride;
   }
   double racc = 0.0;   // UPD: sum of r . r over the tile's own nodes
-
-  for (int q = tid; q < 3 * UR; q += nthr) {
-    Ul[q * URS + V - 1] = T(0);
-    Ul[q * URS + V + n] = T(0);
-  }
-  for (int q = tid; q < KP * KR; q += nthr) Kl[q * KRS + V - 1] = T(0);
 
   vt pu[2], pk[2], pq[UPD ? 2 : 1];
   // staged u vector m: extras on the last threads (see k_zlds)
@@ -1275,7 +1257,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
         T w[V];
 #pragma unroll
         for (int t = 0; t < V; ++t) w[t] = (UPD && upd_on) ? rupd(pu[m][t], ua, pq[UPD ? m : 0][t]) : pu[m][t];
-        z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, G, true, h, c2);
+        z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, h, c2);
 #pragma unroll
         for (int t = 0; t < V; ++t) pu[m][t] = w[t];
       }
@@ -1286,7 +1268,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
     for (int m = 0; m < 2; ++m) {
       const int v = uv(m);
       const int r = v / G, c = v - (v / G) * G;
-      if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + V + c * V) = pu[m];
+      if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + c * V) = pu[m];
     }
   };
   auto store_u = [&](int slot, int kk) {
@@ -1311,7 +1293,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
       const int r = v / G, c = v - (v / G) * G;
       const int ey = krow0 + r;
       if (v < KR * G && ey >= 0 && ey <= n - 1)
-        *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + V + c * V) = pk[m];
+        *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + c * V) = pk[m];
     }
   };
 
@@ -1365,7 +1347,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
           for (int dy = 0; dy < 2; ++dy)
-            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy + KOFF) * KRS + V + i0, K[dz][dy], gx, G, shuf);
+            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy + KOFF) * KRS + i0, K[dz][dy], gx);
         T far[V], ksum[V], uc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1380,10 +1362,10 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
         }
 #pragma unroll
         for (int sz = 0; sz < 2; ++sz) {
-          const T* P = Ul + ((sz ? sp : sm) * UR + jr) * URS + V + i0;
+          const T* P = Ul + ((sz ? sp : sm) * UR + jr) * URS + i0;
           T Rw[3][V + 2];
 #pragma unroll
-          for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + dy * URS, Rw[dy], gx, G, shuf);
+          for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + dy * URS, Rw[dy], gx, G);
 #pragma unroll
           for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -1393,11 +1375,11 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
                 far[v] += K[sz][sy][v + sx] * (Rw[1][v + 2 * sx] + (Rw[2 * sy][v + 1] + Rw[2 * sy][v + 2 * sx]));
         }
         {
-          const T* P = Ul + (s0 * UR + jr) * URS + V + i0;
+          const T* P = Ul + (s0 * UR + jr) * URS + i0;
           T R0[V + 2], R2[V + 2];
-          lds_urow<T, V>(P, R0, gx, G, shuf);
+          lds_urow<T, V>(P, R0, gx, G);
           vload<T, V>(P + URS, uc);
-          lds_urow<T, V>(P + 2 * URS, R2, gx, G, shuf);
+          lds_urow<T, V>(P + 2 * URS, R2, gx, G);
 #pragma unroll
           for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -1428,7 +1410,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
           const T au = h * (ksum[v] * uc[v] * third - far[v] * twelfth);
           t[v] = (i0 + v) != 0 ? bv[v] - au : T(0);
         }
-        vstore<T, V>(Tl + jr * URS + V + i0, t);
+        vstore<T, V>(Tl + jr * URS + i0, t);
       }
       if (kk + 1 <= kt1) prep_u(kk + 2);   // kappa planes kk+1, kk+2 are in the ring
       __syncthreads();
@@ -1439,7 +1421,7 @@ __global__ void __launch_bounds__(256) k_resr(ZGeom g, size_t stride, T h, const
           const int jr = 2 * cJ - j0;   // tile row of fine row 2J
 #pragma unroll
           for (int dy = -1; dy <= 1; ++dy) {
-            const T* row = Tl + (jr + dy) * URS + V + 2 * cI;
+            const T* row = Tl + (jr + dy) * URS + 2 * cI;
             r2 += (dy == 0 ? T(1) : T(0.5)) * (T(0.5) * (row[-1] + row[1]) + row[0]);
           }
         }
