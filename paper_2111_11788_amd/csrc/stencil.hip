@@ -288,6 +288,12 @@ __device__ __forceinline__ void nload(const T* p, T* dst) {
   else vload<T, N>(p, dst);
 }
 
+template <class T, int N>
+__device__ __forceinline__ void nstore(T* p, const T* src) {
+  if constexpr (N == 1) p[0] = src[0];
+  else vstore<T, N>(p, src);
+}
+
 // PCG update fused with the first Chebyshev step (zero iterate) of the
 // preconditioner that follows it: x += alpha p, r -= alpha q, sum r.r, and
 // z = c2 D^-1 r with the updated r (needs only the kappa window).
@@ -709,25 +715,30 @@ template <int OP> struct ZOp {
   static constexpr int LEAD = OP == OP_Z1 ? 3 : 1;   // kappa plane stored at step k: k + LEAD
 };
 
-// LDS row strides: dense rows of n values (u) and n elements (kappa)
+// LDS row strides: dense rows of n values (u) and n elements (kappa); the
+// kernels index rows by shifts, n being a power of two
 template <class T>
 __host__ __device__ inline int zlds_urs(int n) { return n; }
 template <class T>
 __host__ __device__ inline int zlds_krs(int n) { return n; }
 // LDS of a k_zlds workgroup: u ring of 3 planes x (rows + 2) rows, kappa
-// ring of KP planes x (rows + 1 + 2 KOFF) rows
-template <class T, int OP = OP_PLAIN>
+// ring of KP planes x (rows + 1 + 2 KOFF) rows; with the fused prolongation
+// a ring of 2 coarse planes x (rows / 2 + 2) rows of n / 2 values
+template <class T>
+__host__ __device__ inline int zlds_crows(int rows) { return rows / 2 + 2; }
+template <class T, int OP = OP_PLAIN, bool PRO = false>
 inline size_t zlds_bytes(const ZGeom& g) {
   return ((size_t)3 * (g.rows + 2) * zlds_urs<T>(g.n) +
-          (size_t)ZOp<OP>::KP * (g.rows + 1 + 2 * ZOp<OP>::KOFF) * zlds_krs<T>(g.n)) * sizeof(T);
+          (size_t)ZOp<OP>::KP * (g.rows + 1 + 2 * ZOp<OP>::KOFF) * zlds_krs<T>(g.n) +
+          (PRO ? (size_t)2 * zlds_crows<T>(g.rows) * (g.n / 2) : 0)) * sizeof(T);
 }
 // the staging covers every row with two vectors per thread
 // and the rings fit the 64 KiB of LDS a workgroup may take without opting in;
 // a row is at most one wave (its halos move by DPP)
-template <class T, int OP = OP_PLAIN>
+template <class T, int OP = OP_PLAIN, bool PRO = false>
 inline bool zlds_ok(const ZGeom& g) {
-  return g.G >= 1 && g.G <= 64 && (g.rows + 2) * g.G <= 2 * g.threads && (g.rows + 1 + 2 * ZOp<OP>::KOFF) * g.G <= 2 * g.threads &&
-         zlds_bytes<T, OP>(g) <= 65536;
+  return g.G >= 1 && g.G <= 64 && (g.G & (g.G - 1)) == 0 && (g.rows + 2) * g.G <= 2 * g.threads && (g.rows + 1 + 2 * ZOp<OP>::KOFF) * g.G <= 2 * g.threads &&
+         zlds_bytes<T, OP, PRO>(g) <= 65536 && (!PRO || g.zc == 1 || g.zlen % 2 == 0);   // PRO: chunks start odd
 }
 
 // c2 D^-1 b for the V staged nodes c*V .. c*V+V-1 of row jj, plane kk, in u
@@ -737,7 +748,7 @@ inline bool zlds_ok(const ZGeom& g) {
 // step would have stored; 0 on boundary nodes.  The branch is uniform over
 // the lanes of a row, which is what the DPP halo exchange needs.
 template <class T, int V>
-__device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int KRS, int krow0, int s0, int s1, int jj,
+__device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int rsh, int krow0, int s0, int s1, int jj,
                                         int kk, int n, int c, T h, T c2) {
   if (jj < 1 || jj > n - 1 || kk < 1 || kk > n - 1) {
 #pragma unroll
@@ -755,7 +766,7 @@ __device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int KRS, int 
 #pragma unroll
     for (int dy = 0; dy < 2; ++dy) {
       T K[V + 1];
-      lds_krow<T, V>(Kl + (sl[dz] * KR + jj - 1 + dy - krow0) * KRS + c * V, K, c);
+      lds_krow<T, V>(Kl + ((sl[dz] * KR + jj - 1 + dy - krow0) << rsh) + c * V, K, c);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         ks[v] += K[v];
@@ -790,10 +801,13 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   if (active && !active[b]) return;   // uniform over the workgroup
   const int rb = (int)(part % (uint32_t)g.row_blocks), zb = (int)(part / (uint32_t)g.row_blocks);
   const int n = g.n, n2 = n * n, G = g.G, R = g.rows;
+  const int gsh = __builtin_ctz((unsigned)G);   // G is a power of two
   const int UR = R + 2, KR = R + 1 + 2 * KOFF;
   const int URS = zlds_urs<T>(n), KRS = zlds_krs<T>(n);
+  const int rsh = __builtin_ctz((unsigned)n);   // LDS rows are n values, n a power of two
   T* Ul = reinterpret_cast<T*>(zsmem);        // [3][UR][URS]:  u rows j0-1 .. j0+R
   T* Kl = Ul + 3 * UR * URS;                   // [KP][KR][KRS]: kappa rows krow0 ..
+  T* Cl = Kl + KP * KR * KRS;                  // PRO: [2][CR][n/2]: coarse rows crow0 ..
   const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
   const int j0 = 1 + rb * R;
   const int krow0 = j0 - 1 - KOFF;
@@ -803,7 +817,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   // last kappa plane staged: the computed planes need k1-1; OP_Z1 also forms
   // the operand on u plane k1
   const int kmax = Z1 ? (k1 < n - 1 ? k1 : n - 1) : k1 - 1;
-  const int gx = tid % G, jr = tid / G;
+  const int gx = tid & (G - 1), jr = tid >> gsh;
   const int j = j0 + jr, i0 = gx * V;
   const bool valid = jr < R && j <= n - 1 && k0 < k1;
   // a row fits in one wave (zlds_ok): halos by DPP, no branch in the gather
@@ -849,53 +863,38 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   // extra kappa vectors; ubase is a multiple of G, so a row stays in one wave
   const int ubase = 2 * nthr - UR * G;
   auto uv = [&](int m) { return m == 0 ? tid : (tid >= ubase ? nthr + tid - ubase : 1 << 30); };
-  // PRO: per staged vector, the coarse values I0 .. I0+V/2 of its parent rows
-  // Jlo = jj/2, Jhi = (jj+1)/2 on coarse planes cK and cK+1 (the parents of
-  // fine planes 2cK and 2cK+1), refreshed every second fine plane
-  constexpr int CQ = V / 2 + 1;
-  T CWin[2][2][2][PRO ? CQ : 1];   // [vector][plane][row][q]
-  int cK = 0;
-  auto load_cplane = [&](int slot, int K) {
+  // PRO: the coarse planes of the correction in an LDS ring of two planes
+  // (plane C in slot C & 1), rows crow0 .. crow0 + CR - 1: the parents
+  // (jj >> 1, (jj + 1) >> 1) of the staged fine rows jj = j0-1 .. j0+R.  A
+  // lane reads the V/2 coarse values under its fine vector from LDS and the
+  // next one from the neighbouring lane.  Coarse plane C is first needed by
+  // fine plane 2C-1 and last by 2C+1; it is stored in the step that stages
+  // fine plane 2C-2, over plane C-2 (last needed by fine plane 2C-3).
+  constexpr int H = V / 2;
+  const int CR = zlds_crows<T>(R), crow0 = (j0 - 1) >> 1;
+  T pc[2][PRO ? H : 1];
+  auto fetch_c = [&](int K) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const int v = uv(m);
-      const int r = v / G, c = v - (v / G) * G;
-      const int jj = j0 - 1 + r;
-      const bool use = v < UR * G && jj <= n && K <= nc;
-#pragma unroll
-      for (int jy = 0; jy < 2; ++jy) {
-        if (!use) {
-#pragma unroll
-          for (int q = 0; q < CQ; ++q) CWin[m][slot][jy][q] = T(0);
-          continue;
-        }
-        const int JJ = jy ? (jj + 1) >> 1 : jj >> 1;
-        const T* row = cb + (size_t)nc2 * K + (size_t)nc * JJ + c * (V / 2);
-        nload<T, V / 2>(row, CWin[m][slot][jy]);
-        CWin[m][slot][jy][V / 2] = row[V / 2];
-      }
+      const int v = tid + m * nthr;
+      const int r = v >> gsh, c = v & (G - 1);
+      if (v < CR * G && crow0 + r <= nc)
+        nload<T, H>(cb + (size_t)nc2 * K + (size_t)nc * (crow0 + r) + c * H, pc[m]);
     }
   };
-  if (PRO) {
-    cK = (k0 - 1) >> 1;
-    load_cplane(0, cK);
-    load_cplane(1, cK + 1);
-  }
-  auto fetch_u = [&](int kk) {
-    if (PRO && (kk >> 1) > cK) {   // fine planes are staged in increasing order
+  auto store_c = [&](int K) {
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int jy = 0; jy < 2; ++jy)
-#pragma unroll
-          for (int q = 0; q < CQ; ++q) CWin[m][0][jy][q] = CWin[m][1][jy][q];
-      ++cK;
-      load_cplane(1, cK + 1);
+    for (int m = 0; m < 2; ++m) {
+      const int v = tid + m * nthr;
+      const int r = v >> gsh, c = v & (G - 1);
+      if (v < CR * G && crow0 + r <= nc) nstore<T, H>(Cl + (((K & 1) * CR + r) << (rsh - 1)) + c * H, pc[m]);
     }
+  };
+  auto fetch_u = [&](int kk) {
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = uv(m);
-      const int r = v / G, c = v - (v / G) * G;
+      const int r = v >> gsh, c = v & (G - 1);
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) {
         const size_t off = (size_t)n2 * kk + (size_t)n * jj + c * V;
@@ -918,25 +917,38 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = uv(m);
-      const int r = v / G, c = v - (v / G) * G;
+      const int r = v >> gsh, c = v & (G - 1);
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) {
         if (Z1) {
           T w[V];
 #pragma unroll
           for (int t = 0; t < V; ++t) w[t] = pu[m][t];
-          z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, h, op.c2);
+          z1_form<T, V>(w, Kl, KR, rsh, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, h, op.c2);
 #pragma unroll
           for (int t = 0; t < V; ++t) pu[m][t] = w[t];
         }
         if (PRO) {
-          // fine nodes c*V .. c*V+V-1 of row jj, plane kk
+          // fine nodes c*V .. c*V+V-1 of row jj, plane kk: coarse values
+          // c*H .. c*H+H of rows jj >> 1, (jj + 1) >> 1 on planes kk >> 1,
+          // (kk + 1) >> 1 (the last value of a row is the zero boundary)
           const bool kodd = (kk & 1) != 0, jodd = (jj & 1) != 0;
+          T W[2][2][H + 1];   // [plane][row][q]
+#pragma unroll
+          for (int pz = 0; pz < 2; ++pz)
+#pragma unroll
+            for (int jy = 0; jy < 2; ++jy) {
+              const int K = (kk + pz) >> 1, J = (jj + jy) >> 1;
+              nload<T, H>(Cl + (((K & 1) * CR + J - crow0) << (rsh - 1)) + c * H, W[pz][jy]);
+              const T nx = from_next(W[pz][jy][0]);
+              W[pz][jy][H] = c == G - 1 ? T(0) : nx;
+            }
+          constexpr int CQ = H + 1;
           T L[CQ];
 #pragma unroll
           for (int q = 0; q < CQ; ++q) {
-            const T P0 = kodd ? T(0.5) * (CWin[m][0][0][q] + CWin[m][1][0][q]) : CWin[m][0][0][q];
-            const T P1 = kodd ? T(0.5) * (CWin[m][0][1][q] + CWin[m][1][1][q]) : CWin[m][0][1][q];
+            const T P0 = kodd ? T(0.5) * (W[0][0][q] + W[1][0][q]) : W[0][0][q];
+            const T P1 = kodd ? T(0.5) * (W[0][1][q] + W[1][1][q]) : W[0][1][q];
             L[q] = jodd ? T(0.5) * (P0 + P1) : P0;
           }
 #pragma unroll
@@ -958,8 +970,8 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = uv(m);
-      const int r = v / G, c = v - (v / G) * G;
-      if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + c * V) = pu[m];
+      const int r = v >> gsh, c = v & (G - 1);
+      if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + ((slot * UR + r) << rsh) + c * V) = pu[m];
     }
   };
   auto store_u = [&](int slot, int kk) {
@@ -970,7 +982,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = tid + m * nthr;
-      const int r = v / G, c = v - (v / G) * G;
+      const int r = v >> gsh, c = v & (G - 1);
       const int ey = krow0 + r;
       if (v < KR * G && ey >= 0 && ey <= n - 1)
         pk[m] = *reinterpret_cast<const vt*>(kb + (size_t)n2 * ez + (size_t)n * ey + c * V);
@@ -981,10 +993,10 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = tid + m * nthr;
-      const int r = v / G, c = v - (v / G) * G;
+      const int r = v >> gsh, c = v & (G - 1);
       const int ey = krow0 + r;
       if (v < KR * G && ey >= 0 && ey <= n - 1)
-        *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + c * V) = pk[m];
+        *reinterpret_cast<vt*>(Kl + ((slot * KR + r) << rsh) + c * V) = pk[m];
     }
   };
 
@@ -993,6 +1005,12 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
     // prologue: u planes k0-1, k0, k0+1 and kappa planes up to k0 + LEAD - 1
     // into LDS; then the loads of u plane k0+2 and kappa plane k0 + LEAD are
     // left in flight
+    // PRO: coarse planes cb0, cb0 + 1 for fine planes k0-1 .. k0+1 (k0 is odd)
+    const int cb0 = (k0 - 1) >> 1;
+    if (PRO) {
+      fetch_c(cb0); store_c(cb0);
+      fetch_c(cb0 + 1); store_c(cb0 + 1);
+    }
     if (Z1) {
       // the operand of u plane kk needs kappa planes kk-1, kk
       for (int ez = k0 - 2; ez <= k0 + 1; ++ez)
@@ -1004,6 +1022,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
       __syncthreads();   // kappa plane k0-2 is no longer read: its slot takes plane k0+2
       if (k0 + 2 <= kmax) { fetch_k(k0 + 2); store_k(k0 + 2); }
     } else {
+      if (PRO) __syncthreads();
       if (NEED_U) {
         fetch_u(k0 - 1); store_u((k0 - 1) % 3, k0 - 1);
         fetch_u(k0); store_u(k0 % 3, k0);
@@ -1011,7 +1030,10 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
       }
       fetch_k(k0 - 1); store_k(k0 - 1);
       fetch_k(k0); store_k(k0);
+      if (PRO) __syncthreads();   // coarse plane cb0 is no longer read
     }
+    // coarse plane cb0 + 2 (first needed by fine plane k0 + 2) over cb0
+    if (PRO && k0 + 2 <= k1) { fetch_c(cb0 + 2); store_c(cb0 + 2); }
     // the epilogue's own operands of plane k0 first: waiting for them later
     // then leaves the staging loads behind them in flight
     const size_t pos0 = (size_t)b * stride + i0 + (size_t)n * j + (size_t)n2 * k0;
@@ -1036,7 +1058,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
           for (int dy = 0; dy < 2; ++dy)
-            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy + KOFF) * KRS + i0, K[dz][dy], gx);
+            lds_krow<T, V>(Kl + ((ks[dz] * KR + jr + dy + KOFF) << rsh) + i0, K[dz][dy], gx);
         T far[V], ksum[V], uc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1053,10 +1075,10 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         if (NEED_U) {
 #pragma unroll
           for (int sz = 0; sz < 2; ++sz) {
-            const T* P = Ul + ((sz ? sp : sm) * UR + jr) * URS + i0;
+            const T* P = Ul + (((sz ? sp : sm) * UR + jr) << rsh) + i0;
             T R[3][V + 2];
 #pragma unroll
-            for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + dy * URS, R[dy], gx, G);
+            for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + (dy << rsh), R[dy], gx, G);
 #pragma unroll
             for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -1066,7 +1088,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
                   far[v] += K[sz][sy][v + sx] * (R[1][v + 2 * sx] + (R[2 * sy][v + 1] + R[2 * sy][v + 2 * sx]));
           }
           {
-            const T* P = Ul + (s0 * UR + jr) * URS + i0;
+            const T* P = Ul + ((s0 * UR + jr) << rsh) + i0;
             T R0[V + 2], R2[V + 2];
             lds_urow<T, V>(P, R0, gx, G);
             vload<T, V>(P + URS, uc);
@@ -1096,9 +1118,13 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         __syncthreads();
         if (NEED_U && k + 2 <= k1) put_u(sm);   // plane k+2 takes the slot of plane k-1
         if (k + LEAD <= kmax) store_k(k + LEAD);
+        // PRO: coarse plane (k + 4) / 2 with fine plane k + 2 (k even), fetched
+        // in the step before
+        if (PRO && ((k - k0) & 1) && k + 3 <= k1) store_c((k + 4) >> 1);
         if (valid) epi.pre(pos0 + (size_t)n2 * (k + 1 - k0));
         if (NEED_U && k + 3 <= k1) fetch_u(k + 3);
         if (k + LEAD + 1 <= kmax) fetch_k(k + LEAD + 1);
+        if (PRO && !((k - k0) & 1) && k + 4 <= k1) fetch_c((k + 5) >> 1);
         __syncthreads();
         const int t = sm; sm = s0; s0 = sp; sp = t;
       }
@@ -1140,7 +1166,7 @@ inline ZGeom resr_geom(int n, int B) { return zgeom<T>(n, B); }
 // fits two vectors per thread
 template <class T, bool Z1 = false>
 inline bool resr_ok(const ZGeom& g) {
-  return g.n >= 4 && g.G >= 1 && g.G <= 64 && g.rows % 2 == 0 && (g.zc == 1 || g.zlen % 2 == 0) &&
+  return g.n >= 4 && g.G >= 1 && g.G <= 64 && (g.G & (g.G - 1)) == 0 && g.rows % 2 == 0 && (g.zc == 1 || g.zlen % 2 == 0) &&
          g.threads <= 256 && (g.rows + 3) * g.G <= 2 * g.threads && (g.rows + 2 + (Z1 ? 2 : 0)) * g.G <= 2 * g.threads &&
          (g.rows + 1) * g.G <= 2 * g.threads - (g.threads >= 192 ? g.threads / 2 : 0) && resr_bytes<T, Z1>(g) <= 65536;
 }
@@ -1186,8 +1212,10 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
   if (active && !active[b]) return;   // uniform over the workgroup
   const int rb = (int)(part % (uint32_t)g.row_blocks), zb = (int)(part / (uint32_t)g.row_blocks);
   const int n = g.n, n2 = n * n, G = g.G, R = g.rows;
+  const int gsh = __builtin_ctz((unsigned)G);   // G is a power of two
   const int UR = R + 3, KR = R + 2 + 2 * KOFF, TR = R + 1;
   const int URS = zlds_urs<T>(n), KRS = zlds_krs<T>(n);
+  const int rsh = __builtin_ctz((unsigned)n);   // LDS rows are n values, n a power of two
   T* Ul = reinterpret_cast<T*>(zsmem);        // [3][UR][URS]:  u rows j0-1 .. j0+R+1
   T* Kl = Ul + 3 * UR * URS;                   // [KP][KR][KRS]: kappa rows j0-1-KOFF .. j0+R+KOFF
   T* Tl = Kl + KP * KR * KRS;                  // [TR][URS]:     t rows j0 .. j0+R
@@ -1235,7 +1263,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = uv(m);
-      const int r = v / G, c = v - (v / G) * G;
+      const int r = v >> gsh, c = v & (G - 1);
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) {
         const size_t off = (size_t)n2 * kk + (size_t)n * jj + c * V;
@@ -1251,13 +1279,13 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = uv(m);
-      const int r = v / G, c = v - (v / G) * G;
+      const int r = v >> gsh, c = v & (G - 1);
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) {
         T w[V];
 #pragma unroll
         for (int t = 0; t < V; ++t) w[t] = (UPD && upd_on) ? rupd(pu[m][t], ua, pq[UPD ? m : 0][t]) : pu[m][t];
-        z1_form<T, V>(w, Kl, KR, KRS, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, h, c2);
+        z1_form<T, V>(w, Kl, KR, rsh, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, h, c2);
 #pragma unroll
         for (int t = 0; t < V; ++t) pu[m][t] = w[t];
       }
@@ -1267,8 +1295,8 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = uv(m);
-      const int r = v / G, c = v - (v / G) * G;
-      if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + (slot * UR + r) * URS + c * V) = pu[m];
+      const int r = v >> gsh, c = v & (G - 1);
+      if (v < UR * G && j0 - 1 + r <= n) *reinterpret_cast<vt*>(Ul + ((slot * UR + r) << rsh) + c * V) = pu[m];
     }
   };
   auto store_u = [&](int slot, int kk) {
@@ -1279,7 +1307,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = tid + m * nthr;
-      const int r = v / G, c = v - (v / G) * G;
+      const int r = v >> gsh, c = v & (G - 1);
       const int ey = krow0 + r;
       if (v < KR * G && ey >= 0 && ey <= n - 1)
         pk[m] = *reinterpret_cast<const vt*>(kb + (size_t)n2 * ez + (size_t)n * ey + c * V);
@@ -1290,10 +1318,10 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int v = tid + m * nthr;
-      const int r = v / G, c = v - (v / G) * G;
+      const int r = v >> gsh, c = v & (G - 1);
       const int ey = krow0 + r;
       if (v < KR * G && ey >= 0 && ey <= n - 1)
-        *reinterpret_cast<vt*>(Kl + (slot * KR + r) * KRS + c * V) = pk[m];
+        *reinterpret_cast<vt*>(Kl + ((slot * KR + r) << rsh) + c * V) = pk[m];
     }
   };
 
@@ -1302,7 +1330,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
   // coarse node owned by this thread: coarse row Jf + (tid / nc), column tid % nc
   const int Jf = (j0 + 1) >> 1;
   const int Jlast = (j0 + R - 1) >> 1 < nc - 1 ? (j0 + R - 1) >> 1 : nc - 1;
-  const int cJ = Jf + tid / nc, cI = tid % nc;
+  const int cJ = Jf + (tid >> __builtin_ctz((unsigned)nc)), cI = tid & (nc - 1);   // nc a power of two
   const bool owner = tid < (R / 2) * nc && cJ <= Jlast;
   T cacc = T(0);
 
@@ -1338,7 +1366,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
       for (int q = 0; q < 2; ++q) {
         const int task = q == 0 ? tid : (tid >= tbase ? nthr + tid - tbase : TR * G);
         if (task >= TR * G) continue;
-        const int jr = task / G, gx = task - (task / G) * G;
+        const int jr = task >> gsh, gx = task & (G - 1);
         const int j = j0 + jr, i0 = gx * V;
         if (j > n - 1) continue;
         T K[2][2][V + 1];
@@ -1347,7 +1375,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
           for (int dy = 0; dy < 2; ++dy)
-            lds_krow<T, V>(Kl + (ks[dz] * KR + jr + dy + KOFF) * KRS + i0, K[dz][dy], gx);
+            lds_krow<T, V>(Kl + ((ks[dz] * KR + jr + dy + KOFF) << rsh) + i0, K[dz][dy], gx);
         T far[V], ksum[V], uc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1362,10 +1390,10 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
         }
 #pragma unroll
         for (int sz = 0; sz < 2; ++sz) {
-          const T* P = Ul + ((sz ? sp : sm) * UR + jr) * URS + i0;
+          const T* P = Ul + (((sz ? sp : sm) * UR + jr) << rsh) + i0;
           T Rw[3][V + 2];
 #pragma unroll
-          for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + dy * URS, Rw[dy], gx, G);
+          for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + (dy << rsh), Rw[dy], gx, G);
 #pragma unroll
           for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -1375,7 +1403,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
                 far[v] += K[sz][sy][v + sx] * (Rw[1][v + 2 * sx] + (Rw[2 * sy][v + 1] + Rw[2 * sy][v + 2 * sx]));
         }
         {
-          const T* P = Ul + (s0 * UR + jr) * URS + i0;
+          const T* P = Ul + ((s0 * UR + jr) << rsh) + i0;
           T R0[V + 2], R2[V + 2];
           lds_urow<T, V>(P, R0, gx, G);
           vload<T, V>(P + URS, uc);
@@ -1410,7 +1438,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
           const T au = h * (ksum[v] * uc[v] * third - far[v] * twelfth);
           t[v] = (i0 + v) != 0 ? bv[v] - au : T(0);
         }
-        vstore<T, V>(Tl + jr * URS + i0, t);
+        vstore<T, V>(Tl + (jr << rsh) + i0, t);
       }
       if (kk + 1 <= kt1) prep_u(kk + 2);   // kappa planes kk+1, kk+2 are in the ring
       __syncthreads();
@@ -1421,7 +1449,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
           const int jr = 2 * cJ - j0;   // tile row of fine row 2J
 #pragma unroll
           for (int dy = -1; dy <= 1; ++dy) {
-            const T* row = Tl + (jr + dy) * URS + 2 * cI;
+            const T* row = Tl + ((jr + dy) << rsh) + 2 * cI;
             r2 += (dy == 0 ? T(1) : T(0.5)) * (T(0.5) * (row[-1] + row[1]) + row[0]);
           }
         }
@@ -1457,10 +1485,10 @@ hipError_t zlaunch_lds(int n, int B, const T* u, const T* xc, const T* kap, cons
                        uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st, OpArgs<T> op = {}) {
   constexpr int V = ZV<T>::V;
   const ZGeom g = zgeom<T>(n, B);
-  if (!zlds_ok<T, OP>(g)) return hipErrorInvalidValue;
+  if (!zlds_ok<T, OP, PRO>(g)) return hipErrorInvalidValue;
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
-  k_zlds<T, V, NEED_U, PRO, OP, Epi><<<dim3(blocks), dim3(g.threads), zlds_bytes<T, OP>(g), st>>>(
+  k_zlds<T, V, NEED_U, PRO, OP, Epi><<<dim3(blocks), dim3(g.threads), zlds_bytes<T, OP, PRO>(g), st>>>(
       g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, PRO ? grid_stride(n / 2) : 0, op);
   return hipGetLastError();
 }
@@ -1468,7 +1496,9 @@ hipError_t zlaunch_lds(int n, int B, const T* u, const T* xc, const T* kap, cons
 // the LDS engine when selected and its staging covers the tile (the register
 // engine otherwise)
 template <class T>
-inline bool use_lds(int n, int B, int var, int bit) { return (var & bit) && zlds_ok<T>(zgeom<T>(n, B)); }
+inline bool use_lds(int n, int B, int var, int bit) {
+  return (var & bit) && (bit == ZVAR_LDS_PRO ? zlds_ok<T, OP_PLAIN, true>(zgeom<T>(n, B)) : zlds_ok<T>(zgeom<T>(n, B)));
+}
 
 template <class T, bool NEED_U, class Epi>
 hipError_t zlaunch(int n, int B, const T* u, const T* kap, const int* active, double* partial, uint32_t pstride,
@@ -1798,7 +1828,7 @@ hipError_t launch_cheb_prolong(int n, int B, const T* kap, const T* b, const T* 
 template <class T>
 bool presmooth_usable(int n, int B) {
   const ZGeom g = zgeom<T>(n, B);
-  return n >= 4 && !use_small<T>(n) && resr_ok<T, true>(resr_geom<T>(n, B)) && zlds_ok<T, OP_Z1>(g);
+  return n >= 4 && !use_small<T>(n) && resr_ok<T, true>(resr_geom<T>(n, B)) && zlds_ok<T, OP_Z1, true>(g);
 }
 
 template <class T>
