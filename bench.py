@@ -419,6 +419,37 @@ def run_c5(args):
     return out
 
 
+def run_pause(args):
+    """Pause-model scheduler stress (Sec. 5.1 benchmark): active ratio A(p) of
+    eq. active_ratio for short / medium / long models, three spreads and
+    batch sampling, on P = 2048 workgroup slots with task widths 1, 8, 64 (the
+    8 / 64 / 512-core partitions scaled by 1/8) and N_l = C (1024, 64, 4)."""
+    import workloads
+    import paper_2111_11788_amd as mm
+    C = args.pause_c
+    counts = [C * 1024, C * 64, C * 4]
+    widths = [1, 8, 64]
+    P = 2048
+    ctx = mm.Context(workloads.C1, arena_bytes=64 << 20)
+    out = {"metric": "pause-model active ratio A(p)", "unit": "fraction", "higher_is_better": True,
+           "config": {"workload": "pause model", "capacity_slots": P, "widths": widths, "counts": counts,
+                      "law": "U(mu - sqrt(3) sigma, mu + sqrt(3) sigma)"}, "runs": []}
+    ctx.pause_model([8], [1], 10.0, 0.0, P)            # warm-up: module load, first launches
+    runs = [("short", 10.0, 0.2, 1), ("medium", 1000.0, 0.2, 1), ("long", 100000.0, 0.2, 1),
+            ("medium", 1000.0, 0.5 / 3 ** 0.5, 1), ("medium", 1000.0, 0.01, 1),
+            ("short", 10.0, 0.2, 8), ("medium", 1000.0, 0.2, 8)]
+    for name, mu, rel_sigma, batch in runs:
+        r, ticks, done = ctx.pause_model(counts, widths, mu, rel_sigma * mu, P, batch)
+        ideal_wall = r["active_slot_s"] / (P * r["ideal_ratio"]) if r["ideal_ratio"] > 0 else 0.0
+        out["runs"].append({"model": name, "mu_us": mu, "sigma_over_mu": rel_sigma, "batch": batch,
+                            "tasks": r["tasks"], "steps": r["steps"], "wall_s": r["wall_s"],
+                            "ideal_wall_s": ideal_wall, "A": r["ratio"], "A_ideal": r["ideal_ratio"],
+                            "overhead_us_per_step": 1e6 * (r["wall_s"] - ideal_wall) / max(1, r["steps"]),
+                            "measured_over_scheduled": r["measured_slot_s"] / r["active_slot_s"]})
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -426,8 +457,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--mode", choices=["c2", "c3", "c4", "c5"], default="c2",
-                    help="c2: the throughput line (default); c3: time-to-eps; c4: serving; c5: 256^3 stress")
+    ap.add_argument("--mode", choices=["c2", "c3", "c4", "c5", "pause"], default="c2",
+                    help="c2: the throughput line (default); c3: time-to-eps; c4: serving; c5: 256^3 stress; "
+                    "pause: pause-model scheduler stress")
+    ap.add_argument("--pause-c", type=int, default=4, help="pause: sample multiplier C of N_l = C N*_l")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default="", help="JSON tuning to apply instead of autotuning "
                     "(e.g. the 'tuning' object of an earlier line)")
@@ -450,7 +483,7 @@ def main():
               "so a multi-GPU run is N copies of this one on disjoint sample ranges", file=sys.stderr)
         sys.exit(2)
     if args.mode != "c2":
-        fn = {"c3": run_c3, "c4": run_c4, "c5": run_c5}[args.mode]
+        fn = {"c3": run_c3, "c4": run_c4, "c5": run_c5, "pause": run_pause}[args.mode]
         print(json.dumps(fn(args)))
         return
 

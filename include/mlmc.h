@@ -265,6 +265,56 @@ typedef struct mlmc_adaptive_info {
 int mlmc_estimate_adaptive(mlmc_ctx* ctx, const mlmc_adaptive_opts* opts, uint64_t* n_per_level,
                            mlmc_adaptive_info* info, mlmc_estimate_out* out);
 
+/* ---------------------------------------------- pause-model scheduler stress */
+
+typedef struct mlmc_pause_opts {
+  int32_t n_levels;         /* levels 0 .. n_levels-1, 1 <= n_levels <= 16 */
+  const int64_t* counts;    /* samples of each level (host, >= 0 each, at most 2^24 in all) */
+  const int32_t* widths;    /* workgroup slots a task of the level holds, 1 .. capacity */
+  double mu_us;             /* mean duration of one sample, microseconds, > 0 */
+  double sigma_us;          /* standard deviation, 0 <= sigma_us <= mu_us / sqrt(3) */
+  int32_t capacity;         /* P: workgroup slots of the device, 1 .. 8192 */
+  int32_t batch;            /* samples per task (batch sampling), >= 1; 1 = one sample per task */
+  double min_step_us;       /* shortest step, >= 0 */
+} mlmc_pause_opts;
+
+typedef struct mlmc_pause_out {
+  int64_t tasks;            /* tasks run (a task: up to `batch` samples of one level) */
+  int64_t steps;            /* scheduling steps (one device launch each) */
+  double clock_mhz;         /* rate of the device clock the durations are counted in */
+  double wall_s;            /* host time from the first launch to the end of the last step */
+  double active_slot_s;     /* a: sum over tasks of width x duration (slot-seconds) */
+  double ratio;             /* A = a / (P wall_s), eq. active_ratio */
+  double ideal_ratio;       /* A of the same schedule with no time between steps */
+  double measured_slot_s;   /* slot-seconds the workgroups spent waiting, device clock */
+} mlmc_pause_out;
+
+/* Pause-model stress of the scheduler (Sec. 5.1, "A benchmarking example"):
+ * the model of a sample only waits, for a time drawn from
+ * U(mu - sqrt(3) sigma, mu + sqrt(3) sigma) (sigma read as a standard
+ * deviation), so a run measures the scheduling alone through the active ratio
+ * A(p) = a(p) / (p t_w(p)) of eq. active_ratio, p being the capacity in
+ * workgroup slots.  A task of level l (batch consecutive samples, or fewer at
+ * the end) holds widths[l] slots for the sum of its samples' durations, the
+ * device counterpart of a partition of q_l cores.  Durations: sample i of
+ * level l takes d = a + w u, a = mu - sqrt(3) sigma, w = 2 sqrt(3) sigma, u the
+ * uniform of word 0 of the Philox4x64-10 block with key (seed, 0) and counter
+ * (i, l, 0, 1) (the xi draw of mlmc_draw_xi uses counter word 3 = 0), drawn
+ * on the device, then counted in device clock ticks as floor(d f + 1/2), f
+ * the clock rate in MHz.  Schedule (host loop, one launch per step): tasks are
+ * queued finest level first, in sample order (the finest-first rule of
+ * Alg. incremental_greedy); at each step boundary every queued task that fits
+ * the free slots is admitted, in queue order; the step lasts
+ * max(min_step, least remaining time of a running task) and every running
+ * workgroup waits min(its task's remaining time, step); tasks whose time is
+ * used up finish.  ticks (host, sum of counts entries, may be NULL) receives
+ * each sample's duration in ticks, level-major; done_step (same size, may be
+ * NULL) the step at whose end the sample's task finished (0-based).
+ * Errors: MLMC_E_INVALID for bad options, MLMC_E_NOMEM when the arena after
+ * the KL tables cannot hold the draws, MLMC_E_DEVICE. */
+int mlmc_pause_model(mlmc_ctx* ctx, const mlmc_pause_opts* opts, int64_t* ticks, int64_t* done_step,
+                     mlmc_pause_out* out);
+
 /* ------------------------------------------------------------- tuning */
 
 /* Execution choices that change speed, not the discrete solution each solve

@@ -29,7 +29,7 @@ KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
            "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_vcycle", "mlmc_solve", "mlmc_qoi",
            "mlmc_sample_level", "mlmc_estimate", "mlmc_estimate_adaptive", "mlmc_get_estimate", "mlmc_reset_stats",
-           "mlmc_node_map",
+           "mlmc_node_map", "mlmc_pause_model",
            "mlmc_set_profiling", "mlmc_kernel_time", "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
            "mlmc_serve_start", "mlmc_serve_stop", "mlmc_submit", "mlmc_submit_batch", "mlmc_poll", "mlmc_drain",
            "mlmc_serve_stats"]
@@ -103,6 +103,18 @@ class AdaptiveInfo(ctypes.Structure):
                 ("beta", ctypes.c_double), ("bias", ctypes.c_double), ("err", ctypes.c_double)]
 
 
+class PauseOpts(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("counts", ctypes.c_void_p), ("widths", ctypes.c_void_p),
+                ("mu_us", ctypes.c_double), ("sigma_us", ctypes.c_double), ("capacity", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("min_step_us", ctypes.c_double)]
+
+
+class PauseOut(ctypes.Structure):
+    _fields_ = [("tasks", ctypes.c_int64), ("steps", ctypes.c_int64), ("clock_mhz", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("active_slot_s", ctypes.c_double), ("ratio", ctypes.c_double),
+                ("ideal_ratio", ctypes.c_double), ("measured_slot_s", ctypes.c_double)]
+
+
 class EstimateOut(ctypes.Structure):
     _fields_ = [("qtilde", ctypes.c_double), ("var_qtilde", ctypes.c_double), ("levels", ctypes.c_int32),
                 ("level", LevelStats * 16)]
@@ -140,6 +152,7 @@ def lib():
                                                   ctypes.POINTER(EstimateOut)]),
         "mlmc_reset_stats": (ctypes.c_int, [P]),
         "mlmc_node_map": (ctypes.c_int, [P, I32, P]),
+        "mlmc_pause_model": (ctypes.c_int, [P, ctypes.POINTER(PauseOpts), P, P, ctypes.POINTER(PauseOut)]),
         "mlmc_set_profiling": (ctypes.c_int, [P, I32]),
         "mlmc_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
         "mlmc_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
@@ -317,6 +330,25 @@ class Context:
         out = np.empty(grid_stride(n), dtype=np.int32)
         self._check(lib().mlmc_node_map(self.h, n, out.ctypes.data))
         return out
+
+    def pause_model(self, counts, widths, mu_us: float, sigma_us: float, capacity: int, batch: int = 1,
+                    min_step_us: float = 0.0):
+        """Pause-model scheduler stress (mlmc_pause_model); returns (summary dict, ticks, done_step).
+
+        ticks and done_step are per sample, level-major (all samples of level 0 first)."""
+        c = np.ascontiguousarray(counts, dtype=np.int64)
+        w = np.ascontiguousarray(widths, dtype=np.int32)
+        if c.shape != w.shape or c.ndim != 1:
+            raise ValueError("counts and widths need one entry per level")
+        opts = PauseOpts(len(c), c.ctypes.data, w.ctypes.data, mu_us, sigma_us, capacity, batch, min_step_us)
+        total = int(c.sum()) if len(c) else 0
+        ticks = np.zeros(max(total, 1), dtype=np.int64)
+        done = np.zeros(max(total, 1), dtype=np.int64)
+        out = PauseOut()
+        self._check(lib().mlmc_pause_model(self.h, ctypes.byref(opts), ticks.ctypes.data, done.ctypes.data,
+                                           ctypes.byref(out)))
+        summary = {k: getattr(out, k) for k, _ in PauseOut._fields_}
+        return summary, ticks[:total], done[:total]
 
     def tuning(self) -> dict:
         t = Tuning()

@@ -10,6 +10,11 @@ namespace mlmc {
 hipError_t launch_draw_xi(uint64_t seed, int level, uint64_t first, int64_t count, int M,
                           double* xi, hipStream_t st);
 // row r: sample ids[r] of level lv[r] into row slots[r] of xi
+hipError_t launch_pause_draw(uint64_t seed, int level, int64_t count, double a, double w, double* out,
+                             hipStream_t st);
+// every workgroup w < nwg waits spin[w] ticks of the device wall clock and adds
+// the ticks it measured to meas[w]
+hipError_t launch_pause_spin(const uint32_t* spin, uint64_t* meas, int nwg, hipStream_t st);
 hipError_t launch_draw_xi_rows(uint64_t seed, int64_t count, int M, const uint64_t* ids, const int* lv,
                                const int* slots, double* xi, hipStream_t st);
 

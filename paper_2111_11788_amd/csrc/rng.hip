@@ -158,7 +158,26 @@ __global__ void __launch_bounds__(kBlock) k_draw_xi_rows(uint64_t seed, int64_t 
     if (4 * j + q < M) out[q] = z[q];
 }
 
+// Pause model: sample i of level lv takes a + w u microseconds, u the uniform
+// of word 0 of block (i, lv, 0, 1) (word 3 = 1 keeps these blocks apart from
+// the xi blocks).  One thread per sample of the level; out[s] for sample s.
+__global__ void __launch_bounds__(kBlock) k_pause_draw(uint64_t seed, uint64_t lv, int64_t count, double a,
+                                                       double w, double* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= count) return;
+  const Block4 b = philox4x64_10((uint64_t)s, lv, 0ull, 1ull, seed, 0ull);
+  out[s] = a + w * to_uniform(b.w[0]);
+}
+
 }  // namespace
+
+hipError_t launch_pause_draw(uint64_t seed, int level, int64_t count, double a, double w, double* out,
+                             hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  k_pause_draw<<<dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, st>>>(seed, (uint64_t)level,
+                                                                                          count, a, w, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_draw_xi_rows(uint64_t seed, int64_t count, int M, const uint64_t* ids, const int* lv,
                                const int* slots, double* xi, hipStream_t st) {
