@@ -18,6 +18,7 @@ Modules
   pcg    Jacobi-preconditioned conjugate gradients (the oracle's solver)
   mlmc   per-sample level differences Y_l, running statistics, allocation,
          the telescoping MLMC estimator
+  pause  pause-model durations and the step schedule of the scheduler stress
 
 Functions without an independent pin say "parity unpinned" in their docstring.
 """
