@@ -229,12 +229,13 @@ __global__ void __launch_bounds__(kBlock) k_fill_interior(SGeom g, size_t stride
   const int n = g.n;
   const size_t n2 = (size_t)n * n;
   vt* out = reinterpret_cast<vt*>(v + (size_t)sp.b * stride + n2);
+  const int lg = __builtin_ctz((unsigned)n);   // n is a power of two
   for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) {
     vt o;
 #pragma unroll
     for (int c = 0; c < V; ++c) {
       const size_t pos = t * V + c;      // offset from plane 1
-      const int i = (int)(pos % n), j = (int)((pos / n) % n);
+      const int i = (int)(pos & (n - 1)), j = (int)((pos >> lg) & (n - 1));
       o[c] = (i != 0 && j != 0) ? value : T(0);
     }
     out[t] = o;
@@ -253,18 +254,22 @@ __global__ void __launch_bounds__(kBlock) k_qoi_partial(SGeom g, size_t stride, 
   const double* ub = u + (size_t)sp.b * stride + n2;
   const double h = 1.0 / n, h3 = h * h * h;
   const int lo = n / 4, hi = 3 * n / 4;
+  typedef Vec<double, 2>::type d2;
+  const int lg = __builtin_ctz((unsigned)n);   // n is a power of two
+  const d2* uv = reinterpret_cast<const d2*>(ub);
   double acc = 0.0;
   for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) {
+    const d2 u2 = uv[t];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const size_t pos = 2 * t + c;
-      const int i = (int)(pos % n), j = (int)((pos / n) % n), k = 1 + (int)(pos / n2);
+      const int i = (int)(pos & (n - 1)), j = (int)((pos >> lg) & (n - 1)), k = 1 + (int)(pos >> (2 * lg));
       double w = h3;
       if (qoi == 1) {
         auto cw = [&](int x) { return (x < lo || x > hi) ? 0.0 : ((x == lo || x == hi) ? 1.0 : 2.0); };
         w *= cw(i) * cw(j) * cw(k);
       }
-      acc += w * ub[pos];    // boundary positions hold 0
+      acc += w * (c ? u2.y : u2.x);    // boundary positions hold 0
     }
   }
   acc = block_sum(acc);

@@ -1749,11 +1749,12 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(int nc, int64_t total, const
                                                     T* __restrict__ kc, const int* __restrict__ active) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
+  const int lg = __builtin_ctz((unsigned)nc);   // nc is a power of two
   const int64_t nce = (int64_t)nc * nc * nc;
-  const int64_t b = t / nce, E = t - b * nce;
+  const int64_t b = t >> (3 * lg), E = t & (nce - 1);
   if (active && !active[b]) return;
   const int nf = 2 * nc;
-  const int EX = (int)(E % nc), EY = (int)((E / nc) % nc), EZ = (int)(E / ((int64_t)nc * nc));
+  const int EX = (int)(E & (nc - 1)), EY = (int)((E >> lg) & (nc - 1)), EZ = (int)(E >> (2 * lg));
   const T* f = kf + b * nce * 8 + 2 * EX + (int64_t)nf * 2 * EY + (int64_t)nf * nf * 2 * EZ;
   const int64_t f2 = (int64_t)nf * nf;
   const T s = ((f[0] + f[1]) + (f[nf] + f[nf + 1])) + ((f[f2] + f[f2 + 1]) + (f[f2 + nf] + f[f2 + nf + 1]));
