@@ -64,6 +64,13 @@ enum { MLMC_QOI_DOMAIN_AVERAGE = 0, MLMC_QOI_SUBCUBE_AVERAGE = 1 };
  * |sqrt(lambda_m) xi_m phi_m|), reported against the fp64 result. */
 enum { MLMC_PREC_FP64 = 0, MLMC_PREC_MIXED = 1, MLMC_PREC_MIXED_BF16KLE = 2 };
 enum { MLMC_SOLVER_GMG_PCG = 0, MLMC_SOLVER_JACOBI_PCG = 1 };
+/* Forcing term f of eq. model (Sec. 2.1: f may be a random field too).
+ * CONSTANT: f = 1.  LOGNORMAL: f = exp(g_f), g_f the truncated KLE with the
+ * modes and eigenvalues of the log-diffusion's field but its own coefficients
+ * xi_f (Philox counter word 3 = 2, see mlmc_forcing), independent of kappa;
+ * one value per element at its centroid, like kappa.  The Dirichlet data stays
+ * u = 0. */
+enum { MLMC_FORCING_CONSTANT = 0, MLMC_FORCING_LOGNORMAL = 1 };
 
 typedef struct mlmc_config {
   int32_t n0;          /* elements per side of the coarsest MLMC mesh, >= 2, power of 2 */
@@ -81,6 +88,7 @@ typedef struct mlmc_config {
   int32_t max_batch;   /* samples solved together on the finest mesh, >= 1; a coarser level takes
                           as many as cost the same interior DOFs (at most 65536, and what the
                           arena holds) */
+  int32_t forcing;     /* MLMC_FORCING_*; LOGNORMAL is not available while serving */
   void* arena;         /* device memory owned by the caller, 256-byte aligned */
   size_t arena_bytes;  /* size of the arena: the HBM budget of the context */
   void* stream;        /* hipStream_t for all device work of the context */
@@ -174,8 +182,8 @@ int mlmc_apply(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa,
 int mlmc_vcycle(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa,
                 const double* r, double* z);
 
-/* Solve A(kappa) u = b for f = 1 (b_i = h^3) for `count` samples with the
- * configured solver and precision, starting from u = 0, to the configured
+/* Solve A(kappa) u = b for f = 1 (b_i = h^3, whatever the configured
+ * forcing) for `count` samples with the configured solver and precision, starting from u = 0, to the configured
  * true relative residual.  u: device, grid layout, fp64 (output);
  * iters (host, may be NULL) receives the PCG iteration count per sample.
  * Returns MLMC_E_NOCONV if some sample did not converge (u holds the last
@@ -188,6 +196,18 @@ int mlmc_solve(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa,
  * exact integral of the trilinear interpolant (Sec. 2.1, "an integral of u
  * on a sub-region").  u: device, grid layout. */
 int mlmc_qoi(mlmc_ctx* ctx, int32_t n, int64_t count, const double* u, double* q);
+
+/* The random forcing of samples first .. first+count-1 of `level` on mesh n
+ * (device arrays, sample-major): xi_f of sample i is drawn like xi
+ * (mlmc_draw_xi) but from the Philox blocks with counter (i, level, j, 2);
+ * f (count x n^3, fp64) receives exp(g_f) at the element centroids, g_f =
+ * sum_m sqrt(lambda_m) phi_m xi_f,m (the KLE of mlmc_field); b (count x
+ * mlmc_grid_stride(n), fp64, grid layout) the load vector of that
+ * elementwise-constant f: b_i = (h^3 / 8) sum of f over the 8 elements around
+ * interior node i (each element integrates a Q1 hat function to h^3 / 8), 0 at
+ * boundary positions.  Errors: MLMC_E_INVALID for bad arguments, MLMC_E_NOMEM
+ * when the arena after the KL tables cannot hold the draw. */
+int mlmc_forcing(mlmc_ctx* ctx, int32_t n, int32_t level, uint64_t first, int64_t count, double* f, double* b);
 
 /* -------------------------------------------------- whole path (host out) */
 

@@ -103,6 +103,22 @@ def load_constant(n: int, f: float = 1.0) -> np.ndarray:
     return np.full((n - 1) ** 3, f * (1.0 / n) ** 3)
 
 
+def load_elements(n: int, f_elem: np.ndarray) -> np.ndarray:
+    """b_g = int f phi_g for f constant on each element (f_elem[e], element
+    layout): each element contributes f_e h^3 / 8 to each of its interior
+    corners (a Q1 hat integrates to h^3 / 8 over each of its 8 elements)."""
+    f_elem = np.asarray(f_elem, dtype=np.float64)
+    eijk = element_ijk(n)
+    off = local_offsets()
+    w = (1.0 / n) ** 3 / 8.0
+    b = np.zeros((n - 1) ** 3)
+    for a in range(8):
+        p = eijk + off[a][None, :]
+        ok = np.all((p >= 1) & (p <= n - 1), axis=1)
+        np.add.at(b, interior_index(n, p[ok, 0], p[ok, 1], p[ok, 2]), w * f_elem[ok])
+    return b
+
+
 GAUSS3_X = np.array([-np.sqrt(3.0 / 5.0), 0.0, np.sqrt(3.0 / 5.0)])
 GAUSS3_W = np.array([5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0])
 

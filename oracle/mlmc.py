@@ -19,10 +19,11 @@ import numpy as np
 from . import fe, field, pcg, rng
 
 
-def solve_qoi(n: int, kap: np.ndarray, qoi: int, rtol: float, max_iter: int):
-    """Q(u_h) for one sample: Jacobi-PCG on the assembled operator, f = 1."""
+def solve_qoi(n: int, kap: np.ndarray, qoi: int, rtol: float, max_iter: int, b=None):
+    """Q(u_h) for one sample: Jacobi-PCG on the assembled operator; f = 1 unless b is given."""
     A = fe.assemble(n, kap)
-    b = fe.load_constant(n)
+    if b is None:
+        b = fe.load_constant(n)
     u, it, rel = pcg.jacobi_pcg(A, b, rtol, max_iter)
     return float(fe.qoi_weights(n, qoi) @ u), it, rel, u
 
@@ -36,15 +37,23 @@ def sample_level(wl, level: int, first: int, count: int, rtol=None, max_iter=Non
     """
     rtol = wl.rtol if rtol is None else rtol
     max_iter = wl.max_iter if max_iter is None else max_iter
-    xi = rng.draw_xi(wl.seed, 0 if common_random_numbers else level, first, count, wl.n_modes)
+    lv = 0 if common_random_numbers else level
+    xi = rng.draw_xi(wl.seed, lv, first, count, wl.n_modes)
     nf = wl.n(level)
     kf = field.kappa(nf, wl.corr_len, wl.sigma2, wl.n_modes, xi)
     kc = field.kappa(nf // 2, wl.corr_len, wl.sigma2, wl.n_modes, xi) if level > 0 else None
+    forced = getattr(wl, "forcing", 0) == 1
+    if forced:   # f = exp(g_f): the KLE of the log-field with its own coefficients (stream 2)
+        xif = rng.draw_xi(wl.seed, lv, first, count, wl.n_modes, stream=2)
+        ff = field.kappa(nf, wl.corr_len, wl.sigma2, wl.n_modes, xif)
+        fc = field.kappa(nf // 2, wl.corr_len, wl.sigma2, wl.n_modes, xif) if level > 0 else None
     Y = np.empty(count); Qf = np.empty(count); Qc = np.zeros(count); its = np.empty(count, dtype=np.int64)
     for s in range(count):
-        Qf[s], its[s], _, _ = solve_qoi(nf, kf[s], wl.qoi, rtol, max_iter)
+        bf = fe.load_elements(nf, ff[s]) if forced else None
+        Qf[s], its[s], _, _ = solve_qoi(nf, kf[s], wl.qoi, rtol, max_iter, bf)
         if level > 0:
-            Qc[s], _, _, _ = solve_qoi(nf // 2, kc[s], wl.qoi, rtol, max_iter)
+            bc = fe.load_elements(nf // 2, fc[s]) if forced else None
+            Qc[s], _, _, _ = solve_qoi(nf // 2, kc[s], wl.qoi, rtol, max_iter, bc)
         Y[s] = Qf[s] - Qc[s]
     return Y, Qf, Qc, its
 

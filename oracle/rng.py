@@ -68,14 +68,16 @@ def philox4x64(counter, key, rounds: int = PHILOX_ROUNDS):
     return x0, x1, x2, x3
 
 
-def raw_words(seed: int, level: int, first: int, count: int, n_modes: int) -> np.ndarray:
-    """Raw Philox words, uint64 [count, 4*ceil(n_modes/4)], for samples first.. ."""
+def raw_words(seed: int, level: int, first: int, count: int, n_modes: int, stream: int = 0) -> np.ndarray:
+    """Raw Philox words, uint64 [count, 4*ceil(n_modes/4)], for samples first.. .
+
+    stream is counter word 3: 0 for xi, 2 for the random forcing's xi_f."""
     nblk = (n_modes + 3) // 4
     out = np.empty((count, 4 * nblk), dtype=np.uint64)
     for s in range(count):
         i = first + s
         for j in range(nblk):
-            out[s, 4 * j:4 * j + 4] = philox4x64((i, level, j, 0), (seed, 0))
+            out[s, 4 * j:4 * j + 4] = philox4x64((i, level, j, stream), (seed, 0))
     return out
 
 
@@ -168,9 +170,9 @@ def box_muller(u: np.ndarray) -> np.ndarray:
     return z
 
 
-def draw_xi(seed: int, level: int, first: int, count: int, n_modes: int) -> np.ndarray:
-    """xi[count, n_modes] (fp64) for samples first..first+count-1 of a level."""
-    w = raw_words(seed, level, first, count, n_modes)
+def draw_xi(seed: int, level: int, first: int, count: int, n_modes: int, stream: int = 0) -> np.ndarray:
+    """xi[count, n_modes] (fp64) for samples first..first+count-1 of a level (stream: counter word 3)."""
+    w = raw_words(seed, level, first, count, n_modes, stream)
     return box_muller(uniforms(w))[:, :n_modes]
 
 

@@ -29,7 +29,7 @@ KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
            "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_vcycle", "mlmc_solve", "mlmc_qoi",
            "mlmc_sample_level", "mlmc_estimate", "mlmc_estimate_adaptive", "mlmc_get_estimate", "mlmc_reset_stats",
-           "mlmc_node_map", "mlmc_pause_model",
+           "mlmc_node_map", "mlmc_pause_model", "mlmc_forcing",
            "mlmc_set_profiling", "mlmc_kernel_time", "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
            "mlmc_serve_start", "mlmc_serve_stop", "mlmc_submit", "mlmc_submit_batch", "mlmc_poll", "mlmc_drain",
            "mlmc_serve_stats"]
@@ -46,7 +46,8 @@ class Config(ctypes.Structure):
                 ("corr_len", ctypes.c_double), ("n_modes", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("qoi", ctypes.c_int32), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("solver", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
+                ("max_batch", ctypes.c_int32), ("forcing", ctypes.c_int32), ("arena", ctypes.c_void_p),
+                ("arena_bytes", ctypes.c_size_t),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -152,6 +153,7 @@ def lib():
                                                   ctypes.POINTER(EstimateOut)]),
         "mlmc_reset_stats": (ctypes.c_int, [P]),
         "mlmc_node_map": (ctypes.c_int, [P, I32, P]),
+        "mlmc_forcing": (ctypes.c_int, [P, I32, I32, U64, I64, P, P]),
         "mlmc_pause_model": (ctypes.c_int, [P, ctypes.POINTER(PauseOpts), P, P, ctypes.POINTER(PauseOut)]),
         "mlmc_set_profiling": (ctypes.c_int, [P, I32]),
         "mlmc_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(Tuning)]),
@@ -183,11 +185,12 @@ def make_config(wl, arena_ptr: int = 0, arena_bytes: int = 0, stream: int = 0, *
     """mlmc_config from a workloads.Workload (fields may be overridden)."""
     v = dict(n0=wl.n0, levels=wl.levels, sigma2=wl.sigma2, corr_len=wl.corr_len, n_modes=wl.n_modes,
              seed=wl.seed, qoi=wl.qoi, rtol=wl.rtol, max_iter=wl.max_iter, precision=wl.precision,
-             solver=wl.solver, cheb_degree=0, max_batch=max(1, wl.batch or 64))
+             solver=wl.solver, cheb_degree=0, max_batch=max(1, wl.batch or 64),
+             forcing=getattr(wl, "forcing", 0))
     v.update(over)
     return Config(v["n0"], v["levels"], v["sigma2"], v["corr_len"], v["n_modes"], v["seed"], v["qoi"],
                   v["rtol"], v["max_iter"], v["precision"], v["solver"], v["cheb_degree"], v["max_batch"],
-                  arena_ptr, arena_bytes, stream)
+                  v["forcing"], arena_ptr, arena_bytes, stream)
 
 
 def workspace_bytes(cfg: Config, level: int, batch: int) -> int:
@@ -324,6 +327,14 @@ class Context:
 
     def reset_stats(self):
         self._check(lib().mlmc_reset_stats(self.h))
+
+    def forcing(self, n: int, level: int, first: int, count: int):
+        """Random forcing of samples first.. of a level on mesh n (mlmc_forcing): (f [count, n^3], b [count, stride])."""
+        t = self.torch
+        f = t.empty((count, n ** 3), dtype=t.float64, device="cuda")
+        b = t.empty((count, grid_stride(n)), dtype=t.float64, device="cuda")
+        self._check(lib().mlmc_forcing(self.h, n, level, first, count, _ptr(f), _ptr(b)))
+        return f, b
 
     def node_map(self, n: int) -> np.ndarray:
         """The device's interior-unknown number at every grid position of mesh n (-1: none)."""

@@ -135,6 +135,27 @@ int mlmc_node_map(mlmc_ctx* ctx, int32_t n, int32_t* out) {
   return MLMC_OK;
 }
 
+int mlmc_forcing(mlmc_ctx* ctx, int32_t n, int32_t level, uint64_t first, int64_t count, double* f, double* b) {
+  if (!ctx) return MLMC_E_INVALID;
+  if (ctx->server) FAIL(MLMC_E_INVALID, "the context is serving");
+  if (n < 2 || !is_pow2(n) || !mesh_of_config(ctx, n) || level < 0 || count < 0 || count > (1 << 30) ||
+      (count > 0 && (!f || !b)))
+    FAIL(MLMC_E_INVALID, "bad forcing arguments");
+  if (count == 0) return MLMC_OK;
+  const size_t xb = align256((size_t)count * ctx->cfg.n_modes * sizeof(double));
+  if (ctx->persistent_top + xb > ctx->cfg.arena_bytes) FAIL(MLMC_E_NOMEM, "arena too small for the forcing draw");
+  // scratch right after the persistent tables (the cached work space there is
+  // dropped and carved again when next needed)
+  ctx->sw.release_graphs();
+  ctx->bw.wf.release_graphs();
+  ctx->bw.wc.release_graphs();
+  ctx->ws_kind = -1;
+  double* xif = reinterpret_cast<double*>((char*)ctx->cfg.arena + ctx->persistent_top);
+  if (int rc = forcing_impl(ctx, n, level, first, (int)count, xif, f, b)) return rc;
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return MLMC_OK;
+}
+
 int mlmc_modes(const mlmc_ctx* ctx, int32_t* triples, double* lambda) {
   if (!ctx) return MLMC_E_INVALID;
   const int M = ctx->cfg.n_modes;

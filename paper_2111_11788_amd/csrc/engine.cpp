@@ -41,6 +41,10 @@ int validate(const mlmc_config* c, std::string& why) {
   if (c->solver != 0 && c->solver != 1) { why = "unknown solver"; return MLMC_E_INVALID; }
   if (c->cheb_degree < 0 || c->cheb_degree > 8) { why = "cheb_degree must be in 0..8"; return MLMC_E_INVALID; }
   if (c->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
+  if (c->forcing != MLMC_FORCING_CONSTANT && c->forcing != MLMC_FORCING_LOGNORMAL) {
+    why = "unknown forcing";
+    return MLMC_E_INVALID;
+  }
   if (c->arena_bytes && !c->arena) { why = "arena_bytes > 0 with a NULL arena"; return MLMC_E_INVALID; }
   if (((uintptr_t)c->arena) % 256) { why = "arena must be 256-byte aligned"; return MLMC_E_INVALID; }
   return MLMC_OK;
@@ -98,6 +102,12 @@ void carve_batch(Carver& cv, BatchWork& w, const mlmc_config& c, int level, int 
     w.uc = cv.take<double>((size_t)B * grid_stride(nc));
     w.wc.carve(cv, nc, B, c.precision, c.solver);
   }
+  if (c.forcing == MLMC_FORCING_LOGNORMAL) {
+    w.xif = cv.take<double>((size_t)B * c.n_modes);
+    w.fe = cv.take<double>((size_t)B * elem_count(nf));
+    w.bf = cv.take<double>((size_t)B * grid_stride(nf));
+    if (level > 0) w.bc = cv.take<double>((size_t)B * grid_stride(nf / 2));
+  }
 }
 
 int ensure_batch_work(mlmc_ctx* ctx, int level, int B) {
@@ -134,13 +144,21 @@ int ensure_tables(mlmc_ctx* ctx, int n, double** tab) {
   return MLMC_OK;
 }
 
-int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float* kap32) {
+int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float* kap32, bool exact) {
   double* tab = nullptr;
   if (int rc = ensure_tables(ctx, n, &tab)) return rc;
   const int M = ctx->cfg.n_modes;
   LAUNCH(MLMC_K_FIELD, (double)B * elems(n) * (8.0 + (kap32 ? 4.0 : 0.0)) + (double)B * M * 8.0,
          launch_field(n, M, B, xi, ctx->d_sqrtlam, ctx->d_triples, tab, ctx->K1, kap, kap32, ctx->st, nullptr,
-                      ctx->cfg.precision == MLMC_PREC_MIXED_BF16KLE));
+                      !exact && ctx->cfg.precision == MLMC_PREC_MIXED_BF16KLE));
+  return MLMC_OK;
+}
+
+int forcing_impl(mlmc_ctx* ctx, int n, int level, uint64_t first, int B, double* xif, double* f, double* b) {
+  const int M = ctx->cfg.n_modes;
+  LAUNCH(MLMC_K_XI, (double)B * M * 8, launch_draw_xi(ctx->cfg.seed, level, first, B, M, xif, ctx->st, 2));
+  if (int rc = field_impl(ctx, n, B, xif, f, nullptr, true)) return rc;
+  LAUNCH(MLMC_K_MISC, (double)B * (elems(n) + grid_stride(n)) * 8, launch_load(n, B, f, b, ctx->st));
   return MLMC_OK;
 }
 
@@ -488,7 +506,7 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
 
 // kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
 int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
-               bool kap32_ready) {
+               bool kap32_ready, const double* bvec) {
   const int n = w.n, B = w.B;
   hipStream_t st = ctx->st;
   const double h = 1.0 / n, h3 = h * h * h;
@@ -507,7 +525,10 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       LAUNCH(MLMC_K_COARSEN, (elems(L[l - 1].n) + elems(L[l].n)) * B * 8,
              launch_coarsen<double>(L[l - 1].n, B, L[l - 1].kap, L[l].kap, st));
     LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, u, 0.0, nullptr, st));
-    LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, w.r, h3, nullptr, st));
+    if (bvec)
+      HIPCHK(hipMemcpyAsync(w.r, bvec, (size_t)B * S0 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else
+      LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, w.r, h3, nullptr, st));
     LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double>(n, B, w.r, w.r, O, &np, st)));
     LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
     for (int round = 0; round < 4 && total_it < ctx->cfg.max_iter; ++round) {
@@ -518,7 +539,8 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       total_it += it;
       // confirm with the true residual; samples above tolerance continue
       LAUNCH(MLMC_K_MISC, 0, launch_set_active(B, O, 1, st));
-      LAUNCHM(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, O.active, B, launch_true_residual(n, B, kap, h3, u, w.r, O, &np, st, zv<double>(ctx)));
+      LAUNCHM(MLMC_K_TRUE_RESIDUAL, ((bvec ? 3 : 2) * d + e) * 8, O.active, B,
+              launch_true_residual(n, B, kap, h3, u, w.r, O, &np, st, zv<double>(ctx), bvec));
       LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
       int na = 0;
       if (int rc = count_active(ctx, O, B, &na)) return rc;
@@ -538,8 +560,13 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       // (its neighbours' u is still being read), the residual of the result
       // demoted to fp32 as the next inner right-hand side, and its fp64 norm;
       // `alt` records which buffer holds each sample's last iterate.
-      LAUNCH(MLMC_K_MISC, d * 4, launch_fill_interior<float>(n, B, w.rin, h3, nullptr, st));
-      LAUNCH(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, (launch_dot<float>(n, B, w.rin, w.rin, O, &np, st)));
+      if (bvec) {   // rin = fp32(b); ||b||^2 from the fp64 b
+        LAUNCH(MLMC_K_MISC, d * 12, launch_demote(n, B, bvec, w.rin, O, st));
+        LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double>(n, B, bvec, bvec, O, &np, st)));
+      } else {
+        LAUNCH(MLMC_K_MISC, d * 4, launch_fill_interior<float>(n, B, w.rin, h3, nullptr, st));
+        LAUNCH(kid<float>(MLMC_K_PCG_DOT), 2 * d * 4, (launch_dot<float>(n, B, w.rin, w.rin, O, &np, st)));
+      }
       LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
       HIPCHK(hipMemsetAsync(w.alt, 0, B * sizeof(int), st));
       // the buffer written by the expected last step is u, so usually no copy
@@ -568,12 +595,13 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
           return rc;
         total_it += it;
         double* uout = bufs[next];
-        if (owed)   // reads u, d, p and kappa; writes u + d, rin
-          LAUNCHM(MLMC_K_TRUE_RESIDUAL, ((ucur ? 8 : 0) + 4 + 4 + 8 + 4) * d + 8 * e, O.active, B,
-                  launch_refine_owed(n, B, kap, h3, ucur, w.d, w.p32, w.p32b, I, uout, w.rin, O, &np, st));
+        const double bb_bytes = bvec ? 8 : 0;
+        if (owed)   // reads u, d, p and kappa (and b); writes u + d, rin
+          LAUNCHM(MLMC_K_TRUE_RESIDUAL, ((ucur ? 8 : 0) + 4 + 4 + 8 + 4 + bb_bytes) * d + 8 * e, O.active, B,
+                  launch_refine_owed(n, B, kap, h3, ucur, w.d, w.p32, w.p32b, I, uout, w.rin, O, &np, st, bvec));
         else
-          LAUNCHM(MLMC_K_TRUE_RESIDUAL, ((ucur ? 8 : 0) + 4 + 8 + 4) * d + 8 * e, O.active, B,
-                  launch_refine(n, B, kap, h3, ucur, w.d, uout, w.rin, O, &np, st, zv<double>(ctx)));
+          LAUNCHM(MLMC_K_TRUE_RESIDUAL, ((ucur ? 8 : 0) + 4 + 8 + 4 + bb_bytes) * d + 8 * e, O.active, B,
+                  launch_refine(n, B, kap, h3, ucur, w.d, uout, w.rin, O, &np, st, zv<double>(ctx), bvec));
         LAUNCH(MLMC_K_MISC, 0, launch_set_phase_mask(B, O.active, w.alt, uout == w.r64 ? 1 : 0, nullptr, st));
         LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
         ucur = uout;
@@ -587,7 +615,10 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       LAUNCH(MLMC_K_MISC, 0, launch_copy<double>(n, B, w.r64, u, moved, st));
     } else {
       LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, u, 0.0, nullptr, st));
-      LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, w.r64, h3, nullptr, st));
+      if (bvec)
+        HIPCHK(hipMemcpyAsync(w.r64, bvec, (size_t)B * S0 * sizeof(double), hipMemcpyDeviceToDevice, st));
+      else
+        LAUNCH(MLMC_K_MISC, d * 8, launch_fill_interior<double>(n, B, w.r64, h3, nullptr, st));
       LAUNCH(MLMC_K_PCG_DOT, 2 * d * 8, (launch_dot<double>(n, B, w.r64, w.r64, O, &np, st)));
       LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_BB, 0.0, np, O, nullptr, st));
       for (int outer = 0; outer < kMaxOuter && total_it < ctx->cfg.max_iter; ++outer) {
@@ -606,7 +637,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
         total_it += it;
         LAUNCHM(MLMC_K_MISC, d * 20, O.active, B, launch_add_correction(n, B, u, w.d, O, st));
         LAUNCHM(MLMC_K_TRUE_RESIDUAL, (2 * d + e) * 8, O.active, B,
-                launch_true_residual(n, B, kap, h3, u, w.r64, O, &np, st, zv<double>(ctx)));
+                launch_true_residual(n, B, kap, h3, u, w.r64, O, &np, st, zv<double>(ctx), bvec));
         LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_RR, rtol * rtol, np, O, nullptr, st));
         int na = 0;
         if (int rc = count_active(ctx, O, B, &na)) return rc;
@@ -677,14 +708,24 @@ int run_level(mlmc_ctx* ctx, int level, uint64_t first, uint64_t count, double* 
     LAUNCH(MLMC_K_XI, (double)B * ctx->cfg.n_modes * 8,
            launch_draw_xi(ctx->cfg.seed, level, start, B, ctx->cfg.n_modes, w.xi, ctx->st));
     const bool mixed = ctx->cfg.precision != MLMC_PREC_FP64;
+    const bool forced = ctx->cfg.forcing == MLMC_FORCING_LOGNORMAL;
+    if (forced)
+      if (int rc = forcing_impl(ctx, nf, level, start, B, w.xif, w.fe, w.bf)) return rc;
     if (int rc = field_impl(ctx, nf, B, w.xi, w.kf, mixed ? w.wf.L32[0].kap : nullptr)) return rc;
     bool conv = false;
-    if (int rc = solve_impl(ctx, w.wf, w.kf, w.uf, iters ? iters + done : nullptr, &conv, mixed)) return rc;
+    if (int rc = solve_impl(ctx, w.wf, w.kf, w.uf, iters ? iters + done : nullptr, &conv, mixed,
+                            forced ? w.bf : nullptr))
+      return rc;
     all_conv = all_conv && conv;
     if (int rc = qoi_impl(ctx, w.wf.outer.s, nf, B, w.uf, w.qf)) return rc;
     if (level > 0) {
+      if (forced) {   // the same xi_f on the coarse mesh
+        if (int rc = field_impl(ctx, nf / 2, B, w.xif, w.fe, nullptr, true)) return rc;
+        LAUNCH(MLMC_K_MISC, (double)B * (elems(nf / 2) + grid_stride(nf / 2)) * 8,
+               launch_load(nf / 2, B, w.fe, w.bc, ctx->st));
+      }
       if (int rc = field_impl(ctx, nf / 2, B, w.xi, w.kc, mixed ? w.wc.L32[0].kap : nullptr)) return rc;
-      if (int rc = solve_impl(ctx, w.wc, w.kc, w.uc, nullptr, &conv, mixed)) return rc;
+      if (int rc = solve_impl(ctx, w.wc, w.kc, w.uc, nullptr, &conv, mixed, forced ? w.bc : nullptr)) return rc;
       all_conv = all_conv && conv;
       if (int rc = qoi_impl(ctx, w.wc.outer.s, nf / 2, B, w.uc, w.qc)) return rc;
     }

@@ -176,6 +176,9 @@ struct BatchWork {
   double* xi = nullptr;
   double *kf = nullptr, *kc = nullptr, *uf = nullptr, *uc = nullptr;
   double *qf = nullptr, *qc = nullptr;
+  // random forcing: xi_f, the element values of f (fine mesh size, reused
+  // for the coarse mesh) and the load vectors of the two meshes
+  double *xif = nullptr, *fe = nullptr, *bf = nullptr, *bc = nullptr;
   SolveWork wf, wc;
 };
 
@@ -346,7 +349,8 @@ struct RUpdate {
   double tol2 = 0.0;
   bool first = false;
 };
-int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float* kap32);
+// exact: fp64 MFMA whatever the precision (the forcing's field)
+int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float* kap32, bool exact = false);
 // One V-cycle on levels l.. of L; returns the buffer that holds the result.
 // With `dot` the last smoothing step of level l also writes the partial sums
 // of b . result (*dot_np per sample).  zero_done: x already holds the first
@@ -404,8 +408,11 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
         int max_iter, int* done_iters, hipGraphExec_t* graph, T* p2 = nullptr, bool fresh = false,
         bool defer = false, T* r2 = nullptr);
 // kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
+// bvec: the right-hand side (grid layout, boundary positions 0), or NULL for f = 1
 int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
-               bool kap32_ready = false);
+               bool kap32_ready = false, const double* bvec = nullptr);
+// xi_f, f and the load vector b of B samples (first, level) on mesh n (random forcing)
+int forcing_impl(mlmc_ctx* ctx, int n, int level, uint64_t first, int B, double* xif, double* f, double* b);
 int qoi_impl(mlmc_ctx* ctx, SolveState& S, int n, int B, const double* u, double* q);
 bool mesh_of_config(const mlmc_ctx* ctx, int n);
 int run_level(mlmc_ctx* ctx, int level, uint64_t first, uint64_t count, double* y, double* q_fine, double* q_coarse,

@@ -8,8 +8,11 @@ namespace mlmc {
 
 // rng.hip
 hipError_t launch_draw_xi(uint64_t seed, int level, uint64_t first, int64_t count, int M,
-                          double* xi, hipStream_t st);
+                          double* xi, hipStream_t st, int stream = 0);
 // row r: sample ids[r] of level lv[r] into row slots[r] of xi
+// b = (h^3 / 8) sum of the 8 element values of f around each interior node of
+// mesh n (grid layout, boundary positions 0), B samples
+hipError_t launch_load(int n, int B, const double* f, double* b, hipStream_t st);
 hipError_t launch_pause_draw(uint64_t seed, int level, int64_t count, double a, double w, double* out,
                              hipStream_t st);
 // every workgroup w < nwg waits spin[w] ticks of the device wall clock and adds
@@ -179,7 +182,7 @@ hipError_t launch_pcg_direction(int n, int B, const T* z, T* p, SolveState s, hi
 // uout = u + d (u may be null: zero), rin = fp32(bconst - A uout), partial sums
 // of (bconst - A uout) . itself in fp64.  uout must not alias u or d.
 hipError_t launch_refine(int n, int B, const double* kap, double bconst, const double* u, const float* d,
-                         double* uout, float* rin, SolveState s, uint32_t* nparts, hipStream_t st, int var = 0);
+                         double* uout, float* rin, SolveState s, uint32_t* nparts, hipStream_t st, int var = 0, const double* bvec = nullptr);
 // launch_refine with the update the fused-direction inner solve still owes d
 // applied on the fly: the correction is d + alpha p (alpha p for a fresh d),
 // p the inner state's current direction (buffers p0/p1, inner.pstate,
@@ -187,10 +190,10 @@ hipError_t launch_refine(int n, int B, const double* kap, double bconst, const d
 bool refine_owed_usable(int n, int B, int var);
 hipError_t launch_refine_owed(int n, int B, const double* kap, double bconst, const double* u, const float* d,
                               const float* p0, const float* p1, SolveState inner, double* uout, float* rin,
-                              SolveState s, uint32_t* nparts, hipStream_t st);
+                              SolveState s, uint32_t* nparts, hipStream_t st, const double* bvec = nullptr);
 hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x,
                                 double* r, SolveState s, uint32_t* nparts, hipStream_t st,
-                                int var = 0);
+                                int var = 0, const double* bvec = nullptr);
 // p = z on active samples (vectorized copy of the planes 1..n-1 range)
 template <class T>
 hipError_t launch_copy(int n, int B, const T* z, T* p, SolveState s, hipStream_t st);

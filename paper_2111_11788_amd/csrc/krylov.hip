@@ -343,6 +343,31 @@ __global__ void __launch_bounds__(kBlock) k_node_map(int n, size_t stride, int32
   out[p] = interior ? (int32_t)((i - 1) + (size_t)m * ((j - 1) + (size_t)m * (k - 1))) : -1;
 }
 
+// load vector of an elementwise-constant forcing f (n^3 values per sample):
+// b = (h^3 / 8) sum of f over the 8 elements around an interior node (the
+// integral of its Q1 hat function over each element is h^3 / 8); every other
+// position of the grid layout, tail included, gets 0
+__global__ void __launch_bounds__(kBlock) k_load(int n, size_t stride, int64_t total, const double* __restrict__ f,
+                                                 double* __restrict__ b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int64_t s = t / (int64_t)stride;
+  const size_t p = (size_t)(t - s * (int64_t)stride);
+  const int lg = __builtin_ctz((unsigned)n);   // n is a power of two
+  const int i = (int)(p & (size_t)(n - 1)), j = (int)((p >> lg) & (size_t)(n - 1));
+  const size_t k = p >> (2 * lg);
+  double v = 0.0;
+  if (i >= 1 && j >= 1 && k >= 1 && k <= (size_t)(n - 1)) {
+    const size_t n2 = (size_t)n * n;
+    const double* fe = f + (size_t)s * n2 * n + (size_t)(i - 1) + (size_t)n * (j - 1) + n2 * (k - 1);
+    const double lo = (fe[0] + fe[1]) + (fe[n] + fe[n + 1]);
+    const double hi = (fe[n2] + fe[n2 + 1]) + (fe[n2 + n] + fe[n2 + n + 1]);
+    const double h = 1.0 / n;
+    v = (h * h * h * 0.125) * (lo + hi);
+  }
+  b[t] = v;
+}
+
 // per-slot masks of the serving phases
 __global__ void k_phase_masks(int S, const int* __restrict__ phase, int* __restrict__ inner, int* __restrict__ trans,
                               int* __restrict__ restart, int* __restrict__ done) {
@@ -486,6 +511,14 @@ hipError_t launch_reduce(int B, int op, double tol2, uint32_t nparts, SolveState
 hipError_t launch_node_map(int n, int32_t* out, hipStream_t st) {
   const size_t stride = grid_stride(n);
   k_node_map<<<dim3((unsigned)((stride + kBlock - 1) / kBlock)), kBlock, 0, st>>>(n, stride, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_load(int n, int B, const double* f, double* b, hipStream_t st) {
+  const size_t stride = grid_stride(n);
+  const int64_t total = (int64_t)B * (int64_t)stride;
+  if (total <= 0) return hipSuccess;
+  k_load<<<dim3((unsigned)((total + kBlock - 1) / kBlock)), kBlock, 0, st>>>(n, stride, total, f, b);
   return hipGetLastError();
 }
 

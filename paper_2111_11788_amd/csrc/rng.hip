@@ -108,9 +108,12 @@ __device__ void fixed_sincos_2pi(double u, const TrigCoeffs& tc, double* sv, dou
   }
 }
 
-// The four normals of Philox block (sample, level, j): two Box-Muller pairs.
-__device__ __forceinline__ void block_normals(uint64_t seed, uint64_t sample, uint64_t level, int j, double* z) {
-  const Block4 b = philox4x64_10(sample, level, (uint64_t)j, 0ull, seed, 0ull);
+// The four normals of Philox block (sample, level, j, stream): two Box-Muller
+// pairs.  Stream 0 draws xi, stream 2 the forcing's xi_f (stream 1 is the
+// pause model's).
+__device__ __forceinline__ void block_normals(uint64_t seed, uint64_t sample, uint64_t level, int j, double* z,
+                                              uint64_t stream = 0) {
+  const Block4 b = philox4x64_10(sample, level, (uint64_t)j, stream, seed, 0ull);
   const TrigCoeffs tc = trig_coeffs();
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
@@ -125,14 +128,15 @@ __device__ __forceinline__ void block_normals(uint64_t seed, uint64_t sample, ui
 
 // One thread per (sample, Philox block); xi row-major [count][M].
 __global__ void __launch_bounds__(kBlock) k_draw_xi(uint64_t seed, uint64_t level, uint64_t first,
-                                                    int64_t count, int M, double* __restrict__ xi) {
+                                                    int64_t count, int M, double* __restrict__ xi,
+                                                    uint64_t stream) {
   const int nblk = (M + 3) >> 2;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= count * nblk) return;
   const int64_t s = tid / nblk;
   const int j = (int)(tid - s * nblk);
   double z[4];
-  block_normals(seed, first + (uint64_t)s, level, j, z);
+  block_normals(seed, first + (uint64_t)s, level, j, z, stream);
   double* out = xi + s * M + 4 * j;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
@@ -189,11 +193,12 @@ hipError_t launch_draw_xi_rows(uint64_t seed, int64_t count, int M, const uint64
 }
 
 hipError_t launch_draw_xi(uint64_t seed, int level, uint64_t first, int64_t count, int M,
-                          double* xi, hipStream_t st) {
+                          double* xi, hipStream_t st, int stream) {
   const int64_t total = count * ((M + 3) / 4);
   if (total <= 0) return hipSuccess;
   const int64_t grid = (total + kBlock - 1) / kBlock;
-  k_draw_xi<<<dim3((unsigned)grid), dim3(kBlock), 0, st>>>(seed, (uint64_t)level, first, count, M, xi);
+  k_draw_xi<<<dim3((unsigned)grid), dim3(kBlock), 0, st>>>(seed, (uint64_t)level, first, count, M, xi,
+                                                           (uint64_t)stream);
   return hipGetLastError();
 }
 

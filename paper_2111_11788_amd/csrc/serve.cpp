@@ -336,6 +336,7 @@ int mlmc_serve_start(mlmc_ctx* ctx, const int32_t* slots_per_mesh) {
   if (!ctx) return MLMC_E_INVALID;
   if (ctx->server) FAIL(MLMC_E_INVALID, "already serving");
   if (ctx->cfg.solver != MLMC_SOLVER_GMG_PCG) FAIL(MLMC_E_INVALID, "serving runs the GMG-PCG solver");
+  if (ctx->cfg.forcing != MLMC_FORCING_CONSTANT) FAIL(MLMC_E_INVALID, "serving solves with f = 1");
   const int L = ctx->cfg.levels;
   std::vector<int> S(L, 0);
   const size_t avail = ctx->cfg.arena_bytes - ctx->persistent_top;

@@ -176,19 +176,24 @@ struct EpiPcgApply {
   }
 };
 
-// r = bconst - A x (fp64 outer residual), accumulate r . r
+// r = b - A x (fp64 outer residual), accumulate r . r; b is the constant
+// bconst, or the vector bvec when given
 template <class T, int V>
 struct EpiTrueResidual {
   static constexpr bool kReduce = true;
   static constexpr bool kBegin = false;
   T bconst;
   T* r;
-  __device__ void pre(size_t) {}
+  const T* bvec = nullptr;
+  T bl[V];
+  __device__ void pre(size_t pos) {
+    if (bvec) vload<T, V>(bvec + pos, bl);
+  }
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
     T o[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      o[v] = ok[v] ? bconst - au[v] : T(0);
+      o[v] = ok[v] ? (bvec ? bl[v] : bconst) - au[v] : T(0);
       acc += (double)o[v] * (double)o[v];
     }
     vstore<T, V>(r + pos, o);
@@ -206,13 +211,17 @@ struct EpiRefine {
   T bconst;
   T* uout;
   float* rin;
-  __device__ void pre(size_t) {}
+  const T* bvec = nullptr;   // the right-hand side vector, if not the constant bconst
+  T bl[V];
+  __device__ void pre(size_t pos) {
+    if (bvec) vload<T, V>(bvec + pos, bl);
+  }
   __device__ void operator()(size_t pos, const T* au, const T* dg, const T* uc, const bool* ok, double& acc) const {
     T us[V];
     float f[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      const T r = ok[v] ? bconst - au[v] : T(0);
+      const T r = ok[v] ? (bvec ? bl[v] : bconst) - au[v] : T(0);
       acc += (double)r * (double)r;
       f[v] = (float)r;
       us[v] = ok[v] ? uc[v] : T(0);
@@ -1895,9 +1904,10 @@ hipError_t launch_pcg_apply_dot(int n, int B, const T* kap, const T* p, T* q, So
 }
 
 hipError_t launch_refine(int n, int B, const double* kap, double bconst, const double* u, const float* d,
-                         double* uout, float* rin, SolveState s, uint32_t* nparts, hipStream_t st, int var) {
+                         double* uout, float* rin, SolveState s, uint32_t* nparts, hipStream_t st, int var,
+                         const double* bvec) {
   return zlaunch_addd<double>(n, B, u, d, kap, s.active, s.partial, s.pstride,
-                              EpiRefine<double, ZV<double>::V>{bconst, uout, rin}, nparts, var, st);
+                              EpiRefine<double, ZV<double>::V>{bconst, uout, rin, bvec}, nparts, var, st);
 }
 
 bool refine_owed_usable(int n, int B, int var) {
@@ -1906,7 +1916,7 @@ bool refine_owed_usable(int n, int B, int var) {
 
 hipError_t launch_refine_owed(int n, int B, const double* kap, double bconst, const double* u, const float* d,
                               const float* p0, const float* p1, SolveState inner, double* uout, float* rin,
-                              SolveState s, uint32_t* nparts, hipStream_t st) {
+                              SolveState s, uint32_t* nparts, hipStream_t st, const double* bvec) {
   if (!zlds_ok<double, OP_ADDD>(zgeom<double>(n, B))) return hipErrorInvalidValue;
   OpArgs<double> op;
   op.d = d;
@@ -1915,13 +1925,14 @@ hipError_t launch_refine_owed(int n, int B, const double* kap, double bconst, co
   op.dstate = inner.pstate;
   op.dalpha = inner.alpha;
   return zlaunch_lds<double, true, false, OP_ADDD>(n, B, u, nullptr, kap, s.active, s.partial, s.pstride,
-                                                   EpiRefine<double, ZV<double>::V>{bconst, uout, rin}, nparts, st, op);
+                                                   EpiRefine<double, ZV<double>::V>{bconst, uout, rin, bvec}, nparts, st,
+                                                   op);
 }
 
 hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, const double* x, double* r,
-                                SolveState s, uint32_t* nparts, hipStream_t st, int var) {
+                                SolveState s, uint32_t* nparts, hipStream_t st, int var, const double* bvec) {
   return zlaunch<double, true>(n, B, x, kap, s.active, s.partial, s.pstride,
-                               EpiTrueResidual<double, ZV<double>::V>{bconst, r}, nparts, var, st);
+                               EpiTrueResidual<double, ZV<double>::V>{bconst, r, bvec}, nparts, var, st);
 }
 
 template <class T>

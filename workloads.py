@@ -39,6 +39,7 @@ class Workload:
     batch: int = 0           # samples per batched solve (0: whole level)
     precision: int = 0       # 0: fp64; 1: fp32 GMG inner solve in fp64 refinement
     solver: int = 0          # 0: GMG-PCG; 1: Jacobi-PCG
+    forcing: int = 0         # 0: f = 1; 1: log-normal random f (own KLE coefficients)
     eps: Optional[float] = None  # target RMSE for the allocation formula
 
     def n(self, level: int) -> int:
