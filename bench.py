@@ -39,22 +39,23 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 TRAFFIC = {
     "profile": "profiles/batched-64cube-1024_hbm_traffic.txt",
     "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 8, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 1, "fuse": 63},
-    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "b39dc836a416fe0a", "kernels.hpp": "250c8d91d09a3b5e", "krylov.hip": "c30e8074544b98ca", "stencil.hip": "9ce92b54e775430f"},
+    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "b39dc836a416fe0a", "kernels.hpp": "c1fb1b4075b2075d", "krylov.hip": "3417955a34ecc56a", "stencil.hip": "f18d689eb84cf607"},
     "bytes_per_launch": {
-        "PCG_UPDATE (f32)": 2716865803,
-        "CHEB_PROLONG (f32)": 1283471857,
-        "RESIDUAL_RESTRICT (f32)": 944329044,
-        "PCG_APPLY (f32)": 6281385600,
-        "TRUE_RESIDUAL (f64)": 8676792209,
+        "PCG_UPDATE (f32)": 2716863866,
+        "CHEB_PROLONG (f32)": 1283292083,
+        "RESIDUAL_RESTRICT (f32)": 944448831,
+        "PCG_APPLY (f32)": 6281418207,
+        "TRUE_RESIDUAL (f64)": 8664096393,
     },
 }
 
 
 # the tuning choices a class's launch mix depends on, with the bits that matter
-# (None: the whole value); the LDS-engine bit of zvar selects the apply's engine
+# (None: the whole value); the LDS-engine bit of zvar selects the apply's
+# engine, the DIRECTION and REFINE fusion bits its form
 TRAFFIC_TUNING_KEYS = {
     "PCG_UPDATE (f32)": {"max_batch": None, "fuse": None},
-    "PCG_APPLY (f32)": {"max_batch": None, "zvar_fp32": 2, "fuse": None},
+    "PCG_APPLY (f32)": {"max_batch": None, "zvar_fp32": 2, "fuse": 32 | 4},
     "TRUE_RESIDUAL (f64)": {"max_batch": None, "zvar_fp64": 2, "fuse": None},
 }
 
