@@ -82,7 +82,8 @@ class ServeStats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("zvar_fp32", ctypes.c_int32), ("zvar_fp64", ctypes.c_int32), ("vsmall_fp32", ctypes.c_int32),
                 ("vsmall_fp64", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("graph_batch", ctypes.c_int32), ("fuse", ctypes.c_int32), ("seconds", ctypes.c_double)]
+                ("graph_batch", ctypes.c_int32), ("fuse", ctypes.c_int32), ("field", ctypes.c_int32),
+                ("seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -56,6 +56,8 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   cv.dry = false;
   ctx->d_sqrtlam = cv.take<double>(cfg->n_modes);
   ctx->d_triples = cv.take<int>(3 * (size_t)cfg->n_modes);
+  ctx->d_xperm = cv.take<int>((size_t)cfg->n_modes);
+  ctx->d_xoff = cv.take<int>((size_t)ctx->K1 + 1);
   ctx->prof_counts = cv.take<int>(mlmc_ctx::kProfCap);
   std::vector<double> sq(cfg->n_modes);
   for (int m = 0; m < cfg->n_modes; ++m) sq[m] = std::sqrt(ctx->modes.lambda[m]);
@@ -63,6 +65,18 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->d_triples, ctx->modes.triples.data(), ctx->modes.triples.size() * sizeof(int),
                        hipMemcpyHostToDevice, ctx->st);
+  // the modes grouped by their x-factor, for the separable evaluation
+  std::vector<int> xperm(cfg->n_modes), xoff(ctx->K1 + 1, 0);
+  for (int m = 0; m < cfg->n_modes; ++m) xoff[ctx->modes.triples[3 * m] + 1] += 1;
+  for (int a = 0; a < ctx->K1; ++a) xoff[a + 1] += xoff[a];
+  {
+    std::vector<int> fill(xoff.begin(), xoff.end() - 1);
+    for (int m = 0; m < cfg->n_modes; ++m) xperm[fill[ctx->modes.triples[3 * m]]++] = m;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->d_xperm, xperm.data(), xperm.size() * sizeof(int), hipMemcpyHostToDevice, ctx->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->d_xoff, xoff.data(), xoff.size() * sizeof(int), hipMemcpyHostToDevice, ctx->st);
   std::vector<std::vector<double>> tabs;
   for (int l = 0; l < cfg->levels && e == hipSuccess; ++l) {
     const int n = cfg->n0 << l;

@@ -54,6 +54,8 @@ size_t persistent_bytes(const mlmc_config* c, int K1) {
   Carver cv;
   cv.take<double>(c->n_modes);
   cv.take<int>(3 * (size_t)c->n_modes);
+  cv.take<int>((size_t)c->n_modes);
+  cv.take<int>((size_t)K1 + 1);
   cv.take<int>(mlmc_ctx::kProfCap);
   for (int l = 0; l < c->levels; ++l) cv.take<double>((size_t)(c->n0 << l) * K1);
   return cv.top;
@@ -144,13 +146,19 @@ int ensure_tables(mlmc_ctx* ctx, int n, double** tab) {
   return MLMC_OK;
 }
 
+bool field_separable(const mlmc_ctx* ctx, int64_t count) {
+  const int k = ctx->field_kernel;
+  return k == 2 || (k == 0 && (ctx->cfg.n_modes >= 256 || count < 48));
+}
+
 int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float* kap32, bool exact) {
   double* tab = nullptr;
   if (int rc = ensure_tables(ctx, n, &tab)) return rc;
   const int M = ctx->cfg.n_modes;
   LAUNCH(MLMC_K_FIELD, (double)B * elems(n) * (8.0 + (kap32 ? 4.0 : 0.0)) + (double)B * M * 8.0,
          launch_field(n, M, B, xi, ctx->d_sqrtlam, ctx->d_triples, tab, ctx->K1, kap, kap32, ctx->st, nullptr,
-                      !exact && ctx->cfg.precision == MLMC_PREC_MIXED_BF16KLE));
+                      !exact && ctx->cfg.precision == MLMC_PREC_MIXED_BF16KLE,
+                      field_separable(ctx, B) ? ctx->d_xperm : nullptr, ctx->d_xoff));
   return MLMC_OK;
 }
 
@@ -762,6 +770,7 @@ int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (t->cheb_degree < 1 || t->cheb_degree > 8) { why = "cheb_degree must be in 1..8"; return MLMC_E_INVALID; }
   if (t->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
   if (t->graph_batch < 0 || t->graph_batch > 16) { why = "graph_batch must be in 0..16"; return MLMC_E_INVALID; }
+  if (t->field < 0 || t->field > 2) { why = "field must be 0 (auto), 1 (MFMA GEMM) or 2 (separable)"; return MLMC_E_INVALID; }
   if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
                    MLMC_FUSE_DIRECTION | MLMC_FUSE_RUPDATE)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
   return MLMC_OK;
@@ -777,6 +786,7 @@ mlmc_tuning current_tuning(const mlmc_ctx* ctx) {
   t.max_batch = ctx->cfg.max_batch;
   t.graph_batch = ctx->use_graphs ? ctx->graph_batch : 0;
   t.fuse = ctx->fuse;
+  t.field = ctx->field_kernel;
   t.seconds = 0.0;
   return t;
 }
@@ -794,6 +804,7 @@ void apply_tuning(mlmc_ctx* ctx, const mlmc_tuning& t) {
   ctx->use_graphs = t.graph_batch > 0;
   ctx->graph_batch = std::max(1, t.graph_batch);
   ctx->fuse = t.fuse;
+  ctx->field_kernel = t.field;
   // captured graphs bake in kernel choices: drop them
   ctx->sw.release_graphs();
   ctx->bw.wf.release_graphs();

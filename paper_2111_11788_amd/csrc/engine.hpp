@@ -219,6 +219,9 @@ struct mlmc_ctx {
   int K1 = 0;
   double* d_sqrtlam = nullptr;
   int* d_triples = nullptr;
+  int* d_xperm = nullptr;         // the modes ordered by their x-factor (stable)
+  int* d_xoff = nullptr;          // [K1 + 1]: modes of x-factor a at d_xperm[xoff[a] .. xoff[a + 1])
+  int field_kernel = 0;           // mlmc_tuning.field
   std::map<int, double*> d_tab;
   size_t persistent_top = 0;
   ChebCoeffs cheb;
@@ -349,7 +352,9 @@ struct RUpdate {
   double tol2 = 0.0;
   bool first = false;
 };
-// exact: fp64 MFMA whatever the precision (the forcing's field)
+// whether the fp64 KLE of `count` samples takes the separable evaluation (mlmc_tuning.field)
+bool field_separable(const mlmc_ctx* ctx, int64_t count);
+// exact: fp64 whatever the precision (the forcing's field)
 int field_impl(mlmc_ctx* ctx, int n, int B, const double* xi, double* kap, float* kap32, bool exact = false);
 // One V-cycle on levels l.. of L; returns the buffer that holds the result.
 // With `dot` the last smoothing step of level l also writes the partial sums

@@ -213,13 +213,87 @@ __global__ void __launch_bounds__(256) k_field_bf16(int n, int M, int64_t count,
   }
 }
 
+// ------------------------------------------------------------ separable form
+// The modes are products phi_i(x) phi_j(y) phi_k(z), so on one x-row of
+// elements (fixed ey, ez)
+//   g[s][ex] = sum_a phi_a(x_ex) H[s][a],
+//   H[s][a]  = sum over the modes m with x-factor a of xi[s][m] sqrt(lambda_m) phi_j(y) phi_k(z):
+// M products per sample and row, then K1 (distinct x-factors, <= 16 for 512
+// modes at correlation length 0.1) per element, against M per element for the
+// dense contraction.  One workgroup per (x-row, block of S samples); w (the
+// y-z factors of the row, in x-grouped mode order) and H live in LDS; every
+// sum runs in a fixed order, so a sample's field does not depend on its batch.
+template <int S>
+__global__ void __launch_bounds__(256) k_field_sep(int n, int M, int K1, int64_t count,
+                                                   const double* __restrict__ xi,
+                                                   const double* __restrict__ sqrtlam,
+                                                   const int* __restrict__ triples,
+                                                   const int* __restrict__ xperm, const int* __restrict__ xoff,
+                                                   const double* __restrict__ tab, double* __restrict__ kappa,
+                                                   float* __restrict__ kappa32, const int* __restrict__ rowmap) {
+  extern __shared__ double fsm[];
+  double* w = fsm;            // [M]
+  double* H = fsm + M;        // [S][K1]
+  const int lg = 31 - __clz(n);
+  const int row = (int)blockIdx.x;               // ey + n ez
+  const int ey = row & (n - 1), ez = row >> lg;
+  const int64_t s0 = (int64_t)blockIdx.y * S;
+  const int tid = (int)threadIdx.x;
+  for (int p = tid; p < M; p += 256) {
+    const int m = xperm[p];
+    w[p] = sqrtlam[m] * (tab[ey * K1 + triples[3 * m + 1]] * tab[ez * K1 + triples[3 * m + 2]]);
+  }
+  __syncthreads();
+  for (int q = tid; q < S * K1; q += 256) {
+    const int s = q / K1, a = q - (q / K1) * K1;
+    double hv = 0.0;
+    if (s0 + s < count) {
+      const int64_t r = rowmap ? rowmap[s0 + s] : s0 + s;
+      const double* x = xi + r * M;
+      for (int p = xoff[a]; p < xoff[a + 1]; ++p) hv += x[xperm[p]] * w[p];
+    }
+    H[q] = hv;
+  }
+  __syncthreads();
+  const int64_t ne = (int64_t)n * n * n;
+  for (int q = tid; q < S * n; q += 256) {
+    const int s = q >> lg, ex = q & (n - 1);
+    if (s0 + s >= count) continue;
+    const double* hs = H + s * K1;
+    const double* tx = tab + ex * K1;
+    double g = 0.0;
+    for (int a = 0; a < K1; ++a) g += hs[a] * tx[a];
+    const int64_t r = rowmap ? rowmap[s0 + s] : s0 + s;
+    const double k = exp(g);
+    const int64_t e = (int64_t)row * n + ex;
+    kappa[r * ne + e] = k;
+    if (kappa32) kappa32[r * ne + e] = (float)k;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_field(int n, int M, int64_t count, const double* xi, const double* sqrtlam,
                         const int* triples, const double* tab, int K1, double* kappa,
-                        float* kappa32, hipStream_t st, const int* rowmap, bool bf16) {
+                        float* kappa32, hipStream_t st, const int* rowmap, bool bf16, const int* xperm,
+                        const int* xoff) {
   if (count <= 0) return hipSuccess;
   const int64_t ne = (int64_t)n * n * n;
+  if (!bf16 && xperm && xoff) {
+    const int S = count >= 48 ? 64 : 16;
+    const size_t lds = (size_t)(M + S * K1) * sizeof(double);
+    if (lds <= 65536) {
+      dim3 grid((unsigned)((int64_t)n * n), (unsigned)((count + S - 1) / S));
+      if (S == 64)
+        k_field_sep<64><<<grid, dim3(256), lds, st>>>(n, M, K1, count, xi, sqrtlam, triples, xperm, xoff, tab, kappa,
+                                                      kappa32, rowmap);
+      else
+        k_field_sep<16><<<grid, dim3(256), lds, st>>>(n, M, K1, count, xi, sqrtlam, triples, xperm, xoff, tab, kappa,
+                                                      kappa32, rowmap);
+      return hipGetLastError();
+    }
+    // the row's factors and sums exceed the LDS of a workgroup: the dense form
+  }
   if (bf16) {
     if (count >= 48) {
       dim3 grid((unsigned)((ne + 63) / 64), (unsigned)((count + 63) / 64));

@@ -24,9 +24,12 @@ hipError_t launch_draw_xi_rows(uint64_t seed, int64_t count, int M, const uint64
 // field.hip: kappa[b][e] = exp(sum_m xi[b][m] sqrtlam[m] tab[ex][t0] tab[ey][t1] tab[ez][t2])
 // rowmap (may be null): row r reads xi row rowmap[r] and writes kappa slot rowmap[r]
 // bf16: the contraction with bf16 operands and fp32 accumulation
+// xperm/xoff (not bf16): the separable evaluation (modes grouped by x-factor)
+// instead of the dense MFMA GEMM
 hipError_t launch_field(int n, int M, int64_t count, const double* xi, const double* sqrtlam,
                         const int* triples, const double* tab, int K1, double* kappa,
-                        float* kappa32, hipStream_t st, const int* rowmap = nullptr, bool bf16 = false);
+                        float* kappa32, hipStream_t st, const int* rowmap = nullptr, bool bf16 = false,
+                        const int* xperm = nullptr, const int* xoff = nullptr);
 
 // Per-sample scalar state of a batched Krylov solve (device arrays of B entries).
 struct SolveState {

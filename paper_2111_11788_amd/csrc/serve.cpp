@@ -146,7 +146,8 @@ int setup_slots(Pool& p, int c) {
   if (int rc = ensure_tables(ctx, n, &tab)) return rc;
   auto& L = p.w.L32;
   SRV_LAUNCH(launch_field(n, ctx->cfg.n_modes, c, p.xi, ctx->d_sqrtlam, ctx->d_triples, tab, ctx->K1, p.kap64,
-                          L[0].kap, st, p.d_slots, ctx->cfg.precision == MLMC_PREC_MIXED_BF16KLE));
+                          L[0].kap, st, p.d_slots, ctx->cfg.precision == MLMC_PREC_MIXED_BF16KLE,
+                          field_separable(ctx, c) ? ctx->d_xperm : nullptr, ctx->d_xoff));
   for (size_t l = 1; l < L.size(); ++l)
     SRV_LAUNCH(launch_coarsen<float>(L[l - 1].n, S, L[l - 1].kap, L[l].kap, st, p.m_new));
   SRV_LAUNCH(launch_fill_interior<double>(n, S, p.u, 0.0, p.m_new, st));

@@ -76,9 +76,11 @@ def test_modes_match_oracle(dev, corr, M, sigma2):
 
 
 @pytest.mark.parametrize("n,M,corr,count", [(4, 8, 0.5, 3), (8, 13, 0.3, 70), (16, 64, 0.3, 17), (32, 130, 0.2, 5)])
-def test_field_matches_oracle(dev, n, M, corr, count):
+@pytest.mark.parametrize("fk", [0, 1, 2])
+def test_field_matches_oracle(dev, n, M, corr, count, fk):
     wl = _wl(n0=n, levels=1, n_modes=M, corr_len=corr)
     ctx = mm.Context(wl, arena_bytes=64 << 20)
+    ctx.set_tuning(field=fk)   # 0: automatic choice, 1: dense MFMA GEMM, 2: separable evaluation
     xi = ctx.draw_xi(0, 3, count)
     k, k32 = ctx.field(n, xi, want32=True)
     want = field.kappa(n, corr, 1.0, M, rng.draw_xi(wl.seed, 0, 3, count, M))
