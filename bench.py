@@ -39,13 +39,13 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 TRAFFIC = {
     "profile": "profiles/batched-64cube-1024_hbm_traffic.txt",
     "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 8, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 1, "fuse": 63},
-    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "b39dc836a416fe0a", "kernels.hpp": "c1fb1b4075b2075d", "krylov.hip": "3417955a34ecc56a", "stencil.hip": "f18d689eb84cf607"},
+    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "b39dc836a416fe0a", "kernels.hpp": "6949e123dc70598a", "krylov.hip": "3417955a34ecc56a", "stencil.hip": "f18d689eb84cf607"},
     "bytes_per_launch": {
-        "PCG_UPDATE (f32)": 2716863866,
-        "CHEB_PROLONG (f32)": 1283292083,
-        "RESIDUAL_RESTRICT (f32)": 944448831,
-        "PCG_APPLY (f32)": 6281418207,
-        "TRUE_RESIDUAL (f64)": 8664096393,
+        "PCG_UPDATE (f32)": 2716864207,
+        "CHEB_PROLONG (f32)": 1283728431,
+        "RESIDUAL_RESTRICT (f32)": 944499854,
+        "PCG_APPLY (f32)": 6281112257,
+        "TRUE_RESIDUAL (f64)": 8659779600,
     },
 }
 
