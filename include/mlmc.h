@@ -350,11 +350,11 @@ typedef struct mlmc_tuning {
   int32_t max_batch;      /* samples per batched solve */
   int32_t graph_batch;    /* captured PCG iterations replayed per convergence check (0: no graphs) */
   int32_t fuse;           /* MLMC_FUSE_* bits: kernel fusions in use (default: all but RUPDATE) */
-  int32_t field;          /* fp64 KLE evaluation: 1 the dense MFMA tile GEMM; 2 separable (per x-row of
-                             elements, H = xi sqrt(lambda) phi_y phi_z summed over the modes of each
-                             x-factor, then g = H phi_x); 0 (default) separable for >= 256 modes or
-                             fewer than 48 samples (where the 16-sample MFMA tiles run mostly empty),
-                             the GEMM otherwise; the bf16 precision always uses its MFMA GEMM */
+  int32_t field;          /* fp64 KLE evaluation: 1 the dense MFMA tile GEMM; 0 (default) or 2 separable
+                             (per x-row of elements, H = xi sqrt(lambda) phi_y phi_z summed over the
+                             modes of each x-factor, then g = H phi_x), or the GEMM when one sample's
+                             coefficients and the mesh's x-table do not fit a workgroup's LDS; the
+                             bf16 precision always uses its MFMA GEMM */
   double seconds;         /* mlmc_autotune: measured seconds per sample of the chosen setting */
 } mlmc_tuning;
 

@@ -14,6 +14,8 @@
 // B[l / 16][l % 16]; accumulator element r of lane l holds D[l / 16 + 4 r][l % 16].
 // Rows = samples, columns = elements, K = modes.  An optional row map sends
 // row r to batch slot rowmap[r] (xi read from and kappa written to that slot).
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -220,11 +222,14 @@ __global__ void __launch_bounds__(256) k_field_bf16(int n, int M, int64_t count,
 //   H[s][a]  = sum over the modes m with x-factor a of xi[s][m] sqrt(lambda_m) phi_j(y) phi_k(z):
 // M products per sample and row, then K1 (distinct x-factors, <= 16 for 512
 // modes at correlation length 0.1) per element, against M per element for the
-// dense contraction.  One workgroup per (x-row, block of S samples); w (the
-// y-z factors of the row, in x-grouped mode order) and H live in LDS; every
-// sum runs in a fixed order, so a sample's field does not depend on its batch.
-template <int S>
-__global__ void __launch_bounds__(256) k_field_sep(int n, int M, int K1, int64_t count,
+// dense contraction.  A workgroup takes S samples and R consecutive x-rows:
+// it stages the samples' xi in x-grouped mode order into LDS once, then per
+// row forms w (the row's y-z factors, sqrt(lambda) included), H and the row's
+// elements.  Every sum runs in a fixed order, so a sample's field does not
+// depend on its batch.
+constexpr int kSepRows = 8;   // x-rows per workgroup
+
+__global__ void __launch_bounds__(256) k_field_sep(int n, int M, int K1, int S, int64_t count,
                                                    const double* __restrict__ xi,
                                                    const double* __restrict__ sqrtlam,
                                                    const int* __restrict__ triples,
@@ -232,42 +237,57 @@ __global__ void __launch_bounds__(256) k_field_sep(int n, int M, int K1, int64_t
                                                    const double* __restrict__ tab, double* __restrict__ kappa,
                                                    float* __restrict__ kappa32, const int* __restrict__ rowmap) {
   extern __shared__ double fsm[];
-  double* w = fsm;            // [M]
-  double* H = fsm + M;        // [S][K1]
+  double* X = fsm;            // [S][M]: xi of the block, x-grouped order
+  double* w = X + S * M;      // [M]
+  double* H = w + M;          // [S][K1]
+  double* T = H + S * K1;     // [K1][n]: phi_a(x_ex), transposed so a row's lanes read consecutive words
   const int lg = 31 - __clz(n);
-  const int row = (int)blockIdx.x;               // ey + n ez
-  const int ey = row & (n - 1), ez = row >> lg;
+  const int nrows = n * n;
+  const int row0 = (int)blockIdx.x * kSepRows;
   const int64_t s0 = (int64_t)blockIdx.y * S;
   const int tid = (int)threadIdx.x;
-  for (int p = tid; p < M; p += 256) {
-    const int m = xperm[p];
-    w[p] = sqrtlam[m] * (tab[ey * K1 + triples[3 * m + 1]] * tab[ez * K1 + triples[3 * m + 2]]);
-  }
-  __syncthreads();
-  for (int q = tid; q < S * K1; q += 256) {
-    const int s = q / K1, a = q - (q / K1) * K1;
-    double hv = 0.0;
+  for (int q = tid; q < S * M; q += 256) {
+    const int s = q / M, p = q - (q / M) * M;
+    double v = 0.0;
     if (s0 + s < count) {
       const int64_t r = rowmap ? rowmap[s0 + s] : s0 + s;
-      const double* x = xi + r * M;
-      for (int p = xoff[a]; p < xoff[a + 1]; ++p) hv += x[xperm[p]] * w[p];
+      v = xi[r * M + xperm[p]];
     }
-    H[q] = hv;
+    X[q] = v;
   }
-  __syncthreads();
+  for (int q = tid; q < K1 * n; q += 256) {
+    const int a = q >> lg, ex = q & (n - 1);
+    T[q] = tab[ex * K1 + a];
+  }
   const int64_t ne = (int64_t)n * n * n;
-  for (int q = tid; q < S * n; q += 256) {
-    const int s = q >> lg, ex = q & (n - 1);
-    if (s0 + s >= count) continue;
-    const double* hs = H + s * K1;
-    const double* tx = tab + ex * K1;
-    double g = 0.0;
-    for (int a = 0; a < K1; ++a) g += hs[a] * tx[a];
-    const int64_t r = rowmap ? rowmap[s0 + s] : s0 + s;
-    const double k = exp(g);
-    const int64_t e = (int64_t)row * n + ex;
-    kappa[r * ne + e] = k;
-    if (kappa32) kappa32[r * ne + e] = (float)k;
+  for (int row = row0; row < row0 + kSepRows && row < nrows; ++row) {
+    const int ey = row & (n - 1), ez = row >> lg;
+    __syncthreads();   // X staged; the previous row's H no longer read
+    for (int p = tid; p < M; p += 256) {
+      const int m = xperm[p];
+      w[p] = sqrtlam[m] * (tab[ey * K1 + triples[3 * m + 1]] * tab[ez * K1 + triples[3 * m + 2]]);
+    }
+    __syncthreads();
+    for (int q = tid; q < S * K1; q += 256) {
+      const int s = q / K1, a = q - (q / K1) * K1;
+      const double* x = X + s * M;
+      double hv = 0.0;
+      for (int p = xoff[a]; p < xoff[a + 1]; ++p) hv += x[p] * w[p];
+      H[q] = hv;
+    }
+    __syncthreads();
+    for (int q = tid; q < S * n; q += 256) {
+      const int s = q >> lg, ex = q & (n - 1);
+      if (s0 + s >= count) continue;
+      const double* hs = H + s * K1;
+      double g = 0.0;
+      for (int a = 0; a < K1; ++a) g += hs[a] * T[a * n + ex];
+      const int64_t r = rowmap ? rowmap[s0 + s] : s0 + s;
+      const double k = exp(g);
+      const int64_t e = (int64_t)row * n + ex;
+      kappa[r * ne + e] = k;
+      if (kappa32) kappa32[r * ne + e] = (float)k;
+    }
   }
 }
 
@@ -280,19 +300,18 @@ hipError_t launch_field(int n, int M, int64_t count, const double* xi, const dou
   if (count <= 0) return hipSuccess;
   const int64_t ne = (int64_t)n * n * n;
   if (!bf16 && xperm && xoff) {
-    const int S = count >= 48 ? 64 : 16;
-    const size_t lds = (size_t)(M + S * K1) * sizeof(double);
-    if (lds <= 65536) {
-      dim3 grid((unsigned)((int64_t)n * n), (unsigned)((count + S - 1) / S));
-      if (S == 64)
-        k_field_sep<64><<<grid, dim3(256), lds, st>>>(n, M, K1, count, xi, sqrtlam, triples, xperm, xoff, tab, kappa,
-                                                      kappa32, rowmap);
-      else
-        k_field_sep<16><<<grid, dim3(256), lds, st>>>(n, M, K1, count, xi, sqrtlam, triples, xperm, xoff, tab, kappa,
-                                                      kappa32, rowmap);
+    // samples per workgroup: as many as fit 64 KiB of LDS with the row's
+    // factors and the transposed x-table, at most 64
+    const int64_t room = (65536 / (int64_t)sizeof(double) - M - (int64_t)K1 * n) / (M + K1);
+    int S = (int)std::min<int64_t>({64, room, count});
+    const size_t lds = ((size_t)S * M + M + (size_t)S * K1 + (size_t)K1 * n) * sizeof(double);
+    if (S >= 1) {
+      dim3 grid((unsigned)(((int64_t)n * n + kSepRows - 1) / kSepRows), (unsigned)((count + S - 1) / S));
+      k_field_sep<<<grid, dim3(256), lds, st>>>(n, M, K1, S, count, xi, sqrtlam, triples, xperm, xoff, tab, kappa,
+                                                 kappa32, rowmap);
       return hipGetLastError();
     }
-    // the row's factors and sums exceed the LDS of a workgroup: the dense form
+    // the block's coefficients and sums exceed the LDS of a workgroup: the dense form
   }
   if (bf16) {
     if (count >= 48) {
