@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(256) k_field_bf16(int n, int M, int64_t count,
 // row forms w (the row's y-z factors, sqrt(lambda) included), H and the row's
 // elements.  Every sum runs in a fixed order, so a sample's field does not
 // depend on its batch.
-constexpr int kSepRows = 8;   // x-rows per workgroup
+constexpr int kSepRows = 16;   // x-rows per workgroup
 
 __global__ void __launch_bounds__(256) k_field_sep(int n, int M, int K1, int S, int64_t count,
                                                    const double* __restrict__ xi,
@@ -301,9 +301,10 @@ hipError_t launch_field(int n, int M, int64_t count, const double* xi, const dou
   const int64_t ne = (int64_t)n * n * n;
   if (!bf16 && xperm && xoff) {
     // samples per workgroup: as many as fit 64 KiB of LDS with the row's
-    // factors and the transposed x-table, at most 64
+    // factors and the transposed x-table, at most 32 (more workgroups per CU
+    // measured faster than larger blocks)
     const int64_t room = (65536 / (int64_t)sizeof(double) - M - (int64_t)K1 * n) / (M + K1);
-    int S = (int)std::min<int64_t>({64, room, count});
+    int S = (int)std::min<int64_t>({32, room, count});
     const size_t lds = ((size_t)S * M + M + (size_t)S * K1 + (size_t)K1 * n) * sizeof(double);
     if (S >= 1) {
       dim3 grid((unsigned)(((int64_t)n * n + kSepRows - 1) / kSepRows), (unsigned)((count + S - 1) / S));
