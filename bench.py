@@ -41,11 +41,11 @@ TRAFFIC = {
     "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 8, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 1, "fuse": 63},
     "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "b39dc836a416fe0a", "kernels.hpp": "6949e123dc70598a", "krylov.hip": "3417955a34ecc56a", "stencil.hip": "f18d689eb84cf607"},
     "bytes_per_launch": {
-        "PCG_UPDATE (f32)": 2716864207,
-        "CHEB_PROLONG (f32)": 1283728431,
-        "RESIDUAL_RESTRICT (f32)": 944499854,
-        "PCG_APPLY (f32)": 6281112257,
-        "TRUE_RESIDUAL (f64)": 8659779600,
+        "PCG_UPDATE (f32)": 2716866556,
+        "CHEB_PROLONG (f32)": 1283449117,
+        "RESIDUAL_RESTRICT (f32)": 944473000,
+        "PCG_APPLY (f32)": 6281059311,
+        "TRUE_RESIDUAL (f64)": 8659164603,
     },
 }
 
