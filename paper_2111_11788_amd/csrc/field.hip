@@ -306,7 +306,7 @@ hipError_t launch_field(int n, int M, int64_t count, const double* xi, const dou
     const int64_t room = (65536 / (int64_t)sizeof(double) - M - (int64_t)K1 * n) / (M + K1);
     int S = (int)std::min<int64_t>({32, room, count});
     const size_t lds = ((size_t)S * M + M + (size_t)S * K1 + (size_t)K1 * n) * sizeof(double);
-    if (S >= 1) {
+    if (S >= 1 && (count + S - 1) / S <= 65535) {   // grid y within the launch limit
       dim3 grid((unsigned)(((int64_t)n * n + kSepRows - 1) / kSepRows), (unsigned)((count + S - 1) / S));
       k_field_sep<<<grid, dim3(256), lds, st>>>(n, M, K1, S, count, xi, sqrtlam, triples, xperm, xoff, tab, kappa,
                                                  kappa32, rowmap);
