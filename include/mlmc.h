@@ -373,7 +373,10 @@ enum {
                               direction buffers); the last x update of a solve runs after it */
   MLMC_FUSE_RUPDATE = 64   /* with DIRECTION and PRESMOOTH: the PCG update r -= alpha q is formed inside
                               the next iteration's first V-cycle kernel (residual restriction), which
-                              writes r to the other of two residual buffers and tests convergence */
+                              writes r to the other of two residual buffers and tests convergence */,
+  MLMC_FUSE_SOLVE = 128    /* mixed precision with GMG on a 4^3 or 8^3 mesh: the whole solve of a sample
+                              (fp64 refinement, fp32 PCG, V-cycle) in one workgroup with every vector in
+                              LDS, one launch per batch; needs vsmall_fp32 >= the mesh */
 };
 
 int mlmc_get_tuning(const mlmc_ctx* ctx, mlmc_tuning* out);
@@ -473,7 +476,7 @@ enum {
   MLMC_K_RESIDUAL, MLMC_K_RESTRICT, MLMC_K_PROLONG, MLMC_K_COARSEST, MLMC_K_COARSEN,
   MLMC_K_PCG_APPLY, MLMC_K_PCG_UPDATE, MLMC_K_PCG_DOT, MLMC_K_PCG_DIRECTION,
   MLMC_K_TRUE_RESIDUAL, MLMC_K_REDUCE, MLMC_K_QOI, MLMC_K_MISC, MLMC_K_CHEB_PROLONG,
-  MLMC_K_PCG_UPDATE_ZERO, MLMC_K_RESIDUAL_RESTRICT, MLMC_K_COUNT
+  MLMC_K_PCG_UPDATE_ZERO, MLMC_K_RESIDUAL_RESTRICT, MLMC_K_SOLVE_SMALL, MLMC_K_COUNT
 };
 int mlmc_set_profiling(mlmc_ctx* ctx, int32_t on);
 int mlmc_kernel_time(mlmc_ctx* ctx, int32_t kernel_id, int32_t precision, int64_t* launches,

@@ -23,7 +23,7 @@ ERRORS = {-1: "MLMC_E_INVALID", -2: "MLMC_E_NOMEM", -3: "MLMC_E_BUDGET", -4: "ML
 KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "RESTRICT", "PROLONG",
            "COARSEST", "COARSEN", "PCG_APPLY", "PCG_UPDATE", "PCG_DOT", "PCG_DIRECTION", "TRUE_RESIDUAL",
            "REDUCE", "QOI", "MISC", "CHEB_PROLONG", "PCG_UPDATE_ZERO",
-           "RESIDUAL_RESTRICT"]
+           "RESIDUAL_RESTRICT", "SOLVE_SMALL"]
 
 # exported symbols of include/mlmc.h (checked by the CPU test suite)
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",

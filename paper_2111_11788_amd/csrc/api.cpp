@@ -330,8 +330,10 @@ int mlmc_autotune(mlmc_ctx* ctx, int32_t level, int32_t batch, mlmc_tuning* best
     mlmc_tuning c = best; c.vsmall_fp32 = v; c.vsmall_fp64 = std::min(v, 8);
     if (int rc = trial(c)) return rc;
   }
+  const int nf = ctx->cfg.n0 << level, nc = level > 0 ? nf / 2 : 0;
   for (int f : {MLMC_FUSE_PROLONG, MLMC_FUSE_UPDATE, MLMC_FUSE_REFINE, MLMC_FUSE_RESTRICT, MLMC_FUSE_PRESMOOTH,
-                MLMC_FUSE_DIRECTION, MLMC_FUSE_RUPDATE}) {
+                MLMC_FUSE_DIRECTION, MLMC_FUSE_RUPDATE, MLMC_FUSE_SOLVE}) {
+    if (f == MLMC_FUSE_SOLVE && nf > 8 && !(nc >= 4 && nc <= 8)) continue;   // no 4^3 or 8^3 solve here
     mlmc_tuning c = best; c.fuse ^= f;
     if (int rc = trial(c)) return rc;
   }

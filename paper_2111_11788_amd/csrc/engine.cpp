@@ -554,6 +554,13 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
       if (int rc = count_active(ctx, O, B, &na)) return rc;
       if (na == 0) break;
     }
+  } else if ((ctx->fuse & MLMC_FUSE_SOLVE) && ctx->cfg.solver == MLMC_SOLVER_GMG_PCG && (n == 4 || n == 8) &&
+             ctx->vsmall_n0[1] >= n) {
+    // the whole solve of each sample in one workgroup (all vectors in LDS)
+    const ChebCoeffs& ch = ctx->cheb;
+    LAUNCH(MLMC_K_SOLVE_SMALL, (e * 8 + d * 8 * (bvec ? 2 : 1)),
+           launch_solve_small(n, B, ch.degree, ch.c1, ch.c2, kap, bvec, h3, u, O.active, O.iters, rtol, kInnerRtol,
+                              ctx->cfg.max_iter, kMaxOuter, st));
   } else {
     auto& L = w.L32;
     SolveState& I = w.inner.s;
@@ -772,7 +779,7 @@ int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (t->graph_batch < 0 || t->graph_batch > 16) { why = "graph_batch must be in 0..16"; return MLMC_E_INVALID; }
   if (t->field < 0 || t->field > 2) { why = "field must be 0 (auto), 1 (MFMA GEMM) or 2 (separable)"; return MLMC_E_INVALID; }
   if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
-                   MLMC_FUSE_DIRECTION | MLMC_FUSE_RUPDATE)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
+                   MLMC_FUSE_DIRECTION | MLMC_FUSE_RUPDATE | MLMC_FUSE_SOLVE)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
   return MLMC_OK;
 }
 

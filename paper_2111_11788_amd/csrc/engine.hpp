@@ -252,7 +252,7 @@ struct mlmc_ctx {
   // kernel, so each solve runs one more residual restriction) and is left to
   // the autotuner
   int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
-             MLMC_FUSE_DIRECTION;
+             MLMC_FUSE_DIRECTION | MLMC_FUSE_SOLVE;
   mlmc_server* server = nullptr;  // serving pools and threads while serving
 };
 

@@ -13,6 +13,15 @@ hipError_t launch_draw_xi(uint64_t seed, int level, uint64_t first, int64_t coun
 // b = (h^3 / 8) sum of the 8 element values of f around each interior node of
 // mesh n (grid layout, boundary positions 0), B samples
 hipError_t launch_load(int n, int B, const double* f, double* b, hipStream_t st);
+// The whole mixed-precision solve of B samples on an n^3 mesh (n = 4 or 8),
+// one workgroup per sample: fp64 refinement (u, r = b - A u with the fp64
+// kappa) around fp32 GMG-PCG to inner_rtol with the V-cycle of launch_vsmall
+// (Chebyshev degree/coefficients c1, c2); b = bvec (grid layout) or bconst at
+// every interior node.  Writes u (grid layout), active (0 where converged to
+// rtol) and iters (inner iterations).
+hipError_t launch_solve_small(int n, int B, int degree, const double* c1, const double* c2, const double* kap,
+                              const double* bvec, double bconst, double* u, int* active, int* iters, double rtol,
+                              double inner_rtol, int max_iter, int max_outer, hipStream_t st);
 hipError_t launch_pause_draw(uint64_t seed, int level, int64_t count, double a, double w, double* out,
                              hipStream_t st);
 // every workgroup w < nwg waits spin[w] ticks of the device wall clock and adds

@@ -61,43 +61,25 @@ __device__ __forceinline__ int lg2(int n) { return 31 - __clz(n); }
   for (int s = (n) * (n) + (int)threadIdx.x; s < (n) * (n) * (n); s += blockDim.x)   \
     if ((s & ((n) - 1)) != 0 && ((s >> lg2(n)) & ((n) - 1)) != 0)
 
+// one of a level's two iterate buffers, chosen without indexing an array
+// (a run-time index would put the pointer arrays in scratch memory)
 template <class T>
-__global__ void __launch_bounds__(256) k_vsmall(SmallArgs a, const T* __restrict__ bglob, T* __restrict__ xglob,
-                                                const int* __restrict__ active) {
-  const int smp = blockIdx.x;
-  if (active && !active[smp]) return;
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* X[kMaxLv][2];
-  T* Bv[kMaxLv];
-  T* Kp[kMaxLv];
-  {
-    T* p = reinterpret_cast<T*>(smem);
-    for (int l = 0; l < a.nlev; ++l) {
-      const int n = a.n0 >> l, S = lds_stride(n);
-      X[l][0] = p; p += S;
-      X[l][1] = p; p += S;
-      Bv[l] = l == 0 ? nullptr : p;
-      if (l > 0) p += S;
-      Kp[l] = p; p += n * n * n;
-    }
-    // zero everything (boundary positions must read as 0), then load kappa
-    const int total = (int)(p - reinterpret_cast<T*>(smem));
-    T* base = reinterpret_cast<T*>(smem);
-    for (int q = threadIdx.x; q < total; q += blockDim.x) base[q] = T(0);
-    __syncthreads();
-    for (int l = 0; l < a.nlev; ++l) {
-      const int n = a.n0 >> l, ne = n * n * n;
-      const T* kg = reinterpret_cast<const T*>(a.kap[l]) + (size_t)smp * ne;
-      for (int q = threadIdx.x; q < ne; q += blockDim.x) Kp[l][q] = kg[q];
-    }
-    __syncthreads();
-  }
-  const T* b0 = bglob + (size_t)smp * a.gstride;
-  int cur[kMaxLv];   // which of X[l][0..1] holds the current iterate
+__device__ __forceinline__ T* pick(T* const (&p)[2], int c) { return c ? p[1] : p[0]; }
+
+// One V-cycle from the n0 = 2^NL mesh with every level in LDS: b0 the n0
+// right-hand side (global or LDS), X/Bv/Kp the levels' buffers (boundary
+// positions 0); the result is left in pick(X[0], cur[0]).  Called by every
+// thread of the workgroup.  The level loops unroll (NL is a constant), so every
+// mesh size and index mask is a constant too.
+template <class T, int NL>
+__device__ void vcycle_lds(const SmallArgs& a, const T* b0, T* (&X)[kMaxLv][2], T* const (&Bv)[kMaxLv],
+                           T* const (&Kp)[kMaxLv], int (&cur)[kMaxLv]) {
+  constexpr int N0 = 1 << NL;
 
   // ------------------------------------------------ down: smooth, restrict
-  for (int l = 0; l < a.nlev - 1; ++l) {
-    const int n = a.n0 >> l;
+#pragma unroll
+  for (int l = 0; l < NL - 1; ++l) {
+    const int n = N0 >> l;
     const T h = T(1) / T(n);
     const T* b = l == 0 ? b0 : Bv[l];
     const T* kap = Kp[l];
@@ -111,8 +93,8 @@ __global__ void __launch_bounds__(256) k_vsmall(SmallArgs a, const T* __restrict
     __syncthreads();
     int c = 0;
     for (int st = 1; st < a.degree; ++st) {
-      const T* xc = X[l][c];
-      T* xo = X[l][c ^ 1];
+      const T* xc = pick(X[l], c);
+      T* xo = pick(X[l], c ^ 1);
       const T c1 = T(a.c1[st]), c2 = T(a.c2[st]);
       const bool use_xo = st > 1;
       FOR_INTERIOR(n, s) {
@@ -127,8 +109,8 @@ __global__ void __launch_bounds__(256) k_vsmall(SmallArgs a, const T* __restrict
     cur[l] = c;
     // residual into the free buffer, then restrict to the next level's rhs
     {
-      const T* xc = X[l][c];
-      T* t = X[l][c ^ 1];
+      const T* xc = pick(X[l], c);
+      T* t = pick(X[l], c ^ 1);
       FOR_INTERIOR(n, s) {
         T au, dg;
         q1(xc, kap, n, s, h, au, dg);
@@ -157,7 +139,7 @@ __global__ void __launch_bounds__(256) k_vsmall(SmallArgs a, const T* __restrict
   }
   // ------------------------------------------------- coarsest (2^3): exact
   {
-    const int l = a.nlev - 1;
+    constexpr int l = NL - 1;
     if (threadIdx.x == 0) {
       const T* k = Kp[l];
       const T ks = ((k[0] + k[1]) + (k[2] + k[3])) + ((k[4] + k[5]) + (k[6] + k[7]));
@@ -168,15 +150,16 @@ __global__ void __launch_bounds__(256) k_vsmall(SmallArgs a, const T* __restrict
     __syncthreads();
   }
   // ------------------------------------------------ up: prolong, smooth
-  for (int l = a.nlev - 2; l >= 0; --l) {
-    const int n = a.n0 >> l, nc = n / 2, c2n = nc * nc;
+#pragma unroll
+  for (int l = NL - 2; l >= 0; --l) {
+    const int n = N0 >> l, nc = n / 2, c2n = nc * nc;
     const T h = T(1) / T(n);
     const T* b = l == 0 ? b0 : Bv[l];
     const T* kap = Kp[l];
     int c = cur[l];
     {
-      T* x = X[l][c];
-      const T* xc = X[l + 1][cur[l + 1]];
+      T* x = pick(X[l], c);
+      const T* xc = pick(X[l + 1], cur[l + 1]);
       const int ln = lg2(n);
       FOR_INTERIOR(n, s) {
         const int i = s & (n - 1), j = (s >> ln) & (n - 1), k = s >> (2 * ln);
@@ -189,8 +172,8 @@ __global__ void __launch_bounds__(256) k_vsmall(SmallArgs a, const T* __restrict
       __syncthreads();
     }
     for (int st = 0; st < a.degree; ++st) {
-      const T* xc = X[l][c];
-      T* xo = X[l][c ^ 1];
+      const T* xc = pick(X[l], c);
+      T* xo = pick(X[l], c ^ 1);
       const T c1 = st == 0 ? T(0) : T(a.c1[st]), c2 = T(a.c2[st]);
       const bool use_xo = st > 0;
       FOR_INTERIOR(n, s) {
@@ -204,12 +187,216 @@ __global__ void __launch_bounds__(256) k_vsmall(SmallArgs a, const T* __restrict
     }
     cur[l] = c;
   }
+}
+
+// carve the V-cycle levels from LDS at p (x, second buffer, restricted
+// right-hand side below n0, kappa); returns the end
+template <class T, int NL>
+__device__ T* carve_levels(T* p, T* (&X)[kMaxLv][2], T* (&Bv)[kMaxLv], T* (&Kp)[kMaxLv]) {
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    const int n = (1 << NL) >> l, S = lds_stride(n);
+    X[l][0] = p; p += S;
+    X[l][1] = p; p += S;
+    Bv[l] = l == 0 ? nullptr : p;
+    if (l > 0) p += S;
+    Kp[l] = p; p += n * n * n;
+  }
+  return p;
+}
+
+template <class T, int NL>
+__global__ void __launch_bounds__(256) k_vsmall(SmallArgs a, const T* __restrict__ bglob, T* __restrict__ xglob,
+                                                const int* __restrict__ active) {
+  const int smp = blockIdx.x;
+  if (active && !active[smp]) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* X[kMaxLv][2];
+  T* Bv[kMaxLv];
+  T* Kp[kMaxLv];
+  {
+    T* p = carve_levels<T, NL>(reinterpret_cast<T*>(smem), X, Bv, Kp);
+    // zero everything (boundary positions must read as 0), then load kappa
+    const int total = (int)(p - reinterpret_cast<T*>(smem));
+    T* base = reinterpret_cast<T*>(smem);
+    for (int q = threadIdx.x; q < total; q += blockDim.x) base[q] = T(0);
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int n = (1 << NL) >> l, ne = n * n * n;
+      const T* kg = reinterpret_cast<const T*>(a.kap[l]) + (size_t)smp * ne;
+      for (int q = threadIdx.x; q < ne; q += blockDim.x) Kp[l][q] = kg[q];
+    }
+    __syncthreads();
+  }
+  const T* b0 = bglob + (size_t)smp * a.gstride;
+  int cur[kMaxLv];   // which of X[l][0..1] holds the current iterate
+  vcycle_lds<T, NL>(a, b0, X, Bv, Kp, cur);
   // write the N0 result
   {
-    const int n = a.n0;
-    const T* x = X[0][cur[0]];
+    constexpr int n = 1 << NL;
+    const T* x = pick(X[0], cur[0]);
     T* xg = xglob + (size_t)smp * a.gstride;
     FOR_INTERIOR(n, s) xg[s] = x[s];
+  }
+}
+
+// --------------------------------------------- whole solve in one workgroup
+// A mesh of at most 8^3 elements fits one workgroup's LDS with every vector
+// of the mixed-precision solve: the fp64 iterate, residual and kappa, the fp32
+// inner PCG vectors (correction, residual, preconditioned residual,
+// direction, operator image) and the fp32 multigrid levels.  One workgroup per
+// sample then runs the fp64 iterative refinement around the fp32 GMG-PCG
+// (the same method as the level-by-level kernels: V-cycle preconditioner from
+// vcycle_lds, inner relative tolerance, fp64 outer residual) with no launch
+// per step.  Sums are taken over the workgroup in a fixed order, so a
+// sample's result does not depend on its batch.
+struct SolveSmallArgs {
+  SmallArgs v;                // the V-cycle (n0 = the mesh)
+  double rtol2, inner_tol2, bconst;
+  int max_iter, max_outer;
+};
+
+// sum of v over the workgroup, the same value in every thread (wave sums,
+// then the wave partials in order)
+__device__ __forceinline__ double wg_allsum(double v, double* ws) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) t += ws[w];
+  return t;
+}
+
+template <int NL>
+__global__ void __launch_bounds__(256) k_solve_small(SolveSmallArgs a, const double* __restrict__ kap,
+                                                     const double* __restrict__ bvec, double* __restrict__ uglob,
+                                                     int* __restrict__ active, int* __restrict__ iters) {
+  const int smp = blockIdx.x;
+  constexpr int n = 1 << NL, ne = n * n * n;
+  const int S = lds_stride(n);
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* U = reinterpret_cast<double*>(smem);   // fp64 iterate
+  double* R = U + S;                               // fp64 residual
+  double* K = R + S;                               // fp64 kappa
+  double* ws = K + ne;                             // wave partials
+  float* Xd = reinterpret_cast<float*>(ws + 8);    // fp32 correction
+  float* Ri = Xd + S;                              // inner residual
+  float* Z = Ri + S;
+  float* P = Z + S;
+  float* Q = P + S;
+  float* X[kMaxLv][2];
+  float* Bv[kMaxLv];
+  float* Kp[kMaxLv];
+  float* end = carve_levels<float, NL>(Q + S, X, Bv, Kp);
+  // zero everything (boundary positions must read as 0)
+  for (int q = threadIdx.x; q < (int)(reinterpret_cast<double*>(Xd) - U); q += blockDim.x) U[q] = 0.0;
+  for (int q = threadIdx.x; q < (int)(end - Xd); q += blockDim.x) Xd[q] = 0.0f;
+  __syncthreads();
+  const double* kg = kap + (size_t)smp * ne;
+  for (int q = threadIdx.x; q < ne; q += blockDim.x) {
+    K[q] = kg[q];
+    Kp[0][q] = (float)kg[q];
+  }
+  __syncthreads();
+  // coarse kappa: the mean of the 8 children, in the order of k_coarsen
+#pragma unroll
+  for (int l = 1; l < NL; ++l) {
+    const int nc = n >> l, nf = 2 * nc, f2 = nf * nf, nce = nc * nc * nc, lc = lg2(nc);
+    for (int E = threadIdx.x; E < nce; E += blockDim.x) {
+      const int EX = E & (nc - 1), EY = (E >> lc) & (nc - 1), EZ = E >> (2 * lc);
+      const float* f = Kp[l - 1] + 2 * EX + nf * 2 * EY + f2 * 2 * EZ;
+      const float sv = ((f[0] + f[1]) + (f[nf] + f[nf + 1])) + ((f[f2] + f[f2 + 1]) + (f[f2 + nf] + f[f2 + nf + 1]));
+      Kp[l][E] = sv * 0.125f;
+    }
+    __syncthreads();
+  }
+  const double* bg = bvec ? bvec + (size_t)smp * a.v.gstride : nullptr;
+  const double h = 1.0 / n;
+  const float hf = 1.0f / (float)n;
+  double acc = 0.0;
+  FOR_INTERIOR(n, s) {
+    const double bv = bg ? bg[s] : a.bconst;
+    R[s] = bv;
+    acc += bv * bv;
+  }
+  const double bb = wg_allsum(acc, ws);
+  int total = 0;
+  bool done = false;
+  for (int outer = 0; outer < a.max_outer && total < a.max_iter && !done; ++outer) {
+    // inner fp32 GMG-PCG on A d = fp32(r), from d = 0, to the inner tolerance
+    acc = 0.0;
+    FOR_INTERIOR(n, s) {
+      const float r = (float)R[s];
+      Ri[s] = r;
+      Xd[s] = 0.0f;
+      acc += (double)r * (double)r;
+    }
+    const double tol2 = a.inner_tol2 * wg_allsum(acc, ws);
+    int cur[kMaxLv];
+    vcycle_lds<float, NL>(a.v, Ri, X, Bv, Kp, cur);
+    acc = 0.0;
+    FOR_INTERIOR(n, s) {
+      const float z = pick(X[0], cur[0])[s];
+      Z[s] = z;
+      P[s] = z;
+      acc += (double)Ri[s] * (double)z;
+    }
+    double rz = wg_allsum(acc, ws);
+    for (int it = 0; total < a.max_iter; ++it) {
+      acc = 0.0;
+      FOR_INTERIOR(n, s) {
+        float au, dg;
+        q1<float>(P, Kp[0], n, s, hf, au, dg);
+        Q[s] = au;
+        acc += (double)P[s] * (double)au;
+      }
+      const double pq = wg_allsum(acc, ws);
+      const float alpha = (float)(rz / pq);
+      acc = 0.0;
+      FOR_INTERIOR(n, s) {
+        Xd[s] += alpha * P[s];
+        const float r = Ri[s] - alpha * Q[s];
+        Ri[s] = r;
+        acc += (double)r * (double)r;
+      }
+      const double rr = wg_allsum(acc, ws);
+      ++total;
+      if (rr <= tol2) break;
+      vcycle_lds<float, NL>(a.v, Ri, X, Bv, Kp, cur);
+      acc = 0.0;
+      FOR_INTERIOR(n, s) {
+        const float z = pick(X[0], cur[0])[s];
+        Z[s] = z;
+        acc += (double)Ri[s] * (double)z;
+      }
+      const double rzn = wg_allsum(acc, ws);
+      const float beta = (float)(rzn / rz);
+      rz = rzn;
+      FOR_INTERIOR(n, s) P[s] = Z[s] + beta * P[s];
+      __syncthreads();
+    }
+    // fp64 refinement: u += d, r = b - A u
+    FOR_INTERIOR(n, s) U[s] += (double)Xd[s];
+    __syncthreads();
+    acc = 0.0;
+    FOR_INTERIOR(n, s) {
+      double au, dg;
+      q1<double>(U, K, n, s, h, au, dg);
+      const double r = (bg ? bg[s] : a.bconst) - au;
+      R[s] = r;
+      acc += r * r;
+    }
+    done = wg_allsum(acc, ws) <= a.rtol2 * bb;
+  }
+  double* ug = uglob + (size_t)smp * a.v.gstride;
+  for (int q = threadIdx.x; q < S; q += blockDim.x) ug[q] = U[q];
+  if (threadIdx.x == 0) {
+    active[smp] = done ? 0 : 1;
+    iters[smp] = total;
   }
 }
 
@@ -238,7 +425,45 @@ hipError_t launch_vsmall(int n0, int B, int degree, const double* c1, const doub
   a.gstride = grid_stride(n0);
   for (int l = 0; l < a.nlev; ++l) a.kap[l] = kap_levels[l];
   const size_t lds = vsmall_lds_bytes<T>(n0);
-  k_vsmall<T><<<dim3(B), dim3(256), lds, st>>>(a, b, x, active);
+  switch (a.nlev) {
+    case 2: k_vsmall<T, 2><<<dim3(B), dim3(256), lds, st>>>(a, b, x, active); break;
+    case 3: k_vsmall<T, 3><<<dim3(B), dim3(256), lds, st>>>(a, b, x, active); break;
+    case 4: k_vsmall<T, 4><<<dim3(B), dim3(256), lds, st>>>(a, b, x, active); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t solve_small_lds_bytes(int n) {
+  const int S = lds_stride(n);
+  return ((size_t)2 * S + (size_t)n * n * n + 8) * sizeof(double) + (size_t)5 * S * sizeof(float) +
+         vsmall_lds_bytes<float>(n);
+}
+
+hipError_t launch_solve_small(int n, int B, int degree, const double* c1, const double* c2, const double* kap,
+                              const double* bvec, double bconst, double* u, int* active, int* iters, double rtol,
+                              double inner_rtol, int max_iter, int max_outer, hipStream_t st) {
+  if (n < 4 || n > 8 || (n & (n - 1)) || degree < 1 || degree > 16 || B <= 0) return hipErrorInvalidValue;
+  SolveSmallArgs a{};
+  a.v.n0 = n;
+  for (int m = n; m >= 2; m /= 2) a.v.nlev++;
+  a.v.degree = degree;
+  for (int q = 0; q < degree; ++q) {
+    a.v.c1[q] = c1[q];
+    a.v.c2[q] = c2[q];
+  }
+  a.v.gstride = grid_stride(n);
+  a.rtol2 = rtol * rtol;
+  a.inner_tol2 = inner_rtol * inner_rtol;
+  a.bconst = bconst;
+  a.max_iter = max_iter;
+  a.max_outer = max_outer;
+  // 4^3 has 27 unknowns: one wave, so the many barriers of a solve cost little
+  const size_t lds = solve_small_lds_bytes(n);
+  if (n == 4)
+    k_solve_small<2><<<dim3(B), dim3(64), lds, st>>>(a, kap, bvec, u, active, iters);
+  else
+    k_solve_small<3><<<dim3(B), dim3(256), lds, st>>>(a, kap, bvec, u, active, iters);
   return hipGetLastError();
 }
 

@@ -47,10 +47,14 @@ def test_forcing_field_and_load_match_oracle(dev, n, level, first, count):
     assert np.all(b.cpu().numpy()[:, mask] == 0.0)
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-8), (1, 1e-7)])
-def test_forced_samples_match_oracle(dev, precision, tol):
+@pytest.mark.parametrize("precision,tol,fuse", [(0, 1e-8, None), (1, 1e-7, None), (1, 1e-7, 63)])
+def test_forced_samples_match_oracle(dev, precision, tol, fuse):
+    # mixed precision on 4^3 and 8^3: by default the whole solve runs in one
+    # workgroup per sample (fuse bit 128), with fuse 63 the level-by-level path
     wl = _wl(precision=precision, rtol=1e-12 if precision == 0 else 1e-10)
     ctx = mm.Context(wl, arena_bytes=256 << 20)
+    if fuse is not None:
+        ctx.set_tuning(fuse=fuse)
     q0 = None
     for level, count in ((0, 6), (1, 5)):
         y, qf, qc, it = ctx.sample_level(level, 1, count)

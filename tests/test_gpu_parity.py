@@ -263,6 +263,35 @@ def test_solve_qoi_matches_oracle(dev, precision, solver, tol, vsmall, n, B, qoi
         assert np.linalg.norm(res) <= 1.5e-12 * np.linalg.norm(bvec)
 
 
+@pytest.mark.parametrize("n,B", [(4, 300), (8, 37)])
+def test_whole_solve_kernel_matches_oracle_and_level_path(dev, n, B):
+    # fuse bit 128: the whole mixed-precision solve of a 4^3 or 8^3 sample in
+    # one workgroup.  It runs the method of the level-by-level path, so both
+    # meet the oracle's QoI, the fp64 true-residual tolerance and a similar
+    # iteration count (a broken preconditioner would still converge, slowly)
+    wl = _wl(n0=n, levels=1, precision=1, n_modes=16, corr_len=0.3, qoi=1)
+    ctx = mm.Context(wl, arena_bytes=512 << 20)
+    kap = ctx.field(n, ctx.draw_xi(0, 5, B))
+    got = {}
+    for fuse in (63 | 128, 63):
+        ctx.set_tuning(fuse=fuse)
+        ctx.set_profiling(True)
+        u, it = ctx.solve(n, kap)
+        assert (ctx.kernel_time("SOLVE_SMALL", 0)[0] > 0) == bool(fuse & 128)
+        ctx.set_profiling(False)
+        got[fuse] = (ctx.qoi(n, u).cpu().numpy(), it.copy(), mm.from_grid(u, n).cpu().numpy())
+    kap_o = field.kappa(n, wl.corr_len, wl.sigma2, wl.n_modes, rng.draw_xi(wl.seed, 0, 5, B, wl.n_modes))
+    bvec = fe.load_constant(n)
+    for fuse, (q, it, uc) in got.items():
+        for b in range(B):
+            A = fe.assemble(n, kap_o[b])
+            assert np.linalg.norm(bvec - A @ uc[b]) <= 1.5e-12 * np.linalg.norm(bvec), (fuse, b)
+            if b % 7 == 0:
+                want = _oracle_q(n, kap_o[b], 1)
+                assert abs(q[b] - want) <= 1e-7 * abs(want), (fuse, b, q[b], want)
+    assert got[63 | 128][1].max() <= 2 * got[63][1].max() + 2
+
+
 def test_gmg_iterations_are_few(dev):
     wl = _wl(n0=32, levels=1, n_modes=64, corr_len=0.3, rtol=1e-8, precision=0)
     ctx = mm.Context(wl, arena_bytes=512 << 20)
