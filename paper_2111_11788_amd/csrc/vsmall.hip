@@ -271,42 +271,55 @@ __device__ __forceinline__ double wg_allsum(double v, double* ws) {
   return t;
 }
 
+// threads of a k_solve_small workgroup: one wave for 4^3 (27 unknowns), four for 8^3
 template <int NL>
-__global__ void __launch_bounds__(256) k_solve_small(SolveSmallArgs a, const double* __restrict__ kap,
+constexpr int solve_small_threads() { return NL == 2 ? 64 : 256; }
+
+// 8^3: 20 KB of LDS per workgroup; held to 80 VGPRs (two spilled) so that
+// six workgroups share a CU (4, 5, 6 and 7 per CU measured 0.21, 0.194,
+// 0.187 and 0.185 us per sample over a 65536-sample batch)
+template <int NL>
+__global__ void __launch_bounds__(256, (NL == 3 ? 6 : 1)) k_solve_small(SolveSmallArgs a, const double* __restrict__ kap,
                                                      const double* __restrict__ bvec, double* __restrict__ uglob,
                                                      int* __restrict__ active, int* __restrict__ iters) {
   const int smp = blockIdx.x;
-  constexpr int n = 1 << NL, ne = n * n * n;
+  constexpr int n = 1 << NL, n2 = n * n, ne = n2 * n;
+  constexpr int TPB = solve_small_threads<NL>();
+  constexpr int MAXP = (ne - n2 + TPB - 1) / TPB;   // positions per thread
   const int S = lds_stride(n);
   extern __shared__ __align__(16) unsigned char smem[];
+  // LDS: what other threads read (the iterate for the fp64 operator, the
+  // V-cycle's right-hand side, the PCG direction and the levels); the rest of
+  // a node's state (fp64 residual, fp32 correction, operator image) stays in
+  // the registers of the thread that owns the node in every sweep
   double* U = reinterpret_cast<double*>(smem);   // fp64 iterate
-  double* R = U + S;                               // fp64 residual
-  double* K = R + S;                               // fp64 kappa
-  double* ws = K + ne;                             // wave partials
-  float* Xd = reinterpret_cast<float*>(ws + 8);    // fp32 correction
-  float* Ri = Xd + S;                              // inner residual
-  float* Z = Ri + S;
-  float* P = Z + S;
-  float* Q = P + S;
+  double* ws = U + S;                              // wave partials
+  float* Ri = reinterpret_cast<float*>(ws + 8);    // inner residual
+  float* P = Ri + S;                               // direction
   float* X[kMaxLv][2];
   float* Bv[kMaxLv];
   float* Kp[kMaxLv];
-  float* end = carve_levels<float, NL>(Q + S, X, Bv, Kp);
+  float* end = carve_levels<float, NL>(P + S, X, Bv, Kp);
+  // the interior nodes this thread owns: position n^2 + tid + t * TPB
+  auto own = [&](auto&& f) {
+#pragma unroll
+    for (int t = 0; t < MAXP; ++t) {
+      const int s = n2 + (int)threadIdx.x + t * TPB;
+      if (s < ne && (s & (n - 1)) != 0 && ((s >> NL) & (n - 1)) != 0) f(t, s);
+    }
+  };
   // zero everything (boundary positions must read as 0)
-  for (int q = threadIdx.x; q < (int)(reinterpret_cast<double*>(Xd) - U); q += blockDim.x) U[q] = 0.0;
-  for (int q = threadIdx.x; q < (int)(end - Xd); q += blockDim.x) Xd[q] = 0.0f;
+  for (int q = threadIdx.x; q < (int)(reinterpret_cast<double*>(Ri) - U); q += TPB) U[q] = 0.0;
+  for (int q = threadIdx.x; q < (int)(end - Ri); q += TPB) Ri[q] = 0.0f;
   __syncthreads();
   const double* kg = kap + (size_t)smp * ne;
-  for (int q = threadIdx.x; q < ne; q += blockDim.x) {
-    K[q] = kg[q];
-    Kp[0][q] = (float)kg[q];
-  }
+  for (int q = threadIdx.x; q < ne; q += TPB) Kp[0][q] = (float)kg[q];
   __syncthreads();
   // coarse kappa: the mean of the 8 children, in the order of k_coarsen
 #pragma unroll
   for (int l = 1; l < NL; ++l) {
     const int nc = n >> l, nf = 2 * nc, f2 = nf * nf, nce = nc * nc * nc, lc = lg2(nc);
-    for (int E = threadIdx.x; E < nce; E += blockDim.x) {
+    for (int E = threadIdx.x; E < nce; E += TPB) {
       const int EX = E & (nc - 1), EY = (E >> lc) & (nc - 1), EZ = E >> (2 * lc);
       const float* f = Kp[l - 1] + 2 * EX + nf * 2 * EY + f2 * 2 * EZ;
       const float sv = ((f[0] + f[1]) + (f[nf] + f[nf + 1])) + ((f[f2] + f[f2 + 1]) + (f[f2 + nf] + f[f2 + nf + 1]));
@@ -317,83 +330,86 @@ __global__ void __launch_bounds__(256) k_solve_small(SolveSmallArgs a, const dou
   const double* bg = bvec ? bvec + (size_t)smp * a.v.gstride : nullptr;
   const double h = 1.0 / n;
   const float hf = 1.0f / (float)n;
-  double acc = 0.0;
-  FOR_INTERIOR(n, s) {
-    const double bv = bg ? bg[s] : a.bconst;
-    R[s] = bv;
-    acc += bv * bv;
+  double r64[MAXP];
+  float xd[MAXP], qv[MAXP];
+#pragma unroll
+  for (int t = 0; t < MAXP; ++t) {
+    r64[t] = 0.0;
+    xd[t] = 0.0f;
+    qv[t] = 0.0f;
   }
+  double acc = 0.0;
+  own([&](int t, int s) {
+    const double bv = bg ? bg[s] : a.bconst;
+    r64[t] = bv;
+    acc += bv * bv;
+  });
   const double bb = wg_allsum(acc, ws);
   int total = 0;
   bool done = false;
   for (int outer = 0; outer < a.max_outer && total < a.max_iter && !done; ++outer) {
     // inner fp32 GMG-PCG on A d = fp32(r), from d = 0, to the inner tolerance
     acc = 0.0;
-    FOR_INTERIOR(n, s) {
-      const float r = (float)R[s];
+    own([&](int t, int s) {
+      const float r = (float)r64[t];
       Ri[s] = r;
-      Xd[s] = 0.0f;
+      xd[t] = 0.0f;
       acc += (double)r * (double)r;
-    }
+    });
     const double tol2 = a.inner_tol2 * wg_allsum(acc, ws);
     int cur[kMaxLv];
     vcycle_lds<float, NL>(a.v, Ri, X, Bv, Kp, cur);
     acc = 0.0;
-    FOR_INTERIOR(n, s) {
+    own([&](int t, int s) {
       const float z = pick(X[0], cur[0])[s];
-      Z[s] = z;
       P[s] = z;
       acc += (double)Ri[s] * (double)z;
-    }
+    });
     double rz = wg_allsum(acc, ws);
-    for (int it = 0; total < a.max_iter; ++it) {
+    while (total < a.max_iter) {
       acc = 0.0;
-      FOR_INTERIOR(n, s) {
+      own([&](int t, int s) {
         float au, dg;
         q1<float>(P, Kp[0], n, s, hf, au, dg);
-        Q[s] = au;
+        qv[t] = au;
         acc += (double)P[s] * (double)au;
-      }
+      });
       const double pq = wg_allsum(acc, ws);
       const float alpha = (float)(rz / pq);
       acc = 0.0;
-      FOR_INTERIOR(n, s) {
-        Xd[s] += alpha * P[s];
-        const float r = Ri[s] - alpha * Q[s];
+      own([&](int t, int s) {
+        xd[t] += alpha * P[s];
+        const float r = Ri[s] - alpha * qv[t];
         Ri[s] = r;
         acc += (double)r * (double)r;
-      }
+      });
       const double rr = wg_allsum(acc, ws);
       ++total;
       if (rr <= tol2) break;
       vcycle_lds<float, NL>(a.v, Ri, X, Bv, Kp, cur);
       acc = 0.0;
-      FOR_INTERIOR(n, s) {
-        const float z = pick(X[0], cur[0])[s];
-        Z[s] = z;
-        acc += (double)Ri[s] * (double)z;
-      }
+      own([&](int t, int s) { acc += (double)Ri[s] * (double)pick(X[0], cur[0])[s]; });
       const double rzn = wg_allsum(acc, ws);
       const float beta = (float)(rzn / rz);
       rz = rzn;
-      FOR_INTERIOR(n, s) P[s] = Z[s] + beta * P[s];
+      own([&](int t, int s) { P[s] = pick(X[0], cur[0])[s] + beta * P[s]; });
       __syncthreads();
     }
-    // fp64 refinement: u += d, r = b - A u
-    FOR_INTERIOR(n, s) U[s] += (double)Xd[s];
+    // fp64 refinement: u += d, r = b - A u (fp64 kappa from global memory)
+    own([&](int t, int s) { U[s] += (double)xd[t]; });
     __syncthreads();
     acc = 0.0;
-    FOR_INTERIOR(n, s) {
+    own([&](int t, int s) {
       double au, dg;
-      q1<double>(U, K, n, s, h, au, dg);
+      q1<double>(U, kg, n, s, h, au, dg);
       const double r = (bg ? bg[s] : a.bconst) - au;
-      R[s] = r;
+      r64[t] = r;
       acc += r * r;
-    }
+    });
     done = wg_allsum(acc, ws) <= a.rtol2 * bb;
   }
   double* ug = uglob + (size_t)smp * a.v.gstride;
-  for (int q = threadIdx.x; q < S; q += blockDim.x) ug[q] = U[q];
+  for (int q = threadIdx.x; q < S; q += TPB) ug[q] = U[q];
   if (threadIdx.x == 0) {
     active[smp] = done ? 0 : 1;
     iters[smp] = total;
@@ -436,8 +452,7 @@ hipError_t launch_vsmall(int n0, int B, int degree, const double* c1, const doub
 
 size_t solve_small_lds_bytes(int n) {
   const int S = lds_stride(n);
-  return ((size_t)2 * S + (size_t)n * n * n + 8) * sizeof(double) + (size_t)5 * S * sizeof(float) +
-         vsmall_lds_bytes<float>(n);
+  return ((size_t)S + 8) * sizeof(double) + (size_t)2 * S * sizeof(float) + vsmall_lds_bytes<float>(n);
 }
 
 hipError_t launch_solve_small(int n, int B, int degree, const double* c1, const double* c2, const double* kap,
@@ -458,12 +473,11 @@ hipError_t launch_solve_small(int n, int B, int degree, const double* c1, const 
   a.bconst = bconst;
   a.max_iter = max_iter;
   a.max_outer = max_outer;
-  // 4^3 has 27 unknowns: one wave, so the many barriers of a solve cost little
   const size_t lds = solve_small_lds_bytes(n);
   if (n == 4)
-    k_solve_small<2><<<dim3(B), dim3(64), lds, st>>>(a, kap, bvec, u, active, iters);
+    k_solve_small<2><<<dim3(B), dim3(solve_small_threads<2>()), lds, st>>>(a, kap, bvec, u, active, iters);
   else
-    k_solve_small<3><<<dim3(B), dim3(256), lds, st>>>(a, kap, bvec, u, active, iters);
+    k_solve_small<3><<<dim3(B), dim3(solve_small_threads<3>()), lds, st>>>(a, kap, bvec, u, active, iters);
   return hipGetLastError();
 }
 
