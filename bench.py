@@ -468,7 +468,9 @@ def main():
                     help="c2: the throughput line (default); c3: time-to-eps; c4: serving; c5: 256^3 stress; "
                     "pause: pause-model scheduler stress")
     ap.add_argument("--pause-c", type=int, default=4, help="pause: sample multiplier C of N_l = C N*_l")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune before timing (default: the pinned tuning the HBM counters were taken with, "
+                    "itself the autotuner's pick on this workload)")
     ap.add_argument("--tuning", default="", help="JSON tuning to apply instead of autotuning "
                     "(e.g. the 'tuning' object of an earlier line)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -497,9 +499,9 @@ def main():
     import workloads
     wl = workloads.C2
     prec = 1 if args.precision == "mixed" else 0
-    tuning = json.loads(args.tuning) if args.tuning else None
+    tuning = json.loads(args.tuning) if args.tuning else (None if args.autotune else dict(TRAFFIC["tuning"]))
     main_run = run_gpu(wl, prec, args.steps, args.warmup, args.batch, profile=True,
-                       autotune=not args.no_autotune and tuning is None, tuning=tuning,
+                       autotune=args.autotune and tuning is None, tuning=tuning,
                        probe_mib=args.copy_probe_mib)
     fp64 = None
     if prec == 1 and not args.no_fp64:
