@@ -205,8 +205,15 @@ __device__ T* carve_levels(T* p, T* (&X)[kMaxLv][2], T* (&Bv)[kMaxLv], T* (&Kp)[
   return p;
 }
 
+// threads of a k_vsmall workgroup: the 16^3 form holds 64 KB of LDS (two
+// workgroups per CU), so it takes 16 waves to keep the SIMDs busy (1024
+// threads: 55 us per launch of 1024 samples against 90 us with 256; 512 fell
+// in between)
+template <int NL>
+constexpr int vsmall_threads() { return NL == 4 ? 1024 : 256; }
+
 template <class T, int NL>
-__global__ void __launch_bounds__(256) k_vsmall(SmallArgs a, const T* __restrict__ bglob, T* __restrict__ xglob,
+__global__ void __launch_bounds__(vsmall_threads<NL>()) k_vsmall(SmallArgs a, const T* __restrict__ bglob, T* __restrict__ xglob,
                                                 const int* __restrict__ active) {
   const int smp = blockIdx.x;
   if (active && !active[smp]) return;
@@ -442,9 +449,9 @@ hipError_t launch_vsmall(int n0, int B, int degree, const double* c1, const doub
   for (int l = 0; l < a.nlev; ++l) a.kap[l] = kap_levels[l];
   const size_t lds = vsmall_lds_bytes<T>(n0);
   switch (a.nlev) {
-    case 2: k_vsmall<T, 2><<<dim3(B), dim3(256), lds, st>>>(a, b, x, active); break;
-    case 3: k_vsmall<T, 3><<<dim3(B), dim3(256), lds, st>>>(a, b, x, active); break;
-    case 4: k_vsmall<T, 4><<<dim3(B), dim3(256), lds, st>>>(a, b, x, active); break;
+    case 2: k_vsmall<T, 2><<<dim3(B), dim3(vsmall_threads<2>()), lds, st>>>(a, b, x, active); break;
+    case 3: k_vsmall<T, 3><<<dim3(B), dim3(vsmall_threads<3>()), lds, st>>>(a, b, x, active); break;
+    case 4: k_vsmall<T, 4><<<dim3(B), dim3(vsmall_threads<4>()), lds, st>>>(a, b, x, active); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
