@@ -249,11 +249,12 @@ __global__ void __launch_bounds__(vsmall_threads<NL>()) k_vsmall(SmallArgs a, co
 }
 
 // --------------------------------------------- whole solve in one workgroup
-// A mesh of at most 8^3 elements fits one workgroup's LDS with every vector
-// of the mixed-precision solve: the fp64 iterate, residual and kappa, the fp32
-// inner PCG vectors (correction, residual, preconditioned residual,
-// direction, operator image) and the fp32 multigrid levels.  One workgroup per
-// sample then runs the fp64 iterative refinement around the fp32 GMG-PCG
+// A mesh of at most 8^3 elements fits one workgroup with the whole state of
+// the mixed-precision solve: in LDS the fp64 iterate, the fp32 inner residual
+// and direction and the fp32 multigrid levels; in registers each node's fp64
+// residual, fp32 correction and operator image (a node is owned by the same
+// thread in every sweep).  One workgroup per sample then runs the fp64
+// iterative refinement around the fp32 GMG-PCG
 // (the same method as the level-by-level kernels: V-cycle preconditioner from
 // vcycle_lds, inner relative tolerance, fp64 outer residual) with no launch
 // per step.  Sums are taken over the workgroup in a fixed order, so a
