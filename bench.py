@@ -398,6 +398,7 @@ def run_c5(args):
                       "n_modes": wl.n_modes, "precision": "mixed"}, "batches": []}
     for B in (4, 8, 16):
         ctx = mm.Context(wl, max_batch=B, cheb_degree=args.cheb_degree)
+        tuned = ctx.autotune(0, B) if args.autotune else None
         y, qf, qc, it = ctx.sample_level(0, 0, B)       # warm-up (carve, graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -416,7 +417,7 @@ def run_c5(args):
         rows.sort(reverse=True)
         ms, name, p, n, by = rows[0]
         rec = {"batch": B, "ms": 1e3 * wall, "sample_dofs_per_s": B * 255 ** 3 / wall,
-               "iters": [int(x) for x in it], "dominant": f"{name} ({'f32' if p else 'f64'})",
+               "iters": [int(x) for x in it], "dominant": f"{name} ({'f32' if p else 'f64'})", "tuning": tuned,
                "dominant_GBps": by / (ms * 1e-3) / 1e9}
         if gold:
             rec["qoi_vs_oracle"] = [{"sample": g["index"], "gpu": float(qf[g["index"]]), "oracle": g["q"],
