@@ -19,6 +19,10 @@ from oracle import fe, field, gmg, mlmc as omlmc, pcg, rng
 from workloads import C1, C2, Workload, element_field, grid_vector
 
 
+# the library's smoothing interval of D^-1 A: [CHEB_HI / 4, CHEB_HI]
+CHEB_HI = 1.75
+
+
 def _wl(**kw):
     base = dict(name="t", n0=4, levels=3, sigma2=1.0, corr_len=0.5, n_modes=8, qoi=0, rtol=1e-12,
                 max_iter=3000, solver=0, precision=0, batch=16)
@@ -158,7 +162,7 @@ def test_vcycle_matches_oracle(dev, n, B, deg, vsmall, fuse, zvar, monkeypatch):
     z = z.cpu().numpy()
     for b in range(B):
         H = gmg.Hierarchy(n, kap[b])
-        want = H.vcycle(r[b], deg, 4.0, 2.0)
+        want = H.vcycle(r[b], deg, 4.0, CHEB_HI)
         assert np.abs(z[b] - want).max() <= 1e-12 * np.abs(want).max()
 
 
@@ -180,7 +184,7 @@ def test_presmoothed_vcycle_matches_oracle_and_stored_step(dev, n, B, monkeypatc
     z = mm.from_grid(outs[0], n).cpu().numpy()
     for b in range(B):
         H = gmg.Hierarchy(n, kap[b])
-        want = H.vcycle(r[b], 1, 4.0, 2.0)
+        want = H.vcycle(r[b], 1, 4.0, CHEB_HI)
         assert np.abs(z[b] - want).max() <= 1e-12 * np.abs(want).max()
 
 
