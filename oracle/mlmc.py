@@ -95,10 +95,13 @@ def estimator(stats: Sequence[RunningStats]):
     return qt, v, vq
 
 
-def optimal_samples(var: Sequence[float], cost: Sequence[float], eps: float) -> List[int]:
-    """eq. mlmc_num_samples."""
+def optimal_samples(var: Sequence[float], cost: Sequence[float], eps: float,
+                    extra_fraction: float = 0.0) -> List[int]:
+    """eq. mlmc_num_samples, each N_l scaled by (1 + extra_fraction) before the
+    ceiling (Sec. 2.3 draws a fraction more than the formula asks for)."""
     tot = sum(math.sqrt(v * c) for v, c in zip(var, cost))
-    return [int(math.ceil(2.0 / (eps * eps) * math.sqrt(v / c) * tot)) for v, c in zip(var, cost)]
+    return [int(math.ceil(2.0 / (eps * eps) * math.sqrt(v / c) * tot * (1.0 + extra_fraction)))
+            for v, c in zip(var, cost)]
 
 
 def num_levels(c: float, alpha: float, eps: float, s: float = 2.0) -> int:
@@ -126,40 +129,52 @@ def run_mlmc(wl, n_per_level: Sequence[int]):
     return qt, v, vq, stats, ys
 
 
-def estimate(wl, eps: float, n_pilot: int, max_rounds: int = 3, extra_fraction: float = 0.0):
+def estimate(wl, eps: float, n_pilot: int, max_rounds: int = 3, extra_fraction: float = 0.0, sampler=None,
+             cost=None, n_fixed: Sequence[int] = None):
     """Pilot, optimal allocation (eq. mlmc_num_samples) and top-up on the fixed
-    level set, with the deterministic cost model C_l = interior DOFs of the
-    pair.  Round 0 draws n_pilot samples per level; each later round tops
-    every level up to max(N_l, n_pilot) from the current 1/N variances.
+    level set.  Round 0 draws n_pilot samples per level; each later round
+    tops every level up to max(N_l, n_pilot), N_l from the current 1/N
+    variances (eq. sample_variance) and the costs C_l, until no level grows or
+    max_rounds allocations were made.  A level's samples continue its index
+    range (sample i of level l is always the same draw).
+    `sampler(level, first, count)` returns the Y values (default: the FE path
+    of sample_level); `cost(level)` the cost of one Y_l (default: the
+    deterministic DOF model).  n_fixed: plain MLMC with caller-given N_l
+    (Sec. 2.2): every level is sampled to n_fixed[l], no pilot or allocation.
     Returns (N_l list, Qtilde, V(Qtilde), stats)."""
+    if sampler is None:
+        sampler = lambda l, first, count: sample_level(wl, l, first, count)[0]
+    if cost is None:
+        cost = lambda l: level_cost(wl, l)
     L = wl.levels
     stats = [RunningStats() for _ in range(L)]
-    target = [n_pilot] * L
-    for rnd in range(max_rounds + 1):
+
+    def top_up(target):
         more = False
         for l in range(L):
             have = stats[l].n
             if target[l] > have:
                 more = True
-                Y, _, _, _ = sample_level(wl, l, have, target[l] - have)
-                for y in Y:
+                for y in sampler(l, have, target[l] - have):
                     stats[l].push(float(y))
-        if not more and rnd > 0:
-            break
-        if rnd == max_rounds:
-            break
-        V = [s.var for s in stats]
-        C = [level_cost(wl, l) for l in range(L)]
-        tot = sum(math.sqrt(v * c) for v, c in zip(V, C))
-        want = [max(int(math.ceil(2.0 / (eps * eps) * math.sqrt(v / c) * tot * (1.0 + extra_fraction))), n_pilot)
-                for v, c in zip(V, C)]
-        grow = False
-        for l in range(L):
-            if want[l] > target[l]:
-                target[l] = want[l]
-                grow = True
-        if not grow:
-            break
+        return more
+
+    if n_fixed is not None:
+        top_up(list(n_fixed))
+    else:
+        target = [n_pilot] * L
+        for rnd in range(max_rounds + 1):
+            more = top_up(target)
+            if (not more and rnd > 0) or rnd == max_rounds:
+                break
+            want = optimal_samples([s.var for s in stats], [cost(l) for l in range(L)], eps, extra_fraction)
+            grow = False
+            for l in range(L):
+                if max(want[l], n_pilot) > target[l]:
+                    target[l] = max(want[l], n_pilot)
+                    grow = True
+            if not grow:
+                break
     qt, v, vq = estimator(stats)
     return [s.n for s in stats], qt, vq, stats
 

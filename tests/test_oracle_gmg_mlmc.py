@@ -239,3 +239,125 @@ def test_adaptive_loop_stops_at_the_largest_mesh():
 def test_adaptive_loop_rejects_a_first_level_without_differences():
     with pytest.raises(ValueError):
         mlmc.estimate_adaptive(_LevelSet(3), 1e-3, 0, 16, sampler=_model())
+
+
+# ------------------------------------------------- allocation loop (estimate)
+# The pilot / eq. mlmc_num_samples / top-up loop pinned on a deterministic level
+# model whose 1/N variances are known exactly: Y_l^i = m_l + a_l (-1)^i has, for
+# every even count, mean m_l and 1/N variance a_l^2 (eq. sample_variance).  The
+# expected sample counts below are worked out by hand from eq. mlmc_num_samples,
+# not by calling the oracle's formula.
+
+def _alternating(m, a, calls):
+    def sampler(l, first, count):
+        calls.append((l, first, count))
+        return np.array([m[l] + a[l] * (-1.0) ** (first + i) for i in range(count)])
+    return sampler
+
+
+def test_estimate_allocation_on_a_known_level_model():
+    # a = (0.0103, 0.0021), C = (1, 16), eps = 1e-3:
+    #   sqrt(V0 C0) = 0.0103, sqrt(V1 C1) = 0.0021 * 4 = 0.0084, sum 0.0187
+    #   N0 = 2e6 * 0.0103 * 0.0187 = 385.22    -> 386
+    #   N1 = 2e6 * (0.0021 / 4) * 0.0187 = 19.635 -> 20
+    # both even, so the variances after the top-up are unchanged and the next
+    # round asks for no more samples
+    calls = []
+    m, a = (0.02, 1e-4), (0.0103, 0.0021)
+    n, qt, vq, st = mlmc.estimate(_LevelSet(2), 1e-3, 8, max_rounds=5, sampler=_alternating(m, a, calls),
+                                  cost=lambda l: (1.0, 16.0)[l])
+    assert n == [386, 20]
+    # pilot first on every level, then each level continues its own index range
+    assert calls == [(0, 0, 8), (1, 0, 8), (0, 8, 378), (1, 8, 12)]
+    assert st[0].var == pytest.approx(a[0] ** 2, rel=1e-12) and st[1].var == pytest.approx(a[1] ** 2, rel=1e-12)
+    assert qt == pytest.approx(m[0] + m[1], rel=1e-12)
+    # the statistical error meets eps^2 / 2 (eq. mlmc_error's variance half)
+    assert vq == pytest.approx(a[0] ** 2 / 386 + a[1] ** 2 / 20, rel=1e-12)
+    assert vq <= 1e-6 / 2
+
+
+def test_estimate_extra_fraction_and_pilot_floor():
+    # extra_fraction 0.1 scales the formula before the ceiling:
+    #   385.22 * 1.1 = 423.74 -> 424;  19.635 * 1.1 = 21.60 -> 22
+    calls = []
+    n, _, _, _ = mlmc.estimate(_LevelSet(2), 1e-3, 8, max_rounds=5, extra_fraction=0.1,
+                               sampler=_alternating((0.02, 1e-4), (0.0103, 0.0021), calls),
+                               cost=lambda l: (1.0, 16.0)[l])
+    assert n == [424, 22]
+    # a level the formula would give fewer samples than the pilot keeps the pilot:
+    #   a1 = 2e-5: N1 = 2e6 * 5e-6 * (0.0103 + 8e-5) = 0.1038 -> 1 < 8
+    calls = []
+    n, _, _, _ = mlmc.estimate(_LevelSet(2), 1e-3, 8, max_rounds=5,
+                               sampler=_alternating((0.02, 1e-4), (0.0103, 2e-5), calls),
+                               cost=lambda l: (1.0, 16.0)[l])
+    # N0 = 2e6 * 0.0103 * 0.01038 = 213.83 -> 214
+    assert n == [214, 8]
+    assert calls == [(0, 0, 8), (1, 0, 8), (0, 8, 206)]
+
+
+def test_estimate_rounds_cap_and_regrowth():
+    # a level whose first 8 samples (the pilot) are quiet (+-1.3e-3) and whose
+    # later ones are loud (+-2.6e-3), one level, C = 1, eps = 1.1e-5:
+    #   round 1 from the pilot: N = 2 (1.3e-3)^2 / eps^2 = 27933.9 -> 27934
+    #   round 2: 1/N variance of the 27934 samples (mean 0: both runs have an
+    #   even count) = (8 * 1.69e-6 + 27926 * 6.76e-6) / 27934, so
+    #   N = 2 V / eps^2 = 111711.5 -> 111712
+    def sampler(l, first, count):
+        calls.append((l, first, count))
+        return np.array([(1.3e-3 if first + i < 8 else 2.6e-3) * (-1.0) ** (first + i) for i in range(count)])
+    eps = 1.1e-5
+    calls = []
+    n, _, _, _ = mlmc.estimate(_LevelSet(1), eps, 8, max_rounds=1, sampler=sampler, cost=lambda l: 1.0)
+    assert n == [27934] and calls == [(0, 0, 8), (0, 8, 27926)]
+    calls = []
+    n, _, _, st = mlmc.estimate(_LevelSet(1), eps, 8, max_rounds=2, sampler=sampler, cost=lambda l: 1.0)
+    v1 = (8 * 1.69e-6 + 27926 * 6.76e-6) / 27934
+    assert 2 * v1 / eps ** 2 == pytest.approx(111711.5, abs=0.1)
+    assert n == [111712] and calls == [(0, 0, 8), (0, 8, 27926), (0, 27934, 111712 - 27934)]
+
+
+def test_estimate_fixed_counts_is_plain_mlmc():
+    calls = []
+    n, qt, vq, st = mlmc.estimate(_LevelSet(2), 1e-3, 8, sampler=_alternating((0.02, 1e-4), (0.01, 0.002), calls),
+                                  n_fixed=(10, 4))
+    assert n == [10, 4] and calls == [(0, 0, 10), (1, 0, 4)]
+    assert qt == pytest.approx(0.0201, rel=1e-12)
+
+
+# ------------------------------------------------------- V-cycle by value
+# One V-cycle z = B b is linear in b; its error propagation is
+#   I - B A = S (I - P B_c P^T A) S
+# with S = p(D^-1 A) the Chebyshev error polynomial of the smoother (the same
+# for the zero-start pre-smoothing and the post-smoothing) and B_c the coarse
+# V-cycle (the exact inverse on the one-unknown 2^3 mesh).  The dense operator
+# is composed here from numpy.linalg alone and compared with the oracle's
+# recursive V-cycle.
+
+def _dense_vcycle(H, lvl, degree, lo_ratio, hi):
+    A = H.As[lvl].toarray()
+    if H.ns[lvl] == 2:
+        return np.linalg.inv(A)
+    d = np.sqrt(np.diag(A))
+    Ssym = A / d[:, None] / d[None, :]
+    lam, V = np.linalg.eigh(Ssym)
+    p = gmg.chebyshev_polynomial(lam, degree, hi / lo_ratio, hi)
+    S = (V * p) @ V.T
+    S = S / d[:, None] * d[None, :]          # D^-1/2 p(D^-1/2 A D^-1/2) D^1/2 = p(D^-1 A)
+    P = H.Ps[lvl].toarray()
+    Bc = _dense_vcycle(H, lvl + 1, degree, lo_ratio, hi)
+    I = np.eye(A.shape[0])
+    E = S @ (I - P @ Bc @ P.T @ A) @ S
+    return (I - E) @ np.linalg.inv(A)
+
+
+@pytest.mark.parametrize("n,degree,hi", [(4, 1, 1.75), (4, 2, 1.75), (8, 1, 1.75), (8, 2, 2.0), (8, 3, 1.75)])
+def test_vcycle_equals_dense_error_operator(n, degree, hi):
+    kap = element_field(n, 1, seed=70 + n, spread=1.5)[0]
+    H = gmg.Hierarchy(n, kap)
+    Bd = _dense_vcycle(H, 0, degree, 4.0, hi)
+    for s in range(3):
+        b = grid_vector(n, 1, seed=80 + s)[0]
+        z = H.vcycle(b, degree, 4.0, hi)
+        assert np.abs(z - Bd @ b).max() <= 1e-12 * np.abs(Bd @ b).max()
+    # the composed operator is symmetric (pre- and post-smoothing are adjoint)
+    assert np.abs(Bd - Bd.T).max() <= 1e-10 * np.abs(Bd).max()
