@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # per-kernel table and the commands are in the committed counter summary.
 TRAFFIC = {
     "profile": "profiles/batched-64cube-1024_hbm_traffic.txt",
-    "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 1, "fuse": 63},
+    "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 1, "fuse": 63, "lanes": 1},
     "sha256_16": {"common.hpp": "84103274fa2b6280", "engine.hpp": "4b5b6d63f226a1c5", "grid.hpp": "b39dc836a416fe0a", "kernels.hpp": "08f555efa50d621c", "krylov.hip": "3417955a34ecc56a", "stencil.hip": "f18d689eb84cf607"},
     "bytes_per_launch": {
         "PCG_UPDATE (f32)": 3170186283,

@@ -97,11 +97,12 @@ typedef struct mlmc_config {
 typedef struct mlmc_ctx mlmc_ctx;
 
 typedef struct mlmc_level_stats {
-  uint64_t n;          /* samples accumulated */
+  uint64_t n;          /* samples accumulated (finite Y only) */
   double mean;         /* mean of Y_l */
   double m2;           /* sum of squared deviations from the mean */
   double var;          /* m2 / n, the 1/N sample variance of eq. sample_variance */
   double cost;         /* mean cost per sample used by the allocation (see below) */
+  uint64_t nonfinite;  /* samples whose Y was NaN or Inf: counted here, kept out of n, mean, m2 */
 } mlmc_level_stats;
 
 typedef struct mlmc_estimate_out {
@@ -109,6 +110,9 @@ typedef struct mlmc_estimate_out {
   double var_qtilde;   /* sum_l var_l / n_l, Sec. 2.2 */
   int32_t levels;      /* number of levels reported below */
   mlmc_level_stats level[16];
+  int32_t lanes;       /* lanes of the last sampling round of the last whole-path call */
+  double active_ratio; /* A = a / (p t_w) of eq. active_ratio over that call's rounds: lane-seconds spent
+                          on tasks / (lanes x wall seconds) */
 } mlmc_estimate_out;
 
 /* ------------------------------------------------------------------ setup */
@@ -170,17 +174,34 @@ int mlmc_field(mlmc_ctx* ctx, int32_t n, int64_t count, const double* xi,
 /* K5 -- y = A(kappa) u for `count` samples on the n^3 mesh: the Q1 stiffness
  * of eq. model with per-element kappa and homogeneous Dirichlet rows and
  * columns eliminated (Sec. 2.1-2.2).  u, y: device, grid layout, fp64;
- * kappa: device, element layout, fp64.  u and y must not overlap. */
+ * kappa: device, element layout, fp64.  u and y must not overlap.  Runs the
+ * stencil engine selected by mlmc_tuning.zvar_fp64 (register window or
+ * LDS-tiled planes). */
 int mlmc_apply(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa,
                const double* u, double* y);
 
+/* mlmc_apply in fp32 (the operator of the mixed-precision inner solve): u, y
+ * and kappa are fp32 arrays in the same layouts; the engine is the one
+ * mlmc_tuning.zvar_fp32 selects.  Errors as mlmc_apply. */
+int mlmc_apply_f32(mlmc_ctx* ctx, int32_t n, int64_t count, const float* kappa,
+                   const float* u, float* y);
+
 /* One multigrid V-cycle z = B(kappa) r of the preconditioner used by the
  * GMG-PCG solve (rediscretised coarse operators with the 8-child mean of
- * kappa, trilinear transfers, Chebyshev-Jacobi smoothing of degree
- * cheb_degree on [1/2, 2] of D^-1 A, exact solve on the 2^3 mesh).
- * r, z: device, grid layout, fp64; kappa: device, element layout, fp64. */
+ * kappa, trilinear transfers, Chebyshev-Jacobi smoothing of the context's
+ * degree on the interval [0.4375, 1.75] of the spectrum of D^-1 A, exact
+ * solve on the 2^3 mesh; the multigrid choices of Sec. 2.3's solver, which
+ * the paper leaves to a library).  r, z: device, grid layout, fp64; kappa:
+ * device, element layout, fp64.  The kernels are the ones the tuning selects
+ * (stencil engine, fusions, coarse single-kernel V-cycle from vsmall_fp64). */
 int mlmc_vcycle(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa,
                 const double* r, double* z);
+
+/* mlmc_vcycle in fp32, the preconditioner of the mixed-precision inner solve:
+ * r, z, kappa fp32, with the tuning's fp32 stencil engine, fusions and
+ * vsmall_fp32.  The arena holds its work space (Errors: MLMC_E_NOMEM). */
+int mlmc_vcycle_f32(mlmc_ctx* ctx, int32_t n, int64_t count, const float* kappa,
+                    const float* r, float* z);
 
 /* Solve A(kappa) u = b for f = 1 (b_i = h^3, whatever the configured
  * forcing) for `count` samples with the configured solver and precision, starting from u = 0, to the configured
@@ -216,21 +237,34 @@ int mlmc_forcing(mlmc_ctx* ctx, int32_t n, int32_t level, uint64_t first, int64_
  * xi and returns Y = Q_l - Q_{l-1} (Sec. 2.2), level 0 returns Y = Q_0.
  * y, q_fine, q_coarse (q_coarse = 0 at level 0) are host arrays of `count`
  * doubles; iters (host, may be NULL) gets the fine-mesh iteration counts.
- * The samples are also folded into the context's running statistics of the
- * level (count, mean, M2 by the Chan et al. merge in sample order).
- * Work is split into batches: max_batch samples on the finest configured
- * mesh, proportionally more on coarser levels (same DOFs per batch, at most
- * 65536 samples, what the arena holds; never fewer than max_batch).
- * Errors: MLMC_E_NOMEM if the arena cannot hold one batch, MLMC_E_NOCONV. */
+ * The samples are also folded into the level's running statistics on the
+ * device in sample order (Welford within blocks of 64 consecutive samples,
+ * blocks merged by the Chan et al. formula in order; NaN / Inf values of Y
+ * are counted apart and not folded in).
+ * Work is split into batches (eq. batch, read for the lanes of the tuning:
+ * see mlmc_last_plan) of at most the lane capacity: max_batch samples on the
+ * finest configured mesh, proportionally more on coarser levels (same DOFs
+ * per batch, at most 65536 samples); the fine and coarse solves of each batch
+ * are separate tasks, assigned finest mesh first to the least-loaded of the
+ * lanes (Alg. incremental_greedy), which run concurrently on their own
+ * streams.  Lanes that the arena cannot hold are dropped (one lane at least;
+ * its batches are halved down to max_batch if needed).  A sample's result
+ * does not depend on its batch or lane.
+ * Errors: MLMC_E_NOMEM if the arena cannot hold one batch; MLMC_E_NOCONV or
+ * MLMC_E_NONFINITE after all samples ran (outputs filled; a solve whose
+ * residual turns NaN / Inf stops at once). */
 int mlmc_sample_level(mlmc_ctx* ctx, int32_t level, uint64_t first, uint64_t count,
                       double* y, double* q_fine, double* q_coarse, int32_t* iters);
 
 typedef struct mlmc_estimate_opts {
-  double eps;             /* target RMSE (absolute) of the estimator, > 0 */
+  double eps;             /* target RMSE (absolute) of the estimator, > 0 (unused with n_fixed) */
   int32_t n_pilot;        /* pilot samples per level before allocating, >= 2 */
   int32_t cost_model;     /* 0: measured GPU seconds per sample; 1: interior DOFs of the pair */
   double extra_fraction;  /* N_l is multiplied by (1 + extra_fraction), >= 0 (Sec. 2.3) */
   int32_t max_rounds;     /* allocation rounds: re-estimate V_l after each top-up, >= 1 */
+  const uint64_t* n_fixed;/* host, `levels` entries, or NULL: plain MLMC with these N_l (Sec. 2.2, eq.
+                             mlmc_average): every level sampled up to n_fixed[l] in one round, no pilot and
+                             no allocation */
 } mlmc_estimate_opts;
 
 /* Multilevel estimate to a target RMSE on the context's fixed level set
@@ -243,7 +277,11 @@ typedef struct mlmc_estimate_opts {
  * needs more samples.  n_per_level (host, `levels` entries, may be NULL)
  * receives the final N_l; out receives the estimator.  The statistical error
  * sum_l V_l / N_l then targets eps^2 / 2 (the bias half of eq. mlmc_error is
- * not estimated).  Errors: as mlmc_sample_level. */
+ * not estimated).  Each round samples every level that needs samples
+ * together, as one set of tasks over the lanes (see mlmc_sample_level).
+ * Errors: as mlmc_sample_level; MLMC_E_NOCONV / MLMC_E_NONFINITE are returned
+ * after the loop ends normally, with n_per_level and out filled (non-finite
+ * samples are kept out of the statistics, unconverged ones are in them). */
 int mlmc_estimate(mlmc_ctx* ctx, const mlmc_estimate_opts* opts, uint64_t* n_per_level,
                   mlmc_estimate_out* out);
 
@@ -355,6 +393,8 @@ typedef struct mlmc_tuning {
                              modes of each x-factor, then g = H phi_x), or the GEMM when one sample's
                              coefficients and the mesh's x-table do not fit a workgroup's LDS; the
                              bf16 precision always uses its MFMA GEMM */
+  int32_t lanes;          /* lanes of a sampling round, 1..8 (default 4): concurrent streams, each solving
+                             its tasks one after another (1: every batch in turn on the context stream) */
   double seconds;         /* mlmc_autotune: measured seconds per sample of the chosen setting */
 } mlmc_tuning;
 
@@ -397,6 +437,29 @@ int mlmc_get_estimate(const mlmc_ctx* ctx, mlmc_estimate_out* out);
 
 /* Clear the running statistics of every level. */
 int mlmc_reset_stats(mlmc_ctx* ctx);
+
+/* K14 -- fold y (device, fp64, `count` values in sample order) into the
+ * running statistics of `level` exactly as the whole-path calls do (Welford
+ * within blocks of 64 consecutive pushes, blocks merged in order by the Chan
+ * et al. formula, eq. sample_variance and eq. mlmc_average; NaN / Inf values
+ * counted apart); the result does not depend on how the values are split
+ * over calls.  Returns MLMC_E_NONFINITE if some value was not finite (the
+ * others are folded in).  For step-level use and tests. */
+int mlmc_fold_stats(mlmc_ctx* ctx, int32_t level, const double* y, uint64_t count);
+
+/* One task of a sampling round (see mlmc_sample_level). */
+typedef struct mlmc_plan_task {
+  int32_t level;       /* MLMC level whose draws the task solves */
+  int32_t n;           /* mesh: n0 << level (the level's own), or half of it (the coarse solve of the pair) */
+  uint64_t first;      /* first sample index */
+  int32_t count;       /* samples */
+  int32_t lane;        /* lane it ran on */
+} mlmc_plan_task;
+
+/* The tasks of the last sampling round in assignment order (finest mesh
+ * first, each to the least-loaded lane); *n receives their number (the first
+ * max of them are written to out, host).  For tests of the scheduling. */
+int mlmc_last_plan(const mlmc_ctx* ctx, mlmc_plan_task* out, int32_t max, int32_t* n);
 
 /* ---------------------------------------------------------------- serving */
 

@@ -1,0 +1,94 @@
+"""Scheduling of a sampling round on one GPU (oracle side; test infrastructure).
+
+The paper's scheduler (Sec. 3-4) gives tasks to partitions of q_l processors:
+  * Alg. incremental_greedy: tasks are taken by decreasing q (the finest level
+    first) and each goes to the least-loaded processors;
+  * eq. batch: a level's samples are handed out in batches of consecutive
+    indices whose size falls with the number still unassigned, between a
+    minimum and a maximum fraction of the samples per partition
+    ceil(N_l / (p|q_l)).
+On one GPU a partition becomes a lane: a stream that solves one batched task
+at a time.  The readings (the equation as printed is garbled: its value is
+always 1) are
+  * partitions of every level: the K lanes, so p|q_l = K;
+  * b = ceil((N - n) / K), kept between ceil(0.01 ceil(N / K)) and
+    ceil(phi^-1 ceil(N / K)) (phi the golden ratio), the defaults the paper
+    states, where N is the number of samples the round assigns to the level
+    and n those already assigned; the minimum is raised to ceil(cap / 8) (at
+    most cap), cap being the lane capacity of the level; every batch is
+    capped by cap and by what is left;
+  * with one lane there is no other partition to leave work for: batches are
+    the capacity;
+  * a batch of a level l > 0 is two tasks, the solve on the level's mesh and
+    the solve on the coarse mesh of its pair (Sec. 2.2); a task's work is its
+    samples times the interior unknowns of its mesh;
+  * tasks are ordered by decreasing mesh (q of the task), then by decreasing
+    level, then in sample order; each goes to the lane with the least work
+    assigned so far, the lowest lane on ties.
+"""
+from __future__ import annotations
+
+import math
+from typing import List, Sequence, Tuple
+
+PHI_INV = (math.sqrt(5.0) - 1.0) / 2.0
+
+
+def dofs(n: int) -> int:
+    return (n - 1) ** 3
+
+
+def batch_sizes(count: int, lanes: int, cap: int) -> List[int]:
+    """Batch sizes of one level's share of a round (eq. batch as read above)."""
+    if lanes <= 1:
+        out, left = [], count
+        while left > 0:
+            out.append(min(left, cap))
+            left -= out[-1]
+        return out
+    per = -(-count // lanes)
+    most = math.ceil(per * PHI_INV)
+    least = max(-(-per // 100), min(cap, -(-cap // 8)))
+    out, left = [], count
+    while left > 0:
+        b = -(-left // lanes)
+        b = max(least, min(most, b))
+        b = min(b, cap, left)
+        out.append(b)
+        left -= b
+    return out
+
+
+def level_cap(n0: int, levels: int, level: int, max_batch: int, limit: int = 65536) -> int:
+    """Samples a lane takes of a level: max_batch on the finest mesh and as many
+    as cost the same interior unknowns (pair of meshes) on a coarser level, at
+    most `limit`, never below max_batch."""
+    def pair(l):
+        n = n0 << l
+        return dofs(n) + (dofs(n // 2) if l > 0 else 0)
+    cap = min(max_batch * max(1.0, pair(levels - 1) / pair(level)), float(limit))
+    return max(max_batch, int(cap))
+
+
+def plan(n0: int, requests: Sequence[Tuple[int, int, int]], lanes: int, caps: Sequence[int]):
+    """Tasks of a round: requests are (level, first, count), caps the lane
+    capacity of each request.  Returns dicts (level, n, first, count, lane) in
+    assignment order."""
+    order = sorted(range(len(requests)), key=lambda r: -requests[r][0])
+    tasks = []
+    for r in order:
+        level, first, count = requests[r]
+        off = 0
+        for b in batch_sizes(count, lanes, caps[r]):
+            n = n0 << level
+            tasks.append(dict(level=level, n=n, first=first + off, count=b))
+            if level > 0:
+                tasks.append(dict(level=level, n=n // 2, first=first + off, count=b))
+            off += b
+    tasks.sort(key=lambda t: -t["n"])          # stable: level, then sample order
+    load = [0] * max(1, lanes)
+    for t in tasks:
+        lane = min(range(len(load)), key=lambda i: (load[i], i))
+        t["lane"] = lane
+        load[lane] += t["count"] * dofs(t["n"])
+    return tasks

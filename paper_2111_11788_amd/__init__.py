@@ -27,7 +27,8 @@ KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "
 
 # exported symbols of include/mlmc.h (checked by the CPU test suite)
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
-           "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_vcycle", "mlmc_solve", "mlmc_qoi",
+           "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_apply_f32", "mlmc_vcycle",
+           "mlmc_vcycle_f32", "mlmc_solve", "mlmc_qoi", "mlmc_fold_stats", "mlmc_last_plan",
            "mlmc_sample_level", "mlmc_estimate", "mlmc_estimate_adaptive", "mlmc_get_estimate", "mlmc_reset_stats",
            "mlmc_node_map", "mlmc_pause_model", "mlmc_forcing",
            "mlmc_set_profiling", "mlmc_kernel_time", "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
@@ -53,7 +54,12 @@ class Config(ctypes.Structure):
 
 class LevelStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("mean", ctypes.c_double), ("m2", ctypes.c_double),
-                ("var", ctypes.c_double), ("cost", ctypes.c_double)]
+                ("var", ctypes.c_double), ("cost", ctypes.c_double), ("nonfinite", ctypes.c_uint64)]
+
+
+class PlanTask(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("n", ctypes.c_int32), ("first", ctypes.c_uint64),
+                ("count", ctypes.c_int32), ("lane", ctypes.c_int32)]
 
 
 class SampleResult(ctypes.Structure):
@@ -83,7 +89,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("zvar_fp32", ctypes.c_int32), ("zvar_fp64", ctypes.c_int32), ("vsmall_fp32", ctypes.c_int32),
                 ("vsmall_fp64", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("graph_batch", ctypes.c_int32), ("fuse", ctypes.c_int32), ("field", ctypes.c_int32),
-                ("seconds", ctypes.c_double)]
+                ("lanes", ctypes.c_int32), ("seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,7 +97,7 @@ class Tuning(ctypes.Structure):
 
 class EstimateOpts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("n_pilot", ctypes.c_int32), ("cost_model", ctypes.c_int32),
-                ("extra_fraction", ctypes.c_double), ("max_rounds", ctypes.c_int32)]
+                ("extra_fraction", ctypes.c_double), ("max_rounds", ctypes.c_int32), ("n_fixed", ctypes.c_void_p)]
 
 
 class AdaptiveOpts(ctypes.Structure):
@@ -119,7 +125,7 @@ class PauseOut(ctypes.Structure):
 
 class EstimateOut(ctypes.Structure):
     _fields_ = [("qtilde", ctypes.c_double), ("var_qtilde", ctypes.c_double), ("levels", ctypes.c_int32),
-                ("level", LevelStats * 16)]
+                ("level", LevelStats * 16), ("lanes", ctypes.c_int32), ("active_ratio", ctypes.c_double)]
 
 
 _lib = None
@@ -144,7 +150,11 @@ def lib():
         "mlmc_draw_xi": (ctypes.c_int, [P, I32, U64, I64, P]),
         "mlmc_field": (ctypes.c_int, [P, I32, I64, P, P, P]),
         "mlmc_apply": (ctypes.c_int, [P, I32, I64, P, P, P]),
+        "mlmc_apply_f32": (ctypes.c_int, [P, I32, I64, P, P, P]),
         "mlmc_vcycle": (ctypes.c_int, [P, I32, I64, P, P, P]),
+        "mlmc_vcycle_f32": (ctypes.c_int, [P, I32, I64, P, P, P]),
+        "mlmc_fold_stats": (ctypes.c_int, [P, I32, P, U64]),
+        "mlmc_last_plan": (ctypes.c_int, [P, P, I32, ctypes.POINTER(I32)]),
         "mlmc_solve": (ctypes.c_int, [P, I32, I64, P, P, P]),
         "mlmc_qoi": (ctypes.c_int, [P, I32, I64, P, P]),
         "mlmc_sample_level": (ctypes.c_int, [P, I32, U64, U64, P, P, P, P]),
@@ -270,6 +280,32 @@ class Context:
         self._check(lib().mlmc_vcycle(self.h, n, r_grid.shape[0], _ptr(kappa), _ptr(r_grid), _ptr(z)))
         return z
 
+    def apply_f32(self, n: int, kappa32, u_grid32):
+        """mlmc_apply_f32: fp32 kappa and u (grid layout) -> fp32 y."""
+        y = self.torch.zeros_like(u_grid32)
+        self._check(lib().mlmc_apply_f32(self.h, n, u_grid32.shape[0], _ptr(kappa32), _ptr(u_grid32), _ptr(y)))
+        return y
+
+    def vcycle_f32(self, n: int, kappa32, r_grid32):
+        """mlmc_vcycle_f32: the fp32 V-cycle of the mixed-precision inner solve."""
+        z = self.torch.zeros_like(r_grid32)
+        self._check(lib().mlmc_vcycle_f32(self.h, n, r_grid32.shape[0], _ptr(kappa32), _ptr(r_grid32), _ptr(z)))
+        return z
+
+    def fold_stats(self, level: int, y, allow_nonfinite: bool = False):
+        """mlmc_fold_stats: fold device fp64 values into a level's running statistics."""
+        rc = lib().mlmc_fold_stats(self.h, level, _ptr(y), y.numel())
+        self._check(rc, allow=(-5,) if allow_nonfinite else ())
+        return rc
+
+    def last_plan(self):
+        """Tasks of the last sampling round: list of dicts (level, n, first, count, lane)."""
+        n = ctypes.c_int32()
+        self._check(lib().mlmc_last_plan(self.h, None, 0, ctypes.byref(n)))
+        buf = (PlanTask * max(1, n.value))()
+        self._check(lib().mlmc_last_plan(self.h, buf, n.value, ctypes.byref(n)))
+        return [{k: getattr(buf[i], k) for k, _ in PlanTask._fields_} for i in range(n.value)]
+
     def solve(self, n: int, kappa, allow_noconv: bool = False):
         B = kappa.shape[0]
         u = self.torch.zeros((B, grid_stride(n)), dtype=self.torch.float64, device="cuda")
@@ -284,20 +320,23 @@ class Context:
         return q
 
     # --- whole path (host outputs) -------------------------------------------
-    def sample_level(self, level: int, first: int, count: int):
+    def sample_level(self, level: int, first: int, count: int, allow=()):
+        """(Y, Q_fine, Q_coarse, fine iterations) of samples first.. of a level; `allow`: error codes
+        returned instead of raised (the outputs are filled)."""
         y = np.zeros(count)
         qf = np.zeros(count)
         qc = np.zeros(count)
         it = np.zeros(count, dtype=np.int32)
-        self._check(lib().mlmc_sample_level(self.h, level, first, count, y.ctypes.data, qf.ctypes.data,
-                                            qc.ctypes.data, it.ctypes.data))
+        self.last_rc = self._check(lib().mlmc_sample_level(self.h, level, first, count, y.ctypes.data,
+                                                           qf.ctypes.data, qc.ctypes.data, it.ctypes.data), allow)
         return y, qf, qc, it
 
     @staticmethod
     def _estimate_dict(out):
         lv = [dict(n=out.level[l].n, mean=out.level[l].mean, m2=out.level[l].m2, var=out.level[l].var,
-                   cost=out.level[l].cost) for l in range(out.levels)]
-        return dict(qtilde=out.qtilde, var_qtilde=out.var_qtilde, levels=lv)
+                   cost=out.level[l].cost, nonfinite=out.level[l].nonfinite) for l in range(out.levels)]
+        return dict(qtilde=out.qtilde, var_qtilde=out.var_qtilde, levels=lv, lanes=out.lanes,
+                    active_ratio=out.active_ratio)
 
     def get_estimate(self):
         out = EstimateOut()
@@ -305,12 +344,16 @@ class Context:
         return self._estimate_dict(out)
 
     def estimate(self, eps: float, n_pilot: int = 32, cost_model: int = 0, extra_fraction: float = 0.0,
-                 max_rounds: int = 3):
-        """Pilot + optimal allocation + top-up (mlmc_estimate); returns (N_l, estimate dict)."""
-        opts = EstimateOpts(eps, n_pilot, cost_model, extra_fraction, max_rounds)
+                 max_rounds: int = 3, n_fixed=None, allow=()):
+        """Pilot + optimal allocation + top-up (mlmc_estimate), or plain MLMC with n_fixed;
+        returns (N_l, estimate dict)."""
+        fixed = None if n_fixed is None else np.ascontiguousarray(n_fixed, dtype=np.uint64)
+        opts = EstimateOpts(eps, n_pilot, cost_model, extra_fraction, max_rounds,
+                            None if fixed is None else fixed.ctypes.data)
         nl = np.zeros(self.cfg.levels, dtype=np.uint64)
         out = EstimateOut()
-        self._check(lib().mlmc_estimate(self.h, ctypes.byref(opts), nl.ctypes.data, ctypes.byref(out)))
+        self.last_rc = self._check(lib().mlmc_estimate(self.h, ctypes.byref(opts), nl.ctypes.data,
+                                                       ctypes.byref(out)), allow)
         return nl, self._estimate_dict(out)
 
     def estimate_adaptive(self, eps: float, l0: int = 1, n_pilot: int = 32, cost_model: int = 0,

@@ -59,6 +59,7 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   ctx->d_xperm = cv.take<int>((size_t)cfg->n_modes);
   ctx->d_xoff = cv.take<int>((size_t)ctx->K1 + 1);
   ctx->prof_counts = cv.take<int>(mlmc_ctx::kProfCap);
+  ctx->d_stats = cv.take<DevStats>((size_t)cfg->levels);
   std::vector<double> sq(cfg->n_modes);
   for (int m = 0; m < cfg->n_modes; ++m) sq[m] = std::sqrt(ctx->modes.lambda[m]);
   hipError_t e = hipMemcpyAsync(ctx->d_sqrtlam, sq.data(), sq.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st);
@@ -85,6 +86,7 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
     ctx->d_tab[n] = d;
     e = hipMemcpyAsync(d, tabs.back().data(), tabs.back().size() * sizeof(double), hipMemcpyHostToDevice, ctx->st);
   }
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->d_stats, 0, (size_t)cfg->levels * sizeof(DevStats), ctx->st);
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_nactive, sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
   if (e != hipSuccess) {
@@ -108,9 +110,14 @@ void mlmc_destroy(mlmc_ctx* ctx) {
     hipEventDestroy(r.b);
   }
   for (auto e : ctx->event_pool) hipEventDestroy(e);
-  ctx->sw.release_graphs();
-  ctx->bw.wf.release_graphs();
-  ctx->bw.wc.release_graphs();
+  drop_work(ctx);
+  for (auto& ln : ctx->lanes)
+    if (ln->sub) {
+      hipStreamSynchronize(ln->sub->st);
+      hipHostFree(ln->sub->h_nactive);
+      hipStreamDestroy(ln->sub->st);
+    }
+  ctx->lanes.clear();
   if (ctx->h_nactive) hipHostFree(ctx->h_nactive);
   if (ctx->own_stream) hipStreamDestroy(ctx->st);
   delete ctx;
@@ -122,11 +129,11 @@ size_t mlmc_workspace_bytes(const mlmc_config* cfg, int32_t level, int32_t batch
   const KLModes md = kl_select(cfg->corr_len, cfg->sigma2, cfg->n_modes);
   mlmc_config c = *cfg;
   if (c.cheb_degree == 0) c.cheb_degree = 2;
-  Carver dry;
-  dry.top = persistent_bytes(&c, (int)md.omega.size());
-  BatchWork w;
-  carve_batch(dry, w, c, level, batch);
-  return dry.top;
+  // one lane: the larger of the pair's two solves, and the round's QoI buffers
+  const int nf = c.n0 << level;
+  size_t w = mesh_work_bytes(c, level, nf, batch);
+  if (level > 0) w = std::max(w, mesh_work_bytes(c, level, nf / 2, batch));
+  return persistent_bytes(&c, (int)md.omega.size()) + w + 2 * align256((size_t)batch * sizeof(double)) + 256;
 }
 
 int mlmc_node_map(mlmc_ctx* ctx, int32_t n, int32_t* out) {
@@ -138,10 +145,7 @@ int mlmc_node_map(mlmc_ctx* ctx, int32_t n, int32_t* out) {
     FAIL(MLMC_E_NOMEM, "arena too small for the node map");
   // scratch right after the persistent tables: the cached work space there is
   // dropped and carved (and cleared) again when next needed
-  ctx->sw.release_graphs();
-  ctx->bw.wf.release_graphs();
-  ctx->bw.wc.release_graphs();
-  ctx->ws_kind = -1;
+  drop_work(ctx);
   int32_t* d = reinterpret_cast<int32_t*>((char*)ctx->cfg.arena + ctx->persistent_top);
   LAUNCH(MLMC_K_MISC, 0, launch_node_map(n, d, ctx->st));
   HIPCHK(hipMemcpyAsync(out, d, S * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
@@ -160,10 +164,7 @@ int mlmc_forcing(mlmc_ctx* ctx, int32_t n, int32_t level, uint64_t first, int64_
   if (ctx->persistent_top + xb > ctx->cfg.arena_bytes) FAIL(MLMC_E_NOMEM, "arena too small for the forcing draw");
   // scratch right after the persistent tables (the cached work space there is
   // dropped and carved again when next needed)
-  ctx->sw.release_graphs();
-  ctx->bw.wf.release_graphs();
-  ctx->bw.wc.release_graphs();
-  ctx->ws_kind = -1;
+  drop_work(ctx);
   double* xif = reinterpret_cast<double*>((char*)ctx->cfg.arena + ctx->persistent_top);
   if (int rc = forcing_impl(ctx, n, level, first, (int)count, xif, f, b)) return rc;
   HIPCHK(hipStreamSynchronize(ctx->st));
@@ -201,7 +202,18 @@ int mlmc_apply(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa, con
     FAIL(MLMC_E_INVALID, "bad apply arguments");
   if (count == 0) return MLMC_OK;
   LAUNCH(MLMC_K_APPLY, (2 * dofs(n) + elems(n)) * count * 8,
-         launch_apply<double>(n, (int)count, kappa, u, y, nullptr, ctx->st));
+         launch_apply<double>(n, (int)count, kappa, u, y, nullptr, ctx->st, zv<double>(ctx)));
+  return MLMC_OK;
+}
+
+int mlmc_apply_f32(mlmc_ctx* ctx, int32_t n, int64_t count, const float* kappa, const float* u, float* y) {
+  if (!ctx) return MLMC_E_INVALID;
+  if (n < 2 || !is_pow2(n) || n > 1024 || count < 0 || count > (1 << 30) || (count > 0 && (!kappa || !u || !y)) ||
+      (count > 0 && u == y))
+    FAIL(MLMC_E_INVALID, "bad apply arguments");
+  if (count == 0) return MLMC_OK;
+  LAUNCH(kid<float>(MLMC_K_APPLY), (2 * dofs(n) + elems(n)) * count * 4,
+         launch_apply<float>(n, (int)count, kappa, u, y, nullptr, ctx->st, zv<float>(ctx)));
   return MLMC_OK;
 }
 
@@ -229,15 +241,44 @@ int mlmc_vcycle(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa, co
   return MLMC_OK;
 }
 
+int mlmc_vcycle_f32(mlmc_ctx* ctx, int32_t n, int64_t count, const float* kappa, const float* r, float* z) {
+  if (!ctx) return MLMC_E_INVALID;
+  if (ctx->server) FAIL(MLMC_E_INVALID, "the context is serving");
+  if (n < 2 || !is_pow2(n) || n > 1024 || count < 1 || count > (1 << 30) || !kappa || !r || !z)
+    FAIL(MLMC_E_INVALID, "bad vcycle arguments");
+  const int B = (int)count;
+  mlmc_config saved = ctx->cfg;
+  ctx->cfg.precision = MLMC_PREC_MIXED;
+  ctx->cfg.solver = MLMC_SOLVER_GMG_PCG;
+  int rc = ensure_solve_work(ctx, n, B);
+  ctx->cfg = saved;
+  if (rc) return rc;
+  auto& L = ctx->sw.L32;
+  float* own0 = L[0].kap;
+  L[0].kap = const_cast<float*>(kappa);
+  hipStream_t st = ctx->st;
+  for (size_t l = 1; l < L.size(); ++l)
+    LAUNCH(kid<float>(MLMC_K_COARSEN), 0, launch_coarsen<float>(L[l - 1].n, B, L[l - 1].kap, L[l].kap, st));
+  SolveState& S = ctx->sw.inner.s;
+  LAUNCH(MLMC_K_MISC, 0, launch_set_active(B, S, 1, st));
+  float* res = nullptr;
+  rc = vcycle<float>(ctx, L, 0, B, r, L[0].x, L[0].xo, L[0].t, S.active, &res);
+  L[0].kap = own0;
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(z, res, (size_t)B * grid_stride(n) * sizeof(float), hipMemcpyDeviceToDevice, st));
+  return MLMC_OK;
+}
+
 int mlmc_solve(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa, double* u, int32_t* iters) {
   if (!ctx) return MLMC_E_INVALID;
   if (ctx->server) FAIL(MLMC_E_INVALID, "the context is serving");
   if (n < 2 || !is_pow2(n) || count < 1 || count > (1 << 30) || !kappa || !u)
     FAIL(MLMC_E_INVALID, "bad solve arguments");
   if (int rc = ensure_solve_work(ctx, n, (int)count)) return rc;
-  bool conv = false;
-  if (int rc = solve_impl(ctx, ctx->sw, kappa, u, iters, &conv)) return rc;
-  if (!conv) FAIL(MLMC_E_NOCONV, "some samples did not reach rtol within max_iter");
+  int status = MLMC_OK;
+  if (int rc = solve_impl(ctx, ctx->sw, kappa, u, iters, &status)) return rc;
+  if (status == MLMC_E_NONFINITE) FAIL(MLMC_E_NONFINITE, "a residual became NaN or Inf");
+  if (status) FAIL(MLMC_E_NOCONV, "some samples did not reach rtol within max_iter");
   return MLMC_OK;
 }
 
@@ -263,7 +304,17 @@ int mlmc_sample_level(mlmc_ctx* ctx, int32_t level, uint64_t first, uint64_t cou
   const int nf = ctx->cfg.n0 << level;
   if (ctx->cfg.qoi == 1 && ((nf % 4) || (level > 0 && (nf / 2) % 4)))
     FAIL(MLMC_E_INVALID, "subcube QoI needs 4 | n on both meshes");
-  return run_level(ctx, level, first, count, y, q_fine, q_coarse, iters, true);
+  if (count == 0) return MLMC_OK;
+  ctx->last_busy = ctx->last_wall = 0.0;
+  std::vector<LevelReq> reqs(1);
+  reqs[0].level = level;
+  reqs[0].first = first;
+  reqs[0].count = count;
+  reqs[0].y = y;
+  reqs[0].qf = q_fine;
+  reqs[0].qc = q_coarse;
+  reqs[0].iters = iters;
+  return run_round(ctx, reqs, true);
 }
 
 int mlmc_get_tuning(const mlmc_ctx* ctx, mlmc_tuning* out) {
@@ -286,13 +337,20 @@ int mlmc_autotune(mlmc_ctx* ctx, int32_t level, int32_t batch, mlmc_tuning* best
   if (level < 0 || level >= ctx->cfg.levels || batch < 1) FAIL(MLMC_E_INVALID, "bad autotune arguments");
   const uint64_t first = 1ull << 40;   // sample indices far from any estimator run
   std::vector<double> y(batch), qf(batch), qc(batch);
+  std::vector<LevelReq> reqs(1);
+  reqs[0].level = level;
+  reqs[0].first = first;
+  reqs[0].count = (uint64_t)batch;
+  reqs[0].y = y.data();
+  reqs[0].qf = qf.data();
+  reqs[0].qc = qc.data();
   auto timed = [&](const mlmc_tuning& t, double* sec) -> int {
     apply_tuning(ctx, t);
     // one untimed run carves work spaces and captures graphs
-    int rc = run_level(ctx, level, first, (uint64_t)batch, y.data(), qf.data(), qc.data(), nullptr, false);
+    int rc = run_round(ctx, reqs, false);
     if (rc && rc != MLMC_E_NOCONV) return rc;
     const auto t0 = std::chrono::steady_clock::now();
-    rc = run_level(ctx, level, first, (uint64_t)batch, y.data(), qf.data(), qc.data(), nullptr, false);
+    rc = run_round(ctx, reqs, false);
     if (rc && rc != MLMC_E_NOCONV) return rc;
     *sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / batch;
     return MLMC_OK;
@@ -347,6 +405,11 @@ int mlmc_autotune(mlmc_ctx* ctx, int32_t level, int32_t batch, mlmc_tuning* best
     mlmc_tuning c = best; c.max_batch = batch / div;
     if (int rc = trial(c)) return rc;
   }
+  for (int k : {1, 2, 4}) {
+    if (k == best.lanes) continue;
+    mlmc_tuning c = best; c.lanes = k;
+    if (int rc = trial(c)) return rc;
+  }
   best.seconds = best_s;
   apply_tuning(ctx, best);
   if (best_out) *best_out = best;
@@ -393,6 +456,29 @@ void decay_rate(const std::vector<double>& vals, int lmax, double dflt, double l
   *c = std::pow(s, logc);
 }
 
+// One sampling round that brings every level 0..L up to target[l] samples
+// (continuing each level's sample indices); NOCONV / NONFINITE are merged into
+// *status (NONFINITE first) and do not stop the caller's loop.
+int sample_to(mlmc_ctx* ctx, const std::vector<uint64_t>& target, int L, int* status) {
+  std::vector<LevelReq> reqs;
+  for (int l = 0; l <= L; ++l) {
+    const uint64_t have = ctx->stats[l].n;
+    if (target[l] > have) {
+      LevelReq q;
+      q.level = l;
+      q.first = ctx->stats[l].next;
+      q.count = target[l] - have;
+      reqs.push_back(q);
+    }
+  }
+  const int rc = run_round(ctx, reqs, true);
+  if (rc == MLMC_E_NONFINITE || rc == MLMC_E_NOCONV) {
+    if (*status != MLMC_E_NONFINITE) *status = rc;
+    return MLMC_OK;
+  }
+  return rc;
+}
+
 }  // namespace
 
 int mlmc_estimate_adaptive(mlmc_ctx* ctx, const mlmc_adaptive_opts* o, uint64_t* n_per_level,
@@ -420,21 +506,15 @@ int mlmc_estimate_adaptive(mlmc_ctx* ctx, const mlmc_adaptive_opts* o, uint64_t*
     return dof_cost(l);
   };
   int L = o->l0;
+  int status = MLMC_OK;
+  ctx->last_busy = ctx->last_wall = 0.0;
   std::vector<uint64_t> target(M, 0);
   for (int l = 0; l <= L; ++l) target[l] = std::max<uint64_t>(ctx->stats[l].n, (uint64_t)o->n_pilot);
   double alpha = 0.0, beta = 0.0, bias = 0.0, err = 0.0;
   int rounds = 0;
   for (int rnd = 0; rnd <= o->max_rounds; ++rnd) {
     rounds = rnd + 1;
-    for (int l = 0; l <= L; ++l) {
-      const uint64_t have = ctx->stats[l].n;
-      if (target[l] > have) {
-        const uint64_t need = target[l] - have;
-        std::vector<double> y(need), qf(need), qc(need);
-        const int rc = mlmc_sample_level(ctx, l, ctx->stats[l].next, need, y.data(), qf.data(), qc.data(), nullptr);
-        if (rc != MLMC_OK && rc != MLMC_E_NOCONV) return rc;
-      }
-    }
+    if (int rc = sample_to(ctx, target, L, &status)) return rc;
     std::vector<double> mean(M), var(M);
     for (int l = 0; l < M; ++l) {
       const Running& r = ctx->stats[l];
@@ -484,7 +564,9 @@ int mlmc_estimate_adaptive(mlmc_ctx* ctx, const mlmc_adaptive_opts* o, uint64_t*
     info->bias = bias;
     info->err = err;
   }
-  if (out) return mlmc_get_estimate(ctx, out);
+  if (out) mlmc_get_estimate(ctx, out);
+  if (status == MLMC_E_NONFINITE) FAIL(status, "some samples were NaN or Inf (kept out of the statistics)");
+  if (status == MLMC_E_NOCONV) FAIL(status, "some samples did not reach rtol within max_iter");
   return MLMC_OK;
 }
 
@@ -500,19 +582,24 @@ int mlmc_get_estimate(const mlmc_ctx* ctx, mlmc_estimate_out* out) {
     o.m2 = r.m2;
     o.var = r.n ? r.m2 / (double)r.n : 0.0;
     o.cost = r.cost;
+    o.nonfinite = r.nonfinite;
     out->qtilde += r.mean;
     if (r.n) out->var_qtilde += o.var / (double)r.n;
   }
+  out->lanes = ctx->last_lanes;
+  out->active_ratio = ctx->last_wall > 0.0 ? ctx->last_busy / ctx->last_wall : 0.0;
   return MLMC_OK;
 }
 
 int mlmc_estimate(mlmc_ctx* ctx, const mlmc_estimate_opts* o, uint64_t* n_per_level, mlmc_estimate_out* out) {
   if (!ctx) return MLMC_E_INVALID;
   if (ctx->server) FAIL(MLMC_E_INVALID, "the context is serving");
-  if (!o || !(o->eps > 0.0) || o->n_pilot < 2 || o->cost_model < 0 || o->cost_model > 1 || !(o->extra_fraction >= 0.0) ||
-      o->max_rounds < 1)
+  if (!o || (!o->n_fixed && !(o->eps > 0.0)) || o->n_pilot < 2 || o->cost_model < 0 || o->cost_model > 1 ||
+      !(o->extra_fraction >= 0.0) || o->max_rounds < 1)
     FAIL(MLMC_E_INVALID, "bad estimate options");
   const int L = ctx->cfg.levels;
+  int status = MLMC_OK;
+  ctx->last_busy = ctx->last_wall = 0.0;
   auto cost_of = [&](int l) {
     const Running& r = ctx->stats[l];
     if (o->cost_model == 1 || r.timed == 0) {
@@ -522,25 +609,16 @@ int mlmc_estimate(mlmc_ctx* ctx, const mlmc_estimate_opts* o, uint64_t* n_per_le
     return r.seconds / (double)r.timed;
   };
   std::vector<uint64_t> target(L, 0);
-  // pilot
+  // pilot (or the caller's fixed N_l)
   for (int l = 0; l < L; ++l) {
     const uint64_t have = ctx->stats[l].n;
-    target[l] = std::max<uint64_t>(have, (uint64_t)o->n_pilot);
+    target[l] = std::max<uint64_t>(have, o->n_fixed ? o->n_fixed[l] : (uint64_t)o->n_pilot);
   }
   for (int round = 0; round <= o->max_rounds; ++round) {
     bool more = false;
-    for (int l = 0; l < L; ++l) {
-      const uint64_t have = ctx->stats[l].n;
-      if (target[l] > have) {
-        more = true;
-        const uint64_t need = target[l] - have;
-        std::vector<double> y(need), qf(need), qc(need);
-        const int rc = mlmc_sample_level(ctx, l, ctx->stats[l].next, need, y.data(), qf.data(), qc.data(), nullptr);
-        if (rc != MLMC_OK && rc != MLMC_E_NOCONV) return rc;
-      }
-    }
-    if (!more && round > 0) break;
-    if (round == o->max_rounds) break;
+    for (int l = 0; l < L; ++l) more = more || target[l] > ctx->stats[l].n;
+    if (int rc = sample_to(ctx, target, L - 1, &status)) return rc;
+    if ((!more && round > 0) || round == o->max_rounds || o->n_fixed) break;
     // eq. mlmc_num_samples on the current estimates
     double tot = 0.0;
     std::vector<double> V(L), C(L);
@@ -565,13 +643,42 @@ int mlmc_estimate(mlmc_ctx* ctx, const mlmc_estimate_opts* o, uint64_t* n_per_le
     ctx->stats[l].cost = cost_of(l);
     if (n_per_level) n_per_level[l] = ctx->stats[l].n;
   }
-  if (out) return mlmc_get_estimate(ctx, out);
+  if (out) mlmc_get_estimate(ctx, out);
+  if (status == MLMC_E_NONFINITE) FAIL(status, "some samples were NaN or Inf (kept out of the statistics)");
+  if (status == MLMC_E_NOCONV) FAIL(status, "some samples did not reach rtol within max_iter");
   return MLMC_OK;
 }
 
 int mlmc_reset_stats(mlmc_ctx* ctx) {
   if (!ctx) return MLMC_E_INVALID;
+  if (ctx->server) FAIL(MLMC_E_INVALID, "the context is serving");
   ctx->stats.assign(ctx->cfg.levels, Running{});
+  HIPCHK(hipMemsetAsync(ctx->d_stats, 0, (size_t)ctx->cfg.levels * sizeof(DevStats), ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return MLMC_OK;
+}
+
+int mlmc_fold_stats(mlmc_ctx* ctx, int32_t level, const double* y, uint64_t count) {
+  if (!ctx) return MLMC_E_INVALID;
+  if (ctx->server) FAIL(MLMC_E_INVALID, "the context is serving");
+  if (level < 0 || level >= ctx->cfg.levels || (count > 0 && !y)) FAIL(MLMC_E_INVALID, "bad fold arguments");
+  if (count == 0) return MLMC_OK;
+  const uint64_t nf0 = ctx->stats[level].nonfinite;
+  StatsJobs jobs{};
+  jobs.j[0] = StatsJob{y, nullptr, count, reinterpret_cast<double*>(ctx->d_stats + level)};
+  LAUNCH(MLMC_K_MISC, 0, launch_level_stats(1, jobs, ctx->st));
+  if (int rc = read_stats(ctx)) return rc;
+  if (ctx->stats[level].nonfinite != nf0) FAIL(MLMC_E_NONFINITE, "some values were NaN or Inf");
+  return MLMC_OK;
+}
+
+int mlmc_last_plan(const mlmc_ctx* ctx, mlmc_plan_task* out, int32_t max, int32_t* n) {
+  if (!ctx || !n || max < 0 || (max > 0 && !out)) return MLMC_E_INVALID;
+  *n = (int32_t)ctx->last_plan.size();
+  for (int32_t i = 0; i < max && i < *n; ++i) {
+    const Task& t = ctx->last_plan[i];
+    out[i] = mlmc_plan_task{t.level, t.n, t.first, t.count, t.lane};
+  }
   return MLMC_OK;
 }
 

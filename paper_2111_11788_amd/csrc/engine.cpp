@@ -57,8 +57,18 @@ size_t persistent_bytes(const mlmc_config* c, int K1) {
   cv.take<int>((size_t)c->n_modes);
   cv.take<int>((size_t)K1 + 1);
   cv.take<int>(mlmc_ctx::kProfCap);
+  cv.take<DevStats>((size_t)c->levels);
   for (int l = 0; l < c->levels; ++l) cv.take<double>((size_t)(c->n0 << l) * K1);
   return cv.top;
+}
+
+void drop_work(mlmc_ctx* ctx) {
+  ctx->sw.release_graphs();
+  ctx->ws_kind = -1;
+  for (auto& ln : ctx->lanes) {
+    ln->w.sw.release_graphs();
+    ln->key = std::make_tuple(-1, -1, -1);
+  }
 }
 
 // Carve a solve work space for (n, B) unless the cached one matches.
@@ -79,7 +89,7 @@ int ensure_solve_work(mlmc_ctx* ctx, int n, int B) {
     FAIL(MLMC_E_NOMEM, "arena too small for a solve of " + std::to_string(B) + " samples on " +
                            std::to_string(n) + "^3: need " + std::to_string(dry.top) + " bytes");
   }
-  ctx->sw.release_graphs();
+  drop_work(ctx);
   ctx->sw = SolveWork{};
   ctx->sw.carve(cv, n, B, ctx->cfg.precision, ctx->cfg.solver);
   HIPCHK(hipMemsetAsync((char*)ctx->cfg.arena + ctx->persistent_top, 0, cv.top - ctx->persistent_top, ctx->st));
@@ -88,55 +98,11 @@ int ensure_solve_work(mlmc_ctx* ctx, int n, int B) {
   return MLMC_OK;
 }
 
-void carve_batch(Carver& cv, BatchWork& w, const mlmc_config& c, int level, int B) {
-  const int nf = c.n0 << level;
-  w.level = level;
-  w.B = B;
-  w.xi = cv.take<double>((size_t)B * c.n_modes);
-  w.kf = cv.take<double>((size_t)B * elem_count(nf));
-  w.uf = cv.take<double>((size_t)B * grid_stride(nf));
-  w.qf = cv.take<double>(B);
-  w.qc = cv.take<double>(B);
-  w.wf.carve(cv, nf, B, c.precision, c.solver);
-  if (level > 0) {
-    const int nc = nf / 2;
-    w.kc = cv.take<double>((size_t)B * elem_count(nc));
-    w.uc = cv.take<double>((size_t)B * grid_stride(nc));
-    w.wc.carve(cv, nc, B, c.precision, c.solver);
-  }
-  if (c.forcing == MLMC_FORCING_LOGNORMAL) {
-    w.xif = cv.take<double>((size_t)B * c.n_modes);
-    w.fe = cv.take<double>((size_t)B * elem_count(nf));
-    w.bf = cv.take<double>((size_t)B * grid_stride(nf));
-    if (level > 0) w.bc = cv.take<double>((size_t)B * grid_stride(nf / 2));
-  }
-}
-
-int ensure_batch_work(mlmc_ctx* ctx, int level, int B) {
-  const auto key = std::make_tuple(1, level, B, 0);
-  if (ctx->ws_kind == 1 && ctx->ws_key == key) return MLMC_OK;
+size_t mesh_work_bytes(const mlmc_config& c, int level, int n, int B) {
   Carver dry;
-  dry.top = ctx->persistent_top;
-  BatchWork probe;
-  carve_batch(dry, probe, ctx->cfg, level, B);
-  if (dry.top > ctx->cfg.arena_bytes) {
-    ctx->ws_kind = -1;
-    FAIL(MLMC_E_NOMEM, "arena too small for a batch of " + std::to_string(B) + " samples at level " +
-                           std::to_string(level) + ": need " + std::to_string(dry.top) + " bytes");
-  }
-  Carver cv;
-  cv.base = (char*)ctx->cfg.arena;
-  cv.cap = ctx->cfg.arena_bytes;
-  cv.top = ctx->persistent_top;
-  cv.dry = false;
-  ctx->bw.wf.release_graphs();
-  ctx->bw.wc.release_graphs();
-  ctx->bw = BatchWork{};
-  carve_batch(cv, ctx->bw, ctx->cfg, level, B);
-  HIPCHK(hipMemsetAsync((char*)ctx->cfg.arena + ctx->persistent_top, 0, cv.top - ctx->persistent_top, ctx->st));
-  ctx->ws_kind = 1;
-  ctx->ws_key = key;
-  return MLMC_OK;
+  MeshWork w;
+  w.carve(dry, c, level, n, B);
+  return dry.top;
 }
 
 int ensure_tables(mlmc_ctx* ctx, int n, double** tab) {
@@ -513,7 +479,7 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
 }
 
 // kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
-int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
+int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, int* status,
                bool kap32_ready, const double* bvec) {
   const int n = w.n, B = w.B;
   hipStream_t st = ctx->st;
@@ -560,7 +526,7 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
     const ChebCoeffs& ch = ctx->cheb;
     LAUNCH(MLMC_K_SOLVE_SMALL, (e * 8 + d * 8 * (bvec ? 2 : 1)),
            launch_solve_small(n, B, ch.degree, ch.c1, ch.c2, kap, bvec, h3, u, O.active, O.iters, rtol, kInnerRtol,
-                              ctx->cfg.max_iter, kMaxOuter, st));
+                              ctx->cfg.max_iter, kMaxOuter, st, O.rr));
   } else {
     auto& L = w.L32;
     SolveState& I = w.inner.s;
@@ -663,12 +629,21 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
     HIPCHK(hipMemcpyAsync(O.iters, I.iters, B * sizeof(int), hipMemcpyDeviceToDevice, st));
   }
   std::vector<int> act(B);
+  std::vector<double> rr(B);
   HIPCHK(hipMemcpyAsync(act.data(), O.active, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(rr.data(), O.rr, B * sizeof(double), hipMemcpyDeviceToHost, st));
   if (iters_host) HIPCHK(hipMemcpyAsync(iters_host, O.iters, B * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  bool ok = true;
-  for (int b = 0; b < B; ++b) ok = ok && act[b] == 0;
-  *all_conv = ok;
+  // the last outer residual tells a NaN / Inf stop from convergence
+  int stat = MLMC_OK;
+  for (int b = 0; b < B; ++b) {
+    if (!std::isfinite(rr[b])) {
+      stat = MLMC_E_NONFINITE;
+      break;
+    }
+    if (act[b]) stat = MLMC_E_NOCONV;
+  }
+  *status = stat;
   return MLMC_OK;
 }
 
@@ -681,91 +656,392 @@ int qoi_impl(mlmc_ctx* ctx, SolveState& S, int n, int B, const double* u, double
 
 bool mesh_of_config(const mlmc_ctx* ctx, int n) { return ctx->d_tab.count(n) > 0; }
 
-// Batch size of a level (dynamic batch size): max_batch samples on the finest
-// configured mesh and, on a coarser level, as many samples as take the same
-// number of DOFs (at most kMaxLevelBatch, and halved while the arena cannot
-// hold the batch), so the small meshes of the coarse levels are not solved in
-// launch-bound slices of max_batch samples.  Never below max_batch (or the
-// remaining count): the arena must hold that much, as before.
-int level_batch(mlmc_ctx* ctx, int level, uint64_t remaining) {
+// ------------------------------------------------------------ sampling rounds
+
+int level_cap(const mlmc_ctx* ctx, int level) {
   const int top = ctx->cfg.levels - 1;
   auto pair = [&](int l) {
     const int nf = ctx->cfg.n0 << l;
     return dofs(nf) + (l > 0 ? dofs(nf / 2) : 0.0);
   };
-  const uint64_t base = std::min<uint64_t>(remaining, (uint64_t)ctx->cfg.max_batch);
-  double cap = (double)ctx->cfg.max_batch * std::max(1.0, pair(top) / pair(level));
-  cap = std::min(cap, (double)kMaxLevelBatch);
-  uint64_t B = std::max<uint64_t>(base, std::min<uint64_t>(remaining, (uint64_t)cap));
-  while (B > base) {
-    Carver dry;
-    dry.top = ctx->persistent_top;
-    BatchWork probe;
-    carve_batch(dry, probe, ctx->cfg, level, (int)B);
-    if (dry.top <= ctx->cfg.arena_bytes) break;
-    B = std::max(base, B / 2);
-  }
-  return (int)B;
+  // max_batch samples on the finest configured mesh; a coarser level takes as
+  // many samples as cost the same interior DOFs (at most kMaxLevelBatch), so
+  // its small meshes are not solved in launch-bound slices
+  const double cap = std::min((double)ctx->cfg.max_batch * std::max(1.0, pair(top) / pair(level)),
+                              (double)kMaxLevelBatch);
+  return std::max(ctx->cfg.max_batch, (int)cap);
 }
 
-// Draw, field, solve(s) and QoI for samples first..first+count-1 of `level`;
-// outputs to host arrays; statistics folded in when `record`.
-int run_level(mlmc_ctx* ctx, int level, uint64_t first, uint64_t count, double* y, double* q_fine, double* q_coarse,
-              int32_t* iters, bool record) {
-  const int nf = ctx->cfg.n0 << level;
-  bool all_conv = true, finite = true;
-  const auto t_start = std::chrono::steady_clock::now();
-  for (uint64_t done = 0; done < count;) {
-    const int B = level_batch(ctx, level, count - done);
-    if (int rc = ensure_batch_work(ctx, level, B)) return rc;
-    BatchWork& w = ctx->bw;
-    const uint64_t start = first + done;
-    LAUNCH(MLMC_K_XI, (double)B * ctx->cfg.n_modes * 8,
-           launch_draw_xi(ctx->cfg.seed, level, start, B, ctx->cfg.n_modes, w.xi, ctx->st));
-    const bool mixed = ctx->cfg.precision != MLMC_PREC_FP64;
-    const bool forced = ctx->cfg.forcing == MLMC_FORCING_LOGNORMAL;
-    if (forced)
-      if (int rc = forcing_impl(ctx, nf, level, start, B, w.xif, w.fe, w.bf)) return rc;
-    if (int rc = field_impl(ctx, nf, B, w.xi, w.kf, mixed ? w.wf.L32[0].kap : nullptr)) return rc;
-    bool conv = false;
-    if (int rc = solve_impl(ctx, w.wf, w.kf, w.uf, iters ? iters + done : nullptr, &conv, mixed,
-                            forced ? w.bf : nullptr))
-      return rc;
-    all_conv = all_conv && conv;
-    if (int rc = qoi_impl(ctx, w.wf.outer.s, nf, B, w.uf, w.qf)) return rc;
-    if (level > 0) {
-      if (forced) {   // the same xi_f on the coarse mesh
-        if (int rc = field_impl(ctx, nf / 2, B, w.xif, w.fe, nullptr, true)) return rc;
-        LAUNCH(MLMC_K_MISC, (double)B * (elems(nf / 2) + grid_stride(nf / 2)) * 8,
-               launch_load(nf / 2, B, w.fe, w.bc, ctx->st));
+// eq. batch with p|q_l read as the K lanes a level's batches can run on: the
+// next batch takes ceil((N - n) / K) of the N - n samples still unassigned,
+// between ceil(0.01 ceil(N / K)) and ceil(phi^-1 ceil(N / K)) (phi the golden
+// ratio), as the defaults the paper states; the minimum is raised to an eighth
+// of the lane capacity (a batched solve costs about the same launches whatever
+// its size) and every batch is capped by the lane capacity.  One lane has no
+// other partition to leave work for: its batches are the capacity.
+std::vector<int> batch_plan(uint64_t count, int K, int cap) {
+  std::vector<int> out;
+  const uint64_t C = (uint64_t)std::max(1, cap);
+  if (K <= 1) {
+    for (uint64_t n = 0; n < count;) {
+      const uint64_t b = std::min(count - n, C);
+      out.push_back((int)b);
+      n += b;
+    }
+    return out;
+  }
+  const uint64_t k = (uint64_t)K;
+  const uint64_t per = (count + k - 1) / k;
+  const double phi_inv = (std::sqrt(5.0) - 1.0) / 2.0;
+  const uint64_t hi = (uint64_t)std::ceil((double)per * phi_inv);
+  const uint64_t lo = std::max<uint64_t>((per + 99) / 100, std::min<uint64_t>(C, (C + 7) / 8));
+  for (uint64_t n = 0; n < count;) {
+    uint64_t b = (count - n + k - 1) / k;
+    b = std::max(lo, std::min(hi, b));
+    b = std::min(b, std::min(C, count - n));
+    out.push_back((int)b);
+    n += b;
+  }
+  return out;
+}
+
+// Tasks of a round (Alg. incremental_greedy on K lanes): every request is cut
+// into batches (batch_plan), a batch of a level l > 0 into its fine-mesh and
+// coarse-mesh solves; the tasks are taken by decreasing mesh (the finest
+// first; among equal meshes the finer level, then sample order) and each goes
+// to the lane with the least estimated work so far (interior DOFs x samples;
+// the lowest lane on ties).
+std::vector<Task> plan_round(const mlmc_ctx* ctx, const std::vector<LevelReq>& reqs, int K,
+                             const std::vector<int>& caps) {
+  std::vector<int> order(reqs.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return reqs[a].level > reqs[b].level; });
+  std::vector<Task> ts;
+  for (int r : order) {
+    const LevelReq& q = reqs[r];
+    uint64_t off = 0;
+    for (int b : batch_plan(q.count, K, caps[r])) {
+      Task t;
+      t.level = q.level;
+      t.req = r;
+      t.first = q.first + off;
+      t.off = off;
+      t.count = b;
+      t.n = ctx->cfg.n0 << q.level;
+      t.which = 0;
+      t.work = (double)b * dofs(t.n);
+      ts.push_back(t);
+      if (q.level > 0) {
+        t.n /= 2;
+        t.which = 1;
+        t.work = (double)b * dofs(t.n);
+        ts.push_back(t);
       }
-      if (int rc = field_impl(ctx, nf / 2, B, w.xi, w.kc, mixed ? w.wc.L32[0].kap : nullptr)) return rc;
-      if (int rc = solve_impl(ctx, w.wc, w.kc, w.uc, nullptr, &conv, mixed, forced ? w.bc : nullptr)) return rc;
-      all_conv = all_conv && conv;
-      if (int rc = qoi_impl(ctx, w.wc.outer.s, nf / 2, B, w.uc, w.qc)) return rc;
+      off += (uint64_t)b;
     }
-    HIPCHK(hipMemcpyAsync(q_fine + done, w.qf, B * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
-    if (level > 0)
-      HIPCHK(hipMemcpyAsync(q_coarse + done, w.qc, B * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
-    HIPCHK(hipStreamSynchronize(ctx->st));
-    const double cost = dofs(nf) + (level > 0 ? dofs(nf / 2) : 0.0);
-    for (int b = 0; b < B; ++b) {
-      if (level == 0) q_coarse[done + b] = 0.0;
-      y[done + b] = q_fine[done + b] - q_coarse[done + b];
-      finite = finite && std::isfinite(y[done + b]);
-      if (record) ctx->stats[level].push(y[done + b]);
+  }
+  std::stable_sort(ts.begin(), ts.end(), [](const Task& a, const Task& b) { return a.n > b.n; });
+  std::vector<double> load(std::max(1, K), 0.0);
+  for (Task& t : ts) {
+    int best = 0;
+    for (int i = 1; i < K; ++i)
+      if (load[i] < load[best]) best = i;
+    t.lane = best;
+    load[best] += t.work;
+  }
+  return ts;
+}
+
+namespace {
+
+int ensure_lanes(mlmc_ctx* ctx, int K) {
+  while ((int)ctx->lanes.size() < K) {
+    auto ln = std::make_unique<LaneState>();
+    if (!ctx->lanes.empty()) {
+      // lanes after the first: an engine view with its own stream (default
+      // priority) and pinned counter
+      auto sub = std::make_unique<mlmc_ctx>();
+      if (hipStreamCreate(&sub->st) != hipSuccess) FAIL(MLMC_E_DEVICE, "cannot create a lane stream");
+      sub->own_stream = true;
+      if (hipHostMalloc((void**)&sub->h_nactive, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        hipStreamDestroy(sub->st);
+        FAIL(MLMC_E_DEVICE, "cannot allocate a lane counter");
+      }
+      ln->sub = std::move(sub);
     }
-    if (record) ctx->stats[level].cost = cost;
-    done += (uint64_t)B;
+    ctx->lanes.push_back(std::move(ln));
   }
-  if (count && record) {
-    Running& r = ctx->stats[level];
-    r.seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-    r.timed += count;
-    r.next = std::max(r.next, first + count);
+  for (size_t i = 1; i < ctx->lanes.size(); ++i) {
+    mlmc_ctx* s = ctx->lanes[i]->sub.get();
+    s->cfg = ctx->cfg;
+    s->K1 = ctx->K1;
+    s->d_sqrtlam = ctx->d_sqrtlam;
+    s->d_triples = ctx->d_triples;
+    s->d_xperm = ctx->d_xperm;
+    s->d_xoff = ctx->d_xoff;
+    s->field_kernel = ctx->field_kernel;
+    s->d_tab = ctx->d_tab;
+    s->persistent_top = ctx->persistent_top;
+    s->cheb = ctx->cheb;
+    s->zvar[0] = ctx->zvar[0];
+    s->zvar[1] = ctx->zvar[1];
+    s->vsmall_n0[0] = ctx->vsmall_n0[0];
+    s->vsmall_n0[1] = ctx->vsmall_n0[1];
+    s->use_graphs = ctx->use_graphs;
+    s->graph_batch = ctx->graph_batch;
+    s->fuse = ctx->fuse;
+    s->profiling = false;
   }
-  if (!finite) FAIL(MLMC_E_NONFINITE, "non-finite QoI");
-  if (!all_conv) FAIL(MLMC_E_NOCONV, "some samples did not reach rtol within max_iter");
+  return MLMC_OK;
+}
+
+// One task on a lane (ctx: the lane's engine view): draw, forcing, field,
+// solve and QoI of its samples on its mesh; the QoIs go to dq (device, the
+// task's slice of the round's buffer).
+int run_task(mlmc_ctx* ctx, LaneState& ln, const Task& t, double* dq, int32_t* iters_host, int* status) {
+  const mlmc_config& c = ctx->cfg;
+  const int B = t.count;
+  const auto key = std::make_tuple(0, t.n, B);
+  if (ln.key != key) {
+    ln.w.sw.release_graphs();
+    ln.w = MeshWork{};
+    Carver cv;
+    cv.base = (char*)c.arena;
+    cv.cap = c.arena_bytes;
+    cv.top = ln.offset;
+    cv.dry = false;
+    ln.w.carve(cv, c, t.level, t.n, B);
+    // zero boundaries of every grid vector (kernels never write them)
+    HIPCHK(hipMemsetAsync((char*)c.arena + ln.offset, 0, cv.top - ln.offset, ctx->st));
+    ln.key = key;
+  }
+  MeshWork& w = ln.w;
+  w.level = t.level;
+  const bool mixed = c.precision != MLMC_PREC_FP64;
+  const bool forced = c.forcing == MLMC_FORCING_LOGNORMAL;
+  LAUNCH(MLMC_K_XI, (double)B * c.n_modes * 8, launch_draw_xi(c.seed, t.level, t.first, B, c.n_modes, w.xi, ctx->st));
+  if (forced)
+    if (int rc = forcing_impl(ctx, t.n, t.level, t.first, B, w.xif, w.fe, w.bvec)) return rc;
+  if (int rc = field_impl(ctx, t.n, B, w.xi, w.kap, mixed ? w.sw.L32[0].kap : nullptr)) return rc;
+  if (int rc = solve_impl(ctx, w.sw, w.kap, w.u, iters_host, status, mixed, forced ? w.bvec : nullptr)) return rc;
+  if (int rc = qoi_impl(ctx, w.sw.outer.s, t.n, B, w.u, w.q)) return rc;
+  HIPCHK(hipMemcpyAsync(dq, w.q, (size_t)B * sizeof(double), hipMemcpyDeviceToDevice, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return MLMC_OK;
+}
+
+int worse(int a, int b) {
+  if (a == MLMC_E_NONFINITE || b == MLMC_E_NONFINITE) return MLMC_E_NONFINITE;
+  if (a == MLMC_E_NOCONV || b == MLMC_E_NOCONV) return MLMC_E_NOCONV;
+  return MLMC_OK;
+}
+
+}  // namespace
+
+int read_stats(mlmc_ctx* ctx) {
+  const int L = ctx->cfg.levels;
+  std::vector<DevStats> rec(L);
+  HIPCHK(hipMemcpyAsync(rec.data(), ctx->d_stats, L * sizeof(DevStats), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  for (int l = 0; l < L; ++l) {
+    double n = rec[l].n, mean = rec[l].mean, m2 = rec[l].m2;
+    chan_merge(n, mean, m2, rec[l].pn, rec[l].pmean, rec[l].pm2);
+    Running& r = ctx->stats[l];
+    r.n = (uint64_t)n;
+    r.mean = mean;
+    r.m2 = m2;
+    r.nonfinite = rec[l].nonfinite;
+  }
+  return MLMC_OK;
+}
+
+int run_round(mlmc_ctx* ctx, std::vector<LevelReq>& reqs, bool record) {
+  const mlmc_config& c = ctx->cfg;
+  uint64_t total = 0;
+  std::vector<uint64_t> base(reqs.size());
+  for (size_t i = 0; i < reqs.size(); ++i) {
+    for (size_t j = 0; j < i; ++j)
+      if (reqs[j].level == reqs[i].level) FAIL(MLMC_E_INVALID, "a round takes each level once");
+    base[i] = total;
+    total += reqs[i].count;
+  }
+  if (total == 0) return MLMC_OK;
+  if (total > ((uint64_t)1 << 31)) FAIL(MLMC_E_INVALID, "too many samples in one call");
+  // the QoIs of every sample on both meshes, at the end of the arena
+  const size_t qbytes = 2 * align256(total * sizeof(double));
+  std::vector<int> caps(reqs.size());
+  for (size_t i = 0; i < reqs.size(); ++i) caps[i] = level_cap(ctx, reqs[i].level);
+  int K = ctx->profiling ? 1 : std::max(1, ctx->n_lanes);
+  std::vector<Task> ts;
+  std::vector<size_t> lane_bytes;
+  for (;;) {
+    ts = plan_round(ctx, reqs, K, caps);
+    lane_bytes.assign(K, 0);
+    for (const Task& t : ts) lane_bytes[t.lane] = std::max(lane_bytes[t.lane], mesh_work_bytes(c, t.level, t.n, t.count));
+    size_t need = ctx->persistent_top + qbytes + 256;   // the QoI buffers start at a 256-byte boundary
+    for (size_t b : lane_bytes) need += b;
+    if (need <= c.arena_bytes) break;
+    if (K > 1) {   // fewer lanes
+      --K;
+      continue;
+    }
+    bool shrunk = false;   // one lane: halve the batches down to max_batch
+    for (int& cp : caps)
+      if (cp > c.max_batch) {
+        cp = std::max(c.max_batch, cp / 2);
+        shrunk = true;
+      }
+    if (shrunk) continue;
+    // still too large: the QoI buffers of a long request crowd out the batch;
+    // run the first and second halves of every request as two rounds (the
+    // statistics are folded in the same sample order)
+    bool splittable = false;
+    for (const LevelReq& q : reqs) splittable = splittable || q.count > (uint64_t)c.max_batch;
+    if (!splittable)
+      FAIL(MLMC_E_NOMEM, "arena too small for a batch of the round: need " + std::to_string(need) + " bytes");
+    std::vector<LevelReq> a = reqs, b = reqs;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+      const uint64_t h = reqs[i].count / 2;
+      a[i].count = h;
+      b[i].first += h;
+      b[i].count -= h;
+      if (b[i].y) b[i].y += h;
+      if (b[i].qf) b[i].qf += h;
+      if (b[i].qc) b[i].qc += h;
+      if (b[i].iters) b[i].iters += h;
+    }
+    a.erase(std::remove_if(a.begin(), a.end(), [](const LevelReq& q) { return q.count == 0; }), a.end());
+    const int ra = run_round(ctx, a, record);
+    if (ra && ra != MLMC_E_NOCONV && ra != MLMC_E_NONFINITE) return ra;
+    const std::string ea = ctx->err;
+    const int rb = run_round(ctx, b, record);
+    if (rb && rb != MLMC_E_NOCONV && rb != MLMC_E_NONFINITE) return rb;
+    const int worst = worse(ra, rb);
+    if (worst == ra && ra) ctx->err = ea;
+    return worst;
+  }
+  if (int rc = ensure_lanes(ctx, K)) return rc;
+  // the step-level work space shares the arena with the lanes
+  ctx->sw.release_graphs();
+  ctx->ws_kind = -1;
+  size_t off = ctx->persistent_top;
+  for (int i = 0; i < K; ++i) {
+    LaneState& ln = *ctx->lanes[i];
+    if (ln.offset != off || ln.bytes != lane_bytes[i]) {
+      ln.w.sw.release_graphs();
+      ln.key = std::make_tuple(-1, -1, -1);
+      ln.offset = off;
+      ln.bytes = lane_bytes[i];
+    }
+    ln.tasks.clear();
+    off += lane_bytes[i];
+  }
+  for (size_t i = 0; i < ts.size(); ++i) ctx->lanes[ts[i].lane]->tasks.push_back((int)i);
+  double* dqf = reinterpret_cast<double*>((char*)c.arena + (c.arena_bytes - qbytes) / 256 * 256);
+  double* dqc = dqf + align256(total * sizeof(double)) / sizeof(double);
+  // lanes start after the work queued so far on the context's stream
+  if (K > 1) {
+    hipEvent_t ev = take_event(ctx);
+    HIPCHK(hipEventRecord(ev, ctx->st));
+    for (int i = 1; i < K; ++i) HIPCHK(hipStreamWaitEvent(ctx->lanes[i]->sub->st, ev, 0));
+    ctx->event_pool.push_back(ev);
+  }
+  std::vector<double> task_s(ts.size(), 0.0);
+  auto body = [&](int i) {
+    LaneState& ln = *ctx->lanes[i];
+    mlmc_ctx* lc = i == 0 ? ctx : ln.sub.get();
+    ln.busy = 0.0;
+    ln.rc = MLMC_OK;
+    ln.status = MLMC_OK;
+    for (int ti : ln.tasks) {
+      const Task& t = ts[ti];
+      const LevelReq& q = reqs[t.req];
+      const auto t0 = std::chrono::steady_clock::now();
+      int st = MLMC_OK;
+      double* dq = (t.which ? dqc : dqf) + base[t.req] + t.off;
+      int32_t* it = (t.which == 0 && q.iters) ? q.iters + t.off : nullptr;
+      const int rc = run_task(lc, ln, t, dq, it, &st);
+      task_s[ti] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      ln.busy += task_s[ti];
+      if (rc) {
+        ln.rc = rc;
+        break;
+      }
+      ln.status = worse(ln.status, st);
+    }
+  };
+  const auto w0 = std::chrono::steady_clock::now();
+  std::vector<std::thread> th;
+  for (int i = 1; i < K; ++i) th.emplace_back(body, i);
+  body(0);
+  for (auto& x : th) x.join();
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+  ctx->last_plan = ts;
+  ctx->last_wall += wall;
+  ctx->last_lanes = K;
+  int status = MLMC_OK;
+  for (int i = 0; i < K; ++i) {
+    LaneState& ln = *ctx->lanes[i];
+    ctx->last_busy += ln.busy / K;
+    if (ln.rc) {
+      if (i > 0) ctx->err = ln.sub->err;
+      drop_work(ctx);
+      return ln.rc;
+    }
+    status = worse(status, ln.status);
+  }
+  // host outputs, then the statistics fold in sample order (one workgroup per level)
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    const LevelReq& q = reqs[r];
+    if (q.qf || q.y)
+      HIPCHK(hipMemcpyAsync(q.qf ? q.qf : q.y, dqf + base[r], q.count * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+    if (q.level > 0 && q.qc)
+      HIPCHK(hipMemcpyAsync(q.qc, dqc + base[r], q.count * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+  }
+  if (record) {
+    StatsJobs jobs{};
+    int nj = 0;
+    for (size_t r = 0; r < reqs.size(); ++r) {
+      jobs.j[nj++] = StatsJob{dqf + base[r], reqs[r].level > 0 ? dqc + base[r] : nullptr, reqs[r].count,
+                              reinterpret_cast<double*>(ctx->d_stats + reqs[r].level)};
+      if (nj == kMaxStatsJobs || r + 1 == reqs.size()) {
+        LAUNCH(MLMC_K_MISC, 0, launch_level_stats(nj, jobs, ctx->st));
+        nj = 0;
+      }
+    }
+  }
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    LevelReq& q = reqs[r];
+    if (q.level == 0 && q.qc) std::fill(q.qc, q.qc + q.count, 0.0);
+    if (q.y && q.qf)
+      for (uint64_t i = 0; i < q.count; ++i) q.y[i] = q.qf[i] - (q.level > 0 && q.qc ? q.qc[i] : 0.0);
+    if (q.y && !q.qf && q.level > 0) {
+      std::vector<double> qc(q.count);
+      HIPCHK(hipMemcpyAsync(qc.data(), dqc + base[r], q.count * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+      HIPCHK(hipStreamSynchronize(ctx->st));
+      for (uint64_t i = 0; i < q.count; ++i) q.y[i] -= qc[i];
+    }
+    if (q.y)
+      for (uint64_t i = 0; i < q.count; ++i)
+        if (!std::isfinite(q.y[i])) status = MLMC_E_NONFINITE;
+  }
+  if (record) {
+    std::vector<uint64_t> nf0(c.levels);
+    for (int l = 0; l < c.levels; ++l) nf0[l] = ctx->stats[l].nonfinite;
+    if (int rc = read_stats(ctx)) return rc;
+    for (size_t r = 0; r < reqs.size(); ++r) {
+      Running& R = ctx->stats[reqs[r].level];
+      if (R.nonfinite != nf0[reqs[r].level]) status = MLMC_E_NONFINITE;
+      const int nf = c.n0 << reqs[r].level;
+      R.cost = dofs(nf) + (reqs[r].level > 0 ? dofs(nf / 2) : 0.0);
+      R.timed += reqs[r].count;
+      R.next = std::max(R.next, reqs[r].first + reqs[r].count);
+    }
+    for (size_t i = 0; i < ts.size(); ++i) ctx->stats[ts[i].level].seconds += task_s[i];
+  }
+  if (status == MLMC_E_NONFINITE) FAIL(MLMC_E_NONFINITE, "a solve or QoI became NaN or Inf");
+  if (status == MLMC_E_NOCONV) FAIL(MLMC_E_NOCONV, "some samples did not reach rtol within max_iter");
   return MLMC_OK;
 }
 
@@ -778,6 +1054,7 @@ int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (t->max_batch < 1) { why = "max_batch must be >= 1"; return MLMC_E_INVALID; }
   if (t->graph_batch < 0 || t->graph_batch > 16) { why = "graph_batch must be in 0..16"; return MLMC_E_INVALID; }
   if (t->field < 0 || t->field > 2) { why = "field must be 0 (auto), 1 (MFMA GEMM) or 2 (separable)"; return MLMC_E_INVALID; }
+  if (t->lanes < 1 || t->lanes > 8) { why = "lanes must be in 1..8"; return MLMC_E_INVALID; }
   if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
                    MLMC_FUSE_DIRECTION | MLMC_FUSE_RUPDATE | MLMC_FUSE_SOLVE)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
   return MLMC_OK;
@@ -794,6 +1071,7 @@ mlmc_tuning current_tuning(const mlmc_ctx* ctx) {
   t.graph_batch = ctx->use_graphs ? ctx->graph_batch : 0;
   t.fuse = ctx->fuse;
   t.field = ctx->field_kernel;
+  t.lanes = ctx->n_lanes;
   t.seconds = 0.0;
   return t;
 }
@@ -812,10 +1090,9 @@ void apply_tuning(mlmc_ctx* ctx, const mlmc_tuning& t) {
   ctx->graph_batch = std::max(1, t.graph_batch);
   ctx->fuse = t.fuse;
   ctx->field_kernel = t.field;
+  ctx->n_lanes = t.lanes;
   // captured graphs bake in kernel choices: drop them
-  ctx->sw.release_graphs();
-  ctx->bw.wf.release_graphs();
-  ctx->bw.wc.release_graphs();
+  drop_work(ctx);
 }
 
 template int vcycle<float>(mlmc_ctx*, std::vector<Level<float>>&, int, int, const float*, float*, float*, float*,

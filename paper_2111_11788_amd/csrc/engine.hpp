@@ -15,6 +15,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -24,6 +25,7 @@
 #include "kl_host.hpp"
 
 struct mlmc_server;
+struct mlmc_ctx;
 
 namespace mlmc {
 namespace eng {
@@ -40,7 +42,7 @@ constexpr double kChebHi = 1.75;
 constexpr double kChebRatio = 4.0;   // smoothing interval [hi / ratio, hi]
 constexpr double kInnerRtol = 1e-4;  // fp32 inner solve tolerance (mixed precision)
 constexpr int kMaxOuter = 30;
-constexpr int kMaxLevelBatch = 65536;   // samples per batch on a coarse level (see level_batch)
+constexpr int kMaxLevelBatch = 65536;   // samples per batch on a coarse level (see level_cap)
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 inline int ilog2i(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
@@ -177,17 +179,64 @@ struct SolveWork {
   }
 };
 
-// Work space of one batch of sample_level: draws, fields, solutions, QoIs.
-struct BatchWork {
-  int level = -1, B = 0;
+// Work space of one task: a batched solve of B samples of MLMC level `level`
+// on one mesh n (the level's own mesh or, for level > 0, its coarse partner
+// n/2 on the same draws): draws, field, solution, QoIs, solver vectors, and
+// for the random forcing xi_f, the element values of f and the load vector.
+struct MeshWork {
+  int level = -1, n = 0, B = 0;
   double* xi = nullptr;
-  double *kf = nullptr, *kc = nullptr, *uf = nullptr, *uc = nullptr;
-  double *qf = nullptr, *qc = nullptr;
-  // random forcing: xi_f, the element values of f (fine mesh size, reused
-  // for the coarse mesh) and the load vectors of the two meshes
-  double *xif = nullptr, *fe = nullptr, *bf = nullptr, *bc = nullptr;
-  SolveWork wf, wc;
+  double *kap = nullptr, *u = nullptr, *q = nullptr;
+  double *xif = nullptr, *fe = nullptr, *bvec = nullptr;
+  SolveWork sw;
+  void carve(Carver& cv, const mlmc_config& c, int level_, int n_, int B_) {
+    level = level_;
+    n = n_;
+    B = B_;
+    xi = cv.take<double>((size_t)B * c.n_modes);
+    kap = cv.take<double>((size_t)B * elem_count(n));
+    u = cv.take<double>((size_t)B * grid_stride(n));
+    q = cv.take<double>(B);
+    sw.carve(cv, n, B, c.precision, c.solver);
+    if (c.forcing == MLMC_FORCING_LOGNORMAL) {
+      xif = cv.take<double>((size_t)B * c.n_modes);
+      fe = cv.take<double>((size_t)B * elem_count(n));
+      bvec = cv.take<double>((size_t)B * grid_stride(n));
+    }
+  }
 };
+
+// One task of a sampling round: `count` samples of `level` from sample
+// index `first`, solved on mesh n (which = 0: the level's mesh, 1: the coarse
+// mesh of its pair), on lane `lane`; `req` indexes the level request and
+// `off` the samples' position in it.
+struct Task {
+  int level = 0, n = 0, which = 0, lane = 0, req = 0;
+  uint64_t first = 0, off = 0;
+  int count = 0;
+  double work = 0.0;   // estimated cost: interior DOFs x samples
+};
+
+// A level's share of a round: samples first .. first+count-1 of `level`;
+// host outputs (each may be null) of count entries.
+struct LevelReq {
+  int level = 0;
+  uint64_t first = 0, count = 0;
+  double *y = nullptr, *qf = nullptr, *qc = nullptr;
+  int32_t* iters = nullptr;
+};
+
+// Device record of a level's running statistics (eq. sample_variance,
+// eq. mlmc_average), folded in push order: the Chan et al. merge, in block
+// order, of every complete block of kStatsBlock consecutive pushes (n, mean,
+// m2) and the Welford state of the incomplete block (pn, pmean, pm2); the
+// result therefore does not depend on how the pushes were split into batches.
+// Non-finite values are counted and not pushed.
+struct DevStats {
+  double n, mean, m2, pn, pmean, pm2;
+  unsigned long long nonfinite, pad;
+};
+static_assert(sizeof(DevStats) == 64, "device statistics record");
 
 // One timed launch.  `cnt` >= 0 indexes the device count of active samples
 // taken just before a masked launch: its bytes count the active share only.
@@ -199,17 +248,12 @@ struct ProfRec {
 };
 
 struct Running {
-  uint64_t n = 0;
+  uint64_t n = 0;            // host mirror of the device record (read after each round)
   double mean = 0.0, m2 = 0.0, cost = 0.0;
-  double seconds = 0.0;     // wall time spent sampling this level
+  uint64_t nonfinite = 0;
+  double seconds = 0.0;     // lane time spent sampling this level
   uint64_t timed = 0;       // samples covered by `seconds`
   uint64_t next = 0;        // next unused sample index of the level
-  void push(double y) {
-    n += 1;
-    const double d = y - mean;
-    mean += d / (double)n;
-    m2 += d * (y - mean);
-  }
 };
 
 }  // namespace eng
@@ -236,8 +280,15 @@ struct mlmc_ctx {
   int ws_kind = -1;              // 0: solve work, 1: batch work
   std::tuple<int, int, int, int> ws_key{-1, -1, -1, -1};
   SolveWork sw;
-  BatchWork bw;
   std::vector<Running> stats;
+  DevStats* d_stats = nullptr;    // [levels] device records of the level statistics (persistent arena)
+  // lanes of the sampling rounds: lane 0 runs on this context's stream, lane
+  // i > 0 on a sub-context with its own stream, pinned counter and host thread
+  std::vector<std::unique_ptr<struct LaneState>> lanes;
+  int n_lanes = 4;                // mlmc_tuning.lanes: concurrent lanes of a round (1: one after another)
+  std::vector<Task> last_plan;    // tasks of the last round, in assignment order
+  double last_busy = 0.0, last_wall = 0.0;   // lane-seconds busy and wall seconds of the last call's rounds
+  int last_lanes = 1;
   bool profiling = false;
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> event_pool;
@@ -261,6 +312,20 @@ struct mlmc_ctx {
   int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
              MLMC_FUSE_DIRECTION | MLMC_FUSE_SOLVE;
   mlmc_server* server = nullptr;  // serving pools and threads while serving
+};
+
+// A lane of the sampling rounds: its engine view (null for lane 0, which runs
+// on the context itself), its work space (a region of the arena) and the
+// layout carved there, kept while the next task has the same layout.
+struct LaneState {
+  std::unique_ptr<mlmc_ctx> sub;
+  MeshWork w;
+  size_t offset = 0, bytes = 0;     // region of the arena
+  std::tuple<int, int, int> key{-1, -1, -1};   // (level, n, B) of the carved layout
+  std::vector<int> tasks;           // indices into the round's task list
+  double busy = 0.0;                // seconds spent on tasks in the current round
+  int rc = MLMC_OK;
+  int status = MLMC_OK;             // worst solve status of its tasks (NOCONV, NONFINITE)
 };
 
 #define FAIL(code, msg)      \
@@ -343,8 +408,11 @@ inline double elems(int n) { return (double)n * n * n; }
 int validate(const mlmc_config* c, std::string& why);
 size_t persistent_bytes(const mlmc_config* c, int K1);
 int ensure_solve_work(mlmc_ctx* ctx, int n, int B);
-void carve_batch(Carver& cv, BatchWork& w, const mlmc_config& c, int level, int B);
-int ensure_batch_work(mlmc_ctx* ctx, int level, int B);
+// Drop every cached work space (the step-level one and the lanes'), with the
+// graphs captured on them: the caller is about to use the arena after the
+// persistent tables for something else.
+void drop_work(mlmc_ctx* ctx);
+size_t mesh_work_bytes(const mlmc_config& c, int level, int n, int B);
 int ensure_tables(mlmc_ctx* ctx, int n, double** tab);
 // The PCG residual update r -= alpha q fused into the first kernel of the next
 // iteration's V-cycle (level 0, pre-smoothed residual restriction): q, the
@@ -421,14 +489,31 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
         bool defer = false, T* r2 = nullptr);
 // kap32_ready: the fp32 copy of kap is already in the fp32 hierarchy (mixed precision)
 // bvec: the right-hand side (grid layout, boundary positions 0), or NULL for f = 1
-int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, bool* all_conv,
+// *status: MLMC_OK when every sample reached rtol, MLMC_E_NONFINITE when some
+// sample's residual became NaN or Inf (its solve stops there), else
+// MLMC_E_NOCONV
+int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_t* iters_host, int* status,
                bool kap32_ready = false, const double* bvec = nullptr);
 // xi_f, f and the load vector b of B samples (first, level) on mesh n (random forcing)
 int forcing_impl(mlmc_ctx* ctx, int n, int level, uint64_t first, int B, double* xif, double* f, double* b);
 int qoi_impl(mlmc_ctx* ctx, SolveState& S, int n, int B, const double* u, double* q);
 bool mesh_of_config(const mlmc_ctx* ctx, int n);
-int run_level(mlmc_ctx* ctx, int level, uint64_t first, uint64_t count, double* y, double* q_fine, double* q_coarse,
-              int32_t* iters, bool record);
+// Samples per lane batch of a level (the DOF budget of max_batch samples on
+// the finest configured mesh, at most kMaxLevelBatch).
+int level_cap(const mlmc_ctx* ctx, int level);
+// Batch sizes of one level's request (eq. batch read for K lanes; see the
+// definition) and the tasks of a round assigned to K lanes finest mesh first
+// to the least-loaded lane (Alg. incremental_greedy).
+std::vector<int> batch_plan(uint64_t count, int K, int cap);
+std::vector<Task> plan_round(const mlmc_ctx* ctx, const std::vector<LevelReq>& reqs, int K, const std::vector<int>& caps);
+// One sampling round: every request's samples drawn, solved on both meshes of
+// the pair and reduced to QoIs, the tasks spread over the lanes; with
+// `record`, Y = Q_l - Q_{l-1} folded into the levels' device statistics in
+// sample order.  Returns the worst status (NONFINITE before NOCONV) after all
+// work is done.
+int run_round(mlmc_ctx* ctx, std::vector<LevelReq>& reqs, bool record);
+// Copy the device statistics of every level into ctx->stats (n, mean, m2).
+int read_stats(mlmc_ctx* ctx);
 int check_tuning(const mlmc_tuning* t, std::string& why);
 mlmc_tuning current_tuning(const mlmc_ctx* ctx);
 void apply_tuning(mlmc_ctx* ctx, const mlmc_tuning& t);

@@ -18,10 +18,13 @@ hipError_t launch_load(int n, int B, const double* f, double* b, hipStream_t st)
 // kappa) around fp32 GMG-PCG to inner_rtol with the V-cycle of launch_vsmall
 // (Chebyshev degree/coefficients c1, c2); b = bvec (grid layout) or bconst at
 // every interior node.  Writes u (grid layout), active (0 where converged to
-// rtol) and iters (inner iterations).
+// rtol) and iters (inner iterations); rr_out (may be null) the last fp64
+// ||b - A u||^2.  A NaN or Inf residual ends a sample's solve (active 0, rr_out
+// non-finite).
 hipError_t launch_solve_small(int n, int B, int degree, const double* c1, const double* c2, const double* kap,
                               const double* bvec, double bconst, double* u, int* active, int* iters, double rtol,
-                              double inner_rtol, int max_iter, int max_outer, hipStream_t st);
+                              double inner_rtol, int max_iter, int max_outer, hipStream_t st,
+                              double* rr_out = nullptr);
 hipError_t launch_pause_draw(uint64_t seed, int level, int64_t count, double a, double w, double* out,
                              hipStream_t st);
 // every workgroup w < nwg waits spin[w] ticks of the device wall clock and adds
@@ -229,8 +232,42 @@ enum ReduceOp : int {
   RED_RR_UPD = 10,   // fused residual update: as RED_RR, and the residual buffer flips unless first
   RED_RR_INNER_UPD = 11 // as RED_RR_INNER (serving), flip as RED_RR_UPD, and a converged slot leaves the mask
 };
+// The RR ops treat a NaN or Inf sum as the end of the sample's solve (active
+// 0, or the DONE / TRANSITION phase), keeping the value in rr so the caller can
+// tell it from convergence.
 hipError_t launch_reduce(int B, int op, double tol2, uint32_t nparts, SolveState s, double* out,
                          hipStream_t st);
+
+// Chan, Golub and LeVeque merge of the summary (nb, mb, m2b) into (n, mean, m2)
+__host__ __device__ inline void chan_merge(double& n, double& mean, double& m2, double nb, double mb, double m2b) {
+#pragma clang fp contract(off)
+  if (nb == 0.0) return;
+  const double nn = n + nb;
+  const double d = mb - mean;
+  mean = mean + d * (nb / nn);
+  m2 = m2 + m2b + d * d * (n * nb / nn);
+  n = nn;
+}
+
+// Level statistics fold (one workgroup per job): Y = qf - qc (qc may be null:
+// Y = qf) for `count` samples in sample order, pushed into the record rec
+// (layout: n, mean, m2, pn, pmean, pm2 as doubles, then the non-finite count
+// as an unsigned 64-bit integer): complete blocks of kStatsBlock pushes are
+// reduced by Welford in order and merged into (n, mean, m2) in block order;
+// the pushes of an incomplete block stay in (pn, pmean, pm2).  Non-finite Y
+// are counted, not pushed.
+constexpr int kStatsBlock = 64;
+constexpr int kMaxStatsJobs = 16;
+struct StatsJob {
+  const double* qf;
+  const double* qc;
+  uint64_t count;
+  double* rec;
+};
+struct StatsJobs {
+  StatsJob j[kMaxStatsJobs];
+};
+hipError_t launch_level_stats(int njobs, const StatsJobs& jobs, hipStream_t st);
 hipError_t launch_count_active(int B, SolveState s, hipStream_t st);
 // out[p] (one sample's grid stride) = interior unknown at position p, or -1
 hipError_t launch_node_map(int n, int32_t* out, hipStream_t st);

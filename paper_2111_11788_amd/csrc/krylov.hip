@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t
     case RED_ALPHA: st.alpha[b] = st.rz[b] / v; st.iters[b] += 1; break;
     case RED_RR:
       st.rr[b] = v;
-      if (v <= tol2 * st.bb[b]) st.active[b] = 0;
+      if (v <= tol2 * st.bb[b] || !isfinite(v)) st.active[b] = 0;
       break;
     case RED_RZ_INIT: st.rz[b] = v; break;
     case RED_BETA: st.beta[b] = v / st.rz[b]; st.rz[b] = v; break;
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t
     }
     case RED_RR_INNER:
       st.rr[b] = v;
-      if (v <= tol2 * st.bb[b]) st.phase[b] = PHASE_TRANSITION;
+      if (v <= tol2 * st.bb[b] || !isfinite(v)) st.phase[b] = PHASE_TRANSITION;
       break;
     case RED_RR_UPD:
     case RED_RR_INNER_UPD: {
@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t
       const int ps = st.pstate[b];
       if (!(ps & 2)) st.pstate[b] = ps ^ 8;
       st.rr[b] = v;
-      if (v <= tol2 * st.bb[b]) {
+      if (v <= tol2 * st.bb[b] || !isfinite(v)) {
         st.active[b] = 0;
         if (op == RED_RR_INNER_UPD) st.phase[b] = PHASE_TRANSITION;
       }
@@ -325,10 +325,99 @@ __global__ void __launch_bounds__(kBlock) k_reduce(int op, double tol2, uint32_t
     }
     case RED_RR_OUTER:
       st.rr[b] = v;
-      st.phase[b] = v <= tol2 * st.bb[b] ? PHASE_DONE : PHASE_RESTART;
+      st.phase[b] = (v <= tol2 * st.bb[b] || !isfinite(v)) ? PHASE_DONE : PHASE_RESTART;
       break;
     default: out[b] = v; break;
   }
+}
+
+// One Welford push of y into (n, mean, m2)
+__device__ __forceinline__ void welford_push(double& n, double& mean, double& m2, double y) {
+#pragma clang fp contract(off)
+  n += 1.0;
+  const double d = y - mean;
+  mean += d / n;
+  m2 += d * (y - mean);
+}
+
+// Level statistics fold, one workgroup per job (see launch_level_stats).  A
+// tile of up to kTile values is compacted to its finite values (in order) in
+// LDS; thread 0 continues the incomplete block with the first of them, one
+// thread per complete block reduces it, thread 0 merges the blocks in order
+// and starts the next incomplete block with the rest.
+constexpr int kStatsTile = 16 * kBlock;
+__global__ void __launch_bounds__(kBlock) k_level_stats(StatsJobs jobs) {
+  const StatsJob J = jobs.j[blockIdx.x];
+  __shared__ double buf[kStatsTile];
+  __shared__ int cnt[kBlock];
+  __shared__ double bmean[kStatsTile / kStatsBlock], bm2[kStatsTile / kStatsBlock];
+  __shared__ double rec[6];
+  __shared__ unsigned long long nonfin;
+  __shared__ int k0s;
+  const int tid = threadIdx.x;
+  if (tid < 6) rec[tid] = J.rec[tid];
+  if (tid == 0) nonfin = reinterpret_cast<const unsigned long long*>(J.rec)[6];
+  __syncthreads();
+  for (uint64_t base = 0; base < J.count; base += kStatsTile) {
+    const int m = (int)(J.count - base < (uint64_t)kStatsTile ? J.count - base : (uint64_t)kStatsTile);
+    // pass 1: finite values among this thread's 16 consecutive ones
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int idx = tid * 16 + k;
+      if (idx < m && isfinite(J.qf[base + idx] - (J.qc ? J.qc[base + idx] : 0.0))) ++c;
+    }
+    cnt[tid] = c;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+      const int t = tid >= off ? cnt[tid - off] : 0;
+      __syncthreads();
+      cnt[tid] += t;
+      __syncthreads();
+    }
+    const int total = cnt[kBlock - 1];
+    // pass 2: the finite values, compacted in sample order
+    int pos = cnt[tid] - c;
+    for (int k = 0; k < 16; ++k) {
+      const int idx = tid * 16 + k;
+      if (idx < m) {
+        const double y = J.qf[base + idx] - (J.qc ? J.qc[base + idx] : 0.0);
+        if (isfinite(y)) buf[pos++] = y;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int k0 = 0;
+      if (rec[3] > 0.0) {   // continue the incomplete block
+        k0 = kStatsBlock - (int)rec[3];
+        if (k0 > total) k0 = total;
+        for (int k = 0; k < k0; ++k) welford_push(rec[3], rec[4], rec[5], buf[k]);
+        if (rec[3] == (double)kStatsBlock) {
+          chan_merge(rec[0], rec[1], rec[2], rec[3], rec[4], rec[5]);
+          rec[3] = rec[4] = rec[5] = 0.0;
+        }
+      }
+      k0s = k0;
+      nonfin += (unsigned long long)(m - total);
+    }
+    __syncthreads();
+    const int k0 = k0s;
+    const int nb = (total - k0) / kStatsBlock;
+    if (tid < nb) {
+      double n = 0.0, mean = 0.0, m2 = 0.0;
+      for (int k = 0; k < kStatsBlock; ++k) welford_push(n, mean, m2, buf[k0 + tid * kStatsBlock + k]);
+      bmean[tid] = mean;
+      bm2[tid] = m2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int q = 0; q < nb; ++q) chan_merge(rec[0], rec[1], rec[2], (double)kStatsBlock, bmean[q], bm2[q]);
+      for (int k = k0 + nb * kStatsBlock; k < total; ++k) welford_push(rec[3], rec[4], rec[5], buf[k]);
+    }
+    __syncthreads();
+  }
+  if (tid < 6) J.rec[tid] = rec[tid];
+  if (tid == 0) reinterpret_cast<unsigned long long*>(J.rec)[6] = nonfin;
 }
 
 // out[p] = the interior unknown at grid position p of a sample, or -1
@@ -500,6 +589,12 @@ template <class T>
 hipError_t launch_fill_interior(int n, int B, T* v, double value, const int* active, hipStream_t st) {
   const SGeom g = sgeom<T>(n);
   k_fill_interior<T><<<sgrid<T>(g, B), kBlock, 0, st>>>(g, grid_stride(n), v, T(value), active);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_stats(int njobs, const StatsJobs& jobs, hipStream_t st) {
+  if (njobs < 1 || njobs > kMaxStatsJobs) return hipErrorInvalidValue;
+  k_level_stats<<<dim3(njobs), dim3(kBlock), 0, st>>>(jobs);
   return hipGetLastError();
 }
 

@@ -69,10 +69,7 @@ extern "C" int mlmc_pause_model(mlmc_ctx* ctx, const mlmc_pause_opts* o, int64_t
   const size_t spin_b = align256((size_t)P * sizeof(uint32_t)), meas_b = align256((size_t)P * sizeof(uint64_t));
   if (ctx->persistent_top + dur_b + spin_b + meas_b > ctx->cfg.arena_bytes)
     FAIL(MLMC_E_NOMEM, "arena too small for the pause-model draws");
-  ctx->sw.release_graphs();
-  ctx->bw.wf.release_graphs();
-  ctx->bw.wc.release_graphs();
-  ctx->ws_kind = -1;
+  drop_work(ctx);
   char* base = (char*)ctx->cfg.arena + ctx->persistent_top;
   double* d_dur = reinterpret_cast<double*>(base);
   uint32_t* d_spin = reinterpret_cast<uint32_t*>(base + dur_b);

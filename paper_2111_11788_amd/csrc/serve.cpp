@@ -360,10 +360,7 @@ int mlmc_serve_start(mlmc_ctx* ctx, const int32_t* slots_per_mesh) {
   if (need > ctx->cfg.arena_bytes)
     FAIL(MLMC_E_NOMEM, "arena too small for the serving pools: need " + std::to_string(need) + " bytes");
   // the pools take over the arena after the persistent tables
-  ctx->sw.release_graphs();
-  ctx->bw.wf.release_graphs();
-  ctx->bw.wc.release_graphs();
-  ctx->ws_kind = -1;
+  drop_work(ctx);
   auto* srv = new mlmc_server();
   srv->ctx = ctx;
   Carver cv;

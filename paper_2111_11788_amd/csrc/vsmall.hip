@@ -289,7 +289,8 @@ constexpr int solve_small_threads() { return NL == 2 ? 64 : 256; }
 template <int NL>
 __global__ void __launch_bounds__(256, (NL == 3 ? 6 : 1)) k_solve_small(SolveSmallArgs a, const double* __restrict__ kap,
                                                      const double* __restrict__ bvec, double* __restrict__ uglob,
-                                                     int* __restrict__ active, int* __restrict__ iters) {
+                                                     int* __restrict__ active, int* __restrict__ iters,
+                                                     double* __restrict__ rr_out) {
   const int smp = blockIdx.x;
   constexpr int n = 1 << NL, n2 = n * n, ne = n2 * n;
   constexpr int TPB = solve_small_threads<NL>();
@@ -355,6 +356,7 @@ __global__ void __launch_bounds__(256, (NL == 3 ? 6 : 1)) k_solve_small(SolveSma
   const double bb = wg_allsum(acc, ws);
   int total = 0;
   bool done = false;
+  double rr_last = bb;
   for (int outer = 0; outer < a.max_outer && total < a.max_iter && !done; ++outer) {
     // inner fp32 GMG-PCG on A d = fp32(r), from d = 0, to the inner tolerance
     acc = 0.0;
@@ -393,7 +395,7 @@ __global__ void __launch_bounds__(256, (NL == 3 ? 6 : 1)) k_solve_small(SolveSma
       });
       const double rr = wg_allsum(acc, ws);
       ++total;
-      if (rr <= tol2) break;
+      if (rr <= tol2 || !isfinite(rr)) break;   // a NaN or Inf residual ends the sample's solve
       vcycle_lds<float, NL>(a.v, Ri, X, Bv, Kp, cur);
       acc = 0.0;
       own([&](int t, int s) { acc += (double)Ri[s] * (double)pick(X[0], cur[0])[s]; });
@@ -414,13 +416,15 @@ __global__ void __launch_bounds__(256, (NL == 3 ? 6 : 1)) k_solve_small(SolveSma
       r64[t] = r;
       acc += r * r;
     });
-    done = wg_allsum(acc, ws) <= a.rtol2 * bb;
+    rr_last = wg_allsum(acc, ws);
+    done = rr_last <= a.rtol2 * bb || !isfinite(rr_last);
   }
   double* ug = uglob + (size_t)smp * a.v.gstride;
   for (int q = threadIdx.x; q < S; q += TPB) ug[q] = U[q];
   if (threadIdx.x == 0) {
     active[smp] = done ? 0 : 1;
     iters[smp] = total;
+    if (rr_out) rr_out[smp] = rr_last;
   }
 }
 
@@ -465,7 +469,7 @@ size_t solve_small_lds_bytes(int n) {
 
 hipError_t launch_solve_small(int n, int B, int degree, const double* c1, const double* c2, const double* kap,
                               const double* bvec, double bconst, double* u, int* active, int* iters, double rtol,
-                              double inner_rtol, int max_iter, int max_outer, hipStream_t st) {
+                              double inner_rtol, int max_iter, int max_outer, hipStream_t st, double* rr_out) {
   if (n < 4 || n > 8 || (n & (n - 1)) || degree < 1 || degree > 16 || B <= 0) return hipErrorInvalidValue;
   SolveSmallArgs a{};
   a.v.n0 = n;
@@ -483,9 +487,9 @@ hipError_t launch_solve_small(int n, int B, int degree, const double* c1, const 
   a.max_outer = max_outer;
   const size_t lds = solve_small_lds_bytes(n);
   if (n == 4)
-    k_solve_small<2><<<dim3(B), dim3(solve_small_threads<2>()), lds, st>>>(a, kap, bvec, u, active, iters);
+    k_solve_small<2><<<dim3(B), dim3(solve_small_threads<2>()), lds, st>>>(a, kap, bvec, u, active, iters, rr_out);
   else
-    k_solve_small<3><<<dim3(B), dim3(solve_small_threads<3>()), lds, st>>>(a, kap, bvec, u, active, iters);
+    k_solve_small<3><<<dim3(B), dim3(solve_small_threads<3>()), lds, st>>>(a, kap, bvec, u, active, iters, rr_out);
   return hipGetLastError();
 }
 

@@ -67,3 +67,13 @@ def test_interior_positions_layout():
     assert len(pos) == (n - 1) ** 3 and len(set(pos.tolist())) == len(pos)
     i, j, k = pos % n, (pos // n) % n, pos // (n * n)
     assert i.min() == 1 and j.min() == 1 and k.min() == 1 and max(i.max(), j.max(), k.max()) == n - 1
+
+
+def test_workspace_of_the_2cube_mesh_in_mixed_precision():
+    # host geometry of the fp32 kernels on meshes narrower than one 16-byte
+    # vector per row (2^3: one unknown); it once divided by zero on the host
+    for prec in (0, 1, 2):
+        cfg = mm.make_config(C1, n0=2, levels=3, precision=prec, solver=0)
+        for level in range(3):
+            for batch in (1, 7, 4096):
+                assert mm.workspace_bytes(cfg, level, batch) > 0
