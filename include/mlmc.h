@@ -218,6 +218,19 @@ int mlmc_solve(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa,
  * on a sub-region").  u: device, grid layout. */
 int mlmc_qoi(mlmc_ctx* ctx, int32_t n, int64_t count, const double* u, double* q);
 
+/* mlmc_qoi for callers that cannot allocate (code under graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same QoI with the
+ * same kernels and bits, but the per-sample partial sums go to a static
+ * 16 MiB device array of the library (each GPU holds its own copy until the
+ * process ends) instead of the arena, so the call allocates nothing, carves
+ * nothing and leaves the context's cached work space alone.  u, q as in
+ * mlmc_qoi.  Limit: count x ceil(vectors / 2048) partial sums must fit the
+ * scratch (about 33000 samples of 64^3, 2 million of 8^3); a larger count is
+ * refused with MLMC_E_INVALID.  Calls that overlap on one GPU (several
+ * streams or threads at once) share the array and race; calls in order on one
+ * stream do not (every partial sum is written before it is read). */
+int mlmc_qoi_noalloc(mlmc_ctx* ctx, int32_t n, int64_t count, const double* u, double* q);
+
 /* The random forcing of samples first .. first+count-1 of `level` on mesh n
  * (device arrays, sample-major): xi_f of sample i is drawn like xi
  * (mlmc_draw_xi) but from the Philox blocks with counter (i, level, j, 2);

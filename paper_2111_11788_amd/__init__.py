@@ -28,7 +28,7 @@ KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "
 # exported symbols of include/mlmc.h (checked by the CPU test suite)
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
            "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_apply_f32", "mlmc_vcycle",
-           "mlmc_vcycle_f32", "mlmc_solve", "mlmc_qoi", "mlmc_fold_stats", "mlmc_last_plan",
+           "mlmc_vcycle_f32", "mlmc_solve", "mlmc_qoi", "mlmc_qoi_noalloc", "mlmc_fold_stats", "mlmc_last_plan",
            "mlmc_sample_level", "mlmc_estimate", "mlmc_estimate_adaptive", "mlmc_get_estimate", "mlmc_reset_stats",
            "mlmc_node_map", "mlmc_pause_model", "mlmc_forcing",
            "mlmc_set_profiling", "mlmc_kernel_time", "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
@@ -157,6 +157,7 @@ def lib():
         "mlmc_last_plan": (ctypes.c_int, [P, P, I32, ctypes.POINTER(I32)]),
         "mlmc_solve": (ctypes.c_int, [P, I32, I64, P, P, P]),
         "mlmc_qoi": (ctypes.c_int, [P, I32, I64, P, P]),
+        "mlmc_qoi_noalloc": (ctypes.c_int, [P, I32, I64, P, P]),
         "mlmc_sample_level": (ctypes.c_int, [P, I32, U64, U64, P, P, P, P]),
         "mlmc_get_estimate": (ctypes.c_int, [P, ctypes.POINTER(EstimateOut)]),
         "mlmc_estimate": (ctypes.c_int, [P, ctypes.POINTER(EstimateOpts), P, ctypes.POINTER(EstimateOut)]),
@@ -317,6 +318,13 @@ class Context:
     def qoi(self, n: int, u_grid):
         q = self.torch.empty(u_grid.shape[0], dtype=self.torch.float64, device="cuda")
         self._check(lib().mlmc_qoi(self.h, n, u_grid.shape[0], _ptr(u_grid), _ptr(q)))
+        return q
+
+    def qoi_noalloc(self, n: int, u_grid, q=None):
+        """mlmc_qoi_noalloc: the QoI with its partial sums in the library's static scratch (q may be given)."""
+        if q is None:
+            q = self.torch.empty(u_grid.shape[0], dtype=self.torch.float64, device="cuda")
+        self._check(lib().mlmc_qoi_noalloc(self.h, n, u_grid.shape[0], _ptr(u_grid), _ptr(q)))
         return q
 
     # --- whole path (host outputs) -------------------------------------------

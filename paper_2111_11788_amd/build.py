@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmlmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["rng.hip", "field.hip", "stencil.hip", "krylov.hip", "vsmall.hip", "pause.hip", "kl_host.cpp", "engine.cpp", "serve.cpp", "api.cpp", "pause.cpp"]
+SOURCES = ["rng.hip", "field.hip", "stencil.hip", "krylov.hip", "vsmall.hip", "pause.hip", "scratch.hip", "kl_host.cpp", "engine.cpp", "serve.cpp", "api.cpp", "pause.cpp"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
           "-I", CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]

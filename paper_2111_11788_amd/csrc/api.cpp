@@ -87,6 +87,7 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
     e = hipMemcpyAsync(d, tabs.back().data(), tabs.back().size() * sizeof(double), hipMemcpyHostToDevice, ctx->st);
   }
   if (e == hipSuccess) e = hipMemsetAsync(ctx->d_stats, 0, (size_t)cfg->levels * sizeof(DevStats), ctx->st);
+  if (e == hipSuccess) e = noalloc_scratch_init(&ctx->device, &ctx->scratch);
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_nactive, sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
   if (e != hipSuccess) {
@@ -294,6 +295,21 @@ int mlmc_qoi(mlmc_ctx* ctx, int32_t n, int64_t count, const double* u, double* q
 }  // extern "C"
 
 extern "C" {
+
+int mlmc_qoi_noalloc(mlmc_ctx* ctx, int32_t n, int64_t count, const double* u, double* q) {
+  if (!ctx) return MLMC_E_INVALID;
+  if (n < 2 || !is_pow2(n) || n > 1024 || count < 1 || count > (1 << 30) || !u || !q)
+    FAIL(MLMC_E_INVALID, "bad qoi arguments");
+  if (ctx->cfg.qoi == 1 && n % 4) FAIL(MLMC_E_INVALID, "subcube QoI needs 4 | n");
+  if (qoi_scratch_bytes(n, (int)count) > noalloc_scratch_bytes())
+    FAIL(MLMC_E_INVALID, "count above the static scratch: at most " +
+                             std::to_string(noalloc_scratch_bytes() / qoi_scratch_bytes(n, 1)) + " samples on " +
+                             std::to_string(n) + "^3");
+  if (!ctx->scratch) FAIL(MLMC_E_DEVICE, "no static scratch on this device");
+  const hipError_t e = launch_qoi_scratch(n, (int)count, ctx->cfg.qoi, u, q, ctx->scratch, ctx->st);
+  if (e != hipSuccess) FAIL(MLMC_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return MLMC_OK;
+}
 
 int mlmc_sample_level(mlmc_ctx* ctx, int32_t level, uint64_t first, uint64_t count, double* y, double* q_fine,
                       double* q_coarse, int32_t* iters) {

@@ -312,6 +312,8 @@ struct mlmc_ctx {
   int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
              MLMC_FUSE_DIRECTION | MLMC_FUSE_SOLVE;
   mlmc_server* server = nullptr;  // serving pools and threads while serving
+  int device = 0;                 // the GPU current at creation
+  void* scratch = nullptr;        // device address of that GPU's static scratch (mlmc_qoi_noalloc)
 };
 
 // A lane of the sampling rounds: its engine view (null for lane 0, which runs

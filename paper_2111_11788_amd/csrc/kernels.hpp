@@ -283,4 +283,13 @@ hipError_t launch_phase_masks(int S, const int* phase, int* inner, int* trans, i
 hipError_t launch_set_phase_list(int count, const int* slots, int* phase, int value, hipStream_t st);
 hipError_t launch_set_phase_mask(int S, const int* mask, int* phase, int value, int* zero, hipStream_t st);
 
+// scratch.hip -- the static device scratch of the allocation-free entry point:
+// its size, the lookup of the current device's copy (once per device, kept),
+// and the QoI of B samples on mesh n with its partial sums there (rejects a
+// batch whose partial sums exceed the scratch)
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch_init(int* device, void** out);
+size_t qoi_scratch_bytes(int n, int B);
+hipError_t launch_qoi_scratch(int n, int B, int qoi, const double* u, double* q, void* scratch_dev, hipStream_t st);
+
 }  // namespace mlmc
