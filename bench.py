@@ -110,6 +110,7 @@ def cpu_baseline(wl, samples: int):
     wall = time.perf_counter() - t0
     dofs = (wl.n0 - 1) ** 3
     return {"value": samples * dofs / wall, "unit": "sample-DOFs/s", "cores": cores, "kind": "oracle",
+            "qoi": [r[1] for r in res],
             "sample": f"{samples} samples of the 64^3 workload (level 0, indices 0..{samples - 1}), "
                       f"assembled CSR + Jacobi-PCG to rel.res 1e-8, {cores} processes x 1 thread",
             "wall_s": round(wall, 3), "mean_sample_s": round(sum(r[0] for r in res) / samples, 3),
@@ -128,7 +129,7 @@ def copy_probe(mib: int):
 
 
 def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bool, autotune: bool = False,
-            tuning: dict | None = None, probe_mib: int = 0):
+            tuning: dict | None = None, probe_mib: int = 0, validate: bool = False):
     import numpy as np
     import torch
     import paper_2111_11788_amd as mm
@@ -142,7 +143,14 @@ def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bo
         tuning = ctx.autotune(0, batch) if autotune else ctx.tuning()
     if probe_mib:
         copy_probe(probe_mib)
-    first = 0
+    check = None
+    if validate:
+        # untimed pass over sample indices 0 .. batch-1 with the same tuning:
+        # the QoIs the oracle values (stored goldens, the CPU baseline's) are
+        # compared with
+        _, qf0, _, it0 = ctx.sample_level(0, 0, batch)
+        check = {"qf": [float(x) for x in qf0], "iters_max": int(it0.max())}
+    first = batch if validate else 0
     for _ in range(warmup):
         ctx.sample_level(0, first, batch)
         first += batch
@@ -156,7 +164,7 @@ def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bo
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     out = {"value": steps * batch * dofs / wall, "ms_per_step": 1e3 * wall / steps,
-           "iters_mean": float(np.mean(its)), "iters_max": int(np.max(its)), "tuning": tuning}
+           "iters_mean": float(np.mean(its)), "iters_max": int(np.max(its)), "tuning": tuning, "check": check}
     if profile:
         ctx.set_profiling(True)
         ctx.sample_level(0, first, batch)
@@ -185,6 +193,79 @@ def run_gpu(wl, precision: int, steps: int, warmup: int, batch: int, profile: bo
     return out
 
 
+def qoi_vs_oracle(check, golden: str, cpu=None):
+    """Relative QoI error of the GPU's samples 0 .. batch-1 against the stored
+    oracle values (Jacobi-PCG to 1e-12) and the CPU baseline's own solves (to
+    the bench tolerance 1e-8)."""
+    if not check:
+        return None
+    out = {}
+    gp = os.path.join(ROOT, "tests", "golden", golden)
+    if os.path.exists(gp):
+        gold = json.load(open(gp))
+        rel = [abs(check["qf"][g["index"]] - g["q"]) / abs(g["q"]) for g in gold["samples"]
+               if g["index"] < len(check["qf"])]
+        out["stored_oracle"] = {"samples": [g["index"] for g in gold["samples"]], "oracle_rtol": gold["rtol"],
+                                "max_rel": max(rel) if rel else None, "source": f"tests/golden/{golden}"}
+    if cpu and cpu.get("qoi"):
+        rel = [abs(check["qf"][i] - q) / abs(q) for i, q in enumerate(cpu["qoi"])]
+        out["cpu_baseline_oracle"] = {"samples": f"0..{len(rel) - 1}", "oracle_rtol": 1e-8, "max_rel": max(rel)}
+    return out
+
+
+def run_c5_leg(steps: int = 3, B: int = 16):
+    """The largest single-GPU workload (256^3, sigma^2 = 2, correlation length
+    0.1, M = 512) at batch B with the library's default tuning: sample-DOFs/s,
+    ms per batch, iterations, the dominant kernel's HBM roofline and the QoI
+    error against the stored oracle values of samples 0 and 1."""
+    import numpy as np
+    import torch
+    import paper_2111_11788_amd as mm
+    import workloads
+    wl = workloads.C5
+    ctx = mm.Context(wl, max_batch=B)
+    _, qf0, _, it0 = ctx.sample_level(0, 0, B)      # untimed: carving, graphs, the QoI check
+    torch.cuda.synchronize()
+    its = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        _, _, _, it = ctx.sample_level(0, B * (k + 1), B)
+        its.append(it)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ctx.set_profiling(True)
+    ctx.sample_level(0, B * (steps + 1), B)
+    rows = []
+    for name in mm.KERNELS:
+        for p in (0, 1):
+            n, ms, by = ctx.kernel_time(name, p)
+            if n:
+                rows.append((ms, name, "f64" if p == 0 else "f32", n, by))
+    ctx.set_profiling(False)
+    tuning = ctx.tuning()
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    rows.sort(reverse=True)
+    ms, name, dt, n, by = rows[0]
+    achieved = by / n / (ms / n * 1e-3) / 1e9
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "c5_stress_qoi.json")))
+    err = [{"sample": g["index"], "rel_err": abs(float(qf0[g["index"]]) - g["q"]) / abs(g["q"])}
+           for g in gold["samples"]]
+    dofs = (wl.n0 - 1) ** 3
+    return {"workload": wl.name, "mesh": "256^3", "samples_per_batch": B, "dofs_per_sample": dofs,
+            "value": B * dofs / wall, "unit": "sample-DOFs/s", "ms_per_batch": 1e3 * wall,
+            "iterations": {"mean": float(np.mean(its)), "max": int(np.max(its))},
+            "roofline": {"bound": "hbm", "kernel": f"{name} ({dt})", "achieved": round(achieved, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "launches": n, "avg_launch_us": round(1e3 * ms / n, 2), "bytes_per_launch": by / n},
+            "kernels": [{"kernel": f"{r[1]} ({r[2]})", "ms": round(r[0], 3), "launches": r[3],
+                         "GBps": round(r[4] / (r[0] * 1e-3) / 1e9, 1) if r[0] > 0 else None} for r in rows[:8]],
+            "qoi_vs_oracle": {"samples": err, "oracle_rtol": gold["rtol"], "max_rel": max(e["rel_err"] for e in err),
+                              "source": "tests/golden/c5_stress_qoi.json"},
+            "tuning": tuning, "steps": steps}
+
+
 def run_c3(args):
     """Time-to-eps of the 5-level MLMC workload (pilot + optimal allocation)."""
     import numpy as np
@@ -195,6 +276,8 @@ def run_c3(args):
 
     def one(eps):
         ctx = mm.Context(wl, max_batch=1024, arena_bytes=40 << 30, cheb_degree=args.cheb_degree)
+        if args.lanes:
+            ctx.set_tuning(lanes=args.lanes)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nl, est = ctx.estimate(eps, n_pilot=32, cost_model=0, max_rounds=3)
@@ -207,7 +290,7 @@ def run_c3(args):
                 "var_qtilde": est["var_qtilde"], "eps2_over_2": eps ** 2 / 2,
                 "var_per_level": [l["var"] for l in est["levels"]],
                 "cost_per_sample_s": [l["cost"] for l in est["levels"]], "sample_dofs": dofs,
-                "sample_dofs_per_s": dofs / wall}
+                "sample_dofs_per_s": dofs / wall, "lanes": est["lanes"], "active_ratio": est["active_ratio"]}
 
     absolute = one(wl.eps)
     # the relative reading of the same target: eps = 1e-3 |Qtilde|, Qtilde from the absolute run
@@ -217,6 +300,8 @@ def run_c3(args):
         """Adaptive MLMC from levels 0..l0: L grows by eq. mlmc_num_levels (the
         configured meshes cap it), N_l by eq. mlmc_num_samples."""
         ctx = mm.Context(wl, max_batch=1024, arena_bytes=40 << 30, cheb_degree=args.cheb_degree)
+        if args.lanes:
+            ctx.set_tuning(lanes=args.lanes)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nl, info, est = ctx.estimate_adaptive(eps, l0=l0, n_pilot=32, cost_model=0, max_rounds=10)
@@ -228,7 +313,8 @@ def run_c3(args):
         return {"eps": eps, "l0": l0, "seconds": wall, "L": L, "meshes_used": [wl.n(l) for l in range(L + 1)],
                 "n_per_level": [int(nl[l]) for l in range(L + 1)], "qtilde": est["qtilde"],
                 "var_qtilde": est["var_qtilde"], "bias": info["bias"], "err": info["err"], "alpha": info["alpha"],
-                "beta": info["beta"], "rounds": info["rounds"], "sample_dofs_per_s": dofs / wall}
+                "beta": info["beta"], "rounds": info["rounds"], "sample_dofs_per_s": dofs / wall,
+                "lanes": est["lanes"], "active_ratio": est["active_ratio"]}
 
     adapt = adaptive(wl.eps * abs(absolute["qtilde"]), 1)
     return {"metric": "time-to-eps", "value": absolute["seconds"], "unit": "s", "higher_is_better": False,
@@ -289,6 +375,14 @@ def run_c4(args):
             next_id[l] += np.uint64(c)
         return lv, ids
 
+    def active_ratio(a, b):
+        """A = a / (p t_w) of eq. active_ratio between two serve_stats
+        snapshots: slot-seconds in use weighted by each slot's share of the HBM
+        budget, over the budget held by all slots times the wall time."""
+        num = sum((b["slot_busy_s"][m] - a["slot_busy_s"][m]) * b["slot_bytes"][m] for m in range(16))
+        den = sum(b["slots"][m] * b["slot_bytes"][m] for m in range(16)) * (b["uptime_s"] - a["uptime_s"])
+        return num / den if den > 0 else None
+
     def pct(x, q):
         """nearest-rank percentile"""
         xs = np.sort(x)
@@ -305,12 +399,15 @@ def run_c4(args):
     outstanding = clients
     t0 = time.perf_counter()
     warm_end, end = t0 + 1.0, t0 + 1.0 + args.sat_seconds
+    snap0 = None
     n_done = 0
     dofs_done = 0.0
     while True:
         r = ctx.drain_array(timeout=0.005)
         now = time.perf_counter()
         outstanding -= len(r)
+        if now >= warm_end and snap0 is None:
+            snap0 = ctx.serve_stats()
         if now >= warm_end and now < end:
             n_done += len(r)
             dofs_done += float(dofs[r["level"]].sum())
@@ -320,6 +417,7 @@ def run_c4(args):
             lv, ids = draw(len(r))
             ctx.submit_batch(lv, ids)
             outstanding += len(r)
+    snap1 = ctx.serve_stats()
     while outstanding > 0:
         outstanding -= len(ctx.drain_array(timeout=0.05))
     sat_rate = n_done / args.sat_seconds
@@ -331,7 +429,8 @@ def run_c4(args):
                       "precision": "mixed"},
            "kle_bf16_vs_fp64": kle_check,
            "saturation": {"requests_per_s": sat_rate, "sample_dofs_per_s": sat_dofs, "clients": clients,
-                          "seconds": args.sat_seconds, "kind": "closed loop"},
+                          "seconds": args.sat_seconds, "kind": "closed loop",
+                          "active_ratio": active_ratio(snap0, snap1) if snap0 else None},
            "rates": []}
     for frac in (0.5, 0.8, 0.95):
         rate = frac * sat_rate
@@ -341,6 +440,7 @@ def run_c4(args):
         tickets = np.zeros(n, dtype=np.uint64)
         lag = np.zeros(n)
         got = []
+        s0 = ctx.serve_stats()
         t0 = time.perf_counter()
         i = 0
         while i < n:
@@ -363,6 +463,7 @@ def run_c4(args):
             if time.perf_counter() - t0 > args.serve_seconds + 600:
                 raise TimeoutError("serving run did not finish")
         wall = time.perf_counter() - t0
+        a_ratio = active_ratio(s0, ctx.serve_stats())
         res = np.concatenate(got)
         order = np.argsort(tickets)
         pos = order[np.searchsorted(tickets[order], res["ticket"])]
@@ -377,6 +478,7 @@ def run_c4(args):
                              "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99),
                              "max_submit_lag_ms": 1e3 * float(lag.max()),
                              "sample_dofs_per_s": float(dofs[lv].sum()) / wall, "per_level": per,
+                             "active_ratio": a_ratio,
                              "all_ok": bool((res["status"] == 0).all())})
     ctx.serve_stop()
     return out
@@ -480,6 +582,7 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the fp64 comparison run")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 256^3 leg of the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--slots", default="", help="c4: slots per mesh, comma separated")
@@ -488,6 +591,8 @@ def main():
                     "(0: twice the slots)")
     ap.add_argument("--sat-seconds", type=float, default=3.0, help="c4: measured closed-loop seconds")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="c3: concurrent lanes of the sampling rounds (0: the library default)")
     ap.add_argument("--cheb-degree", type=int, default=0,
                     help="c3/c4/c5: Chebyshev smoothing degree (0: the library default)")
     args = ap.parse_args()
@@ -506,11 +611,13 @@ def main():
     tuning = json.loads(args.tuning) if args.tuning else (None if args.autotune else dict(TRAFFIC["tuning"]))
     main_run = run_gpu(wl, prec, args.steps, args.warmup, args.batch, profile=True,
                        autotune=args.autotune and tuning is None, tuning=tuning,
-                       probe_mib=args.copy_probe_mib)
+                       probe_mib=args.copy_probe_mib, validate=True)
     fp64 = None
     if prec == 1 and not args.no_fp64:
         fp64 = run_gpu(wl, 0, max(1, args.steps // 2), 1, args.batch, profile=False)
+    c5 = None if args.no_c5 else run_c5_leg()
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_samples)
+    check = qoi_vs_oracle(main_run.get("check"), "c2_batched_qoi.json", cpu)
 
     line = {
         "metric": METRIC, "value": main_run["value"], "unit": "sample-DOFs/s", "n_gpus": 1,
@@ -526,9 +633,11 @@ def main():
         "tuning": main_run["tuning"],
         "roofline": main_run.get("roofline"),
         "kernels": main_run.get("kernels"),
+        "qoi_vs_oracle": check,
         "fp64_path": None if fp64 is None else {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
                                                 "iters_mean": fp64["iters_mean"]},
-        "cpu_baseline": cpu,
+        "largest_single_gpu_config": c5,
+        "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items() if k != "qoi"},
     }
     print(json.dumps(line))
 

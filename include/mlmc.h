@@ -496,6 +496,11 @@ typedef struct mlmc_serve_stats_out {
   int32_t running;      /* solves in slots */
   int32_t slots[16];    /* pool capacity per mesh n0 << m */
   int32_t occupied[16];
+  double slot_busy_s[16]; /* per mesh: sum over solver steps of occupied slots x step seconds */
+  double slot_bytes[16];  /* per mesh: arena bytes of one slot (its share of the HBM budget) */
+  double uptime_s;        /* seconds since serving started; with the two above, the active ratio
+                             A = a / (p t_w) of eq. active_ratio over a window is
+                             sum_m d(slot_busy_s[m]) slot_bytes[m] / (sum_m slots[m] slot_bytes[m] d(uptime_s)) */
 } mlmc_serve_stats_out;
 
 /* Start serving: the arena after the KL tables is split into one resident

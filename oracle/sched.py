@@ -14,9 +14,10 @@ always 1) are
   * b = ceil((N - n) / K), kept between ceil(0.01 ceil(N / K)) and
     ceil(phi^-1 ceil(N / K)) (phi the golden ratio), the defaults the paper
     states, where N is the number of samples the round assigns to the level
-    and n those already assigned; the minimum is raised to ceil(cap / 8) (at
-    most cap), cap being the lane capacity of the level; every batch is
-    capped by cap and by what is left;
+    and n those already assigned; the minimum is raised to min(cap, fill),
+    cap being the lane capacity of the level and fill the samples that fill
+    the device (a property of the GPU's kernels, given as an input here);
+    every batch is capped by cap and by what is left;
   * with one lane there is no other partition to leave work for: batches are
     the capacity;
   * a batch of a level l > 0 is two tasks, the solve on the level's mesh and
@@ -38,7 +39,7 @@ def dofs(n: int) -> int:
     return (n - 1) ** 3
 
 
-def batch_sizes(count: int, lanes: int, cap: int) -> List[int]:
+def batch_sizes(count: int, lanes: int, cap: int, fill: int) -> List[int]:
     """Batch sizes of one level's share of a round (eq. batch as read above)."""
     if lanes <= 1:
         out, left = [], count
@@ -48,7 +49,7 @@ def batch_sizes(count: int, lanes: int, cap: int) -> List[int]:
         return out
     per = -(-count // lanes)
     most = math.ceil(per * PHI_INV)
-    least = max(-(-per // 100), min(cap, -(-cap // 8)))
+    least = max(-(-per // 100), min(cap, max(1, fill)))
     out, left = [], count
     while left > 0:
         b = -(-left // lanes)
@@ -70,16 +71,17 @@ def level_cap(n0: int, levels: int, level: int, max_batch: int, limit: int = 655
     return max(max_batch, int(cap))
 
 
-def plan(n0: int, requests: Sequence[Tuple[int, int, int]], lanes: int, caps: Sequence[int]):
-    """Tasks of a round: requests are (level, first, count), caps the lane
-    capacity of each request.  Returns dicts (level, n, first, count, lane) in
-    assignment order."""
+def plan(n0: int, requests: Sequence[Tuple[int, int, int]], lanes: int, caps: Sequence[int],
+         fills: Sequence[int]):
+    """Tasks of a round: requests are (level, first, count), caps and fills the
+    lane capacity and the device-filling batch of each request.  Returns dicts
+    (level, n, first, count, lane) in assignment order."""
     order = sorted(range(len(requests)), key=lambda r: -requests[r][0])
     tasks = []
     for r in order:
         level, first, count = requests[r]
         off = 0
-        for b in batch_sizes(count, lanes, caps[r]):
+        for b in batch_sizes(count, lanes, caps[r], fills[r]):
             n = n0 << level
             tasks.append(dict(level=level, n=n, first=first + off, count=b))
             if level > 0:

@@ -672,14 +672,22 @@ int level_cap(const mlmc_ctx* ctx, int level) {
   return std::max(ctx->cfg.max_batch, (int)cap);
 }
 
+int fill_batch(int n) {
+  const ZGeom g = zgeom<float>(n, 1);
+  if (g.G < 1) return kFillWaves;
+  const int waves = g.row_blocks * (g.threads / 64);
+  return (kFillWaves + waves - 1) / waves;
+}
+
 // eq. batch with p|q_l read as the K lanes a level's batches can run on: the
 // next batch takes ceil((N - n) / K) of the N - n samples still unassigned,
 // between ceil(0.01 ceil(N / K)) and ceil(phi^-1 ceil(N / K)) (phi the golden
-// ratio), as the defaults the paper states; the minimum is raised to an eighth
-// of the lane capacity (a batched solve costs about the same launches whatever
-// its size) and every batch is capped by the lane capacity.  One lane has no
-// other partition to leave work for: its batches are the capacity.
-std::vector<int> batch_plan(uint64_t count, int K, int cap) {
+// ratio), as the defaults the paper states; the minimum is raised to the
+// samples that fill the device (`fill`, at most the capacity: smaller batches
+// split their planes over more workgroups and re-read more halos) and every
+// batch is capped by the lane capacity.  One lane has no other partition to
+// leave work for: its batches are the capacity.
+std::vector<int> batch_plan(uint64_t count, int K, int cap, int fill) {
   std::vector<int> out;
   const uint64_t C = (uint64_t)std::max(1, cap);
   if (K <= 1) {
@@ -694,7 +702,7 @@ std::vector<int> batch_plan(uint64_t count, int K, int cap) {
   const uint64_t per = (count + k - 1) / k;
   const double phi_inv = (std::sqrt(5.0) - 1.0) / 2.0;
   const uint64_t hi = (uint64_t)std::ceil((double)per * phi_inv);
-  const uint64_t lo = std::max<uint64_t>((per + 99) / 100, std::min<uint64_t>(C, (C + 7) / 8));
+  const uint64_t lo = std::max<uint64_t>((per + 99) / 100, std::min<uint64_t>(C, (uint64_t)std::max(1, fill)));
   for (uint64_t n = 0; n < count;) {
     uint64_t b = (count - n + k - 1) / k;
     b = std::max(lo, std::min(hi, b));
@@ -720,7 +728,7 @@ std::vector<Task> plan_round(const mlmc_ctx* ctx, const std::vector<LevelReq>& r
   for (int r : order) {
     const LevelReq& q = reqs[r];
     uint64_t off = 0;
-    for (int b : batch_plan(q.count, K, caps[r])) {
+    for (int b : batch_plan(q.count, K, caps[r], fill_batch(ctx->cfg.n0 << q.level))) {
       Task t;
       t.level = q.level;
       t.req = r;

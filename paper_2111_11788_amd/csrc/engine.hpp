@@ -506,7 +506,11 @@ int level_cap(const mlmc_ctx* ctx, int level);
 // Batch sizes of one level's request (eq. batch read for K lanes; see the
 // definition) and the tasks of a round assigned to K lanes finest mesh first
 // to the least-loaded lane (Alg. incremental_greedy).
-std::vector<int> batch_plan(uint64_t count, int K, int cap);
+std::vector<int> batch_plan(uint64_t count, int K, int cap, int fill);
+// Samples of an n^3 mesh whose fp32 stencil launches reach kFillWaves waves
+// (the occupancy from which the engine stops splitting a sample's planes over
+// several workgroups)
+int fill_batch(int n);
 std::vector<Task> plan_round(const mlmc_ctx* ctx, const std::vector<LevelReq>& reqs, int K, const std::vector<int>& caps);
 // One sampling round: every request's samples drawn, solved on both meshes of
 // the pair and reduced to QoIs, the tasks spread over the lanes; with

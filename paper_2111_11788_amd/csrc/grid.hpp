@@ -27,6 +27,9 @@ struct ZGeom {
   __host__ __device__ uint32_t parts() const { return (uint32_t)row_blocks * zc; }
 };
 
+// waves of a launch from which the samples' planes are no longer split
+constexpr long kFillWaves = 8192;
+
 template <class T>
 inline ZGeom zgeom(int n, int B) {
   ZGeom g;
@@ -47,7 +50,7 @@ inline ZGeom zgeom(int n, int B) {
   // split the planes when there are few samples, so the chip has >= ~8 waves per SIMD
   const long waves = (long)B * g.row_blocks * (g.threads / 64);
   int zc = 1;
-  while (waves * zc < 8192 && (n - 1) / (zc * 2) >= 8) zc *= 2;
+  while (waves * zc < kFillWaves && (n - 1) / (zc * 2) >= 8) zc *= 2;
   g.zc = zc;
   g.zlen = (n - 1 + zc - 1) / zc;
   return g;

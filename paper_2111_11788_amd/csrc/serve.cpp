@@ -49,6 +49,8 @@ struct Request {
 
 struct Pool {
   int m = 0, n = 0, S = 0;
+  double busy_slot_s = 0.0;     // sum over steps of occupied slots x step seconds (server mutex)
+  size_t slot_bytes = 0;        // arena bytes of one slot
   mlmc_ctx sub;                 // engine view: shared tables, own stream and pinned counter
   SolveWork w;
   double *kap64 = nullptr, *u = nullptr, *xi = nullptr, *q = nullptr;
@@ -265,9 +267,11 @@ void pool_loop(mlmc_server* srv, Pool* p) {
         if (it != srv->reqs.end() && it->second.t_admit < 0) it->second.t_admit = srv->now();
       }
     }
+    const double t_step = srv->now();
     int rc = c ? setup_slots(*p, c) : MLMC_OK;
     if (!rc) rc = step(*p);
     std::lock_guard<std::mutex> lk(srv->mu);
+    p->busy_slot_s += (double)p->occupied * (srv->now() - t_step);
     if (rc) {
       srv->error = rc;
       srv->error_msg = p->sub.err;
@@ -375,6 +379,7 @@ int mlmc_serve_start(mlmc_ctx* ctx, const int32_t* slots_per_mesh) {
     Pool& p = *srv->pools.back();
     if (S[m] == 0) continue;
     p.carve(cv, ctx->cfg, m, S[m]);
+    p.slot_bytes = pool_bytes(ctx->cfg, m, 1);
     p.sub.cfg = ctx->cfg;
     p.sub.modes = ctx->modes;
     p.sub.K1 = ctx->K1;
@@ -529,11 +534,14 @@ int mlmc_serve_stats(mlmc_ctx* ctx, mlmc_serve_stats_out* out) {
     const Pool& p = *srv->pools[m];
     out->slots[m] = p.S;
     out->occupied[m] = p.occupied;
+    out->slot_busy_s[m] = p.busy_slot_s;
+    out->slot_bytes[m] = (double)p.slot_bytes;
     q += (int)p.queue.size();
     occ += p.occupied;
   }
   out->queued = q;
   out->running = occ;
+  out->uptime_s = srv->now();
   return srv->error;
 }
 

@@ -68,13 +68,32 @@ def test_fold_counts_nonfinite_apart(dev):
     assert abs(lv["mean"] - ref.mean) <= 1e-13 * abs(ref.mean) + 1e-16
 
 
+def _fill(n):
+    """Samples of an n^3 mesh that fill the device: 8192 waves of the fp32
+    stencil launch geometry (a thread per 4 nodes of a row, workgroups of up to
+    256 threads holding whole rows)."""
+    g = n // 4
+    if g < 1:
+        return 8192
+    rowthreads = (n - 1) * g
+    threads = 256 if rowthreads >= 256 else -(-rowthreads // 64) * 64
+    rows = max(1, threads // g)
+    waves = -(-(n - 1) // rows) * (threads // 64)
+    return -(-8192 // waves)
+
+
+def test_fill_geometry_examples():
+    # 64^3: 4 workgroups of 16 rows, 4 waves each -> 512 samples; 256^3: 64 x 4 -> 32
+    assert _fill(64) == 512 and _fill(256) == 32 and _fill(8) == 8192
+
+
 @pytest.mark.parametrize("lanes", [2, 4])
 def test_lanes_give_the_same_bits_and_the_oracle_plan(dev, lanes):
     # a round over three levels (plain MLMC with fixed N_l) on several lanes:
     # every sample's QoIs are the bits of the one-lane run, the estimator too,
     # and the tasks are the scheduling oracle's, lane for lane
     wl = _wl(levels=3, n0=8, n_modes=16, corr_len=0.3, batch=16)
-    nfix = [600, 70, 9]
+    nfix = [5000, 70, 9]
     res = {}
     for k in (1, lanes):
         ctx = mm.Context(wl, arena_bytes=2 << 30)
@@ -83,7 +102,10 @@ def test_lanes_give_the_same_bits_and_the_oracle_plan(dev, lanes):
         assert [int(x) for x in nl] == nfix
         plan = ctx.last_plan()
         caps = [sched.level_cap(wl.n0, wl.levels, l, 16) for l in range(3)]
-        want = sched.plan(wl.n0, [(l, 0, nfix[l]) for l in range(3)], k, caps)
+        fills = [_fill(wl.n(l)) for l in range(3)]
+        want = sched.plan(wl.n0, [(l, 0, nfix[l]) for l in range(3)], k, caps, fills)
+        if k > 1:
+            assert len(set(t["lane"] for t in plan)) > 1
         assert [(t["level"], t["n"], t["first"], t["count"], t["lane"]) for t in plan] == \
                [(t["level"], t["n"], t["first"], t["count"], t["lane"]) for t in want]
         assert est["lanes"] == k and 0.0 < est["active_ratio"] <= 1.0 + 1e-9

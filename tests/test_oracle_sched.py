@@ -6,28 +6,31 @@ from oracle import sched
 
 
 def test_batch_sizes_fall_with_the_unassigned_samples():
-    # 100 samples on 4 lanes, capacity 40: per = 25, maximum ceil(25 * 0.618) = 16,
-    # minimum max(ceil(0.25), ceil(40 / 8)) = 5; each batch ceil(left / 4) clamped:
+    # 100 samples on 4 lanes, capacity 40, device fill 5: per = 25, maximum
+    # ceil(25 * 0.618) = 16, minimum max(ceil(0.25), min(40, 5)) = 5; each batch
+    # ceil(left / 4) clamped:
     #   left 100 -> 25 -> 16;  84 -> 21 -> 16;  68 -> 17 -> 16;  52 -> 13;  39 -> 10;
     #   29 -> 8;  21 -> 6;  15 -> 4 -> 5;  10 -> 3 -> 5;  5 -> 2 -> 5
-    assert sched.batch_sizes(100, 4, 40) == [16, 16, 16, 13, 10, 8, 6, 5, 5, 5]
+    assert sched.batch_sizes(100, 4, 40, 5) == [16, 16, 16, 13, 10, 8, 6, 5, 5, 5]
 
 
 def test_batch_sizes_floor_and_one_lane():
-    # the floor of an eighth of the capacity keeps a small level in one batch
-    assert sched.batch_sizes(100, 4, 1000) == [100]
+    # the device-filling floor keeps a small level in one batch
+    assert sched.batch_sizes(100, 4, 1000, 125) == [100]
+    # ... and never exceeds the capacity: a 256^3 batch of 16 (fill 32) stays whole
+    assert sched.batch_sizes(16, 4, 16, 32) == [16]
     # one lane: capacity-sized batches
-    assert sched.batch_sizes(2500, 1, 1024) == [1024, 1024, 452]
-    assert sched.batch_sizes(0, 4, 10) == []
+    assert sched.batch_sizes(2500, 1, 1024, 512) == [1024, 1024, 452]
+    assert sched.batch_sizes(0, 4, 10, 1) == []
 
 
 def test_maximum_is_the_golden_fraction():
     # the first batch of a level is phi^-1 of its per-lane share
     per = 1000
-    assert sched.batch_sizes(4 * per, 4, 10 ** 6) == [4000]   # the floor ceil(10^6 / 8) takes all that is left
-    b = sched.batch_sizes(4 * per, 4, 8000)[0]                  # floor 1000, maximum 618
+    assert sched.batch_sizes(4 * per, 4, 10 ** 6, 125000) == [4000]   # the floor takes all that is left
+    b = sched.batch_sizes(4 * per, 4, 8000, 1000)[0]                  # floor 1000, maximum 619
     assert b == 1000
-    b = sched.batch_sizes(4 * per, 4, 800)[0]                   # floor 100, maximum ceil(618.03) = 619
+    b = sched.batch_sizes(4 * per, 4, 800, 100)[0]                    # floor 100, maximum ceil(618.03) = 619
     assert b == 619 and abs(b / per - 0.618) < 2e-3
 
 
@@ -41,7 +44,7 @@ def test_level_cap_follows_the_dof_budget():
 
 
 def test_greedy_assignment_by_hand():
-    # meshes 4, 8, 16 (levels 0..2), requests 5, 3, 2 samples, 2 lanes, capacity 2
+    # meshes 4, 8, 16 (levels 0..2), requests 5, 3, 2 samples, 2 lanes, capacity 2, fill 1
     # batches: level 2 [1, 1]; level 1 [2, 1]; level 0 [2, 2, 1]
     # tasks by decreasing mesh with their work (samples x interior unknowns):
     #   16^3: L2 fine 3375, L2 fine 3375
@@ -50,7 +53,7 @@ def test_greedy_assignment_by_hand():
     # least-loaded lane each time (loads after each step):
     #   (3375,0) (3375,3375) (3718,3375) (3718,3718) (4404,3718) (4404,4061)
     #   (4404,4115) (4404,4142) (4404,4196) (4404,4250) (4404,4277)
-    t = sched.plan(4, [(0, 0, 5), (1, 0, 3), (2, 0, 2)], 2, [2, 2, 2])
+    t = sched.plan(4, [(0, 0, 5), (1, 0, 3), (2, 0, 2)], 2, [2, 2, 2], [1, 1, 1])
     assert [x["lane"] for x in t] == [0, 1, 0, 1, 0, 1, 1, 1, 1, 1, 1]
     assert [(x["level"], x["n"], x["first"], x["count"]) for x in t] == [
         (2, 16, 0, 1), (2, 16, 1, 1),
@@ -59,5 +62,5 @@ def test_greedy_assignment_by_hand():
 
 
 def test_one_lane_keeps_request_order_by_mesh():
-    t = sched.plan(8, [(1, 32, 4), (0, 32, 4)], 1, [64, 64])
+    t = sched.plan(8, [(1, 32, 4), (0, 32, 4)], 1, [64, 64], [8, 8])
     assert [(x["level"], x["n"], x["lane"]) for x in t] == [(1, 16, 0), (1, 8, 0), (0, 8, 0)]
