@@ -273,21 +273,131 @@ __device__ __forceinline__ double from_next(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <class T, int V>
+// Halo modes of the row exchange.  HALO_SELECT: a wave holds several rows;
+// whole-wave shifts and a select of 0 at the row ends.  HALO_DPPROW: a row is
+// exactly one 16-lane DPP row (G = 16): shifts within the DPP rows, whose ends
+// receive 0 with no select.  HALO_WAVE: a row is exactly one wave (G = 64):
+// whole-wave shifts, 0 at the wave ends with no select.
+enum : int { HALO_SELECT = 0, HALO_DPPROW = 1, HALO_WAVE = 2 };
+inline int halo_mode(int G) { return G == 16 ? HALO_DPPROW : (G == 64 ? HALO_WAVE : HALO_SELECT); }
+
+template <int HALO>
+__device__ __forceinline__ int halo_prev_i(int x) {
+  if constexpr (HALO == HALO_DPPROW) return __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);   // row_shr:1
+  else return dpp_prev_i(x);
+}
+template <int HALO>
+__device__ __forceinline__ int halo_next_i(int x) {
+  if constexpr (HALO == HALO_DPPROW) return __builtin_amdgcn_update_dpp(0, x, 0x101, 0xF, 0xF, true);   // row_shl:1
+  else return dpp_next_i(x);
+}
+template <int HALO, class T>
+__device__ __forceinline__ T halo_prev(T x, int gx) {
+  T v;
+  if constexpr (sizeof(T) == 4) {
+    v = __int_as_float(halo_prev_i<HALO>(__float_as_int(x)));
+  } else {
+    const long long w = __double_as_longlong(x);
+    const int lo = halo_prev_i<HALO>((int)(w & 0xffffffffll)), hi = halo_prev_i<HALO>((int)(w >> 32));
+    v = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+  if constexpr (HALO == HALO_SELECT) return gx == 0 ? T(0) : v;
+  else return v;
+}
+template <int HALO, class T>
+__device__ __forceinline__ T halo_next(T x, int gx, int G) {
+  T v;
+  if constexpr (sizeof(T) == 4) {
+    v = __int_as_float(halo_next_i<HALO>(__float_as_int(x)));
+  } else {
+    const long long w = __double_as_longlong(x);
+    const int lo = halo_next_i<HALO>((int)(w & 0xffffffffll)), hi = halo_next_i<HALO>((int)(w >> 32));
+    v = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+  if constexpr (HALO == HALO_SELECT) return gx == G - 1 ? T(0) : v;
+  else return v;
+}
+
+template <class T, int V, int HALO = HALO_SELECT>
 __device__ __forceinline__ void lds_urow(const T* row, T* dst, int gx, int G) {
   vload<T, V>(row, dst + 1);
-  const T l = from_prev(dst[V]);
-  const T r = from_next(dst[1]);
-  dst[0] = gx == 0 ? T(0) : l;
-  dst[V + 1] = gx == G - 1 ? T(0) : r;
+  dst[0] = halo_prev<HALO>(dst[V], gx);
+  dst[V + 1] = halo_next<HALO>(dst[1], gx, G);
 }
 
 // kappa row segment: element i0-1 (zero for i0 = 0) and i0 .. i0+V-1
-template <class T, int V>
+template <class T, int V, int HALO = HALO_SELECT>
 __device__ __forceinline__ void lds_krow(const T* row, T* dst, int gx) {
   vload<T, V>(row, dst + 1);
-  const T l = from_prev(dst[V]);
-  dst[0] = gx == 0 ? T(0) : l;
+  dst[0] = halo_prev<HALO>(dst[V], gx);
+}
+
+// The 8-element sum of kappa at each of the V nodes from the four kappa row
+// segments around them (element layers dz = node plane -1 / +0, element rows
+// dy likewise; column c = v holds the element left of node v, c = v + 1 the
+// one right of it): pair sums over the two layers, then over the two rows,
+// then over the two columns.  The stencil kernels and the on-the-fly
+// smoothing operand take the diagonal from this same sequence, so they agree
+// to the bit.
+template <class T, int V>
+__device__ __forceinline__ void ksum_from_rows(const T (&K)[2][2][V + 1], T (&Z)[2][V + 1], T* ks) {
+  T C[V + 1];
+#pragma unroll
+  for (int c = 0; c <= V; ++c) {
+    Z[0][c] = K[0][0][c] + K[1][0][c];
+    Z[1][c] = K[0][1][c] + K[1][1][c];
+    C[c] = Z[0][c] + Z[1][c];
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) ks[v] = C[v] + C[v + 1];
+}
+
+// Q1 row pieces of the V nodes i0 .. i0+V-1 of row j, plane k, from the LDS
+// tile: Kd (d = 0, 1) point at element row j-1 of element layers k-1 and k at
+// column i0 (element row j one row further); Um, U0, Up at node row j-1 of
+// planes k-1, k, k+1 (rows j, j+1 further).  ks: the 8-element sum; fr: the
+// 20 neighbours (12 edge diagonals and 8 corners) each times the sum of kappa
+// over the elements it shares with the node (two elements for an edge
+// diagonal, one for a corner); uc: the centre values.  A u = h (ks uc / 3 -
+// fr / 12).  The kappa pair sums are shared by the V nodes of the segment.
+template <class T, int V, int HALO>
+__device__ __forceinline__ void q1_gather(const T* K0, const T* K1, const T* Um, const T* U0, const T* Up, int rsh,
+                                          int gx, int G, T* ks, T* fr, T* uc) {
+  T K[2][2][V + 1];
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy) {
+    lds_krow<T, V, HALO>(K0 + (dy << rsh), K[0][dy], gx);
+    lds_krow<T, V, HALO>(K1 + (dy << rsh), K[1][dy], gx);
+  }
+  T Z[2][V + 1];
+  ksum_from_rows<T, V>(K, Z, ks);
+  {
+    // plane k: the edge diagonals (i +- 1, j +- 1), two element layers each
+    T Rm[V + 2], Rp[V + 2];
+    lds_urow<T, V, HALO>(U0, Rm, gx, G);
+    vload<T, V>(U0 + (1 << rsh), uc);
+    lds_urow<T, V, HALO>(U0 + (2 << rsh), Rp, gx, G);
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      fr[v] = Z[0][v] * Rm[v] + Z[0][v + 1] * Rm[v + 2] + Z[1][v] * Rp[v] + Z[1][v + 1] * Rp[v + 2];
+  }
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz) {
+    // plane k -+ 1: edge diagonals (i +- 1, j) over the two element rows,
+    // (i, j +- 1) over the two element columns, and the four corners
+    const T* U = dz ? Up : Um;
+    T Q[3][V + 2];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) lds_urow<T, V, HALO>(U + (dy << rsh), Q[dy], gx, G);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const T y0 = K[dz][0][v] + K[dz][1][v], y1 = K[dz][0][v + 1] + K[dz][1][v + 1];
+      const T x0 = K[dz][0][v] + K[dz][0][v + 1], x1 = K[dz][1][v] + K[dz][1][v + 1];
+      fr[v] += y0 * Q[1][v] + y1 * Q[1][v + 2] + x0 * Q[0][v + 1] + x1 * Q[2][v + 1] +
+               (K[dz][0][v] * Q[0][v] + K[dz][0][v + 1] * Q[0][v + 2] + K[dz][1][v] * Q[2][v] +
+                K[dz][1][v + 1] * Q[2][v + 2]);
+    }
+  }
 }
 
 // N consecutive values (N = 1 or an aligned vector)
@@ -756,7 +866,7 @@ inline bool zlds_ok(const ZGeom& g) {
 // stencil kernels' diagonal and of EpiChebZero, so the value is the one that
 // step would have stored; 0 on boundary nodes.  The branch is uniform over
 // the lanes of a row, which is what the DPP halo exchange needs.
-template <class T, int V>
+template <class T, int V, int HALO>
 __device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int rsh, int krow0, int s0, int s1, int jj,
                                         int kk, int n, int c, T h, T c2) {
   if (jj < 1 || jj > n - 1 || kk < 1 || kk > n - 1) {
@@ -764,24 +874,14 @@ __device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int rsh, int 
     for (int v = 0; v < V; ++v) u[v] = T(0);
     return;
   }
-  // the 8-element sum accumulated one kappa row at a time, in the order
-  // (sz, sy, sx) of the stencil kernels, so few values are live
   const int sl[2] = {s0, s1};
-  T ks[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) ks[v] = T(0);
+  T K[2][2][V + 1], Z[2][V + 1], ks[V];
 #pragma unroll
   for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-    for (int dy = 0; dy < 2; ++dy) {
-      T K[V + 1];
-      lds_krow<T, V>(Kl + ((sl[dz] * KR + jj - 1 + dy - krow0) << rsh) + c * V, K, c);
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        ks[v] += K[v];
-        ks[v] += K[v + 1];
-      }
-    }
+    for (int dy = 0; dy < 2; ++dy)
+      lds_krow<T, V, HALO>(Kl + ((sl[dz] * KR + jj - 1 + dy - krow0) << rsh) + c * V, K[dz][dy], c);
+  ksum_from_rows<T, V>(K, Z, ks);
   const T third = T(1) / T(3);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
@@ -790,7 +890,7 @@ __device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int rsh, int 
   }
 }
 
-template <class T, int V, bool NEED_U, bool PRO, int OP, class Epi>
+template <class T, int V, bool NEED_U, bool PRO, int OP, class Epi, int HALO>
 __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const T* __restrict__ u,
                                               const T* __restrict__ kap, const int* __restrict__ active,
                                               double* __restrict__ partial, uint32_t pstride, Epi epi,
@@ -933,7 +1033,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
           T w[V];
 #pragma unroll
           for (int t = 0; t < V; ++t) w[t] = pu[m][t];
-          z1_form<T, V>(w, Kl, KR, rsh, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, h, op.c2);
+          z1_form<T, V, HALO>(w, Kl, KR, rsh, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, h, op.c2);
 #pragma unroll
           for (int t = 0; t < V; ++t) pu[m][t] = w[t];
         }
@@ -949,8 +1049,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
             for (int jy = 0; jy < 2; ++jy) {
               const int K = (kk + pz) >> 1, J = (jj + jy) >> 1;
               nload<T, H>(Cl + (((K & 1) * CR + J - crow0) << (rsh - 1)) + c * H, W[pz][jy]);
-              const T nx = from_next(W[pz][jy][0]);
-              W[pz][jy][H] = c == G - 1 ? T(0) : nx;
+              W[pz][jy][H] = halo_next<HALO>(W[pz][jy][0], c, G);
             }
           constexpr int CQ = H + 1;
           T L[CQ];
@@ -1057,58 +1156,26 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
     const T third = T(1) / T(3), twelfth = T(1) / T(12);
     for (int k = k0; k < k1; ++k) {
       if (valid) {
-        // The same 20-neighbour sum as the register engine, gathered one u
-        // plane at a time (planes k-1 and k+1: the centre row and the rows
-        // j-1, j+1; plane k: rows j-1, j+1 and the centre values) so that only
-        // one plane of the window is live.
-        T K[2][2][V + 1];
-        const int ks[2] = {(k - 1) & (KP - 1), k & (KP - 1)};
-#pragma unroll
-        for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-          for (int dy = 0; dy < 2; ++dy)
-            lds_krow<T, V>(Kl + ((ks[dz] * KR + jr + dy + KOFF) << rsh) + i0, K[dz][dy], gx);
+        // the Q1 row from the LDS tile (see q1_gather); without the u
+        // operand only the diagonal is needed
+        const int km = (k - 1) & (KP - 1), kc = k & (KP - 1);
         T far[V], ksum[V], uc[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          far[v] = T(0);
-          ksum[v] = T(0);
-#pragma unroll
-          for (int sz = 0; sz < 2; ++sz)
-#pragma unroll
-            for (int sy = 0; sy < 2; ++sy)
-#pragma unroll
-              for (int sx = 0; sx < 2; ++sx) ksum[v] += K[sz][sy][v + sx];
-          uc[v] = T(0);
-        }
         if (NEED_U) {
+          q1_gather<T, V, HALO>(Kl + ((km * KR + jr + KOFF) << rsh) + i0, Kl + ((kc * KR + jr + KOFF) << rsh) + i0,
+                                Ul + ((sm * UR + jr) << rsh) + i0, Ul + ((s0 * UR + jr) << rsh) + i0,
+                                Ul + ((sp * UR + jr) << rsh) + i0, rsh, gx, G, ksum, far, uc);
+        } else {
+          T K[2][2][V + 1], Z[2][V + 1];
 #pragma unroll
-          for (int sz = 0; sz < 2; ++sz) {
-            const T* P = Ul + (((sz ? sp : sm) * UR + jr) << rsh) + i0;
-            T R[3][V + 2];
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + (dy << rsh), R[dy], gx, G);
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-#pragma unroll
-              for (int sy = 0; sy < 2; ++sy)
-#pragma unroll
-                for (int sx = 0; sx < 2; ++sx)
-                  far[v] += K[sz][sy][v + sx] * (R[1][v + 2 * sx] + (R[2 * sy][v + 1] + R[2 * sy][v + 2 * sx]));
+          for (int dy = 0; dy < 2; ++dy) {
+            lds_krow<T, V, HALO>(Kl + ((km * KR + jr + dy + KOFF) << rsh) + i0, K[0][dy], gx);
+            lds_krow<T, V, HALO>(Kl + ((kc * KR + jr + dy + KOFF) << rsh) + i0, K[1][dy], gx);
           }
-          {
-            const T* P = Ul + ((s0 * UR + jr) << rsh) + i0;
-            T R0[V + 2], R2[V + 2];
-            lds_urow<T, V>(P, R0, gx, G);
-            vload<T, V>(P + URS, uc);
-            lds_urow<T, V>(P + 2 * URS, R2, gx, G);
+          ksum_from_rows<T, V>(K, Z, ksum);
 #pragma unroll
-            for (int v = 0; v < V; ++v)
-#pragma unroll
-              for (int sy = 0; sy < 2; ++sy)
-#pragma unroll
-                for (int sx = 0; sx < 2; ++sx)
-                  far[v] += (K[0][sy][v + sx] + K[1][sy][v + sx]) * (sy ? R2 : R0)[v + 2 * sx];
+          for (int v = 0; v < V; ++v) {
+            far[v] = T(0);
+            uc[v] = T(0);
           }
         }
         T au[V], dg[V];
@@ -1205,7 +1272,7 @@ __device__ __forceinline__ T rupd(T r, T a, T q) { return fma(-a, q, r); }
 template <class T, int V, bool Z1, bool UPD>
 constexpr int resr_min_waves() { return sizeof(T) == 4 && !UPD ? 4 : 1; }
 
-template <class T, int V, bool Z1, bool UPD>
+template <class T, int V, bool Z1, bool UPD, int HALO>
 __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr(ZGeom g, size_t stride, T h, const T* __restrict__ x,
                                               const T* __restrict__ bf, const T* __restrict__ kap,
                                               const int* __restrict__ active, T* __restrict__ bc, size_t cstride,
@@ -1294,7 +1361,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
         T w[V];
 #pragma unroll
         for (int t = 0; t < V; ++t) w[t] = (UPD && upd_on) ? rupd(pu[m][t], ua, pq[UPD ? m : 0][t]) : pu[m][t];
-        z1_form<T, V>(w, Kl, KR, rsh, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, h, c2);
+        z1_form<T, V, HALO>(w, Kl, KR, rsh, krow0, (kk - 1) & (KP - 1), kk & (KP - 1), jj, kk, n, c, h, c2);
 #pragma unroll
         for (int t = 0; t < V; ++t) pu[m][t] = w[t];
       }
@@ -1378,53 +1445,10 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
         const int jr = task >> gsh, gx = task & (G - 1);
         const int j = j0 + jr, i0 = gx * V;
         if (j > n - 1) continue;
-        T K[2][2][V + 1];
-        const int ks[2] = {km, kc};
-#pragma unroll
-        for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-          for (int dy = 0; dy < 2; ++dy)
-            lds_krow<T, V>(Kl + ((ks[dz] * KR + jr + dy + KOFF) << rsh) + i0, K[dz][dy], gx);
         T far[V], ksum[V], uc[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          far[v] = T(0);
-          ksum[v] = T(0);
-#pragma unroll
-          for (int sz = 0; sz < 2; ++sz)
-#pragma unroll
-            for (int sy = 0; sy < 2; ++sy)
-#pragma unroll
-              for (int sx = 0; sx < 2; ++sx) ksum[v] += K[sz][sy][v + sx];
-        }
-#pragma unroll
-        for (int sz = 0; sz < 2; ++sz) {
-          const T* P = Ul + (((sz ? sp : sm) * UR + jr) << rsh) + i0;
-          T Rw[3][V + 2];
-#pragma unroll
-          for (int dy = 0; dy < 3; ++dy) lds_urow<T, V>(P + (dy << rsh), Rw[dy], gx, G);
-#pragma unroll
-          for (int v = 0; v < V; ++v)
-#pragma unroll
-            for (int sy = 0; sy < 2; ++sy)
-#pragma unroll
-              for (int sx = 0; sx < 2; ++sx)
-                far[v] += K[sz][sy][v + sx] * (Rw[1][v + 2 * sx] + (Rw[2 * sy][v + 1] + Rw[2 * sy][v + 2 * sx]));
-        }
-        {
-          const T* P = Ul + ((s0 * UR + jr) << rsh) + i0;
-          T R0[V + 2], R2[V + 2];
-          lds_urow<T, V>(P, R0, gx, G);
-          vload<T, V>(P + URS, uc);
-          lds_urow<T, V>(P + 2 * URS, R2, gx, G);
-#pragma unroll
-          for (int v = 0; v < V; ++v)
-#pragma unroll
-            for (int sy = 0; sy < 2; ++sy)
-#pragma unroll
-              for (int sx = 0; sx < 2; ++sx)
-                far[v] += (K[0][sy][v + sx] + K[1][sy][v + sx]) * (sy ? R2 : R0)[v + 2 * sx];
-        }
+        q1_gather<T, V, HALO>(Kl + ((km * KR + jr + KOFF) << rsh) + i0, Kl + ((kc * KR + jr + KOFF) << rsh) + i0,
+                              Ul + ((sm * UR + jr) << rsh) + i0, Ul + ((s0 * UR + jr) << rsh) + i0,
+                              Ul + ((sp * UR + jr) << rsh) + i0, rsh, gx, G, ksum, far, uc);
         T bv[V], t[V];
         const size_t own = i0 + (size_t)n * j + (size_t)n2 * kk;
         vload<T, V>(bb + own, bv);
@@ -1497,8 +1521,21 @@ hipError_t zlaunch_lds(int n, int B, const T* u, const T* xc, const T* kap, cons
   if (!zlds_ok<T, OP, PRO>(g)) return hipErrorInvalidValue;
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
-  k_zlds<T, V, NEED_U, PRO, OP, Epi><<<dim3(blocks), dim3(g.threads), zlds_bytes<T, OP, PRO>(g), st>>>(
-      g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, PRO ? grid_stride(n / 2) : 0, op);
+  const size_t lds = zlds_bytes<T, OP, PRO>(g);
+  const size_t cs = PRO ? grid_stride(n / 2) : 0;
+  switch (halo_mode(g.G)) {
+    case HALO_DPPROW:
+      k_zlds<T, V, NEED_U, PRO, OP, Epi, HALO_DPPROW><<<dim3(blocks), dim3(g.threads), lds, st>>>(
+          g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, cs, op);
+      break;
+    case HALO_WAVE:
+      k_zlds<T, V, NEED_U, PRO, OP, Epi, HALO_WAVE><<<dim3(blocks), dim3(g.threads), lds, st>>>(
+          g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, cs, op);
+      break;
+    default:
+      k_zlds<T, V, NEED_U, PRO, OP, Epi, HALO_SELECT><<<dim3(blocks), dim3(g.threads), lds, st>>>(
+          g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, cs, op);
+  }
   return hipGetLastError();
 }
 
@@ -1938,6 +1975,24 @@ hipError_t launch_true_residual(int n, int B, const double* kap, double bconst, 
 template <class T>
 bool resr_usable(int n, int B) { return resr_ok<T>(resr_geom<T>(n, B)); }
 
+template <class T, int V, bool Z1, bool UPD>
+void resr_dispatch(const ZGeom& g, uint32_t blocks, size_t lds, hipStream_t st, size_t stride, T h, const T* x,
+                   const T* bf, const T* kap, const int* active, T* bc, size_t cstride, T c2, ResrUpd<T> upd) {
+  switch (halo_mode(g.G)) {
+    case HALO_DPPROW:
+      k_resr<T, V, Z1, UPD, HALO_DPPROW><<<dim3(blocks), dim3(g.threads), lds, st>>>(g, stride, h, x, bf, kap, active,
+                                                                                   bc, cstride, c2, upd);
+      break;
+    case HALO_WAVE:
+      k_resr<T, V, Z1, UPD, HALO_WAVE><<<dim3(blocks), dim3(g.threads), lds, st>>>(g, stride, h, x, bf, kap, active,
+                                                                                 bc, cstride, c2, upd);
+      break;
+    default:
+      k_resr<T, V, Z1, UPD, HALO_SELECT><<<dim3(blocks), dim3(g.threads), lds, st>>>(g, stride, h, x, bf, kap, active,
+                                                                                   bc, cstride, c2, upd);
+  }
+}
+
 template <class T>
 hipError_t launch_residual_restrict(int n, int B, const T* kap, const T* b, const T* x, T* bc, const int* active,
                                    hipStream_t st, bool presmooth, double c2) {
@@ -1946,13 +2001,13 @@ hipError_t launch_residual_restrict(int n, int B, const T* kap, const T* b, cons
   const uint32_t blocks = g.parts() * (uint32_t)B;
   if (presmooth) {
     if (!presmooth_usable<T>(n, B)) return hipErrorInvalidValue;
-    k_resr<T, V, true, false><<<dim3(blocks), dim3(g.threads), resr_bytes<T, true>(g), st>>>(
-        g, grid_stride(n), T(1) / T(n), nullptr, b, kap, active, bc, grid_stride(n / 2), T(c2), ResrUpd<T>{});
+    resr_dispatch<T, V, true, false>(g, blocks, resr_bytes<T, true>(g), st, grid_stride(n), T(1) / T(n), nullptr, b,
+                                     kap, active, bc, grid_stride(n / 2), T(c2), ResrUpd<T>{});
     return hipGetLastError();
   }
   if (!resr_ok<T>(g)) return hipErrorInvalidValue;
-  k_resr<T, V, false, false><<<dim3(blocks), dim3(g.threads), resr_bytes<T, false>(g), st>>>(
-      g, grid_stride(n), T(1) / T(n), x, b, kap, active, bc, grid_stride(n / 2), T(0), ResrUpd<T>{});
+  resr_dispatch<T, V, false, false>(g, blocks, resr_bytes<T, false>(g), st, grid_stride(n), T(1) / T(n), x, b, kap,
+                                    active, bc, grid_stride(n / 2), T(0), ResrUpd<T>{});
   return hipGetLastError();
 }
 
@@ -1971,8 +2026,8 @@ hipError_t launch_residual_restrict_update(int n, int B, const T* kap, const T* 
   u.partial = s.partial;
   u.pstride = s.pstride;
   const uint32_t blocks = g.parts() * (uint32_t)B;
-  k_resr<T, V, true, true><<<dim3(blocks), dim3(g.threads), resr_bytes<T, true>(g), st>>>(
-      g, grid_stride(n), T(1) / T(n), nullptr, r0, kap, s.active, bc, grid_stride(n / 2), T(c2), u);
+  resr_dispatch<T, V, true, true>(g, blocks, resr_bytes<T, true>(g), st, grid_stride(n), T(1) / T(n), nullptr, r0, kap,
+                                  s.active, bc, grid_stride(n / 2), T(c2), u);
   return hipGetLastError();
 }
 
