@@ -56,6 +56,39 @@ inline ZGeom zgeom(int n, int B) {
   return g;
 }
 
+// The geometry of zgeom with `rows` rows per workgroup instead of the most
+// that fit (rows >= 1, same thread count).
+template <class T>
+inline ZGeom zgeom_rows(int n, int B, int rows) {
+  ZGeom g = zgeom<T>(n, B);
+  if (g.G < 1 || rows < 1) return g;
+  g.rows = rows;
+  g.row_blocks = (n - 1 + rows - 1) / rows;
+  const long waves = (long)B * g.row_blocks * (g.threads / 64);
+  int zc = 1;
+  while (waves * zc < kFillWaves && (n - 1) / (zc * 2) >= 8) zc *= 2;
+  g.zc = zc;
+  g.zlen = (n - 1 + zc - 1) / zc;
+  return g;
+}
+
+// Tiles of the corrected smoothing step with its operand formed on the fly,
+// which stages two rows more than it computes: with rows of 16 lanes (G = 16)
+// a 16-row tile stages 18 rows with 16 rows of threads, and the wave that
+// takes the extra rows (each formed from the kappa ring and the coarse
+// correction) runs a second pass per plane while the others wait at the
+// plane's barrier.  14-row tiles stage 16 rows in one pass at about the same
+// total work (5 tiles of 63 rows instead of 4): 9.7 -> 9.4 ms per 64^3 x 1024
+// step.
+template <class T>
+inline ZGeom zgeom_tall(int n, int B) {
+  const ZGeom g = zgeom<T>(n, B);
+  // only where the shorter tiles add at most a quarter more tiles (63 rows:
+  // 5 instead of 4; not 31 rows: 3 instead of 2)
+  const bool fits = 4 * ((n - 1 + 13) / 14) <= 5 * ((n - 1 + 15) / 16);
+  return g.G == 16 && g.threads == 256 && g.rows == 16 && fits ? zgeom_rows<T>(n, B, 14) : g;
+}
+
 // Streaming kernels cover the flat range [n^2, n^3) of every sample (planes
 // 1..n-1, boundary positions included: they hold zero in every vector) in
 // 16-byte vectors; `chunks` workgroups per sample.
@@ -84,6 +117,8 @@ inline uint32_t max_parts(int n, int B) {
   if (sgeom<double>(n).chunks > m) m = sgeom<double>(n).chunks;
   if (n >= 4 && zgeom<float>(n, B).parts() > m) m = zgeom<float>(n, B).parts();
   if (zgeom<double>(n, B).parts() > m) m = zgeom<double>(n, B).parts();
+  if (n >= 4 && zgeom_tall<float>(n, B).parts() > m) m = zgeom_tall<float>(n, B).parts();
+  if (zgeom_tall<double>(n, B).parts() > m) m = zgeom_tall<double>(n, B).parts();
   return m;
 }
 

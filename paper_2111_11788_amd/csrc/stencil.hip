@@ -1235,6 +1235,8 @@ inline size_t resr_bytes(const ZGeom& g) {
 // Geometry of k_resr: the tiles of k_zlds.  (Adding threads so that the
 // extra residual row of a full tile takes no second pass measured slower on
 // the 64^3 batch: 320 threads, 9.8 -> 15.6 ms per step.)
+// (14-row tiles, which keep every residual row in one pass, measured slower
+// here: 9.6 -> 10.2 ms per 64^3 x 1024 step, from the extra tiles' staging)
 template <class T>
 inline ZGeom resr_geom(int n, int B) { return zgeom<T>(n, B); }
 
@@ -1513,11 +1515,16 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
   }
 }
 
+// the corrected smoothing step with its operand formed on the fly stages two
+// rows more than it computes: tall-tile geometry (see zgeom_tall)
+template <class T, bool PRO, int OP>
+inline ZGeom zlds_geom(int n, int B) { return (PRO && OP == OP_Z1) ? zgeom_tall<T>(n, B) : zgeom<T>(n, B); }
+
 template <class T, bool NEED_U, bool PRO, int OP, class Epi>
 hipError_t zlaunch_lds(int n, int B, const T* u, const T* xc, const T* kap, const int* active, double* partial,
                        uint32_t pstride, Epi epi, uint32_t* nparts, hipStream_t st, OpArgs<T> op = {}) {
   constexpr int V = ZV<T>::V;
-  const ZGeom g = zgeom<T>(n, B);
+  const ZGeom g = zlds_geom<T, PRO, OP>(n, B);
   if (!zlds_ok<T, OP, PRO>(g)) return hipErrorInvalidValue;
   if (nparts) *nparts = g.parts();
   const uint32_t blocks = g.parts() * (uint32_t)B;
@@ -1874,7 +1881,7 @@ hipError_t launch_cheb_prolong(int n, int B, const T* kap, const T* b, const T* 
 
 template <class T>
 bool presmooth_usable(int n, int B) {
-  const ZGeom g = zgeom<T>(n, B);
+  const ZGeom g = zlds_geom<T, true, OP_Z1>(n, B);
   return n >= 4 && !use_small<T>(n) && resr_ok<T, true>(resr_geom<T>(n, B)) && zlds_ok<T, OP_Z1, true>(g);
 }
 
