@@ -40,13 +40,13 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 TRAFFIC = {
     "profile": "profiles/batched-64cube-1024_hbm_traffic.txt",
     "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 1, "fuse": 63, "lanes": 1},
-    "sha256_16": {"common.hpp": "84103274fa2b6280", "engine.hpp": "4b5b6d63f226a1c5", "grid.hpp": "b39dc836a416fe0a", "kernels.hpp": "08f555efa50d621c", "krylov.hip": "3417955a34ecc56a", "stencil.hip": "f18d689eb84cf607"},
+    "sha256_16": {"common.hpp": "84103274fa2b6280", "engine.hpp": "ae24b78fbfca7bd6", "grid.hpp": "b240c0e6cdf9fd1c", "kernels.hpp": "037887b66ba1ce4b", "krylov.hip": "2ed8ae7ac3631406", "stencil.hip": "d4b9c76d277a2723"},
     "bytes_per_launch": {
-        "PCG_UPDATE (f32)": 3170186283,
-        "CHEB_PROLONG (f32)": 2221311089,
-        "RESIDUAL_RESTRICT (f32)": 1635846088,
-        "PCG_APPLY (f32)": 7329883640,
-        "TRUE_RESIDUAL (f64)": 8659916115,
+        "PCG_APPLY (f32)": 7327100137,
+        "CHEB_PROLONG (f32)": 2094136895,
+        "RESIDUAL_RESTRICT (f32)": 1652254844,
+        "PCG_UPDATE (f32)": 3168461471,
+        "TRUE_RESIDUAL (f64)": 8660487668,
     },
 }
 
@@ -569,7 +569,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=1024)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "fp64", "bf16kle"], default="mixed",
+                    help="mixed: fp32 multigrid in fp64 refinement; fp64; bf16kle: mixed with the KLE on bf16 MFMA")
     ap.add_argument("--mode", choices=["c2", "c3", "c4", "c5", "pause"], default="c2",
                     help="c2: the throughput line (default); c3: time-to-eps; c4: serving; c5: 256^3 stress; "
                     "pause: pause-model scheduler stress")
@@ -607,7 +608,7 @@ def main():
 
     import workloads
     wl = workloads.C2
-    prec = 1 if args.precision == "mixed" else 0
+    prec = {"mixed": 1, "fp64": 0, "bf16kle": 2}[args.precision]
     tuning = json.loads(args.tuning) if args.tuning else (None if args.autotune else dict(TRAFFIC["tuning"]))
     main_run = run_gpu(wl, prec, args.steps, args.warmup, args.batch, profile=True,
                        autotune=args.autotune and tuning is None, tuning=tuning,
@@ -623,12 +624,13 @@ def main():
         "metric": METRIC, "value": main_run["value"], "unit": "sample-DOFs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if prec == 1 else "f64", "data": "synthetic",
+        "dtype": {1: "f32+f64", 0: "f64", 2: "bf16+f32+f64"}[prec], "data": "synthetic",
         "config": {"workload": wl.name, "mesh": f"{wl.n0}^3 Q1 hexahedra", "samples_per_step": args.batch,
                    "dofs_per_sample": (wl.n0 - 1) ** 3, "n_modes": wl.n_modes, "corr_len": wl.corr_len,
                    "sigma2": wl.sigma2, "qoi": "subcube [1/4,3/4]^3 average", "rtol": wl.rtol,
                    "solver": "GMG-PCG (Chebyshev-Jacobi smoothing, V-cycle to 2^3)",
-                   "precision": "fp32 GMG-PCG inside fp64 refinement" if prec == 1 else "fp64"},
+                   "precision": {1: "fp32 GMG-PCG inside fp64 refinement", 0: "fp64",
+                                 2: "fp32 GMG-PCG inside fp64 refinement, KLE on bf16 MFMA"}[prec]},
         "iterations": {"mean": main_run["iters_mean"], "max": main_run["iters_max"]},
         "tuning": main_run["tuning"],
         "roofline": main_run.get("roofline"),
