@@ -266,6 +266,15 @@ def run_c5_leg(steps: int = 3, B: int = 16):
             "tuning": tuning, "steps": steps}
 
 
+def _round_tuning(ctx, args):
+    """--lanes and --no-pack of the sampling rounds."""
+    import paper_2111_11788_amd as mm
+    if args.lanes:
+        ctx.set_tuning(lanes=args.lanes)
+    if args.no_pack:
+        ctx.set_tuning(fuse=ctx.tuning()["fuse"] & ~mm.FUSE_PACK)
+
+
 def run_c3(args):
     """Time-to-eps of the 5-level MLMC workload (pilot + optimal allocation)."""
     import numpy as np
@@ -276,8 +285,7 @@ def run_c3(args):
 
     def one(eps):
         ctx = mm.Context(wl, max_batch=1024, arena_bytes=40 << 30, cheb_degree=args.cheb_degree)
-        if args.lanes:
-            ctx.set_tuning(lanes=args.lanes)
+        _round_tuning(ctx, args)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nl, est = ctx.estimate(eps, n_pilot=32, cost_model=0, max_rounds=3)
@@ -300,8 +308,7 @@ def run_c3(args):
         """Adaptive MLMC from levels 0..l0: L grows by eq. mlmc_num_levels (the
         configured meshes cap it), N_l by eq. mlmc_num_samples."""
         ctx = mm.Context(wl, max_batch=1024, arena_bytes=40 << 30, cheb_degree=args.cheb_degree)
-        if args.lanes:
-            ctx.set_tuning(lanes=args.lanes)
+        _round_tuning(ctx, args)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nl, info, est = ctx.estimate_adaptive(eps, l0=l0, n_pilot=32, cost_model=0, max_rounds=10)
@@ -592,6 +599,8 @@ def main():
                     "(0: twice the slots)")
     ap.add_argument("--sat-seconds", type=float, default=3.0, help="c4: measured closed-loop seconds")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--no-pack", action="store_true",
+                    help="c3: solves of two levels on one mesh in separate tasks")
     ap.add_argument("--lanes", type=int, default=0,
                     help="c3: concurrent lanes of the sampling rounds (0: the library default)")
     ap.add_argument("--cheb-degree", type=int, default=0,

@@ -400,7 +400,7 @@ typedef struct mlmc_tuning {
   int32_t cheb_degree;    /* Chebyshev smoothing degree per half V-cycle, 1..8 */
   int32_t max_batch;      /* samples per batched solve */
   int32_t graph_batch;    /* captured PCG iterations replayed per convergence check (0: no graphs) */
-  int32_t fuse;           /* MLMC_FUSE_* bits: kernel fusions in use (default: all but RUPDATE) */
+  int32_t fuse;           /* MLMC_FUSE_* bits: kernel fusions and packing in use (default: all but RUPDATE) */
   int32_t field;          /* fp64 KLE evaluation: 1 the dense MFMA tile GEMM; 0 (default) or 2 separable
                              (per x-row of elements, H = xi sqrt(lambda) phi_y phi_z summed over the
                              modes of each x-factor, then g = H phi_x), or the GEMM when one sample's
@@ -427,9 +427,12 @@ enum {
   MLMC_FUSE_RUPDATE = 64   /* with DIRECTION and PRESMOOTH: the PCG update r -= alpha q is formed inside
                               the next iteration's first V-cycle kernel (residual restriction), which
                               writes r to the other of two residual buffers and tests convergence */,
-  MLMC_FUSE_SOLVE = 128    /* mixed precision with GMG on a 4^3 or 8^3 mesh: the whole solve of a sample
+  MLMC_FUSE_SOLVE = 128,   /* mixed precision with GMG on a 4^3 or 8^3 mesh: the whole solve of a sample
                               (fp64 refinement, fp32 PCG, V-cycle) in one workgroup with every vector in
                               LDS, one launch per batch; needs vsmall_fp32 >= the mesh */
+  MLMC_FUSE_PACK = 256     /* sampling rounds: the solves of two levels on the same mesh (level l's own
+                              and level l+1's coarse one) share one batched solve when together they fit
+                              the lane capacity of that mesh */
 };
 
 int mlmc_get_tuning(const mlmc_ctx* ctx, mlmc_tuning* out);
@@ -460,18 +463,20 @@ int mlmc_reset_stats(mlmc_ctx* ctx);
  * others are folded in).  For step-level use and tests. */
 int mlmc_fold_stats(mlmc_ctx* ctx, int32_t level, const double* y, uint64_t count);
 
-/* One task of a sampling round (see mlmc_sample_level). */
+/* One part of a task of a sampling round (see mlmc_sample_level). */
 typedef struct mlmc_plan_task {
-  int32_t level;       /* MLMC level whose draws the task solves */
+  int32_t level;       /* MLMC level whose draws the part solves */
   int32_t n;           /* mesh: n0 << level (the level's own), or half of it (the coarse solve of the pair) */
   uint64_t first;      /* first sample index */
   int32_t count;       /* samples */
-  int32_t lane;        /* lane it ran on */
+  int32_t lane;        /* lane its task ran on */
+  int32_t task;        /* index of its task (one batched solve) in assignment order */
 } mlmc_plan_task;
 
-/* The tasks of the last sampling round in assignment order (finest mesh
- * first, each to the least-loaded lane); *n receives their number (the first
- * max of them are written to out, host).  For tests of the scheduling. */
+/* The parts of the tasks of the last sampling round, tasks in assignment
+ * order (finest mesh first, each to the least-loaded lane), parts in their
+ * order within the task; *n receives their number (the first max of them are
+ * written to out, host).  For tests of the scheduling. */
 int mlmc_last_plan(const mlmc_ctx* ctx, mlmc_plan_task* out, int32_t max, int32_t* n);
 
 /* ---------------------------------------------------------------- serving */

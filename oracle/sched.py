@@ -20,9 +20,10 @@ always 1) are
     every batch is capped by cap and by what is left;
   * with one lane there is no other partition to leave work for: batches are
     the capacity;
-  * a batch of a level l > 0 is two tasks, the solve on the level's mesh and
-    the solve on the coarse mesh of its pair (Sec. 2.2); a task's work is its
-    samples times the interior unknowns of its mesh;
+  * a batch of a level l > 0 is two solves, on the level's mesh and on the
+    coarse mesh of its pair (Sec. 2.2); optionally the solves of two levels on
+    one mesh share a task (see plan); a task's work is its samples times the
+    interior unknowns of its mesh;
   * tasks are ordered by decreasing mesh (q of the task), then by decreasing
     level, then in sample order; each goes to the lane with the least work
     assigned so far, the lowest lane on ties.
@@ -72,25 +73,50 @@ def level_cap(n0: int, levels: int, level: int, max_batch: int, limit: int = 655
 
 
 def plan(n0: int, requests: Sequence[Tuple[int, int, int]], lanes: int, caps: Sequence[int],
-         fills: Sequence[int]):
-    """Tasks of a round: requests are (level, first, count), caps and fills the
-    lane capacity and the device-filling batch of each request.  Returns dicts
-    (level, n, first, count, lane) in assignment order."""
-    order = sorted(range(len(requests)), key=lambda r: -requests[r][0])
-    tasks = []
-    for r in order:
-        level, first, count = requests[r]
+         fills: Sequence[int], pack: bool = False):
+    """Tasks of a round: requests are (level, first, count); caps[m] and
+    fills[m] the lane capacity and the device-filling batch of level m (whose
+    own mesh is n0 << m), indexed by level.  With `pack`, the coarse solves of
+    level m+1 and the fine solves of level m (both on mesh n0 << m) are paired
+    in order, the i-th with the i-th, into one task when together they fit
+    caps[m]; without it a mesh's coarse solves come before its fine ones.
+    Returns the tasks in assignment order, each a dict (n, lane, parts), parts
+    being dicts (level, first, count) in their order within the task."""
+    levels = len(caps)
+    coarse = [[] for _ in range(levels)]
+    fine = [[] for _ in range(levels)]
+    for level, first, count in sorted(requests, key=lambda q: -q[0]):
         off = 0
-        for b in batch_sizes(count, lanes, caps[r], fills[r]):
-            n = n0 << level
-            tasks.append(dict(level=level, n=n, first=first + off, count=b))
+        for b in batch_sizes(count, lanes, caps[level], fills[level]):
+            part = dict(level=level, first=first + off, count=b)
+            fine[level].append(part)
             if level > 0:
-                tasks.append(dict(level=level, n=n // 2, first=first + off, count=b))
+                coarse[level - 1].append(dict(part))
             off += b
-    tasks.sort(key=lambda t: -t["n"])          # stable: level, then sample order
+    tasks = []
+    for m in range(levels - 1, -1, -1):
+        a, f = coarse[m], fine[m]
+        if not pack:
+            groups = [[p] for p in a] + [[p] for p in f]
+        else:
+            groups = []
+            for i in range(max(len(a), len(f))):
+                if i < len(a) and i < len(f) and a[i]["count"] + f[i]["count"] <= caps[m]:
+                    groups.append([a[i], f[i]])
+                else:
+                    groups += [[a[i]]] if i < len(a) else []
+                    groups += [[f[i]]] if i < len(f) else []
+        for g in groups:
+            tasks.append(dict(n=n0 << m, parts=g, count=sum(p["count"] for p in g)))
     load = [0] * max(1, lanes)
     for t in tasks:
         lane = min(range(len(load)), key=lambda i: (load[i], i))
         t["lane"] = lane
         load[lane] += t["count"] * dofs(t["n"])
     return tasks
+
+
+def flat(tasks):
+    """(level, n, first, count, lane, task) of every part, tasks in order."""
+    return [(p["level"], t["n"], p["first"], p["count"], t["lane"], i)
+            for i, t in enumerate(tasks) for p in t["parts"]]

@@ -24,6 +24,9 @@ KERNELS = ["XI", "FIELD", "APPLY", "CHEB_ZERO", "CHEB", "CHEB_XO", "RESIDUAL", "
            "COARSEST", "COARSEN", "PCG_APPLY", "PCG_UPDATE", "PCG_DOT", "PCG_DIRECTION", "TRUE_RESIDUAL",
            "REDUCE", "QOI", "MISC", "CHEB_PROLONG", "PCG_UPDATE_ZERO",
            "RESIDUAL_RESTRICT", "SOLVE_SMALL"]
+# MLMC_FUSE_* bits of the tuning's `fuse` field
+FUSE_PROLONG, FUSE_UPDATE, FUSE_REFINE, FUSE_RESTRICT = 1, 2, 4, 8
+FUSE_PRESMOOTH, FUSE_DIRECTION, FUSE_RUPDATE, FUSE_SOLVE, FUSE_PACK = 16, 32, 64, 128, 256
 
 # exported symbols of include/mlmc.h (checked by the CPU test suite)
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
@@ -59,7 +62,7 @@ class LevelStats(ctypes.Structure):
 
 class PlanTask(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("n", ctypes.c_int32), ("first", ctypes.c_uint64),
-                ("count", ctypes.c_int32), ("lane", ctypes.c_int32)]
+                ("count", ctypes.c_int32), ("lane", ctypes.c_int32), ("task", ctypes.c_int32)]
 
 
 class SampleResult(ctypes.Structure):
@@ -301,7 +304,7 @@ class Context:
         return rc
 
     def last_plan(self):
-        """Tasks of the last sampling round: list of dicts (level, n, first, count, lane)."""
+        """Parts of the tasks of the last sampling round: list of dicts (level, n, first, count, lane, task)."""
         n = ctypes.c_int32()
         self._check(lib().mlmc_last_plan(self.h, None, 0, ctypes.byref(n)))
         buf = (PlanTask * max(1, n.value))()

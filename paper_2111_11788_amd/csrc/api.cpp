@@ -406,8 +406,9 @@ int mlmc_autotune(mlmc_ctx* ctx, int32_t level, int32_t batch, mlmc_tuning* best
   }
   const int nf = ctx->cfg.n0 << level, nc = level > 0 ? nf / 2 : 0;
   for (int f : {MLMC_FUSE_PROLONG, MLMC_FUSE_UPDATE, MLMC_FUSE_REFINE, MLMC_FUSE_RESTRICT, MLMC_FUSE_PRESMOOTH,
-                MLMC_FUSE_DIRECTION, MLMC_FUSE_RUPDATE, MLMC_FUSE_SOLVE}) {
+                MLMC_FUSE_DIRECTION, MLMC_FUSE_RUPDATE, MLMC_FUSE_SOLVE, MLMC_FUSE_PACK}) {
     if (f == MLMC_FUSE_SOLVE && nf > 8 && !(nc >= 4 && nc <= 8)) continue;   // no 4^3 or 8^3 solve here
+    if (f == MLMC_FUSE_PACK) continue;   // a single level has nothing to pack
     mlmc_tuning c = best; c.fuse ^= f;
     if (int rc = trial(c)) return rc;
   }
@@ -690,11 +691,15 @@ int mlmc_fold_stats(mlmc_ctx* ctx, int32_t level, const double* y, uint64_t coun
 
 int mlmc_last_plan(const mlmc_ctx* ctx, mlmc_plan_task* out, int32_t max, int32_t* n) {
   if (!ctx || !n || max < 0 || (max > 0 && !out)) return MLMC_E_INVALID;
-  *n = (int32_t)ctx->last_plan.size();
-  for (int32_t i = 0; i < max && i < *n; ++i) {
+  int32_t k = 0;
+  for (size_t i = 0; i < ctx->last_plan.size(); ++i) {
     const Task& t = ctx->last_plan[i];
-    out[i] = mlmc_plan_task{t.level, t.n, t.first, t.count, t.lane};
+    for (const Part& p : t.parts) {
+      if (k < max) out[k] = mlmc_plan_task{p.level, t.n, p.first, p.count, t.lane, (int32_t)i};
+      ++k;
+    }
   }
+  *n = k;
   return MLMC_OK;
 }
 

@@ -715,40 +715,74 @@ std::vector<int> batch_plan(uint64_t count, int K, int cap, int fill) {
 
 // Tasks of a round (Alg. incremental_greedy on K lanes): every request is cut
 // into batches (batch_plan), a batch of a level l > 0 into its fine-mesh and
-// coarse-mesh solves; the tasks are taken by decreasing mesh (the finest
-// first; among equal meshes the finer level, then sample order) and each goes
-// to the lane with the least estimated work so far (interior DOFs x samples;
-// the lowest lane on ties).
+// coarse-mesh solves.  With `pack`, the solves of two levels on the same mesh
+// n (the coarse solves of level l+1 and the fine solves of level l) are paired
+// in order, the i-th of one with the i-th of the other, into one task when
+// together they fit the lane capacity of the level whose own mesh is n
+// (`caps` holds the capacity of every level, indexed by level).  The
+// tasks are taken by decreasing mesh (the finest first; on one mesh the
+// finer level's first, then sample order) and each goes to the lane with the
+// least estimated work so far (interior DOFs x samples; the lowest lane on
+// ties).  Without packing a mesh's coarse solves all come before its fine ones.
 std::vector<Task> plan_round(const mlmc_ctx* ctx, const std::vector<LevelReq>& reqs, int K,
-                             const std::vector<int>& caps) {
+                             const std::vector<int>& caps, bool pack) {
   std::vector<int> order(reqs.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return reqs[a].level > reqs[b].level; });
-  std::vector<Task> ts;
+  const int n0 = ctx->cfg.n0;
+  // solves of each mesh level m (mesh n0 << m): the coarse solves of level m+1, then the fine of level m
+  const int nm = ctx->cfg.levels;
+  std::vector<std::vector<Part>> coarse(nm), fine(nm);
   for (int r : order) {
     const LevelReq& q = reqs[r];
     uint64_t off = 0;
-    for (int b : batch_plan(q.count, K, caps[r], fill_batch(ctx->cfg.n0 << q.level))) {
-      Task t;
-      t.level = q.level;
-      t.req = r;
-      t.first = q.first + off;
-      t.off = off;
-      t.count = b;
-      t.n = ctx->cfg.n0 << q.level;
-      t.which = 0;
-      t.work = (double)b * dofs(t.n);
-      ts.push_back(t);
+    for (int b : batch_plan(q.count, K, caps[q.level], fill_batch(n0 << q.level))) {
+      Part p;
+      p.level = q.level;
+      p.req = r;
+      p.first = q.first + off;
+      p.off = off;
+      p.count = b;
+      p.which = 0;
+      fine[q.level].push_back(p);
       if (q.level > 0) {
-        t.n /= 2;
-        t.which = 1;
-        t.work = (double)b * dofs(t.n);
-        ts.push_back(t);
+        p.which = 1;
+        coarse[q.level - 1].push_back(p);
       }
       off += (uint64_t)b;
     }
   }
-  std::stable_sort(ts.begin(), ts.end(), [](const Task& a, const Task& b) { return a.n > b.n; });
+  std::vector<Task> ts;
+  auto add = [&](int m, std::initializer_list<const Part*> ps) {
+    Task t;
+    t.n = n0 << m;
+    for (const Part* p : ps) {
+      t.parts.push_back(*p);
+      t.count += p->count;
+    }
+    t.work = (double)t.count * dofs(t.n);
+    ts.push_back(t);
+  };
+  for (int m = nm - 1; m >= 0; --m) {
+    const auto& A = coarse[m];
+    const auto& F = fine[m];
+    const int cap = caps[m];
+    if (!pack) {
+      for (const Part& p : A) add(m, {&p});
+      for (const Part& p : F) add(m, {&p});
+      continue;
+    }
+    const size_t len = std::max(A.size(), F.size());
+    for (size_t i = 0; i < len; ++i) {
+      const bool ha = i < A.size(), hf = i < F.size();
+      if (ha && hf && A[i].count + F[i].count <= cap) {
+        add(m, {&A[i], &F[i]});
+      } else {
+        if (ha) add(m, {&A[i]});
+        if (hf) add(m, {&F[i]});
+      }
+    }
+  }
   std::vector<double> load(std::max(1, K), 0.0);
   for (Task& t : ts) {
     int best = 0;
@@ -803,10 +837,13 @@ int ensure_lanes(mlmc_ctx* ctx, int K) {
   return MLMC_OK;
 }
 
-// One task on a lane (ctx: the lane's engine view): draw, forcing, field,
-// solve and QoI of its samples on its mesh; the QoIs go to dq (device, the
-// task's slice of the round's buffer).
-int run_task(mlmc_ctx* ctx, LaneState& ln, const Task& t, double* dq, int32_t* iters_host, int* status) {
+// One task on a lane (ctx: the lane's engine view): draws of every part,
+// forcing, field, solve and QoI of the task's samples on its mesh; each
+// part's QoIs go to its slice of the round's buffers (dqf: the level's own
+// mesh, dqc: the coarse one, offset base[req] + off), the iteration counts of
+// the level's own solves to the request's host array.
+int run_task(mlmc_ctx* ctx, LaneState& ln, const Task& t, const std::vector<LevelReq>& reqs,
+             const std::vector<uint64_t>& base, double* dqf, double* dqc, int* status) {
   const mlmc_config& c = ctx->cfg;
   const int B = t.count;
   const auto key = std::make_tuple(0, t.n, B);
@@ -818,22 +855,41 @@ int run_task(mlmc_ctx* ctx, LaneState& ln, const Task& t, double* dq, int32_t* i
     cv.cap = c.arena_bytes;
     cv.top = ln.offset;
     cv.dry = false;
-    ln.w.carve(cv, c, t.level, t.n, B);
+    ln.w.carve(cv, c, t.parts[0].level, t.n, B);
     // zero boundaries of every grid vector (kernels never write them)
     HIPCHK(hipMemsetAsync((char*)c.arena + ln.offset, 0, cv.top - ln.offset, ctx->st));
     ln.key = key;
   }
   MeshWork& w = ln.w;
-  w.level = t.level;
+  w.level = t.parts[0].level;
   const bool mixed = c.precision != MLMC_PREC_FP64;
   const bool forced = c.forcing == MLMC_FORCING_LOGNORMAL;
-  LAUNCH(MLMC_K_XI, (double)B * c.n_modes * 8, launch_draw_xi(c.seed, t.level, t.first, B, c.n_modes, w.xi, ctx->st));
-  if (forced)
-    if (int rc = forcing_impl(ctx, t.n, t.level, t.first, B, w.xif, w.fe, w.bvec)) return rc;
+  const int M = c.n_modes;
+  int o = 0;
+  for (const Part& p : t.parts) {
+    LAUNCH(MLMC_K_XI, (double)p.count * M * 8,
+           launch_draw_xi(c.seed, p.level, p.first, p.count, M, w.xi + (size_t)o * M, ctx->st));
+    if (forced)   // xi_f: the forcing's own coefficients (stream 2)
+      LAUNCH(MLMC_K_XI, (double)p.count * M * 8,
+             launch_draw_xi(c.seed, p.level, p.first, p.count, M, w.xif + (size_t)o * M, ctx->st, 2));
+    o += p.count;
+  }
+  if (forced) {
+    if (int rc = field_impl(ctx, t.n, B, w.xif, w.fe, nullptr, true)) return rc;
+    LAUNCH(MLMC_K_MISC, (double)B * (elems(t.n) + grid_stride(t.n)) * 8, launch_load(t.n, B, w.fe, w.bvec, ctx->st));
+  }
   if (int rc = field_impl(ctx, t.n, B, w.xi, w.kap, mixed ? w.sw.L32[0].kap : nullptr)) return rc;
-  if (int rc = solve_impl(ctx, w.sw, w.kap, w.u, iters_host, status, mixed, forced ? w.bvec : nullptr)) return rc;
+  std::vector<int32_t> its(B);
+  if (int rc = solve_impl(ctx, w.sw, w.kap, w.u, its.data(), status, mixed, forced ? w.bvec : nullptr)) return rc;
   if (int rc = qoi_impl(ctx, w.sw.outer.s, t.n, B, w.u, w.q)) return rc;
-  HIPCHK(hipMemcpyAsync(dq, w.q, (size_t)B * sizeof(double), hipMemcpyDeviceToDevice, ctx->st));
+  o = 0;
+  for (const Part& p : t.parts) {
+    double* dq = (p.which ? dqc : dqf) + base[p.req] + p.off;
+    HIPCHK(hipMemcpyAsync(dq, w.q + o, (size_t)p.count * sizeof(double), hipMemcpyDeviceToDevice, ctx->st));
+    if (p.which == 0 && reqs[p.req].iters)
+      std::memcpy(reqs[p.req].iters + p.off, its.data() + o, (size_t)p.count * sizeof(int32_t));
+    o += p.count;
+  }
   HIPCHK(hipStreamSynchronize(ctx->st));
   return MLMC_OK;
 }
@@ -877,15 +933,17 @@ int run_round(mlmc_ctx* ctx, std::vector<LevelReq>& reqs, bool record) {
   if (total > ((uint64_t)1 << 31)) FAIL(MLMC_E_INVALID, "too many samples in one call");
   // the QoIs of every sample on both meshes, at the end of the arena
   const size_t qbytes = 2 * align256(total * sizeof(double));
-  std::vector<int> caps(reqs.size());
-  for (size_t i = 0; i < reqs.size(); ++i) caps[i] = level_cap(ctx, reqs[i].level);
+  // lane capacity of each level, which also bounds a packed task on the level's own mesh
+  std::vector<int> caps(c.levels);
+  for (int l = 0; l < c.levels; ++l) caps[l] = level_cap(ctx, l);
   int K = ctx->profiling ? 1 : std::max(1, ctx->n_lanes);
   std::vector<Task> ts;
   std::vector<size_t> lane_bytes;
   for (;;) {
-    ts = plan_round(ctx, reqs, K, caps);
+    ts = plan_round(ctx, reqs, K, caps, (ctx->fuse & MLMC_FUSE_PACK) != 0);
     lane_bytes.assign(K, 0);
-    for (const Task& t : ts) lane_bytes[t.lane] = std::max(lane_bytes[t.lane], mesh_work_bytes(c, t.level, t.n, t.count));
+    for (const Task& t : ts)
+      lane_bytes[t.lane] = std::max(lane_bytes[t.lane], mesh_work_bytes(c, t.parts[0].level, t.n, t.count));
     size_t need = ctx->persistent_top + qbytes + 256;   // the QoI buffers start at a 256-byte boundary
     for (size_t b : lane_bytes) need += b;
     if (need <= c.arena_bytes) break;
@@ -963,12 +1021,9 @@ int run_round(mlmc_ctx* ctx, std::vector<LevelReq>& reqs, bool record) {
     ln.status = MLMC_OK;
     for (int ti : ln.tasks) {
       const Task& t = ts[ti];
-      const LevelReq& q = reqs[t.req];
       const auto t0 = std::chrono::steady_clock::now();
       int st = MLMC_OK;
-      double* dq = (t.which ? dqc : dqf) + base[t.req] + t.off;
-      int32_t* it = (t.which == 0 && q.iters) ? q.iters + t.off : nullptr;
-      const int rc = run_task(lc, ln, t, dq, it, &st);
+      const int rc = run_task(lc, ln, t, reqs, base, dqf, dqc, &st);
       task_s[ti] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       ln.busy += task_s[ti];
       if (rc) {
@@ -1046,7 +1101,9 @@ int run_round(mlmc_ctx* ctx, std::vector<LevelReq>& reqs, bool record) {
       R.timed += reqs[r].count;
       R.next = std::max(R.next, reqs[r].first + reqs[r].count);
     }
-    for (size_t i = 0; i < ts.size(); ++i) ctx->stats[ts[i].level].seconds += task_s[i];
+    // a task's time is shared by its parts by their samples
+    for (size_t i = 0; i < ts.size(); ++i)
+      for (const Part& p : ts[i].parts) ctx->stats[p.level].seconds += task_s[i] * p.count / ts[i].count;
   }
   if (status == MLMC_E_NONFINITE) FAIL(MLMC_E_NONFINITE, "a solve or QoI became NaN or Inf");
   if (status == MLMC_E_NOCONV) FAIL(MLMC_E_NOCONV, "some samples did not reach rtol within max_iter");
@@ -1064,7 +1121,7 @@ int check_tuning(const mlmc_tuning* t, std::string& why) {
   if (t->field < 0 || t->field > 2) { why = "field must be 0 (auto), 1 (MFMA GEMM) or 2 (separable)"; return MLMC_E_INVALID; }
   if (t->lanes < 1 || t->lanes > 8) { why = "lanes must be in 1..8"; return MLMC_E_INVALID; }
   if (t->fuse & ~(MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
-                   MLMC_FUSE_DIRECTION | MLMC_FUSE_RUPDATE | MLMC_FUSE_SOLVE)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
+                   MLMC_FUSE_DIRECTION | MLMC_FUSE_RUPDATE | MLMC_FUSE_SOLVE | MLMC_FUSE_PACK)) { why = "unknown fuse bits"; return MLMC_E_INVALID; }
   return MLMC_OK;
 }
 

@@ -206,15 +206,22 @@ struct MeshWork {
   }
 };
 
-// One task of a sampling round: `count` samples of `level` from sample
-// index `first`, solved on mesh n (which = 0: the level's mesh, 1: the coarse
-// mesh of its pair), on lane `lane`; `req` indexes the level request and
-// `off` the samples' position in it.
-struct Task {
-  int level = 0, n = 0, which = 0, lane = 0, req = 0;
+// A part of a task: `count` samples of `level` from sample index `first`, on
+// the level's own mesh (which = 0) or the coarse mesh of its pair (1); `req`
+// indexes the level request and `off` the samples' position in it.
+struct Part {
+  int level = 0, which = 0, req = 0;
   uint64_t first = 0, off = 0;
   int count = 0;
+};
+
+// One task of a sampling round: a batched solve of its parts' samples, in
+// order, on mesh n, on lane `lane` (parts of different levels on the same mesh
+// share the task when packing is on).
+struct Task {
+  int n = 0, lane = 0, count = 0;
   double work = 0.0;   // estimated cost: interior DOFs x samples
+  std::vector<Part> parts;
 };
 
 // A level's share of a round: samples first .. first+count-1 of `level`;
@@ -310,7 +317,7 @@ struct mlmc_ctx {
   // kernel, so each solve runs one more residual restriction) and is left to
   // the autotuner
   int fuse = MLMC_FUSE_PROLONG | MLMC_FUSE_UPDATE | MLMC_FUSE_REFINE | MLMC_FUSE_RESTRICT | MLMC_FUSE_PRESMOOTH |
-             MLMC_FUSE_DIRECTION | MLMC_FUSE_SOLVE;
+             MLMC_FUSE_DIRECTION | MLMC_FUSE_SOLVE | MLMC_FUSE_PACK;
   mlmc_server* server = nullptr;  // serving pools and threads while serving
   int device = 0;                 // the GPU current at creation
   void* scratch = nullptr;        // device address of that GPU's static scratch (mlmc_qoi_noalloc)
@@ -511,7 +518,8 @@ std::vector<int> batch_plan(uint64_t count, int K, int cap, int fill);
 // (the occupancy from which the engine stops splitting a sample's planes over
 // several workgroups)
 int fill_batch(int n);
-std::vector<Task> plan_round(const mlmc_ctx* ctx, const std::vector<LevelReq>& reqs, int K, const std::vector<int>& caps);
+std::vector<Task> plan_round(const mlmc_ctx* ctx, const std::vector<LevelReq>& reqs, int K, const std::vector<int>& caps,
+                             bool pack);
 // One sampling round: every request's samples drawn, solved on both meshes of
 // the pair and reduced to QoIs, the tasks spread over the lanes; with
 // `record`, Y = Q_l - Q_{l-1} folded into the levels' device statistics in

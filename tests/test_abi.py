@@ -77,3 +77,11 @@ def test_workspace_of_the_2cube_mesh_in_mixed_precision():
         for level in range(3):
             for batch in (1, 7, 4096):
                 assert mm.workspace_bytes(cfg, level, batch) > 0
+
+
+def test_binding_fuse_bits_match_the_header():
+    text = open(os.path.join(ROOT, "include", "mlmc.h")).read()
+    bits = dict((k, int(v)) for k, v in re.findall(r"\bMLMC_FUSE_([A-Z]+)\s*=\s*(\d+)", text))
+    assert len(bits) == 9
+    for k, v in bits.items():
+        assert getattr(mm, "FUSE_" + k) == v, k

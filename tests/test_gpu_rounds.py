@@ -87,27 +87,31 @@ def test_fill_geometry_examples():
     assert _fill(64) == 512 and _fill(256) == 32 and _fill(8) == 8192
 
 
-@pytest.mark.parametrize("lanes", [2, 4])
-def test_lanes_give_the_same_bits_and_the_oracle_plan(dev, lanes):
+@pytest.mark.parametrize("lanes,pack", [(2, True), (4, True), (4, False)])
+def test_lanes_give_the_same_bits_and_the_oracle_plan(dev, lanes, pack):
     # a round over three levels (plain MLMC with fixed N_l) on several lanes:
     # every sample's QoIs are the bits of the one-lane run, the estimator too,
-    # and the tasks are the scheduling oracle's, lane for lane
+    # and the tasks are the scheduling oracle's, part for part and lane for
+    # lane, with and without packing two levels' solves on one mesh
     wl = _wl(levels=3, n0=8, n_modes=16, corr_len=0.3, batch=16)
     nfix = [5000, 70, 9]
     res = {}
     for k in (1, lanes):
         ctx = mm.Context(wl, arena_bytes=2 << 30)
-        ctx.set_tuning(lanes=k)
+        fuse = ctx.tuning()["fuse"]
+        fuse = (fuse | mm.FUSE_PACK) if pack else (fuse & ~mm.FUSE_PACK)
+        ctx.set_tuning(lanes=k, fuse=fuse)
         nl, est = ctx.estimate(0.0, n_fixed=nfix)
         assert [int(x) for x in nl] == nfix
         plan = ctx.last_plan()
         caps = [sched.level_cap(wl.n0, wl.levels, l, 16) for l in range(3)]
         fills = [_fill(wl.n(l)) for l in range(3)]
-        want = sched.plan(wl.n0, [(l, 0, nfix[l]) for l in range(3)], k, caps, fills)
+        want = sched.plan(wl.n0, [(l, 0, nfix[l]) for l in range(3)], k, caps, fills, pack=pack)
         if k > 1:
             assert len(set(t["lane"] for t in plan)) > 1
-        assert [(t["level"], t["n"], t["first"], t["count"], t["lane"]) for t in plan] == \
-               [(t["level"], t["n"], t["first"], t["count"], t["lane"]) for t in want]
+        if pack:
+            assert any(len(t["parts"]) == 2 for t in want)
+        assert [(t["level"], t["n"], t["first"], t["count"], t["lane"], t["task"]) for t in plan] == sched.flat(want)
         assert est["lanes"] == k and 0.0 < est["active_ratio"] <= 1.0 + 1e-9
         per = [ctx.sample_level(l, 1000, 40) for l in range(3)]
         res[k] = (est, per)

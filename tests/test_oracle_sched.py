@@ -55,12 +55,34 @@ def test_greedy_assignment_by_hand():
     #   (4404,4115) (4404,4142) (4404,4196) (4404,4250) (4404,4277)
     t = sched.plan(4, [(0, 0, 5), (1, 0, 3), (2, 0, 2)], 2, [2, 2, 2], [1, 1, 1])
     assert [x["lane"] for x in t] == [0, 1, 0, 1, 0, 1, 1, 1, 1, 1, 1]
-    assert [(x["level"], x["n"], x["first"], x["count"]) for x in t] == [
+    assert [(p["level"], x["n"], p["first"], p["count"]) for x in t for p in x["parts"]] == [
         (2, 16, 0, 1), (2, 16, 1, 1),
         (2, 8, 0, 1), (2, 8, 1, 1), (1, 8, 0, 2), (1, 8, 2, 1),
         (1, 4, 0, 2), (1, 4, 2, 1), (0, 4, 0, 2), (0, 4, 2, 2), (0, 4, 4, 1)]
 
 
+def test_packing_pairs_levels_on_one_mesh_by_hand():
+    # the same round with packing, capacities 2 / 3 / 2 for levels 0 / 1 / 2:
+    # level 1 batches (3 samples, cap 3, fill 1): per 2, most ceil(1.24) = 2 -> [2, 1]
+    # 8^3 (mesh level 1, cap 3): coarse L2 [1, 1] with fine L1 [2, 1] -> pairs
+    #   (1 + 2 = 3 fits) and (1 + 1 = 2 fits): two tasks of 3 and 2 samples
+    # 4^3 (mesh level 0, cap 2): coarse L1 [2, 1] with fine L0 [2, 2, 1] ->
+    #   2 + 2 = 4 > 2: apart; 1 + 2 = 3 > 2: apart; then fine L0 [1] alone
+    # work: 16^3 3375, 3375; 8^3 1029, 686; 4^3 54, 54, 27, 54, 27
+    # lanes: (3375,0) (3375,3375) (4404,3375) (4404,4061) (4404,4115) (4404,4169)
+    #        (4404,4196) (4404,4250) (4404,4277)
+    t = sched.plan(4, [(0, 0, 5), (1, 0, 3), (2, 0, 2)], 2, [2, 3, 2], [1, 1, 1], pack=True)
+    assert [[(p["level"], p["first"], p["count"]) for p in x["parts"]] for x in t] == [
+        [(2, 0, 1)], [(2, 1, 1)],
+        [(2, 0, 1), (1, 0, 2)], [(2, 1, 1), (1, 2, 1)],
+        [(1, 0, 2)], [(0, 0, 2)], [(1, 2, 1)], [(0, 2, 2)], [(0, 4, 1)]]
+    assert [x["n"] for x in t] == [16, 16, 8, 8, 4, 4, 4, 4, 4]
+    assert [x["lane"] for x in t] == [0, 1, 0, 1, 1, 1, 1, 1, 1]
+
+
 def test_one_lane_keeps_request_order_by_mesh():
     t = sched.plan(8, [(1, 32, 4), (0, 32, 4)], 1, [64, 64], [8, 8])
-    assert [(x["level"], x["n"], x["lane"]) for x in t] == [(1, 16, 0), (1, 8, 0), (0, 8, 0)]
+    assert [(p["level"], x["n"], x["lane"]) for x in t for p in x["parts"]] == [(1, 16, 0), (1, 8, 0), (0, 8, 0)]
+    # with packing the two 8^3 solves share one task
+    t = sched.plan(8, [(1, 32, 4), (0, 32, 4)], 1, [64, 64], [8, 8], pack=True)
+    assert [[p["level"] for p in x["parts"]] for x in t] == [[1], [1, 0]]
