@@ -35,12 +35,13 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # read off a 1 GiB copy kernel in the same runs), averaged over the launches of
 # the event-timed pass like the roofline's achieved rate (same samples and
 # tuning, so the same launch mix).  They stand
-# for the kernels only while these sources and this tuning are unchanged; the
-# per-kernel table and the commands are in the committed counter summary.
+# for the kernels only while the device sources (the .hip launchers and the
+# headers they include) and this tuning are unchanged; the per-kernel table and
+# the commands are in the committed counter summary.
 TRAFFIC = {
     "profile": "profiles/batched-64cube-1024_hbm_traffic.txt",
     "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 1, "fuse": 63, "lanes": 1},
-    "sha256_16": {"common.hpp": "84103274fa2b6280", "engine.hpp": "ae24b78fbfca7bd6", "grid.hpp": "b240c0e6cdf9fd1c", "kernels.hpp": "037887b66ba1ce4b", "krylov.hip": "2ed8ae7ac3631406", "stencil.hip": "d4b9c76d277a2723"},
+    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "b240c0e6cdf9fd1c", "kernels.hpp": "037887b66ba1ce4b", "krylov.hip": "2ed8ae7ac3631406", "stencil.hip": "d4b9c76d277a2723"},
     "bytes_per_launch": {
         "PCG_APPLY (f32)": 7327100137,
         "CHEB_PROLONG (f32)": 2094136895,
