@@ -29,6 +29,8 @@
 #include "grid.hpp"
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace mlmc {
 namespace {
 
@@ -47,6 +49,9 @@ __device__ __forceinline__ double block_sum(double v) {
   return t;
 }
 
+template <int X>
+using Ic = std::integral_constant<int, X>;
+
 template <class T, int V>
 struct Vec {
   typedef T type __attribute__((ext_vector_type(V)));
@@ -54,19 +59,27 @@ struct Vec {
 
 template <class T, int V>
 __device__ __forceinline__ void vload(const T* p, T* dst) {
-  typedef typename Vec<T, V>::type vt;
-  const vt v = *reinterpret_cast<const vt*>(p);
+  if constexpr (V == 1) {
+    dst[0] = *p;
+  } else {
+    typedef typename Vec<T, V>::type vt;
+    const vt v = *reinterpret_cast<const vt*>(p);
 #pragma unroll
-  for (int q = 0; q < V; ++q) dst[q] = v[q];
+    for (int q = 0; q < V; ++q) dst[q] = v[q];
+  }
 }
 
 template <class T, int V>
 __device__ __forceinline__ void vstore(T* p, const T* src) {
-  typedef typename Vec<T, V>::type vt;
-  vt v;
+  if constexpr (V == 1) {
+    *p = src[0];
+  } else {
+    typedef typename Vec<T, V>::type vt;
+    vt v;
 #pragma unroll
-  for (int q = 0; q < V; ++q) v[q] = src[q];
-  *reinterpret_cast<vt*>(p) = v;
+    for (int q = 0; q < V; ++q) v[q] = src[q];
+    *reinterpret_cast<vt*>(p) = v;
+  }
 }
 
 // 1 / D for the Jacobi scaling: the hardware reciprocal in fp32 (1 ulp; the
@@ -1274,7 +1287,7 @@ __device__ __forceinline__ T rupd(T r, T a, T q) { return fma(-a, q, r); }
 template <class T, int V, bool Z1, bool UPD>
 constexpr int resr_min_waves() { return sizeof(T) == 4 && !UPD ? 4 : 1; }
 
-template <class T, int V, bool Z1, bool UPD, int HALO>
+template <class T, int V, bool Z1, bool UPD, int HALO, int RW>
 __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr(ZGeom g, size_t stride, T h, const T* __restrict__ x,
                                               const T* __restrict__ bf, const T* __restrict__ kap,
                                               const int* __restrict__ active, T* __restrict__ bc, size_t cstride,
@@ -1314,6 +1327,15 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
   const T* bb = bf + (size_t)b * stride;
   const T* kb = kap + (size_t)b * n2 * n;
   const int nc = n >> 1, nc2 = nc * nc;
+  // element offset within a sample's array as a 32-bit byte offset on the
+  // sample's (uniform) base, so that a per-lane address takes one register:
+  // rows are at most 64 vectors (resr_ok), so a sample's array is at most
+  // 256^3 fp32 or 128^3 fp64 values
+  auto at = [](auto* base, size_t off) {
+    typedef std::remove_reference_t<decltype(*base)> E;
+    return reinterpret_cast<E*>(reinterpret_cast<std::conditional_t<std::is_const_v<E>, const char*, char*>>(base) +
+                                (uint32_t)off * (uint32_t)sizeof(E));
+  };
   // UPD: r_old in R[par], r written to R[1 - par] unless this is the first
   // iteration; q and alpha of the previous iteration
   bool upd_on = false;
@@ -1345,8 +1367,8 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) {
         const size_t off = (size_t)n2 * kk + (size_t)n * jj + c * V;
-        pu[m] = *reinterpret_cast<const vt*>(ub + off);
-        if (UPD && upd_on) pq[UPD ? m : 0] = *reinterpret_cast<const vt*>(qb + off);
+        pu[m] = *reinterpret_cast<const vt*>(at(ub, off));
+        if (UPD && upd_on) pq[UPD ? m : 0] = *reinterpret_cast<const vt*>(at(qb, off));
       }
     }
   };
@@ -1388,7 +1410,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
       const int r = v >> gsh, c = v & (G - 1);
       const int ey = krow0 + r;
       if (v < KR * G && ey >= 0 && ey <= n - 1)
-        pk[m] = *reinterpret_cast<const vt*>(kb + (size_t)n2 * ez + (size_t)n * ey + c * V);
+        pk[m] = *reinterpret_cast<const vt*>(at(kb, (size_t)n2 * ez + (size_t)n * ey + c * V));
     }
   };
   auto store_k = [&](int ez) {
@@ -1404,6 +1426,17 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
   };
 
   const int tbase = nthr >= 192 ? nthr / 2 : 0;
+  // A full tile has one row more to compute than threads (R G = nthr).  A
+  // second pass of vector tasks for it would fall on one wave, which every
+  // wave then waits for at the plane's barrier; where the row is 64 RW nodes
+  // (RW = 1, 2; the launcher checks) it is one pass of one wave instead (RW
+  // nodes per lane, halos by whole-wave shifts), on the wave below the one
+  // that forms the extra staged u vectors.  Each node's arithmetic is the
+  // vector task's.
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr int VX = RW;   // nodes per lane of the row's pass; 0: two passes of vector tasks
+  const bool row_wave = RW != 0;
+  const int xw = (ubase >> 6) > 0 ? (ubase >> 6) - 1 : 0;
 
   // coarse node owned by this thread: coarse row Jf + (tid / nc), column tid % nc
   const int Jf = (j0 + 1) >> 1;
@@ -1437,43 +1470,59 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
     for (int kk = k0; kk <= kt1; ++kk) {
       const int km = (kk - 1) & (KP - 1), kc = kk & (KP - 1);
       // residual of rows j0 .. j0+R on plane kk into LDS
-      // tasks: one per thread, the extra rows of a full tile (TR * G - nthr
-      // tasks, at most nthr) on the threads from tbase on, i.e. not on the
-      // waves that stage the extra u and kappa vectors
-#pragma unroll 1
-      for (int q = 0; q < 2; ++q) {
-        const int task = q == 0 ? tid : (tid >= tbase ? nthr + tid - tbase : TR * G);
-        if (task >= TR * G) continue;
-        const int jr = task >> gsh, gx = task & (G - 1);
-        const int j = j0 + jr, i0 = gx * V;
-        if (j > n - 1) continue;
-        T far[V], ksum[V], uc[V];
-        q1_gather<T, V, HALO>(Kl + ((km * KR + jr + KOFF) << rsh) + i0, Kl + ((kc * KR + jr + KOFF) << rsh) + i0,
-                              Ul + ((sm * UR + jr) << rsh) + i0, Ul + ((s0 * UR + jr) << rsh) + i0,
-                              Ul + ((sp * UR + jr) << rsh) + i0, rsh, gx, G, ksum, far, uc);
-        T bv[V], t[V];
+      // the residual of VV nodes i0 = gx VV .. of tile row jr; a row is GG
+      // lanes of VV nodes (halo mode HH)
+      auto task_row = [&](auto vv, auto hh, int jr, int gx, int GG) {
+        constexpr int VV = decltype(vv)::value, HH = decltype(hh)::value;
+        const int j = j0 + jr, i0 = gx * VV;
+        T far[VV], ksum[VV], uc[VV];
+        q1_gather<T, VV, HH>(Kl + ((km * KR + jr + KOFF) << rsh) + i0, Kl + ((kc * KR + jr + KOFF) << rsh) + i0,
+                             Ul + ((sm * UR + jr) << rsh) + i0, Ul + ((s0 * UR + jr) << rsh) + i0,
+                             Ul + ((sp * UR + jr) << rsh) + i0, rsh, gx, GG, ksum, far, uc);
+        T bv[VV], t[VV];
         const size_t own = i0 + (size_t)n * j + (size_t)n2 * kk;
-        vload<T, V>(bb + own, bv);
+        vload<T, VV>(at(bb, own), bv);
         if (UPD) {
           if (upd_on) {
-            T qv[V];
-            vload<T, V>(qb + own, qv);
+            T qv[VV];
+            vload<T, VV>(at(qb, own), qv);
 #pragma unroll
-            for (int v = 0; v < V; ++v) bv[v] = rupd(bv[v], ua, qv[v]);
+            for (int v = 0; v < VV; ++v) bv[v] = rupd(bv[v], ua, qv[v]);
           }
           // the tile's own nodes: rows j0 .. j0+R-1, planes k0 .. k1-1
           if (jr < R && kk < k1) {
-            if (upd_on) vstore<T, V>(rnb + own, bv);
+            if (upd_on) vstore<T, VV>(at(rnb, own), bv);
 #pragma unroll
-            for (int v = 0; v < V; ++v) racc += (double)bv[v] * (double)bv[v];
+            for (int v = 0; v < VV; ++v) racc += (double)bv[v] * (double)bv[v];
           }
         }
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
+        for (int v = 0; v < VV; ++v) {
           const T au = h * (ksum[v] * uc[v] * third - far[v] * twelfth);
           t[v] = (i0 + v) != 0 ? bv[v] - au : T(0);
         }
-        vstore<T, V>(Tl + (jr << rsh) + i0, t);
+        vstore<T, VV>(Tl + (jr << rsh) + i0, t);
+      };
+      if (row_wave) {
+        // rows j0 .. j0+R-1 one task per thread; row j0+R on wave xw alone,
+        // one lane per VX nodes
+        if (j0 + (tid >> gsh) <= n - 1) task_row(Ic<V>(), Ic<HALO>(), tid >> gsh, tid & (G - 1), G);
+        __builtin_amdgcn_sched_barrier(0);   // the two passes' registers are not live at once
+        if (wave == xw && j0 + R <= n - 1) {
+          task_row(Ic<(VX > 0 ? VX : 1)>(), Ic<HALO_WAVE>(), R, lane, 64);
+        }
+      } else {
+        // tasks: one per thread, the extra rows of a full tile (TR * G - nthr
+        // tasks, at most nthr) on the threads from tbase on, i.e. not on the
+        // waves that stage the extra u and kappa vectors
+#pragma unroll 1
+        for (int q = 0; q < 2; ++q) {
+          const int task = q == 0 ? tid : (tid >= tbase ? nthr + tid - tbase : TR * G);
+          if (task >= TR * G) continue;
+          const int jr = task >> gsh;
+          if (j0 + jr > n - 1) continue;
+          task_row(Ic<V>(), Ic<HALO>(), jr, task & (G - 1), G);
+        }
       }
       if (kk + 1 <= kt1) prep_u(kk + 2);   // kappa planes kk+1, kk+2 are in the ring
       __syncthreads();
@@ -1985,19 +2034,33 @@ bool resr_usable(int n, int B) { return resr_ok<T>(resr_geom<T>(n, B)); }
 template <class T, int V, bool Z1, bool UPD>
 void resr_dispatch(const ZGeom& g, uint32_t blocks, size_t lds, hipStream_t st, size_t stride, T h, const T* x,
                    const T* bf, const T* kap, const int* active, T* bc, size_t cstride, T c2, ResrUpd<T> upd) {
-  switch (halo_mode(g.G)) {
-    case HALO_DPPROW:
-      k_resr<T, V, Z1, UPD, HALO_DPPROW><<<dim3(blocks), dim3(g.threads), lds, st>>>(g, stride, h, x, bf, kap, active,
-                                                                                   bc, cstride, c2, upd);
-      break;
-    case HALO_WAVE:
-      k_resr<T, V, Z1, UPD, HALO_WAVE><<<dim3(blocks), dim3(g.threads), lds, st>>>(g, stride, h, x, bf, kap, active,
-                                                                                 bc, cstride, c2, upd);
-      break;
-    default:
-      k_resr<T, V, Z1, UPD, HALO_SELECT><<<dim3(blocks), dim3(g.threads), lds, st>>>(g, stride, h, x, bf, kap, active,
-                                                                                   bc, cstride, c2, upd);
+  // the extra row of a full tile in one pass of one wave where it is 64 or
+  // 128 nodes and narrower than a row of vector tasks
+  const bool full = g.rows * g.G == g.threads;
+  const int rw = full && g.n == 64 && V > 1 ? 1 : (full && g.n == 128 && V > 2 ? 2 : 0);
+  const int halo = halo_mode(g.G);
+#define MLMC_RESR(H, RWV)                                                                                          \
+  k_resr<T, V, Z1, UPD, H, RWV><<<dim3(blocks), dim3(g.threads), lds, st>>>(g, stride, h, x, bf, kap, active, bc, \
+                                                                           cstride, c2, upd)
+  // rows of 16 vectors are 64 fp32 (or 32 fp64) nodes, rows of 32 vectors
+  // 128 fp32 (or 64 fp64) nodes
+  constexpr int RW_SELECT = sizeof(T) == 4 ? 2 : 1;
+  if (halo == HALO_DPPROW) {
+    if constexpr (sizeof(T) == 4) {
+      if (rw == 1) {
+        MLMC_RESR(HALO_DPPROW, 1);
+        return;
+      }
+    }
+    MLMC_RESR(HALO_DPPROW, 0);
+  } else if (halo == HALO_WAVE) {
+    MLMC_RESR(HALO_WAVE, 0);
+  } else if (rw == RW_SELECT) {
+    MLMC_RESR(HALO_SELECT, RW_SELECT);
+  } else {
+    MLMC_RESR(HALO_SELECT, 0);
   }
+#undef MLMC_RESR
 }
 
 template <class T>

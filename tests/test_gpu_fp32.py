@@ -71,11 +71,22 @@ def test_apply_f32_matches_csr(dev, n, B, check, zvar):
     print(f"apply f32 n={n} B={B} zvar={zvar}: max err / row scale {worst:.2e}")
 
 
+_HIER = {}
+
+
 def _vcycle_oracle(n, kap, r, deg):
-    return gmg.Hierarchy(n, kap.astype(np.float64)).vcycle(r.astype(np.float64), deg, 4.0, CHEB_HI)
+    # the oracle's hierarchy of one sample, kept for the other degree (the
+    # 128^3 assembly takes tens of seconds)
+    key = (n, kap.tobytes())
+    if key not in _HIER:
+        _HIER.clear()
+        _HIER[key] = gmg.Hierarchy(n, kap.astype(np.float64))
+    return _HIER[key].vcycle(r.astype(np.float64), deg, 4.0, CHEB_HI)
 
 
-@pytest.mark.parametrize("n,B,check", [(16, 6, (0, 5)), (32, 4, (1, 3)), (64, 512, (0, 300, 511))])
+# 64^3 x 512: the tiles of the 64^3 x 1024 step; 128^3: rows of 32 vectors
+# (the extra residual row of a tile as one wave of two nodes per lane)
+@pytest.mark.parametrize("n,B,check", [(16, 6, (0, 5)), (32, 4, (1, 3)), (64, 512, (0, 300, 511)), (128, 2, (1,))])
 @pytest.mark.parametrize("deg", [1, 2])
 def test_vcycle_f32_matches_oracle(dev, n, B, check, deg):
     # every fusion set the path uses (0 none, 63 the default set, 127 with the
@@ -86,7 +97,7 @@ def test_vcycle_f32_matches_oracle(dev, n, B, check, deg):
     want = {b: _vcycle_oracle(n, kap[b], r[b], deg) for b in check}
     kt = torch.tensor(kap, device=dev)
     rg = mm.to_grid(torch.tensor(r, device=dev), n)
-    ctx = mm.Context(_wl(n0=n), cheb_degree=deg, arena_bytes=(8 << 30) if n == 64 else (512 << 20))
+    ctx = mm.Context(_wl(n0=n), cheb_degree=deg, arena_bytes=(8 << 30) if n == 64 else (1 << 30))
     worst = 0.0
     for fuse in (0, 63, 127):
         for zvar in (2, 6):
