@@ -373,7 +373,7 @@ __device__ __forceinline__ void ksum_from_rows(const T (&K)[2][2][V + 1], T (&Z)
 // over the elements it shares with the node (two elements for an edge
 // diagonal, one for a corner); uc: the centre values.  A u = h (ks uc / 3 -
 // fr / 12).  The kappa pair sums are shared by the V nodes of the segment.
-template <class T, int V, int HALO>
+template <class T, int V, int HALO, bool CHAIN = false>
 __device__ __forceinline__ void q1_gather(const T* K0, const T* K1, const T* Um, const T* U0, const T* Up, int rsh,
                                           int gx, int G, T* ks, T* fr, T* uc) {
   T K[2][2][V + 1];
@@ -402,13 +402,35 @@ __device__ __forceinline__ void q1_gather(const T* K0, const T* K1, const T* Um,
     T Q[3][V + 2];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) lds_urow<T, V, HALO>(U + (dy << rsh), Q[dy], gx, G);
+    if constexpr (CHAIN) {
+      // one fused multiply-add per neighbour into the running sums, row by
+      // row (fewer instructions; more registers live)
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const T y0 = K[dz][0][v] + K[dz][1][v], y1 = K[dz][0][v + 1] + K[dz][1][v + 1];
-      const T x0 = K[dz][0][v] + K[dz][0][v + 1], x1 = K[dz][1][v] + K[dz][1][v + 1];
-      fr[v] += y0 * Q[1][v] + y1 * Q[1][v + 2] + x0 * Q[0][v + 1] + x1 * Q[2][v + 1] +
-               (K[dz][0][v] * Q[0][v] + K[dz][0][v + 1] * Q[0][v + 2] + K[dz][1][v] * Q[2][v] +
-                K[dz][1][v + 1] * Q[2][v + 2]);
+      for (int v = 0; v < V; ++v) {
+        fr[v] = fma(K[dz][0][v] + K[dz][0][v + 1], Q[0][v + 1], fr[v]);
+        fr[v] = fma(K[dz][0][v], Q[0][v], fr[v]);
+        fr[v] = fma(K[dz][0][v + 1], Q[0][v + 2], fr[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        fr[v] = fma(K[dz][0][v] + K[dz][1][v], Q[1][v], fr[v]);
+        fr[v] = fma(K[dz][0][v + 1] + K[dz][1][v + 1], Q[1][v + 2], fr[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        fr[v] = fma(K[dz][1][v] + K[dz][1][v + 1], Q[2][v + 1], fr[v]);
+        fr[v] = fma(K[dz][1][v], Q[2][v], fr[v]);
+        fr[v] = fma(K[dz][1][v + 1], Q[2][v + 2], fr[v]);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const T y0 = K[dz][0][v] + K[dz][1][v], y1 = K[dz][0][v + 1] + K[dz][1][v + 1];
+        const T x0 = K[dz][0][v] + K[dz][0][v + 1], x1 = K[dz][1][v] + K[dz][1][v + 1];
+        fr[v] += y0 * Q[1][v] + y1 * Q[1][v + 2] + x0 * Q[0][v + 1] + x1 * Q[2][v + 1] +
+                 (K[dz][0][v] * Q[0][v] + K[dz][0][v + 1] * Q[0][v + 2] + K[dz][1][v] * Q[2][v] +
+                  K[dz][1][v + 1] * Q[2][v + 2]);
+      }
     }
   }
 }
@@ -1166,7 +1188,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
 #pragma unroll
     for (int v = 0; v < V; ++v) ok[v] = (i0 + v) != 0;
     int sm = (k0 - 1) % 3, s0 = k0 % 3, sp = (k0 + 1) % 3;   // u slots of planes k-1, k, k+1
-    const T third = T(1) / T(3), twelfth = T(1) / T(12);
+    const T third = T(1) / T(3), h12 = h * (T(1) / T(12));
     for (int k = k0; k < k1; ++k) {
       if (valid) {
         // the Q1 row from the LDS tile (see q1_gather); without the u
@@ -1174,7 +1196,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         const int km = (k - 1) & (KP - 1), kc = k & (KP - 1);
         T far[V], ksum[V], uc[V];
         if (NEED_U) {
-          q1_gather<T, V, HALO>(Kl + ((km * KR + jr + KOFF) << rsh) + i0, Kl + ((kc * KR + jr + KOFF) << rsh) + i0,
+          q1_gather<T, V, HALO, true>(Kl + ((km * KR + jr + KOFF) << rsh) + i0, Kl + ((kc * KR + jr + KOFF) << rsh) + i0,
                                 Ul + ((sm * UR + jr) << rsh) + i0, Ul + ((s0 * UR + jr) << rsh) + i0,
                                 Ul + ((sp * UR + jr) << rsh) + i0, rsh, gx, G, ksum, far, uc);
         } else {
@@ -1194,7 +1216,7 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         T au[V], dg[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          au[v] = h * (ksum[v] * uc[v] * third - far[v] * twelfth);
+          au[v] = h12 * fma(ksum[v] * uc[v], T(4), -far[v]);   // h (ks uc / 3 - fr / 12)
           dg[v] = h * ksum[v] * third;
         }
         epi(pos0 + (size_t)n2 * (k - k0), au, dg, uc, ok, acc);
@@ -1331,11 +1353,12 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
   // sample's (uniform) base, so that a per-lane address takes one register:
   // rows are at most 64 vectors (resr_ok), so a sample's array is at most
   // 256^3 fp32 or 128^3 fp64 values
-  auto at = [](auto* base, size_t off) {
+  auto at = [](auto* base, uint32_t off) {
     typedef std::remove_reference_t<decltype(*base)> E;
     return reinterpret_cast<E*>(reinterpret_cast<std::conditional_t<std::is_const_v<E>, const char*, char*>>(base) +
-                                (uint32_t)off * (uint32_t)sizeof(E));
+                                off * (uint32_t)sizeof(E));
   };
+  T* bcb = bc + (size_t)b * cstride;
   // UPD: r_old in R[par], r written to R[1 - par] unless this is the first
   // iteration; q and alpha of the previous iteration
   bool upd_on = false;
@@ -1366,7 +1389,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
       const int r = v >> gsh, c = v & (G - 1);
       const int jj = j0 - 1 + r;
       if (v < UR * G && jj <= n) {
-        const size_t off = (size_t)n2 * kk + (size_t)n * jj + c * V;
+        const uint32_t off = (uint32_t)(n2 * kk + n * jj + c * V);
         pu[m] = *reinterpret_cast<const vt*>(at(ub, off));
         if (UPD && upd_on) pq[UPD ? m : 0] = *reinterpret_cast<const vt*>(at(qb, off));
       }
@@ -1410,7 +1433,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
       const int r = v >> gsh, c = v & (G - 1);
       const int ey = krow0 + r;
       if (v < KR * G && ey >= 0 && ey <= n - 1)
-        pk[m] = *reinterpret_cast<const vt*>(at(kb, (size_t)n2 * ez + (size_t)n * ey + c * V));
+        pk[m] = *reinterpret_cast<const vt*>(at(kb, (uint32_t)(n2 * ez + n * ey + c * V)));
     }
   };
   auto store_k = [&](int ez) {
@@ -1466,7 +1489,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
     if (k0 + LEAD <= kmax) fetch_k(k0 + LEAD);
     __syncthreads();
     int sm = (k0 - 1) % 3, s0 = k0 % 3, sp = (k0 + 1) % 3;
-    const T third = T(1) / T(3), twelfth = T(1) / T(12);
+    const T h12 = h * (T(1) / T(12));
     for (int kk = k0; kk <= kt1; ++kk) {
       const int km = (kk - 1) & (KP - 1), kc = kk & (KP - 1);
       // residual of rows j0 .. j0+R on plane kk into LDS
@@ -1480,7 +1503,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
                              Ul + ((sm * UR + jr) << rsh) + i0, Ul + ((s0 * UR + jr) << rsh) + i0,
                              Ul + ((sp * UR + jr) << rsh) + i0, rsh, gx, GG, ksum, far, uc);
         T bv[VV], t[VV];
-        const size_t own = i0 + (size_t)n * j + (size_t)n2 * kk;
+        const uint32_t own = (uint32_t)(i0 + n * j + n2 * kk);
         vload<T, VV>(at(bb, own), bv);
         if (UPD) {
           if (upd_on) {
@@ -1497,10 +1520,8 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
           }
         }
 #pragma unroll
-        for (int v = 0; v < VV; ++v) {
-          const T au = h * (ksum[v] * uc[v] * third - far[v] * twelfth);
-          t[v] = (i0 + v) != 0 ? bv[v] - au : T(0);
-        }
+        for (int v = 0; v < VV; ++v)   // b - h (ks uc / 3 - fr / 12)
+          t[v] = (i0 + v) != 0 ? fma(-h12, fma(ksum[v] * uc[v], T(4), -far[v]), bv[v]) : T(0);
         vstore<T, VV>(Tl + (jr << rsh) + i0, t);
       };
       if (row_wave) {
@@ -1541,7 +1562,7 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
           // odd plane 2K+1 closes coarse plane K (from the second odd plane on)
           // and opens plane K+1
           const int K = (kk - 1) >> 1;
-          if (kk > k0 && K <= nc - 1) bc[(size_t)b * cstride + cI + (size_t)nc * cJ + (size_t)nc2 * K] = cacc + T(0.5) * r2;
+          if (kk > k0 && K <= nc - 1) *at(bcb, (uint32_t)(cI + nc * cJ + nc2 * K)) = cacc + T(0.5) * r2;
           cacc = T(0.5) * r2;
         } else {
           cacc += r2;
