@@ -153,6 +153,17 @@ size_t mlmc_workspace_bytes(const mlmc_config* cfg, int32_t level, int32_t batch
  * n_modes entries each; either may be NULL). */
 int mlmc_modes(const mlmc_ctx* ctx, int32_t* triples, double* lambda);
 
+/* The same selection without a context (host only, no device call): the
+ * n_modes modes of the separable exponential-covariance KLE (Sec. 5.2) with
+ * correlation length corr_len and variance sigma2, as mlmc_modes writes them,
+ * and the 1D frequencies omega of the indices they use (omega_q of 1D mode q,
+ * increasing; the first max_omega of them are written, *n_omega receives
+ * their number).  Arrays are host memory and may be NULL.
+ * Errors: MLMC_E_INVALID (corr_len not positive and finite, sigma2 negative
+ * or not finite, n_modes outside 1..4096, omega NULL with max_omega > 0). */
+int mlmc_kl_modes(double corr_len, double sigma2, int32_t n_modes, int32_t* triples, double* lambda, double* omega,
+                  int32_t max_omega, int32_t* n_omega);
+
 /* ------------------------------------------- step-level entry points (device) */
 
 /* K1 -- xi[s*n_modes + m] (device, fp64, [count][n_modes]) for the samples

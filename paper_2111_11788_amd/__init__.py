@@ -30,7 +30,7 @@ FUSE_PRESMOOTH, FUSE_DIRECTION, FUSE_RUPDATE, FUSE_SOLVE, FUSE_PACK = 16, 32, 64
 
 # exported symbols of include/mlmc.h (checked by the CPU test suite)
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
-           "mlmc_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_apply_f32", "mlmc_vcycle",
+           "mlmc_modes", "mlmc_kl_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_apply_f32", "mlmc_vcycle",
            "mlmc_vcycle_f32", "mlmc_solve", "mlmc_qoi", "mlmc_qoi_noalloc", "mlmc_fold_stats", "mlmc_last_plan",
            "mlmc_sample_level", "mlmc_estimate", "mlmc_estimate_adaptive", "mlmc_get_estimate", "mlmc_reset_stats",
            "mlmc_node_map", "mlmc_pause_model", "mlmc_forcing",
@@ -151,6 +151,7 @@ def lib():
         "mlmc_grid_stride": (ctypes.c_size_t, [I32]),
         "mlmc_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config), I32, I32]),
         "mlmc_modes": (ctypes.c_int, [P, P, P]),
+        "mlmc_kl_modes": (ctypes.c_int, [D, D, I32, P, P, P, I32, P]),
         "mlmc_draw_xi": (ctypes.c_int, [P, I32, U64, I64, P]),
         "mlmc_field": (ctypes.c_int, [P, I32, I64, P, P, P]),
         "mlmc_apply": (ctypes.c_int, [P, I32, I64, P, P, P]),
@@ -207,6 +208,20 @@ def make_config(wl, arena_ptr: int = 0, arena_bytes: int = 0, stream: int = 0, *
     return Config(v["n0"], v["levels"], v["sigma2"], v["corr_len"], v["n_modes"], v["seed"], v["qoi"],
                   v["rtol"], v["max_iter"], v["precision"], v["solver"], v["cheb_degree"], v["max_batch"],
                   v["forcing"], arena_ptr, arena_bytes, stream)
+
+
+def kl_modes(corr_len: float, sigma2: float, n_modes: int):
+    """The library's KLE mode selection without a context (host only):
+    (triples [M, 3] int32, lambda [M], omega of the 1D modes used)."""
+    tri = np.zeros((n_modes, 3), dtype=np.int32)
+    lam = np.zeros(n_modes)
+    k1 = ctypes.c_int32()
+    rc = lib().mlmc_kl_modes(corr_len, sigma2, n_modes, tri.ctypes.data, lam.ctypes.data, None, 0, ctypes.byref(k1))
+    if rc != MLMC_OK:
+        raise MLMCError(rc, "mlmc_kl_modes: bad arguments")
+    om = np.zeros(max(1, k1.value))
+    lib().mlmc_kl_modes(corr_len, sigma2, n_modes, None, None, om.ctypes.data, k1.value, None)
+    return tri, lam, om[:k1.value]
 
 
 def workspace_bytes(cfg: Config, level: int, batch: int) -> int:

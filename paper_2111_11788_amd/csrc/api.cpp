@@ -180,6 +180,20 @@ int mlmc_modes(const mlmc_ctx* ctx, int32_t* triples, double* lambda) {
   return MLMC_OK;
 }
 
+int mlmc_kl_modes(double corr_len, double sigma2, int32_t n_modes, int32_t* triples, double* lambda, double* omega,
+                  int32_t max_omega, int32_t* n_omega) {
+  if (!(corr_len > 0.0) || !std::isfinite(corr_len) || !(sigma2 >= 0.0) || !std::isfinite(sigma2) || n_modes < 1 ||
+      n_modes > 4096 || max_omega < 0 || (max_omega > 0 && !omega))
+    return MLMC_E_INVALID;
+  const KLModes md = kl_select(corr_len, sigma2, n_modes);
+  if (triples) std::memcpy(triples, md.triples.data(), 3 * (size_t)n_modes * sizeof(int32_t));
+  if (lambda) std::memcpy(lambda, md.lambda.data(), (size_t)n_modes * sizeof(double));
+  const int k1 = (int)md.omega.size();
+  if (omega) std::memcpy(omega, md.omega.data(), (size_t)std::min(k1, (int)max_omega) * sizeof(double));
+  if (n_omega) *n_omega = k1;
+  return MLMC_OK;
+}
+
 int mlmc_draw_xi(mlmc_ctx* ctx, int32_t level, uint64_t first, int64_t count, double* xi) {
   if (!ctx) return MLMC_E_INVALID;
   if (count < 0 || (count > 0 && !xi) || level < 0) FAIL(MLMC_E_INVALID, "bad draw_xi arguments");
