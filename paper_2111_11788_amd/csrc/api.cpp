@@ -449,42 +449,27 @@ int mlmc_autotune(mlmc_ctx* ctx, int32_t level, int32_t batch, mlmc_tuning* best
 
 namespace {
 
-// (c, r) of vals_l ~ c s^(-r l) over l = 1..lmax: least squares of log_s
-// when two or more levels exist (r clamped to [lo, hi], c refitted for the
-// clamped r), else r = dflt through the one level (Sec. 2.3: c and alpha
-// estimated from the level means).  Same operation order as the oracle.
+// (c, r) of vals_l ~ c s^(-r l) over l = 1..lmax (Sec. 2.3: c and alpha
+// estimated from the level means, the variance decay likewise): the
+// least-squares line through (l, log_s vals_l) from its normal equations,
+// whose level sums are exact integers; r is clamped to [lo, hi] and c then
+// refitted for the clamped slope.  One level gives no slope: r = dflt
+// through that point.
 void decay_rate(const std::vector<double>& vals, int lmax, double dflt, double lo, double hi, double s, double* c,
                 double* r) {
   const double ls = std::log(s);
-  std::vector<double> x, y;
+  const double n = (double)lmax;
+  const double sx = 0.5 * n * (n + 1.0), sxx = n * (n + 1.0) * (2.0 * n + 1.0) / 6.0;
+  double sy = 0.0, sxy = 0.0;
   for (int l = 1; l <= lmax; ++l) {
-    x.push_back((double)l);
-    y.push_back(std::log(std::max(std::fabs(vals[l]), 1e-300)) / ls);
+    const double y = std::log(std::max(std::fabs(vals[l]), 1e-300)) / ls;
+    sy += y;
+    sxy += (double)l * y;
   }
-  const double m = (double)x.size();
   double rr = dflt;
-  if (x.size() >= 2) {
-    double xm = 0.0, ym = 0.0;
-    for (size_t i = 0; i < x.size(); ++i) xm += x[i];
-    for (size_t i = 0; i < y.size(); ++i) ym += y[i];
-    xm /= m;
-    ym /= m;
-    double sxx = 0.0, sxy = 0.0;
-    for (size_t i = 0; i < x.size(); ++i) sxx += (x[i] - xm) * (x[i] - xm);
-    for (size_t i = 0; i < x.size(); ++i) sxy += (x[i] - xm) * (y[i] - ym);
-    rr = -sxy / sxx;
-    if (lo <= rr && rr <= hi) {
-      *r = rr;
-      *c = std::pow(s, ym + rr * xm);
-      return;
-    }
-    rr = std::min(std::max(rr, lo), hi);
-  }
-  double logc = 0.0;
-  for (size_t i = 0; i < x.size(); ++i) logc += y[i] + rr * x[i];
-  logc /= m;
+  if (lmax >= 2) rr = std::min(std::max(-(n * sxy - sx * sy) / (n * sxx - sx * sx), lo), hi);
   *r = rr;
-  *c = std::pow(s, logc);
+  *c = std::pow(s, (sy + rr * sx) / n);
 }
 
 // One sampling round that brings every level 0..L up to target[l] samples
