@@ -291,6 +291,98 @@ __global__ void __launch_bounds__(256) k_field_sep(int n, int M, int K1, int S, 
   }
 }
 
+// ------------------------------------------ separable form, one z-plane per workgroup
+// The same sum factorised over all three axes: on the element plane ez of
+// sample s,
+//   A[a][b]   = sum over the modes m = (a, b, c) of sqrt(lambda_m) xi[s][m] phi_c(z_ez)
+//   B[ey][a]  = sum_b A[a][b] phi_b(y_ey)
+//   g[ey][ex] = sum_a phi_a(x_ex) B[ey][a]
+// so an element costs K1 fused multiply-adds and the exponential, and the
+// plane's M + n K1^2 other products are shared by its n^2 elements.  A
+// thread keeps its column's phi_a(x_ex) in registers (KM >= K1 of them) and
+// walks the plane's rows 256 / n at a time; B is formed RB rows at a time
+// into LDS.  Every sum runs in a fixed order (A over the modes in x-grouped
+// order, B over b, g over a), so a sample's field does not depend on its
+// batch.
+template <int KM>
+__global__ void __launch_bounds__(256) k_field_plane(int n, int M, int K1, int RB, int64_t count,
+                                                     const double* __restrict__ xi,
+                                                     const double* __restrict__ sqrtlam,
+                                                     const int* __restrict__ triples,
+                                                     const int* __restrict__ xperm, const int* __restrict__ xoff,
+                                                     const double* __restrict__ tab, double* __restrict__ kappa,
+                                                     float* __restrict__ kappa32, const int* __restrict__ rowmap) {
+  extern __shared__ double fsm[];
+  double* wv = fsm;                                   // [M] sqrt(lambda) xi phi_c(z), x-grouped order
+  double* A = wv + M;                                 // [K1][K1]
+  double* Bm = A + K1 * K1;                           // [RB][K1]
+  int* bv = reinterpret_cast<int*>(Bm + RB * K1);     // [M] y-factor of each mode
+  const int lg = 31 - __clz(n);
+  const int ez = (int)blockIdx.x;
+  const int64_t s = (int64_t)blockIdx.y;
+  if (s >= count) return;
+  const int64_t r = rowmap ? rowmap[s] : s;
+  const int tid = (int)threadIdx.x;
+  for (int p = tid; p < M; p += 256) {
+    const int m = xperm[p];
+    const int b = triples[3 * m + 1], c = triples[3 * m + 2];
+    wv[p] = sqrtlam[m] * xi[r * M + m] * tab[ez * K1 + c];
+    bv[p] = b;
+  }
+  // this thread's column and its x-factors
+  const int ex = tid & (n - 1), rph = tid >> lg, rstep = 256 >> lg;
+  double ph[KM];
+#pragma unroll
+  for (int a = 0; a < KM; ++a) ph[a] = a < K1 ? tab[ex * K1 + a] : 0.0;
+  __syncthreads();
+  for (int q = tid; q < K1 * K1; q += 256) {
+    const int a = q / K1, b = q - a * K1;
+    double acc = 0.0;
+    for (int p = xoff[a]; p < xoff[a + 1]; ++p)
+      if (bv[p] == b) acc += wv[p];
+    A[q] = acc;
+  }
+  const int64_t ne = (int64_t)n * n * n;
+  double* kr = kappa + r * ne + (int64_t)ez * n * n;
+  float* kr32 = kappa32 ? kappa32 + r * ne + (int64_t)ez * n * n : nullptr;
+  for (int y0 = 0; y0 < n; y0 += RB) {
+    __syncthreads();   // A formed; the previous rows' B no longer read
+    for (int q = tid; q < RB * K1; q += 256) {
+      const int yr = q / K1, a = q - yr * K1;
+      const double* ty = tab + (y0 + yr) * K1;
+      const double* Aa = A + a * K1;
+      double acc = 0.0;
+      for (int b = 0; b < K1; ++b) acc = fma(Aa[b], ty[b], acc);
+      Bm[q] = acc;
+    }
+    __syncthreads();
+    for (int yr = rph; yr < RB; yr += rstep) {
+      const double* bb = Bm + yr * K1;
+      double g = 0.0;
+#pragma unroll
+      for (int a = 0; a < KM; ++a)
+        if (a < K1) g = fma(ph[a], bb[a], g);
+      const double k = exp(g);
+      const int64_t e = (int64_t)(y0 + yr) * n + ex;
+      kr[e] = k;
+      if (kr32) kr32[e] = (float)k;
+    }
+  }
+}
+
+template <int KM>
+void launch_field_plane(int n, int M, int K1, int64_t count, const double* xi, const double* sqrtlam,
+                        const int* triples, const int* xperm, const int* xoff, const double* tab, double* kappa,
+                        float* kappa32, const int* rowmap, hipStream_t st) {
+  // B rows per pass: at most 2048 values, a multiple of the rows walked at once
+  const int rstep = 256 / n;
+  int RB = std::min(n, std::max(rstep, (2048 / K1) / rstep * rstep));
+  const size_t lds = ((size_t)M + (size_t)K1 * K1 + (size_t)RB * K1) * sizeof(double) + (size_t)M * sizeof(int);
+  dim3 grid((unsigned)n, (unsigned)count);
+  k_field_plane<KM><<<grid, dim3(256), lds, st>>>(n, M, K1, RB, count, xi, sqrtlam, triples, xperm, xoff, tab, kappa,
+                                                  kappa32, rowmap);
+}
+
 }  // namespace
 
 hipError_t launch_field(int n, int M, int64_t count, const double* xi, const double* sqrtlam,
@@ -299,6 +391,13 @@ hipError_t launch_field(int n, int M, int64_t count, const double* xi, const dou
                         const int* xoff) {
   if (count <= 0) return hipSuccess;
   const int64_t ne = (int64_t)n * n * n;
+  if (!bf16 && xperm && xoff && (n == 64 || n == 128 || n == 256) && K1 <= 32 && M <= 2048 && count <= 65535) {
+    // one workgroup per sample and element plane (at most 48 KiB of LDS)
+    if (K1 <= 8) launch_field_plane<8>(n, M, K1, count, xi, sqrtlam, triples, xperm, xoff, tab, kappa, kappa32, rowmap, st);
+    else if (K1 <= 16) launch_field_plane<16>(n, M, K1, count, xi, sqrtlam, triples, xperm, xoff, tab, kappa, kappa32, rowmap, st);
+    else launch_field_plane<32>(n, M, K1, count, xi, sqrtlam, triples, xperm, xoff, tab, kappa, kappa32, rowmap, st);
+    return hipGetLastError();
+  }
   if (!bf16 && xperm && xoff) {
     // samples per workgroup: as many as fit 64 KiB of LDS with the row's
     // factors and the transposed x-table, at most 32 (more workgroups per CU

@@ -79,15 +79,29 @@ def test_modes_match_oracle(dev, corr, M, sigma2):
     assert np.allclose(lam, l2, rtol=1e-14, atol=0)
 
 
-@pytest.mark.parametrize("n,M,corr,count", [(4, 8, 0.5, 3), (8, 13, 0.3, 70), (16, 64, 0.3, 17), (32, 130, 0.2, 5)])
+_FIELD = {}
+
+
+def _oracle_field(n, corr, M, seed, count):
+    key = (n, corr, M, seed, count)
+    if key not in _FIELD:
+        _FIELD[key] = field.kappa(n, corr, 1.0, M, rng.draw_xi(seed, 0, 3, count, M))
+    return _FIELD[key]
+
+
+# from 64^3 on the separable form runs one workgroup per element plane with
+# 8, 16 or 32 x-factors in registers (K1 = 8, 16, 23 here)
+@pytest.mark.parametrize("n,M,corr,count", [(4, 8, 0.5, 3), (8, 13, 0.3, 70), (16, 64, 0.3, 17), (32, 130, 0.2, 5),
+                                            (64, 64, 0.3, 3), (64, 512, 0.1, 2), (64, 512, 0.2, 2),
+                                            (128, 130, 0.2, 2), (256, 64, 0.3, 1)])
 @pytest.mark.parametrize("fk", [0, 1, 2])
 def test_field_matches_oracle(dev, n, M, corr, count, fk):
     wl = _wl(n0=n, levels=1, n_modes=M, corr_len=corr)
-    ctx = mm.Context(wl, arena_bytes=64 << 20)
+    ctx = mm.Context(wl, arena_bytes=(512 << 20) if n >= 128 else (64 << 20))
     ctx.set_tuning(field=fk)   # 0: automatic choice, 1: dense MFMA GEMM, 2: separable evaluation
     xi = ctx.draw_xi(0, 3, count)
     k, k32 = ctx.field(n, xi, want32=True)
-    want = field.kappa(n, corr, 1.0, M, rng.draw_xi(wl.seed, 0, 3, count, M))
+    want = _oracle_field(n, corr, M, wl.seed, count)
     got = k.cpu().numpy()
     rel = np.abs(got - want) / want
     assert rel.max() < 1e-13, rel.max()
