@@ -43,11 +43,11 @@ TRAFFIC = {
     "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 1, "fuse": 63, "lanes": 1},
     "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "b240c0e6cdf9fd1c", "kernels.hpp": "037887b66ba1ce4b", "krylov.hip": "2ed8ae7ac3631406", "stencil.hip": "bbd95089cbce70c8"},
     "bytes_per_launch": {
-        "PCG_APPLY (f32)": 7326725667,
-        "CHEB_PROLONG (f32)": 2115502057,
-        "RESIDUAL_RESTRICT (f32)": 1657601095,
-        "PCG_UPDATE (f32)": 3168466936,
-        "TRUE_RESIDUAL (f64)": 8660102959,
+        "PCG_APPLY (f32)": 7327534764,
+        "CHEB_PROLONG (f32)": 2116224091,
+        "RESIDUAL_RESTRICT (f32)": 1658505160,
+        "PCG_UPDATE (f32)": 3168457756,
+        "TRUE_RESIDUAL (f64)": 8658820622,
     },
 }
 

@@ -90,10 +90,13 @@ def _oracle_field(n, corr, M, seed, count):
 
 
 # from 64^3 on the separable form runs one workgroup per element plane with
-# 8, 16 or 32 x-factors in registers (K1 = 8, 16, 23 here)
+# its contraction on MFMA in 2, 4 or 8 k-steps (K1 = 8, 16, 23 here; 2048
+# modes is the largest plane block); 4096 modes (the largest M) at 8^3 fit
+# no separable block and take the dense GEMM
 @pytest.mark.parametrize("n,M,corr,count", [(4, 8, 0.5, 3), (8, 13, 0.3, 70), (16, 64, 0.3, 17), (32, 130, 0.2, 5),
                                             (64, 64, 0.3, 3), (64, 512, 0.1, 2), (64, 512, 0.2, 2),
-                                            (128, 130, 0.2, 2), (256, 64, 0.3, 1)])
+                                            (64, 2048, 0.05, 1), (128, 130, 0.2, 2), (256, 64, 0.3, 1),
+                                            (8, 4096, 0.1, 3)])
 @pytest.mark.parametrize("fk", [0, 1, 2])
 def test_field_matches_oracle(dev, n, M, corr, count, fk):
     wl = _wl(n0=n, levels=1, n_modes=M, corr_len=corr)
