@@ -517,6 +517,8 @@ typedef struct mlmc_serve_stats_out {
   double uptime_s;        /* seconds since serving started; with the two above, the active ratio
                              A = a / (p t_w) of eq. active_ratio over a window is
                              sum_m d(slot_busy_s[m]) slot_bytes[m] / (sum_m slots[m] slot_bytes[m] d(uptime_s)) */
+  uint64_t lends;         /* times an idle pool's region took a guest pool of another mesh */
+  uint64_t reclaims;      /* times a pool took its region back from a guest */
 } mlmc_serve_stats_out;
 
 /* Start serving: the arena after the KL tables is split into one resident
@@ -527,8 +529,14 @@ typedef struct mlmc_serve_stats_out {
  * step at a time and admit queued solves into free slots between steps
  * (continuous batching).  The solver is the mixed-precision GMG-PCG.  While
  * serving, the batch entry points (sample_level, solve, vcycle, qoi,
- * estimate, autotune) return MLMC_E_INVALID.  Errors: MLMC_E_NOMEM when the
- * arena cannot hold the requested pools. */
+ * estimate, autotune) return MLMC_E_INVALID.  Each mesh owns a region of the
+ * arena (its pool; with the equal split its whole share).  When a mesh has
+ * queued solves and every slot busy while another mesh's pool is idle and its
+ * region holds a pool of the first mesh's slot count, that region takes a
+ * guest pool serving the first mesh's queue (its slots compute exactly as the
+ * mesh's own); the region's owner takes it back, after the guest's running
+ * solves finish, as soon as it has work of its own.  Errors: MLMC_E_NOMEM
+ * when the arena cannot hold the requested pools. */
 int mlmc_serve_start(mlmc_ctx* ctx, const int32_t* slots_per_mesh);
 
 /* Stop serving; requests not finished are dropped.  Idempotent. */

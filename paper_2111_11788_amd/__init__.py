@@ -86,7 +86,8 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint64), ("sample_dofs", ctypes.c_double), ("busy_seconds", ctypes.c_double),
                 ("queued", ctypes.c_int32), ("running", ctypes.c_int32), ("slots", ctypes.c_int32 * 16),
                 ("occupied", ctypes.c_int32 * 16), ("slot_busy_s", ctypes.c_double * 16),
-                ("slot_bytes", ctypes.c_double * 16), ("uptime_s", ctypes.c_double)]
+                ("slot_bytes", ctypes.c_double * 16), ("uptime_s", ctypes.c_double), ("lends", ctypes.c_uint64),
+                ("reclaims", ctypes.c_uint64)]
 
 
 class Tuning(ctypes.Structure):
@@ -479,7 +480,8 @@ class Context:
         self._check(lib().mlmc_serve_stats(self.h, ctypes.byref(s)))
         return dict(completed=s.completed, sample_dofs=s.sample_dofs, busy_seconds=s.busy_seconds,
                     queued=s.queued, running=s.running, slots=list(s.slots), occupied=list(s.occupied),
-                    slot_busy_s=list(s.slot_busy_s), slot_bytes=list(s.slot_bytes), uptime_s=s.uptime_s)
+                    slot_busy_s=list(s.slot_busy_s), slot_bytes=list(s.slot_bytes), uptime_s=s.uptime_s,
+                    lends=s.lends, reclaims=s.reclaims)
 
     def submit_batch(self, levels, samples):
         lv = np.ascontiguousarray(levels, dtype=np.int32)

@@ -65,6 +65,16 @@ struct Pool {
   std::deque<Job> queue;        // guarded by the server mutex
   int occupied = 0;
   std::thread th;
+  // Lending (all guarded by the server mutex).  A main pool owns an arena
+  // region; while it is idle its region may hold a guest pool of another
+  // mesh with the same slot count as that mesh's own pool, which serves that
+  // pool's queue.
+  size_t region_off = 0, region_bytes = 0;   // a main pool's region
+  Pool* owner = nullptr;        // a guest: the main pool whose queue it serves
+  Pool* helper = nullptr;       // a main pool: its guest running in another region
+  std::unique_ptr<Pool> guest;  // a main pool: the guest in its region (it is lent)
+  bool closing = false;         // a guest: admit nothing more, end when its slots are empty
+  bool exited = false;          // a guest: its thread has ended
 
   void carve(Carver& cv, const mlmc_config& c, int m_, int S_) {
     m = m_;
@@ -109,6 +119,7 @@ struct mlmc_server {
   std::string error_msg;
   Clock::time_point t0 = Clock::now();
   uint64_t completed = 0;
+  uint64_t lends = 0, reclaims = 0;
   double dofs_done = 0.0;
   double first_submit = -1.0, last_done = 0.0;
 
@@ -240,21 +251,151 @@ int step(Pool& p) {
   return MLMC_OK;
 }
 
+// Pool set-up: carve its buffers from `off` in the arena, its engine view
+// (shared tables, own stream and pinned counter), pinned host arrays, and the
+// region cleared (zero boundaries, every slot free).
+int init_pool(mlmc_ctx* ctx, Pool& p, size_t off, int m, int S) {
+  Carver cv;
+  cv.base = (char*)ctx->cfg.arena;
+  cv.cap = ctx->cfg.arena_bytes;
+  cv.top = off;
+  cv.dry = false;
+  p.carve(cv, ctx->cfg, m, S);
+  p.slot_bytes = pool_bytes(ctx->cfg, m, 1);
+  p.sub.cfg = ctx->cfg;
+  p.sub.modes = ctx->modes;
+  p.sub.K1 = ctx->K1;
+  p.sub.d_sqrtlam = ctx->d_sqrtlam;
+  p.sub.d_triples = ctx->d_triples;
+  p.sub.d_xperm = ctx->d_xperm;
+  p.sub.d_xoff = ctx->d_xoff;
+  p.sub.d_tab = ctx->d_tab;
+  p.sub.cheb = ctx->cheb;
+  p.sub.zvar[0] = ctx->zvar[0];
+  p.sub.zvar[1] = ctx->zvar[1];
+  p.sub.vsmall_n0[0] = ctx->vsmall_n0[0];
+  p.sub.vsmall_n0[1] = ctx->vsmall_n0[1];
+  p.sub.fuse = ctx->fuse;
+  p.sub.use_graphs = false;
+  p.busy.assign(S, 0);
+  p.job.assign(S, Job{});
+  if (hipStreamCreate(&p.sub.st) != hipSuccess) return MLMC_E_DEVICE;
+  p.sub.own_stream = true;
+  if (hipHostMalloc((void**)&p.h_ids, S * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p.h_lv, S * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p.h_slots, S * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p.h_phase, S * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p.h_iters, S * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p.h_q, S * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p.sub.h_nactive, sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return MLMC_E_DEVICE;
+  if (hipMemsetAsync((char*)ctx->cfg.arena + off, 0, cv.top - off, p.sub.st) != hipSuccess ||
+      hipStreamSynchronize(p.sub.st) != hipSuccess)
+    return MLMC_E_DEVICE;
+  return MLMC_OK;
+}
+
+// The pool's stream and pinned host arrays (idempotent).
+void free_pool(Pool& p) {
+  if (p.sub.st) {
+    hipStreamSynchronize(p.sub.st);
+    hipStreamDestroy(p.sub.st);
+    p.sub.st = nullptr;
+  }
+  for (void** h : {(void**)&p.h_ids, (void**)&p.h_lv, (void**)&p.h_slots, (void**)&p.h_phase, (void**)&p.h_iters,
+                   (void**)&p.h_q, (void**)&p.sub.h_nactive})
+    if (*h) {
+      hipHostFree(*h);
+      *h = nullptr;
+    }
+}
+
+void pool_loop(mlmc_server* srv, Pool* p);
+
+// Called by main pool P after its step, server mutex held: when P has queued
+// jobs and every slot busy, and another main pool is idle with a region that
+// holds a pool of P's mesh and slot count, that region takes a guest pool for
+// P (the same slot count, so each slot's arithmetic is that of P's own
+// slots).  The guest's set-up runs under the mutex (a stream, pinned arrays
+// and one clear of the region).
+void maybe_lend(mlmc_server* srv, Pool* P) {
+  if (srv->stopping || P->helper || P->S == 0 || P->queue.empty() || P->occupied < P->S) return;
+  mlmc_ctx* ctx = srv->ctx;
+  const size_t need = pool_bytes(ctx->cfg, P->m, P->S);
+  for (auto& lp : srv->pools) {
+    Pool* L = lp.get();
+    if (L == P || L->S == 0 || L->guest || L->helper || L->occupied > 0 || !L->queue.empty() || L->region_bytes < need)
+      continue;
+    std::unique_ptr<Pool> g(new Pool());
+    if (init_pool(ctx, *g, L->region_off, P->m, P->S) != MLMC_OK) {
+      free_pool(*g);
+      return;
+    }
+    g->owner = P;
+    P->helper = g.get();
+    L->guest = std::move(g);
+    srv->lends++;
+    L->guest->th = std::thread(pool_loop, srv, L->guest.get());
+    return;
+  }
+}
+
+// Called by lent main pool L whose own queue has work, server mutex held
+// through lk: the guest stops admitting and finishes its slots, then L's
+// region is cleared and L serves again.  False when the server stops (or
+// the clear fails) meanwhile.
+bool reclaim(mlmc_server* srv, Pool* L, std::unique_lock<std::mutex>& lk) {
+  Pool* g = L->guest.get();
+  g->closing = true;
+  srv->cv.notify_all();
+  srv->cv.wait(lk, [&] { return srv->stopping || g->exited; });
+  if (srv->stopping) return false;   // serve_stop joins and frees the guest
+  lk.unlock();
+  if (g->th.joinable()) g->th.join();
+  free_pool(*g);
+  const bool ok = hipMemsetAsync((char*)srv->ctx->cfg.arena + L->region_off, 0, L->region_bytes, L->sub.st) == hipSuccess &&
+                  hipStreamSynchronize(L->sub.st) == hipSuccess;
+  lk.lock();
+  g->owner->helper = nullptr;
+  L->guest.reset();
+  srv->reclaims++;
+  if (!ok) {
+    srv->error = MLMC_E_DEVICE;
+    srv->error_msg = "clearing a returned pool region failed";
+    srv->stopping = true;
+    srv->cv.notify_all();
+    return false;
+  }
+  return true;
+}
+
 void pool_loop(mlmc_server* srv, Pool* p) {
   const int max_iter = srv->ctx->cfg.max_iter;
   std::vector<int> steps(p->S, 0);
+  Pool* src = p->owner ? p->owner : p;   // the pool whose queue feeds these slots
   for (;;) {
     int c = 0;
     {
       std::unique_lock<std::mutex> lk(srv->mu);
       srv->cv.wait(lk, [&] {
-        return srv->stopping || p->occupied > 0 || (!p->queue.empty() && p->occupied < p->S);
+        if (srv->stopping) return true;
+        if (p->owner) return p->occupied > 0 || p->closing || (!src->queue.empty() && p->occupied < p->S);
+        if (p->guest) return !p->queue.empty();   // lent: wake to take the region back
+        return p->occupied > 0 || (!p->queue.empty() && p->occupied < p->S);
       });
-      if (srv->stopping) return;
-      for (int s = 0; s < p->S && !p->queue.empty(); ++s) {
+      if (srv->stopping || (p->owner && p->closing && p->occupied == 0)) {
+        if (p->owner) p->exited = true;
+        srv->cv.notify_all();
+        return;
+      }
+      if (p->guest) {
+        if (!reclaim(srv, p, lk)) return;
+        continue;
+      }
+      for (int s = 0; s < p->S && !src->queue.empty() && !p->closing; ++s) {
         if (p->busy[s]) continue;
-        const Job j = p->queue.front();
-        p->queue.pop_front();
+        const Job j = src->queue.front();
+        src->queue.pop_front();
         p->busy[s] = 1;
         p->job[s] = j;
         steps[s] = 0;
@@ -271,11 +412,12 @@ void pool_loop(mlmc_server* srv, Pool* p) {
     int rc = c ? setup_slots(*p, c) : MLMC_OK;
     if (!rc) rc = step(*p);
     std::lock_guard<std::mutex> lk(srv->mu);
-    p->busy_slot_s += (double)p->occupied * (srv->now() - t_step);
+    src->busy_slot_s += (double)p->occupied * (srv->now() - t_step);   // a guest's slots count for its mesh
     if (rc) {
       srv->error = rc;
       srv->error_msg = p->sub.err;
       srv->stopping = true;
+      if (p->owner) p->exited = true;
       srv->cv.notify_all();
       return;
     }
@@ -315,6 +457,7 @@ void pool_loop(mlmc_server* srv, Pool* p) {
       p->busy[s] = 0;
       p->occupied--;
     }
+    if (!p->owner) maybe_lend(srv, p);
     srv->cv.notify_all();
     srv->done_cv.notify_all();
   }
@@ -358,58 +501,37 @@ int mlmc_serve_start(mlmc_ctx* ctx, const int32_t* slots_per_mesh) {
       S[m] = (int)std::min<size_t>(4096, share / per);
     }
   }
+  // each mesh's region: its pool, or with the default split its whole share
+  // (so that an idle region can take a guest pool of another mesh)
+  std::vector<size_t> region(L, 0);
   size_t need = ctx->persistent_top;
-  for (int m = 0; m < L; ++m)
-    if (S[m] > 0) need += pool_bytes(ctx->cfg, m, S[m]);
+  for (int m = 0; m < L; ++m) {
+    if (S[m] == 0) continue;
+    region[m] = align256(slots_per_mesh ? pool_bytes(ctx->cfg, m, S[m])
+                                        : std::max(pool_bytes(ctx->cfg, m, S[m]),
+                                                   (size_t)(0.95 * (double)avail / L)));
+    need += region[m];
+  }
   if (need > ctx->cfg.arena_bytes)
     FAIL(MLMC_E_NOMEM, "arena too small for the serving pools: need " + std::to_string(need) + " bytes");
   // the pools take over the arena after the persistent tables
   drop_work(ctx);
   auto* srv = new mlmc_server();
   srv->ctx = ctx;
-  Carver cv;
-  cv.base = (char*)ctx->cfg.arena;
-  cv.cap = ctx->cfg.arena_bytes;
-  cv.top = ctx->persistent_top;
-  cv.dry = false;
-  const size_t start = cv.top;
+  ctx->server = srv;
+  size_t off = ctx->persistent_top;
   int rc = MLMC_OK;
-  for (int m = 0; m < L && !rc; ++m) {
+  for (int m = 0; m < L; ++m) {
     srv->pools.emplace_back(new Pool());
     Pool& p = *srv->pools.back();
-    if (S[m] == 0) continue;
-    p.carve(cv, ctx->cfg, m, S[m]);
-    p.slot_bytes = pool_bytes(ctx->cfg, m, 1);
-    p.sub.cfg = ctx->cfg;
-    p.sub.modes = ctx->modes;
-    p.sub.K1 = ctx->K1;
-    p.sub.d_sqrtlam = ctx->d_sqrtlam;
-    p.sub.d_triples = ctx->d_triples;
-    p.sub.d_tab = ctx->d_tab;
-    p.sub.cheb = ctx->cheb;
-    p.sub.zvar[0] = ctx->zvar[0];
-    p.sub.zvar[1] = ctx->zvar[1];
-    p.sub.vsmall_n0[0] = ctx->vsmall_n0[0];
-    p.sub.vsmall_n0[1] = ctx->vsmall_n0[1];
-    p.sub.fuse = ctx->fuse;
-    p.sub.use_graphs = false;
-    if (hipStreamCreate(&p.sub.st) != hipSuccess) rc = MLMC_E_DEVICE;
-    p.sub.own_stream = true;
-    const int s = S[m];
-    if (!rc && (hipHostMalloc((void**)&p.h_ids, s * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc((void**)&p.h_lv, s * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc((void**)&p.h_slots, s * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc((void**)&p.h_phase, s * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc((void**)&p.h_iters, s * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc((void**)&p.h_q, s * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc((void**)&p.sub.h_nactive, sizeof(int), hipHostMallocDefault) != hipSuccess))
-      rc = MLMC_E_DEVICE;
-    p.busy.assign(s, 0);
-    p.job.assign(s, Job{});
+    p.m = m;
+    p.n = ctx->cfg.n0 << m;
+    if (S[m] == 0 || rc) continue;
+    p.region_off = off;
+    p.region_bytes = region[m];
+    off += region[m];
+    rc = init_pool(ctx, p, p.region_off, m, S[m]);
   }
-  if (!rc && hipMemsetAsync((char*)ctx->cfg.arena + start, 0, cv.top - start, ctx->st) != hipSuccess) rc = MLMC_E_DEVICE;
-  if (!rc && hipStreamSynchronize(ctx->st) != hipSuccess) rc = MLMC_E_DEVICE;
-  ctx->server = srv;
   if (rc) {
     mlmc_serve_stop(ctx);
     FAIL(rc, "serving set-up failed");
@@ -429,20 +551,17 @@ int mlmc_serve_stop(mlmc_ctx* ctx) {
   }
   srv->cv.notify_all();
   srv->done_cv.notify_all();
-  for (auto& p : srv->pools) {
+  // main pools first (a lent pool's thread may be taking its region back),
+  // then the guests still in a region
+  for (auto& p : srv->pools)
     if (p->th.joinable()) p->th.join();
-    if (p->sub.st) {
-      hipStreamSynchronize(p->sub.st);
-      hipStreamDestroy(p->sub.st);
+  for (auto& p : srv->pools)
+    if (p->guest) {
+      if (p->guest->th.joinable()) p->guest->th.join();
+      free_pool(*p->guest);
+      p->guest.reset();
     }
-    hipHostFree(p->h_ids);
-    hipHostFree(p->h_lv);
-    hipHostFree(p->h_slots);
-    hipHostFree(p->h_phase);
-    hipHostFree(p->h_iters);
-    hipHostFree(p->h_q);
-    hipHostFree(p->sub.h_nactive);
-  }
+  for (auto& p : srv->pools) free_pool(*p);
   ctx->server = nullptr;
   delete srv;
   return MLMC_OK;
@@ -532,13 +651,17 @@ int mlmc_serve_stats(mlmc_ctx* ctx, mlmc_serve_stats_out* out) {
   int q = 0, occ = 0;
   for (int m = 0; m < (int)srv->pools.size() && m < 16; ++m) {
     const Pool& p = *srv->pools[m];
-    out->slots[m] = p.S;
-    out->occupied[m] = p.occupied;
+    // a mesh's slots: its own pool unless lent out, plus its guest elsewhere
+    const int gs = p.helper ? p.helper->S : 0, go = p.helper ? p.helper->occupied : 0;
+    out->slots[m] = (p.guest ? 0 : p.S) + gs;
+    out->occupied[m] = p.occupied + go;
     out->slot_busy_s[m] = p.busy_slot_s;
     out->slot_bytes[m] = (double)p.slot_bytes;
     q += (int)p.queue.size();
-    occ += p.occupied;
+    occ += p.occupied + go;
   }
+  out->lends = srv->lends;
+  out->reclaims = srv->reclaims;
   out->queued = q;
   out->running = occ;
   out->uptime_s = srv->now();

@@ -108,3 +108,37 @@ def test_submit_batch_and_drain_array_match_single_submits(dev):
         s = by_sample[(int(r["level"]), int(r["sample"]))]
         assert r["status"] == 0 and s["status"] == 0
         assert r["y"] == s["y"] and r["q_fine"] == s["q_fine"] and r["iters"] == s["iters"]
+
+
+def test_idle_region_lends_and_takes_back(dev):
+    # 2 slots per mesh: a burst of 8^3 samples keeps the 8^3 pool full while
+    # the larger meshes idle, so an idle region takes a guest 8^3 pool of 2
+    # slots; a 32^3 request (whose coarse solve is on 16^3) makes the lender
+    # take its region back.  Every 8^3 result has the bits of the same sample
+    # served alone, the 32^3 one matches the oracle.
+    import time
+    wl = _wl()
+    ctx = mm.Context(wl, arena_bytes=1 << 30)
+    ctx.serve_start([2, 2, 2])
+    alone = {s: next(iter(ctx.wait([ctx.submit(0, s)]).values())) for s in (3, 29)}
+    assert ctx.serve_stats()["lends"] == 0
+    tickets = [ctx.submit(0, s) for s in range(40)]
+    t0 = time.time()
+    while ctx.serve_stats()["lends"] == 0 and time.time() - t0 < 10.0:
+        time.sleep(0.002)
+    st = ctx.serve_stats()
+    assert st["lends"] >= 1
+    assert st["slots"][0] == 4 and (st["slots"][1] == 0 or st["slots"][2] == 0)
+    t2 = ctx.submit(2, 5)
+    res = ctx.wait(tickets + [t2])
+    st = ctx.serve_stats()
+    ctx.serve_stop()
+    assert st["reclaims"] >= 1 and st["completed"] == 43
+    assert all(r["status"] == 0 for r in res.values())
+    for s in (3, 29):
+        r = res[tickets[s]]
+        for k in ("y", "q_fine", "iters"):
+            assert r[k] == alone[s][k], (s, k)
+    r = res[t2]
+    y, qf, qc, _ = omlmc.sample_level(wl, 2, 5, 1, rtol=1e-12, max_iter=20000)
+    assert abs(r["q_fine"] - qf[0]) <= 1e-7 * abs(qf[0]) and abs(r["q_coarse"] - qc[0]) <= 1e-7 * abs(qc[0])
