@@ -438,7 +438,8 @@ def run_c4(args):
            "kle_bf16_vs_fp64": kle_check,
            "saturation": {"requests_per_s": sat_rate, "sample_dofs_per_s": sat_dofs, "clients": clients,
                           "seconds": args.sat_seconds, "kind": "closed loop",
-                          "active_ratio": active_ratio(snap0, snap1) if snap0 else None},
+                          "active_ratio": active_ratio(snap0, snap1) if snap0 else None,
+                          "lends": snap1["lends"], "reclaims": snap1["reclaims"]},
            "rates": []}
     for frac in (0.5, 0.8, 0.95):
         rate = frac * sat_rate
@@ -471,7 +472,8 @@ def run_c4(args):
             if time.perf_counter() - t0 > args.serve_seconds + 600:
                 raise TimeoutError("serving run did not finish")
         wall = time.perf_counter() - t0
-        a_ratio = active_ratio(s0, ctx.serve_stats())
+        s1 = ctx.serve_stats()
+        a_ratio = active_ratio(s0, s1)
         res = np.concatenate(got)
         order = np.argsort(tickets)
         pos = order[np.searchsorted(tickets[order], res["ticket"])]
@@ -486,7 +488,8 @@ def run_c4(args):
                              "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99),
                              "max_submit_lag_ms": 1e3 * float(lag.max()),
                              "sample_dofs_per_s": float(dofs[lv].sum()) / wall, "per_level": per,
-                             "active_ratio": a_ratio,
+                             "active_ratio": a_ratio, "lends": s1["lends"] - s0["lends"],
+                             "reclaims": s1["reclaims"] - s0["reclaims"],
                              "all_ok": bool((res["status"] == 0).all())})
     ctx.serve_stop()
     return out

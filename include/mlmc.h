@@ -531,7 +531,7 @@ typedef struct mlmc_serve_stats_out {
  * serving, the batch entry points (sample_level, solve, vcycle, qoi,
  * estimate, autotune) return MLMC_E_INVALID.  Each mesh owns a region of the
  * arena (its pool; with the equal split its whole share).  When a mesh has
- * queued solves and every slot busy while another mesh's pool is idle and its
+ * more queued solves than free slots while another mesh's pool is idle and its
  * region holds a pool of the first mesh's slot count, that region takes a
  * guest pool serving the first mesh's queue (its slots compute exactly as the
  * mesh's own); the region's owner takes it back, after the guest's running

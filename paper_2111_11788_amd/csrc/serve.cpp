@@ -312,14 +312,15 @@ void free_pool(Pool& p) {
 
 void pool_loop(mlmc_server* srv, Pool* p);
 
-// Called by main pool P after its step, server mutex held: when P has queued
-// jobs and every slot busy, and another main pool is idle with a region that
+// Called by main pool P after its step, server mutex held: when P's queue
+// holds more jobs than its free slots, and another main pool is idle with a region that
 // holds a pool of P's mesh and slot count, that region takes a guest pool for
 // P (the same slot count, so each slot's arithmetic is that of P's own
 // slots).  The guest's set-up runs under the mutex (a stream, pinned arrays
 // and one clear of the region).
 void maybe_lend(mlmc_server* srv, Pool* P) {
-  if (srv->stopping || P->helper || P->S == 0 || P->queue.empty() || P->occupied < P->S) return;
+  // more queued than P's free slots take at its next admission
+  if (srv->stopping || P->helper || P->S == 0 || (int64_t)P->queue.size() <= (int64_t)(P->S - P->occupied)) return;
   mlmc_ctx* ctx = srv->ctx;
   const size_t need = pool_bytes(ctx->cfg, P->m, P->S);
   for (auto& lp : srv->pools) {
