@@ -46,7 +46,7 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   const size_t need = persistent_bytes(cfg, ctx->K1);
   if (need > cfg->arena_bytes) {
     g_create_error = "arena smaller than the " + std::to_string(need) + " bytes of KL tables";
-    if (ctx->own_stream) hipStreamDestroy(ctx->st);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->st);
     delete ctx;
     return MLMC_E_NOMEM;
   }
@@ -92,8 +92,8 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
   if (e != hipSuccess) {
     g_create_error = std::string("HIP error during create: ") + hipGetErrorString(e);
-    if (ctx->h_nactive) hipHostFree(ctx->h_nactive);
-    if (ctx->own_stream) hipStreamDestroy(ctx->st);
+    if (ctx->h_nactive) (void)hipHostFree(ctx->h_nactive);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->st);
     delete ctx;
     return MLMC_E_DEVICE;
   }
@@ -105,22 +105,23 @@ int mlmc_create(const mlmc_config* cfg, mlmc_ctx** out) {
 void mlmc_destroy(mlmc_ctx* ctx) {
   if (!ctx) return;
   mlmc_serve_stop(ctx);
-  hipStreamSynchronize(ctx->st);
+  // teardown: errors have nowhere to go
+  (void)hipStreamSynchronize(ctx->st);
   for (auto& r : ctx->prof) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
-  for (auto e : ctx->event_pool) hipEventDestroy(e);
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   drop_work(ctx);
   for (auto& ln : ctx->lanes)
     if (ln->sub) {
-      hipStreamSynchronize(ln->sub->st);
-      hipHostFree(ln->sub->h_nactive);
-      hipStreamDestroy(ln->sub->st);
+      (void)hipStreamSynchronize(ln->sub->st);
+      (void)hipHostFree(ln->sub->h_nactive);
+      (void)hipStreamDestroy(ln->sub->st);
     }
   ctx->lanes.clear();
-  if (ctx->h_nactive) hipHostFree(ctx->h_nactive);
-  if (ctx->own_stream) hipStreamDestroy(ctx->st);
+  if (ctx->h_nactive) (void)hipHostFree(ctx->h_nactive);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->st);
   delete ctx;
 }
 

@@ -19,8 +19,8 @@ hipEvent_t take_event(mlmc_ctx* ctx) {
     ctx->event_pool.pop_back();
     return e;
   }
-  hipEvent_t e;
-  hipEventCreate(&e);
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -414,12 +414,12 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
       const int rc = pcg_iteration_dir<T>(ctx, L, B, S, x, r, p, p2, q, tol2, RED_RR, true, false, r2);
       const hipError_t ec = hipStreamEndCapture(st, &g);
       if (rc) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
       }
       HIPCHK(ec);
       const hipError_t ei = hipGraphInstantiate(graph, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);   // the instantiated graph does not need it
       HIPCHK(ei);
     }
     while (it < max_iter && *ctx->h_nactive > 0) {
@@ -452,12 +452,12 @@ int pcg(mlmc_ctx* ctx, std::vector<Level<T>>& L, int B, SolveState& S, T* x, T* 
     const int rc = pcg_iteration<T>(ctx, L, B, S, x, r, p, q, tol2);
     const hipError_t ec = hipStreamEndCapture(st, &g);
     if (rc) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return rc;
     }
     HIPCHK(ec);
     const hipError_t ei = hipGraphInstantiate(graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);   // the instantiated graph does not need it
     HIPCHK(ei);
   }
   int it = 0;
@@ -806,7 +806,7 @@ int ensure_lanes(mlmc_ctx* ctx, int K) {
       if (hipStreamCreate(&sub->st) != hipSuccess) FAIL(MLMC_E_DEVICE, "cannot create a lane stream");
       sub->own_stream = true;
       if (hipHostMalloc((void**)&sub->h_nactive, sizeof(int), hipHostMallocDefault) != hipSuccess) {
-        hipStreamDestroy(sub->st);
+        (void)hipStreamDestroy(sub->st);
         FAIL(MLMC_E_DEVICE, "cannot allocate a lane counter");
       }
       ln->sub = std::move(sub);

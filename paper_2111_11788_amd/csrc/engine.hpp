@@ -125,7 +125,7 @@ struct SolveWork {
   void release_graphs() {
     for (auto& g : iter_exec)
       if (g) {
-        hipGraphExecDestroy(g);
+        (void)hipGraphExecDestroy(g);
         g = nullptr;
       }
   }
@@ -372,7 +372,10 @@ int launch(mlmc_ctx* ctx, int id, double bytes, const int* mask, int B, F&& f) {
     }
     a = take_event(ctx);
     b = take_event(ctx);
-    hipEventRecord(a, ctx->st);
+    if (!a || !b || hipEventRecord(a, ctx->st) != hipSuccess) {
+      ctx->err = "profiling event failed";
+      return MLMC_E_DEVICE;
+    }
   }
   const hipError_t e = f();
   if (e != hipSuccess) {
@@ -380,7 +383,10 @@ int launch(mlmc_ctx* ctx, int id, double bytes, const int* mask, int B, F&& f) {
     return MLMC_E_DEVICE;
   }
   if (ctx->profiling) {
-    hipEventRecord(b, ctx->st);
+    if (hipEventRecord(b, ctx->st) != hipSuccess) {
+      ctx->err = "profiling event failed";
+      return MLMC_E_DEVICE;
+    }
     ctx->prof.push_back(ProfRec{id, a, b, bytes, cnt, B});
   }
   return MLMC_OK;

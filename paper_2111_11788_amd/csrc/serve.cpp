@@ -298,14 +298,14 @@ int init_pool(mlmc_ctx* ctx, Pool& p, size_t off, int m, int S) {
 // The pool's stream and pinned host arrays (idempotent).
 void free_pool(Pool& p) {
   if (p.sub.st) {
-    hipStreamSynchronize(p.sub.st);
-    hipStreamDestroy(p.sub.st);
+    (void)hipStreamSynchronize(p.sub.st);   // teardown: nothing to report to
+    (void)hipStreamDestroy(p.sub.st);
     p.sub.st = nullptr;
   }
   for (void** h : {(void**)&p.h_ids, (void**)&p.h_lv, (void**)&p.h_slots, (void**)&p.h_phase, (void**)&p.h_iters,
                    (void**)&p.h_q, (void**)&p.sub.h_nactive})
     if (*h) {
-      hipHostFree(*h);
+      (void)hipHostFree(*h);
       *h = nullptr;
     }
 }
