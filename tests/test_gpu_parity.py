@@ -95,8 +95,8 @@ def _oracle_field(n, corr, M, seed, count):
 # no separable block and take the dense GEMM
 @pytest.mark.parametrize("n,M,corr,count", [(4, 8, 0.5, 3), (8, 13, 0.3, 70), (16, 64, 0.3, 17), (32, 130, 0.2, 5),
                                             (64, 64, 0.3, 3), (64, 512, 0.1, 2), (64, 512, 0.2, 2),
-                                            (64, 2048, 0.05, 1), (128, 130, 0.2, 2), (256, 64, 0.3, 1),
-                                            (8, 4096, 0.1, 3)])
+                                            (64, 2048, 0.05, 1), (128, 130, 0.2, 2), (128, 512, 0.2, 1),
+                                            (256, 64, 0.3, 1), (256, 130, 0.2, 1), (8, 4096, 0.1, 3)])
 @pytest.mark.parametrize("fk", [0, 1, 2])
 def test_field_matches_oracle(dev, n, M, corr, count, fk):
     wl = _wl(n0=n, levels=1, n_modes=M, corr_len=corr)
