@@ -129,3 +129,23 @@ def test_mixed_solve_inner_iterations_are_bounded(dev, n, B, deg):
           f"fp64 max {counts[0].max()} mean {counts[0].mean():.2f}")
     assert counts[1].max() <= counts[0].max() + 4
     assert counts[1].max() <= 14
+
+
+def test_vcycle_f32_256cube_fused_restriction_matches_unfused(dev):
+    # 256^3 (rows of one wave of vectors, 4-row tiles whose extra residual
+    # row takes a second pass): the fused residual restriction against the
+    # separate residual and restriction kernels, Chebyshev degree 2 (no
+    # on-the-fly pre-smoothing); the oracle's 256^3 hierarchy is too large
+    # to assemble here
+    n, B = 256, 2
+    kap, r = _inputs(n, B, 4242, (0, 1))
+    kt = torch.tensor(kap, device=dev)
+    rg = mm.to_grid(torch.tensor(r, device=dev), n)
+    ctx = mm.Context(_wl(n0=n), cheb_degree=2, arena_bytes=8 << 30)
+    out = {}
+    for fuse in (0, 8):
+        ctx.set_tuning(fuse=fuse, zvar_fp32=2, vsmall_fp32=16)
+        out[fuse] = mm.from_grid(ctx.vcycle_f32(n, kt, rg), n).cpu().numpy().astype(np.float64)
+    for b in range(B):
+        err = np.abs(out[8][b] - out[0][b]).max() / np.abs(out[0][b]).max()
+        assert err <= 2e-5, (b, err)
