@@ -197,6 +197,17 @@ int mlmc_apply(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa,
 int mlmc_apply_f32(mlmc_ctx* ctx, int32_t n, int64_t count, const float* kappa,
                    const float* u, float* y);
 
+/* z = c D^-1 b for `count` samples on the n^3 mesh, the first
+ * Chebyshev-Jacobi smoothing step from a zero iterate of the V-cycle below,
+ * with D_i = (h/3) sum of kappa_e over the 8 elements e around node i, the
+ * diagonal of A(kappa) (the smoothers compute it from kappa in the same
+ * order).  b, z: device, grid layout, fp64 (z = 0 where the layout holds no
+ * unknown); kappa: device, element layout, fp64.  With b = 1 and c = 1 it
+ * exports D^-1, for parity tests of the diagonal.  b and z must not overlap.
+ * Errors: MLMC_E_INVALID (bad sizes, NULL or overlapping arrays). */
+int mlmc_jacobi(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa, const double* b, double c,
+                double* z);
+
 /* One multigrid V-cycle z = B(kappa) r of the preconditioner used by the
  * GMG-PCG solve (rediscretised coarse operators with the 8-child mean of
  * kappa, trilinear transfers, Chebyshev-Jacobi smoothing of the context's

@@ -30,7 +30,7 @@ FUSE_PRESMOOTH, FUSE_DIRECTION, FUSE_RUPDATE, FUSE_SOLVE, FUSE_PACK = 16, 32, 64
 
 # exported symbols of include/mlmc.h (checked by the CPU test suite)
 SYMBOLS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_grid_stride", "mlmc_workspace_bytes",
-           "mlmc_modes", "mlmc_kl_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_apply_f32", "mlmc_vcycle",
+           "mlmc_modes", "mlmc_kl_modes", "mlmc_draw_xi", "mlmc_field", "mlmc_apply", "mlmc_apply_f32", "mlmc_jacobi", "mlmc_vcycle",
            "mlmc_vcycle_f32", "mlmc_solve", "mlmc_qoi", "mlmc_qoi_noalloc", "mlmc_fold_stats", "mlmc_last_plan",
            "mlmc_sample_level", "mlmc_estimate", "mlmc_estimate_adaptive", "mlmc_get_estimate", "mlmc_reset_stats",
            "mlmc_node_map", "mlmc_pause_model", "mlmc_forcing",
@@ -157,6 +157,7 @@ def lib():
         "mlmc_field": (ctypes.c_int, [P, I32, I64, P, P, P]),
         "mlmc_apply": (ctypes.c_int, [P, I32, I64, P, P, P]),
         "mlmc_apply_f32": (ctypes.c_int, [P, I32, I64, P, P, P]),
+        "mlmc_jacobi": (ctypes.c_int, [P, I32, I64, P, P, D, P]),
         "mlmc_vcycle": (ctypes.c_int, [P, I32, I64, P, P, P]),
         "mlmc_vcycle_f32": (ctypes.c_int, [P, I32, I64, P, P, P]),
         "mlmc_fold_stats": (ctypes.c_int, [P, I32, P, U64]),
@@ -295,6 +296,12 @@ class Context:
         y = self.torch.zeros_like(u_grid)
         self._check(lib().mlmc_apply(self.h, n, u_grid.shape[0], _ptr(kappa), _ptr(u_grid), _ptr(y)))
         return y
+
+    def jacobi(self, n: int, kappa, b_grid, c: float = 1.0):
+        """mlmc_jacobi: z = c D^-1 b (fp64, grid layout)."""
+        z = self.torch.zeros_like(b_grid)
+        self._check(lib().mlmc_jacobi(self.h, n, b_grid.shape[0], _ptr(kappa), _ptr(b_grid), c, _ptr(z)))
+        return z
 
     def vcycle(self, n: int, kappa, r_grid):
         z = self.torch.zeros_like(r_grid)

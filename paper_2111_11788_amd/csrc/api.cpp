@@ -233,6 +233,19 @@ int mlmc_apply_f32(mlmc_ctx* ctx, int32_t n, int64_t count, const float* kappa, 
   return MLMC_OK;
 }
 
+int mlmc_jacobi(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa, const double* b, double c,
+                double* z) {
+  if (!ctx) return MLMC_E_INVALID;
+  if (n < 2 || !is_pow2(n) || n > 1024 || count < 0 || count > (1 << 30) || (count > 0 && (!kappa || !b || !z)) ||
+      (count > 0 && b == z) || !std::isfinite(c))
+    FAIL(MLMC_E_INVALID, "bad jacobi arguments");
+  if (count == 0) return MLMC_OK;
+  LAUNCH(MLMC_K_CHEB_ZERO, (2 * dofs(n) + elems(n)) * count * 8,
+         launch_cheb<double>(n, (int)count, kappa, b, nullptr, nullptr, z, 0.0, c, true, false, nullptr, ctx->st,
+                             nullptr, nullptr, zv<double>(ctx)));
+  return MLMC_OK;
+}
+
 int mlmc_vcycle(mlmc_ctx* ctx, int32_t n, int64_t count, const double* kappa, const double* r, double* z) {
   if (!ctx) return MLMC_E_INVALID;
   if (ctx->server) FAIL(MLMC_E_INVALID, "the context is serving");

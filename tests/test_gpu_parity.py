@@ -138,6 +138,29 @@ def test_bf16_field_within_its_rounding_bound(dev, n, M, corr, count):
     assert rel.max() < 0.05
 
 
+@pytest.mark.parametrize("zvar", [0, 2])
+@pytest.mark.parametrize("n,B", [(2, 3), (4, 3), (8, 5), (16, 2), (32, 1), (64, 2)])
+def test_jacobi_diagonal_matches_csr(dev, n, B, zvar):
+    # z = c D^-1 b with D the diagonal of the assembled CSR matrix; with b = 1
+    # and c = 1 the exported D^-1 itself (both stencil engines)
+    kap = element_field(n, B, seed=300 + n, spread=1.5)
+    b = grid_vector(n, B, seed=400 + n)
+    ctx = mm.Context(_wl(n0=n, levels=1), arena_bytes=256 << 20)
+    ctx.set_tuning(zvar_fp64=zvar)
+    kt = torch.tensor(kap, device=dev)
+    ones = mm.to_grid(torch.ones((B, (n - 1) ** 3), dtype=torch.float64, device=dev), n)
+    dinv = ctx.jacobi(n, kt, ones)
+    z = mm.from_grid(ctx.jacobi(n, kt, mm.to_grid(torch.tensor(b, device=dev), n), 0.7), n).cpu().numpy()
+    mask = np.ones(dinv.shape[1], dtype=bool)
+    mask[mm.interior_positions(n)] = False
+    assert np.all(dinv.cpu().numpy()[:, mask] == 0.0)
+    dinv = mm.from_grid(dinv, n).cpu().numpy()
+    for s in range(B):
+        d = fe.assemble(n, kap[s]).diagonal()
+        assert np.abs(dinv[s] * d - 1.0).max() <= 1e-14
+        assert np.abs(z[s] - 0.7 * b[s] / d).max() <= 1e-14 * np.abs(0.7 * b[s] / d).max()
+
+
 @pytest.mark.parametrize("zvar", [0, 1, 2])
 @pytest.mark.parametrize("n,B", [(4, 3), (8, 5), (16, 2), (32, 1)])
 def test_apply_matches_csr(dev, n, B, zvar):
