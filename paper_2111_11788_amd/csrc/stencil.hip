@@ -925,7 +925,7 @@ __device__ __forceinline__ void z1_form(T* u, const T* Kl, int KR, int rsh, int 
   }
 }
 
-template <class T, int V, bool NEED_U, bool PRO, int OP, class Epi, int HALO>
+template <class T, int V, bool NEED_U, bool PRO, int OP, class Epi, int HALO, int NC = 0>
 __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const T* __restrict__ u,
                                               const T* __restrict__ kap, const int* __restrict__ active,
                                               double* __restrict__ partial, uint32_t pstride, Epi epi,
@@ -944,7 +944,9 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   const uint32_t part = lin - b * per;
   if (active && !active[b]) return;   // uniform over the workgroup
   const int rb = (int)(part % (uint32_t)g.row_blocks), zb = (int)(part / (uint32_t)g.row_blocks);
-  const int n = g.n, n2 = n * n, G = g.G, R = g.rows;
+  // NC > 0: the mesh size known at compile time (G = NC / V: the launcher
+  // checks), so LDS row offsets fold into the instructions' immediate offsets
+  const int n = NC ? NC : g.n, n2 = n * n, G = NC ? NC / V : g.G, R = g.rows;
   const int gsh = __builtin_ctz((unsigned)G);   // G is a power of two
   const int UR = R + 2, KR = R + 1 + 2 * KOFF;
   const int URS = zlds_urs<T>(n), KRS = zlds_krs<T>(n);
@@ -1309,7 +1311,7 @@ __device__ __forceinline__ T rupd(T r, T a, T q) { return fma(-a, q, r); }
 template <class T, int V, bool Z1, bool UPD>
 constexpr int resr_min_waves() { return sizeof(T) == 4 && !UPD ? 4 : 1; }
 
-template <class T, int V, bool Z1, bool UPD, int HALO, int RW>
+template <class T, int V, bool Z1, bool UPD, int HALO, int RW, int NC = 0>
 __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr(ZGeom g, size_t stride, T h, const T* __restrict__ x,
                                               const T* __restrict__ bf, const T* __restrict__ kap,
                                               const int* __restrict__ active, T* __restrict__ bc, size_t cstride,
@@ -1324,7 +1326,10 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
   const uint32_t part = lin - b * per;
   if (active && !active[b]) return;   // uniform over the workgroup
   const int rb = (int)(part % (uint32_t)g.row_blocks), zb = (int)(part / (uint32_t)g.row_blocks);
-  const int n = g.n, n2 = n * n, G = g.G, R = g.rows;
+  // NC > 0: the mesh size known at compile time (256 threads, G = NC / V,
+  // R = 256 / G: the launcher checks), so LDS row offsets fold into the
+  // instructions' immediate offsets
+  const int n = NC ? NC : g.n, n2 = n * n, G = NC ? NC / V : g.G, R = NC ? 256 / (NC / V) : g.rows;
   const int gsh = __builtin_ctz((unsigned)G);   // G is a power of two
   const int UR = R + 3, KR = R + 2 + 2 * KOFF, TR = R + 1;
   const int URS = zlds_urs<T>(n), KRS = zlds_krs<T>(n);
@@ -1549,15 +1554,24 @@ __global__ void __launch_bounds__(256, (resr_min_waves<T, V, Z1, UPD>())) k_resr
       __syncthreads();
       // in-plane full weighting of t at the owned coarse node, folded over planes
       if (owner) {
+        // t at fine columns 2I, 2I+1 by one aligned pair read per row (lanes
+        // at consecutive pairs: no LDS bank conflicts); column 2I-1 is the
+        // previous lane's second value (coarse column I-1 of the same coarse
+        // row, an owner too), passed by a whole-wave shift, except on a
+        // wave's first lane, where a coarse row wider than a wave (nc > 64)
+        // continues from the previous wave: read from LDS there
+        typedef typename Vec<T, 2>::type t2;
+        const int jr = 2 * cJ - j0;   // tile row of fine row 2J
         T r2 = T(0);
-        if (cI > 0) {
-          const int jr = 2 * cJ - j0;   // tile row of fine row 2J
 #pragma unroll
-          for (int dy = -1; dy <= 1; ++dy) {
-            const T* row = Tl + ((jr + dy) << rsh) + 2 * cI;
-            r2 += (dy == 0 ? T(1) : T(0.5)) * (T(0.5) * (row[-1] + row[1]) + row[0]);
-          }
+        for (int dy = -1; dy <= 1; ++dy) {
+          const T* row = Tl + ((jr + dy) << rsh) + 2 * cI;
+          const t2 pr = *reinterpret_cast<const t2*>(row);
+          T left = from_prev(pr[1]);
+          if (nc > 64 && lane == 0 && cI > 0) left = row[-1];
+          r2 += (dy == 0 ? T(1) : T(0.5)) * (T(0.5) * (left + pr[1]) + pr[0]);
         }
+        if (cI == 0) r2 = T(0);
         if (kk & 1) {
           // odd plane 2K+1 closes coarse plane K (from the second odd plane on)
           // and opens plane K+1
@@ -1602,6 +1616,13 @@ hipError_t zlaunch_lds(int n, int B, const T* u, const T* xc, const T* kap, cons
   const size_t cs = PRO ? grid_stride(n / 2) : 0;
   switch (halo_mode(g.G)) {
     case HALO_DPPROW:
+      if constexpr (sizeof(T) == 4) {
+        if (n == 64) {   // the fp32 64^3 mesh: its row size compiled in
+          k_zlds<T, V, NEED_U, PRO, OP, Epi, HALO_DPPROW, 64><<<dim3(blocks), dim3(g.threads), lds, st>>>(
+              g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, cs, op);
+          break;
+        }
+      }
       k_zlds<T, V, NEED_U, PRO, OP, Epi, HALO_DPPROW><<<dim3(blocks), dim3(g.threads), lds, st>>>(
           g, grid_stride(n), T(1) / T(n), u, kap, active, partial, pstride, epi, xc, cs, op);
       break;
@@ -2069,6 +2090,11 @@ void resr_dispatch(const ZGeom& g, uint32_t blocks, size_t lds, hipStream_t st, 
   if (halo == HALO_DPPROW) {
     if constexpr (sizeof(T) == 4) {
       if (rw == 1) {
+        if (g.n == 64 && g.threads == 256 && g.rows == 16) {
+          k_resr<T, V, Z1, UPD, HALO_DPPROW, 1, 64><<<dim3(blocks), dim3(g.threads), lds, st>>>(
+              g, stride, h, x, bf, kap, active, bc, cstride, c2, upd);
+          return;
+        }
         MLMC_RESR(HALO_DPPROW, 1);
         return;
       }
