@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # the commands are in the committed counter summary.
 TRAFFIC = {
     "profile": "profiles/batched-64cube-1024_hbm_traffic.txt",
-    "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 1024, "graph_batch": 1, "fuse": 63, "lanes": 1},
+    "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 256, "graph_batch": 1, "fuse": 447, "lanes": 4},
     "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "b240c0e6cdf9fd1c", "kernels.hpp": "037887b66ba1ce4b", "krylov.hip": "2ed8ae7ac3631406", "stencil.hip": "bbd95089cbce70c8"},
     "bytes_per_launch": {
         "PCG_APPLY (f32)": 7327534764,

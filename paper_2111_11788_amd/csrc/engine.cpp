@@ -649,7 +649,9 @@ int solve_impl(mlmc_ctx* ctx, SolveWork& w, const double* kap, double* u, int32_
 
 int qoi_impl(mlmc_ctx* ctx, SolveState& S, int n, int B, const double* u, double* q) {
   uint32_t np = 0;
-  LAUNCH(MLMC_K_QOI, dofs(n) * B * 8, launch_qoi_partial(n, B, ctx->cfg.qoi, u, S, &np, ctx->st));
+  const double m = ctx->cfg.qoi == 1 ? (double)(3 * n / 4 - n / 4 + 1) : 0.0;   // subcube nodes per axis
+  LAUNCH(MLMC_K_QOI, (ctx->cfg.qoi == 1 ? m * m * m : dofs(n)) * B * 8,
+         launch_qoi_partial(n, B, ctx->cfg.qoi, u, S, &np, ctx->st));
   LAUNCH(MLMC_K_REDUCE, 0, launch_reduce(B, RED_STORE, 0.0, np, S, q, ctx->st));
   return MLMC_OK;
 }

@@ -242,38 +242,53 @@ __global__ void __launch_bounds__(kBlock) k_fill_interior(SGeom g, size_t stride
   }
 }
 
-// QoI weights: domain average h^3; subcube [1/4,3/4]^3 average
-// h^3 prod_d c(i_d) with c = 2 strictly inside, 1 on the faces, 0 outside
-// (the number of subcube elements touching the node along each axis).
-__global__ void __launch_bounds__(kBlock) k_qoi_partial(SGeom g, size_t stride, int qoi, const double* __restrict__ u,
+// QoI weights: domain average h^3 at every node (k_qoi_partial); subcube
+// [1/4,3/4]^3 average h^3 prod_d c(i_d) with c = 2 strictly inside, 1 on the
+// faces, 0 outside (the number of subcube elements touching the node along
+// each axis; k_qoi_subcube).
+__global__ void __launch_bounds__(kBlock) k_qoi_partial(SGeom g, size_t stride, const double* __restrict__ u,
                                                         SolveState st, bool masked) {
   const Span sp = span_of(g);
   if (masked && !st.active[sp.b]) return;
-  const int n = g.n;
-  const size_t n2 = (size_t)n * n;
+  const size_t n2 = (size_t)g.n * g.n;
   const double* ub = u + (size_t)sp.b * stride + n2;
-  const double h = 1.0 / n, h3 = h * h * h;
-  const int lo = n / 4, hi = 3 * n / 4;
+  const double h = 1.0 / g.n, h3 = h * h * h;
   typedef Vec<double, 2>::type d2;
-  const int lg = __builtin_ctz((unsigned)n);   // n is a power of two
   const d2* uv = reinterpret_cast<const d2*>(ub);
   double acc = 0.0;
   for (size_t t = sp.lo + threadIdx.x; t < sp.hi; t += kBlock) {
     const d2 u2 = uv[t];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const size_t pos = 2 * t + c;
-      const int i = (int)(pos & (n - 1)), j = (int)((pos >> lg) & (n - 1)), k = 1 + (int)(pos >> (2 * lg));
-      double w = h3;
-      if (qoi == 1) {
-        auto cw = [&](int x) { return (x < lo || x > hi) ? 0.0 : ((x == lo || x == hi) ? 1.0 : 2.0); };
-        w *= cw(i) * cw(j) * cw(k);
-      }
-      acc += w * (c ? u2.y : u2.x);    // boundary positions hold 0
-    }
+    acc += h3 * u2.x;   // boundary positions hold 0
+    acc += h3 * u2.y;
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) st.partial[(size_t)sp.b * st.pstride + sp.c] = acc;
+}
+
+// The subcube QoI reads only the nodes its weights cover: the box
+// [n/4, 3n/4]^3 of m^3 nodes (m = n/2 + 1), in `chunks` workgroups per sample,
+// x fastest; the weights as above.
+__global__ void __launch_bounds__(kBlock) k_qoi_subcube(int n, uint32_t chunks, size_t stride,
+                                                        const double* __restrict__ u, SolveState st, bool masked) {
+  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = logical / chunks, c = logical - b * chunks;
+  if (masked && !st.active[b]) return;
+  const int lo = n / 4, hi = 3 * n / 4;
+  const uint32_t m = (uint32_t)(hi - lo + 1), total = m * m * m;
+  const uint32_t per = (total + chunks - 1) / chunks;
+  const uint32_t t0 = c * per, t1 = t0 + per < total ? t0 + per : total;
+  const double* ub = u + (size_t)b * stride;
+  const double h = 1.0 / n, h3 = h * h * h;
+  auto cw = [&](int x) { return (x == lo || x == hi) ? 1.0 : 2.0; };
+  double acc = 0.0;
+  for (uint32_t t = t0 + threadIdx.x; t < t1; t += kBlock) {
+    const uint32_t a = t / m, i = t - a * m;
+    const uint32_t k = a / m, j = a - k * m;
+    const int x = lo + (int)i, y = lo + (int)j, z = lo + (int)k;
+    acc += h3 * cw(x) * cw(y) * cw(z) * ub[(size_t)z * n * n + (size_t)y * n + x];
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) st.partial[(size_t)b * st.pstride + c] = acc;
 }
 
 // one workgroup per sample: fixed-order sum of its partials, then the scalar op
@@ -635,8 +650,18 @@ hipError_t launch_set_active(int B, SolveState s, int value, hipStream_t st) {
 hipError_t launch_qoi_partial(int n, int B, int qoi, const double* u, SolveState s, uint32_t* nparts,
                               hipStream_t st, bool masked) {
   const SGeom g = sgeom<double>(n);
+  if (qoi == 1) {
+    // the subcube's nodes only, in at most as many parts as the whole-mesh form
+    const uint32_t m = (uint32_t)(3 * n / 4 - n / 4 + 1);
+    uint32_t ch = (uint32_t)(((size_t)m * m * m + kBlock * 8 - 1) / (kBlock * 8));
+    if (ch > g.chunks) ch = g.chunks;
+    if (ch < 1) ch = 1;
+    if (nparts) *nparts = ch;
+    k_qoi_subcube<<<dim3(ch * (uint32_t)B), kBlock, 0, st>>>(n, ch, grid_stride(n), u, s, masked);
+    return hipGetLastError();
+  }
   if (nparts) *nparts = g.chunks;
-  k_qoi_partial<<<sgrid<double>(g, B), kBlock, 0, st>>>(g, grid_stride(n), qoi, u, s, masked);
+  k_qoi_partial<<<sgrid<double>(g, B), kBlock, 0, st>>>(g, grid_stride(n), u, s, masked);
   return hipGetLastError();
 }
 
