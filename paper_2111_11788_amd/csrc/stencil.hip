@@ -546,6 +546,16 @@ struct EpiDirApply {
       vload<T, V>(pold + pos, pv);
     }
   }
+  // the same with p_old at the thread's own nodes already in registers (the
+  // LDS engine stages them): no second read of p_old
+  template <class W>
+  __device__ void pre_own(size_t pos, const W& pown) {
+    if (prev) {
+      if (!fresh) vload<T, V>(x + pos, xv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) pv[v] = pown[v];
+    }
+  }
   __device__ void begin(uint32_t b) {
     const int ps = pstate[b];
     prev = (ps & 2) == 0;
@@ -1003,12 +1013,27 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
   vt pu[2], pk[2];
   fvt pd[ADDD ? 2 : 1], pq[ADDD ? 2 : 1];
   vt pp[DIR ? 2 : 1];
+  // OP_DIR: p_old at the thread's own nodes of the next plane to finish (and
+  // of the first plane, in the prologue)
+  vt pown{}, pown0{};
   // staged u vector m of this thread: the first nthr by thread id, the rest
   // (a tile taller than the workgroup) by the last threads, so that extra
   // work (the OP_Z1 / PRO operand) does not pile onto wave 0, which stages the
   // extra kappa vectors; ubase is a multiple of G, so a row stays in one wave
   const int ubase = 2 * nthr - UR * G;
-  auto uv = [&](int m) { return m == 0 ? tid : (tid >= ubase ? nthr + tid - ubase : 1 << 30); };
+  // OP_DIR: the map is rotated by one row, so that a thread's first vector is
+  // its own row j (tile row jr + 1) and the p_old it stages there serves its
+  // x update as well; the extra vectors take tile rows R + 1 and 0
+  auto uv = [&](int m) {
+    int v = m == 0 ? tid : (tid >= ubase ? nthr + tid - ubase : 1 << 30);
+    if constexpr (DIR) {
+      if (v < UR * G) {
+        v += G;
+        if (v >= UR * G) v -= UR * G;
+      }
+    }
+    return v;
+  };
   // PRO: the coarse planes of the correction in an LDS ring of two planes
   // (plane C in slot C & 1), rows crow0 .. crow0 + CR - 1: the parents
   // (jj >> 1, (jj + 1) >> 1) of the staged fine rows jj = j0-1 .. j0+R.  A
@@ -1171,7 +1196,9 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
       if (NEED_U) {
         fetch_u(k0 - 1); store_u((k0 - 1) % 3, k0 - 1);
         fetch_u(k0); store_u(k0 % 3, k0);
+        if constexpr (DIR) pown0 = pp[0];
         fetch_u(k0 + 1); store_u((k0 + 1) % 3, k0 + 1);
+        if constexpr (DIR) pown = pp[0];
       }
       fetch_k(k0 - 1); store_k(k0 - 1);
       fetch_k(k0); store_k(k0);
@@ -1182,7 +1209,10 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
     // the epilogue's own operands of plane k0 first: waiting for them later
     // then leaves the staging loads behind them in flight
     const size_t pos0 = (size_t)b * stride + i0 + (size_t)n * j + (size_t)n2 * k0;
-    if (valid) epi.pre(pos0);
+    if (valid) {
+      if constexpr (DIR) epi.pre_own(pos0, pown0);
+      else epi.pre(pos0);
+    }
     if (NEED_U && k0 + 2 <= k1) fetch_u(k0 + 2);
     if (k0 + LEAD <= kmax) fetch_k(k0 + LEAD);
     __syncthreads();
@@ -1234,7 +1264,12 @@ __global__ void __launch_bounds__(256) k_zlds(ZGeom g, size_t stride, T h, const
         // PRO: coarse plane (k + 4) / 2 with fine plane k + 2 (k even), fetched
         // in the step before
         if (PRO && ((k - k0) & 1) && k + 3 <= k1) store_c((k + 4) >> 1);
-        if (valid) epi.pre(pos0 + (size_t)n2 * (k + 1 - k0));
+        if (valid) {
+          if constexpr (DIR) epi.pre_own(pos0 + (size_t)n2 * (k + 1 - k0), pown);
+          else epi.pre(pos0 + (size_t)n2 * (k + 1 - k0));
+        }
+        // OP_DIR: p_old of plane k + 2 (prepared above) for the next step
+        if constexpr (DIR) pown = pp[0];
         if (NEED_U && k + 3 <= k1) fetch_u(k + 3);
         if (k + LEAD + 1 <= kmax) fetch_k(k + LEAD + 1);
         if (PRO && !((k - k0) & 1) && k + 4 <= k1) fetch_c((k + 5) >> 1);
