@@ -41,13 +41,13 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 TRAFFIC = {
     "profile": "profiles/batched-64cube-1024_hbm_traffic.txt",
     "tuning": {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 256, "graph_batch": 1, "fuse": 447, "lanes": 4},
-    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "b240c0e6cdf9fd1c", "kernels.hpp": "037887b66ba1ce4b", "krylov.hip": "2ed8ae7ac3631406", "stencil.hip": "bbd95089cbce70c8"},
+    "sha256_16": {"common.hpp": "84103274fa2b6280", "grid.hpp": "b240c0e6cdf9fd1c", "kernels.hpp": "037887b66ba1ce4b", "krylov.hip": "cdf3168b8678bec1", "stencil.hip": "e58c30d0c1b92bf7"},
     "bytes_per_launch": {
-        "PCG_APPLY (f32)": 7327534764,
-        "CHEB_PROLONG (f32)": 2116224091,
-        "RESIDUAL_RESTRICT (f32)": 1658505160,
-        "PCG_UPDATE (f32)": 3168457756,
-        "TRUE_RESIDUAL (f64)": 8658820622,
+        "PCG_APPLY (f32)": 1654327456,
+        "CHEB_PROLONG (f32)": 522266031,
+        "RESIDUAL_RESTRICT (f32)": 395964223,
+        "PCG_UPDATE (f32)": 792139355,
+        "TRUE_RESIDUAL (f64)": 2168757237,
     },
 }
 
