@@ -215,13 +215,14 @@ def qoi_vs_oracle(check, golden: str, cpu=None):
     return out
 
 
-# the 256^3 leg's tuning: the library defaults with the autotuner's picks on
-# that workload, Chebyshev degree 1 and the prolongation and zero-start
-# pre-smoothing fusions off (about 98 against 104 ms per 16 samples; splitting
-# the 16 samples into four concurrent batches, as the autotuner also picked,
-# measured the same)
-C5_TUNING = {"zvar_fp32": 6, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 16,
-             "graph_batch": 2, "fuse": 430, "field": 0, "lanes": 4}
+# the 256^3 leg's tuning: the autotuner's pick on that workload with 16
+# samples per call (four concurrent batches of 4, Chebyshev degree 1, LDS
+# stencil engine, every fusion but the prolongation, two captured PCG
+# iterations per convergence check): about 93 against 98 ms per 16 samples
+# for the earlier pick (zvar 6, one batch of 16, prolongation and pre-smoothing
+# fusions off)
+C5_TUNING = {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 4,
+             "graph_batch": 2, "fuse": 510, "field": 0, "lanes": 4}
 
 
 def run_c5_leg(steps: int = 3, B: int = 16, tuning=None):

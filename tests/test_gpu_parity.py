@@ -275,6 +275,23 @@ def test_fp64_degree1_solve_matches_oracle(dev, n, B, fuse):
         assert np.linalg.norm(res) <= 1.5e-12 * np.linalg.norm(bvec)
 
 
+@pytest.mark.parametrize("n,B", [(4, 3), (8, 2), (64, 3), (128, 2), (256, 1)])
+@pytest.mark.parametrize("qoi", [0, 1])
+def test_qoi_functional_matches_oracle_weights(dev, n, B, qoi):
+    # the QoI kernels (the whole mesh for the domain average, the subcube's
+    # nodes only for the subcube average) on random nodal vectors against the
+    # oracle's weights w . u, including the subcube's faces and corners
+    wl = _wl(n0=n, levels=1, qoi=qoi)
+    ctx = mm.Context(wl, arena_bytes=4 << 30)
+    u = grid_vector(n, B, seed=900 + n + qoi)
+    q = ctx.qoi(n, mm.to_grid(torch.tensor(u, device=dev), n)).cpu().numpy()
+    w = fe.qoi_weights(n, qoi)
+    for b in range(B):
+        want = float(w @ u[b])
+        assert abs(q[b] - want) <= 1e-12 * float(np.abs(w) @ np.abs(u[b])), (n, b, q[b], want)
+    ctx.close()
+
+
 def _oracle_q(n, kap, qoi, rtol=1e-12):
     q, it, rel, u = omlmc.solve_qoi(n, kap, qoi, rtol, 20000)
     return q
