@@ -23,12 +23,21 @@ import workloads
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def test_256cube_samples_match_stored_oracle_values():
+# the tuning the bench's 256^3 leg pins (16 samples per call as four
+# concurrent batches of 4, every fusion but the prolongation)
+C5_PINNED = {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 4,
+             "graph_batch": 2, "fuse": 510, "field": 0, "lanes": 4}
+
+
+@pytest.mark.parametrize("tuning,count", [(None, 2), (C5_PINNED, 16)], ids=["defaults", "bench-pinned"])
+def test_256cube_samples_match_stored_oracle_values(tuning, count):
     gold = json.load(open(os.path.join(HERE, "golden", "c5_stress_qoi.json")))
     wl = workloads.C5
     assert gold["n"] == wl.n0 and gold["n_modes"] == wl.n_modes and gold["seed"] == wl.seed
-    ctx = mm.Context(wl, max_batch=2, rtol=gold["rtol"], max_iter=2000)
-    y, qf, qc, it = ctx.sample_level(0, 0, 2)
+    ctx = mm.Context(wl, max_batch=count, rtol=gold["rtol"], max_iter=2000)
+    if tuning:
+        ctx.set_tuning(**tuning)
+    y, qf, qc, it = ctx.sample_level(0, 0, count)
     for g in gold["samples"]:
         q = float(qf[g["index"]])
         rel = abs(q - g["q"]) / abs(g["q"])
