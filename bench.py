@@ -216,11 +216,11 @@ def qoi_vs_oracle(check, golden: str, cpu=None):
 
 
 # the 256^3 leg's tuning: the autotuner's pick on that workload with 16
-# samples per call (four concurrent batches of 4, Chebyshev degree 1, LDS
-# stencil engine, every fusion but the prolongation, two captured PCG
-# iterations per convergence check): about 93 against 98 ms per 16 samples
-# for the earlier pick (zvar 6, one batch of 16, prolongation and pre-smoothing
-# fusions off)
+# samples per call: four concurrent batches of 4, Chebyshev degree 1, two
+# captured PCG iterations per convergence check, the prolongation fusion off
+# (the pre-smoothing and residual-update bits, set, act only with it, so the
+# kernels are those of the earlier pick, which ran the 16 samples as one
+# batch): about 93 against 98 ms per 16 samples
 C5_TUNING = {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 4,
              "graph_batch": 2, "fuse": 510, "field": 0, "lanes": 4}
 
@@ -535,6 +535,9 @@ def run_c5(args):
     for B in (4, 8, 16):
         ctx = mm.Context(wl, max_batch=B, cheb_degree=args.cheb_degree)
         tuned = ctx.autotune(0, B) if args.autotune else None
+        if tuned is None and args.c5_tuning:
+            ctx.set_tuning(**{k: v for k, v in json.loads(args.c5_tuning).items() if k != "seconds"})
+            tuned = ctx.tuning()
         y, qf, qc, it = ctx.sample_level(0, 0, B)       # warm-up (carve, graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -618,7 +621,8 @@ def main():
                     help="run a plain copy of this many MiB first (counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the fp64 comparison run")
     ap.add_argument("--no-c5", action="store_true", help="skip the 256^3 leg of the default line")
-    ap.add_argument("--c5-tuning", default="", help="JSON tuning of the 256^3 leg ('{}': library defaults)")
+    ap.add_argument("--c5-tuning", default="", help="JSON tuning of the 256^3 leg ('{}': library defaults); "
+                    "with --mode c5, the tuning of its three batch sizes (default there: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--slots", default="", help="c4: slots per mesh, comma separated")

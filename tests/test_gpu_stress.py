@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 # the tuning the bench's 256^3 leg pins (16 samples per call as four
-# concurrent batches of 4, every fusion but the prolongation)
+# concurrent batches of 4, the prolongation fusion off)
 C5_PINNED = {"zvar_fp32": 2, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1, "max_batch": 4,
              "graph_batch": 2, "fuse": 510, "field": 0, "lanes": 4}
 
