@@ -384,6 +384,31 @@ def test_batch_composition_does_not_change_results(dev):
     assert qf1[0] == qf[3] and qc1[0] == qc[3] and it1[0] == it[3]
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_recarved_work_space_gives_the_same_bits(dev, precision):
+    # a work space carved over memory an earlier, differently sized batch left
+    # dirty (only its never-written positions and non-grid buffers cleared)
+    # gives the bits of a fresh context: through the sampling lanes and
+    # through the solve entry point
+    wl = _wl(n0=16, levels=2, n_modes=32, corr_len=0.3, rtol=1e-10, precision=precision, batch=16)
+    ctx = mm.Context(wl, arena_bytes=512 << 20)
+    ctx.sample_level(1, 0, 13)
+    ctx.sample_level(0, 40, 11)
+    y, qf, qc, it = ctx.sample_level(1, 100, 6)
+    fresh = mm.Context(wl, arena_bytes=512 << 20)
+    y0, qf0, qc0, it0 = fresh.sample_level(1, 100, 6)
+    assert np.array_equal(qf, qf0) and np.array_equal(qc, qc0) and np.array_equal(it, it0)
+    n = 16
+    kap9 = torch.tensor(element_field(n, 9, seed=71, spread=1.0), device=dev)
+    kap5 = torch.tensor(element_field(n, 5, seed=72, spread=1.0), device=dev)
+    ctx.solve(n, kap9)
+    u, it5 = ctx.solve(n, kap5)
+    u0, it50 = fresh.solve(n, kap5)
+    assert torch.equal(u, u0) and np.array_equal(it5, it50)
+    ctx.close()
+    fresh.close()
+
+
 def test_estimate_allocation_matches_oracle(dev):
     # pilot + eq. mlmc_num_samples + top-up, deterministic DOF cost model
     wl = _wl(n0=4, levels=3, n_modes=8, corr_len=0.5, solver=0, rtol=1e-12, batch=64, precision=0)
