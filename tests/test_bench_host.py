@@ -16,6 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_gpu_tests_pin_the_bench_tunings():
     assert c2cfg.BENCH_TUNING == bench.TRAFFIC["tuning"]
+    assert c2cfg.FP64_TUNING == bench.FP64_TUNING
     assert c5cfg.C5_PINNED == bench.C5_TUNING
 
 

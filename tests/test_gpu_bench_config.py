@@ -51,3 +51,25 @@ def test_bench_batch_matches_stored_oracle_values(rtol, tol, tuning):
     assert np.all(np.isfinite(qf)) and np.all(qc == 0.0)
     assert it.max() <= (12 if rtol == 1e-8 else 30)
     ctx.close()
+
+
+# the tuning of the bench's fp64 leg (the same workload in fp64)
+FP64_TUNING = {"zvar_fp32": 6, "zvar_fp64": 2, "vsmall_fp32": 16, "vsmall_fp64": 8, "cheb_degree": 1,
+               "max_batch": 256, "graph_batch": 0, "fuse": 443, "field": 0, "lanes": 4}
+
+
+@pytest.mark.parametrize("rtol,tol", [(1e-8, 1e-6), (1e-12, 1e-10)])
+def test_fp64_leg_matches_stored_oracle_values(rtol, tol):
+    gold = json.load(open(os.path.join(HERE, "golden", "c2_batched_qoi.json")))
+    wl = workloads.C2
+    ctx = mm.Context(wl, precision=0, max_batch=1024, rtol=rtol)
+    ctx.set_tuning(**FP64_TUNING)
+    y, qf, qc, it = ctx.sample_level(0, 0, 1024)
+    for g in gold["samples"]:
+        q = float(qf[g["index"]])
+        rel = abs(q - g["q"]) / abs(g["q"])
+        print(f"64^3 fp64 sample {g['index']} rtol {rtol}: gpu {q!r} oracle {g['q']!r} rel {rel:.2e} "
+              f"iters {int(it[g['index']])}")
+        assert rel <= tol
+    assert np.all(np.isfinite(qf)) and np.all(qc == 0.0)
+    ctx.close()
